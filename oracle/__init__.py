@@ -1,0 +1,217 @@
+"""CPU oracle for the Llama decision path (arXiv 2102.01887, Alg. 1 and Eq. 1).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg use this package.  The product (``paper_2102_01887_amd``)
+never imports it, and it imports nothing from the product.
+
+``liboracle.so`` is built from ``oracle.c`` by ``build()`` (plain gcc).  The
+wrappers below only marshal numpy arrays; all arithmetic is in the C file.
+The learned-surrogate oracle (FP64 MLP with BF16 rounding emulation) is in
+``oracle/mlp.py``.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SRC_PATH = os.path.join(HERE, "oracle.c")
+
+PAPER = 0
+PROB = 1
+
+OK, E_ARG, E_RANGE, E_CYCLE, E_STATE = 0, -1, -2, -3, -4
+
+
+def build(verbose=False):
+    """Compile oracle.c into liboracle.so with gcc (no GPU code)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
+           SRC_PATH, "-o", LIB_PATH + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def load(path):
+    """Load an oracle library from ``path`` and declare its signatures."""
+    L = ctypes.CDLL(path)
+    p = ctypes.c_void_p
+    i32, i64 = ctypes.c_int32, ctypes.c_int64
+    L.oracle_reference_cfg.argtypes = [i32, p, p, p, p, p]
+    L.oracle_worst_path.argtypes = [i32, p, p, p, p, i32, p]
+    L.oracle_targets.argtypes = [i64, p, p, p, i32, p, i32, p, p, p]
+    L.oracle_select.argtypes = [i64, p, p, i32, i32, p, p, p, p, p, p, p]
+    L.oracle_decide.argtypes = [i64, p, p, p, i32, p, i32, p, p, p, p, p,
+                                p, p, p, p, p]
+    for f in (L.oracle_reference_cfg, L.oracle_worst_path,
+              L.oracle_targets, L.oracle_select, L.oracle_decide):
+        f.restype = ctypes.c_int
+    return L
+
+
+class use:
+    """Context manager: route the wrappers below through another build of the
+    oracle (the test suite uses it to check that planted mistakes are caught)."""
+
+    def __init__(self, path):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.prev = _lib
+        _lib = load(self.path)
+        return _lib
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.prev
+        return False
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        _lib = load(LIB_PATH)
+    return _lib
+
+
+class OracleError(RuntimeError):
+    def __init__(self, fn, rc):
+        super().__init__(f"{fn} returned {rc}")
+        self.rc = rc
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _arr(a, dtype):
+    return None if a is None else np.ascontiguousarray(a, dtype=dtype)
+
+
+def _check(fn, rc):
+    if rc != OK:
+        raise OracleError(fn, rc)
+
+
+def reference_cfg(cfg_off, hw, batch, res):
+    cfg_off = _arr(cfg_off, np.int32)
+    n_ops = len(cfg_off) - 1
+    out = np.empty(n_ops, np.int32)
+    a = [_arr(x, np.int32) for x in (hw, batch, res)]
+    _check("oracle_reference_cfg",
+           lib().oracle_reference_cfg(n_ops, _ptr(cfg_off), *map(_ptr, a), _ptr(out)))
+    return out
+
+
+def reference_latency(cfg_off, lat, ref_k):
+    """ref[v] = lat of the op's reference configuration (int64)."""
+    cfg_off = np.asarray(cfg_off, np.int64)
+    return np.asarray(lat, np.int64)[cfg_off[:-1] + np.asarray(ref_k, np.int64)]
+
+
+def worst_path(succ_off, succ_ids, succ_q16, ref_lat, mode):
+    succ_off = _arr(succ_off, np.int32)
+    n_ops = len(succ_off) - 1
+    ids = _arr(succ_ids, np.int32)
+    q = _arr(succ_q16, np.uint32)
+    ref = _arr(ref_lat, np.int64)
+    W = np.empty(n_ops, np.int64)
+    _check("oracle_worst_path",
+           lib().oracle_worst_path(n_ops, _ptr(succ_off), _ptr(ids), _ptr(q),
+                                   _ptr(ref), mode, _ptr(W)))
+    return W
+
+
+def targets(inv_op, elapsed, slo, n_hw, Q, ref_lat, W):
+    inv_op, elapsed, slo = (_arr(x, np.int32) for x in (inv_op, elapsed, slo))
+    n = len(inv_op)
+    Q = _arr(Q, np.int64)
+    ref = _arr(ref_lat, np.int64)
+    Wa = _arr(W, np.int64)
+    out = np.empty((n, n_hw), np.int32)
+    _check("oracle_targets",
+           lib().oracle_targets(n, _ptr(inv_op), _ptr(elapsed), _ptr(slo), n_hw,
+                                _ptr(Q), len(ref), _ptr(ref), _ptr(Wa), _ptr(out)))
+    return out
+
+
+def select(inv_op, target, n_hw, cfg_off, hw, batch, lat, cost):
+    inv_op = _arr(inv_op, np.int32)
+    n = len(inv_op)
+    target = _arr(target, np.int32).reshape(n, n_hw)
+    cfg_off = _arr(cfg_off, np.int32)
+    hw, batch, lat = (_arr(x, np.int32) for x in (hw, batch, lat))
+    cost = _arr(cost, np.int64)
+    cfg = np.empty(n, np.int32)
+    flag = np.empty(n, np.uint8)
+    _check("oracle_select",
+           lib().oracle_select(n, _ptr(inv_op), _ptr(target), n_hw, len(cfg_off) - 1,
+                               _ptr(cfg_off), _ptr(hw), _ptr(batch), _ptr(lat),
+                               _ptr(cost), _ptr(cfg), _ptr(flag)))
+    return cfg, flag
+
+
+def decide(inv_op, elapsed, slo, n_hw, Q, ref_lat, W, cfg_off, hw, batch, lat, cost):
+    inv_op, elapsed, slo = (_arr(x, np.int32) for x in (inv_op, elapsed, slo))
+    n = len(inv_op)
+    Q = _arr(Q, np.int64)
+    ref = _arr(ref_lat, np.int64)
+    Wa = _arr(W, np.int64)
+    cfg_off = _arr(cfg_off, np.int32)
+    hw, batch, lat = (_arr(x, np.int32) for x in (hw, batch, lat))
+    cost = _arr(cost, np.int64)
+    cfg = np.empty(n, np.int32)
+    flag = np.empty(n, np.uint8)
+    scratch = np.empty(n_hw, np.int32)
+    _check("oracle_decide",
+           lib().oracle_decide(n, _ptr(inv_op), _ptr(elapsed), _ptr(slo), n_hw,
+                               _ptr(Q), len(ref), _ptr(ref), _ptr(Wa), _ptr(cfg_off),
+                               _ptr(hw), _ptr(batch), _ptr(lat), _ptr(cost),
+                               _ptr(cfg), _ptr(flag), _ptr(scratch)))
+    return cfg, flag
+
+
+class Problem:
+    """Bundle of one workload's arrays with the oracle's derived quantities.
+
+    Holds exactly the caller's inputs (DAG CSR, profile table, invocations);
+    ``ref``/``W``/``targets``/``decide`` are computed by the oracle above.
+    """
+
+    def __init__(self, w):
+        self.w = w
+        self.ref_k = (reference_cfg(w.cfg_off, w.hw, w.batch, w.res)
+                      if w.ref_cfg is None else np.asarray(w.ref_cfg, np.int32))
+        self.ref = reference_latency(w.cfg_off, w.lat, self.ref_k)
+        self._W = {}
+
+    def W(self, mode):
+        if mode not in self._W:
+            w = self.w
+            self._W[mode] = worst_path(w.succ_off, w.succ_ids, w.succ_q16, self.ref, mode)
+        return self._W[mode]
+
+    def targets(self, mode, Q=None, sl=slice(None)):
+        w = self.w
+        return targets(w.inv_op[sl], w.elapsed[sl], w.slo[sl], w.n_hw, Q,
+                       self.ref, self.W(mode))
+
+    def decide(self, mode, Q=None, sl=slice(None)):
+        w = self.w
+        return decide(w.inv_op[sl], w.elapsed[sl], w.slo[sl], w.n_hw, Q, self.ref,
+                      self.W(mode), w.cfg_off, w.hw, w.batch, w.lat, w.cost)
+
+    def select(self, target, sl=slice(None)):
+        w = self.w
+        return select(w.inv_op[sl], target, w.n_hw, w.cfg_off, w.hw, w.batch,
+                      w.lat, w.cost)

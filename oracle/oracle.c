@@ -1,0 +1,286 @@
+/*
+ * CPU oracle for the per-invocation decision path of Llama (Romero, Zhao,
+ * Yadwadkar, Kozyrakis, "Llama: A Heterogeneous & Serverless Framework for
+ * Auto-Tuning Video Analytics Pipelines", arXiv 2102.01887).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this library.  The product path (the HIP
+ * library under paper_2102_01887_amd/) never calls, links or includes it, and
+ * this file includes nothing from there.
+ *
+ * It is written to be read against the paper, not to be fast: every loop is
+ * the plain definition, integer arithmetic is exact (128-bit products where
+ * a product could need it), and there is no blocking, sorting, ranking or
+ * precomputed index of any kind.
+ *
+ * What it computes
+ *   - reference latency of each operation (Sec. 3.2, Operation-Profiler: the
+ *     smallest CPU configuration, 1 core and batch 1);
+ *   - W[v], the largest remaining reference-path latency from v to any output
+ *     operation (Alg. 1, RemainingPathLatency, taken over every sequential
+ *     path that contains v; Sec. 4.1 says the path latency starts at op);
+ *   - the per-invocation, per-backend slack of Alg. 1:
+ *         min over paths P containing v of  ref[v] / pLat(v,P) * remaining
+ *     which, because floor(a/x) does not increase with x, equals
+ *         floor(ref[v] * remaining / W[v]);
+ *   - the Eq. 1 choice: among configurations whose latency is strictly below
+ *     the slack of their own backend, the one with the smallest cost per
+ *     item C/B, lowest caller index on ties; if none qualifies, the fastest
+ *     configuration (smallest L, lowest index on ties).
+ *
+ * Readings of points the paper leaves open (all integer):
+ *   - latencies and times are microseconds, costs nano-dollars;
+ *   - remaining = slo - elapsed - Q[h] in 64-bit, clamped to [0, 2^31-1];
+ *     a remaining time of 0 gives slack 0 (Alg. 1 is silent past the deadline);
+ *   - the slack is the floor of the exact quotient;
+ *   - PROB mode discounts each downstream edge by its branch probability,
+ *     q/65536 with q in [1, 65536], applied tail-first along the path with a
+ *     floor at every step; with every q = 65536 it is Alg. 1 exactly;
+ *   - an invocation is invalid when its op is out of range or its elapsed or
+ *     slo field is negative: its slack is -1 for every backend and its choice
+ *     is -1 with flag 0.
+ *
+ * Parity pins: the test suite checks this file against literal path
+ * enumeration with exact rationals on every 5-op DAG, against closed forms
+ * (single op, equal-reference chains, symmetric forks), against a worked
+ * example derived by hand from Alg. 1 and Eq. 1, and against invariants.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_OK 0
+#define ORACLE_E_ARG (-1)
+#define ORACLE_E_RANGE (-2)
+#define ORACLE_E_CYCLE (-3)
+#define ORACLE_E_STATE (-4)
+
+#define ORACLE_PAPER 0
+#define ORACLE_PROB 1
+
+#define Q_ONE 65536
+
+/*
+ * Reference configuration of each operation (Sec. 3.2): among the op's
+ * configurations on hardware type 0 (CPU) with batch 1, the one with the
+ * smallest resource size; the lowest caller index wins a tie.  An op with no
+ * such configuration is an error (ORACLE_E_STATE).  ref_k receives the local
+ * (per-op) index.
+ */
+int oracle_reference_cfg(int32_t n_ops, const int32_t *cfg_off,
+                         const int32_t *hw, const int32_t *batch,
+                         const int32_t *res, int32_t *ref_k)
+{
+    if (n_ops < 0 || !cfg_off || !hw || !batch || !res || !ref_k)
+        return ORACLE_E_ARG;
+    for (int32_t v = 0; v < n_ops; ++v) {
+        int32_t best = -1;
+        for (int32_t x = cfg_off[v]; x < cfg_off[v + 1]; ++x) {
+            if (hw[x] != 0 || batch[x] != 1)
+                continue;
+            if (best < 0 || res[x] < res[best])
+                best = x;
+        }
+        if (best < 0)
+            return ORACLE_E_STATE;
+        ref_k[v] = best - cfg_off[v];
+    }
+    return ORACLE_OK;
+}
+
+/* Value that the edge v->w contributes to W[v] (both modes). */
+static int64_t edge_value(int32_t mode, uint32_t q, int64_t w_succ)
+{
+    if (mode == ORACLE_PAPER)
+        return w_succ;
+    /* floor(q * W[w] / 65536), exact in 128 bits */
+    __int128 p = (__int128)q * (__int128)w_succ;
+    return (int64_t)(p / Q_ONE);
+}
+
+/*
+ * W[v] = ref[v] + max over successors w of edge_value(W[w]); W[v] = ref[v]
+ * at an output operation.  This is the largest remaining reference-path
+ * latency over every path from v to an output (in PROB mode the Horner form
+ * of the path latency, evaluated from the tail).
+ *
+ * Computed as a plain fixpoint: start from W = ref and sweep every op until
+ * nothing changes.  On a DAG this settles after at most (longest path + 1)
+ * sweeps; if it is still changing after n_ops + 1 sweeps the graph has a
+ * cycle.  succ_q16 may be NULL (every q = 65536).
+ */
+int oracle_worst_path(int32_t n_ops, const int32_t *succ_off,
+                      const int32_t *succ_ids, const uint32_t *succ_q16,
+                      const int64_t *ref_lat, int32_t mode, int64_t *W)
+{
+    if (n_ops < 0 || !succ_off || !ref_lat || !W)
+        return ORACLE_E_ARG;
+    if (mode != ORACLE_PAPER && mode != ORACLE_PROB)
+        return ORACLE_E_ARG;
+    for (int32_t v = 0; v < n_ops; ++v)
+        W[v] = ref_lat[v];
+    for (int64_t sweep = 0; sweep <= (int64_t)n_ops + 1; ++sweep) {
+        int changed = 0;
+        for (int32_t v = n_ops - 1; v >= 0; --v) {
+            int64_t m = 0;
+            for (int32_t e = succ_off[v]; e < succ_off[v + 1]; ++e) {
+                int32_t w = succ_ids[e];
+                if (w < 0 || w >= n_ops)
+                    return ORACLE_E_RANGE;
+                uint32_t q = succ_q16 ? succ_q16[e] : Q_ONE;
+                int64_t c = edge_value(mode, q, W[w]);
+                if (c > m)
+                    m = c;
+            }
+            int64_t nv = ref_lat[v] + m;
+            if (nv != W[v]) {
+                W[v] = nv;
+                changed = 1;
+            }
+        }
+        if (!changed)
+            return ORACLE_OK;
+    }
+    return ORACLE_E_CYCLE;
+}
+
+/* Remaining time for backend h (reading: clamped to [0, 2^31-1]). */
+static int64_t remaining_time(int32_t elapsed, int32_t slo, int64_t q)
+{
+    __int128 r = (__int128)slo - (__int128)elapsed - (__int128)q;
+    if (r < 0)
+        r = 0;
+    if (r > INT32_MAX)
+        r = INT32_MAX;
+    return (int64_t)r;
+}
+
+/*
+ * Alg. 1 for every invocation and every backend h:
+ *   target[i*n_hw + h] = floor(ref[v] * R_h / W[v]),  R_h = slo - elapsed - Q[h]
+ * Q may be NULL (all zero).  Invalid invocations get -1 for every backend.
+ */
+int oracle_targets(int64_t n_inv, const int32_t *inv_op,
+                   const int32_t *elapsed, const int32_t *slo, int32_t n_hw,
+                   const int64_t *Q, int32_t n_ops, const int64_t *ref_lat,
+                   const int64_t *W, int32_t *target)
+{
+    if (n_inv < 0 || n_hw < 1 || n_ops < 0)
+        return ORACLE_E_ARG;
+    if (n_inv > 0 && (!inv_op || !elapsed || !slo || !target))
+        return ORACLE_E_ARG;
+    if (!ref_lat || !W)
+        return ORACLE_E_ARG;
+    for (int64_t i = 0; i < n_inv; ++i) {
+        int32_t v = inv_op[i];
+        int valid = v >= 0 && v < n_ops && elapsed[i] >= 0 && slo[i] >= 0;
+        for (int32_t h = 0; h < n_hw; ++h) {
+            int32_t t = -1;
+            if (valid) {
+                int64_t R = remaining_time(elapsed[i], slo[i], Q ? Q[h] : 0);
+                __int128 num = (__int128)ref_lat[v] * (__int128)R;
+                t = (int32_t)(num / (__int128)W[v]);
+            }
+            target[i * n_hw + h] = t;
+        }
+    }
+    return ORACLE_OK;
+}
+
+/*
+ * Eq. 1 with the fallback "fastest": for invocation i of op v, scan every
+ * configuration x of v.  x is feasible when lat[x] < target[i][hw[x]]
+ * (strict, as in Eq. 1).  Among feasible x pick the smallest cost[x]/batch[x]
+ * (compared exactly by cross-multiplication), lowest index on ties; flag 1.
+ * If none is feasible pick the smallest lat[x], lowest index on ties; flag 0.
+ * cfg receives the local index (x - cfg_off[v]); an invocation whose op is
+ * out of range gets cfg -1, flag 0.  flag may be NULL.
+ */
+int oracle_select(int64_t n_inv, const int32_t *inv_op, const int32_t *target,
+                  int32_t n_hw, int32_t n_ops, const int32_t *cfg_off,
+                  const int32_t *hw, const int32_t *batch,
+                  const int32_t *lat, const int64_t *cost, int32_t *cfg,
+                  uint8_t *flag)
+{
+    if (n_inv < 0 || n_hw < 1 || n_ops < 0)
+        return ORACLE_E_ARG;
+    if (n_inv > 0 && (!inv_op || !target || !cfg))
+        return ORACLE_E_ARG;
+    if (!cfg_off || !hw || !batch || !lat || !cost)
+        return ORACLE_E_ARG;
+    for (int64_t i = 0; i < n_inv; ++i) {
+        int32_t v = inv_op[i];
+        if (v < 0 || v >= n_ops) {
+            cfg[i] = -1;
+            if (flag)
+                flag[i] = 0;
+            continue;
+        }
+        int32_t best = -1;
+        for (int32_t x = cfg_off[v]; x < cfg_off[v + 1]; ++x) {
+            int32_t h = hw[x];
+            if (h < 0 || h >= n_hw)
+                return ORACLE_E_RANGE;
+            if (!(lat[x] < target[i * n_hw + h]))
+                continue;
+            if (best < 0) {
+                best = x;
+                continue;
+            }
+            /* cost[x]/batch[x] < cost[best]/batch[best] ? */
+            __int128 lhs = (__int128)cost[x] * (__int128)batch[best];
+            __int128 rhs = (__int128)cost[best] * (__int128)batch[x];
+            if (lhs < rhs)
+                best = x;
+        }
+        if (best >= 0) {
+            cfg[i] = best - cfg_off[v];
+            if (flag)
+                flag[i] = 1;
+            continue;
+        }
+        int32_t fast = cfg_off[v];
+        for (int32_t x = cfg_off[v] + 1; x < cfg_off[v + 1]; ++x)
+            if (lat[x] < lat[fast])
+                fast = x;
+        cfg[i] = cfg_off[v + 1] > cfg_off[v] ? fast - cfg_off[v] : -1;
+        if (flag)
+            flag[i] = 0;
+    }
+    return ORACLE_OK;
+}
+
+/*
+ * The whole decision for each invocation: Alg. 1 slack for every backend,
+ * then the Eq. 1 choice.  Invalid invocations (op out of range, negative
+ * elapsed or slo) get cfg -1, flag 0.  target_scratch holds n_hw int32 and is
+ * the caller's (so this file allocates nothing per invocation).
+ */
+int oracle_decide(int64_t n_inv, const int32_t *inv_op, const int32_t *elapsed,
+                  const int32_t *slo, int32_t n_hw, const int64_t *Q,
+                  int32_t n_ops, const int64_t *ref_lat, const int64_t *W,
+                  const int32_t *cfg_off, const int32_t *hw,
+                  const int32_t *batch, const int32_t *lat,
+                  const int64_t *cost, int32_t *cfg, uint8_t *flag,
+                  int32_t *target_scratch)
+{
+    if (n_inv < 0 || n_hw < 1 || !target_scratch)
+        return ORACLE_E_ARG;
+    for (int64_t i = 0; i < n_inv; ++i) {
+        int rc = oracle_targets(1, inv_op + i, elapsed + i, slo + i, n_hw, Q,
+                                n_ops, ref_lat, W, target_scratch);
+        if (rc)
+            return rc;
+        if (target_scratch[0] < 0) {
+            cfg[i] = -1;
+            if (flag)
+                flag[i] = 0;
+            continue;
+        }
+        rc = oracle_select(1, inv_op + i, target_scratch, n_hw, n_ops, cfg_off,
+                           hw, batch, lat, cost, cfg + i, flag ? flag + i : 0);
+        if (rc)
+            return rc;
+    }
+    return ORACLE_OK;
+}

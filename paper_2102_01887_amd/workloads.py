@@ -1,0 +1,363 @@
+"""Seeded synthetic workloads for the decision path.
+
+This module only draws inputs: pipeline DAGs (CSR successor lists with branch
+probabilities in Q16), per-operation configuration tables (hardware type,
+batch, resource size, latency in integer microseconds, cost in integer
+nano-dollars) and pending invocations (op, elapsed time, SLO).  It computes
+none of the method's quantities (no reference latency, path latency, slack or
+choice), so both the GPU path and the CPU oracle can be fed from it.
+
+Shapes follow the paper's pipelines (Tab. 2: AMBER Alert is 5 ops with a
+branch and ~129 configurations per op; Toonify is parallel; Synthetic is a
+7-op chain), scaled up to data-parallel sizes.  All randomness is numpy's
+PCG64 (``np.random.default_rng(seed)``).
+"""
+from dataclasses import dataclass, field
+import hashlib
+from typing import Optional
+
+import numpy as np
+
+Q_ONE = 65536
+INT32_MAX = 2**31 - 1
+
+
+@dataclass
+class Workload:
+    name: str
+    n_hw: int
+    pipe_off: np.ndarray          # int32 [P+1]; pipeline p owns ops [pipe_off[p], pipe_off[p+1])
+    succ_off: np.ndarray          # int32 [n_ops+1] CSR over global op ids
+    succ_ids: np.ndarray          # int32 [n_edges]
+    succ_q16: np.ndarray          # uint32 [n_edges], branch probability * 65536, in [1, 65536]
+    cfg_off: np.ndarray           # int32 [n_ops+1]
+    hw: np.ndarray                # int32 [n_cfg]
+    batch: np.ndarray             # int32 [n_cfg]
+    res: np.ndarray               # int32 [n_cfg]
+    lat: np.ndarray               # int32 [n_cfg], microseconds, >= 1
+    cost: np.ndarray              # int64 [n_cfg], nano-dollars per configuration run
+    inv_op: np.ndarray            # int32 [n_inv]
+    elapsed: np.ndarray           # int32 [n_inv], microseconds
+    slo: np.ndarray               # int32 [n_inv], microseconds
+    Q: Optional[np.ndarray] = None        # int64 [n_hw] queueing time per backend
+    ref_cfg: Optional[np.ndarray] = None  # int32 [n_ops] or None (automatic rule)
+    hw_res_total: Optional[np.ndarray] = None
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_ops(self):
+        return len(self.cfg_off) - 1
+
+    @property
+    def n_pipelines(self):
+        return len(self.pipe_off) - 1
+
+    @property
+    def n_cfg(self):
+        return int(self.cfg_off[-1])
+
+    @property
+    def n_inv(self):
+        return len(self.inv_op)
+
+    def sha256(self):
+        h = hashlib.sha256()
+        for k in ("pipe_off", "succ_off", "succ_ids", "succ_q16", "cfg_off", "hw",
+                  "batch", "res", "lat", "cost", "inv_op", "elapsed", "slo"):
+            h.update(np.ascontiguousarray(getattr(self, k)).tobytes())
+        if self.Q is not None:
+            h.update(np.ascontiguousarray(self.Q).tobytes())
+        return h.hexdigest()
+
+    def with_invocations(self, inv_op, elapsed, slo, Q=None, name=None):
+        import copy
+        w = copy.copy(self)
+        w.inv_op = np.ascontiguousarray(inv_op, np.int32)
+        w.elapsed = np.ascontiguousarray(elapsed, np.int32)
+        w.slo = np.ascontiguousarray(slo, np.int32)
+        w.Q = None if Q is None else np.ascontiguousarray(Q, np.int64)
+        if name:
+            w.name = name
+        return w
+
+
+def csr_from_edges(n_ops, src, dst, q=None):
+    """CSR successor lists (sorted by destination within each source)."""
+    src = np.asarray(src, np.int64)
+    dst = np.asarray(dst, np.int64)
+    q = np.full(len(src), Q_ONE, np.int64) if q is None else np.asarray(q, np.int64)
+    order = np.lexsort((dst, src))
+    src, dst, q = src[order], dst[order], q[order]
+    off = np.zeros(n_ops + 1, np.int64)
+    np.add.at(off, src + 1, 1)
+    off = np.cumsum(off)
+    return off.astype(np.int32), dst.astype(np.int32), q.astype(np.uint32)
+
+
+# ---------------------------------------------------------------------------
+# DAG shapes
+# ---------------------------------------------------------------------------
+
+def layered_dag(rng, n, d):
+    """A layered DAG of n ops over d non-empty levels (ops numbered level by
+    level).  Each op of a non-final level gets U{1..3} distinct successors in
+    the next level; an op of a later level left without a predecessor gets
+    one from the previous level.  Branch probabilities q = round(U[0.05,1]*2^16).
+    Returns local (src, dst, q) edge arrays."""
+    cuts = np.sort(rng.choice(np.arange(1, n), d - 1, replace=False)) if d > 1 else np.array([], int)
+    bounds = np.concatenate([[0], cuts, [n]]).astype(np.int64)
+    src, dst = [], []
+    for l in range(d - 1):
+        a, b = bounds[l], bounds[l + 1]
+        c, e = bounds[l + 1], bounds[l + 2]
+        width = e - c
+        has_pred = np.zeros(width, bool)
+        for v in range(a, b):
+            k = int(rng.integers(1, 4))
+            k = min(k, width)
+            succ = rng.choice(width, k, replace=False)
+            has_pred[succ] = True
+            src.extend([v] * k)
+            dst.extend((c + succ).tolist())
+        for j in np.nonzero(~has_pred)[0]:
+            src.append(int(rng.integers(a, b)))
+            dst.append(int(c + j))
+    m = len(src)
+    q = np.clip(np.rint(rng.uniform(0.05, 1.0, m) * Q_ONE), 1, Q_ONE).astype(np.int64)
+    return np.asarray(src, np.int64), np.asarray(dst, np.int64), q
+
+
+def _assemble_dags(rng, sizes, depth_fn):
+    """Concatenate one layered DAG per pipeline into global CSR arrays."""
+    pipe_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    S, D, Qs = [], [], []
+    for p, n in enumerate(sizes):
+        d = depth_fn(int(n))
+        s, t, q = layered_dag(rng, int(n), d)
+        S.append(s + pipe_off[p])
+        D.append(t + pipe_off[p])
+        Qs.append(q)
+    n_ops = int(pipe_off[-1])
+    succ_off, succ_ids, succ_q16 = csr_from_edges(
+        n_ops, np.concatenate(S), np.concatenate(D), np.concatenate(Qs))
+    return pipe_off.astype(np.int32), succ_off, succ_ids, succ_q16
+
+
+# ---------------------------------------------------------------------------
+# Configuration 1: plain, tiny
+# ---------------------------------------------------------------------------
+
+def make_c1(seed=0, queue=False, n_inv=1000):
+    """One 6-op DAG: chain 0-1-2-3-4 plus a conditional branch 2->5 taken with
+    p = 0.3 (AMBER Alert's detect-then-branch shape).  2 hardware types,
+    batch {1,2,4,8} (8 configs/op, k = 4*hw + log2 B, resource 1),
+    per-(op,hw) L1 ~ U_int[1e3,1e5], gamma ~ U[0.3,0.9],
+    L(B) = clip(floor(L1 * B^gamma), 1e3, 1e5); cost ~ U_int[10, 1e4];
+    1000 invocations, SLO 500 ms, elapsed ~ U_int[0, SLO]."""
+    rng = np.random.default_rng(seed)
+    n_ops, n_hw = 6, 2
+    src = [0, 1, 2, 3, 2]
+    dst = [1, 2, 3, 4, 5]
+    q = [Q_ONE, Q_ONE, Q_ONE, Q_ONE, 19661]
+    succ_off, succ_ids, succ_q16 = csr_from_edges(n_ops, src, dst, q)
+    B = np.array([1, 2, 4, 8])
+    hw, batch, lat = [], [], []
+    for v in range(n_ops):
+        for h in range(n_hw):
+            L1 = int(rng.integers(1000, 100001))
+            g = rng.uniform(0.3, 0.9)
+            L = np.clip(np.floor(L1 * B.astype(float) ** g), 1000, 100000).astype(np.int64)
+            hw.extend([h] * 4)
+            batch.extend(B.tolist())
+            lat.extend(L.tolist())
+    n_cfg = n_ops * 8
+    cost = rng.integers(10, 10001, n_cfg).astype(np.int64)
+    inv_op = rng.integers(0, n_ops, n_inv).astype(np.int32)
+    slo = np.full(n_inv, 500000, np.int32)
+    elapsed = rng.integers(0, 500001, n_inv).astype(np.int32)
+    return Workload(
+        name="c1-plain-tiny" + ("-queue" if queue else ""), n_hw=n_hw,
+        pipe_off=np.array([0, n_ops], np.int32), succ_off=succ_off, succ_ids=succ_ids,
+        succ_q16=succ_q16, cfg_off=(np.arange(n_ops + 1) * 8).astype(np.int32),
+        hw=np.asarray(hw, np.int32), batch=np.asarray(batch, np.int32),
+        res=np.ones(n_cfg, np.int32), lat=np.asarray(lat, np.int32), cost=cost,
+        inv_op=inv_op, elapsed=elapsed, slo=slo,
+        Q=np.array([20000, 5000], np.int64) if queue else None,
+        meta={"seed": seed})
+
+
+# ---------------------------------------------------------------------------
+# Configurations 2 and 3: plain scaled / batched uneven
+# ---------------------------------------------------------------------------
+
+def _latency_cost(rng, n_ops, n_hw, cfg_off, hw, batch, mem, cost_model="uniform"):
+    """Per (op, hw): L1 ~ U_int[1e3,1e5], gamma ~ U[0.3,0.9], beta ~ U[0,0.5];
+    per op s ~ lognormal(0, 0.5);  L = clip(floor(s*L1*B^gamma*m^-beta), 1, 2^31-1).
+    Cost: max(1, floor(s * U_int[10, 1e4])) ("uniform"), or the paper-shaped
+    price_hw * m * L per run ("priced", Sec. 6 resource-second pricing)."""
+    n_cfg = len(hw)
+    s_op = rng.lognormal(0.0, 0.5, n_ops)
+    L1 = rng.integers(1000, 100001, (n_ops, n_hw)).astype(np.float64)
+    g = rng.uniform(0.3, 0.9, (n_ops, n_hw))
+    be = rng.uniform(0.0, 0.5, (n_ops, n_hw))
+    op_of = np.repeat(np.arange(n_ops), np.diff(cfg_off))
+    s = s_op[op_of]
+    lat = np.floor(s * L1[op_of, hw] * batch.astype(np.float64) ** g[op_of, hw]
+                   * mem.astype(np.float64) ** (-be[op_of, hw]))
+    lat = np.clip(lat, 1, INT32_MAX).astype(np.int32)
+    if cost_model == "uniform":
+        cost = np.maximum(1, np.floor(s * rng.integers(10, 10001, n_cfg))).astype(np.int64)
+    elif cost_model == "priced":
+        price = np.array([1, 3, 7, 12, 20, 30, 45, 60][:n_hw], np.int64)  # nano-$ per (unit * us)
+        cost = (price[hw] * mem.astype(np.int64) * lat.astype(np.int64)).astype(np.int64)
+    else:
+        raise ValueError(cost_model)
+    return lat, cost
+
+
+def _invocations(rng, pipe_off, n_inv, slo_lo=100_000, slo_hi=10_000_000):
+    P = len(pipe_off) - 1
+    sizes = np.diff(pipe_off).astype(np.int64)
+    p = rng.integers(0, P, n_inv)
+    local = np.minimum((rng.random(n_inv) * sizes[p]).astype(np.int64), sizes[p] - 1)
+    inv_op = (pipe_off[:-1].astype(np.int64)[p] + local).astype(np.int32)
+    slo = rng.integers(slo_lo, slo_hi + 1, n_inv).astype(np.int64)
+    elapsed = rng.integers(0, slo + 1).astype(np.int32)
+    return inv_op, elapsed, slo.astype(np.int32)
+
+
+def make_c2(seed=1, n_pipelines=256, n_inv=1_000_000, queue=False, cost_model="uniform"):
+    """256 layered DAGs of U{10..40} ops over U{3..min(10,n)} levels; 4 hardware
+    types x n_b ~ U{4..32} batch values ({1} plus distinct values in 2..64) x
+    memory {1,2,4,8} = 64..512 configs/op in caller order (hw, B, mem);
+    1M invocations, SLO ~ U_int[0.1 s, 10 s], elapsed ~ U_int[0, SLO]."""
+    rng = np.random.default_rng(seed)
+    n_hw = 4
+    sizes = rng.integers(10, 41, n_pipelines)
+    pipe_off, succ_off, succ_ids, succ_q16 = _assemble_dags(
+        rng, sizes, lambda n: int(rng.integers(3, min(10, n) + 1)))
+    n_ops = int(pipe_off[-1])
+    mem_vals = np.array([1, 2, 4, 8], np.int32)
+    counts = np.empty(n_ops, np.int64)
+    HW, BB, MM = [], [], []
+    for v in range(n_ops):
+        nb = int(rng.integers(4, 33))
+        bs = np.concatenate([[1], np.sort(rng.choice(np.arange(2, 65), nb - 1, replace=False))])
+        h, b, m = np.meshgrid(np.arange(n_hw), bs, mem_vals, indexing="ij")
+        HW.append(h.ravel()); BB.append(b.ravel()); MM.append(m.ravel())
+        counts[v] = h.size
+    cfg_off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    hw = np.concatenate(HW).astype(np.int32)
+    batch = np.concatenate(BB).astype(np.int32)
+    res = np.concatenate(MM).astype(np.int32)
+    lat, cost = _latency_cost(rng, n_ops, n_hw, cfg_off, hw, batch, res, cost_model)
+    inv_op, elapsed, slo = _invocations(rng, pipe_off, n_inv)
+    Q = rng.integers(0, 50001, n_hw).astype(np.int64) if queue else None
+    return Workload(
+        name="c2-plain-scaled" + ("-queue" if queue else "") + ("" if cost_model == "uniform" else "-" + cost_model),
+        n_hw=n_hw, pipe_off=pipe_off, succ_off=succ_off, succ_ids=succ_ids,
+        succ_q16=succ_q16, cfg_off=cfg_off, hw=hw, batch=batch, res=res, lat=lat,
+        cost=cost, inv_op=inv_op, elapsed=elapsed, slo=slo, Q=Q,
+        meta={"seed": seed, "n_pipelines": n_pipelines})
+
+
+def make_c3(seed=2, n_pipelines=4096, n_inv=4_000_000, max_ops=200, max_cfg=2048):
+    """4096 pipelines with op counts round(exp(U[ln 3, ln 200])) (the C2 DAG
+    generator); configs/op round(exp(U[ln 16, ln 2048])): the reference triple
+    (hw 0, B 1, mem 1) plus distinct (hw, B, mem) triples drawn from the
+    4 x 64 x 8 grid (B in 1..64, mem in 1..128 powers of two), caller order
+    (hw, B, mem); 4M invocations as in C2."""
+    rng = np.random.default_rng(seed)
+    n_hw = 4
+    sizes = np.rint(np.exp(rng.uniform(np.log(3), np.log(max_ops), n_pipelines))).astype(np.int64)
+    pipe_off, succ_off, succ_ids, succ_q16 = _assemble_dags(
+        rng, sizes, lambda n: int(rng.integers(3, min(10, n) + 1)))
+    n_ops = int(pipe_off[-1])
+    grid = 4 * 64 * 8
+    c = np.rint(np.exp(rng.uniform(np.log(16), np.log(max_cfg), n_ops))).astype(np.int64)
+    c = np.minimum(c, grid)
+    cfg_off = np.concatenate([[0], np.cumsum(c)]).astype(np.int64)
+    idx = np.empty(int(cfg_off[-1]), np.int64)
+    for v in range(n_ops):
+        a = int(cfg_off[v])
+        idx[a] = 0
+        idx[a + 1:a + c[v]] = np.sort(rng.choice(grid - 1, c[v] - 1, replace=False) + 1)
+    hw = (idx // 512).astype(np.int32)
+    batch = ((idx // 8) % 64 + 1).astype(np.int32)
+    res = (1 << (idx % 8)).astype(np.int32)
+    del idx
+    lat, cost = _latency_cost(rng, n_ops, n_hw, cfg_off, hw, batch, res)
+    inv_op, elapsed, slo = _invocations(rng, pipe_off, n_inv)
+    return Workload(
+        name="c3-batched-uneven", n_hw=n_hw, pipe_off=pipe_off, succ_off=succ_off,
+        succ_ids=succ_ids, succ_q16=succ_q16, cfg_off=cfg_off.astype(np.int32), hw=hw,
+        batch=batch, res=res, lat=lat, cost=cost, inv_op=inv_op, elapsed=elapsed,
+        slo=slo, meta={"seed": seed, "n_pipelines": n_pipelines})
+
+
+# ---------------------------------------------------------------------------
+# Small random problems for exhaustive / fuzz checks
+# ---------------------------------------------------------------------------
+
+def random_table(rng, n_ops, n_hw, cfg_lo=1, cfg_hi=8, lat_hi=50, cost_hi=30, batch_hi=4,
+                 with_reference=True):
+    """Random per-op tables with small value ranges (many ties).  When
+    with_reference, every op's first configuration is (hw 0, batch 1, res 1)."""
+    counts = rng.integers(cfg_lo, cfg_hi + 1, n_ops)
+    cfg_off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    n = int(cfg_off[-1])
+    hw = rng.integers(0, n_hw, n).astype(np.int32)
+    batch = rng.integers(1, batch_hi + 1, n).astype(np.int32)
+    res = rng.integers(1, 4, n).astype(np.int32)
+    lat = rng.integers(1, lat_hi + 1, n).astype(np.int32)
+    cost = rng.integers(0, cost_hi + 1, n).astype(np.int64)
+    if with_reference:
+        first = cfg_off[:-1]
+        hw[first] = 0
+        batch[first] = 1
+        res[first] = 1
+    return cfg_off, hw, batch, res, lat, cost
+
+
+def dag_from_mask(n_ops, mask):
+    """DAG on n_ops vertices whose edge set is the bitmask over the
+    upper-triangular pairs (i<j) in row-major order."""
+    src, dst = [], []
+    bit = 0
+    for i in range(n_ops):
+        for j in range(i + 1, n_ops):
+            if (mask >> bit) & 1:
+                src.append(i)
+                dst.append(j)
+            bit += 1
+    return src, dst
+
+
+def random_small(rng, n_ops=None, n_hw=None, n_inv=64, edge_p=0.35, name="fuzz",
+                 q_choices=None, max_ref=1000, slo_hi=20000):
+    """A single-pipeline random DAG (edges only from lower to higher ids, then
+    relabelled by a random permutation) with a random small table."""
+    n_ops = int(rng.integers(1, 9)) if n_ops is None else n_ops
+    n_hw = int(rng.integers(1, 4)) if n_hw is None else n_hw
+    src, dst = [], []
+    for i in range(n_ops):
+        for j in range(i + 1, n_ops):
+            if rng.random() < edge_p:
+                src.append(i)
+                dst.append(j)
+    perm = rng.permutation(n_ops)
+    src = [int(perm[s]) for s in src]
+    dst = [int(perm[t]) for t in dst]
+    if q_choices is None:
+        q = rng.integers(1, Q_ONE + 1, len(src))
+    else:
+        q = rng.choice(np.asarray(q_choices), len(src))
+    succ_off, succ_ids, succ_q16 = csr_from_edges(n_ops, src, dst, q)
+    cfg_off, hw, batch, res, lat, cost = random_table(rng, n_ops, n_hw, lat_hi=max_ref)
+    inv_op = rng.integers(0, n_ops, n_inv).astype(np.int32)
+    slo = rng.integers(0, slo_hi + 1, n_inv).astype(np.int32)
+    elapsed = rng.integers(0, slo_hi + 1, n_inv).astype(np.int32)
+    return Workload(name=name, n_hw=n_hw, pipe_off=np.array([0, n_ops], np.int32),
+                    succ_off=succ_off, succ_ids=succ_ids, succ_q16=succ_q16,
+                    cfg_off=cfg_off, hw=hw, batch=batch, res=res, lat=lat, cost=cost,
+                    inv_op=inv_op, elapsed=elapsed, slo=slo)
