@@ -1,0 +1,260 @@
+/*
+ * llama.h -- C ABI of the MI355X (gfx950) decision engine for Llama
+ * (Romero, Zhao, Yadwadkar, Kozyrakis, arXiv 2102.01887).
+ *
+ * For every pending operation invocation the library computes, on the GPU,
+ *   (1) the invocation's latency target ("slack") for every backend, by
+ *       splitting the remaining end-to-end time along the remaining DAG path
+ *       weighted by reference-configuration latencies (Alg. 1, Sec. 4.1), and
+ *   (2) the cheapest configuration of the operation whose latency is strictly
+ *       below the slack of its own backend, by cost per item C/B, or the
+ *       fastest configuration when none qualifies (Eq. 1, Sec. 4.2, with the
+ *       fallback weight alpha taken as unbounded).
+ *
+ * Units: latencies and times are int32 microseconds, costs int64 nano-dollars
+ * per configuration run.  All arithmetic is integer, so results are exact.
+ *
+ * Conventions for every function:
+ *   - return LLAMA_OK (0) or a negative status; no exception crosses the ABI;
+ *     on failure llama_last_error() describes the first problem found and
+ *     outputs are unspecified;
+ *   - "host" pointers are read during the call only; the library copies what
+ *     it keeps, so the caller may free them on return;
+ *   - "device" pointers are caller-owned GPU memory (for example torch
+ *     tensors) and are never retained after the work enqueued by the call;
+ *   - `stream` is a hipStream_t (NULL = the default stream); decision calls
+ *     only enqueue work and return; outputs are valid once the stream has
+ *     synchronised; they may be captured into a hipGraph and allocate
+ *     nothing, except the full-scan scratch growth described at
+ *     llama_decide;
+ *   - a context is not thread-safe: use one per thread or lock around it.
+ */
+#ifndef LLAMA_H
+#define LLAMA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct llama_ctx llama_ctx;
+
+enum llama_status {
+    LLAMA_OK = 0,
+    LLAMA_E_ARG = -1,    /* null pointer, negative count, bad enum, size mismatch */
+    LLAMA_E_RANGE = -2,  /* a value outside the documented bounds below */
+    LLAMA_E_CYCLE = -3,  /* the successor lists contain a cycle */
+    LLAMA_E_STATE = -4,  /* call order, missing reference configuration */
+    LLAMA_E_DEVICE = -5, /* HIP runtime error (text in llama_last_error) */
+    LLAMA_E_NOMEM = -6   /* device or host allocation failed */
+};
+
+/* Path latency used by the slack (Alg. 1 RemainingPathLatency). */
+enum llama_slack_mode {
+    /* Sum of reference latencies from op (inclusive) to the output; slack is
+     * the minimum over all paths through op (Alg. 1 as printed). */
+    LLAMA_SLACK_PAPER = 0,
+    /* Each downstream edge is discounted by its branch probability q/65536,
+     * applied tail-first with a floor at every step; equals PAPER when every
+     * q = 65536. */
+    LLAMA_SLACK_PROB = 1
+};
+
+/* How llama_decide evaluates Eq. 1 (the result is identical in every mode). */
+enum llama_scan_mode {
+    LLAMA_SCAN_AUTO = 0,    /* library's choice (currently INDEXED) */
+    /* Each op's cost/latency frontier over all backends, turned into
+     * remaining-time thresholds (one 64-byte record per op). */
+    LLAMA_SCAN_INDEXED = 1,
+    /* Every configuration of the op: invocations are bucketed by op on the
+     * GPU and each wavefront scans one op's table for its invocations.  Uses
+     * context scratch of 4 bytes per invocation (see llama_reserve). */
+    LLAMA_SCAN_FULL = 2,
+    /* Every configuration, one wavefront per invocation, lanes over the
+     * configurations, wavefront min reduction; no scratch. */
+    LLAMA_SCAN_WAVE = 3
+};
+
+#define LLAMA_MAX_HW 8                 /* backends (hardware types) */
+#define LLAMA_MAX_CFG_PER_OP 65535     /* configurations of one operation */
+#define LLAMA_MAX_COST ((int64_t)1 << 40)
+#define LLAMA_MAX_BATCH 65536
+#define LLAMA_Q_ONE 65536              /* branch probability 1.0 in Q16 */
+
+/* Device error word bits (llama_stats.device_error). */
+#define LLAMA_DEVERR_INVALID_INVOCATION 1u
+
+/* Create a context bound to HIP device `device` (its ordinal). */
+int llama_create(llama_ctx **out, int32_t device);
+
+/* Release a context and every device buffer it owns; NULL is ignored.
+ * Waits for the context's own work; the caller must have synchronised any
+ * stream that still runs decision work against it. */
+void llama_destroy(llama_ctx *ctx);
+
+/* Text of the last failure on this context ("" after success).  The string
+ * belongs to the context and is valid until its next call. */
+const char *llama_last_error(const llama_ctx *ctx);
+
+/*
+ * Pipeline DAGs (Sec. 3.2 Application Interface and Pipeline-Decomposer;
+ * Sec. 2 sequential, parallel and branching patterns).  All host pointers.
+ *
+ *   n_pipelines      >= 1
+ *   pipe_op_offsets  [n_pipelines+1], pipeline p owns the global op ids
+ *                    [off[p], off[p+1]); off[0] = 0, non-decreasing;
+ *                    n_ops = off[n_pipelines] >= 1
+ *   succ_offsets     [n_ops+1] CSR row offsets of successor lists
+ *   succ_ids         [n_edges] successor op ids; every edge stays inside its
+ *                    pipeline; no self-loops
+ *   succ_prob_q16    [n_edges] branch probability * 65536 in [1, 65536];
+ *                    NULL means 65536 (unconditional) for every edge
+ *
+ * Every op with no successor is an output operation, every op with no
+ * predecessor an input operation; any number of either is accepted.
+ * Errors: LLAMA_E_ARG, LLAMA_E_RANGE (ids, probabilities, pipeline bounds),
+ * LLAMA_E_CYCLE.  Replaces any previous DAG and drops the profile tables
+ * (llama_set_profiles must be called again).
+ */
+int llama_set_dag(llama_ctx *ctx, int32_t n_pipelines,
+                  const int32_t *pipe_op_offsets, const int32_t *succ_offsets,
+                  const int32_t *succ_ids, const uint32_t *succ_prob_q16);
+
+/*
+ * Configuration specifications of every operation (Sec. 3.2
+ * Operation-Profiler: knob values, latency and resource use per
+ * configuration; reference configuration).  All host pointers; row x of op v
+ * lies in [cfg_offsets[v], cfg_offsets[v+1]) and its local (caller) index
+ * k = x - cfg_offsets[v] is what llama_select / llama_decide return.
+ *
+ *   n_ops          must equal the DAG's op count (llama_set_dag first)
+ *   n_hw           number of backends, 1..LLAMA_MAX_HW
+ *   cfg_offsets    [n_ops+1]; 1..LLAMA_MAX_CFG_PER_OP configurations per op
+ *   cfg_hw         [n_cfg] backend of the configuration, 0..n_hw-1
+ *                  (0 is the CPU backend used by the reference rule)
+ *   cfg_batch      [n_cfg] batch size B, 1..LLAMA_MAX_BATCH
+ *   cfg_res        [n_cfg] resource size R (cores, MB, ...), >= 1
+ *   cfg_lat_us     [n_cfg] profiled latency L, >= 1
+ *   cfg_cost_nusd  [n_cfg] cost C of one run, 0..LLAMA_MAX_COST
+ *   ref_cfg        [n_ops] local index of each op's reference configuration,
+ *                  or NULL for the paper's rule: the hw-0 (CPU), batch-1
+ *                  configuration with the smallest resource size, lowest
+ *                  index on ties (LLAMA_E_STATE if an op has none)
+ *   hw_res_total   [n_hw] resource limit per backend (R_total of Eq. 1 and
+ *                  Eq. 2), >= 1; may be NULL (not used by the decision)
+ *
+ * Also bounded: (ops in a pipeline) * (largest reference latency in it)
+ * < 2^46, so every path latency and every intermediate product fits int64.
+ * Builds the device tables and computes the remaining-path latencies for
+ * both slack modes before returning (synchronously).
+ */
+int llama_set_profiles(llama_ctx *ctx, int32_t n_ops, int32_t n_hw,
+                       const int32_t *cfg_offsets, const int32_t *cfg_hw,
+                       const int32_t *cfg_batch, const int32_t *cfg_res,
+                       const int32_t *cfg_lat_us, const int64_t *cfg_cost_nusd,
+                       const int32_t *ref_cfg, const int64_t *hw_res_total);
+
+/*
+ * Recompute, on `stream`, the largest remaining reference-path latency W[v]
+ * of every op for both slack modes (Alg. 1 RemainingPathLatency with the
+ * minimum over paths, as a level-synchronous longest-path relaxation from the
+ * outputs upward) and the per-configuration remaining-time thresholds that
+ * llama_decide uses.  llama_set_profiles already does this; call it again
+ * after changing reference latencies (llama_update_latencies).
+ */
+int llama_relax(llama_ctx *ctx, void *stream);
+
+/*
+ * Replace the profiled latency of every configuration (for example after
+ * feedback, Sec. 3.3 Manager) without changing the table's shape; host
+ * pointer [n_cfg], same bounds as in llama_set_profiles.  Rebuilds the
+ * frontier tables and runs llama_relax synchronously.
+ */
+int llama_update_latencies(llama_ctx *ctx, const int32_t *cfg_lat_us);
+
+/*
+ * Alg. 1 for n_inv invocations (device pointers):
+ *   d_inv_op      [n_inv] global op id of the invocation
+ *   d_elapsed_us  [n_inv] time already spent by the invocation's pipeline run
+ *   d_slo_us      [n_inv] the pipeline's end-to-end latency target
+ *   d_queue_us    [n_hw] estimated queueing time per backend (Eq. 2), or NULL
+ *                 for zero
+ *   slack_mode    LLAMA_SLACK_PAPER or LLAMA_SLACK_PROB
+ *   d_target_us   [n_inv * n_hw] output, row-major (invocation, backend):
+ *                 R = clamp(slo - elapsed - queue[h], 0, 2^31-1) and
+ *                 target = R == 0 ? 0 : floor(ref[v] * R / W[v])
+ * An invocation with op outside [0, n_ops) or a negative elapsed or slo is
+ * invalid: its targets are -1 and the device error word records it.
+ */
+int llama_targets(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
+                  const int32_t *d_elapsed_us, const int32_t *d_slo_us,
+                  const int64_t *d_queue_us, int32_t slack_mode,
+                  int32_t *d_target_us, void *stream);
+
+/*
+ * Eq. 1 given targets (device pointers):
+ *   d_target_us   [n_inv * n_hw] as written by llama_targets (any values)
+ *   d_cfg         [n_inv] output: local index of the configuration with the
+ *                 smallest C/B among those with L < target[hw], lowest index
+ *                 on ties; if none, the smallest L, lowest index on ties;
+ *                 -1 for an op outside [0, n_ops)
+ *   d_flag        [n_inv] output: 1 = a configuration met its slack,
+ *                 0 = fallback or invalid; may be NULL
+ */
+int llama_select(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
+                 const int32_t *d_target_us, int32_t *d_cfg, uint8_t *d_flag,
+                 void *stream);
+
+/*
+ * llama_targets followed by llama_select, fused, without materialising the
+ * targets.  Same arguments and results; scan_mode picks the evaluation
+ * strategy (every mode gives identical outputs).
+ *
+ * Context-owned device buffers used per call: with d_queue_us != NULL the
+ * INDEXED mode rebuilds the op records for that queue vector, and the FULL
+ * mode buckets invocations; two such calls on one context must therefore not
+ * run concurrently on different streams.  The FULL mode needs scratch for
+ * n_inv invocations: the library grows it on demand, except while `stream`
+ * is being captured into a graph (then LLAMA_E_STATE; call llama_reserve
+ * first).
+ */
+int llama_decide(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
+                 const int32_t *d_elapsed_us, const int32_t *d_slo_us,
+                 const int64_t *d_queue_us, int32_t slack_mode,
+                 int32_t scan_mode, int32_t *d_cfg, uint8_t *d_flag,
+                 void *stream);
+
+/* Pre-size the scratch that LLAMA_SCAN_FULL needs for batches of up to
+ * max_inv invocations (device memory, 4 bytes per invocation).  Synchronous. */
+int llama_reserve(llama_ctx *ctx, int64_t max_inv);
+
+/* Context-level counters (Tab. 3 analogue).  Synchronises the context. */
+typedef struct llama_stats {
+    int32_t n_ops, n_hw, n_pipelines, max_depth;
+    int64_t n_cfg, n_edges;
+    int64_t frontier_entries;   /* entries in the per-(op, backend) frontiers */
+    uint32_t device_error;      /* LLAMA_DEVERR_* bits seen since the last reset */
+    int64_t device_bytes;       /* device memory owned by the context */
+} llama_stats;
+
+/* Fill *out; when reset_error is non-zero, clear the device error word. */
+int llama_get_stats(llama_ctx *ctx, llama_stats *out, int32_t reset_error);
+
+/*
+ * Copy internal tables to host memory, for tests of the ingest step:
+ *   what = 0: W for PAPER mode   (int64 [n_ops])
+ *   what = 1: W for PROB mode    (int64 [n_ops])
+ *   what = 2: packed keys, caller order (uint32 [n_cfg]): rank << 16 | k,
+ *             where rank is the dense rank of C/B within the op
+ *   what = 3: reference latency  (int32 [n_ops])
+ *   what = 4: fastest config     (int32 [n_ops], local index)
+ * `bytes` is the capacity of `host_out`; LLAMA_E_ARG if it is too small.
+ */
+int llama_debug_export(llama_ctx *ctx, int32_t what, void *host_out, int64_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LLAMA_H */

@@ -1,0 +1,229 @@
+"""ctypes binding of libllama (include/llama.h).
+
+Argument marshalling only: host tables are passed as numpy arrays, device
+buffers as torch CUDA tensors (their data_ptr()), streams as torch streams
+(their HIP handle).  Every step of the decision runs in the library's HIP
+kernels; there is no Python or CPU fallback, and a missing library is an
+ImportError.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libllama.so")
+
+OK, E_ARG, E_RANGE, E_CYCLE, E_STATE, E_DEVICE, E_NOMEM = 0, -1, -2, -3, -4, -5, -6
+SLACK_PAPER, SLACK_PROB = 0, 1
+SCAN_AUTO, SCAN_INDEXED, SCAN_FULL, SCAN_WAVE = 0, 1, 2, 3
+SCANS = (SCAN_INDEXED, SCAN_FULL, SCAN_WAVE)
+DEVERR_INVALID_INVOCATION = 1
+
+EXPORTS = ["llama_create", "llama_destroy", "llama_last_error", "llama_set_dag",
+           "llama_set_profiles", "llama_relax", "llama_update_latencies", "llama_targets",
+           "llama_select", "llama_decide", "llama_reserve", "llama_get_stats",
+           "llama_debug_export"]
+
+
+class LlamaStats(ctypes.Structure):
+    _fields_ = [("n_ops", ctypes.c_int32), ("n_hw", ctypes.c_int32),
+                ("n_pipelines", ctypes.c_int32), ("max_depth", ctypes.c_int32),
+                ("n_cfg", ctypes.c_int64), ("n_edges", ctypes.c_int64),
+                ("frontier_entries", ctypes.c_int64), ("device_error", ctypes.c_uint32),
+                ("device_bytes", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libllama.so and declare the C signatures."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2102_01887_amd.build`")
+    L = ctypes.CDLL(path)
+    p, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    sig = {
+        "llama_create": [ctypes.POINTER(p), i32],
+        "llama_destroy": [p],
+        "llama_last_error": [p],
+        "llama_set_dag": [p, i32, p, p, p, p],
+        "llama_set_profiles": [p, i32, i32, p, p, p, p, p, p, p, p],
+        "llama_relax": [p, p],
+        "llama_update_latencies": [p, p],
+        "llama_targets": [p, i64, p, p, p, p, i32, p, p],
+        "llama_select": [p, i64, p, p, p, p, p],
+        "llama_decide": [p, i64, p, p, p, p, i32, i32, p, p, p],
+        "llama_reserve": [p, i64],
+        "llama_get_stats": [p, ctypes.POINTER(LlamaStats), i32],
+        "llama_debug_export": [p, i32, p, i64],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.llama_destroy.restype = None
+    L.llama_last_error.restype = ctypes.c_char_p
+    if path == LIB_PATH:
+        _lib = L
+    return L
+
+
+class LlamaError(RuntimeError):
+    def __init__(self, fn, rc, msg):
+        super().__init__(f"{fn} failed ({rc}): {msg}")
+        self.rc = rc
+
+
+def _np(a, dtype):
+    return None if a is None else np.ascontiguousarray(a, dtype=dtype)
+
+
+def _hp(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dp(t, dtype_name, n=None):
+    """Device pointer of a contiguous CUDA tensor of the given dtype."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if str(t.dtype) != "torch." + dtype_name:
+        raise ValueError(f"expected torch.{dtype_name}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if n is not None and t.numel() < n:
+        raise ValueError(f"tensor has {t.numel()} elements, need {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Llama:
+    """One library context on one device."""
+
+    def __init__(self, device=0):
+        self._L = load_library()
+        self._ctx = ctypes.c_void_p()
+        rc = self._L.llama_create(ctypes.byref(self._ctx), int(device))
+        if rc != OK:
+            raise LlamaError("llama_create", rc, "no usable HIP device")
+        self.device = device
+        self.n_ops = self.n_hw = None
+        self._keep = None
+
+    def close(self):
+        if self._ctx:
+            self._L.llama_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, fn, rc):
+        if rc != OK:
+            raise LlamaError(fn, rc, self._L.llama_last_error(self._ctx).decode())
+
+    # -- ingest -------------------------------------------------------------
+    def set_dag(self, pipe_off, succ_off, succ_ids, succ_q16=None):
+        pipe_off, succ_off, succ_ids = (_np(x, np.int32) for x in (pipe_off, succ_off, succ_ids))
+        q = _np(succ_q16, np.uint32)
+        self._check("llama_set_dag", self._L.llama_set_dag(
+            self._ctx, len(pipe_off) - 1, _hp(pipe_off), _hp(succ_off), _hp(succ_ids), _hp(q)))
+        self.n_ops = int(pipe_off[-1])
+
+    def set_profiles(self, n_hw, cfg_off, hw, batch, res, lat, cost, ref_cfg=None,
+                     hw_res_total=None):
+        cfg_off, hw, batch, res, lat = (_np(x, np.int32) for x in (cfg_off, hw, batch, res, lat))
+        cost = _np(cost, np.int64)
+        ref = _np(ref_cfg, np.int32)
+        tot = _np(hw_res_total, np.int64)
+        self._check("llama_set_profiles", self._L.llama_set_profiles(
+            self._ctx, len(cfg_off) - 1, int(n_hw), _hp(cfg_off), _hp(hw), _hp(batch), _hp(res),
+            _hp(lat), _hp(cost), _hp(ref), _hp(tot)))
+        self.n_hw = int(n_hw)
+        self.n_cfg = int(cfg_off[-1])
+
+    def load(self, w):
+        """set_dag + set_profiles from a workloads.Workload."""
+        self.set_dag(w.pipe_off, w.succ_off, w.succ_ids, w.succ_q16)
+        self.set_profiles(w.n_hw, w.cfg_off, w.hw, w.batch, w.res, w.lat, w.cost, w.ref_cfg,
+                          w.hw_res_total)
+        return self
+
+    def update_latencies(self, lat):
+        lat = _np(lat, np.int32)
+        self._check("llama_update_latencies", self._L.llama_update_latencies(self._ctx, _hp(lat)))
+
+    def reserve(self, max_inv):
+        self._check("llama_reserve", self._L.llama_reserve(self._ctx, int(max_inv)))
+
+    def relax(self, stream=None):
+        self._check("llama_relax", self._L.llama_relax(self._ctx, _stream(stream)))
+
+    # -- decisions (device tensors) --------------------------------------------
+    def targets(self, op, elapsed, slo, queue=None, mode=SLACK_PAPER, out=None, stream=None):
+        import torch
+        n = op.numel()
+        if out is None:
+            out = torch.empty((n, self.n_hw), dtype=torch.int32, device=op.device)
+        self._check("llama_targets", self._L.llama_targets(
+            self._ctx, n, _dp(op, "int32"), _dp(elapsed, "int32", n), _dp(slo, "int32", n),
+            _dp(queue, "int64", self.n_hw), int(mode), _dp(out, "int32", n * self.n_hw),
+            _stream(stream)))
+        return out
+
+    def select(self, op, target, cfg=None, flag=None, stream=None):
+        import torch
+        n = op.numel()
+        if cfg is None:
+            cfg = torch.empty(n, dtype=torch.int32, device=op.device)
+        if flag is None:
+            flag = torch.empty(n, dtype=torch.uint8, device=op.device)
+        self._check("llama_select", self._L.llama_select(
+            self._ctx, n, _dp(op, "int32"), _dp(target, "int32", n * self.n_hw),
+            _dp(cfg, "int32", n), _dp(flag, "uint8", n), _stream(stream)))
+        return cfg, flag
+
+    def decide(self, op, elapsed, slo, queue=None, mode=SLACK_PAPER, scan=SCAN_AUTO, cfg=None,
+               flag=None, stream=None, with_flag=True):
+        import torch
+        n = op.numel()
+        if cfg is None:
+            cfg = torch.empty(n, dtype=torch.int32, device=op.device)
+        if flag is None and with_flag:
+            flag = torch.empty(n, dtype=torch.uint8, device=op.device)
+        self._check("llama_decide", self._L.llama_decide(
+            self._ctx, n, _dp(op, "int32"), _dp(elapsed, "int32", n), _dp(slo, "int32", n),
+            _dp(queue, "int64", self.n_hw), int(mode), int(scan), _dp(cfg, "int32", n),
+            _dp(flag, "uint8", n), _stream(stream)))
+        return cfg, flag
+
+    # -- introspection ----------------------------------------------------------
+    def stats(self, reset_error=False):
+        s = LlamaStats()
+        self._check("llama_get_stats", self._L.llama_get_stats(self._ctx, ctypes.byref(s),
+                                                               1 if reset_error else 0))
+        return {k: getattr(s, k) for k, _ in LlamaStats._fields_}
+
+    def export(self, what):
+        n_ops, n_cfg = self.n_ops, self.n_cfg
+        spec = {"W_paper": (0, np.int64, n_ops), "W_prob": (1, np.int64, n_ops),
+                "key": (2, np.uint32, n_cfg), "ref": (3, np.int32, n_ops),
+                "fastest": (4, np.int32, n_ops)}
+        code, dt, n = spec[what]
+        out = np.empty(n, dt)
+        self._check("llama_debug_export", self._L.llama_debug_export(
+            self._ctx, code, _hp(out), out.nbytes))
+        return out

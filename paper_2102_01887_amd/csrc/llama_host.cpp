@@ -1,0 +1,738 @@
+// Host side of libllama: argument validation, ingest of the pipeline DAGs
+// and configuration tables into device-resident layouts, and the launches of
+// the decision kernels.  Implements include/llama.h.
+//
+// Ingest (once per llama_set_dag / llama_set_profiles, not per decision):
+//   * heights of every op above the outputs (reverse Kahn order), used by the
+//     level-synchronous relaxation on the GPU; a cycle is rejected;
+//   * the reference latency of each op (Sec. 3.2: smallest CPU configuration,
+//     1 core and batch 1, unless the caller names one);
+//   * the dense rank of each configuration's cost per item C/B within its op
+//     (equal rationals share a rank), packed with the caller index as
+//     key = rank << 16 | k, so that the smallest key is the cheapest
+//     configuration with the lowest index among equals (Eq. 1 tie rule);
+//   * the fastest configuration of each op (smallest L, lowest index);
+//   * per (op, backend), the cost/latency frontier: configurations of that
+//     backend sorted by latency, keeping each one whose key is smaller than
+//     every faster one's.  The feasible set for any slack is a latency prefix,
+//     so its cheapest member is the last frontier entry inside the prefix;
+//   * the full table grouped by (op, backend) for the scan that visits every
+//     configuration.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "llama.h"
+#include "llama_internal.h"
+
+using llama::DevTables;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+}  // namespace
+
+struct llama_ctx {
+  int device = 0;
+  std::string err;
+  hipStream_t stream = nullptr;  // the context's own stream for ingest work
+
+  // DAG
+  bool has_dag = false;
+  int32_t n_pipelines = 0, n_ops = 0, max_depth = 0;
+  int64_t n_edges = 0;
+  std::vector<int32_t> pipe_off, succ_off, succ_ids, pipe_of;
+  std::vector<uint32_t> succ_q;
+  DevBuf d_pipe_off, d_pipe_lvl, d_lvl_bnd, d_lvl_ops, d_succ_off, d_succ_ids, d_succ_q;
+
+  // profiles
+  bool has_prof = false;
+  int32_t n_hw = 0;
+  int64_t n_cfg = 0, n_front = 0;
+  std::vector<int32_t> cfg_off, hw, batch, res, lat, ref_k, ref, fastest;
+  std::vector<int64_t> cost;
+  std::vector<uint32_t> key;  // caller order
+  DevBuf d_ref, d_W, d_hdr, d_front_L, d_rec, d_ovf, d_rec_q, d_ovf_q, d_seg_off, d_tab;
+  DevBuf d_mst, d_mst_op, d_mst_first;
+  int64_t n_mst = 0;
+  DevBuf d_err;
+  DevBuf d_cnt, d_start, d_cursor, d_perm, d_hist;  // bucketed full scan
+  int64_t perm_cap = 0;
+
+  DevTables tables() const {
+    DevTables t{};
+    t.n_ops = n_ops;
+    t.n_hw = n_hw;
+    t.n_pipelines = n_pipelines;
+    t.hs = llama::header_stride(n_hw);
+    t.n_front = n_front;
+    t.pipe_off = d_pipe_off.as<int32_t>();
+    t.pipe_lvl = d_pipe_lvl.as<int32_t>();
+    t.lvl_bnd = d_lvl_bnd.as<int32_t>();
+    t.lvl_ops = d_lvl_ops.as<int32_t>();
+    t.succ_off = d_succ_off.as<int32_t>();
+    t.succ_ids = d_succ_ids.as<int32_t>();
+    t.succ_q = d_succ_q.as<uint32_t>();
+    t.ref = d_ref.as<int32_t>();
+    t.W = d_W.as<int64_t>();
+    t.hdr = d_hdr.as<int32_t>();
+    t.front_L = d_front_L.as<uint2>();
+    t.n_mst = n_mst;
+    t.mst = d_mst.as<uint2>();
+    t.mst_op = d_mst_op.as<int32_t>();
+    t.mst_first = d_mst_first.as<int32_t>();
+    t.rec = d_rec.as<uint4>();
+    t.ovf = d_ovf.as<uint2>();
+    t.rec_q = d_rec_q.as<uint4>();
+    t.ovf_q = d_ovf_q.as<uint2>();
+    t.seg_off = d_seg_off.as<int32_t>();
+    t.tab = d_tab.as<uint2>();
+    t.err = d_err.as<uint32_t>();
+    return t;
+  }
+
+  int64_t device_bytes() const {
+    const DevBuf* all[] = {&d_pipe_off, &d_pipe_lvl, &d_lvl_bnd, &d_lvl_ops, &d_succ_off,
+                           &d_succ_ids, &d_succ_q, &d_ref, &d_W, &d_hdr, &d_front_L,
+                           &d_rec, &d_ovf, &d_rec_q, &d_ovf_q, &d_seg_off, &d_tab, &d_err,
+                           &d_cnt, &d_start, &d_cursor, &d_perm, &d_hist, &d_mst, &d_mst_op,
+                           &d_mst_first};
+    int64_t s = 0;
+    for (auto* b : all) s += (int64_t)b->bytes;
+    return s;
+  }
+};
+
+namespace {
+
+int fail(llama_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  c->err = buf;
+  return code;
+}
+
+int hip_fail(llama_ctx* c, hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory)
+    return fail(c, LLAMA_E_NOMEM, "%s: %s", what, hipGetErrorString(e));
+  return fail(c, LLAMA_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Allocate `buf` for `bytes` and copy `src` into it (src may be null).
+int upload(llama_ctx* c, DevBuf& buf, const void* src, size_t bytes, const char* what) {
+  buf.release();
+  size_t n = bytes ? bytes : 4;
+  hipError_t e = hipMalloc(&buf.p, n);
+  if (e != hipSuccess) {
+    buf.p = nullptr;
+    return hip_fail(c, e, what);
+  }
+  buf.bytes = n;
+  if (src && bytes) {
+    e = hipMemcpyAsync(buf.p, src, bytes, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, what);
+  }
+  return LLAMA_OK;
+}
+
+template <typename T>
+int upload_vec(llama_ctx* c, DevBuf& buf, const std::vector<T>& v, const char* what) {
+  return upload(c, buf, v.data(), v.size() * sizeof(T), what);
+}
+
+int enter(llama_ctx* c) {
+  if (!c) return LLAMA_E_ARG;
+  c->err.clear();
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  return LLAMA_OK;
+}
+
+int sync_ctx(llama_ctx* c, const char* what) {
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, what);
+  return LLAMA_OK;
+}
+
+// C/B of x is smaller than C/B of y (exact: C <= 2^40, B <= 2^16).
+inline bool per_item_less(const llama_ctx* c, int64_t x, int64_t y) {
+  return c->cost[x] * (int64_t)c->batch[y] < c->cost[y] * (int64_t)c->batch[x];
+}
+
+int build_tables(llama_ctx* c);
+
+}  // namespace
+
+extern "C" {
+
+int llama_create(llama_ctx** out, int32_t device) {
+  if (!out) return LLAMA_E_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return LLAMA_E_DEVICE;
+  llama_ctx* c = new (std::nothrow) llama_ctx();
+  if (!c) return LLAMA_E_NOMEM;
+  c->device = device;
+  if (hipSetDevice(device) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return LLAMA_E_DEVICE;
+  }
+  if (upload(c, c->d_err, nullptr, sizeof(uint32_t), "error word") != LLAMA_OK ||
+      hipMemsetAsync(c->d_err.p, 0, sizeof(uint32_t), c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    (void)hipStreamDestroy(c->stream);
+    delete c;
+    return LLAMA_E_DEVICE;
+  }
+  *out = c;
+  return LLAMA_OK;
+}
+
+void llama_destroy(llama_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* llama_last_error(const llama_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int llama_set_dag(llama_ctx* c, int32_t n_pipelines, const int32_t* pipe_off,
+                  const int32_t* succ_off, const int32_t* succ_ids, const uint32_t* succ_q) {
+  int rc = enter(c);
+  if (rc) return rc;
+  if (n_pipelines < 1 || !pipe_off || !succ_off)
+    return fail(c, LLAMA_E_ARG, "set_dag: need n_pipelines >= 1, pipe_op_offsets and succ_offsets");
+  if (pipe_off[0] != 0) return fail(c, LLAMA_E_RANGE, "set_dag: pipe_op_offsets[0] must be 0");
+  for (int p = 0; p < n_pipelines; ++p)
+    if (pipe_off[p + 1] < pipe_off[p])
+      return fail(c, LLAMA_E_RANGE, "set_dag: pipe_op_offsets decreases at pipeline %d", p);
+  const int32_t n_ops = pipe_off[n_pipelines];
+  if (n_ops < 1) return fail(c, LLAMA_E_RANGE, "set_dag: no operations");
+  if (succ_off[0] != 0) return fail(c, LLAMA_E_RANGE, "set_dag: succ_offsets[0] must be 0");
+  for (int v = 0; v < n_ops; ++v)
+    if (succ_off[v + 1] < succ_off[v])
+      return fail(c, LLAMA_E_RANGE, "set_dag: succ_offsets decreases at op %d", v);
+  const int64_t n_edges = succ_off[n_ops];
+  if (n_edges > 0 && !succ_ids) return fail(c, LLAMA_E_ARG, "set_dag: succ_ids is null");
+
+  c->has_dag = false;
+  c->has_prof = false;
+  std::vector<int32_t> pipe_of(n_ops);
+  for (int p = 0; p < n_pipelines; ++p)
+    for (int v = pipe_off[p]; v < pipe_off[p + 1]; ++v) pipe_of[v] = p;
+  for (int v = 0; v < n_ops; ++v)
+    for (int e = succ_off[v]; e < succ_off[v + 1]; ++e) {
+      const int w = succ_ids[e];
+      if (w < 0 || w >= n_ops) return fail(c, LLAMA_E_RANGE, "set_dag: edge %d -> %d out of range", v, w);
+      if (w == v) return fail(c, LLAMA_E_CYCLE, "set_dag: self-loop at op %d", v);
+      if (pipe_of[w] != pipe_of[v])
+        return fail(c, LLAMA_E_RANGE, "set_dag: edge %d -> %d crosses pipelines", v, w);
+      if (succ_q && (succ_q[e] < 1 || succ_q[e] > (uint32_t)LLAMA_Q_ONE))
+        return fail(c, LLAMA_E_RANGE, "set_dag: branch probability %u of edge %d -> %d not in [1, 65536]",
+                    succ_q[e], v, w);
+    }
+
+  // Heights above the outputs by reverse Kahn order: an op is final once all
+  // of its successors are; height = 1 + max height of the successors.
+  std::vector<int32_t> pred_cnt(n_ops + 1, 0), pred_off, preds(n_edges);
+  for (int64_t e = 0; e < n_edges; ++e) pred_cnt[succ_ids[e] + 1]++;
+  pred_off.assign(n_ops + 1, 0);
+  for (int v = 0; v < n_ops; ++v) pred_off[v + 1] = pred_off[v] + pred_cnt[v + 1];
+  {
+    std::vector<int32_t> fill(pred_off.begin(), pred_off.end() - 1);
+    for (int v = 0; v < n_ops; ++v)
+      for (int e = succ_off[v]; e < succ_off[v + 1]; ++e) preds[fill[succ_ids[e]]++] = v;
+  }
+  std::vector<int32_t> outdeg(n_ops), height(n_ops, 0), queue;
+  queue.reserve(n_ops);
+  for (int v = 0; v < n_ops; ++v) {
+    outdeg[v] = succ_off[v + 1] - succ_off[v];
+    if (!outdeg[v]) queue.push_back(v);
+  }
+  for (size_t h = 0; h < queue.size(); ++h) {
+    const int w = queue[h];
+    for (int e = pred_off[w]; e < pred_off[w + 1]; ++e) {
+      const int u = preds[e];
+      height[u] = std::max(height[u], height[w] + 1);
+      if (--outdeg[u] == 0) queue.push_back(u);
+    }
+  }
+  if ((int64_t)queue.size() != n_ops) return fail(c, LLAMA_E_CYCLE, "set_dag: the successor lists contain a cycle");
+
+  // Ops of each pipeline grouped by height (outputs first).
+  std::vector<int32_t> pipe_lvl(n_pipelines + 1, 0), lvl_bnd, lvl_ops(n_ops);
+  int32_t max_depth = 0;
+  for (int p = 0; p < n_pipelines; ++p) {
+    const int a = pipe_off[p], b = pipe_off[p + 1];
+    int hmax = -1;
+    for (int v = a; v < b; ++v) hmax = std::max(hmax, height[v]);
+    std::vector<int32_t> cnt(hmax + 2, 0);
+    for (int v = a; v < b; ++v) cnt[height[v] + 1]++;
+    for (int l = 0; l <= hmax; ++l) cnt[l + 1] += cnt[l];
+    for (int l = 0; l <= hmax; ++l) lvl_bnd.push_back(a + cnt[l]);
+    std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int v = a; v < b; ++v) lvl_ops[a + fill[height[v]]++] = v;
+    pipe_lvl[p + 1] = pipe_lvl[p] + (hmax + 1);
+    max_depth = std::max(max_depth, hmax + 1);
+  }
+  lvl_bnd.push_back(n_ops);
+
+  c->n_pipelines = n_pipelines;
+  c->n_ops = n_ops;
+  c->n_edges = n_edges;
+  c->max_depth = max_depth;
+  c->pipe_off.assign(pipe_off, pipe_off + n_pipelines + 1);
+  c->succ_off.assign(succ_off, succ_off + n_ops + 1);
+  c->succ_ids.assign(succ_ids ? succ_ids : succ_off, succ_ids ? succ_ids + n_edges : succ_off);
+  if (succ_q) c->succ_q.assign(succ_q, succ_q + n_edges);
+  else c->succ_q.assign(n_edges, (uint32_t)LLAMA_Q_ONE);
+  c->pipe_of.swap(pipe_of);
+
+  if ((rc = upload_vec(c, c->d_pipe_off, c->pipe_off, "pipe_off")) ||
+      (rc = upload_vec(c, c->d_pipe_lvl, pipe_lvl, "pipe_lvl")) ||
+      (rc = upload_vec(c, c->d_lvl_bnd, lvl_bnd, "lvl_bnd")) ||
+      (rc = upload_vec(c, c->d_lvl_ops, lvl_ops, "lvl_ops")) ||
+      (rc = upload_vec(c, c->d_succ_off, c->succ_off, "succ_off")) ||
+      (rc = upload_vec(c, c->d_succ_ids, c->succ_ids, "succ_ids")) ||
+      (rc = upload_vec(c, c->d_succ_q, c->succ_q, "succ_q")))
+    return rc;
+  if ((rc = sync_ctx(c, "set_dag upload"))) return rc;
+  c->has_dag = true;
+  return LLAMA_OK;
+}
+
+int llama_set_profiles(llama_ctx* c, int32_t n_ops, int32_t n_hw, const int32_t* cfg_off,
+                       const int32_t* hw, const int32_t* batch, const int32_t* res,
+                       const int32_t* lat, const int64_t* cost, const int32_t* ref_cfg,
+                       const int64_t* hw_res_total) {
+  int rc = enter(c);
+  if (rc) return rc;
+  if (!c->has_dag) return fail(c, LLAMA_E_STATE, "set_profiles: call llama_set_dag first");
+  if (n_ops != c->n_ops) return fail(c, LLAMA_E_STATE, "set_profiles: n_ops %d != DAG's %d", n_ops, c->n_ops);
+  if (n_hw < 1 || n_hw > LLAMA_MAX_HW) return fail(c, LLAMA_E_RANGE, "set_profiles: n_hw %d not in [1, %d]", n_hw, LLAMA_MAX_HW);
+  if (!cfg_off || !hw || !batch || !res || !lat || !cost)
+    return fail(c, LLAMA_E_ARG, "set_profiles: null table pointer");
+  if (cfg_off[0] != 0) return fail(c, LLAMA_E_RANGE, "set_profiles: cfg_offsets[0] must be 0");
+  for (int v = 0; v < n_ops; ++v) {
+    const int64_t k = (int64_t)cfg_off[v + 1] - cfg_off[v];
+    if (k < 1 || k > LLAMA_MAX_CFG_PER_OP)
+      return fail(c, LLAMA_E_RANGE, "set_profiles: op %d has %lld configurations (need 1..%d)", v,
+                  (long long)k, LLAMA_MAX_CFG_PER_OP);
+  }
+  const int64_t n_cfg = cfg_off[n_ops];
+  for (int64_t x = 0; x < n_cfg; ++x) {
+    if (hw[x] < 0 || hw[x] >= n_hw) return fail(c, LLAMA_E_RANGE, "set_profiles: cfg %lld hw %d not in [0, %d)", (long long)x, hw[x], n_hw);
+    if (batch[x] < 1 || batch[x] > LLAMA_MAX_BATCH) return fail(c, LLAMA_E_RANGE, "set_profiles: cfg %lld batch %d", (long long)x, batch[x]);
+    if (res[x] < 1) return fail(c, LLAMA_E_RANGE, "set_profiles: cfg %lld resource %d < 1", (long long)x, res[x]);
+    if (lat[x] < 1) return fail(c, LLAMA_E_RANGE, "set_profiles: cfg %lld latency %d < 1", (long long)x, lat[x]);
+    if (cost[x] < 0 || cost[x] > LLAMA_MAX_COST) return fail(c, LLAMA_E_RANGE, "set_profiles: cfg %lld cost out of [0, 2^40]", (long long)x);
+  }
+  if (hw_res_total)
+    for (int h = 0; h < n_hw; ++h)
+      if (hw_res_total[h] < 1) return fail(c, LLAMA_E_RANGE, "set_profiles: hw_res_total[%d] < 1", h);
+
+  std::vector<int32_t> ref_k(n_ops);
+  for (int v = 0; v < n_ops; ++v) {
+    const int a = cfg_off[v], b = cfg_off[v + 1];
+    if (ref_cfg) {
+      if (ref_cfg[v] < 0 || ref_cfg[v] >= b - a)
+        return fail(c, LLAMA_E_RANGE, "set_profiles: ref_cfg[%d] = %d out of range", v, ref_cfg[v]);
+      ref_k[v] = ref_cfg[v];
+      continue;
+    }
+    int best = -1;  // hw 0, batch 1, smallest resource, lowest index
+    for (int x = a; x < b; ++x)
+      if (hw[x] == 0 && batch[x] == 1 && (best < 0 || res[x] < res[best])) best = x;
+    if (best < 0) return fail(c, LLAMA_E_STATE, "set_profiles: op %d has no hw-0 batch-1 configuration for the reference", v);
+    ref_k[v] = best - a;
+  }
+  // Path latencies must stay below 2^46 so that q * W and ref * R fit int64.
+  for (int p = 0; p < c->n_pipelines; ++p) {
+    int64_t mx = 0;
+    for (int v = c->pipe_off[p]; v < c->pipe_off[p + 1]; ++v)
+      mx = std::max<int64_t>(mx, lat[cfg_off[v] + ref_k[v]]);
+    const int64_t nv = c->pipe_off[p + 1] - c->pipe_off[p];
+    if (mx > 0 && nv > ((int64_t)1 << 46) / mx)
+      return fail(c, LLAMA_E_RANGE, "set_profiles: pipeline %d: ops * max reference latency >= 2^46", p);
+  }
+
+  c->has_prof = false;
+  c->perm_cap = 0;  // full-scan scratch is sized by the op count: regrow on demand
+  c->n_hw = n_hw;
+  c->n_cfg = n_cfg;
+  c->cfg_off.assign(cfg_off, cfg_off + n_ops + 1);
+  c->hw.assign(hw, hw + n_cfg);
+  c->batch.assign(batch, batch + n_cfg);
+  c->res.assign(res, res + n_cfg);
+  c->lat.assign(lat, lat + n_cfg);
+  c->cost.assign(cost, cost + n_cfg);
+  c->ref_k.swap(ref_k);
+
+  // Dense rank of C/B within each op -> packed keys (caller order).
+  c->key.assign(n_cfg, 0);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int v = 0; v < n_ops; ++v) {
+    const int a = c->cfg_off[v], b = c->cfg_off[v + 1];
+    std::vector<int32_t> idx(b - a);
+    std::iota(idx.begin(), idx.end(), a);
+    std::stable_sort(idx.begin(), idx.end(), [c](int32_t x, int32_t y) { return per_item_less(c, x, y); });
+    uint32_t rank = 0;
+    for (size_t j = 0; j < idx.size(); ++j) {
+      if (j > 0 && per_item_less(c, idx[j - 1], idx[j])) ++rank;
+      c->key[idx[j]] = (rank << 16) | (uint32_t)(idx[j] - a);
+    }
+  }
+  if ((rc = build_tables(c))) return rc;
+  c->has_prof = true;
+  return LLAMA_OK;
+}
+
+int llama_update_latencies(llama_ctx* c, const int32_t* lat) {
+  int rc = enter(c);
+  if (rc) return rc;
+  if (!c->has_prof) return fail(c, LLAMA_E_STATE, "update_latencies: no profiles");
+  if (!lat) return fail(c, LLAMA_E_ARG, "update_latencies: null pointer");
+  for (int64_t x = 0; x < c->n_cfg; ++x)
+    if (lat[x] < 1) return fail(c, LLAMA_E_RANGE, "update_latencies: cfg %lld latency %d < 1", (long long)x, lat[x]);
+  for (int p = 0; p < c->n_pipelines; ++p) {
+    int64_t mx = 0;
+    for (int v = c->pipe_off[p]; v < c->pipe_off[p + 1]; ++v)
+      mx = std::max<int64_t>(mx, lat[c->cfg_off[v] + c->ref_k[v]]);
+    const int64_t nv = c->pipe_off[p + 1] - c->pipe_off[p];
+    if (mx > 0 && nv > ((int64_t)1 << 46) / mx)
+      return fail(c, LLAMA_E_RANGE, "update_latencies: pipeline %d: ops * max reference latency >= 2^46", p);
+  }
+  c->has_prof = false;
+  c->lat.assign(lat, lat + c->n_cfg);
+  if ((rc = build_tables(c))) return rc;
+  c->has_prof = true;
+  return LLAMA_OK;
+}
+
+int llama_relax(llama_ctx* c, void* stream) {
+  int rc = enter(c);
+  if (rc) return rc;
+  if (!c->has_prof) return fail(c, LLAMA_E_STATE, "relax: no profiles");
+  hipError_t e = llama::launch_relax(c->tables(), (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(c, e, "relax launch");
+  return LLAMA_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Everything derived from the latencies: reference latency, fastest config,
+// frontiers, full table; then W and thresholds on the GPU.
+int build_tables(llama_ctx* c) {
+  const int n_ops = c->n_ops, n_hw = c->n_hw;
+  const int hs = llama::header_stride(n_hw);
+  c->ref.assign(n_ops, 0);
+  c->fastest.assign(n_ops, 0);
+  std::vector<int32_t> seg_off((size_t)n_ops * n_hw + 1, 0);
+  std::vector<int64_t> front_cnt((size_t)n_ops * n_hw, 0);
+  std::vector<uint2> tab(c->n_cfg);
+
+  // Pass 1: per op, reference, fastest, backend segments of the full table,
+  // and frontier sizes.
+  std::vector<std::vector<uint2>> fronts(n_ops);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int v = 0; v < n_ops; ++v) {
+    const int a = c->cfg_off[v], b = c->cfg_off[v + 1];
+    c->ref[v] = c->lat[a + c->ref_k[v]];
+    int f = a;
+    for (int x = a + 1; x < b; ++x)
+      if (c->lat[x] < c->lat[f]) f = x;
+    c->fastest[v] = f - a;
+    std::vector<int32_t> cnt(n_hw + 1, 0);
+    for (int x = a; x < b; ++x) cnt[c->hw[x] + 1]++;
+    for (int h = 0; h < n_hw; ++h) cnt[h + 1] += cnt[h];
+    std::vector<int32_t> order(b - a);
+    {
+      std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+      for (int x = a; x < b; ++x) order[fill[c->hw[x]]++] = x;  // stable by caller index
+    }
+    for (int j = 0; j < b - a; ++j) tab[a + j] = make_uint2((uint32_t)c->lat[order[j]], c->key[order[j]]);
+    for (int h = 0; h < n_hw; ++h) seg_off[(size_t)v * n_hw + h] = a + cnt[h];
+    // frontier of each backend: latency ascending (key ascending among equal
+    // latencies); keep entries whose key beats every faster entry's.
+    std::vector<uint2>& fr = fronts[v];
+    for (int h = 0; h < n_hw; ++h) {
+      std::vector<int32_t> s(order.begin() + cnt[h], order.begin() + cnt[h + 1]);
+      std::sort(s.begin(), s.end(), [c](int32_t x, int32_t y) {
+        return c->lat[x] != c->lat[y] ? c->lat[x] < c->lat[y] : c->key[x] < c->key[y];
+      });
+      uint32_t best = llama::KEY_NONE;
+      int64_t kept = 0;
+      for (int32_t x : s)
+        if (c->key[x] < best) {
+          best = c->key[x];
+          fr.push_back(make_uint2((uint32_t)c->lat[x], c->key[x]));
+          ++kept;
+        }
+      front_cnt[(size_t)v * n_hw + h] = kept;
+    }
+  }
+  seg_off[(size_t)n_ops * n_hw] = (int32_t)c->n_cfg;
+
+  // Queue-free merged frontier of each op over all backends: latency
+  // ascending (key ascending among equal latencies), keeping each entry whose
+  // key beats every faster one's.  Its thresholds are refreshed on the GPU
+  // after every relaxation; the record's other words are fixed here.
+  std::vector<std::vector<uint2>> merged(n_ops);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int v = 0; v < n_ops; ++v) {
+    std::vector<uint2> all(fronts[v]);
+    std::sort(all.begin(), all.end(), [](const uint2& p, const uint2& q) {
+      return p.x != q.x ? p.x < q.x : p.y < q.y;
+    });
+    uint32_t best = llama::KEY_NONE;
+    for (const uint2& e : all)
+      if (e.y < best) {
+        best = e.y;
+        merged[v].push_back(e);
+      }
+  }
+  std::vector<int32_t> mst_first(n_ops + 1, 0);
+  for (int v = 0; v < n_ops; ++v) mst_first[v + 1] = mst_first[v] + (int32_t)merged[v].size();
+  c->n_mst = mst_first[n_ops];
+  std::vector<uint2> mst(c->n_mst);
+  std::vector<int32_t> mst_op(c->n_mst);
+  std::vector<uint32_t> rec_tmpl((size_t)2 * n_ops * llama::REC_WORDS, 0);
+  for (int v = 0; v < n_ops; ++v) {
+    const int n = (int)merged[v].size();
+    for (int j = 0; j < n; ++j) {
+      mst[mst_first[v] + j] = merged[v][j];
+      mst_op[mst_first[v] + j] = v;
+    }
+    uint32_t w[llama::REC_WORDS] = {0};
+    w[0] = (uint32_t)n | ((uint32_t)c->fastest[v] << 16);
+    for (int slot = 0; slot < llama::REC_SLOTS; ++slot) {
+      const int j = n - 1 - slot;
+      w[1 + slot] = 0x7FFFFFFFu;  // thresholds: written by the GPU after relaxation
+      const uint32_t k = j >= 0 ? (merged[v][j].y & 0xFFFFu) : 0u;
+      w[1 + llama::REC_SLOTS + slot / 2] |= k << (16 * (slot & 1));
+    }
+    for (int mode = 0; mode < 2; ++mode)
+      std::copy(w, w + llama::REC_WORDS, rec_tmpl.begin() + ((size_t)mode * n_ops + v) * llama::REC_WORDS);
+  }
+  merged.clear();
+
+  // Pass 2: frontier offsets and headers.
+  std::vector<int32_t> hdr((size_t)n_ops * hs, 0);
+  int64_t pos = 0;
+  for (int v = 0; v < n_ops; ++v) {
+    for (int h = 0; h < n_hw; ++h) {
+      hdr[(size_t)v * hs + h] = (int32_t)pos;
+      pos += front_cnt[(size_t)v * n_hw + h];
+    }
+    hdr[(size_t)v * hs + n_hw] = (int32_t)pos;
+    hdr[(size_t)v * hs + n_hw + 1] = c->fastest[v];
+  }
+  if (pos > INT32_MAX) return fail(c, LLAMA_E_RANGE, "set_profiles: frontier too large");
+  c->n_front = pos;
+  std::vector<uint2> front_L(pos);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int v = 0; v < n_ops; ++v)
+    std::copy(fronts[v].begin(), fronts[v].end(), front_L.begin() + hdr[(size_t)v * hs]);
+  fronts.clear();
+
+  int rc;
+  if ((rc = upload_vec(c, c->d_ref, c->ref, "ref")) ||
+      (rc = upload(c, c->d_W, nullptr, sizeof(int64_t) * 2 * (size_t)n_ops, "W")) ||
+      (rc = upload_vec(c, c->d_hdr, hdr, "hdr")) ||
+      (rc = upload_vec(c, c->d_front_L, front_L, "front_L")) ||
+      (rc = upload_vec(c, c->d_rec, rec_tmpl, "records")) ||
+      (rc = upload_vec(c, c->d_mst, mst, "merged frontier")) ||
+      (rc = upload_vec(c, c->d_mst_op, mst_op, "merged frontier ops")) ||
+      (rc = upload_vec(c, c->d_mst_first, mst_first, "merged frontier offsets")) ||
+      (rc = upload(c, c->d_ovf, nullptr, sizeof(uint2) * 2 * (size_t)pos, "record overflow")) ||
+      (rc = upload(c, c->d_rec_q, nullptr, (size_t)llama::REC_WORDS * 4 * n_ops, "records (queue)")) ||
+      (rc = upload(c, c->d_ovf_q, nullptr, sizeof(uint2) * (size_t)pos, "record overflow (queue)")) ||
+      (rc = upload_vec(c, c->d_seg_off, seg_off, "seg_off")) ||
+      (rc = upload(c, c->d_cnt, nullptr, sizeof(int32_t) * ((size_t)n_ops + 1), "bucket counts")) ||
+      (rc = upload(c, c->d_start, nullptr, sizeof(int32_t) * ((size_t)n_ops + 1), "bucket starts")) ||
+      (rc = upload(c, c->d_cursor, nullptr, sizeof(int32_t) * (size_t)n_ops, "bucket cursors")) ||
+      (rc = upload_vec(c, c->d_tab, tab, "tab")))
+    return rc;
+  hipError_t e = llama::launch_relax(c->tables(), c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "relax launch");
+  return sync_ctx(c, "set_profiles");
+}
+
+int reserve_perm(llama_ctx* c, int64_t n, hipStream_t stream) {
+  if (n <= c->perm_cap) return LLAMA_OK;
+  if (n > INT32_MAX) return fail(c, LLAMA_E_RANGE, "full scan: more than 2^31-1 invocations in one call");
+  if (stream) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &st) == hipSuccess && st != hipStreamCaptureStatusNone)
+      return fail(c, LLAMA_E_STATE, "full scan: scratch for %lld invocations must be reserved before graph capture (llama_reserve)", (long long)n);
+  }
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(c, e, "reserve sync");
+  int rc = upload(c, c->d_perm, nullptr, sizeof(int32_t) * (size_t)n, "full-scan permutation");
+  if (!rc)
+    rc = upload(c, c->d_hist, nullptr, sizeof(int32_t) * (size_t)llama::full_scan_hist_words(n, c->n_ops),
+                "full-scan histograms");
+  if (rc) {
+    c->perm_cap = 0;
+    return rc;
+  }
+  c->perm_cap = n;
+  return LLAMA_OK;
+}
+
+int check_batch(llama_ctx* c, int64_t n, const void* op, const char* fn) {
+  if (!c->has_prof) return fail(c, LLAMA_E_STATE, "%s: call llama_set_dag and llama_set_profiles first", fn);
+  if (n < 0) return fail(c, LLAMA_E_ARG, "%s: n_inv < 0", fn);
+  if (n > 0 && !op) return fail(c, LLAMA_E_ARG, "%s: null invocation pointer", fn);
+  return LLAMA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int llama_targets(llama_ctx* c, int64_t n, const int32_t* op, const int32_t* elapsed,
+                  const int32_t* slo, const int64_t* queue, int32_t mode, int32_t* target,
+                  void* stream) {
+  int rc = enter(c);
+  if (rc) return rc;
+  if ((rc = check_batch(c, n, op, "targets"))) return rc;
+  if (n > 0 && (!elapsed || !slo || !target)) return fail(c, LLAMA_E_ARG, "targets: null pointer");
+  if (mode != LLAMA_SLACK_PAPER && mode != LLAMA_SLACK_PROB) return fail(c, LLAMA_E_ARG, "targets: bad slack_mode %d", mode);
+  llama::Batch b{};
+  b.n = n; b.op = op; b.elapsed = elapsed; b.slo = slo; b.queue = queue; b.target_out = target; b.mode = mode;
+  hipError_t e = llama::launch_targets(c->tables(), b, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(c, e, "targets launch");
+  return LLAMA_OK;
+}
+
+int llama_select(llama_ctx* c, int64_t n, const int32_t* op, const int32_t* target, int32_t* cfg,
+                 uint8_t* flag, void* stream) {
+  int rc = enter(c);
+  if (rc) return rc;
+  if ((rc = check_batch(c, n, op, "select"))) return rc;
+  if (n > 0 && (!target || !cfg)) return fail(c, LLAMA_E_ARG, "select: null pointer");
+  llama::Batch b{};
+  b.n = n; b.op = op; b.target = target; b.cfg = cfg; b.flag = flag;
+  hipError_t e = llama::launch_select_indexed(c->tables(), b, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(c, e, "select launch");
+  return LLAMA_OK;
+}
+
+int llama_decide(llama_ctx* c, int64_t n, const int32_t* op, const int32_t* elapsed,
+                 const int32_t* slo, const int64_t* queue, int32_t mode, int32_t scan,
+                 int32_t* cfg, uint8_t* flag, void* stream) {
+  int rc = enter(c);
+  if (rc) return rc;
+  if ((rc = check_batch(c, n, op, "decide"))) return rc;
+  if (n > 0 && (!elapsed || !slo || !cfg)) return fail(c, LLAMA_E_ARG, "decide: null pointer");
+  if (mode != LLAMA_SLACK_PAPER && mode != LLAMA_SLACK_PROB) return fail(c, LLAMA_E_ARG, "decide: bad slack_mode %d", mode);
+  if (scan < LLAMA_SCAN_AUTO || scan > LLAMA_SCAN_WAVE) return fail(c, LLAMA_E_ARG, "decide: bad scan_mode %d", scan);
+  llama::Batch b{};
+  b.n = n; b.op = op; b.elapsed = elapsed; b.slo = slo; b.queue = queue; b.cfg = cfg; b.flag = flag; b.mode = mode;
+  hipError_t e;
+  if (scan == LLAMA_SCAN_FULL) {
+    if ((rc = reserve_perm(c, n, (hipStream_t)stream))) return rc;
+    llama::FullScratch w{c->d_cnt.as<int32_t>(), c->d_start.as<int32_t>(), c->d_cursor.as<int32_t>(),
+                         c->d_perm.as<int32_t>(), c->d_hist.as<int32_t>()};
+    e = llama::launch_decide_full(c->tables(), b, w, (hipStream_t)stream);
+  } else if (scan == LLAMA_SCAN_WAVE) {
+    e = llama::launch_decide_wave(c->tables(), b, (hipStream_t)stream);
+  } else {
+    e = llama::launch_decide_indexed(c->tables(), b, (hipStream_t)stream);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "decide launch");
+  return LLAMA_OK;
+}
+
+int llama_reserve(llama_ctx* c, int64_t max_inv) {
+  int rc = enter(c);
+  if (rc) return rc;
+  if (max_inv < 0) return fail(c, LLAMA_E_ARG, "reserve: negative size");
+  return reserve_perm(c, max_inv, nullptr);
+}
+
+int llama_get_stats(llama_ctx* c, llama_stats* out, int32_t reset_error) {
+  int rc = enter(c);
+  if (rc) return rc;
+  if (!out) return fail(c, LLAMA_E_ARG, "get_stats: null pointer");
+  std::memset(out, 0, sizeof *out);
+  out->n_ops = c->n_ops;
+  out->n_hw = c->n_hw;
+  out->n_pipelines = c->n_pipelines;
+  out->max_depth = c->max_depth;
+  out->n_cfg = c->n_cfg;
+  out->n_edges = c->n_edges;
+  out->frontier_entries = c->n_front;
+  out->device_bytes = c->device_bytes();
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(c, e, "get_stats sync");
+  uint32_t w = 0;
+  e = hipMemcpy(&w, c->d_err.p, sizeof w, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(c, e, "get_stats read");
+  out->device_error = w;
+  if (reset_error) {
+    e = hipMemset(c->d_err.p, 0, sizeof(uint32_t));
+    if (e != hipSuccess) return hip_fail(c, e, "get_stats reset");
+  }
+  return LLAMA_OK;
+}
+
+int llama_debug_export(llama_ctx* c, int32_t what, void* out, int64_t bytes) {
+  int rc = enter(c);
+  if (rc) return rc;
+  if (!out) return fail(c, LLAMA_E_ARG, "debug_export: null pointer");
+  if (!c->has_prof) return fail(c, LLAMA_E_STATE, "debug_export: no profiles");
+  const void* src = nullptr;
+  int64_t need = 0;
+  bool device = false;
+  switch (what) {
+    case 0: src = c->d_W.p; need = 8ll * c->n_ops; device = true; break;
+    case 1: src = c->d_W.as<int64_t>() + c->n_ops; need = 8ll * c->n_ops; device = true; break;
+    case 2: src = c->key.data(); need = 4ll * c->n_cfg; break;
+    case 3: src = c->ref.data(); need = 4ll * c->n_ops; break;
+    case 4: src = c->fastest.data(); need = 4ll * c->n_ops; break;
+    default: return fail(c, LLAMA_E_ARG, "debug_export: unknown table %d", what);
+  }
+  if (bytes < need) return fail(c, LLAMA_E_ARG, "debug_export: need %lld bytes", (long long)need);
+  if (!device) {
+    std::memcpy(out, src, need);
+    return LLAMA_OK;
+  }
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(out, src, need, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(c, e, "debug_export copy");
+  return LLAMA_OK;
+}
+
+}  // extern "C"

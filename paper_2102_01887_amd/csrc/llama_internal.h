@@ -1,0 +1,106 @@
+// Internal interface between the host side of libllama (llama_host.cpp) and
+// its HIP kernels (llama_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+namespace llama {
+
+constexpr uint32_t KEY_NONE = 0xFFFFFFFFu;   // "no feasible configuration"
+constexpr uint32_t THR_NEVER = 0xFFFFFFFFu;  // remaining-time threshold never met
+constexpr int MAX_HW = 8;
+
+// Per-op decision record (64 bytes).  The op's frontier over all backends in
+// remaining-time space: entries {T, k} such that configuration k (local index)
+// is feasible for an invocation iff slo - elapsed >= T, with T strictly
+// increasing and the configuration's cost key strictly decreasing along the
+// frontier.  The record keeps the REC_SLOTS entries with the largest T (the
+// cheapest configurations, which most invocations can afford), in descending
+// T order:
+//   word 0        entry count n (low 16 bits) | fastest configuration << 16
+//   words 1..10   T of slots 0..9 (slot 0 = largest T)
+//   words 11..15  k of slots (2j, 2j+1) as two 16-bit halves
+// The whole frontier, ascending in T, is also in the overflow array at
+// [hdr offset of the op, + n); the decision reads it only when no slot is
+// feasible and n > REC_SLOTS.
+constexpr int REC_WORDS = 16;
+constexpr int REC_SLOTS = 10;
+
+// Stride (int32 words) of the per-op header: frontier offsets for each
+// backend (n_hw + 1 entries), then the fastest configuration, padded to a
+// multiple of 4 words so the header can be read with 16-byte loads.
+inline constexpr int header_stride(int n_hw) { return (n_hw + 2 + 3) & ~3; }
+
+// Device-resident tables of one context.  All pointers are device memory
+// owned by the context.
+struct DevTables {
+  int32_t n_ops;
+  int32_t n_hw;
+  int32_t n_pipelines;
+  int32_t hs;              // header_stride(n_hw)
+  int64_t n_front;         // frontier entries (all ops, all backends)
+
+  // DAG
+  const int32_t* pipe_off;   // [P+1] op range of each pipeline
+  const int32_t* pipe_lvl;   // [P+1] range of each pipeline's levels in lvl_bnd
+  const int32_t* lvl_bnd;    // [n_levels+1] start of each level in lvl_ops
+  const int32_t* lvl_ops;    // [n_ops] ops ordered by pipeline, then height (outputs first)
+  const int32_t* succ_off;   // [n_ops+1]
+  const int32_t* succ_ids;   // [n_edges]
+  const uint32_t* succ_q;    // [n_edges] Q16 branch probability
+
+  // profiles
+  const int32_t* ref;        // [n_ops] reference-configuration latency
+  int64_t* W;                // [2*n_ops] remaining worst-path latency: PAPER rows, then PROB rows
+  const int32_t* hdr;        // [n_ops*hs] frontier offsets per backend + fastest (local index)
+  const uint2* front_L;      // [n_front] {latency, key}: per (op, backend), latency ascending, key strictly descending
+  int64_t n_mst;              // entries of the queue-free merged frontiers (all ops)
+  const uint2* mst;          // [n_mst] {L, key}, per op ascending in L
+  const int32_t* mst_op;     // [n_mst] op of each entry
+  const int32_t* mst_first;  // [n_ops+1] first entry of each op
+  uint4* rec;                // [2*n_ops*4] decision records (REC_WORDS words per op), PAPER then PROB, queue = 0
+  uint2* ovf;                // [2*n_front] full frontiers {T, key} ascending, PAPER then PROB
+  uint4* rec_q;              // [n_ops*4] records for a per-call queueing-time vector
+  uint2* ovf_q;              // [n_front]
+  const int32_t* seg_off;    // [n_ops*n_hw+1] backend segments of the full table
+  const uint2* tab;          // [n_cfg] {latency, key}, grouped by (op, backend), caller order inside
+  uint32_t* err;             // device error word
+};
+
+// Per-call invocation batch (device pointers owned by the caller).
+struct Batch {
+  int64_t n;
+  const int32_t* op;
+  const int32_t* elapsed;
+  const int32_t* slo;
+  const int64_t* queue;      // [n_hw] or nullptr
+  const int32_t* target;     // [n*n_hw] (select only)
+  int32_t* target_out;       // [n*n_hw] (targets only)
+  int32_t* cfg;
+  uint8_t* flag;             // may be nullptr
+  int32_t mode;              // 0 = PAPER, 1 = PROB
+};
+
+hipError_t launch_relax(const DevTables& t, hipStream_t s);
+// Build records for modes [mode0, mode0 + n_modes) into rec/ovf (consecutive
+// per-mode blocks of n_ops*4 uint4 and n_front uint2).
+hipError_t launch_records(const DevTables& t, int mode0, int n_modes, const int64_t* queue, uint4* rec,
+                          uint2* ovf, hipStream_t s);
+hipError_t launch_targets(const DevTables& t, const Batch& b, hipStream_t s);
+hipError_t launch_select_indexed(const DevTables& t, const Batch& b, hipStream_t s);
+hipError_t launch_decide_indexed(const DevTables& t, const Batch& b, hipStream_t s);
+// Scratch of the bucketed full scan (device memory owned by the context).
+struct FullScratch {
+  int32_t* cnt;     // [n_ops + 1]
+  int32_t* start;   // [n_ops + 1]
+  int32_t* cursor;  // [n_ops]
+  int32_t* perm;    // [n_inv]
+  int32_t* hist;    // [full_scan_hist_words(n_inv, n_ops)]
+};
+// Words of per-chunk histogram scratch the full scan needs for n_inv invocations.
+int64_t full_scan_hist_words(int64_t n_inv, int32_t n_ops);
+hipError_t launch_decide_full(const DevTables& t, const Batch& b, const FullScratch& w, hipStream_t s);
+hipError_t launch_decide_wave(const DevTables& t, const Batch& b, hipStream_t s);
+
+}  // namespace llama

@@ -1,0 +1,858 @@
+// HIP kernels (gfx950) of the decision path:
+//   relax_kernel            remaining worst-path latency W (Alg. 1
+//                           RemainingPathLatency, min over paths) and the
+//                           per-frontier-entry remaining-time thresholds
+//   targets_kernel          Alg. 1 slack per invocation and backend
+//   select_indexed_kernel   Eq. 1 given slacks, on the cost/latency frontiers
+//   decide_indexed_kernel   Alg. 1 + Eq. 1 fused, on the threshold frontiers
+//   decide_full_kernel      Alg. 1 + Eq. 1 fused, scanning every configuration
+//                           with a wavefront min reduction (DPP)
+//
+// Everything is integer.  Exact floor division of non-negative 64-bit values
+// uses an FP64 quotient estimate followed by an exact integer correction.
+#include <hip/hip_runtime.h>
+
+#include "llama_internal.h"
+
+namespace llama {
+namespace {
+
+constexpr int64_t INT32_MAX_64 = 0x7FFFFFFFll;
+
+// floor(a / b) for 0 <= a < 2^62 and 1 <= b < 2^62 when the quotient is
+// below 2^32.  The FP64 estimate is within 2^-20 of a/b (three roundings of
+// relative size 2^-53 on a quotient below 2^32), so truncating it is off by
+// at most one; a single signed correction step with the exact remainder
+// makes it exact.
+__device__ __forceinline__ int64_t div_floor_pos(int64_t a, int64_t b) {
+  int64_t q = (int64_t)((double)a / (double)b);
+  int64_t r = a - q * b;
+  if (r < 0) {
+    q -= 1;
+  } else if (r >= b) {
+    q += 1;
+  }
+  return q;
+}
+
+// Remaining time of one backend, clamped to [0, 2^31-1].
+__device__ __forceinline__ int64_t remaining_time(int64_t r0, int64_t queue) {
+  int64_t r = r0 - queue;
+  r = r < 0 ? 0 : r;
+  return r > INT32_MAX_64 ? INT32_MAX_64 : r;
+}
+
+// Smallest remaining time R for which L < floor(ref * R / W), that is
+// ceil((L + 1) * W / ref); THR_NEVER when that exceeds 2^31-1 (no clamped R
+// reaches it).  Exact: (L+1)*W is compared with ref*(2^31-1) in 128 bits.
+__device__ __forceinline__ uint32_t remaining_threshold(uint32_t L, int64_t W, int32_t ref) {
+  const unsigned __int128 lhs = (unsigned __int128)((uint64_t)L + 1u) * (uint64_t)W;
+  const uint64_t lim = (uint64_t)ref * (uint64_t)INT32_MAX_64;
+  if (lhs > (unsigned __int128)lim) return THR_NEVER;
+  const int64_t num = (int64_t)(uint64_t)lhs + ref - 1;
+  return (uint32_t)div_floor_pos(num, ref);
+}
+
+// ---------------------------------------------------------------------------
+// Relaxation: one workgroup per pipeline, levels from the outputs upward.
+// A pipeline's ops, edges and level lists are staged in LDS when they fit;
+// otherwise the same recurrence runs on global memory.
+// ---------------------------------------------------------------------------
+constexpr int RELAX_MAX_OPS = 1024;
+constexpr int RELAX_MAX_EDGES = 3072;
+
+__device__ __forceinline__ int64_t branch_discount(uint32_t q, int64_t w) {
+  return (int64_t)(((uint64_t)q * (uint64_t)w) >> 16);
+}
+
+__global__ __launch_bounds__(64) void relax_kernel(DevTables t) {
+  __shared__ int64_t sWP[RELAX_MAX_OPS], sWQ[RELAX_MAX_OPS];
+  __shared__ int32_t sRef[RELAX_MAX_OPS], sOff[RELAX_MAX_OPS + 1];
+  __shared__ int32_t sLvl[RELAX_MAX_OPS], sBnd[RELAX_MAX_OPS + 1];
+  __shared__ int32_t sSucc[RELAX_MAX_EDGES];
+  __shared__ uint32_t sQ[RELAX_MAX_EDGES];
+  const int p = blockIdx.x;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  const int n_ops = t.n_ops;
+  const int a = t.pipe_off[p], n = t.pipe_off[p + 1] - a;
+  const int e0 = t.succ_off[a], ne = t.succ_off[a + n] - e0;
+  const int l0 = t.pipe_lvl[p], nl = t.pipe_lvl[p + 1] - l0;
+  int64_t* WP = t.W;
+  int64_t* WQ = t.W + n_ops;
+  if (n <= RELAX_MAX_OPS && ne <= RELAX_MAX_EDGES) {
+    for (int i = tid; i < n; i += bs) {
+      sRef[i] = t.ref[a + i];
+      sOff[i] = t.succ_off[a + i] - e0;
+      sLvl[i] = t.lvl_ops[a + i] - a;
+    }
+    for (int i = tid; i <= nl; i += bs) sBnd[i] = t.lvl_bnd[l0 + i] - a;
+    for (int i = tid; i < ne; i += bs) {
+      sSucc[i] = t.succ_ids[e0 + i] - a;
+      sQ[i] = t.succ_q[e0 + i];
+    }
+    if (tid == 0) sOff[n] = ne;
+    __syncthreads();
+    for (int l = 0; l < nl; ++l) {
+      for (int idx = sBnd[l] + tid; idx < sBnd[l + 1]; idx += bs) {
+        const int v = sLvl[idx];
+        int64_t mp = 0, mq = 0;
+        for (int e = sOff[v]; e < sOff[v + 1]; ++e) {
+          const int w = sSucc[e];
+          const int64_t wp = sWP[w], wq = branch_discount(sQ[e], sWQ[w]);
+          mp = wp > mp ? wp : mp;
+          mq = wq > mq ? wq : mq;
+        }
+        sWP[v] = sRef[v] + mp;
+        sWQ[v] = sRef[v] + mq;
+      }
+      __syncthreads();
+    }
+    for (int i = tid; i < n; i += bs) {
+      WP[a + i] = sWP[i];
+      WQ[a + i] = sWQ[i];
+    }
+    return;
+  }
+  for (int l = l0; l < l0 + nl; ++l) {
+    const int end = t.lvl_bnd[l + 1];
+    for (int idx = t.lvl_bnd[l] + tid; idx < end; idx += bs) {
+      const int v = t.lvl_ops[idx];
+      int64_t mp = 0, mq = 0;
+      for (int e = t.succ_off[v]; e < t.succ_off[v + 1]; ++e) {
+        const int w = t.succ_ids[e];
+        const int64_t wp = WP[w], wq = branch_discount(t.succ_q[e], WQ[w]);
+        mp = wp > mp ? wp : mp;
+        mq = wq > mq ? wq : mq;
+      }
+      const int64_t r = t.ref[v];
+      WP[v] = r + mp;
+      WQ[v] = r + mq;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Decision records: one 64-lane workgroup per (op, slack mode).
+//   1. every frontier entry {L, key} of backend h gets its remaining-time
+//      threshold T = ceil((L+1) * W / ref) + queue[h] (lanes in parallel, LDS);
+//   2. an entry survives the merge of the backends' lists iff its key is below
+//      the key of every entry that precedes it in (T, key) order; within its
+//      own list that always holds, and in another list the predecessors form a
+//      prefix whose smallest key is its last one (binary search in LDS);
+//   3. a prefix count of survivors gives each survivor its position in the
+//      merged frontier, written ascending to the overflow array; the
+//      REC_SLOTS largest-T entries also go to the record, descending.
+// Frontiers longer than the LDS stage are merged serially by lane 0.
+// ---------------------------------------------------------------------------
+constexpr int REC_LDS = 512;
+constexpr int BUCKET_CHUNK = 16384;  // invocations per histogram chunk
+constexpr int BUCKET_LDS_OPS = 12288;  // ops countable in one LDS histogram (48 KB)
+constexpr int SCAN_CHUNK = 4096;     // configurations staged at once (32 KB)
+constexpr int64_t T_INF = 0x7FFFFFFFFFFFFFFFll;
+
+// Stored form of a remaining-time threshold T: U = T - 1, clamped at
+// INT32_MIN, so that "feasible iff slo - elapsed >= T" reads "U < r0" and
+// U = INT32_MAX can mean "never" (no r0 exceeds it).
+__device__ __forceinline__ int32_t stored_threshold(int64_t T) {
+  const int64_t U = T - 1;
+  return U < -INT32_MAX_64 - 1 ? (int32_t)(-INT32_MAX_64 - 1) : (int32_t)U;
+}
+
+__device__ __forceinline__ int wave_inclusive_scan(int x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
+template <int NHW>
+__device__ __forceinline__ void build_record(const DevTables& t, int v, int mode, const int64_t* queue,
+                                             uint32_t* rw, uint2* ovf, int64_t* sT, uint32_t* sK,
+                                             int32_t* sC, uint32_t* sSlotT, uint32_t* sSlotK,
+                                             int32_t* sN) {
+  const int lane = threadIdx.x;
+  const int32_t* hdr = t.hdr + (int64_t)v * t.hs;
+  int off[NHW + 1];
+#pragma unroll
+  for (int h = 0; h <= NHW; ++h) off[h] = hdr[h];
+  const int base = off[0], n_e = off[NHW] - base;
+  const int64_t W = t.W[(int64_t)mode * t.n_ops + v];
+  const int32_t ref = t.ref[v];
+  int64_t Qh[NHW];
+#pragma unroll
+  for (int h = 0; h < NHW; ++h) Qh[h] = queue ? queue[h] : 0;
+  auto threshold = [&](int j, int h) -> int64_t {  // j: absolute frontier index
+    const uint32_t thr = remaining_threshold(t.front_L[j].x, W, ref);
+    return thr == THR_NEVER ? T_INF : (int64_t)thr + Qh[h];
+  };
+  auto list_of = [&](int j) -> int {  // j: index relative to base
+    int h = 0;
+#pragma unroll
+    for (int g = 1; g < NHW; ++g) h += (base + j >= off[g]) ? 1 : 0;
+    return h;
+  };
+
+  if (n_e <= REC_LDS) {
+    for (int j = lane; j < n_e; j += 64) {
+      sT[j] = threshold(base + j, list_of(j));
+      sK[j] = t.front_L[base + j].y;
+    }
+    __syncthreads();
+    // number of entries of list g that precede (Tj, Kj)
+    auto preceding = [&](int g, int64_t Tj, uint32_t Kj) -> int {
+      int lo = off[g] - base, hi = off[g + 1] - base;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const bool before = sT[mid] < Tj || (sT[mid] == Tj && sK[mid] < Kj);
+        if (before) lo = mid + 1; else hi = mid;
+      }
+      return lo;
+    };
+    for (int j = lane; j < n_e; j += 64) {
+      const int h = list_of(j);
+      const int64_t Tj = sT[j];
+      const uint32_t Kj = sK[j];
+      bool surv = Tj <= INT32_MAX_64;
+      if (surv) {
+#pragma unroll
+        for (int g = 0; g < NHW; ++g) {
+          if (g == h) continue;
+          const int p = preceding(g, Tj, Kj);
+          if (p > off[g] - base && sK[p - 1] < Kj) surv = false;
+        }
+      }
+      sC[j] = surv ? 1 : 0;
+    }
+    __syncthreads();
+    {  // inclusive prefix count of survivors, one contiguous chunk per lane
+      const int c = (n_e + 63) / 64;
+      const int a0 = lane * c < n_e ? lane * c : n_e;
+      const int a1 = a0 + c < n_e ? a0 + c : n_e;
+      int sum = 0;
+      for (int j = a0; j < a1; ++j) sum += sC[j];
+      int run = wave_inclusive_scan(sum) - sum;
+      for (int j = a0; j < a1; ++j) {
+        run += sC[j];
+        sC[j] = run;
+      }
+    }
+    __syncthreads();
+    const int n = n_e > 0 ? sC[n_e - 1] : 0;
+    auto count_before = [&](int idx) -> int { return idx > 0 ? sC[idx - 1] : 0; };
+    for (int j = lane; j < n_e; j += 64) {
+      if (sC[j] == count_before(j)) continue;  // not a survivor
+      const int h = list_of(j);
+      const int64_t Tj = sT[j];
+      const uint32_t Kj = sK[j];
+      int pos = count_before(j) - count_before(off[h] - base);
+#pragma unroll
+      for (int g = 0; g < NHW; ++g) {
+        if (g == h) continue;
+        pos += count_before(preceding(g, Tj, Kj)) - count_before(off[g] - base);
+      }
+      const int32_t Tc = stored_threshold(Tj);
+      ovf[base + pos] = make_uint2((uint32_t)Tc, Kj);
+      const int slot = n - 1 - pos;
+      if (slot < REC_SLOTS) {
+        sSlotT[slot] = (uint32_t)Tc;
+        sSlotK[slot] = Kj & 0xFFFFu;
+      }
+    }
+    if (lane == 0) *sN = n;
+  } else if (lane == 0) {
+    // serial merge of the backends' lists (each ascending in T)
+    int pos[NHW];
+    int64_t hT[NHW];
+    uint32_t hK[NHW];
+#pragma unroll
+    for (int h = 0; h < NHW; ++h) {
+      pos[h] = off[h];
+      hT[h] = pos[h] < off[h + 1] ? threshold(pos[h], h) : T_INF;
+      hK[h] = pos[h] < off[h + 1] ? t.front_L[pos[h]].y : KEY_NONE;
+    }
+    uint32_t best = KEY_NONE;
+    int n = 0;
+    for (;;) {
+      int sel = 0;
+      int64_t tmin = hT[0];
+      uint32_t kmin = hK[0];
+#pragma unroll
+      for (int h = 1; h < NHW; ++h)
+        if (hT[h] < tmin || (hT[h] == tmin && hK[h] < kmin)) {
+          sel = h;
+          tmin = hT[h];
+          kmin = hK[h];
+        }
+      if (tmin > INT32_MAX_64) break;
+      if (kmin < best) {
+        best = kmin;
+        ovf[base + n] = make_uint2((uint32_t)stored_threshold(tmin), kmin);
+        ++n;
+      }
+#pragma unroll
+      for (int h = 0; h < NHW; ++h)
+        if (h == sel) {
+          ++pos[h];
+          hT[h] = pos[h] < off[h + 1] ? threshold(pos[h], h) : T_INF;
+          hK[h] = pos[h] < off[h + 1] ? t.front_L[pos[h]].y : KEY_NONE;
+        }
+    }
+    for (int s = 0; s < REC_SLOTS && s < n; ++s) {
+      const uint2 f = ovf[base + n - 1 - s];
+      sSlotT[s] = f.x;
+      sSlotK[s] = f.y & 0xFFFFu;
+    }
+    *sN = n;
+  }
+  __syncthreads();
+  if (lane < REC_WORDS) {
+    const int n = *sN;
+    uint32_t word;
+    if (lane == 0) {
+      word = (uint32_t)n | ((uint32_t)hdr[NHW + 1] << 16);
+    } else if (lane <= REC_SLOTS) {
+      word = lane - 1 < n ? sSlotT[lane - 1] : 0x7FFFFFFFu;
+    } else {
+      const int s0 = 2 * (lane - 1 - REC_SLOTS);
+      const uint32_t lo = s0 < n ? sSlotK[s0] : 0u;
+      const uint32_t hi = s0 + 1 < n ? sSlotK[s0 + 1] : 0u;
+      word = lo | (hi << 16);
+    }
+    rw[lane] = word;
+  }
+  __syncthreads();  // the LDS stage is reused by the next record
+}
+
+// One 64-lane workgroup per op; it builds the op's records for n_modes slack
+// modes in turn (the frontier entries stay hot in cache between modes).
+template <int NHW>
+__global__ __launch_bounds__(64) void records_kernel(DevTables t, int mode0, int n_modes, const int64_t* queue,
+                                                     uint4* rec_all, uint2* ovf_all) {
+  __shared__ int64_t sT[REC_LDS];
+  __shared__ uint32_t sK[REC_LDS];
+  __shared__ int32_t sC[REC_LDS];
+  __shared__ uint32_t sSlotT[REC_SLOTS], sSlotK[REC_SLOTS];
+  __shared__ int32_t sN;
+  const int v = blockIdx.x;
+  for (int m = 0; m < n_modes; ++m) {
+    uint32_t* rw = reinterpret_cast<uint32_t*>(rec_all + ((int64_t)m * t.n_ops + v) * (REC_WORDS / 4));
+    build_record<NHW>(t, v, mode0 + m, queue, rw, ovf_all + (int64_t)m * t.n_front, sT, sK, sC, sSlotT,
+                      sSlotK, &sN);
+  }
+}
+
+// Queue-free records: the merged frontier of each op (which entries survive
+// and their order) depends only on latencies, because every threshold of an
+// op is the same increasing function of L.  Ingest fixes that structure and
+// the record's static words; after each relaxation one thread per merged
+// entry writes its threshold for both slack modes into the record slot and
+// the ascending overflow copy.
+__global__ __launch_bounds__(256) void thresholds_kernel(DevTables t) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= t.n_mst) return;
+  const int v = t.mst_op[j];
+  const int first = t.mst_first[v];
+  const int n = t.mst_first[v + 1] - first;
+  const int pos = (int)(j - first);
+  const int slot = n - 1 - pos;
+  const uint2 e = t.mst[j];  // {L, key}
+  const int32_t ref = t.ref[v];
+  const int base = t.hdr[(int64_t)v * t.hs];
+#pragma unroll
+  for (int mode = 0; mode < 2; ++mode) {
+    const uint32_t thr = remaining_threshold(e.x, t.W[(int64_t)mode * t.n_ops + v], ref);
+    const int32_t U = thr == THR_NEVER ? 0x7FFFFFFF : (int32_t)thr - 1;
+    t.ovf[(int64_t)mode * t.n_front + base + pos] = make_uint2((uint32_t)U, e.y);
+    if (slot < REC_SLOTS) {
+      uint32_t* rw = reinterpret_cast<uint32_t*>(t.rec + ((int64_t)mode * t.n_ops + v) * (REC_WORDS / 4));
+      rw[1 + slot] = (uint32_t)U;
+    }
+  }
+}
+
+__device__ __forceinline__ bool invalid_invocation(int v, int e, int s, int n_ops) {
+  return (unsigned)v >= (unsigned)n_ops || (e | s) < 0;
+}
+
+// ---------------------------------------------------------------------------
+// Targets: one invocation per lane.
+// ---------------------------------------------------------------------------
+template <int NHW>
+__global__ __launch_bounds__(256) void targets_kernel(DevTables t, Batch b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= b.n) return;
+  const int v = b.op[i], e = b.elapsed[i], s = b.slo[i];
+  int32_t out[NHW];
+  if (invalid_invocation(v, e, s, t.n_ops)) {
+#pragma unroll
+    for (int h = 0; h < NHW; ++h) out[h] = -1;
+    atomicOr(t.err, 1u);
+  } else {
+    const int64_t r0 = (int64_t)s - e;
+    const int64_t ref = t.ref[v];
+    const int64_t W = t.W[(int64_t)b.mode * t.n_ops + v];
+#pragma unroll
+    for (int h = 0; h < NHW; ++h) {
+      const int64_t R = remaining_time(r0, b.queue ? b.queue[h] : 0);
+      out[h] = R == 0 ? 0 : (int32_t)div_floor_pos(ref * R, W);
+    }
+  }
+  int32_t* dst = b.target_out + i * NHW;
+#pragma unroll
+  for (int h = 0; h < NHW; ++h) dst[h] = out[h];
+}
+
+// Last entry of a frontier segment [lo, hi) whose first word passes `ok`;
+// returns its key or KEY_NONE.  Entries are ordered so that `ok` holds on a
+// prefix.
+template <typename Pred>
+__device__ __forceinline__ uint32_t frontier_key(const uint2* f, int lo, int hi, Pred ok) {
+  const int base = lo;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (ok(f[mid].x)) lo = mid + 1; else hi = mid;
+  }
+  return lo > base ? f[lo - 1].y : KEY_NONE;
+}
+
+__device__ __forceinline__ void write_choice(const Batch& b, int64_t i, uint32_t best, int fastest) {
+  const bool feasible = best != KEY_NONE;
+  b.cfg[i] = feasible ? (int32_t)(best & 0xFFFFu) : fastest;
+  if (b.flag) b.flag[i] = feasible ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// Eq. 1 given slacks: feasible iff L < target[hw]; on each (op, backend)
+// frontier the feasible entries are a prefix and the last one has the
+// smallest key.
+// ---------------------------------------------------------------------------
+template <int NHW>
+__global__ __launch_bounds__(256) void select_indexed_kernel(DevTables t, Batch b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= b.n) return;
+  const int v = b.op[i];
+  if ((unsigned)v >= (unsigned)t.n_ops) {
+    b.cfg[i] = -1;
+    if (b.flag) b.flag[i] = 0;
+    atomicOr(t.err, 1u);
+    return;
+  }
+  const int32_t* hdr = t.hdr + (int64_t)v * t.hs;
+  const int32_t* tg = b.target + i * NHW;
+  uint32_t best = KEY_NONE;
+#pragma unroll
+  for (int h = 0; h < NHW; ++h) {
+    const int32_t target = tg[h];
+    const uint32_t k = frontier_key(t.front_L, hdr[h], hdr[h + 1],
+                                    [target](uint32_t L) { return (int32_t)L < target; });
+    best = k < best ? k : best;
+  }
+  write_choice(b, i, best, hdr[NHW + 1]);
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 1 + Eq. 1 fused on the decision records: a configuration is feasible
+// iff slo - elapsed >= T (stored as U = T - 1 < r0), so each invocation reads its op's 64-byte record
+// (four 16-byte loads of one line) and takes the first feasible slot in
+// descending-T order, which is the cheapest feasible configuration; no
+// division and no data-dependent branch unless the frontier continues past
+// the record.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void decide_indexed_kernel(DevTables t, Batch b, const uint4* rec,
+                                                             const uint2* ovf) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= b.n) return;
+  const int v = b.op[i], e = b.elapsed[i], s = b.slo[i];
+  if (invalid_invocation(v, e, s, t.n_ops)) {
+    b.cfg[i] = -1;
+    if (b.flag) b.flag[i] = 0;
+    atomicOr(t.err, 1u);
+    return;
+  }
+  const int32_t r0 = s - e;  // both non-negative: no overflow
+  const uint4* r = rec + (int64_t)v * (REC_WORDS / 4);
+  const uint4 a = r[0], bq = r[1], c = r[2], d = r[3];
+  const uint32_t T[REC_SLOTS] = {a.y, a.z, a.w, bq.x, bq.y, bq.z, bq.w, c.x, c.y, c.z};
+  const uint32_t K2[REC_SLOTS / 2] = {c.w, d.x, d.y, d.z, d.w};
+  const int n = (int)(a.x & 0xFFFFu);
+  int sel = -1;
+#pragma unroll
+  for (int slot = REC_SLOTS - 1; slot >= 0; --slot) {
+    const int k = (int)((K2[slot >> 1] >> (16 * (slot & 1))) & 0xFFFFu);
+    if (slot < n && (int32_t)T[slot] < r0) sel = k;
+  }
+  if (sel < 0 && n > REC_SLOTS) {
+    // every slot needs more time: search the rest of the frontier (ascending)
+    const int lo0 = t.hdr[(int64_t)v * t.hs];
+    int lo = lo0, hi = lo0 + n - REC_SLOTS;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if ((int32_t)ovf[mid].x < r0) lo = mid + 1; else hi = mid;
+    }
+    if (lo > lo0) sel = (int)(ovf[lo - 1].y & 0xFFFFu);
+  }
+  b.cfg[i] = sel >= 0 ? sel : (int)(a.x >> 16);
+  if (b.flag) b.flag[i] = sel >= 0 ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// Full scan, the plain Eq. 1 evaluation of every configuration.
+//   bucket_count / bucket_offsets / bucket_scatter: counting sort of the
+//     valid invocations by op (invalid ones are answered at once);
+//   scan_bucketed_kernel: one wavefront per op, lanes = that op's
+//     invocations; the op's table is walked with wave-uniform (scalar)
+//     loads, so each (invocation, configuration) pair costs one compare, one
+//     select and one min.
+// decide_wave_kernel keeps the same evaluation with lanes = configurations
+// and a DPP min reduction across the wave; it needs no scratch.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void fill_zero_kernel(int32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// Invalid invocations are answered here and left out of the buckets.
+__device__ __forceinline__ bool bucket_key(const DevTables& t, const Batch& b, int64_t i, int* v) {
+  *v = b.op[i];
+  const int e = b.elapsed[i], s = b.slo[i];
+  if (invalid_invocation(*v, e, s, t.n_ops)) {
+    b.cfg[i] = -1;
+    if (b.flag) b.flag[i] = 0;
+    atomicOr(t.err, 1u);
+    return false;
+  }
+  return true;
+}
+
+// Few ops: each workgroup counts its chunk of BUCKET_CHUNK invocations in an
+// LDS histogram and writes it as one row of hist[chunk][op].
+__global__ __launch_bounds__(1024) void bucket_hist_kernel(DevTables t, Batch b, int32_t* hist) {
+  extern __shared__ int32_t sh[];
+  const int n_ops = t.n_ops;
+  for (int j = threadIdx.x; j < n_ops; j += blockDim.x) sh[j] = 0;
+  __syncthreads();
+  const int64_t a = (int64_t)blockIdx.x * BUCKET_CHUNK;
+  const int64_t e = a + BUCKET_CHUNK < b.n ? a + BUCKET_CHUNK : b.n;
+  for (int64_t i = a + threadIdx.x; i < e; i += blockDim.x) {
+    int v;
+    if (bucket_key(t, b, i, &v)) atomicAdd(&sh[v], 1);
+  }
+  __syncthreads();
+  int32_t* row = hist + (int64_t)blockIdx.x * n_ops;
+  for (int j = threadIdx.x; j < n_ops; j += blockDim.x) row[j] = sh[j];
+}
+
+// Per op: exclusive prefix over chunks (in place) and the op's total.
+__global__ __launch_bounds__(256) void bucket_columns_kernel(int32_t* hist, int n_chunks, int n_ops,
+                                                             int32_t* total) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n_ops) return;
+  int run = 0;
+  int c = 0;
+  for (; c + 8 <= n_chunks; c += 8) {  // eight independent loads in flight
+    int x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = hist[(int64_t)(c + k) * n_ops + v];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      hist[(int64_t)(c + k) * n_ops + v] = run;
+      run += x[k];
+    }
+  }
+  for (; c < n_chunks; ++c) {
+    const int x = hist[(int64_t)c * n_ops + v];
+    hist[(int64_t)c * n_ops + v] = run;
+    run += x;
+  }
+  total[v] = run;
+}
+
+// Each chunk places its invocations at start[op] + (earlier chunks' count) +
+// (rank inside the chunk, from an LDS counter).
+__global__ __launch_bounds__(1024) void bucket_place_kernel(DevTables t, Batch b, const int32_t* hist,
+                                                           const int32_t* start, int32_t* perm) {
+  extern __shared__ int32_t sh[];
+  const int n_ops = t.n_ops;
+  for (int j = threadIdx.x; j < n_ops; j += blockDim.x) sh[j] = 0;
+  __syncthreads();
+  const int32_t* row = hist + (int64_t)blockIdx.x * n_ops;
+  const int64_t a = (int64_t)blockIdx.x * BUCKET_CHUNK;
+  const int64_t e = a + BUCKET_CHUNK < b.n ? a + BUCKET_CHUNK : b.n;
+  for (int64_t i = a + threadIdx.x; i < e; i += blockDim.x) {
+    const int v = b.op[i];
+    if (invalid_invocation(v, b.elapsed[i], b.slo[i], n_ops)) continue;
+    perm[start[v] + row[v] + atomicAdd(&sh[v], 1)] = (int32_t)i;
+  }
+}
+
+// Many ops: global atomics (few invocations share an op, so little contention).
+__global__ __launch_bounds__(256) void bucket_count_kernel(DevTables t, Batch b, int32_t* cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= b.n) return;
+  int v;
+  if (bucket_key(t, b, i, &v)) atomicAdd(&cnt[v], 1);
+}
+
+__global__ __launch_bounds__(256) void bucket_scatter_kernel(DevTables t, Batch b, int32_t* cursor,
+                                                             int32_t* perm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= b.n) return;
+  const int v = b.op[i];
+  if (invalid_invocation(v, b.elapsed[i], b.slo[i], t.n_ops)) return;
+  perm[atomicAdd(&cursor[v], 1)] = (int32_t)i;
+}
+
+// Exclusive prefix sum of cnt[0..n) into start[0..n] and cursor[0..n), one
+// workgroup of 1024 lanes, each owning a contiguous chunk.
+__global__ __launch_bounds__(1024) void bucket_offsets_kernel(const int32_t* cnt, int32_t n,
+                                                              int32_t* start, int32_t* cursor) {
+  __shared__ int32_t wsum[16];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int c = (n + 1023) / 1024;
+  const int a0 = tid * c < n ? tid * c : n;
+  const int a1 = a0 + c < n ? a0 + c : n;
+  int sum = 0;
+  for (int j = a0; j < a1; ++j) sum += cnt[j];
+  const int incl = wave_inclusive_scan(sum);
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  int run = incl - sum;
+  for (int w = 0; w < wv; ++w) run += wsum[w];
+  for (int j = a0; j < a1; ++j) {
+    start[j] = run;
+    if (cursor) cursor[j] = run;
+    run += cnt[j];
+  }
+  if (tid == 1023) start[n] = run;
+}
+
+// One 256-lane workgroup per op, lanes = the op's invocations.  The op's
+// table is the same for every lane, so it is read through the scalar cache
+// (constant address space: s_load into SGPRs) and each (invocation,
+// configuration) pair costs one compare, one select and one min, with the
+// configuration's latency and key as scalar operands.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(4))) u32x4 const_u32x4;
+
+template <int NHW>
+__global__ __launch_bounds__(256) void scan_bucketed_kernel(DevTables t, Batch b, const int32_t* start,
+                                                            const int32_t* perm) {
+  const int v = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int p0 = start[v], p1 = start[v + 1];
+  if (p0 == p1) return;
+  const int64_t ref = t.ref[v];
+  const int64_t W = t.W[(int64_t)b.mode * t.n_ops + v];
+  int seg[NHW + 1];
+#pragma unroll
+  for (int h = 0; h <= NHW; ++h) seg[h] = t.seg_off[(int64_t)v * NHW + h];
+  const int fastest = t.hdr[(int64_t)v * t.hs + NHW + 1];
+  const_u32x4* tab2 = (const_u32x4*)(const void*)t.tab;  // two configurations per 16 bytes
+  for (int pb = p0; pb < p1; pb += 256) {
+    const int p = pb + tid;
+    const bool live = p < p1;
+    const int64_t i = live ? perm[p] : 0;
+    const int64_t r0 = live ? (int64_t)b.slo[i] - b.elapsed[i] : 0;
+    uint32_t best = KEY_NONE;
+#pragma unroll
+    for (int h = 0; h < NHW; ++h) {
+      const int64_t R = remaining_time(r0, b.queue ? b.queue[h] : 0);
+      const int32_t tg = R == 0 ? 0 : (int32_t)div_floor_pos(ref * R, W);
+      int x = seg[h];
+      const int x1 = seg[h + 1];
+      if (x < x1 && (x & 1)) {  // align to a pair
+        const uint2 c = t.tab[x];
+        const uint32_t m = (int32_t)c.x < tg ? c.y : KEY_NONE;
+        best = m < best ? m : best;
+        ++x;
+      }
+      for (; x + 8 <= x1; x += 8) {
+        const u32x4 q0 = tab2[x >> 1], q1 = tab2[(x >> 1) + 1], q2 = tab2[(x >> 1) + 2], q3 = tab2[(x >> 1) + 3];
+        uint32_t m0 = (int32_t)q0.x < tg ? q0.y : KEY_NONE;
+        uint32_t m1 = (int32_t)q0.z < tg ? q0.w : KEY_NONE;
+        uint32_t m2 = (int32_t)q1.x < tg ? q1.y : KEY_NONE;
+        uint32_t m3 = (int32_t)q1.z < tg ? q1.w : KEY_NONE;
+        uint32_t m4 = (int32_t)q2.x < tg ? q2.y : KEY_NONE;
+        uint32_t m5 = (int32_t)q2.z < tg ? q2.w : KEY_NONE;
+        uint32_t m6 = (int32_t)q3.x < tg ? q3.y : KEY_NONE;
+        uint32_t m7 = (int32_t)q3.z < tg ? q3.w : KEY_NONE;
+        m0 = m0 < m1 ? m0 : m1;
+        m2 = m2 < m3 ? m2 : m3;
+        m4 = m4 < m5 ? m4 : m5;
+        m6 = m6 < m7 ? m6 : m7;
+        m0 = m0 < m2 ? m0 : m2;
+        m4 = m4 < m6 ? m4 : m6;
+        m0 = m0 < m4 ? m0 : m4;
+        best = m0 < best ? m0 : best;
+      }
+      for (; x < x1; ++x) {
+        const uint2 c = t.tab[x];
+        const uint32_t m = (int32_t)c.x < tg ? c.y : KEY_NONE;
+        best = m < best ? m : best;
+      }
+    }
+    if (live) write_choice(b, i, best, fastest);
+  }
+}
+
+// DPP controls (GFX9 encoding).
+constexpr int DPP_QUAD_XOR1 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int DPP_QUAD_XOR2 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;
+constexpr int DPP_ROW_MIRROR = 0x140;
+constexpr int DPP_ROW_BCAST15 = 0x142;
+constexpr int DPP_ROW_BCAST31 = 0x143;
+
+__device__ __forceinline__ uint32_t umin32(uint32_t a, uint32_t b) { return a < b ? a : b; }
+
+// Minimum over the 64 lanes, returned to every lane.
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+  v = umin32(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, DPP_QUAD_XOR1, 0xF, 0xF, false));
+  v = umin32(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, DPP_QUAD_XOR2, 0xF, 0xF, false));
+  v = umin32(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, DPP_ROW_HALF_MIRROR, 0xF, 0xF, false));
+  v = umin32(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, DPP_ROW_MIRROR, 0xF, 0xF, false));
+  // every lane of a 16-lane row now holds the row minimum
+  v = umin32(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, DPP_ROW_BCAST15, 0xA, 0xF, false));
+  v = umin32(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, DPP_ROW_BCAST31, 0xC, 0xF, false));
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+template <int NHW>
+__global__ __launch_bounds__(256) void decide_wave_kernel(DevTables t, Batch b) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t i = wave; i < b.n; i += n_waves) {
+    const int v = b.op[i], e = b.elapsed[i], s = b.slo[i];
+    if (invalid_invocation(v, e, s, t.n_ops)) {
+      if (lane == 0) {
+        b.cfg[i] = -1;
+        if (b.flag) b.flag[i] = 0;
+        atomicOr(t.err, 1u);
+      }
+      continue;
+    }
+    const int64_t r0 = (int64_t)s - e;
+    const int64_t ref = t.ref[v];
+    const int64_t W = t.W[(int64_t)b.mode * t.n_ops + v];
+    const int32_t* seg = t.seg_off + (int64_t)v * NHW;
+    uint32_t best = KEY_NONE;
+#pragma unroll
+    for (int h = 0; h < NHW; ++h) {
+      const int64_t R = remaining_time(r0, b.queue ? b.queue[h] : 0);
+      const int32_t target = R == 0 ? 0 : (int32_t)div_floor_pos(ref * R, W);
+      for (int x = seg[h] + lane; x < seg[h + 1]; x += 64) {
+        const uint2 c = t.tab[x];
+        if ((int32_t)c.x < target) best = umin32(best, c.y);
+      }
+    }
+    // any lane feasible?  otherwise skip the reduction and fall back
+    const uint64_t any = __builtin_amdgcn_ballot_w64(best != KEY_NONE);
+    if (any) best = wave_min_u32(best);
+    if (lane == 0) write_choice(b, i, best, t.hdr[(int64_t)v * t.hs + NHW + 1]);
+  }
+}
+
+inline unsigned blocks_for(int64_t n, int per_block) {
+  return (unsigned)((n + per_block - 1) / per_block);
+}
+
+#define LLAMA_DISPATCH_NHW(KERNEL, GRID, BLOCK, STREAM, ...)                         \
+  switch (t.n_hw) {                                                                  \
+    case 1: hipLaunchKernelGGL(KERNEL<1>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
+    case 2: hipLaunchKernelGGL(KERNEL<2>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
+    case 3: hipLaunchKernelGGL(KERNEL<3>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
+    case 4: hipLaunchKernelGGL(KERNEL<4>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
+    case 5: hipLaunchKernelGGL(KERNEL<5>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
+    case 6: hipLaunchKernelGGL(KERNEL<6>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
+    case 7: hipLaunchKernelGGL(KERNEL<7>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
+    case 8: hipLaunchKernelGGL(KERNEL<8>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
+    default: return hipErrorInvalidValue;                                            \
+  }
+
+}  // namespace
+
+hipError_t launch_records(const DevTables& t, int mode0, int n_modes, const int64_t* queue, uint4* rec,
+                          uint2* ovf, hipStream_t s) {
+  if (t.n_ops <= 0) return hipSuccess;
+  LLAMA_DISPATCH_NHW(records_kernel, dim3(t.n_ops), dim3(64), s, t, mode0, n_modes, queue, rec, ovf);
+  return hipGetLastError();
+}
+
+hipError_t launch_relax(const DevTables& t, hipStream_t s) {
+  if (t.n_pipelines <= 0) return hipSuccess;
+  hipLaunchKernelGGL(relax_kernel, dim3(t.n_pipelines), dim3(64), 0, s, t);
+  if (t.n_mst > 0)
+    hipLaunchKernelGGL(thresholds_kernel, dim3(blocks_for(t.n_mst, 256)), dim3(256), 0, s, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_targets(const DevTables& t, const Batch& b, hipStream_t s) {
+  if (b.n == 0) return hipSuccess;
+  LLAMA_DISPATCH_NHW(targets_kernel, dim3(blocks_for(b.n, 256)), dim3(256), s, t, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_indexed(const DevTables& t, const Batch& b, hipStream_t s) {
+  if (b.n == 0) return hipSuccess;
+  LLAMA_DISPATCH_NHW(select_indexed_kernel, dim3(blocks_for(b.n, 256)), dim3(256), s, t, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_decide_indexed(const DevTables& t, const Batch& b, hipStream_t s) {
+  if (b.n == 0) return hipSuccess;
+  const uint4* rec = t.rec + (int64_t)b.mode * t.n_ops * (REC_WORDS / 4);
+  const uint2* ovf = t.ovf + (int64_t)b.mode * t.n_front;
+  if (b.queue) {
+    // records for this call's queueing times, in the context's own buffer
+    hipError_t e = launch_records(t, b.mode, 1, b.queue, t.rec_q, t.ovf_q, s);
+    if (e != hipSuccess) return e;
+    rec = t.rec_q;
+    ovf = t.ovf_q;
+  }
+  hipLaunchKernelGGL(decide_indexed_kernel, dim3(blocks_for(b.n, 256)), dim3(256), 0, s, t, b, rec, ovf);
+  return hipGetLastError();
+}
+
+int64_t full_scan_hist_words(int64_t n_inv, int32_t n_ops) {
+  if (n_ops > BUCKET_LDS_OPS) return 0;
+  return ((n_inv + BUCKET_CHUNK - 1) / BUCKET_CHUNK) * (int64_t)n_ops;
+}
+
+hipError_t launch_decide_full(const DevTables& t, const Batch& b, const FullScratch& w, hipStream_t s) {
+  if (b.n == 0) return hipSuccess;
+  if (t.n_ops <= BUCKET_LDS_OPS) {
+    const int n_chunks = (int)((b.n + BUCKET_CHUNK - 1) / BUCKET_CHUNK);
+    const size_t lds = sizeof(int32_t) * (size_t)t.n_ops;
+    hipLaunchKernelGGL(bucket_hist_kernel, dim3(n_chunks), dim3(1024), lds, s, t, b, w.hist);
+    hipLaunchKernelGGL(bucket_columns_kernel, dim3(blocks_for(t.n_ops, 256)), dim3(256), 0, s, w.hist,
+                       n_chunks, t.n_ops, w.cnt);
+    hipLaunchKernelGGL(bucket_offsets_kernel, dim3(1), dim3(1024), 0, s, w.cnt, t.n_ops, w.start,
+                       (int32_t*)nullptr);
+    hipLaunchKernelGGL(bucket_place_kernel, dim3(n_chunks), dim3(1024), lds, s, t, b, w.hist, w.start, w.perm);
+  } else {
+    const unsigned g = blocks_for(b.n, 256);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks_for(t.n_ops + 1, 256)), dim3(256), 0, s, w.cnt,
+                       (int64_t)t.n_ops + 1);
+    hipLaunchKernelGGL(bucket_count_kernel, dim3(g), dim3(256), 0, s, t, b, w.cnt);
+    hipLaunchKernelGGL(bucket_offsets_kernel, dim3(1), dim3(1024), 0, s, w.cnt, t.n_ops, w.start, w.cursor);
+    hipLaunchKernelGGL(bucket_scatter_kernel, dim3(g), dim3(256), 0, s, t, b, w.cursor, w.perm);
+  }
+  LLAMA_DISPATCH_NHW(scan_bucketed_kernel, dim3(t.n_ops), dim3(256), s, t, b, w.start, w.perm);
+  return hipGetLastError();
+}
+
+hipError_t launch_decide_wave(const DevTables& t, const Batch& b, hipStream_t s) {
+  if (b.n == 0) return hipSuccess;
+  // 4 waves per block; enough blocks for every CU several times over, each
+  // wave then walks its invocations with a grid stride.
+  const int64_t waves = b.n < (int64_t)256 * 4 * 16 ? b.n : (int64_t)256 * 4 * 16;
+  LLAMA_DISPATCH_NHW(decide_wave_kernel, dim3(blocks_for(waves, 4)), dim3(256), s, t, b);
+  return hipGetLastError();
+}
+
+}  // namespace llama
