@@ -253,6 +253,89 @@ int llama_get_stats(llama_ctx *ctx, llama_stats *out, int32_t reset_error);
  */
 int llama_debug_export(llama_ctx *ctx, int32_t what, void *host_out, int64_t bytes);
 
+/* ------------------------------------------------------------------------
+ * Learned latency surrogate.
+ *
+ * The paper corrects profiled latencies through a feedback loop and notes
+ * that estimators other than exponential smoothing can be used (Sec. 3.3,
+ * Manager); it also shows that input content changes an operation's latency
+ * several-fold (Sec. 2, Fig. 3).  The surrogate predicts, for each
+ * (invocation, configuration) row, the mean and the 95th percentile of
+ * ln(latency in microseconds) from a per-row embedding (one per profile row)
+ * and 16 content features:
+ *     x = [E[row] (16), f (16)], h1 = GELU(W1 x + b1), h2 = GELU(W2 h1 + b2)
+ *     (mu, q) = W3 h2 + b3,      hidden width 256, GELU = tanh form
+ * BF16 weights, embedding, features and activations; FP32 accumulation, FP32
+ * master weights and AdamW state.  Training loss per row:
+ *     (mu - y)^2 + rho_0.95(y - q),  rho_t(u) = u (t - [u < 0]),
+ * y = observed ln latency.  Parameters are one float vector laid out
+ *     E [n_cfg][16], W1 [256][32], b1 [256], W2 [256][256], b2 [256],
+ *     W3 [2][256], b3 [2]
+ * with n_cfg = the profile's configuration rows.  Features are BF16 bit
+ * patterns (uint16), 16 per invocation or training row.
+ * ---------------------------------------------------------------------- */
+#define LLAMA_SURR_EMB 16
+#define LLAMA_SURR_FEAT 16
+#define LLAMA_SURR_HIDDEN 256
+
+/* Number of floats in the parameter vector for n_rows profile rows. */
+int64_t llama_surrogate_param_count(int64_t n_rows);
+
+/* Deterministic initial parameters from `seed` (normal weights scaled by
+ * fan-in, zero biases, b3 = (mean_log_latency, mean_log_latency + 0.5));
+ * resets AdamW state.  Needs llama_set_profiles.  Synchronous. */
+int llama_surrogate_init(llama_ctx *ctx, uint64_t seed, float mean_log_latency);
+
+/* Replace / read the FP32 parameter vector (host pointer, n floats exactly
+ * llama_surrogate_param_count(n_cfg)).  _set resets AdamW state.  Synchronous. */
+int llama_surrogate_set(llama_ctx *ctx, const float *params, int64_t n);
+int llama_surrogate_get(llama_ctx *ctx, float *params, int64_t n);
+
+/* Gradient of the mean batch loss from the last llama_surrogate_train_step
+ * (host pointer, same layout).  Synchronous. */
+int llama_surrogate_grads(llama_ctx *ctx, float *grads, int64_t n);
+
+/* Pre-size the training workspace for batches of up to max_batch rows
+ * (needed before capturing training or forward calls into a graph). */
+int llama_surrogate_reserve(llama_ctx *ctx, int64_t max_batch);
+
+/* Training-path forward for n rows (device pointers): d_rows [n] profile row
+ * ids, d_feat [n][16] BF16, d_out [n][2] FP32 (mu, q). */
+int llama_surrogate_forward(llama_ctx *ctx, int64_t n, const int32_t *d_rows,
+                            const uint16_t *d_feat, float *d_out, void *stream);
+
+/* One training step on a batch (device pointers d_rows, d_feat, d_y [batch]
+ * observed ln latency): forward, backward into the gradient buffer and, when
+ * `update` is non-zero, one AdamW step (betas 0.9, 0.999, eps 1e-8; decoupled
+ * weight decay on E, W1, W2, W3) with learning rate lr.  d_loss_sum, when not
+ * NULL, has the batch's summed loss added to it. */
+int llama_surrogate_train_step(llama_ctx *ctx, int64_t batch, const int32_t *d_rows,
+                               const uint16_t *d_feat, const float *d_y, float lr,
+                               float weight_decay, int32_t update, float *d_loss_sum,
+                               void *stream);
+
+/* Checkpoint: parameters, AdamW moments and step count in one versioned
+ * binary file; _load requires the same number of profile rows. */
+int llama_surrogate_save(llama_ctx *ctx, const char *path);
+int llama_surrogate_load(llama_ctx *ctx, const char *path);
+
+/*
+ * llama_decide with the surrogate's latency in place of the profile: for
+ * every configuration x of the invocation's op, L(x) = ceil(exp(q)) when the
+ * predicted spread q - mu is finite and in [0, spread_max], otherwise the
+ * profiled latency; Eq. 1 then runs on those latencies (fallback: the
+ * smallest predicted latency).  d_feat [n_inv][16] BF16 content features.
+ * d_lat_out, when not NULL, receives each row's latency at
+ * [i * lat_stride + k] (lat_stride >= the largest configuration count).
+ * The fused kernel keeps every hidden activation on chip.
+ */
+int llama_decide_learned(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
+                         const int32_t *d_elapsed_us, const int32_t *d_slo_us,
+                         const int64_t *d_queue_us, int32_t slack_mode,
+                         const uint16_t *d_feat, float spread_max, int32_t *d_cfg,
+                         uint8_t *d_flag, int32_t *d_lat_out, int64_t lat_stride,
+                         void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -50,8 +50,9 @@ def load(path):
     L.oracle_select.argtypes = [i64, p, p, i32, i32, p, p, p, p, p, p, p]
     L.oracle_decide.argtypes = [i64, p, p, p, i32, p, i32, p, p, p, p, p,
                                 p, p, p, p, p]
-    for f in (L.oracle_reference_cfg, L.oracle_worst_path,
-              L.oracle_targets, L.oracle_select, L.oracle_decide):
+    L.oracle_select_lat.argtypes = [i64, p, p, i32, i32, p, p, p, p, i64, p, p, p]
+    for f in (L.oracle_reference_cfg, L.oracle_worst_path, L.oracle_targets,
+              L.oracle_select, L.oracle_decide, L.oracle_select_lat):
         f.restype = ctypes.c_int
     return L
 
@@ -158,6 +159,25 @@ def select(inv_op, target, n_hw, cfg_off, hw, batch, lat, cost):
            lib().oracle_select(n, _ptr(inv_op), _ptr(target), n_hw, len(cfg_off) - 1,
                                _ptr(cfg_off), _ptr(hw), _ptr(batch), _ptr(lat),
                                _ptr(cost), _ptr(cfg), _ptr(flag)))
+    return cfg, flag
+
+
+def select_lat(inv_op, target, n_hw, cfg_off, hw, batch, lat_inv, cost):
+    """Eq. 1 with a latency per (invocation, configuration): lat_inv is
+    [n_inv, stride] holding the op's configurations in caller order."""
+    inv_op = _arr(inv_op, np.int32)
+    n = len(inv_op)
+    target = _arr(target, np.int32).reshape(n, n_hw)
+    cfg_off = _arr(cfg_off, np.int32)
+    hw, batch = (_arr(x, np.int32) for x in (hw, batch))
+    lat_inv = _arr(lat_inv, np.int32).reshape(n, -1)
+    cost = _arr(cost, np.int64)
+    cfg = np.empty(n, np.int32)
+    flag = np.empty(n, np.uint8)
+    _check("oracle_select_lat",
+           lib().oracle_select_lat(n, _ptr(inv_op), _ptr(target), n_hw, len(cfg_off) - 1,
+                                   _ptr(cfg_off), _ptr(hw), _ptr(batch), _ptr(lat_inv),
+                                   lat_inv.shape[1], _ptr(cost), _ptr(cfg), _ptr(flag)))
     return cfg, flag
 
 

@@ -187,6 +187,15 @@ int oracle_targets(int64_t n_inv, const int32_t *inv_op,
     return ORACLE_OK;
 }
 
+/* Cost per item of x is strictly below that of y: C_x/B_x < C_y/B_y, by exact
+ * cross-multiplication. */
+static int per_item_less(const int64_t *cost, const int32_t *batch, int32_t x, int32_t y)
+{
+    __int128 lhs = (__int128)cost[x] * (__int128)batch[y];
+    __int128 rhs = (__int128)cost[y] * (__int128)batch[x];
+    return lhs < rhs;
+}
+
 /*
  * Eq. 1 with the fallback "fastest": for invocation i of op v, scan every
  * configuration x of v.  x is feasible when lat[x] < target[i][hw[x]]
@@ -227,10 +236,7 @@ int oracle_select(int64_t n_inv, const int32_t *inv_op, const int32_t *target,
                 best = x;
                 continue;
             }
-            /* cost[x]/batch[x] < cost[best]/batch[best] ? */
-            __int128 lhs = (__int128)cost[x] * (__int128)batch[best];
-            __int128 rhs = (__int128)cost[best] * (__int128)batch[x];
-            if (lhs < rhs)
+            if (per_item_less(cost, batch, x, best))
                 best = x;
         }
         if (best >= 0) {
@@ -281,6 +287,65 @@ int oracle_decide(int64_t n_inv, const int32_t *inv_op, const int32_t *elapsed,
                            hw, batch, lat, cost, cfg + i, flag ? flag + i : 0);
         if (rc)
             return rc;
+    }
+    return ORACLE_OK;
+}
+
+/*
+ * Eq. 1 with per-invocation latencies (the learned form): identical to
+ * oracle_select except that configuration x of invocation i is feasible when
+ * lat_inv[i * lat_stride + (x - cfg_off[v])] < target[i][hw[x]], and the
+ * fallback is the configuration with the smallest such latency (lowest index
+ * on ties).  Costs and batches are the profile's.
+ */
+int oracle_select_lat(int64_t n_inv, const int32_t *inv_op, const int32_t *target,
+                      int32_t n_hw, int32_t n_ops, const int32_t *cfg_off,
+                      const int32_t *hw, const int32_t *batch,
+                      const int32_t *lat_inv, int64_t lat_stride,
+                      const int64_t *cost, int32_t *cfg, uint8_t *flag)
+{
+    if (n_inv < 0 || n_hw < 1 || n_ops < 0 || lat_stride < 0)
+        return ORACLE_E_ARG;
+    if (n_inv > 0 && (!inv_op || !target || !cfg || !lat_inv))
+        return ORACLE_E_ARG;
+    if (!cfg_off || !hw || !batch || !cost)
+        return ORACLE_E_ARG;
+    for (int64_t i = 0; i < n_inv; ++i) {
+        int32_t v = inv_op[i];
+        if (v < 0 || v >= n_ops || cfg_off[v + 1] - cfg_off[v] > lat_stride) {
+            cfg[i] = -1;
+            if (flag)
+                flag[i] = 0;
+            continue;
+        }
+        const int32_t *L = lat_inv + i * lat_stride - cfg_off[v];
+        int32_t best = -1;
+        for (int32_t x = cfg_off[v]; x < cfg_off[v + 1]; ++x) {
+            int32_t h = hw[x];
+            if (h < 0 || h >= n_hw)
+                return ORACLE_E_RANGE;
+            if (!(L[x] < target[i * n_hw + h]))
+                continue;
+            if (best < 0) {
+                best = x;
+                continue;
+            }
+            if (per_item_less(cost, batch, x, best))
+                best = x;
+        }
+        if (best >= 0) {
+            cfg[i] = best - cfg_off[v];
+            if (flag)
+                flag[i] = 1;
+            continue;
+        }
+        int32_t fast = cfg_off[v];
+        for (int32_t x = cfg_off[v] + 1; x < cfg_off[v + 1]; ++x)
+            if (L[x] < L[fast])
+                fast = x;
+        cfg[i] = fast - cfg_off[v];
+        if (flag)
+            flag[i] = 0;
     }
     return ORACLE_OK;
 }

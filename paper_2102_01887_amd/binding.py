@@ -23,7 +23,10 @@ DEVERR_INVALID_INVOCATION = 1
 EXPORTS = ["llama_create", "llama_destroy", "llama_last_error", "llama_set_dag",
            "llama_set_profiles", "llama_relax", "llama_update_latencies", "llama_targets",
            "llama_select", "llama_decide", "llama_reserve", "llama_get_stats",
-           "llama_debug_export"]
+           "llama_debug_export", "llama_surrogate_param_count", "llama_surrogate_init",
+           "llama_surrogate_set", "llama_surrogate_get", "llama_surrogate_grads",
+           "llama_surrogate_reserve", "llama_surrogate_forward", "llama_surrogate_train_step",
+           "llama_surrogate_save", "llama_surrogate_load", "llama_decide_learned"]
 
 
 class LlamaStats(ctypes.Structure):
@@ -60,12 +63,24 @@ def load_library(path=LIB_PATH):
         "llama_reserve": [p, i64],
         "llama_get_stats": [p, ctypes.POINTER(LlamaStats), i32],
         "llama_debug_export": [p, i32, p, i64],
+        "llama_surrogate_param_count": [i64],
+        "llama_surrogate_init": [p, ctypes.c_uint64, ctypes.c_float],
+        "llama_surrogate_set": [p, p, i64],
+        "llama_surrogate_get": [p, p, i64],
+        "llama_surrogate_grads": [p, p, i64],
+        "llama_surrogate_reserve": [p, i64],
+        "llama_surrogate_forward": [p, i64, p, p, p, p],
+        "llama_surrogate_train_step": [p, i64, p, p, p, ctypes.c_float, ctypes.c_float, i32, p, p],
+        "llama_surrogate_save": [p, ctypes.c_char_p],
+        "llama_surrogate_load": [p, ctypes.c_char_p],
+        "llama_decide_learned": [p, i64, p, p, p, p, i32, p, ctypes.c_float, p, p, p, i64, p],
     }
     for name, args in sig.items():
         f = getattr(L, name)
         f.argtypes = args
         f.restype = ctypes.c_int
     L.llama_destroy.restype = None
+    L.llama_surrogate_param_count.restype = ctypes.c_int64
     L.llama_last_error.restype = ctypes.c_char_p
     if path == LIB_PATH:
         _lib = L
@@ -96,6 +111,17 @@ def _dp(t, dtype_name, n=None):
         raise ValueError(f"expected torch.{dtype_name}, got {t.dtype}")
     if not t.is_contiguous():
         raise ValueError("expected a contiguous tensor")
+    if n is not None and t.numel() < n:
+        raise ValueError(f"tensor has {t.numel()} elements, need {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dp16(t, n=None):
+    """Device pointer of a contiguous 2-byte tensor holding BF16 bit patterns."""
+    if t is None:
+        return None
+    if not t.is_cuda or t.element_size() != 2 or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor of bfloat16 (or 16-bit) elements")
     if n is not None and t.numel() < n:
         raise ValueError(f"tensor has {t.numel()} elements, need {n}")
     return ctypes.c_void_p(t.data_ptr())
@@ -227,3 +253,68 @@ class Llama:
         self._check("llama_debug_export", self._L.llama_debug_export(
             self._ctx, code, _hp(out), out.nbytes))
         return out
+
+    # -- learned surrogate --------------------------------------------------------
+    def surrogate_param_count(self):
+        return int(self._L.llama_surrogate_param_count(self.n_cfg))
+
+    def surrogate_init(self, seed=0, mean_log_latency=10.0):
+        self._check("llama_surrogate_init",
+                    self._L.llama_surrogate_init(self._ctx, int(seed), float(mean_log_latency)))
+
+    def surrogate_set(self, params):
+        p = _np(params, np.float32)
+        self._check("llama_surrogate_set", self._L.llama_surrogate_set(self._ctx, _hp(p), p.size))
+
+    def surrogate_get(self):
+        out = np.empty(self.surrogate_param_count(), np.float32)
+        self._check("llama_surrogate_get", self._L.llama_surrogate_get(self._ctx, _hp(out), out.size))
+        return out
+
+    def surrogate_grads(self):
+        out = np.empty(self.surrogate_param_count(), np.float32)
+        self._check("llama_surrogate_grads", self._L.llama_surrogate_grads(self._ctx, _hp(out), out.size))
+        return out
+
+    def surrogate_reserve(self, max_batch):
+        self._check("llama_surrogate_reserve", self._L.llama_surrogate_reserve(self._ctx, int(max_batch)))
+
+    def surrogate_forward(self, rows, feat, out=None, stream=None):
+        import torch
+        n = rows.numel()
+        if out is None:
+            out = torch.empty((n, 2), dtype=torch.float32, device=rows.device)
+        self._check("llama_surrogate_forward", self._L.llama_surrogate_forward(
+            self._ctx, n, _dp(rows, "int32"), _dp16(feat, 16 * n), _dp(out, "float32", 2 * n),
+            _stream(stream)))
+        return out
+
+    def surrogate_train_step(self, rows, feat, y, lr, weight_decay=0.0, update=True, loss_sum=None,
+                             stream=None):
+        n = rows.numel()
+        self._check("llama_surrogate_train_step", self._L.llama_surrogate_train_step(
+            self._ctx, n, _dp(rows, "int32"), _dp16(feat, 16 * n), _dp(y, "float32", n),
+            float(lr), float(weight_decay), 1 if update else 0, _dp(loss_sum, "float32", 1),
+            _stream(stream)))
+
+    def surrogate_save(self, path):
+        self._check("llama_surrogate_save", self._L.llama_surrogate_save(self._ctx, str(path).encode()))
+
+    def surrogate_load(self, path):
+        self._check("llama_surrogate_load", self._L.llama_surrogate_load(self._ctx, str(path).encode()))
+
+    def decide_learned(self, op, elapsed, slo, feat, queue=None, mode=SLACK_PAPER, spread_max=1.3862944,
+                       cfg=None, flag=None, lat_out=None, lat_stride=0, stream=None):
+        import torch
+        n = op.numel()
+        if cfg is None:
+            cfg = torch.empty(n, dtype=torch.int32, device=op.device)
+        if flag is None:
+            flag = torch.empty(n, dtype=torch.uint8, device=op.device)
+        self._check("llama_decide_learned", self._L.llama_decide_learned(
+            self._ctx, n, _dp(op, "int32"), _dp(elapsed, "int32", n), _dp(slo, "int32", n),
+            _dp(queue, "int64", self.n_hw), int(mode), _dp16(feat, 16 * n), float(spread_max),
+            _dp(cfg, "int32", n), _dp(flag, "uint8", n),
+            _dp(lat_out, "int32", n * lat_stride) if lat_out is not None else None,
+            int(lat_stride), _stream(stream)))
+        return cfg, flag

@@ -1,0 +1,131 @@
+// Internal: the context object shared by the host sources of libllama.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <string>
+#include <vector>
+
+#include "llama.h"
+#include "llama_internal.h"
+
+namespace llama {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// Learned-surrogate state (surrogate_host.cpp).
+struct Surrogate {
+  bool ready = false;
+  int64_t n_rows = 0, n_params = 0, step = 0;
+  DevBuf master, adam_m, adam_v, grad;              // fp32 [n_params], layout E, W1, b1, W2, b2, W3, b3
+  DevBuf E16, W1_16, W2_16, W2p16, W3_16;           // bf16 shadows
+  int64_t ws_batch = 0;                             // training workspace capacity (rows)
+  DevBuf X16, z1, h1, z2, h2, out, dout, dh2, dz2, dh1, dz1, dX;
+};
+
+}  // namespace llama
+
+using llama::DevBuf;
+using llama::DevTables;
+
+
+struct llama_ctx {
+  int device = 0;
+  std::string err;
+  hipStream_t stream = nullptr;  // the context's own stream for ingest work
+
+  // DAG
+  bool has_dag = false;
+  int32_t n_pipelines = 0, n_ops = 0, max_depth = 0;
+  int64_t n_edges = 0;
+  std::vector<int32_t> pipe_off, succ_off, succ_ids, pipe_of;
+  std::vector<uint32_t> succ_q;
+  DevBuf d_pipe_off, d_pipe_lvl, d_lvl_bnd, d_lvl_ops, d_succ_off, d_succ_ids, d_succ_q;
+
+  // profiles
+  bool has_prof = false;
+  int32_t n_hw = 0;
+  int64_t n_cfg = 0, n_front = 0;
+  std::vector<int32_t> cfg_off, hw, batch, res, lat, ref_k, ref, fastest;
+  std::vector<int64_t> cost;
+  std::vector<uint32_t> key;  // caller order
+  DevBuf d_ref, d_W, d_hdr, d_front_L, d_rec, d_ovf, d_rec_q, d_ovf_q, d_seg_off, d_tab;
+  DevBuf d_mst, d_mst_op, d_mst_first;
+  DevBuf d_cfg_off, d_cfg_hw, d_cfg_lat, d_cfg_key;
+  int64_t n_mst = 0;
+  DevBuf d_err;
+  llama::Surrogate surr;
+  DevBuf d_cnt, d_start, d_cursor, d_perm, d_hist;  // bucketed full scan
+  int64_t perm_cap = 0;
+
+  DevTables tables() const {
+    DevTables t{};
+    t.n_ops = n_ops;
+    t.n_hw = n_hw;
+    t.n_pipelines = n_pipelines;
+    t.hs = llama::header_stride(n_hw);
+    t.n_front = n_front;
+    t.pipe_off = d_pipe_off.as<int32_t>();
+    t.pipe_lvl = d_pipe_lvl.as<int32_t>();
+    t.lvl_bnd = d_lvl_bnd.as<int32_t>();
+    t.lvl_ops = d_lvl_ops.as<int32_t>();
+    t.succ_off = d_succ_off.as<int32_t>();
+    t.succ_ids = d_succ_ids.as<int32_t>();
+    t.succ_q = d_succ_q.as<uint32_t>();
+    t.ref = d_ref.as<int32_t>();
+    t.W = d_W.as<int64_t>();
+    t.hdr = d_hdr.as<int32_t>();
+    t.front_L = d_front_L.as<uint2>();
+    t.n_mst = n_mst;
+    t.mst = d_mst.as<uint2>();
+    t.mst_op = d_mst_op.as<int32_t>();
+    t.mst_first = d_mst_first.as<int32_t>();
+    t.rec = d_rec.as<uint4>();
+    t.ovf = d_ovf.as<uint2>();
+    t.rec_q = d_rec_q.as<uint4>();
+    t.ovf_q = d_ovf_q.as<uint2>();
+    t.cfg_off = d_cfg_off.as<int32_t>();
+    t.cfg_hw = d_cfg_hw.as<int32_t>();
+    t.cfg_lat = d_cfg_lat.as<int32_t>();
+    t.cfg_key = d_cfg_key.as<uint32_t>();
+    t.seg_off = d_seg_off.as<int32_t>();
+    t.tab = d_tab.as<uint2>();
+    t.err = d_err.as<uint32_t>();
+    return t;
+  }
+
+  int64_t device_bytes() const {
+    const DevBuf* all[] = {&d_pipe_off, &d_pipe_lvl, &d_lvl_bnd, &d_lvl_ops, &d_succ_off,
+                           &d_succ_ids, &d_succ_q, &d_ref, &d_W, &d_hdr, &d_front_L,
+                           &d_rec, &d_ovf, &d_rec_q, &d_ovf_q, &d_seg_off, &d_tab, &d_err,
+                           &d_cnt, &d_start, &d_cursor, &d_perm, &d_hist, &d_mst, &d_mst_op,
+                           &d_mst_first, &d_cfg_off, &d_cfg_hw, &d_cfg_lat, &d_cfg_key};
+    int64_t s = 0;
+    for (auto* b : all) s += (int64_t)b->bytes;
+    return s;
+  }
+};
+
+
+namespace llama {
+// helpers implemented in llama_host.cpp
+int fail(llama_ctx* c, int code, const char* fmt, ...);
+int hip_fail(llama_ctx* c, hipError_t e, const char* what);
+int upload(llama_ctx* c, DevBuf& buf, const void* src, size_t bytes, const char* what);
+int enter(llama_ctx* c);
+int sync_ctx(llama_ctx* c, const char* what);
+}  // namespace llama

@@ -30,102 +30,17 @@
 #include <vector>
 
 #include "llama.h"
+#include "llama_ctx.h"
 #include "llama_internal.h"
 
 using llama::DevTables;
+using llama::fail;
+using llama::hip_fail;
+using llama::upload;
+using llama::enter;
+using llama::sync_ctx;
 
-namespace {
-
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-  DevBuf() = default;
-  DevBuf(const DevBuf&) = delete;
-  DevBuf& operator=(const DevBuf&) = delete;
-  ~DevBuf() { release(); }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-  }
-  template <typename T>
-  T* as() const { return static_cast<T*>(p); }
-};
-
-}  // namespace
-
-struct llama_ctx {
-  int device = 0;
-  std::string err;
-  hipStream_t stream = nullptr;  // the context's own stream for ingest work
-
-  // DAG
-  bool has_dag = false;
-  int32_t n_pipelines = 0, n_ops = 0, max_depth = 0;
-  int64_t n_edges = 0;
-  std::vector<int32_t> pipe_off, succ_off, succ_ids, pipe_of;
-  std::vector<uint32_t> succ_q;
-  DevBuf d_pipe_off, d_pipe_lvl, d_lvl_bnd, d_lvl_ops, d_succ_off, d_succ_ids, d_succ_q;
-
-  // profiles
-  bool has_prof = false;
-  int32_t n_hw = 0;
-  int64_t n_cfg = 0, n_front = 0;
-  std::vector<int32_t> cfg_off, hw, batch, res, lat, ref_k, ref, fastest;
-  std::vector<int64_t> cost;
-  std::vector<uint32_t> key;  // caller order
-  DevBuf d_ref, d_W, d_hdr, d_front_L, d_rec, d_ovf, d_rec_q, d_ovf_q, d_seg_off, d_tab;
-  DevBuf d_mst, d_mst_op, d_mst_first;
-  int64_t n_mst = 0;
-  DevBuf d_err;
-  DevBuf d_cnt, d_start, d_cursor, d_perm, d_hist;  // bucketed full scan
-  int64_t perm_cap = 0;
-
-  DevTables tables() const {
-    DevTables t{};
-    t.n_ops = n_ops;
-    t.n_hw = n_hw;
-    t.n_pipelines = n_pipelines;
-    t.hs = llama::header_stride(n_hw);
-    t.n_front = n_front;
-    t.pipe_off = d_pipe_off.as<int32_t>();
-    t.pipe_lvl = d_pipe_lvl.as<int32_t>();
-    t.lvl_bnd = d_lvl_bnd.as<int32_t>();
-    t.lvl_ops = d_lvl_ops.as<int32_t>();
-    t.succ_off = d_succ_off.as<int32_t>();
-    t.succ_ids = d_succ_ids.as<int32_t>();
-    t.succ_q = d_succ_q.as<uint32_t>();
-    t.ref = d_ref.as<int32_t>();
-    t.W = d_W.as<int64_t>();
-    t.hdr = d_hdr.as<int32_t>();
-    t.front_L = d_front_L.as<uint2>();
-    t.n_mst = n_mst;
-    t.mst = d_mst.as<uint2>();
-    t.mst_op = d_mst_op.as<int32_t>();
-    t.mst_first = d_mst_first.as<int32_t>();
-    t.rec = d_rec.as<uint4>();
-    t.ovf = d_ovf.as<uint2>();
-    t.rec_q = d_rec_q.as<uint4>();
-    t.ovf_q = d_ovf_q.as<uint2>();
-    t.seg_off = d_seg_off.as<int32_t>();
-    t.tab = d_tab.as<uint2>();
-    t.err = d_err.as<uint32_t>();
-    return t;
-  }
-
-  int64_t device_bytes() const {
-    const DevBuf* all[] = {&d_pipe_off, &d_pipe_lvl, &d_lvl_bnd, &d_lvl_ops, &d_succ_off,
-                           &d_succ_ids, &d_succ_q, &d_ref, &d_W, &d_hdr, &d_front_L,
-                           &d_rec, &d_ovf, &d_rec_q, &d_ovf_q, &d_seg_off, &d_tab, &d_err,
-                           &d_cnt, &d_start, &d_cursor, &d_perm, &d_hist, &d_mst, &d_mst_op,
-                           &d_mst_first};
-    int64_t s = 0;
-    for (auto* b : all) s += (int64_t)b->bytes;
-    return s;
-  }
-};
-
-namespace {
+namespace llama {
 
 int fail(llama_ctx* c, int code, const char* fmt, ...) {
   char buf[512];
@@ -160,11 +75,6 @@ int upload(llama_ctx* c, DevBuf& buf, const void* src, size_t bytes, const char*
   return LLAMA_OK;
 }
 
-template <typename T>
-int upload_vec(llama_ctx* c, DevBuf& buf, const std::vector<T>& v, const char* what) {
-  return upload(c, buf, v.data(), v.size() * sizeof(T), what);
-}
-
 int enter(llama_ctx* c) {
   if (!c) return LLAMA_E_ARG;
   c->err.clear();
@@ -177,6 +87,15 @@ int sync_ctx(llama_ctx* c, const char* what) {
   hipError_t e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(c, e, what);
   return LLAMA_OK;
+}
+
+}  // namespace llama
+
+namespace {
+
+template <typename T>
+int upload_vec(llama_ctx* c, DevBuf& buf, const std::vector<T>& v, const char* what) {
+  return upload(c, buf, v.data(), v.size() * sizeof(T), what);
 }
 
 // C/B of x is smaller than C/B of y (exact: C <= 2^40, B <= 2^16).
@@ -578,6 +497,10 @@ int build_tables(llama_ctx* c) {
       (rc = upload(c, c->d_rec_q, nullptr, (size_t)llama::REC_WORDS * 4 * n_ops, "records (queue)")) ||
       (rc = upload(c, c->d_ovf_q, nullptr, sizeof(uint2) * (size_t)pos, "record overflow (queue)")) ||
       (rc = upload_vec(c, c->d_seg_off, seg_off, "seg_off")) ||
+      (rc = upload_vec(c, c->d_cfg_off, c->cfg_off, "cfg_off")) ||
+      (rc = upload_vec(c, c->d_cfg_hw, c->hw, "cfg_hw")) ||
+      (rc = upload_vec(c, c->d_cfg_lat, c->lat, "cfg_lat")) ||
+      (rc = upload_vec(c, c->d_cfg_key, c->key, "cfg_key")) ||
       (rc = upload(c, c->d_cnt, nullptr, sizeof(int32_t) * ((size_t)n_ops + 1), "bucket counts")) ||
       (rc = upload(c, c->d_start, nullptr, sizeof(int32_t) * ((size_t)n_ops + 1), "bucket starts")) ||
       (rc = upload(c, c->d_cursor, nullptr, sizeof(int32_t) * (size_t)n_ops, "bucket cursors")) ||

@@ -63,6 +63,10 @@ struct DevTables {
   uint2* ovf;                // [2*n_front] full frontiers {T, key} ascending, PAPER then PROB
   uint4* rec_q;              // [n_ops*4] records for a per-call queueing-time vector
   uint2* ovf_q;              // [n_front]
+  const int32_t* cfg_off;    // [n_ops+1] caller-order configuration rows of each op
+  const int32_t* cfg_hw;     // [n_cfg] backend, caller order
+  const int32_t* cfg_lat;    // [n_cfg] profiled latency, caller order
+  const uint32_t* cfg_key;   // [n_cfg] rank << 16 | k, caller order
   const int32_t* seg_off;    // [n_ops*n_hw+1] backend segments of the full table
   const uint2* tab;          // [n_cfg] {latency, key}, grouped by (op, backend), caller order inside
   uint32_t* err;             // device error word
@@ -102,5 +106,43 @@ struct FullScratch {
 int64_t full_scan_hist_words(int64_t n_inv, int32_t n_ops);
 hipError_t launch_decide_full(const DevTables& t, const Batch& b, const FullScratch& w, hipStream_t s);
 hipError_t launch_decide_wave(const DevTables& t, const Batch& b, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Learned surrogate
+// ---------------------------------------------------------------------------
+constexpr int SURR_EMB = 16, SURR_FEAT = 16, SURR_IN = 32, SURR_HID = 256, SURR_OUT = 2;
+
+// Device buffers of the surrogate (BF16 arrays as void*).  Parameters are one
+// FP32 vector laid out E [n_rows][16], W1 [256][32], b1 [256], W2 [256][256],
+// b2 [256], W3 [2][256], b3 [2]; o* are the offsets of each part.
+struct SurrogateBufs {
+  int64_t n_params, nE, oW1, ob1, oW2, ob2, oW3, ob3;
+  float *master, *adam_m, *adam_v, *grad;
+  const float *b1, *b2, *b3;
+  void *E16, *W1_16, *W2_16, *W2p16, *W3_16;
+  // training workspace, B rows
+  void *X16, *h1, *h2, *dout, *dz2, *dz1;
+  float *z1, *z2, *out, *dh2, *dh1, *dX;
+};
+
+struct LearnedArgs {
+  const void* feat;          // [n_inv][16] BF16 content features
+  const void *E16, *W1_16, *W2p16, *W3_16;
+  const float *b1, *b2, *b3;
+  float spread_max;          // fall back to the profile when q - mu is outside [0, spread_max]
+  int32_t* lat_out;          // optional [n_inv][lat_stride] predicted p95 latency per row
+  int64_t lat_stride;
+};
+
+hipError_t launch_gemm_bf16(int M, int N, int K, const void* a, int64_t sam, int64_t sak, const void* b,
+                            int64_t sbk, int64_t sbn, float* c, int64_t ldc, const float* bias, bool accumulate,
+                            hipStream_t s);
+hipError_t launch_surrogate_forward(const SurrogateBufs& w, int64_t B, const int32_t* rows, const void* feat,
+                                    hipStream_t s);
+hipError_t launch_surrogate_backward(const SurrogateBufs& w, int64_t B, const int32_t* rows, const float* y,
+                                     float* loss_sum, hipStream_t s);
+hipError_t launch_adamw(const SurrogateBufs& w, float lr, float wd, int64_t step, hipStream_t s);
+hipError_t launch_shadows(const SurrogateBufs& w, hipStream_t s);
+hipError_t launch_decide_learned(const DevTables& t, const Batch& b, const LearnedArgs& a, hipStream_t s);
 
 }  // namespace llama

@@ -148,7 +148,6 @@ __global__ __launch_bounds__(64) void relax_kernel(DevTables t) {
 constexpr int REC_LDS = 512;
 constexpr int BUCKET_CHUNK = 16384;  // invocations per histogram chunk
 constexpr int BUCKET_LDS_OPS = 12288;  // ops countable in one LDS histogram (48 KB)
-constexpr int SCAN_CHUNK = 4096;     // configurations staged at once (32 KB)
 constexpr int64_t T_INF = 0x7FFFFFFFFFFFFFFFll;
 
 // Stored form of a remaining-time threshold T: U = T - 1, clamped at

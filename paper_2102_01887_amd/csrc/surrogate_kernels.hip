@@ -1,0 +1,481 @@
+// HIP kernels (gfx950) of the learned latency surrogate.
+//
+// The network, per (invocation, configuration) row:
+//   x = [E[row] (16), f (16)] (BF16)
+//   h1 = GELU(W1 x + b1), h2 = GELU(W2 h1 + b2) (256 each, rounded to BF16)
+//   (mu, q) = W3 h2 + b3 : mean and 95th percentile of ln(latency in us)
+// GELU is the tanh form (Hendrycks & Gimpel 2016), written here as
+// x * sigmoid(2u), u = sqrt(2/pi) (x + 0.044715 x^3), which is the same
+// function.
+//
+// Training: gemm_bf16_kernel (v_mfma_f32_16x16x32_bf16, FP32 accumulation,
+// LDS tiles) for every product of the forward and backward passes, plus
+// elementwise kernels (GELU, loss gradient, GELU', column sums, embedding
+// scatter) and AdamW on FP32 master weights with BF16 shadows.
+//
+// Inference: decide_learned_kernel, persistent, one wavefront per invocation
+// and 64 configuration rows per pass.  W1 and a K-permuted copy of W2 sit in
+// LDS (144 KB); hidden activations never leave registers: the layer-1 output
+// fragment of each lane is, up to a fixed permutation of the contraction
+// index, exactly its layer-2 input fragment.  Each row's p95 latency feeds
+// the Eq. 1 scan of the plain path, reduced across the wavefront.
+#include <hip/hip_runtime.h>
+
+#include "llama_internal.h"
+
+namespace llama {
+namespace {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr float GELU_C = 0.7978845608028654f;
+constexpr float GELU_A = 0.044715f;
+constexpr float TAU = 0.95f;
+constexpr int HID = 256, IN = 32, EMB = 16;
+
+__device__ __forceinline__ float gelu(float x) {
+  const float u = GELU_C * (x + GELU_A * x * x * x);
+  return x / (1.0f + __expf(-2.0f * u));
+}
+
+__device__ __forceinline__ float gelu_grad(float x) {
+  const float u = GELU_C * (x + GELU_A * x * x * x);
+  const float t = 2.0f / (1.0f + __expf(-2.0f * u)) - 1.0f;  // tanh(u)
+  return 0.5f * (1.0f + t) + 0.5f * x * (1.0f - t * t) * GELU_C * (1.0f + 3.0f * GELU_A * x * x);
+}
+
+__device__ __forceinline__ floatx4 mfma16x16x32(const bf16x8& a, const bf16x8& b, const floatx4& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// C[m][n] (+)= sum_k A(m,k) B(k,n) (+ bias[n]), BF16 inputs with arbitrary
+// element strides, FP32 output.  64x64 tile per 256-lane workgroup, each
+// wavefront a 32x32 quarter (2x2 MFMA blocks), K in steps of 32 through LDS.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, const bf16* __restrict__ a,
+                                                        int64_t sam, int64_t sak, const bf16* __restrict__ b,
+                                                        int64_t sbk, int64_t sbn, float* __restrict__ c,
+                                                        int64_t ldc, const float* __restrict__ bias,
+                                                        int accumulate) {
+  __shared__ __attribute__((aligned(16))) bf16 sA[64][40];  // [m][k], 8 pad columns
+  __shared__ __attribute__((aligned(16))) bf16 sB[64][40];  // [n][k]
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int g = lane >> 4, r = lane & 15;
+  floatx4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const bf16 zero = (bf16)0.0f;
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    for (int e = tid; e < 64 * 32; e += 256) {
+      const int mm = e >> 5, kk = e & 31;
+      const int gm = m0 + mm, gk = k0 + kk;
+      sA[mm][kk] = (gm < M && gk < K) ? a[gm * sam + gk * sak] : zero;
+      const int gn = n0 + mm;
+      sB[mm][kk] = (gn < N && gk < K) ? b[gk * sbk + gn * sbn] : zero;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+      const bf16x8 af = *reinterpret_cast<const bf16x8*>(&sA[wm + mb * 16 + r][8 * g]);
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        const bf16x8 bfr = *reinterpret_cast<const bf16x8*>(&sB[wn + nb * 16 + r][8 * g]);
+        acc[mb][nb] = mfma16x16x32(af, bfr, acc[mb][nb]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = m0 + wm + mb * 16 + 4 * g + i;
+        const int col = n0 + wn + nb * 16 + r;
+        if (row < M && col < N) {
+          float x = acc[mb][nb][i] + (bias ? bias[col] : 0.0f);
+          if (accumulate) x += c[row * ldc + col];
+          c[row * ldc + col] = x;
+        }
+      }
+}
+
+// X[m] = [E16[rows[m]], feat[m]]
+__global__ __launch_bounds__(256) void gather_x_kernel(int64_t B, const int32_t* rows, const bf16* feat,
+                                                       const bf16* E16, bf16* X) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= B * IN) return;
+  const int64_t m = e / IN;
+  const int j = (int)(e % IN);
+  X[e] = j < EMB ? E16[(int64_t)rows[m] * EMB + j] : feat[m * EMB + (j - EMB)];
+}
+
+__global__ __launch_bounds__(256) void gelu_round_kernel(int64_t n, const float* z, bf16* h) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) h[i] = (bf16)gelu(z[i]);
+}
+
+// Per row: d loss / d mu = 2 (mu - y) / B; d loss / d q = ([y < q] - tau) / B
+// (pinball loss on u = y - q); rounded to BF16.  Adds the batch's loss sum.
+__global__ __launch_bounds__(256) void loss_grad_kernel(int64_t B, const float* out, const float* y,
+                                                        bf16* dout, float* loss_sum) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= B) return;
+  const float mu = out[2 * m], q = out[2 * m + 1], t = y[m];
+  const float inv = 1.0f / (float)B;
+  const bool below = t < q;
+  dout[2 * m] = (bf16)(2.0f * (mu - t) * inv);
+  dout[2 * m + 1] = (bf16)(((below ? 1.0f : 0.0f) - TAU) * inv);
+  if (loss_sum) {
+    const float u = t - q;
+    atomicAdd(loss_sum, (mu - t) * (mu - t) + u * (TAU - (below ? 1.0f : 0.0f)));
+  }
+}
+
+__global__ __launch_bounds__(256) void gelu_bwd_round_kernel(int64_t n, const float* dh, const float* z,
+                                                             bf16* dz) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dz[i] = (bf16)(dh[i] * gelu_grad(z[i]));
+}
+
+// out[n] = sum over m of x[m][n]
+__global__ __launch_bounds__(256) void colsum_kernel(int64_t M, int N, const bf16* x, float* out) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.0f;
+  for (int64_t m = 0; m < M; ++m) s += (float)x[m * N + n];
+  out[n] = s;
+}
+
+__global__ __launch_bounds__(256) void scatter_embed_kernel(int64_t B, const int32_t* rows, const float* dX,
+                                                            float* dE) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= B * EMB) return;
+  const int64_t m = e / EMB;
+  const int j = (int)(e % EMB);
+  atomicAdd(&dE[(int64_t)rows[m] * EMB + j], dX[m * IN + j]);
+}
+
+__global__ __launch_bounds__(256) void fill_f32_kernel(int64_t n, float* p, float v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// AdamW on the flat master vector; decoupled decay only on [0, decay_end0)
+// (E and W1) and the W2, W3 ranges.
+__global__ __launch_bounds__(256) void adamw_kernel(int64_t n, float* p, const float* g, float* m, float* v,
+                                                    float lr, float wd, float c1, float c2, float beta1,
+                                                    float beta2, float eps, int64_t d0, int64_t d1a,
+                                                    int64_t d1b, int64_t d2a, int64_t d2b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float w = p[i];
+  const bool decay = i < d0 || (i >= d1a && i < d1b) || (i >= d2a && i < d2b);
+  if (decay) w *= 1.0f - lr * wd;
+  const float gi = g[i];
+  const float mi = beta1 * m[i] + (1.0f - beta1) * gi;
+  const float vi = beta2 * v[i] + (1.0f - beta2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] = w - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// BF16 shadows of E, W1, W2, W3 and the K-permuted W2 used by the fused
+// inference kernel: W2p[o][32 kb + 8 g + j] = W2[o][32 kb + (j < 4 ? 4g + j : 12 + 4g + j)].
+__global__ __launch_bounds__(256) void shadows_kernel(const float* master, int64_t nE, bf16* E16, bf16* W1_16,
+                                                      bf16* W2_16, bf16* W2p16, bf16* W3_16) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t oW1 = nE, oW2 = oW1 + HID * IN + HID, oW3 = oW2 + HID * HID + HID;
+  if (i < nE) E16[i] = (bf16)master[i];
+  if (i < HID * IN) W1_16[i] = (bf16)master[oW1 + i];
+  if (i < HID * HID) {
+    W2_16[i] = (bf16)master[oW2 + i];
+    const int o = (int)(i / HID), col = (int)(i % HID);
+    const int kb = col >> 5, g = (col >> 3) & 3, j = col & 7;
+    const int src = 32 * kb + (j < 4 ? 4 * g + j : 12 + 4 * g + j);
+    W2p16[i] = (bf16)master[oW2 + (int64_t)o * HID + src];
+  }
+  if (i < 2 * HID) W3_16[i] = (bf16)master[oW3 + i];
+}
+
+// ---------------------------------------------------------------------------
+// Fused inference + Eq. 1 scan (see file comment).
+// ---------------------------------------------------------------------------
+constexpr int LEARNED_WAVES = 4;  // wavefronts per workgroup (one per SIMD: 512 registers each)
+constexpr size_t LEARNED_LDS = sizeof(bf16) * (HID * HID + HID * IN) + sizeof(float) * (HID * 2 + 2 * HID);
+
+__device__ __forceinline__ int64_t remaining(int64_t r0, int64_t queue) {
+  int64_t r = r0 - queue;
+  r = r < 0 ? 0 : r;
+  return r > 0x7FFFFFFFll ? 0x7FFFFFFFll : r;
+}
+
+__device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b) {
+  int64_t q = (int64_t)((double)a / (double)b);
+  const int64_t rem = a - q * b;
+  if (rem < 0) q -= 1; else if (rem >= b) q += 1;
+  return q;
+}
+
+template <int NHW>
+__global__ __launch_bounds__(256) void decide_learned_kernel(DevTables t, Batch b, LearnedArgs s) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  bf16* sW2 = reinterpret_cast<bf16*>(lds);               // [256][256] K-permuted
+  bf16* sW1 = sW2 + HID * HID;                             // [256][32]
+  float* sB1 = reinterpret_cast<float*>(sW1 + HID * IN);   // [256]
+  float* sB2 = sB1 + HID;                                  // [256]
+  float* sW3 = sB2 + HID;                                  // [2][256], BF16 values
+  const int tid = threadIdx.x;
+  const bf16* W3_16 = reinterpret_cast<const bf16*>(s.W3_16);
+  const bf16* E16 = reinterpret_cast<const bf16*>(s.E16);
+  const bf16* feat = reinterpret_cast<const bf16*>(s.feat);
+  {
+    const uint4* src = reinterpret_cast<const uint4*>(s.W2p16);  // 16 bytes = 8 BF16
+    uint4* dst = reinterpret_cast<uint4*>(sW2);
+    for (int i = tid; i < HID * HID / 8; i += blockDim.x) dst[i] = src[i];
+    const uint4* src1 = reinterpret_cast<const uint4*>(s.W1_16);
+    uint4* dst1 = reinterpret_cast<uint4*>(sW1);
+    for (int i = tid; i < HID * IN / 8; i += blockDim.x) dst1[i] = src1[i];
+    for (int i = tid; i < HID; i += blockDim.x) {
+      sB1[i] = s.b1[i];
+      sB2[i] = s.b2[i];
+      sW3[i] = (float)W3_16[i];
+      sW3[HID + i] = (float)W3_16[HID + i];
+    }
+  }
+  __syncthreads();
+  const float b3_0 = s.b3[0], b3_1 = s.b3[1];
+  const int lane = tid & 63, g = lane >> 4, r = lane & 15;
+  const int64_t wave0 = (int64_t)blockIdx.x * LEARNED_WAVES + (tid >> 6);
+  const int64_t n_waves = (int64_t)gridDim.x * LEARNED_WAVES;
+  for (int64_t i = wave0; i < b.n; i += n_waves) {
+    const int v = b.op[i], e = b.elapsed[i], sl = b.slo[i];
+    if ((unsigned)v >= (unsigned)t.n_ops || (e | sl) < 0) {
+      if (lane == 0) {
+        b.cfg[i] = -1;
+        if (b.flag) b.flag[i] = 0;
+        atomicOr(t.err, 1u);
+      }
+      continue;
+    }
+    const int64_t r0 = (int64_t)sl - e;
+    const int64_t ref = t.ref[v];
+    const int64_t W = t.W[(int64_t)b.mode * t.n_ops + v];
+    int32_t tgt[NHW];
+#pragma unroll
+    for (int h = 0; h < NHW; ++h) {
+      const int64_t R = remaining(r0, b.queue ? b.queue[h] : 0);
+      tgt[h] = R == 0 ? 0 : (int32_t)floor_div(ref * R, W);
+    }
+    const int a0 = t.cfg_off[v], n_c = t.cfg_off[v + 1] - a0;
+    // feature half of the layer-1 input fragment (lane groups 2 and 3)
+    bf16x8 ffrag;
+    if (g >= 2) ffrag = *reinterpret_cast<const bf16x8*>(feat + i * EMB + 8 * (g - 2));
+    uint32_t best = KEY_NONE;
+    uint64_t fast = ~0ull;
+    for (int c0 = 0; c0 < n_c; c0 += 64) {
+      // ---- layer 1: z1^T[unit][row] = W1 . x^T, 16 unit blocks x 4 row blocks
+      bf16x8 xfrag[4];
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        const int k = c0 + nb * 16 + r;
+        const int row = a0 + (k < n_c ? k : 0);
+        xfrag[nb] = g < 2 ? *reinterpret_cast<const bf16x8*>(E16 + (int64_t)row * EMB + 8 * g) : ffrag;
+      }
+      // hf[kb][nb] is the layer-2 input fragment of row 16nb + r for K block
+      // kb: units 32kb + 4g + q (slots 0..3) and 32kb + 16 + 4g + q (slots
+      // 4..7), exactly the layer-1 outputs of unit blocks 2kb and 2kb + 1.
+      bf16x8 hf[8][4];
+#pragma unroll
+      for (int mb = 0; mb < 16; ++mb) {
+        const bf16x8 w1 = *reinterpret_cast<const bf16x8*>(sW1 + (16 * mb + r) * IN + 8 * g);
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+          const floatx4 z = mfma16x16x32(w1, xfrag[nb], floatx4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            hf[mb >> 1][nb][4 * (mb & 1) + q] = (bf16)gelu(z[q] + sB1[16 * mb + 4 * g + q]);
+        }
+      }
+      // ---- layers 2 and 3
+      float p0[4] = {0.f, 0.f, 0.f, 0.f}, p1[4] = {0.f, 0.f, 0.f, 0.f};
+      for (int mb2 = 0; mb2 < 16; ++mb2) {
+        floatx4 acc[4];
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) acc[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) {
+          const bf16x8 w2 = *reinterpret_cast<const bf16x8*>(sW2 + (16 * mb2 + r) * HID + 32 * kb + 8 * g);
+#pragma unroll
+          for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma16x16x32(w2, hf[kb][nb], acc[nb]);
+        }
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int u = 16 * mb2 + 4 * g + q;
+            const float h2 = (float)(bf16)gelu(acc[nb][q] + sB2[u]);
+            p0[nb] += sW3[u] * h2;
+            p1[nb] += sW3[HID + u] * h2;
+          }
+      }
+      // sum the four lane groups' partial dot products (same row r)
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        p0[nb] += __shfl_xor(p0[nb], 16, 64);
+        p1[nb] += __shfl_xor(p1[nb], 16, 64);
+        p0[nb] += __shfl_xor(p0[nb], 32, 64);
+        p1[nb] += __shfl_xor(p1[nb], 32, 64);
+      }
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        const int k = c0 + nb * 16 + r;
+        if (k >= n_c) continue;
+        const int x = a0 + k;
+        const float mu = p0[nb] + b3_0, q95 = p1[nb] + b3_1;
+        const float spread = q95 - mu;
+        int32_t L;
+        // predicted p95 when the spread is finite and in [0, spread_max], else the profile
+        if (spread >= 0.0f && spread <= s.spread_max && mu == mu && q95 == q95) {
+          const float ex = ceilf(expf(q95));
+          L = ex >= 2147483647.0f ? 0x7FFFFFFF : (int32_t)ex;
+        } else {
+          L = t.cfg_lat[x];
+        }
+        if (s.lat_out && g == 0) s.lat_out[i * s.lat_stride + k] = L;
+        const int h = t.cfg_hw[x];
+        int32_t tg = tgt[0];
+#pragma unroll
+        for (int hh = 1; hh < NHW; ++hh) tg = h == hh ? tgt[hh] : tg;
+        const uint32_t key = t.cfg_key[x];
+        if (L < tg) best = key < best ? key : best;
+        const uint64_t fk = ((uint64_t)(uint32_t)L << 16) | (uint64_t)k;
+        fast = fk < fast ? fk : fast;
+      }
+    }
+    // minimum over the wavefront (every lane group holds the same rows)
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t ob = __shfl_xor(best, d, 64);
+      best = ob < best ? ob : best;
+      const uint64_t of = __shfl_xor(fast, d, 64);
+      fast = of < fast ? of : fast;
+    }
+    if (lane == 0) {
+      const bool feasible = best != KEY_NONE;
+      b.cfg[i] = feasible ? (int32_t)(best & 0xFFFFu) : (int32_t)(fast & 0xFFFFu);
+      if (b.flag) b.flag[i] = feasible ? 1 : 0;
+    }
+  }
+}
+
+inline unsigned grid1(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_gemm_bf16(int M, int N, int K, const void* a, int64_t sam, int64_t sak, const void* bm,
+                            int64_t sbk, int64_t sbn, float* c, int64_t ldc, const float* bias, bool accumulate,
+                            hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  dim3 grid(grid1(N, 64), grid1(M, 64));
+  hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, s, M, N, K, (const bf16*)a, sam, sak,
+                     (const bf16*)bm, sbk, sbn, c, ldc, bias, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_surrogate_forward(const SurrogateBufs& w, int64_t B, const int32_t* rows, const void* feat,
+                                    hipStream_t s) {
+  hipLaunchKernelGGL(gather_x_kernel, dim3(grid1(B * IN, 256)), dim3(256), 0, s, B, rows, (const bf16*)feat,
+                     (const bf16*)w.E16, (bf16*)w.X16);
+  hipError_t e;
+  if ((e = launch_gemm_bf16((int)B, HID, IN, w.X16, IN, 1, w.W1_16, 1, IN, w.z1, HID, w.b1, false, s))) return e;
+  hipLaunchKernelGGL(gelu_round_kernel, dim3(grid1(B * HID, 256)), dim3(256), 0, s, B * HID, w.z1, (bf16*)w.h1);
+  if ((e = launch_gemm_bf16((int)B, HID, HID, w.h1, HID, 1, w.W2_16, 1, HID, w.z2, HID, w.b2, false, s))) return e;
+  hipLaunchKernelGGL(gelu_round_kernel, dim3(grid1(B * HID, 256)), dim3(256), 0, s, B * HID, w.z2, (bf16*)w.h2);
+  return launch_gemm_bf16((int)B, 2, HID, w.h2, HID, 1, w.W3_16, 1, HID, w.out, 2, w.b3, false, s);
+}
+
+hipError_t launch_surrogate_backward(const SurrogateBufs& w, int64_t B, const int32_t* rows, const float* y,
+                                     float* loss_sum, hipStream_t s) {
+  hipError_t e;
+  float* g = w.grad;
+  hipLaunchKernelGGL(loss_grad_kernel, dim3(grid1(B, 256)), dim3(256), 0, s, B, w.out, y, (bf16*)w.dout,
+                     loss_sum);
+  // layer 3: dW3 = dout^T h2, db3 = colsum(dout), dh2 = dout W3
+  if ((e = launch_gemm_bf16(2, HID, (int)B, w.dout, 1, 2, w.h2, HID, 1, g + w.oW3, HID, nullptr, false, s))) return e;
+  hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(256), 0, s, B, 2, (const bf16*)w.dout, g + w.ob3);
+  if ((e = launch_gemm_bf16((int)B, HID, 2, w.dout, 2, 1, w.W3_16, HID, 1, w.dh2, HID, nullptr, false, s))) return e;
+  hipLaunchKernelGGL(gelu_bwd_round_kernel, dim3(grid1(B * HID, 256)), dim3(256), 0, s, B * HID, w.dh2, w.z2,
+                     (bf16*)w.dz2);
+  // layer 2
+  if ((e = launch_gemm_bf16(HID, HID, (int)B, w.dz2, 1, HID, w.h1, HID, 1, g + w.oW2, HID, nullptr, false, s))) return e;
+  hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(256), 0, s, B, HID, (const bf16*)w.dz2, g + w.ob2);
+  if ((e = launch_gemm_bf16((int)B, HID, HID, w.dz2, HID, 1, w.W2_16, HID, 1, w.dh1, HID, nullptr, false, s))) return e;
+  hipLaunchKernelGGL(gelu_bwd_round_kernel, dim3(grid1(B * HID, 256)), dim3(256), 0, s, B * HID, w.dh1, w.z1,
+                     (bf16*)w.dz1);
+  // layer 1 and the embedding
+  if ((e = launch_gemm_bf16(HID, IN, (int)B, w.dz1, 1, HID, w.X16, IN, 1, g + w.oW1, IN, nullptr, false, s))) return e;
+  hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(256), 0, s, B, HID, (const bf16*)w.dz1, g + w.ob1);
+  if ((e = launch_gemm_bf16((int)B, IN, HID, w.dz1, HID, 1, w.W1_16, IN, 1, w.dX, IN, nullptr, false, s))) return e;
+  hipLaunchKernelGGL(fill_f32_kernel, dim3(grid1(w.nE, 256)), dim3(256), 0, s, w.nE, g, 0.0f);
+  hipLaunchKernelGGL(scatter_embed_kernel, dim3(grid1(B * EMB, 256)), dim3(256), 0, s, B, rows, w.dX, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_adamw(const SurrogateBufs& w, float lr, float wd, int64_t step, hipStream_t s) {
+  const float beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f;
+  const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
+  hipLaunchKernelGGL(adamw_kernel, dim3(grid1(w.n_params, 256)), dim3(256), 0, s, w.n_params, w.master, w.grad,
+                     w.adam_m, w.adam_v, lr, wd, c1, c2, beta1, beta2, eps, w.ob1, w.oW2, w.ob2, w.oW3, w.ob3);
+  return hipGetLastError();
+}
+
+hipError_t launch_shadows(const SurrogateBufs& w, hipStream_t s) {
+  const int64_t n = w.nE > HID * HID ? w.nE : HID * HID;
+  hipLaunchKernelGGL(shadows_kernel, dim3(grid1(n, 256)), dim3(256), 0, s, w.master, w.nE, (bf16*)w.E16,
+                     (bf16*)w.W1_16, (bf16*)w.W2_16, (bf16*)w.W2p16, (bf16*)w.W3_16);
+  return hipGetLastError();
+}
+
+hipError_t launch_decide_learned(const DevTables& t, const Batch& b, const LearnedArgs& a, hipStream_t s) {
+  if (b.n == 0) return hipSuccess;
+  const int blocks = 256;  // persistent: one workgroup per CU (LDS-bound), grid-stride over invocations
+  const unsigned grid = (unsigned)(b.n < (int64_t)blocks * LEARNED_WAVES ? (b.n + LEARNED_WAVES - 1) / LEARNED_WAVES
+                                                                          : blocks);
+#define LLAMA_LEARNED_CASE(N)                                                                          \
+  case N:                                                                                              \
+    {                                                                                                  \
+      hipError_t e = hipFuncSetAttribute((const void*)decide_learned_kernel<N>,                        \
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)LEARNED_LDS); \
+      if (e != hipSuccess) return e;                                                                   \
+    }                                                                                                  \
+    hipLaunchKernelGGL(decide_learned_kernel<N>, dim3(grid), dim3(64 * LEARNED_WAVES), LEARNED_LDS, s, t, b, a); \
+    break;
+  switch (t.n_hw) {
+    LLAMA_LEARNED_CASE(1)
+    LLAMA_LEARNED_CASE(2)
+    LLAMA_LEARNED_CASE(3)
+    LLAMA_LEARNED_CASE(4)
+    LLAMA_LEARNED_CASE(5)
+    LLAMA_LEARNED_CASE(6)
+    LLAMA_LEARNED_CASE(7)
+    LLAMA_LEARNED_CASE(8)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef LLAMA_LEARNED_CASE
+  return hipGetLastError();
+}
+
+}  // namespace llama

@@ -361,3 +361,138 @@ def random_small(rng, n_ops=None, n_hw=None, n_inv=64, edge_p=0.35, name="fuzz",
                     succ_off=succ_off, succ_ids=succ_ids, succ_q16=succ_q16,
                     cfg_off=cfg_off, hw=hw, batch=batch, res=res, lat=lat, cost=cost,
                     inv_op=inv_op, elapsed=elapsed, slo=slo)
+
+
+# ---------------------------------------------------------------------------
+# Configuration 4: learned surrogate (content features, simulator samples)
+# ---------------------------------------------------------------------------
+
+N_FEAT = 16
+RESOLUTIONS = ((854, 480), (1280, 720), (1920, 1080))
+PX_720P = 1280 * 720
+
+
+@dataclass
+class Content:
+    """Per-invocation content: integer object counts and resolution (the
+    truth model's inputs) and the 16 features the surrogate sees (BF16-exact
+    float32 values)."""
+    n_obj: np.ndarray      # int32 [n]
+    px: np.ndarray         # int64 [n] pixels per frame
+    feat: np.ndarray       # float32 [n, 16], already rounded to bfloat16
+
+
+@dataclass
+class SurrogateWorld:
+    """C1's DAG with 64 configurations per op and the simulator's hidden truth
+    coefficients: mean ln latency of row x for content f is
+    ln L[x] + a[op, hw(x)] ln(1 + n_obj(f)) + b[op] ln(px(f) / px_720p),
+    observed with lognormal(0, sigma) noise."""
+    w: Workload
+    a: np.ndarray          # float64 [n_ops, n_hw]
+    b: np.ndarray          # float64 [n_ops]
+    sigma: float
+
+
+def _to_bf16_exact(x):
+    x32 = np.ascontiguousarray(np.asarray(x, np.float32))
+    u = x32.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return r.view(np.float32)
+
+
+def draw_content(rng, n):
+    """Object counts: people and cars Poisson with rate lognormal(ln 2, 1),
+    at most 60 objects in all; faces Binomial(people, 0.6); resolution 480p,
+    720p or 1080p (the paper's videos are 720p and 1080p, Tab. 2); motion,
+    blur, brightness U[0,1]; conditional-branch hit rate Beta(3, 7); frame
+    phase U[0, 2 pi)."""
+    people = rng.poisson(rng.lognormal(np.log(2.0), 1.0, n))
+    cars = rng.poisson(rng.lognormal(np.log(2.0), 1.0, n))
+    people = np.minimum(people, 60)
+    cars = np.minimum(cars, 60 - people)
+    faces = rng.binomial(people, 0.6)
+    n_obj = people + cars
+    res = rng.integers(0, 3, n)
+    wh = np.asarray(RESOLUTIONS, np.int64)[res]
+    px = wh[:, 0] * wh[:, 1]
+    phase = rng.uniform(0, 2 * np.pi, n)
+    f = np.zeros((n, N_FEAT), np.float64)
+    f[:, 0] = people / 60.0
+    f[:, 1] = cars / 60.0
+    f[:, 2] = faces / 60.0
+    f[:, 3] = np.log1p(n_obj) / np.log(61.0)
+    f[:, 4] = wh[:, 0] / 1920.0
+    f[:, 5] = wh[:, 1] / 1080.0
+    f[:, 6] = px / (1920.0 * 1080.0)
+    f[:, 7] = rng.uniform(0, 1, n)
+    f[:, 8] = rng.uniform(0, 1, n)
+    f[:, 9] = rng.uniform(0, 1, n)
+    f[:, 10] = rng.beta(3, 7, n)
+    f[:, 11] = np.sin(phase)
+    f[:, 12] = np.cos(phase)
+    return Content(n_obj.astype(np.int32), px.astype(np.int64), _to_bf16_exact(f))
+
+
+def make_c4_world(seed=3, sigma=0.3):
+    """C1's 6-op DAG; 64 configurations per op: 2 hardware types x batch
+    {1,2,4,8} x 8 resource sizes {1,...,128}, k = 32 hw + 8 log2 B + log2 m;
+    L = clip(floor(L1 B^gamma m^-beta), 1e3, 1e5) per (op, hw) draws as in C2;
+    cost = price_hw * m * L (resource-seconds priced per backend, Sec. 6);
+    truth coefficients a_CPU ~ U[0.3, 0.7], a_GPU ~ U[0.05, 0.35] (spanning
+    Fig. 3's 17.2x and 4x at 60 objects), b ~ U[0.5, 1]."""
+    base = make_c1(seed=seed, n_inv=1)
+    rng = np.random.default_rng(seed + 1000)
+    n_ops, n_hw = base.n_ops, 2
+    B = np.array([1, 2, 4, 8])
+    M = 2 ** np.arange(8)
+    hw, batch, res, lat = [], [], [], []
+    for v in range(n_ops):
+        for h in range(n_hw):
+            L1 = int(rng.integers(1000, 100001))
+            g = rng.uniform(0.3, 0.9)
+            be = rng.uniform(0.0, 0.5)
+            for b in B:
+                for m in M:
+                    hw.append(h); batch.append(b); res.append(m)
+                    lat.append(np.clip(np.floor(L1 * float(b) ** g * float(m) ** (-be)), 1000, 100000))
+    hw = np.asarray(hw, np.int32)
+    res = np.asarray(res, np.int32)
+    lat = np.asarray(lat, np.int32)
+    price = np.array([1, 3], np.int64)
+    cost = price[hw] * res.astype(np.int64) * lat.astype(np.int64)
+    n_cfg = len(hw)
+    w = Workload(name="c4-surrogate", n_hw=n_hw, pipe_off=base.pipe_off, succ_off=base.succ_off,
+                 succ_ids=base.succ_ids, succ_q16=base.succ_q16,
+                 cfg_off=(np.arange(n_ops + 1) * 64).astype(np.int32), hw=hw,
+                 batch=np.asarray(batch, np.int32), res=res, lat=lat, cost=cost,
+                 inv_op=np.zeros(0, np.int32), elapsed=np.zeros(0, np.int32),
+                 slo=np.zeros(0, np.int32), meta={"seed": seed})
+    a = np.stack([rng.uniform(0.3, 0.7, n_ops), rng.uniform(0.05, 0.35, n_ops)], axis=1)
+    b = rng.uniform(0.5, 1.0, n_ops)
+    assert n_cfg == n_ops * 64
+    return SurrogateWorld(w, a, b, sigma)
+
+
+def simulate_c4(world, rng, n):
+    """n simulator executions: a uniformly drawn profile row, fresh content,
+    and the observed ln latency (truth mean plus N(0, sigma^2) noise).
+    Returns (rows int32 [n], Content, y float32 [n])."""
+    w = world.w
+    rows = rng.integers(0, w.n_cfg, n).astype(np.int32)
+    c = draw_content(rng, n)
+    op = rows // 64
+    mu = (np.log(w.lat[rows].astype(np.float64)) + world.a[op, w.hw[rows]] * np.log1p(c.n_obj)
+          + world.b[op] * np.log(c.px / PX_720P))
+    y = (mu + world.sigma * rng.standard_normal(n)).astype(np.float32)
+    return rows, c, y
+
+
+def c4_invocations(world, rng, n, slo=500_000):
+    """n pending invocations of the C4 pipeline (as C1: SLO 500 ms, elapsed
+    U[0, SLO]) with their content."""
+    w = world.w
+    inv_op = rng.integers(0, w.n_ops, n).astype(np.int32)
+    elapsed = rng.integers(0, slo + 1, n).astype(np.int32)
+    c = draw_content(rng, n)
+    return w.with_invocations(inv_op, elapsed, np.full(n, slo, np.int32), name="c4-inference"), c

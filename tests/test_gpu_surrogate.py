@@ -1,0 +1,238 @@
+"""GPU parity and quality of the learned latency surrogate.
+
+Tolerances (floating point):
+  * forward outputs (mu, q in ln us): the GPU accumulates BF16 products in FP32
+    and rounds the same activations to BF16 as the oracle (FP64), so the two
+    differ only by accumulation order plus rare one-ulp BF16 rounding flips
+    (2^-8 relative on one of 256 hidden units); |delta| <= 1e-2 absolute;
+  * gradients: relative Frobenius error <= 2e-2 per tensor (the backward adds
+    BF16 rounding points on gradients, where flips are likewise rare);
+  * AdamW: FP32 against FP64 on the same gradients, 1e-5 relative;
+  * fused inference: ln of the predicted latency within 1e-2 of the oracle's on
+    rows both accept, the accept/fallback decision equal on >= 99% of rows, and
+    the configuration choice given the GPU's own integer latencies bit-exact.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp
+from paper_2102_01887_amd import binding as B
+from paper_2102_01887_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+SPREAD_MAX = math.log(4.0)
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def setup_world(seed=3):
+    torch = _torch()
+    world = wl.make_c4_world(seed)
+    L = B.Llama(0).load(world.w)
+    return torch, world, L
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def feat_dev(torch, f):
+    return torch.from_numpy(np.ascontiguousarray(f, np.float32)).to(torch.bfloat16).cuda()
+
+
+def test_forward_matches_oracle():
+    torch, world, L = setup_world()
+    L.surrogate_init(seed=11, mean_log_latency=10.0)
+    P = mlp.unflatten(L.surrogate_get().astype(np.float64), world.w.n_cfg)
+    rng = np.random.default_rng(0)
+    n = 3001
+    rows, c, y = wl.simulate_c4(world, rng, n)
+    out = L.surrogate_forward(dev(torch, rows), feat_dev(torch, c.feat))
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    want = mlp.forward(P, rows, c.feat.astype(np.float64))["out"]
+    err = np.abs(got - want)
+    say(f"forward: max |delta| {err.max():.2e}, mean {err.mean():.2e}")
+    assert err.max() <= 1e-2 and err.mean() <= 1e-4
+
+
+def test_gradients_match_oracle():
+    torch, world, L = setup_world()
+    L.surrogate_init(seed=12, mean_log_latency=10.5)
+    P = mlp.unflatten(L.surrogate_get().astype(np.float64), world.w.n_cfg)
+    rng = np.random.default_rng(1)
+    n = 2048
+    rows, c, y = wl.simulate_c4(world, rng, n)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    L.surrogate_train_step(dev(torch, rows), feat_dev(torch, c.feat), dev(torch, y), lr=0.0,
+                           update=False, loss_sum=loss)
+    torch.cuda.synchronize()
+    g_gpu = mlp.unflatten(L.surrogate_grads().astype(np.float64), world.w.n_cfg)
+    l_or, g_or = mlp.loss_and_grads(P, rows, c.feat.astype(np.float64), y.astype(np.float64))
+    assert abs(loss.item() / n - l_or) <= 1e-3 * max(1.0, abs(l_or))
+    for k in mlp.NAMES:
+        rel = np.linalg.norm(g_gpu[k] - g_or[k]) / max(np.linalg.norm(g_or[k]), 1e-30)
+        say(f"grad {k}: relative error {rel:.2e}")
+        assert rel <= 2e-2, k
+
+
+def test_adamw_step_matches_oracle():
+    torch, world, L = setup_world()
+    L.surrogate_init(seed=13, mean_log_latency=10.0)
+    p0 = L.surrogate_get().astype(np.float64)
+    rng = np.random.default_rng(2)
+    rows, c, y = wl.simulate_c4(world, rng, 1024)
+    lr, wd = 1e-3, 1e-4
+    L.surrogate_train_step(dev(torch, rows), feat_dev(torch, c.feat), dev(torch, y), lr=lr,
+                           weight_decay=wd, update=True)
+    torch.cuda.synchronize()
+    g = mlp.unflatten(L.surrogate_grads().astype(np.float64), world.w.n_cfg)
+    p = mlp.unflatten(p0.copy(), world.w.n_cfg)
+    zeros = {k: np.zeros_like(v) for k, v in p.items()}
+    mlp.adamw_step(p, g, zeros, {k: np.zeros_like(v) for k, v in p.items()}, 1, lr, wd)
+    got = L.surrogate_get().astype(np.float64)
+    want = mlp.flatten(p)
+    assert np.allclose(got, want, rtol=1e-5, atol=1e-6)
+
+
+def inference_case(torch, world, L, n, seed):
+    rng = np.random.default_rng(seed)
+    w, c = wl.c4_invocations(world, rng, n)
+    P_or = oracle.Problem(w)
+    tgt = P_or.targets(0)
+    lat = torch.full((n, 64), -7, dtype=torch.int32, device="cuda")
+    cfg, flag = L.decide_learned(dev(torch, w.inv_op), dev(torch, w.elapsed), dev(torch, w.slo),
+                                 feat_dev(torch, c.feat), spread_max=SPREAD_MAX, lat_out=lat,
+                                 lat_stride=64)
+    torch.cuda.synchronize()
+    return w, c, tgt, cfg.cpu().numpy(), flag.cpu().numpy(), lat.cpu().numpy()
+
+
+def check_inference(world, L, w, c, tgt, cfg, flag, lat):
+    P = mlp.unflatten(L.surrogate_get().astype(np.float64), world.w.n_cfg)
+    n = w.n_inv
+    rows = (w.inv_op[:, None] * 64 + np.arange(64)[None, :]).ravel()
+    feats = np.repeat(c.feat.astype(np.float64), 64, axis=0)
+    out = mlp.forward(P, rows, feats)["out"]
+    L_or, ok_or = mlp.predicted_latency(out, world.w.lat[rows], SPREAD_MAX)
+    L_or, ok_or = L_or.reshape(n, 64), ok_or.reshape(n, 64)
+    prof = world.w.lat[rows].reshape(n, 64)
+    spread = (out[:, 1] - out[:, 0]).reshape(n, 64)
+    # rows whose spread lies within 1e-2 of an end of [0, spread_max] may be
+    # accepted on one side and not the other; every other row must agree
+    edge = (np.abs(spread) < 1e-2) | (np.abs(spread - SPREAD_MAX) < 1e-2)
+    assert (lat > 0).all()
+    keep = ~edge & ok_or
+    dl = np.abs(np.log(lat[keep].astype(np.float64)) - np.log(L_or[keep].astype(np.float64)))
+    say(f"inference: {keep.sum()} predicted rows, max |d ln L| {dl.max() if dl.size else 0:.2e}, "
+        f"{edge.sum()} rows at the spread limits")
+    assert dl.size == 0 or dl.max() <= 1e-2
+    assert np.array_equal(lat[~edge & ~ok_or], prof[~edge & ~ok_or])
+    # decision given the GPU's own latencies: bit-exact
+    c_or, f_or = oracle.select_lat(w.inv_op, tgt, w.n_hw, w.cfg_off, w.hw, w.batch, lat, w.cost)
+    assert np.array_equal(cfg, c_or) and np.array_equal(flag, f_or)
+
+
+def test_fused_inference_matches_oracle():
+    torch, world, L = setup_world()
+    L.surrogate_init(seed=14, mean_log_latency=10.0)
+    for n, seed in ((1, 5), (4097, 6)):
+        check_inference(world, L, *inference_case(torch, world, L, n, seed))
+
+
+def train(torch, L, world, n_samples, epochs=3, batch=4096, lr=5e-3, wd=1e-4, seed=7):
+    """The recipe: n_samples simulator executions, `epochs` passes in batches
+    of 4096, AdamW with cosine-decayed learning rate."""
+    rng = np.random.default_rng(seed)
+    per_epoch = n_samples // batch
+    rows, c, y = wl.simulate_c4(world, rng, per_epoch * batch)
+    d_rows, d_feat, d_y = dev(torch, rows), feat_dev(torch, c.feat), dev(torch, y)
+    del rows, c, y
+    L.surrogate_reserve(batch)
+    steps = epochs * per_epoch
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    for s in range(steps):
+        lr_s = lr * 0.5 * (1 + math.cos(math.pi * s / steps))
+        b = s % per_epoch
+        sl = slice(b * batch, (b + 1) * batch)
+        last = s >= steps - per_epoch // 10
+        L.surrogate_train_step(d_rows[sl], d_feat[sl], d_y[sl], lr=lr_s, weight_decay=wd,
+                               loss_sum=loss if last else None)
+        if s % 2000 == 0:
+            torch.cuda.synchronize()
+            say(f"train step {s}/{steps}")
+    torch.cuda.synchronize()
+    return loss.item() / ((steps - (steps - per_epoch // 10)) * batch)
+
+
+def evaluate(world, w, c, tgt, cfg_gpu):
+    """Regret and miss rate of the surrogate's and the plain profile's choices
+    against the truth decision (p95 of the simulator's latency model)."""
+    n = w.n_inv
+    rows = (w.inv_op[:, None] * 64 + np.arange(64)[None, :])
+    op = w.inv_op[:, None]
+    mu = mlp.truth_mean_log_latency(world.w.lat[rows], world.a[op, world.w.hw[rows]], world.b[op],
+                                    c.n_obj[:, None], c.px[:, None])
+    truth = mlp.truth_p95_latency(mu, world.sigma).astype(np.int32)
+    t_c, t_f = oracle.select_lat(w.inv_op, tgt, w.n_hw, w.cfg_off, w.hw, w.batch, truth, w.cost)
+    plain_c, _ = oracle.select(w.inv_op, tgt, w.n_hw, w.cfg_off, w.hw, w.batch, w.lat, w.cost)
+    base = (w.inv_op * 64).astype(np.int64)
+    r_s = mlp.regret(cfg_gpu, t_c, t_f, truth, tgt, w.hw, w.cost, w.batch, base)
+    r_p = mlp.regret(plain_c, t_c, t_f, truth, tgt, w.hw, w.cost, w.batch, base)
+    return r_s, r_p
+
+
+def test_trained_surrogate_beats_the_profile():
+    torch, world, L = setup_world()
+    L.surrogate_init(seed=15, mean_log_latency=10.5)
+    final_loss = train(torch, L, world, n_samples=10_000_000)
+    say(f"final training loss {final_loss:.4f}")
+    w, c, tgt, cfg, flag, lat = inference_case(torch, world, L, 20_000, seed=8)
+    check_inference(world, L, w, c, tgt, cfg, flag, lat)
+    r_s, r_p = evaluate(world, w, c, tgt, cfg)
+    say(f"surrogate: {r_s}\nplain:     {r_p}")
+    assert r_s["mean_regret"] <= 0.02
+    assert r_s["miss_rate"] < r_p["miss_rate"]
+
+
+def test_checkpoint_resume(tmp_path):
+    torch, world, L = setup_world()
+    rng = np.random.default_rng(9)
+    batches = [wl.simulate_c4(world, rng, 512) for _ in range(6)]
+    dbat = [(dev(torch, r), feat_dev(torch, c.feat), dev(torch, y)) for r, c, y in batches]
+
+    def run(ctx, bs):
+        for r, f, y in bs:
+            ctx.surrogate_train_step(r, f, y, lr=1e-3, weight_decay=1e-4)
+        torch.cuda.synchronize()
+
+    L.surrogate_init(seed=16, mean_log_latency=10.0)
+    run(L, dbat[:3])
+    path = tmp_path / "surr.bin"
+    L.surrogate_save(path)
+    saved = L.surrogate_get()
+    L2 = B.Llama(0).load(world.w)
+    L2.surrogate_load(path)
+    assert np.array_equal(L2.surrogate_get(), saved)
+    run(L2, dbat[3:])
+    L3 = B.Llama(0).load(world.w)
+    L3.surrogate_init(seed=16, mean_log_latency=10.0)
+    run(L3, dbat)
+    assert np.allclose(L2.surrogate_get(), L3.surrogate_get(), rtol=1e-4, atol=1e-5)
+    other = wl.make_c2(n_pipelines=2, n_inv=10)
+    L4 = B.Llama(0).load(other)
+    with pytest.raises(B.LlamaError):
+        L4.surrogate_load(path)

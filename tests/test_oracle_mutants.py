@@ -17,8 +17,8 @@ import test_oracle_pins as pins
 MUTANTS = {
     "non-strict feasibility": ("if (!(lat[x] < target[i * n_hw + h]))",
                                "if (!(lat[x] <= target[i * n_hw + h]))"),
-    "cost tie to highest index": ("if (lhs < rhs)", "if (lhs <= rhs)"),
-    "transposed batch operand": ("(__int128)cost[x] * (__int128)batch[best]",
+    "cost tie to highest index": ("return lhs < rhs;", "return lhs <= rhs;"),
+    "transposed batch operand": ("(__int128)cost[x] * (__int128)batch[y]",
                                  "(__int128)cost[x] * (__int128)batch[x]"),
     "max instead of sum along path": ("int64_t nv = ref_lat[v] + m;",
                                       "int64_t nv = ref_lat[v] > m ? ref_lat[v] : m;"),
