@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--mode", choices=["paper", "prob"], default="paper")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the learned-surrogate section (training + fused inference)")
+    ap.add_argument("--train-samples", type=int, default=10_000_000)
     ap.add_argument("--kernel-reps", type=int, default=50,
                     help="launches per graph when timing single kernels")
     return ap.parse_args()
@@ -63,6 +66,105 @@ def time_graph(torch, stream, g, replays):
         b.record(stream)
     b.synchronize()
     return a.elapsed_time(b) / replays
+
+
+# BF16 dense MFMA peak (MI355X) in TFLOP/s; FLOPs per surrogate row (forward)
+MFMA_BF16_PEAK_TFS = 2500.0
+ROW_FLOPS = 2 * (32 * 256 + 256 * 256 + 256 * 2)
+
+
+def regret_stats(choice, truth_choice, truth_flag, truth_lat, target, hw, cost, batch, base):
+    """Mean cost-per-item regret against the truth decision over invocations
+    whose truth decision is feasible and whose chosen configuration is truly
+    feasible, and the miss rate (chosen configuration truly infeasible while
+    a feasible one existed)."""
+    import numpy as np
+    idx = np.arange(len(choice))
+    xc, xt = base + choice, base + truth_choice
+    feas = truth_lat[idx, choice] < target[idx, hw[xc]]
+    has = truth_flag == 1
+    ok = has & feas
+    per_item = cost.astype(np.float64) / batch.astype(np.float64)
+    reg = per_item[xc[ok]] / per_item[xt[ok]] - 1.0
+    return {"mean_regret": float(reg.mean()) if reg.size else 0.0,
+            "miss_rate": float(np.mean(has & ~feas)), "scored": int(ok.sum())}
+
+
+def bench_surrogate(args, torch, B, wl, log):
+    """Train the surrogate with the full recipe on the GPU, time the fused
+    inference kernel on 1M invocations x 64 configurations, and score its
+    decisions against the simulator's truth (and the plain profile's)."""
+    import numpy as np
+    world = wl.make_c4_world(3)
+    L = B.Llama(0).load(world.w)
+    L.surrogate_init(seed=15, mean_log_latency=10.5)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    bf = lambda f: torch.from_numpy(np.ascontiguousarray(f, np.float32)).to(torch.bfloat16).cuda()
+    log(f"bench: simulating {args.train_samples} training executions")
+    rows, c, y = wl.simulate_c4(world, np.random.default_rng(7), args.train_samples)
+    d_rows, d_feat, d_y = dev(rows), bf(c.feat), dev(y)
+    del rows, c, y
+    s = torch.cuda.Stream()
+    epochs, batch = 3, 4096
+    steps = epochs * (args.train_samples // batch)
+    L.surrogate_reserve(batch)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    log(f"bench: training {steps} steps")
+    with torch.cuda.stream(s):
+        a.record(s)
+        L.surrogate_fit(d_rows, d_feat, d_y, epochs=epochs, batch=batch, lr_max=5e-3,
+                        weight_decay=1e-4, loss_sum=loss, stream=s)
+        b.record(s)
+    b.synchronize()
+    train_ms = a.elapsed_time(b)
+    final_loss = loss.item() / (((args.train_samples // batch + 9) // 10) * batch)
+    del d_rows, d_feat, d_y
+    n = 1_000_000
+    w4, c4 = wl.c4_invocations(world, np.random.default_rng(8), n)
+    op, el, slo, feat = dev(w4.inv_op), dev(w4.elapsed), dev(w4.slo), bf(c4.feat)
+    cfg = torch.empty(n, dtype=torch.int32, device="cuda")
+    flag = torch.empty(n, dtype=torch.uint8, device="cuda")
+    learned = lambda: L.decide_learned(op, el, slo, feat, cfg=cfg, flag=flag, stream=s)
+    plain = lambda: L.decide(op, el, slo, cfg=cfg, flag=flag, stream=s)
+    with torch.cuda.stream(s):
+        learned()
+        plain()
+    torch.cuda.synchronize()
+    g_l = graph_of(torch, s, learned, 2)
+    g_p = graph_of(torch, s, plain, 20)
+    ms_l = time_graph(torch, s, g_l, 3) / 2
+    ms_p = time_graph(torch, s, g_p, 3) / 20
+    tflops = n * 64 * ROW_FLOPS / (ms_l * 1e-3) / 1e12
+    # decisions on a sample, scored against the simulator's truth
+    m = 20_000
+    sl = slice(0, m)
+    tgt = L.targets(op[sl], el[sl], slo[sl])
+    truth = wl.c4_truth_p95(world, w4.inv_op[:m], wl.Content(c4.n_obj[:m], c4.px[:m], c4.feat[:m]))
+    t_c, t_f = L.select_rows(op[sl], tgt, dev(truth))
+    s_c, _ = L.decide_learned(op[sl], el[sl], slo[sl], feat[sl])
+    p_c, _ = L.decide(op[sl], el[sl], slo[sl])
+    torch.cuda.synchronize()
+    args_np = (t_c.cpu().numpy(), t_f.cpu().numpy(), truth, tgt.cpu().numpy(), world.w.hw,
+               world.w.cost, world.w.batch, (w4.inv_op[:m] * 64).astype(np.int64))
+    r_s = regret_stats(s_c.cpu().numpy(), *args_np)
+    r_p = regret_stats(p_c.cpu().numpy(), *args_np)
+    return {
+        "workload": "c4: C1's 6-op DAG, 64 configs/op; train 10M simulator samples x 3 epochs "
+                    "(batch 4096, AdamW, cosine lr 5e-3); infer 1M invocations x 64 configs",
+        "train_ms": train_ms, "train_steps": steps,
+        "train_samples_per_s": epochs * args.train_samples / (train_ms * 1e-3),
+        "final_loss": final_loss,
+        "inference_ms": ms_l, "decisions_per_s": n / (ms_l * 1e-3),
+        "plain_decisions_per_s_same_workload": n / (ms_p * 1e-3),
+        "throughput_vs_plain": ms_p / ms_l,
+        "roofline": {"bound": "mfma", "achieved": tflops, "peak": MFMA_BF16_PEAK_TFS,
+                     "unit": "TFLOP/s", "frac": tflops / MFMA_BF16_PEAK_TFS,
+                     "kernel": "decide_learned_kernel", "flops_per_row": ROW_FLOPS},
+        "regret_surrogate": r_s, "regret_plain_profile": r_p, "regret_sample": m,
+        "dtype": "bf16 (fp32 accumulate)",
+    }
 
 
 def main():
@@ -174,6 +276,10 @@ def main():
                          f"decide (Alg. 1 + Eq. 1 scan of every configuration), median of "
                          f"{len(times)} runs"}
 
+    surr = None
+    if not args.no_surrogate:
+        surr = bench_surrogate(args, torch, B, wl, log)
+
     out = {
         "metric": METRIC,
         "value": n / (ms_step * 1e-3),
@@ -209,6 +315,7 @@ def main():
         "wave_scan": {"kernel": "decide_wave_kernel", "ms": ms_wave,
                       "decisions_per_s": n / (ms_wave * 1e-3)},
         "frontier_entries": st["frontier_entries"],
+        "surrogate": surr,
     }
     print(json.dumps(out), flush=True)
 

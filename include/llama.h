@@ -225,6 +225,20 @@ int llama_decide(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
                  int32_t scan_mode, int32_t *d_cfg, uint8_t *d_flag,
                  void *stream);
 
+/*
+ * Eq. 1 given targets and a latency per (invocation, configuration) instead
+ * of the profile's (for example measured or predicted latencies):
+ *   d_target_us [n_inv * n_hw] as in llama_select;
+ *   d_lat_us    [n_inv * lat_stride], configuration k of invocation i's op at
+ *               [i * lat_stride + k] (caller order); an op with more than
+ *               lat_stride configurations makes the invocation invalid (-1);
+ * feasible iff lat < target[hw]; cheapest C/B (profile costs) among the
+ * feasible, else the smallest latency; lowest index on ties.
+ */
+int llama_select_rows(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
+                      const int32_t *d_target_us, const int32_t *d_lat_us,
+                      int64_t lat_stride, int32_t *d_cfg, uint8_t *d_flag, void *stream);
+
 /* Pre-size the scratch that LLAMA_SCAN_FULL needs for batches of up to
  * max_inv invocations (device memory, 4 bytes per invocation).  Synchronous. */
 int llama_reserve(llama_ctx *ctx, int64_t max_inv);
@@ -313,6 +327,16 @@ int llama_surrogate_train_step(llama_ctx *ctx, int64_t batch, const int32_t *d_r
                                const uint16_t *d_feat, const float *d_y, float lr,
                                float weight_decay, int32_t update, float *d_loss_sum,
                                void *stream);
+
+/* The training recipe, enqueued natively on `stream`: `epochs` passes over n
+ * samples (device pointers as in llama_surrogate_train_step) in consecutive
+ * batches of `batch` rows (n / batch steps per epoch), one AdamW step each,
+ * learning rate lr_max * (1 + cos(pi * step / total)) / 2.  d_loss_sum, when
+ * not NULL, accumulates the summed loss of the last tenth of the final epoch. */
+int llama_surrogate_fit(llama_ctx *ctx, int64_t n, const int32_t *d_rows,
+                        const uint16_t *d_feat, const float *d_y, int32_t epochs,
+                        int64_t batch, float lr_max, float weight_decay,
+                        float *d_loss_sum, void *stream);
 
 /* Checkpoint: parameters, AdamW moments and step count in one versioned
  * binary file; _load requires the same number of profile rows. */

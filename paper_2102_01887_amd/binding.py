@@ -26,7 +26,8 @@ EXPORTS = ["llama_create", "llama_destroy", "llama_last_error", "llama_set_dag",
            "llama_debug_export", "llama_surrogate_param_count", "llama_surrogate_init",
            "llama_surrogate_set", "llama_surrogate_get", "llama_surrogate_grads",
            "llama_surrogate_reserve", "llama_surrogate_forward", "llama_surrogate_train_step",
-           "llama_surrogate_save", "llama_surrogate_load", "llama_decide_learned"]
+           "llama_surrogate_save", "llama_surrogate_load", "llama_decide_learned",
+           "llama_surrogate_fit", "llama_select_rows"]
 
 
 class LlamaStats(ctypes.Structure):
@@ -61,6 +62,7 @@ def load_library(path=LIB_PATH):
         "llama_select": [p, i64, p, p, p, p, p],
         "llama_decide": [p, i64, p, p, p, p, i32, i32, p, p, p],
         "llama_reserve": [p, i64],
+        "llama_select_rows": [p, i64, p, p, p, i64, p, p, p],
         "llama_get_stats": [p, ctypes.POINTER(LlamaStats), i32],
         "llama_debug_export": [p, i32, p, i64],
         "llama_surrogate_param_count": [i64],
@@ -71,6 +73,7 @@ def load_library(path=LIB_PATH):
         "llama_surrogate_reserve": [p, i64],
         "llama_surrogate_forward": [p, i64, p, p, p, p],
         "llama_surrogate_train_step": [p, i64, p, p, p, ctypes.c_float, ctypes.c_float, i32, p, p],
+        "llama_surrogate_fit": [p, i64, p, p, p, i32, i64, ctypes.c_float, ctypes.c_float, p, p],
         "llama_surrogate_save": [p, ctypes.c_char_p],
         "llama_surrogate_load": [p, ctypes.c_char_p],
         "llama_decide_learned": [p, i64, p, p, p, p, i32, p, ctypes.c_float, p, p, p, i64, p],
@@ -222,6 +225,21 @@ class Llama:
             _dp(cfg, "int32", n), _dp(flag, "uint8", n), _stream(stream)))
         return cfg, flag
 
+    def select_rows(self, op, target, lat, cfg=None, flag=None, stream=None):
+        """Eq. 1 with a latency per (invocation, configuration): lat is [n, stride]."""
+        import torch
+        n = op.numel()
+        stride = lat.shape[1] if lat.dim() == 2 else lat.numel() // max(n, 1)
+        if cfg is None:
+            cfg = torch.empty(n, dtype=torch.int32, device=op.device)
+        if flag is None:
+            flag = torch.empty(n, dtype=torch.uint8, device=op.device)
+        self._check("llama_select_rows", self._L.llama_select_rows(
+            self._ctx, n, _dp(op, "int32"), _dp(target, "int32", n * self.n_hw),
+            _dp(lat, "int32", n * stride), int(stride), _dp(cfg, "int32", n), _dp(flag, "uint8", n),
+            _stream(stream)))
+        return cfg, flag
+
     def decide(self, op, elapsed, slo, queue=None, mode=SLACK_PAPER, scan=SCAN_AUTO, cfg=None,
                flag=None, stream=None, with_flag=True):
         import torch
@@ -295,6 +313,14 @@ class Llama:
         self._check("llama_surrogate_train_step", self._L.llama_surrogate_train_step(
             self._ctx, n, _dp(rows, "int32"), _dp16(feat, 16 * n), _dp(y, "float32", n),
             float(lr), float(weight_decay), 1 if update else 0, _dp(loss_sum, "float32", 1),
+            _stream(stream)))
+
+    def surrogate_fit(self, rows, feat, y, epochs=3, batch=4096, lr_max=5e-3, weight_decay=1e-4,
+                      loss_sum=None, stream=None):
+        n = rows.numel()
+        self._check("llama_surrogate_fit", self._L.llama_surrogate_fit(
+            self._ctx, n, _dp(rows, "int32"), _dp16(feat, 16 * n), _dp(y, "float32", n), int(epochs),
+            int(batch), float(lr_max), float(weight_decay), _dp(loss_sum, "float32", 1),
             _stream(stream)))
 
     def surrogate_save(self, path):

@@ -598,6 +598,20 @@ int llama_decide(llama_ctx* c, int64_t n, const int32_t* op, const int32_t* elap
   return LLAMA_OK;
 }
 
+int llama_select_rows(llama_ctx* c, int64_t n, const int32_t* op, const int32_t* target, const int32_t* lat,
+                      int64_t lat_stride, int32_t* cfg, uint8_t* flag, void* stream) {
+  int rc = enter(c);
+  if (rc) return rc;
+  if ((rc = check_batch(c, n, op, "select_rows"))) return rc;
+  if (n > 0 && (!target || !lat || !cfg)) return fail(c, LLAMA_E_ARG, "select_rows: null pointer");
+  if (lat_stride < 1) return fail(c, LLAMA_E_ARG, "select_rows: lat_stride < 1");
+  llama::Batch b{};
+  b.n = n; b.op = op; b.target = target; b.cfg = cfg; b.flag = flag;
+  hipError_t e = llama::launch_select_rows(c->tables(), b, lat, lat_stride, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(c, e, "select_rows launch");
+  return LLAMA_OK;
+}
+
 int llama_reserve(llama_ctx* c, int64_t max_inv) {
   int rc = enter(c);
   if (rc) return rc;

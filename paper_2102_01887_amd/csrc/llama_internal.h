@@ -106,6 +106,8 @@ struct FullScratch {
 int64_t full_scan_hist_words(int64_t n_inv, int32_t n_ops);
 hipError_t launch_decide_full(const DevTables& t, const Batch& b, const FullScratch& w, hipStream_t s);
 hipError_t launch_decide_wave(const DevTables& t, const Batch& b, hipStream_t s);
+hipError_t launch_select_rows(const DevTables& t, const Batch& b, const int32_t* lat, int64_t stride,
+                              hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Learned surrogate

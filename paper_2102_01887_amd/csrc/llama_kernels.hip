@@ -756,6 +756,55 @@ __global__ __launch_bounds__(256) void decide_wave_kernel(DevTables t, Batch b) 
   }
 }
 
+// Eq. 1 given targets and a latency per (invocation, configuration): one
+// wavefront per invocation, lanes over the op's configurations (caller order),
+// wavefront min reductions for the cheapest feasible key and the fastest.
+template <int NHW>
+__global__ __launch_bounds__(256) void select_rows_kernel(DevTables t, Batch b, const int32_t* lat,
+                                                          int64_t stride) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t i = wave; i < b.n; i += n_waves) {
+    const int v = b.op[i];
+    if ((unsigned)v >= (unsigned)t.n_ops || t.cfg_off[v + 1] - t.cfg_off[v] > stride) {
+      if (lane == 0) {
+        b.cfg[i] = -1;
+        if (b.flag) b.flag[i] = 0;
+        atomicOr(t.err, 1u);
+      }
+      continue;
+    }
+    int32_t tg[NHW];
+#pragma unroll
+    for (int h = 0; h < NHW; ++h) tg[h] = b.target[i * NHW + h];
+    const int a0 = t.cfg_off[v], n_c = t.cfg_off[v + 1] - a0;
+    uint32_t best = KEY_NONE;
+    uint64_t fast = ~0ull;
+    for (int k = lane; k < n_c; k += 64) {
+      const int32_t L = lat[i * stride + k];
+      const int h = t.cfg_hw[a0 + k];
+      int32_t target = tg[0];
+#pragma unroll
+      for (int hh = 1; hh < NHW; ++hh) target = h == hh ? tg[hh] : target;
+      const uint32_t key = t.cfg_key[a0 + k];
+      if (L < target) best = umin32(best, key);
+      const uint64_t fk = ((uint64_t)(uint32_t)L << 16) | (uint64_t)k;
+      fast = fk < fast ? fk : fast;
+    }
+    best = wave_min_u32(best);
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint64_t o = __shfl_xor(fast, d, 64);
+      fast = o < fast ? o : fast;
+    }
+    if (lane == 0) {
+      b.cfg[i] = best != KEY_NONE ? (int32_t)(best & 0xFFFFu) : (int32_t)(fast & 0xFFFFu);
+      if (b.flag) b.flag[i] = best != KEY_NONE ? 1 : 0;
+    }
+  }
+}
+
 inline unsigned blocks_for(int64_t n, int per_block) {
   return (unsigned)((n + per_block - 1) / per_block);
 }
@@ -842,6 +891,14 @@ hipError_t launch_decide_full(const DevTables& t, const Batch& b, const FullScra
     hipLaunchKernelGGL(bucket_scatter_kernel, dim3(g), dim3(256), 0, s, t, b, w.cursor, w.perm);
   }
   LLAMA_DISPATCH_NHW(scan_bucketed_kernel, dim3(t.n_ops), dim3(256), s, t, b, w.start, w.perm);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_rows(const DevTables& t, const Batch& b, const int32_t* lat, int64_t stride,
+                              hipStream_t s) {
+  if (b.n == 0) return hipSuccess;
+  const int64_t waves = b.n < (int64_t)256 * 4 * 16 ? b.n : (int64_t)256 * 4 * 16;
+  LLAMA_DISPATCH_NHW(select_rows_kernel, dim3(blocks_for(waves, 4)), dim3(256), s, t, b, lat, stride);
   return hipGetLastError();
 }
 

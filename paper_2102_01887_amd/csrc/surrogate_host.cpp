@@ -257,6 +257,37 @@ int llama_surrogate_train_step(llama_ctx* c, int64_t batch, const int32_t* d_row
   return LLAMA_OK;
 }
 
+int llama_surrogate_fit(llama_ctx* c, int64_t n, const int32_t* d_rows, const uint16_t* d_feat, const float* d_y,
+                        int32_t epochs, int64_t batch, float lr_max, float weight_decay, float* d_loss_sum,
+                        void* stream) {
+  int rc = enter(c);
+  if (rc) return rc;
+  if ((rc = check_ready(c, "surrogate_fit"))) return rc;
+  if (batch < 1 || batch > INT32_MAX || n < batch || epochs < 1)
+    return fail(c, LLAMA_E_ARG, "surrogate_fit: need epochs >= 1 and n >= batch >= 1");
+  if (!d_rows || !d_feat || !d_y) return fail(c, LLAMA_E_ARG, "surrogate_fit: null pointer");
+  if (!(lr_max >= 0.0f) || !(weight_decay >= 0.0f)) return fail(c, LLAMA_E_ARG, "surrogate_fit: bad lr or weight decay");
+  if ((rc = reserve_ws(c, batch, (hipStream_t)stream))) return rc;
+  const int64_t per_epoch = n / batch, steps = per_epoch * epochs;
+  const llama::SurrogateBufs w = bufs(c);
+  hipStream_t s = (hipStream_t)stream;
+  for (int64_t k = 0; k < steps; ++k) {
+    const int64_t off = (k % per_epoch) * batch;
+    const float lr = (float)(0.5 * lr_max * (1.0 + std::cos(3.141592653589793 * (double)k / (double)steps)));
+    // the loss of the last tenth of the final epoch
+    float* loss = (d_loss_sum && k >= steps - (per_epoch + 9) / 10) ? d_loss_sum : nullptr;
+    hipError_t e = llama::launch_surrogate_forward(w, batch, d_rows + off, d_feat + off * llama::SURR_FEAT, s);
+    if (e == hipSuccess) e = llama::launch_surrogate_backward(w, batch, d_rows + off, d_y + off, loss, s);
+    if (e == hipSuccess) {
+      c->surr.step += 1;
+      e = llama::launch_adamw(w, lr, weight_decay, c->surr.step, s);
+    }
+    if (e == hipSuccess) e = llama::launch_shadows(w, s);
+    if (e != hipSuccess) return hip_fail(c, e, "surrogate_fit launch");
+  }
+  return LLAMA_OK;
+}
+
 int llama_surrogate_save(llama_ctx* c, const char* path) {
   int rc = enter(c);
   if (rc) return rc;

@@ -296,3 +296,18 @@ def test_ingest_errors():
     with pytest.raises(B.LlamaError) as e:
         L.decide(op, op, op, mode=7)
     assert e.value.rc == B.E_ARG
+
+
+def test_select_rows_matches_oracle():
+    torch = _torch()
+    rng = np.random.default_rng(17)
+    for w in (wl.make_c2(seed=10, n_pipelines=6, n_inv=3001), wl.make_c1(n_inv=777)):
+        r = Run(w)
+        stride = int(np.diff(w.cfg_off).max()) + 3
+        lat = rng.integers(1, 400_000, (w.n_inv, stride)).astype(np.int32)
+        lat[:, :5] = rng.integers(1, 3, (w.n_inv, 5))  # ties among the fastest
+        t = r.P.targets(PAPER)
+        c_or, f_or = oracle.select_lat(w.inv_op, t, w.n_hw, w.cfg_off, w.hw, w.batch, lat, w.cost)
+        c, f = r.L.select_rows(r.op, dev(t, torch), dev(lat, torch))
+        torch.cuda.synchronize()
+        assert np.array_equal(c.cpu().numpy(), c_or) and np.array_equal(f.cpu().numpy(), f_or)

@@ -154,28 +154,18 @@ def test_fused_inference_matches_oracle():
 
 
 def train(torch, L, world, n_samples, epochs=3, batch=4096, lr=5e-3, wd=1e-4, seed=7):
-    """The recipe: n_samples simulator executions, `epochs` passes in batches
-    of 4096, AdamW with cosine-decayed learning rate."""
+    """The recipe (llama_surrogate_fit): n_samples simulator executions,
+    `epochs` passes in batches of 4096, AdamW with cosine-decayed learning rate."""
     rng = np.random.default_rng(seed)
-    per_epoch = n_samples // batch
-    rows, c, y = wl.simulate_c4(world, rng, per_epoch * batch)
+    rows, c, y = wl.simulate_c4(world, rng, n_samples)
     d_rows, d_feat, d_y = dev(torch, rows), feat_dev(torch, c.feat), dev(torch, y)
     del rows, c, y
-    L.surrogate_reserve(batch)
-    steps = epochs * per_epoch
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
-    for s in range(steps):
-        lr_s = lr * 0.5 * (1 + math.cos(math.pi * s / steps))
-        b = s % per_epoch
-        sl = slice(b * batch, (b + 1) * batch)
-        last = s >= steps - per_epoch // 10
-        L.surrogate_train_step(d_rows[sl], d_feat[sl], d_y[sl], lr=lr_s, weight_decay=wd,
-                               loss_sum=loss if last else None)
-        if s % 2000 == 0:
-            torch.cuda.synchronize()
-            say(f"train step {s}/{steps}")
+    L.surrogate_fit(d_rows, d_feat, d_y, epochs=epochs, batch=batch, lr_max=lr, weight_decay=wd,
+                    loss_sum=loss)
     torch.cuda.synchronize()
-    return loss.item() / ((steps - (steps - per_epoch // 10)) * batch)
+    per_epoch = n_samples // batch
+    return loss.item() / (((per_epoch + 9) // 10) * batch)
 
 
 def evaluate(world, w, c, tgt, cfg_gpu):
