@@ -38,10 +38,17 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--mode", choices=["paper", "prob"], default="paper")
+    ap.add_argument("--workload", choices=["c2", "c3"], default="c2",
+                    help="c2: 256 pipelines, 1M invocations (default); c3: 4,096 uneven pipelines, 4M")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the learned-surrogate section (training + fused inference)")
     ap.add_argument("--train-samples", type=int, default=10_000_000)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop section")
+    ap.add_argument("--pmc-pass", action="store_true",
+                    help="for hardware-counter runs: a 256 MiB device copy (calibration) and a few "
+                         "eager relax + decide launches on the benchmark workload, nothing timed")
+    ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--kernel-reps", type=int, default=50,
                     help="launches per graph when timing single kernels")
     return ap.parse_args()
@@ -150,6 +157,7 @@ def bench_surrogate(args, torch, B, wl, log):
                world.w.cost, world.w.batch, (w4.inv_op[:m] * 64).astype(np.int64))
     r_s = regret_stats(s_c.cpu().numpy(), *args_np)
     r_p = regret_stats(p_c.cpu().numpy(), *args_np)
+    args._surrogate_ctx = (L, world)
     return {
         "workload": "c4: C1's 6-op DAG, 64 configs/op; train 10M simulator samples x 3 epochs "
                     "(batch 4096, AdamW, cosine lr 5e-3); infer 1M invocations x 64 configs",
@@ -165,6 +173,79 @@ def bench_surrogate(args, torch, B, wl, log):
         "regret_surrogate": r_s, "regret_plain_profile": r_p, "regret_sample": m,
         "dtype": "bf16 (fp32 accumulate)",
     }
+
+
+def drive_poisson(srv, op, el, slo, rate, duration, seed, feat=None):
+    """Offer a Poisson stream of the given rate for `duration` seconds (numpy
+    request arrays); returns per-request latency (ns) and the sustained rate."""
+    import numpy as np
+    from paper_2102_01887_amd import workloads as wl
+    off = wl.poisson_arrivals(np.random.default_rng(seed), rate, duration)
+    n = min(len(off), len(op))
+    t0 = time.monotonic_ns() + 2_000_000
+    arr = t0 + off[:n]
+    i = done = 0
+    lats = []
+    while done < n:
+        now = time.monotonic_ns()
+        j = int(np.searchsorted(arr, now, side="right"))
+        if j > i:
+            k, _ = srv.submit(op[i:j], el[i:j], slo[i:j], None if feat is None else feat[i:j],
+                              arrival_ns=arr[i:j])
+            i += k
+        t, _, _, lat = srv.poll(wait_ms=0)
+        done += len(t)
+        lats.append(lat)
+    elapsed = (time.monotonic_ns() - t0) * 1e-9
+    return np.concatenate(lats), n / elapsed
+
+
+def bench_serving(args, torch, B, wl, log, surrogate_ctx=None):
+    """Serving loop on C5 (1,024 uneven pipelines): Poisson arrivals at
+    50k-500k/s, 65,536 slots, 256 MB admission budget; p50/p99 latency from
+    arrival to decision and the sustained rate."""
+    import numpy as np
+    log("bench: generating workload c5 (1,024 pipelines)")
+    w = wl.make_c5(n_inv=600_000)
+    L = B.Llama(0).load(w)
+    out = {"workload": "c5: 1,024 layered pipelines of 3-200 ops, 16-2048 configs/op, "
+                       "Poisson arrivals, 65,536 slots, 256 MB admission budget",
+           "n_ops": w.n_ops, "n_cfg": w.n_cfg, "plain": []}
+    srv = B.Server(L, n_slots=65536, mem_budget_bytes=256 << 20, max_batch=65536, max_inflight=4)
+    drive_poisson(srv, w.inv_op, w.elapsed, w.slo, 50_000, 0.2, 1)  # warm-up, not reported
+    srv.close()
+    for rate in (50_000, 100_000, 200_000, 500_000):
+        srv = B.Server(L, n_slots=65536, mem_budget_bytes=256 << 20, max_batch=65536, max_inflight=4)
+        lat, sustained = drive_poisson(srv, w.inv_op, w.elapsed, w.slo, rate, args.serve_seconds, rate)
+        st = srv.stats()
+        srv.close()
+        p50, p99 = (np.percentile(lat, [50, 99]) / 1e3).tolist()
+        log(f"bench: serve {rate}/s -> p50 {p50:.1f} us p99 {p99:.1f} us, {sustained:.0f}/s")
+        out["plain"].append({"offered_per_s": rate, "decisions": int(len(lat)),
+                             "sustained_per_s": sustained, "p50_us": p50, "p99_us": p99,
+                             "batches": st["batches"], "mean_batch": len(lat) / max(1, st["batches"])})
+    if surrogate_ctx is not None:
+        Ls, world = surrogate_ctx
+        wq, content = wl.c4_invocations(world, np.random.default_rng(9), 400_000)
+        bits = (np.ascontiguousarray(content.feat, np.float32).view(np.uint32) >> 16).astype(np.uint16)
+        out["learned"] = []
+        srv = B.Server(Ls, n_slots=65536, mem_budget_bytes=256 << 20, max_batch=65536, max_inflight=4,
+                       learned=True)
+        drive_poisson(srv, wq.inv_op, wq.elapsed, wq.slo, 50_000, 0.2, 1, feat=bits)  # warm-up
+        srv.close()
+        for rate in (50_000, 200_000):
+            srv = B.Server(Ls, n_slots=65536, mem_budget_bytes=256 << 20, max_batch=65536,
+                           max_inflight=4, learned=True)
+            lat, sustained = drive_poisson(srv, wq.inv_op, wq.elapsed, wq.slo, rate, args.serve_seconds,
+                                           rate, feat=bits)
+            st = srv.stats()
+            srv.close()
+            p50, p99 = (np.percentile(lat, [50, 99]) / 1e3).tolist()
+            log(f"bench: serve learned {rate}/s -> p50 {p50:.1f} us p99 {p99:.1f} us")
+            out["learned"].append({"offered_per_s": rate, "decisions": int(len(lat)),
+                                   "sustained_per_s": sustained, "p50_us": p50, "p99_us": p99,
+                                   "batches": st["batches"]})
+    return out
 
 
 def main():
@@ -183,8 +264,27 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     mode = B.SLACK_PAPER if args.mode == "paper" else B.SLACK_PROB
 
-    log("bench: generating workload c2 (256 pipelines, 1M invocations)")
-    w = wl.make_c2()
+    if args.pmc_pass:
+        import numpy as np
+        log(f"bench: counter pass on {args.workload}")
+        w = wl.make_c2() if args.workload == "c2" else wl.make_c3()
+        L = B.Llama(0).load(w)
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        op, el, slo = dev(w.inv_op), dev(w.elapsed), dev(w.slo)
+        L.autotune(op, el, slo)
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")  # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        for _ in range(5):
+            L.relax()
+            L.decide(op, el, slo)
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_pass": args.workload, "copy_bytes": src.numel() * 4,
+                          "decide_algo_bytes": w.n_inv * 17}), flush=True)
+        return
+
+    log(f"bench: generating workload {args.workload}")
+    w = wl.make_c2() if args.workload == "c2" else wl.make_c3()
     L = B.Llama(0).load(w)
     st = L.stats()
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
@@ -203,6 +303,9 @@ def main():
     def step():
         relax()
         decide(B.SCAN_INDEXED)()
+
+    tuned = L.autotune(op, el, slo, stream=s)
+    log(f"bench: autotuned decision schedule: {tuned[0]} invocations per thread ({tuned[1]:.2f} us)")
 
     torch.cuda.synchronize()
     with torch.cuda.stream(s):
@@ -277,8 +380,12 @@ def main():
                          f"{len(times)} runs"}
 
     surr = None
+    args._surrogate_ctx = None
     if not args.no_surrogate:
         surr = bench_surrogate(args, torch, B, wl, log)
+    serve = None
+    if not args.no_serve:
+        serve = bench_serving(args, torch, B, wl, log, args._surrogate_ctx)
 
     out = {
         "metric": METRIC,
@@ -293,12 +400,15 @@ def main():
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": "c2 plain scaled: 256 layered DAGs of 10-40 ops, "
-                               "64-512 configs/op (4 hw x batch x 4 memory sizes), "
-                               "1M invocations, SLO 0.1-10 s",
+        "config": {"workload": ("c2 plain scaled: 256 layered DAGs of 10-40 ops, "
+                                "64-512 configs/op (4 hw x batch x 4 memory sizes), "
+                                "1M invocations, SLO 0.1-10 s") if args.workload == "c2" else
+                               ("c3 batched uneven: 4,096 layered DAGs of 3-200 ops, "
+                                "16-2048 configs/op, 4M invocations, SLO 0.1-10 s"),
                    "n_pipelines": w.n_pipelines, "n_ops": w.n_ops, "n_cfg": w.n_cfg,
                    "n_inv": n, "n_hw": w.n_hw, "slack_mode": args.mode,
-                   "scan": "indexed", "step": "relax + decide, one HIP graph"},
+                   "scan": "indexed", "step": "relax + decide, one HIP graph",
+                   "schedule": {"invocations_per_thread": tuned[0]}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "decide_indexed_kernel", "kernel_ms": ms_dec,
@@ -316,6 +426,7 @@ def main():
                       "decisions_per_s": n / (ms_wave * 1e-3)},
         "frontier_entries": st["frontier_entries"],
         "surrogate": surr,
+        "serving": serve,
     }
     print(json.dumps(out), flush=True)
 

@@ -239,6 +239,18 @@ int llama_select_rows(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
                       const int32_t *d_target_us, const int32_t *d_lat_us,
                       int64_t lat_stride, int32_t *d_cfg, uint8_t *d_flag, void *stream);
 
+/*
+ * Autotuner: time every schedule of the indexed decision kernel (invocations
+ * per thread 1, 2, 4) on the caller's batch (device pointers; d_cfg_scratch
+ * [n_inv] receives decisions), check that all of them give identical
+ * decisions (LLAMA_E_DEVICE otherwise), and keep the fastest for this
+ * context.  *chosen receives its parameter and *best_us its time per launch
+ * (either may be NULL).  Synchronous.
+ */
+int llama_autotune(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
+                   const int32_t *d_elapsed_us, const int32_t *d_slo_us, int32_t *d_cfg_scratch,
+                   int32_t *chosen, float *best_us, void *stream);
+
 /* Pre-size the scratch that LLAMA_SCAN_FULL needs for batches of up to
  * max_inv invocations (device memory, 4 bytes per invocation).  Synchronous. */
 int llama_reserve(llama_ctx *ctx, int64_t max_inv);
@@ -359,6 +371,63 @@ int llama_decide_learned(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
                          const uint16_t *d_feat, float spread_max, int32_t *d_cfg,
                          uint8_t *d_flag, int32_t *d_lat_out, int64_t lat_stride,
                          void *stream);
+
+/* ------------------------------------------------------------------------
+ * Serving loop: continuous batching of arriving invocations (the Manager
+ * spawning invocations and the Configurator deciding them, Sec. 3.3 and
+ * Sec. 4; admission bounded like the paper's commit queues, Sec. 4.3).
+ *
+ * Requests sit in a ring of slots in pinned host memory that the decision
+ * kernels read and write in place.  A request is admitted when a slot is free
+ * and bytes_per_request x (admitted, not yet collected) stays within the
+ * memory budget; llama_serve_submit admits the longest prefix that fits.  A
+ * worker thread launches every admitted request not yet on the GPU as one
+ * batch (at most max_batch, contiguous in the ring) on one of max_inflight
+ * streams while earlier batches run, and retires batches in order.  Decisions
+ * are collected in admission order (llama_serve_poll), which frees slots.
+ * While a server is open, the context's tables and surrogate must not be
+ * changed.  A server is driven by one caller thread.
+ * ---------------------------------------------------------------------- */
+typedef struct llama_server llama_server;
+
+typedef struct llama_serve_config {
+    int32_t n_slots;           /* ring capacity, >= 1 */
+    int64_t mem_budget_bytes;  /* admission budget, >= one request */
+    int32_t max_batch;         /* largest batch per launch, >= 1 */
+    int32_t max_inflight;      /* batches on the GPU at once, 1..16 */
+    int32_t learned;           /* 0: profile latencies, 1: surrogate (features required) */
+    int32_t slack_mode;        /* LLAMA_SLACK_PAPER or LLAMA_SLACK_PROB */
+    float spread_max;          /* learned mode: see llama_decide_learned */
+} llama_serve_config;
+
+typedef struct llama_serve_stats {
+    int64_t submitted, admitted, rejected, decided, collected, batches;
+    int64_t bytes_in_use, peak_bytes_in_use, max_batch_seen, in_flight_batches;
+} llama_serve_stats;
+
+/* Bytes charged per admitted request (64, or 96 with features). */
+int64_t llama_serve_bytes_per_request(int32_t learned);
+
+int llama_serve_open(llama_ctx *ctx, const llama_serve_config *cfg, llama_server **out);
+
+/* Offer n requests (host pointers; feat [n][16] BF16 in learned mode, else
+ * may be NULL; arrival_ns: CLOCK_MONOTONIC arrival times, NULL = now).
+ * *n_admitted receives how many, from the front, were admitted; tickets
+ * [n] (may be NULL) receive their sequence numbers. */
+int llama_serve_submit(llama_server *srv, int32_t n, const int32_t *op, const int32_t *elapsed_us,
+                       const int32_t *slo_us, const uint16_t *feat, const int64_t *arrival_ns,
+                       int64_t *tickets, int32_t *n_admitted);
+
+/* Collect up to max decided requests in admission order (waiting up to
+ * wait_ms for the first): tickets, choices, flags and arrival-to-decision
+ * latency in ns (any output may be NULL).  *n_out receives the count. */
+int llama_serve_poll(llama_server *srv, int32_t max, int64_t *tickets, int32_t *cfg, uint8_t *flag,
+                     int64_t *latency_ns, int32_t *n_out, int32_t wait_ms);
+
+int llama_serve_stats_get(llama_server *srv, llama_serve_stats *out);
+
+/* Finish every admitted request, stop the worker and free the server. */
+int llama_serve_close(llama_server *srv);
 
 #ifdef __cplusplus
 }

@@ -27,7 +27,9 @@ EXPORTS = ["llama_create", "llama_destroy", "llama_last_error", "llama_set_dag",
            "llama_surrogate_set", "llama_surrogate_get", "llama_surrogate_grads",
            "llama_surrogate_reserve", "llama_surrogate_forward", "llama_surrogate_train_step",
            "llama_surrogate_save", "llama_surrogate_load", "llama_decide_learned",
-           "llama_surrogate_fit", "llama_select_rows"]
+           "llama_surrogate_fit", "llama_select_rows", "llama_serve_bytes_per_request",
+           "llama_serve_open", "llama_serve_submit", "llama_serve_poll", "llama_serve_stats_get",
+           "llama_serve_close", "llama_autotune"]
 
 
 class LlamaStats(ctypes.Structure):
@@ -36,6 +38,19 @@ class LlamaStats(ctypes.Structure):
                 ("n_cfg", ctypes.c_int64), ("n_edges", ctypes.c_int64),
                 ("frontier_entries", ctypes.c_int64), ("device_error", ctypes.c_uint32),
                 ("device_bytes", ctypes.c_int64)]
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("n_slots", ctypes.c_int32), ("mem_budget_bytes", ctypes.c_int64),
+                ("max_batch", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+                ("learned", ctypes.c_int32), ("slack_mode", ctypes.c_int32),
+                ("spread_max", ctypes.c_float)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in (
+        "submitted", "admitted", "rejected", "decided", "collected", "batches", "bytes_in_use",
+        "peak_bytes_in_use", "max_batch_seen", "in_flight_batches")]
 
 
 _lib = None
@@ -63,6 +78,13 @@ def load_library(path=LIB_PATH):
         "llama_decide": [p, i64, p, p, p, p, i32, i32, p, p, p],
         "llama_reserve": [p, i64],
         "llama_select_rows": [p, i64, p, p, p, i64, p, p, p],
+        "llama_serve_bytes_per_request": [i32],
+        "llama_autotune": [p, i64, p, p, p, p, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float), p],
+        "llama_serve_open": [p, ctypes.POINTER(ServeConfig), ctypes.POINTER(p)],
+        "llama_serve_submit": [p, i32, p, p, p, p, p, p, ctypes.POINTER(i32)],
+        "llama_serve_poll": [p, i32, p, p, p, p, ctypes.POINTER(i32), i32],
+        "llama_serve_stats_get": [p, ctypes.POINTER(ServeStats)],
+        "llama_serve_close": [p],
         "llama_get_stats": [p, ctypes.POINTER(LlamaStats), i32],
         "llama_debug_export": [p, i32, p, i64],
         "llama_surrogate_param_count": [i64],
@@ -84,6 +106,7 @@ def load_library(path=LIB_PATH):
         f.restype = ctypes.c_int
     L.llama_destroy.restype = None
     L.llama_surrogate_param_count.restype = ctypes.c_int64
+    L.llama_serve_bytes_per_request.restype = ctypes.c_int64
     L.llama_last_error.restype = ctypes.c_char_p
     if path == LIB_PATH:
         _lib = L
@@ -194,6 +217,17 @@ class Llama:
     def update_latencies(self, lat):
         lat = _np(lat, np.int32)
         self._check("llama_update_latencies", self._L.llama_update_latencies(self._ctx, _hp(lat)))
+
+    def autotune(self, op, elapsed, slo, stream=None):
+        """Pick the fastest decision schedule on this batch; returns (parameter, us)."""
+        import torch
+        n = op.numel()
+        scratch = torch.empty(n, dtype=torch.int32, device=op.device)
+        k, us = ctypes.c_int32(), ctypes.c_float()
+        self._check("llama_autotune", self._L.llama_autotune(
+            self._ctx, n, _dp(op, "int32"), _dp(elapsed, "int32", n), _dp(slo, "int32", n),
+            _dp(scratch, "int32", n), ctypes.byref(k), ctypes.byref(us), _stream(stream)))
+        return k.value, us.value
 
     def reserve(self, max_inv):
         self._check("llama_reserve", self._L.llama_reserve(self._ctx, int(max_inv)))
@@ -344,3 +378,63 @@ class Llama:
             _dp(lat_out, "int32", n * lat_stride) if lat_out is not None else None,
             int(lat_stride), _stream(stream)))
         return cfg, flag
+
+
+class Server:
+    """Continuous-batching serving loop on one context (llama_serve_*)."""
+
+    def __init__(self, llama, n_slots=65536, mem_budget_bytes=256 << 20, max_batch=65536,
+                 max_inflight=4, learned=False, slack_mode=SLACK_PAPER, spread_max=1.3862944):
+        self._llama = llama
+        self._L = llama._L
+        self.learned = bool(learned)
+        cfg = ServeConfig(int(n_slots), int(mem_budget_bytes), int(max_batch), int(max_inflight),
+                          1 if learned else 0, int(slack_mode), float(spread_max))
+        self._srv = ctypes.c_void_p()
+        llama._check("llama_serve_open", self._L.llama_serve_open(llama._ctx, ctypes.byref(cfg),
+                                                                  ctypes.byref(self._srv)))
+
+    def submit(self, op, elapsed, slo, feat=None, arrival_ns=None):
+        """Offer requests (numpy); returns the admitted count and their tickets."""
+        op, elapsed, slo = (_np(x, np.int32) for x in (op, elapsed, slo))
+        n = len(op)
+        f = None if feat is None else np.ascontiguousarray(feat, dtype=np.uint16)
+        t = _np(arrival_ns, np.int64)
+        tickets = np.empty(n, np.int64)
+        k = ctypes.c_int32()
+        rc = self._L.llama_serve_submit(self._srv, n, _hp(op), _hp(elapsed), _hp(slo), _hp(f), _hp(t),
+                                        _hp(tickets), ctypes.byref(k))
+        if rc != OK:
+            raise LlamaError("llama_serve_submit", rc, "serving loop failed")
+        return k.value, tickets[:k.value]
+
+    def poll(self, max_n=1 << 16, wait_ms=0):
+        tickets = np.empty(max_n, np.int64)
+        cfg = np.empty(max_n, np.int32)
+        flag = np.empty(max_n, np.uint8)
+        lat = np.empty(max_n, np.int64)
+        k = ctypes.c_int32()
+        rc = self._L.llama_serve_poll(self._srv, max_n, _hp(tickets), _hp(cfg), _hp(flag), _hp(lat),
+                                      ctypes.byref(k), int(wait_ms))
+        if rc != OK:
+            raise LlamaError("llama_serve_poll", rc, "serving loop failed")
+        n = k.value
+        return tickets[:n], cfg[:n], flag[:n], lat[:n]
+
+    def stats(self):
+        st = ServeStats()
+        self._L.llama_serve_stats_get(self._srv, ctypes.byref(st))
+        return {k: getattr(st, k) for k, _ in ServeStats._fields_}
+
+    def close(self):
+        if self._srv:
+            rc = self._L.llama_serve_close(self._srv)
+            self._srv = ctypes.c_void_p()
+            if rc != OK:
+                raise LlamaError("llama_serve_close", rc, "serving loop failed")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

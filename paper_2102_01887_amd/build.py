@@ -25,7 +25,7 @@ DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I" + INCLUDE, "-I" + CSRC]
 
 KERNELS = ["llama_kernels.hip", "surrogate_kernels.hip"]
-HOST = ["llama_host.cpp", "surrogate_host.cpp"]
+HOST = ["llama_host.cpp", "surrogate_host.cpp", "serve_host.cpp"]
 
 
 def _run(cmd, verbose):
@@ -48,7 +48,7 @@ def build(verbose=True):
               os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-fopenmp", *objs, "-o", tmp,
+    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-fopenmp", "-pthread", *objs, "-o", tmp,
           "-Wl,-rpath,/opt/rocm/lib:/opt/rocm/llvm/lib"], verbose)
     os.replace(tmp, LIB)
     return LIB

@@ -71,6 +71,7 @@ struct llama_ctx {
   llama::Surrogate surr;
   DevBuf d_cnt, d_start, d_cursor, d_perm, d_hist;  // bucketed full scan
   int64_t perm_cap = 0;
+  int32_t decide_ipt = 1;  // schedule chosen by llama_autotune
 
   DevTables tables() const {
     DevTables t{};
@@ -79,6 +80,7 @@ struct llama_ctx {
     t.n_pipelines = n_pipelines;
     t.hs = llama::header_stride(n_hw);
     t.n_front = n_front;
+    t.decide_ipt = decide_ipt;
     t.pipe_off = d_pipe_off.as<int32_t>();
     t.pipe_lvl = d_pipe_lvl.as<int32_t>();
     t.lvl_bnd = d_lvl_bnd.as<int32_t>();

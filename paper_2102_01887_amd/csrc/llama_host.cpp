@@ -612,6 +612,61 @@ int llama_select_rows(llama_ctx* c, int64_t n, const int32_t* op, const int32_t*
   return LLAMA_OK;
 }
 
+int llama_autotune(llama_ctx* c, int64_t n, const int32_t* op, const int32_t* elapsed, const int32_t* slo,
+                   int32_t* cfg_scratch, int32_t* chosen_ipt, float* best_us, void* stream) {
+  int rc = enter(c);
+  if (rc) return rc;
+  if ((rc = check_batch(c, n, op, "autotune"))) return rc;
+  if (n < 1 || !elapsed || !slo || !cfg_scratch) return fail(c, LLAMA_E_ARG, "autotune: need a non-empty batch and scratch");
+  hipStream_t s = (hipStream_t)stream;
+  const int cands[3] = {1, 2, 4};
+  float best = 0.0f;
+  int best_ipt = 1;
+  std::vector<int32_t> ref_out, out;
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return fail(c, LLAMA_E_DEVICE, "autotune events");
+  const int saved = c->decide_ipt;
+  for (int ci = 0; ci < 3; ++ci) {
+    c->decide_ipt = cands[ci];
+    llama::Batch bt{};
+    bt.n = n; bt.op = op; bt.elapsed = elapsed; bt.slo = slo; bt.cfg = cfg_scratch; bt.mode = LLAMA_SLACK_PAPER;
+    hipError_t e = llama::launch_decide_indexed(c->tables(), bt, s);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(a, s);
+    for (int r = 0; r < 10 && e == hipSuccess; ++r) e = llama::launch_decide_indexed(c->tables(), bt, s);
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    // every schedule must give the same decisions
+    out.resize(n);
+    if (e == hipSuccess) e = hipMemcpy(out.data(), cfg_scratch, sizeof(int32_t) * n, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      c->decide_ipt = saved;
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+      return hip_fail(c, e, "autotune");
+    }
+    if (ci == 0) ref_out = out;
+    else if (out != ref_out) {
+      c->decide_ipt = saved;
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+      return fail(c, LLAMA_E_DEVICE, "autotune: schedule %d changed the decisions", cands[ci]);
+    }
+    const float us = ms * 100.0f;  // ms / 10 launches, in us
+    if (ci == 0 || us < best) {
+      best = us;
+      best_ipt = cands[ci];
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  c->decide_ipt = best_ipt;
+  if (chosen_ipt) *chosen_ipt = best_ipt;
+  if (best_us) *best_us = best;
+  return LLAMA_OK;
+}
+
 int llama_reserve(llama_ctx* c, int64_t max_inv) {
   int rc = enter(c);
   if (rc) return rc;

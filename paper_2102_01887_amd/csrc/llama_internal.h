@@ -40,6 +40,7 @@ struct DevTables {
   int32_t n_pipelines;
   int32_t hs;              // header_stride(n_hw)
   int64_t n_front;         // frontier entries (all ops, all backends)
+  int32_t decide_ipt;      // schedule: invocations per thread of the indexed decision (1, 2 or 4)
 
   // DAG
   const int32_t* pipe_off;   // [P+1] op range of each pipeline

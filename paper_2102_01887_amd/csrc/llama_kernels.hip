@@ -461,20 +461,9 @@ __global__ __launch_bounds__(256) void select_indexed_kernel(DevTables t, Batch 
 // division and no data-dependent branch unless the frontier continues past
 // the record.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void decide_indexed_kernel(DevTables t, Batch b, const uint4* rec,
-                                                             const uint2* ovf) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= b.n) return;
-  const int v = b.op[i], e = b.elapsed[i], s = b.slo[i];
-  if (invalid_invocation(v, e, s, t.n_ops)) {
-    b.cfg[i] = -1;
-    if (b.flag) b.flag[i] = 0;
-    atomicOr(t.err, 1u);
-    return;
-  }
-  const int32_t r0 = s - e;  // both non-negative: no overflow
-  const uint4* r = rec + (int64_t)v * (REC_WORDS / 4);
-  const uint4 a = r[0], bq = r[1], c = r[2], d = r[3];
+
+__device__ __forceinline__ int record_choice(const uint4& a, const uint4& bq, const uint4& c, const uint4& d,
+                                             int32_t r0, int* n_out) {
   const uint32_t T[REC_SLOTS] = {a.y, a.z, a.w, bq.x, bq.y, bq.z, bq.w, c.x, c.y, c.z};
   const uint32_t K2[REC_SLOTS / 2] = {c.w, d.x, d.y, d.z, d.w};
   const int n = (int)(a.x & 0xFFFFu);
@@ -484,18 +473,63 @@ __global__ __launch_bounds__(256) void decide_indexed_kernel(DevTables t, Batch 
     const int k = (int)((K2[slot >> 1] >> (16 * (slot & 1))) & 0xFFFFu);
     if (slot < n && (int32_t)T[slot] < r0) sel = k;
   }
-  if (sel < 0 && n > REC_SLOTS) {
-    // every slot needs more time: search the rest of the frontier (ascending)
-    const int lo0 = t.hdr[(int64_t)v * t.hs];
-    int lo = lo0, hi = lo0 + n - REC_SLOTS;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if ((int32_t)ovf[mid].x < r0) lo = mid + 1; else hi = mid;
-    }
-    if (lo > lo0) sel = (int)(ovf[lo - 1].y & 0xFFFFu);
+  *n_out = n;
+  return sel;
+}
+
+// DECIDE_IPT = invocations per thread (a schedule parameter chosen by the
+// autotuner): each thread decides DECIDE_IPT invocations spaced by the block
+// size, so every load instruction stays coalesced, and issues all loads first.
+template <int DECIDE_IPT>
+__global__ __launch_bounds__(256) void decide_indexed_kernel(DevTables t, Batch b, const uint4* rec,
+                                                             const uint2* ovf) {
+  const int64_t base = (int64_t)blockIdx.x * blockDim.x * DECIDE_IPT + threadIdx.x;
+  int v[DECIDE_IPT], e[DECIDE_IPT], s[DECIDE_IPT];
+#pragma unroll
+  for (int u = 0; u < DECIDE_IPT; ++u) {
+    const int64_t i = base + (int64_t)u * blockDim.x;
+    const bool in = i < b.n;
+    v[u] = in ? b.op[i] : 0;
+    e[u] = in ? b.elapsed[i] : 0;
+    s[u] = in ? b.slo[i] : 0;
   }
-  b.cfg[i] = sel >= 0 ? sel : (int)(a.x >> 16);
-  if (b.flag) b.flag[i] = sel >= 0 ? 1 : 0;
+  uint4 ra[DECIDE_IPT], rb[DECIDE_IPT], rc[DECIDE_IPT], rd[DECIDE_IPT];
+  bool ok[DECIDE_IPT];
+#pragma unroll
+  for (int u = 0; u < DECIDE_IPT; ++u) {
+    ok[u] = !invalid_invocation(v[u], e[u], s[u], t.n_ops);
+    const uint4* r = rec + (int64_t)(ok[u] ? v[u] : 0) * (REC_WORDS / 4);
+    ra[u] = r[0];
+    rb[u] = r[1];
+    rc[u] = r[2];
+    rd[u] = r[3];
+  }
+#pragma unroll
+  for (int u = 0; u < DECIDE_IPT; ++u) {
+    const int64_t i = base + (int64_t)u * blockDim.x;
+    if (i >= b.n) continue;
+    if (!ok[u]) {
+      b.cfg[i] = -1;
+      if (b.flag) b.flag[i] = 0;
+      atomicOr(t.err, 1u);
+      continue;
+    }
+    const int32_t r0 = s[u] - e[u];  // both non-negative: no overflow
+    int n;
+    int sel = record_choice(ra[u], rb[u], rc[u], rd[u], r0, &n);
+    if (sel < 0 && n > REC_SLOTS) {
+      // every slot needs more time: search the rest of the frontier (ascending)
+      const int lo0 = t.hdr[(int64_t)v[u] * t.hs];
+      int lo = lo0, hi = lo0 + n - REC_SLOTS;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int32_t)ovf[mid].x < r0) lo = mid + 1; else hi = mid;
+      }
+      if (lo > lo0) sel = (int)(ovf[lo - 1].y & 0xFFFFu);
+    }
+    b.cfg[i] = sel >= 0 ? sel : (int)(ra[u].x >> 16);
+    if (b.flag) b.flag[i] = sel >= 0 ? 1 : 0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -862,7 +896,17 @@ hipError_t launch_decide_indexed(const DevTables& t, const Batch& b, hipStream_t
     rec = t.rec_q;
     ovf = t.ovf_q;
   }
-  hipLaunchKernelGGL(decide_indexed_kernel, dim3(blocks_for(b.n, 256)), dim3(256), 0, s, t, b, rec, ovf);
+  switch (t.decide_ipt) {
+    case 2:
+      hipLaunchKernelGGL(decide_indexed_kernel<2>, dim3(blocks_for(b.n, 256 * 2)), dim3(256), 0, s, t, b, rec, ovf);
+      break;
+    case 4:
+      hipLaunchKernelGGL(decide_indexed_kernel<4>, dim3(blocks_for(b.n, 256 * 4)), dim3(256), 0, s, t, b, rec, ovf);
+      break;
+    default:
+      hipLaunchKernelGGL(decide_indexed_kernel<1>, dim3(blocks_for(b.n, 256)), dim3(256), 0, s, t, b, rec, ovf);
+      break;
+  }
   return hipGetLastError();
 }
 

@@ -54,31 +54,42 @@ __device__ __forceinline__ floatx4 mfma16x16x32(const bf16x8& a, const bf16x8& b
 // C[m][n] (+)= sum_k A(m,k) B(k,n) (+ bias[n]), BF16 inputs with arbitrary
 // element strides, FP32 output.  64x64 tile per 256-lane workgroup, each
 // wavefront a 32x32 quarter (2x2 MFMA blocks), K in steps of 32 through LDS.
+// Tiles are loaded along whichever index has unit stride, so both plain and
+// transposed operands read coalesced.  With gridDim.z > 1 the K range is
+// split across workgroups that add their partial sums atomically (C must then
+// be zeroed first, and the bias is added by split 0 only).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, const bf16* __restrict__ a,
                                                         int64_t sam, int64_t sak, const bf16* __restrict__ b,
                                                         int64_t sbk, int64_t sbn, float* __restrict__ c,
                                                         int64_t ldc, const float* __restrict__ bias,
-                                                        int accumulate) {
+                                                        int accumulate, int k_chunk) {
   __shared__ __attribute__((aligned(16))) bf16 sA[64][40];  // [m][k], 8 pad columns
   __shared__ __attribute__((aligned(16))) bf16 sB[64][40];  // [n][k]
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int kb0 = blockIdx.z * k_chunk;
+  const int kb1 = kb0 + k_chunk < K ? kb0 + k_chunk : K;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int g = lane >> 4, r = lane & 15;
+  const bool a_along_m = sam == 1 && sak != 1;
+  const bool b_along_n = sbn == 1 && sbk != 1;
   floatx4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
   const bf16 zero = (bf16)0.0f;
-  for (int k0 = 0; k0 < K; k0 += 32) {
+  for (int k0 = kb0; k0 < kb1; k0 += 32) {
     for (int e = tid; e < 64 * 32; e += 256) {
-      const int mm = e >> 5, kk = e & 31;
+      int mm, kk;
+      if (a_along_m) { mm = e & 63; kk = e >> 6; } else { mm = e >> 5; kk = e & 31; }
       const int gm = m0 + mm, gk = k0 + kk;
-      sA[mm][kk] = (gm < M && gk < K) ? a[gm * sam + gk * sak] : zero;
-      const int gn = n0 + mm;
-      sB[mm][kk] = (gn < N && gk < K) ? b[gk * sbk + gn * sbn] : zero;
+      sA[mm][kk] = (gm < M && gk < kb1) ? a[gm * sam + gk * sak] : zero;
+      int nn, kn;
+      if (b_along_n) { nn = e & 63; kn = e >> 6; } else { nn = e >> 5; kn = e & 31; }
+      const int gn = n0 + nn, gkn = k0 + kn;
+      sB[nn][kn] = (gn < N && gkn < kb1) ? b[gkn * sbk + gn * sbn] : zero;
     }
     __syncthreads();
 #pragma unroll
@@ -92,6 +103,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, con
     }
     __syncthreads();
   }
+  const bool split = gridDim.z > 1;
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
@@ -101,9 +113,13 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, con
         const int row = m0 + wm + mb * 16 + 4 * g + i;
         const int col = n0 + wn + nb * 16 + r;
         if (row < M && col < N) {
-          float x = acc[mb][nb][i] + (bias ? bias[col] : 0.0f);
-          if (accumulate) x += c[row * ldc + col];
-          c[row * ldc + col] = x;
+          float x = acc[mb][nb][i] + ((bias && blockIdx.z == 0) ? bias[col] : 0.0f);
+          if (split) {
+            atomicAdd(&c[row * ldc + col], x);
+          } else {
+            if (accumulate) x += c[row * ldc + col];
+            c[row * ldc + col] = x;
+          }
         }
       }
 }
@@ -146,13 +162,23 @@ __global__ __launch_bounds__(256) void gelu_bwd_round_kernel(int64_t n, const fl
   if (i < n) dz[i] = (bf16)(dh[i] * gelu_grad(z[i]));
 }
 
-// out[n] = sum over m of x[m][n]
+// out[n] += sum over m of x[m][n]: each 256-lane workgroup sums 64 columns
+// over a chunk of COLSUM_ROWS rows (4 lanes per column), reduces in LDS and
+// adds atomically (out must be zeroed first).
+constexpr int COLSUM_ROWS = 512;
 __global__ __launch_bounds__(256) void colsum_kernel(int64_t M, int N, const bf16* x, float* out) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
+  __shared__ float part[4][64];
+  const int col = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int q = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.y * COLSUM_ROWS;
+  const int64_t r1 = r0 + COLSUM_ROWS < M ? r0 + COLSUM_ROWS : M;
   float s = 0.0f;
-  for (int64_t m = 0; m < M; ++m) s += (float)x[m * N + n];
-  out[n] = s;
+  if (col < N)
+    for (int64_t m = r0 + q; m < r1; m += 4) s += (float)x[m * N + col];
+  part[q][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (q == 0 && col < N) atomicAdd(&out[col], part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] +
+                                                  part[3][threadIdx.x]);
 }
 
 __global__ __launch_bounds__(256) void scatter_embed_kernel(int64_t B, const int32_t* rows, const float* dX,
@@ -162,6 +188,11 @@ __global__ __launch_bounds__(256) void scatter_embed_kernel(int64_t B, const int
   const int64_t m = e / EMB;
   const int j = (int)(e % EMB);
   atomicAdd(&dE[(int64_t)rows[m] * EMB + j], dX[m * IN + j]);
+}
+
+__global__ __launch_bounds__(256) void zero_2d_kernel(int M, int N, float* c, int64_t ldc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < (int64_t)M * N) c[(e / N) * ldc + e % N] = 0.0f;
 }
 
 __global__ __launch_bounds__(256) void fill_f32_kernel(int64_t n, float* p, float v) {
@@ -388,9 +419,26 @@ hipError_t launch_gemm_bf16(int M, int N, int K, const void* a, int64_t sam, int
                             int64_t sbk, int64_t sbn, float* c, int64_t ldc, const float* bias, bool accumulate,
                             hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  dim3 grid(grid1(N, 64), grid1(M, 64));
-  hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, s, M, N, K, (const bf16*)a, sam, sak,
-                     (const bf16*)bm, sbk, sbn, c, ldc, bias, accumulate ? 1 : 0);
+  const unsigned gx = grid1(N, 64), gy = grid1(M, 64);
+  // few output tiles and a long K (weight gradients over the batch): split K
+  unsigned gz = 1;
+  if (gx * gy < 128 && K >= 1024 && !accumulate) {
+    gz = (unsigned)((K + 255) / 256);
+    if (gz > 64) gz = 64;
+  }
+  const int k_chunk = (int)(((K + (int)gz - 1) / (int)gz + 31) / 32 * 32);
+  gz = (unsigned)((K + k_chunk - 1) / k_chunk);
+  if (gz > 1)  // the split-K partial sums are added atomically into a zeroed C
+    hipLaunchKernelGGL(zero_2d_kernel, dim3(grid1((int64_t)M * N, 256)), dim3(256), 0, s, M, N, c, ldc);
+  hipLaunchKernelGGL(gemm_bf16_kernel, dim3(gx, gy, gz), dim3(256), 0, s, M, N, K, (const bf16*)a, sam, sak,
+                     (const bf16*)bm, sbk, sbn, c, ldc, bias, accumulate ? 1 : 0, gz > 1 ? k_chunk : K);
+  return hipGetLastError();
+}
+
+hipError_t launch_colsum(int64_t M, int N, const void* x, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(fill_f32_kernel, dim3(grid1(N, 256)), dim3(256), 0, s, (int64_t)N, out, 0.0f);
+  hipLaunchKernelGGL(colsum_kernel, dim3(grid1(N, 64), (unsigned)((M + COLSUM_ROWS - 1) / COLSUM_ROWS)), dim3(256), 0,
+                     s, M, N, (const bf16*)x, out);
   return hipGetLastError();
 }
 
@@ -414,19 +462,19 @@ hipError_t launch_surrogate_backward(const SurrogateBufs& w, int64_t B, const in
                      loss_sum);
   // layer 3: dW3 = dout^T h2, db3 = colsum(dout), dh2 = dout W3
   if ((e = launch_gemm_bf16(2, HID, (int)B, w.dout, 1, 2, w.h2, HID, 1, g + w.oW3, HID, nullptr, false, s))) return e;
-  hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(256), 0, s, B, 2, (const bf16*)w.dout, g + w.ob3);
+  if ((e = launch_colsum(B, 2, w.dout, g + w.ob3, s))) return e;
   if ((e = launch_gemm_bf16((int)B, HID, 2, w.dout, 2, 1, w.W3_16, HID, 1, w.dh2, HID, nullptr, false, s))) return e;
   hipLaunchKernelGGL(gelu_bwd_round_kernel, dim3(grid1(B * HID, 256)), dim3(256), 0, s, B * HID, w.dh2, w.z2,
                      (bf16*)w.dz2);
   // layer 2
   if ((e = launch_gemm_bf16(HID, HID, (int)B, w.dz2, 1, HID, w.h1, HID, 1, g + w.oW2, HID, nullptr, false, s))) return e;
-  hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(256), 0, s, B, HID, (const bf16*)w.dz2, g + w.ob2);
+  if ((e = launch_colsum(B, HID, w.dz2, g + w.ob2, s))) return e;
   if ((e = launch_gemm_bf16((int)B, HID, HID, w.dz2, HID, 1, w.W2_16, HID, 1, w.dh1, HID, nullptr, false, s))) return e;
   hipLaunchKernelGGL(gelu_bwd_round_kernel, dim3(grid1(B * HID, 256)), dim3(256), 0, s, B * HID, w.dh1, w.z1,
                      (bf16*)w.dz1);
   // layer 1 and the embedding
   if ((e = launch_gemm_bf16(HID, IN, (int)B, w.dz1, 1, HID, w.X16, IN, 1, g + w.oW1, IN, nullptr, false, s))) return e;
-  hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(256), 0, s, B, HID, (const bf16*)w.dz1, g + w.ob1);
+  if ((e = launch_colsum(B, HID, w.dz1, g + w.ob1, s))) return e;
   if ((e = launch_gemm_bf16((int)B, IN, HID, w.dz1, HID, 1, w.W1_16, IN, 1, w.dX, IN, nullptr, false, s))) return e;
   hipLaunchKernelGGL(fill_f32_kernel, dim3(grid1(w.nE, 256)), dim3(256), 0, s, w.nE, g, 0.0f);
   hipLaunchKernelGGL(scatter_embed_kernel, dim3(grid1(B * EMB, 256)), dim3(256), 0, s, B, rows, w.dX, g);

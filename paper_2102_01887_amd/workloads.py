@@ -507,3 +507,22 @@ def c4_truth_p95(world, inv_op, content):
     mu = (np.log(w.lat[rows].astype(np.float64)) + world.a[op, w.hw[rows]] * np.log1p(content.n_obj[:, None])
           + world.b[op] * np.log(content.px[:, None] / PX_720P))
     return np.minimum(np.ceil(np.exp(mu + 1.6448536269514722 * world.sigma)), INT32_MAX).astype(np.int32)
+
+
+# ---------------------------------------------------------------------------
+# Configuration 5: serving (Poisson arrivals over 1,024 uneven pipelines)
+# ---------------------------------------------------------------------------
+
+def make_c5(seed=6, n_pipelines=1024, n_inv=1_000_000, max_cfg=2048):
+    """1,024 pipelines shaped as in C3 (op counts 3-200, 16-2048 configurations
+    per op) with a pool of invocations as in C2."""
+    w = make_c3(seed=seed, n_pipelines=n_pipelines, n_inv=n_inv, max_cfg=max_cfg)
+    w.name = "c5-serving"
+    return w
+
+
+def poisson_arrivals(rng, rate_per_s, duration_s):
+    """Arrival offsets in ns of a Poisson process of the given rate."""
+    n = rng.poisson(rate_per_s * duration_s)
+    t = np.sort(rng.uniform(0.0, duration_s, n))
+    return (t * 1e9).astype(np.int64)

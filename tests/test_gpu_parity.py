@@ -311,3 +311,25 @@ def test_select_rows_matches_oracle():
         c, f = r.L.select_rows(r.op, dev(t, torch), dev(lat, torch))
         torch.cuda.synchronize()
         assert np.array_equal(c.cpu().numpy(), c_or) and np.array_equal(f.cpu().numpy(), f_or)
+
+
+def test_c3_reduced():
+    # uneven pipelines (3-200 ops) and tables (16-2048 configurations per op)
+    w = wl.make_c3(seed=12, n_pipelines=64, n_inv=40_001)
+    assert_full_parity(Run(w), modes=(PAPER,))
+
+
+def test_c3_full_size_sampled():
+    # 4,096 pipelines, ~80M configurations, 4M invocations, decided in one call;
+    # the oracle checks a 200,000-invocation sample of the same call
+    torch = _torch()
+    w = wl.make_c3()
+    say(f"c3: {w.n_ops} ops, {w.n_cfg} configurations, {w.n_inv} invocations")
+    L = B.Llama(0).load(w)
+    c, f = L.decide(dev(w.inv_op, torch), dev(w.elapsed, torch), dev(w.slo, torch))
+    torch.cuda.synchronize()
+    c, f = c.cpu().numpy(), f.cpu().numpy()
+    idx = np.sort(np.random.default_rng(0).choice(w.n_inv, 200_000, replace=False))
+    ws = w.with_invocations(w.inv_op[idx], w.elapsed[idx], w.slo[idx])
+    c_or, f_or = oracle.Problem(ws).decide(PAPER)
+    assert np.array_equal(c[idx], c_or) and np.array_equal(f[idx], f_or)
