@@ -305,7 +305,7 @@ def main():
         decide(B.SCAN_INDEXED)()
 
     tuned = L.autotune(op, el, slo, stream=s)
-    log(f"bench: autotuned decision schedule: {tuned[0]} invocations per thread ({tuned[1]:.2f} us)")
+    log(f"bench: autotuned decision schedule: {B.SCHEDULE_NAMES[tuned[0]]} ({tuned[1]:.2f} us)")
 
     torch.cuda.synchronize()
     with torch.cuda.stream(s):
@@ -408,10 +408,10 @@ def main():
                    "n_pipelines": w.n_pipelines, "n_ops": w.n_ops, "n_cfg": w.n_cfg,
                    "n_inv": n, "n_hw": w.n_hw, "slack_mode": args.mode,
                    "scan": "indexed", "step": "relax + decide, one HIP graph",
-                   "schedule": {"invocations_per_thread": tuned[0]}},
+                   "decide_schedule": B.SCHEDULE_NAMES[tuned[0]]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "decide_indexed_kernel", "kernel_ms": ms_dec,
+                     "kernel": ("decide_lds_kernel" if tuned[0] == 3 else "decide_indexed_kernel"), "kernel_ms": ms_dec,
                      "algo_bytes": algo_bytes},
         "cpu_baseline": cpu,
         "bit_exact": bit_exact,

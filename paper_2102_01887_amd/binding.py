@@ -18,6 +18,8 @@ OK, E_ARG, E_RANGE, E_CYCLE, E_STATE, E_DEVICE, E_NOMEM = 0, -1, -2, -3, -4, -5,
 SLACK_PAPER, SLACK_PROB = 0, 1
 SCAN_AUTO, SCAN_INDEXED, SCAN_FULL, SCAN_WAVE = 0, 1, 2, 3
 SCANS = (SCAN_INDEXED, SCAN_FULL, SCAN_WAVE)
+# decision schedules that llama_autotune chooses among (index = its *chosen)
+SCHEDULE_NAMES = ("direct-1", "direct-2", "direct-4", "lds-persistent")
 DEVERR_INVALID_INVOCATION = 1
 
 EXPORTS = ["llama_create", "llama_destroy", "llama_last_error", "llama_set_dag",
@@ -219,7 +221,7 @@ class Llama:
         self._check("llama_update_latencies", self._L.llama_update_latencies(self._ctx, _hp(lat)))
 
     def autotune(self, op, elapsed, slo, stream=None):
-        """Pick the fastest decision schedule on this batch; returns (parameter, us)."""
+        """Pick the fastest decision schedule on this batch; returns (schedule index, us)."""
         import torch
         n = op.numel()
         scratch = torch.empty(n, dtype=torch.int32, device=op.device)

@@ -63,7 +63,7 @@ struct llama_ctx {
   std::vector<int32_t> cfg_off, hw, batch, res, lat, ref_k, ref, fastest;
   std::vector<int64_t> cost;
   std::vector<uint32_t> key;  // caller order
-  DevBuf d_ref, d_W, d_hdr, d_front_L, d_rec, d_ovf, d_rec_q, d_ovf_q, d_seg_off, d_tab;
+  DevBuf d_ref, d_W, d_hdr, d_front_L, d_rec, d_rec_tail, d_ovf, d_rec_q, d_rec_tail_q, d_ovf_q, d_seg_off, d_tab;
   DevBuf d_mst, d_mst_op, d_mst_first;
   DevBuf d_cfg_off, d_cfg_hw, d_cfg_lat, d_cfg_key;
   int64_t n_mst = 0;
@@ -71,7 +71,8 @@ struct llama_ctx {
   llama::Surrogate surr;
   DevBuf d_cnt, d_start, d_cursor, d_perm, d_hist;  // bucketed full scan
   int64_t perm_cap = 0;
-  int32_t decide_ipt = 1;  // schedule chosen by llama_autotune
+  int32_t decide_sched = 0;  // schedule chosen by llama_autotune (llama::DecideSchedule)
+  int32_t n_cu = 256;        // compute units of the device
 
   DevTables tables() const {
     DevTables t{};
@@ -80,7 +81,8 @@ struct llama_ctx {
     t.n_pipelines = n_pipelines;
     t.hs = llama::header_stride(n_hw);
     t.n_front = n_front;
-    t.decide_ipt = decide_ipt;
+    t.decide_sched = decide_sched;
+    t.n_cu = n_cu;
     t.pipe_off = d_pipe_off.as<int32_t>();
     t.pipe_lvl = d_pipe_lvl.as<int32_t>();
     t.lvl_bnd = d_lvl_bnd.as<int32_t>();
@@ -97,6 +99,8 @@ struct llama_ctx {
     t.mst_op = d_mst_op.as<int32_t>();
     t.mst_first = d_mst_first.as<int32_t>();
     t.rec = d_rec.as<uint4>();
+    t.rec_tail = d_rec_tail.as<uint4>();
+    t.rec_tail_q = d_rec_tail_q.as<uint4>();
     t.ovf = d_ovf.as<uint2>();
     t.rec_q = d_rec_q.as<uint4>();
     t.ovf_q = d_ovf_q.as<uint2>();
@@ -113,7 +117,7 @@ struct llama_ctx {
   int64_t device_bytes() const {
     const DevBuf* all[] = {&d_pipe_off, &d_pipe_lvl, &d_lvl_bnd, &d_lvl_ops, &d_succ_off,
                            &d_succ_ids, &d_succ_q, &d_ref, &d_W, &d_hdr, &d_front_L,
-                           &d_rec, &d_ovf, &d_rec_q, &d_ovf_q, &d_seg_off, &d_tab, &d_err,
+                           &d_rec, &d_rec_tail, &d_ovf, &d_rec_q, &d_rec_tail_q, &d_ovf_q, &d_seg_off, &d_tab, &d_err,
                            &d_cnt, &d_start, &d_cursor, &d_perm, &d_hist, &d_mst, &d_mst_op,
                            &d_mst_first, &d_cfg_off, &d_cfg_hw, &d_cfg_lat, &d_cfg_key};
     int64_t s = 0;

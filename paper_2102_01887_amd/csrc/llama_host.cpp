@@ -117,6 +117,10 @@ int llama_create(llama_ctx** out, int32_t device) {
   llama_ctx* c = new (std::nothrow) llama_ctx();
   if (!c) return LLAMA_E_NOMEM;
   c->device = device;
+  {
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cu > 0) c->n_cu = cu;
+  }
   if (hipSetDevice(device) != hipSuccess ||
       hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
     delete c;
@@ -445,7 +449,7 @@ int build_tables(llama_ctx* c) {
   c->n_mst = mst_first[n_ops];
   std::vector<uint2> mst(c->n_mst);
   std::vector<int32_t> mst_op(c->n_mst);
-  std::vector<uint32_t> rec_tmpl((size_t)2 * n_ops * llama::REC_WORDS, 0);
+  std::vector<uint4> rec_hot((size_t)2 * n_ops), rec_tail((size_t)2 * n_ops * 3);
   for (int v = 0; v < n_ops; ++v) {
     const int n = (int)merged[v].size();
     for (int j = 0; j < n; ++j) {
@@ -456,12 +460,13 @@ int build_tables(llama_ctx* c) {
     w[0] = (uint32_t)n | ((uint32_t)c->fastest[v] << 16);
     for (int slot = 0; slot < llama::REC_SLOTS; ++slot) {
       const int j = n - 1 - slot;
-      w[1 + slot] = 0x7FFFFFFFu;  // thresholds: written by the GPU after relaxation
+      w[llama::rec_u_word(slot)] = 0x7FFFFFFFu;  // thresholds: written by the GPU after relaxation
       const uint32_t k = j >= 0 ? (merged[v][j].y & 0xFFFFu) : 0u;
-      w[1 + llama::REC_SLOTS + slot / 2] |= k << (16 * (slot & 1));
+      w[llama::rec_k_word(slot)] |= k << llama::rec_k_shift(slot);
     }
     for (int mode = 0; mode < 2; ++mode)
-      std::copy(w, w + llama::REC_WORDS, rec_tmpl.begin() + ((size_t)mode * n_ops + v) * llama::REC_WORDS);
+      for (int k = 0; k < llama::REC_WORDS; ++k)
+        *llama::rec_word(rec_hot.data(), rec_tail.data(), (int64_t)mode * n_ops + v, k) = w[k];
   }
   merged.clear();
 
@@ -489,12 +494,14 @@ int build_tables(llama_ctx* c) {
       (rc = upload(c, c->d_W, nullptr, sizeof(int64_t) * 2 * (size_t)n_ops, "W")) ||
       (rc = upload_vec(c, c->d_hdr, hdr, "hdr")) ||
       (rc = upload_vec(c, c->d_front_L, front_L, "front_L")) ||
-      (rc = upload_vec(c, c->d_rec, rec_tmpl, "records")) ||
+      (rc = upload_vec(c, c->d_rec, rec_hot, "records")) ||
+      (rc = upload_vec(c, c->d_rec_tail, rec_tail, "record tails")) ||
       (rc = upload_vec(c, c->d_mst, mst, "merged frontier")) ||
       (rc = upload_vec(c, c->d_mst_op, mst_op, "merged frontier ops")) ||
       (rc = upload_vec(c, c->d_mst_first, mst_first, "merged frontier offsets")) ||
       (rc = upload(c, c->d_ovf, nullptr, sizeof(uint2) * 2 * (size_t)pos, "record overflow")) ||
-      (rc = upload(c, c->d_rec_q, nullptr, (size_t)llama::REC_WORDS * 4 * n_ops, "records (queue)")) ||
+      (rc = upload(c, c->d_rec_q, nullptr, sizeof(uint4) * (size_t)n_ops, "records (queue)")) ||
+      (rc = upload(c, c->d_rec_tail_q, nullptr, sizeof(uint4) * 3 * (size_t)n_ops, "record tails (queue)")) ||
       (rc = upload(c, c->d_ovf_q, nullptr, sizeof(uint2) * (size_t)pos, "record overflow (queue)")) ||
       (rc = upload_vec(c, c->d_seg_off, seg_off, "seg_off")) ||
       (rc = upload_vec(c, c->d_cfg_off, c->cfg_off, "cfg_off")) ||
@@ -619,15 +626,16 @@ int llama_autotune(llama_ctx* c, int64_t n, const int32_t* op, const int32_t* el
   if ((rc = check_batch(c, n, op, "autotune"))) return rc;
   if (n < 1 || !elapsed || !slo || !cfg_scratch) return fail(c, LLAMA_E_ARG, "autotune: need a non-empty batch and scratch");
   hipStream_t s = (hipStream_t)stream;
-  const int cands[3] = {1, 2, 4};
+  std::vector<int> cands = {llama::SCHED_DIRECT1, llama::SCHED_DIRECT2, llama::SCHED_DIRECT4};
+  if (c->n_ops <= llama::LDS_REC_MAX_OPS) cands.push_back(llama::SCHED_LDS);
   float best = 0.0f;
-  int best_ipt = 1;
+  int best_ipt = llama::SCHED_DIRECT1;
   std::vector<int32_t> ref_out, out;
   hipEvent_t a = nullptr, b = nullptr;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return fail(c, LLAMA_E_DEVICE, "autotune events");
-  const int saved = c->decide_ipt;
-  for (int ci = 0; ci < 3; ++ci) {
-    c->decide_ipt = cands[ci];
+  const int saved = c->decide_sched;
+  for (size_t ci = 0; ci < cands.size(); ++ci) {
+    c->decide_sched = cands[ci];
     llama::Batch bt{};
     bt.n = n; bt.op = op; bt.elapsed = elapsed; bt.slo = slo; bt.cfg = cfg_scratch; bt.mode = LLAMA_SLACK_PAPER;
     hipError_t e = llama::launch_decide_indexed(c->tables(), bt, s);  // warm-up
@@ -641,14 +649,14 @@ int llama_autotune(llama_ctx* c, int64_t n, const int32_t* op, const int32_t* el
     out.resize(n);
     if (e == hipSuccess) e = hipMemcpy(out.data(), cfg_scratch, sizeof(int32_t) * n, hipMemcpyDeviceToHost);
     if (e != hipSuccess) {
-      c->decide_ipt = saved;
+      c->decide_sched = saved;
       (void)hipEventDestroy(a);
       (void)hipEventDestroy(b);
       return hip_fail(c, e, "autotune");
     }
     if (ci == 0) ref_out = out;
     else if (out != ref_out) {
-      c->decide_ipt = saved;
+      c->decide_sched = saved;
       (void)hipEventDestroy(a);
       (void)hipEventDestroy(b);
       return fail(c, LLAMA_E_DEVICE, "autotune: schedule %d changed the decisions", cands[ci]);
@@ -661,7 +669,7 @@ int llama_autotune(llama_ctx* c, int64_t n, const int32_t* op, const int32_t* el
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
-  c->decide_ipt = best_ipt;
+  c->decide_sched = best_ipt;
   if (chosen_ipt) *chosen_ipt = best_ipt;
   if (best_us) *best_us = best;
   return LLAMA_OK;

@@ -17,15 +17,32 @@ constexpr int MAX_HW = 8;
 // increasing and the configuration's cost key strictly decreasing along the
 // frontier.  The record keeps the REC_SLOTS entries with the largest T (the
 // cheapest configurations, which most invocations can afford), in descending
-// T order:
+// T order, thresholds stored as U = T - 1 (feasible iff U < slo - elapsed):
 //   word 0        entry count n (low 16 bits) | fastest configuration << 16
-//   words 1..10   T of slots 0..9 (slot 0 = largest T)
-//   words 11..15  k of slots (2j, 2j+1) as two 16-bit halves
-// The whole frontier, ascending in T, is also in the overflow array at
-// [hdr offset of the op, + n); the decision reads it only when no slot is
-// feasible and n > REC_SLOTS.
+//   words 1, 2    U of slots 0 and 1 (slot 0 = largest T)
+//   word 3        k of slots 0 and 1 (16-bit halves)
+//   words 4..11   U of slots 2..9
+//   words 12..15  k of slots (2j, 2j+1), j = 1..4
+// The first 16 bytes alone decide every invocation that can afford one of
+// the two cheapest entries, so records are stored as two arrays: the hot
+// words 0..3 (one uint4 per op) and the tail words 4..15 (three uint4 per op).
+// The whole frontier, ascending in T, is also in
+// the overflow array at [hdr offset of the op, + n); the decision reads it
+// only when no slot is feasible and n > REC_SLOTS.
 constexpr int REC_WORDS = 16;
 constexpr int REC_SLOTS = 10;
+__host__ __device__ inline constexpr int rec_u_word(int slot) { return slot < 2 ? 1 + slot : slot + 2; }
+__host__ __device__ inline constexpr int rec_k_word(int slot) { return slot < 2 ? 3 : 12 + (slot - 2) / 2; }
+__host__ __device__ inline constexpr int rec_k_shift(int slot) { return 16 * (slot & 1); }
+// Address of word w of record r (r = mode * n_ops + op) in the two arrays.
+__host__ __device__ inline uint32_t* rec_word(uint4* hot, uint4* tail, int64_t r, int w) {
+  return w < 4 ? reinterpret_cast<uint32_t*>(hot + r) + w
+               : reinterpret_cast<uint32_t*>(tail + r * 3) + (w - 4);
+}
+
+// Schedules of the indexed decision (chosen by llama_autotune).
+enum DecideSchedule { SCHED_DIRECT1 = 0, SCHED_DIRECT2 = 1, SCHED_DIRECT4 = 2, SCHED_LDS = 3 };
+constexpr int LDS_REC_MAX_OPS = 9216;  // 16 bytes per op staged in LDS (144 KB)
 
 // Stride (int32 words) of the per-op header: frontier offsets for each
 // backend (n_hw + 1 entries), then the fastest configuration, padded to a
@@ -40,7 +57,8 @@ struct DevTables {
   int32_t n_pipelines;
   int32_t hs;              // header_stride(n_hw)
   int64_t n_front;         // frontier entries (all ops, all backends)
-  int32_t decide_ipt;      // schedule: invocations per thread of the indexed decision (1, 2 or 4)
+  int32_t decide_sched;    // DecideSchedule of the indexed decision
+  int32_t n_cu;            // compute units of the device
 
   // DAG
   const int32_t* pipe_off;   // [P+1] op range of each pipeline
@@ -60,9 +78,11 @@ struct DevTables {
   const uint2* mst;          // [n_mst] {L, key}, per op ascending in L
   const int32_t* mst_op;     // [n_mst] op of each entry
   const int32_t* mst_first;  // [n_ops+1] first entry of each op
-  uint4* rec;                // [2*n_ops*4] decision records (REC_WORDS words per op), PAPER then PROB, queue = 0
+  uint4* rec;                // [2*n_ops] record words 0..3, PAPER then PROB, queue = 0
+  uint4* rec_tail;           // [2*n_ops*3] record words 4..15
   uint2* ovf;                // [2*n_front] full frontiers {T, key} ascending, PAPER then PROB
-  uint4* rec_q;              // [n_ops*4] records for a per-call queueing-time vector
+  uint4* rec_q;              // [n_ops] records for a per-call queueing-time vector
+  uint4* rec_tail_q;         // [n_ops*3]
   uint2* ovf_q;              // [n_front]
   const int32_t* cfg_off;    // [n_ops+1] caller-order configuration rows of each op
   const int32_t* cfg_hw;     // [n_cfg] backend, caller order
@@ -88,10 +108,10 @@ struct Batch {
 };
 
 hipError_t launch_relax(const DevTables& t, hipStream_t s);
-// Build records for modes [mode0, mode0 + n_modes) into rec/ovf (consecutive
-// per-mode blocks of n_ops*4 uint4 and n_front uint2).
+// Build records for modes [mode0, mode0 + n_modes) into rec/rec_tail/ovf
+// (consecutive per-mode blocks of n_ops, 3*n_ops uint4 and n_front uint2).
 hipError_t launch_records(const DevTables& t, int mode0, int n_modes, const int64_t* queue, uint4* rec,
-                          uint2* ovf, hipStream_t s);
+                          uint4* rec_tail, uint2* ovf, hipStream_t s);
 hipError_t launch_targets(const DevTables& t, const Batch& b, hipStream_t s);
 hipError_t launch_select_indexed(const DevTables& t, const Batch& b, hipStream_t s);
 hipError_t launch_decide_indexed(const DevTables& t, const Batch& b, hipStream_t s);

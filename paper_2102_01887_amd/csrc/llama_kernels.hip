@@ -170,7 +170,7 @@ __device__ __forceinline__ int wave_inclusive_scan(int x) {
 
 template <int NHW>
 __device__ __forceinline__ void build_record(const DevTables& t, int v, int mode, const int64_t* queue,
-                                             uint32_t* rw, uint2* ovf, int64_t* sT, uint32_t* sK,
+                                             uint4* rec_hot, uint4* rec_tail, int64_t rec_index, uint2* ovf, int64_t* sT, uint32_t* sK,
                                              int32_t* sC, uint32_t* sSlotT, uint32_t* sSlotK,
                                              int32_t* sN) {
   const int lane = threadIdx.x;
@@ -310,18 +310,14 @@ __device__ __forceinline__ void build_record(const DevTables& t, int v, int mode
   __syncthreads();
   if (lane < REC_WORDS) {
     const int n = *sN;
-    uint32_t word;
-    if (lane == 0) {
-      word = (uint32_t)n | ((uint32_t)hdr[NHW + 1] << 16);
-    } else if (lane <= REC_SLOTS) {
-      word = lane - 1 < n ? sSlotT[lane - 1] : 0x7FFFFFFFu;
-    } else {
-      const int s0 = 2 * (lane - 1 - REC_SLOTS);
-      const uint32_t lo = s0 < n ? sSlotK[s0] : 0u;
-      const uint32_t hi = s0 + 1 < n ? sSlotK[s0 + 1] : 0u;
-      word = lo | (hi << 16);
+    uint32_t word = 0;
+    if (lane == 0) word = (uint32_t)n | ((uint32_t)hdr[NHW + 1] << 16);
+#pragma unroll
+    for (int slot = 0; slot < REC_SLOTS; ++slot) {
+      if (lane == rec_u_word(slot)) word = slot < n ? sSlotT[slot] : 0x7FFFFFFFu;
+      if (lane == rec_k_word(slot) && slot < n) word |= sSlotK[slot] << rec_k_shift(slot);
     }
-    rw[lane] = word;
+    *rec_word(rec_hot, rec_tail, rec_index, lane) = word;
   }
   __syncthreads();  // the LDS stage is reused by the next record
 }
@@ -330,18 +326,16 @@ __device__ __forceinline__ void build_record(const DevTables& t, int v, int mode
 // modes in turn (the frontier entries stay hot in cache between modes).
 template <int NHW>
 __global__ __launch_bounds__(64) void records_kernel(DevTables t, int mode0, int n_modes, const int64_t* queue,
-                                                     uint4* rec_all, uint2* ovf_all) {
+                                                     uint4* rec_all, uint4* tail_all, uint2* ovf_all) {
   __shared__ int64_t sT[REC_LDS];
   __shared__ uint32_t sK[REC_LDS];
   __shared__ int32_t sC[REC_LDS];
   __shared__ uint32_t sSlotT[REC_SLOTS], sSlotK[REC_SLOTS];
   __shared__ int32_t sN;
   const int v = blockIdx.x;
-  for (int m = 0; m < n_modes; ++m) {
-    uint32_t* rw = reinterpret_cast<uint32_t*>(rec_all + ((int64_t)m * t.n_ops + v) * (REC_WORDS / 4));
-    build_record<NHW>(t, v, mode0 + m, queue, rw, ovf_all + (int64_t)m * t.n_front, sT, sK, sC, sSlotT,
-                      sSlotK, &sN);
-  }
+  for (int m = 0; m < n_modes; ++m)
+    build_record<NHW>(t, v, mode0 + m, queue, rec_all, tail_all, (int64_t)m * t.n_ops + v,
+                      ovf_all + (int64_t)m * t.n_front, sT, sK, sC, sSlotT, sSlotK, &sN);
 }
 
 // Queue-free records: the merged frontier of each op (which entries survive
@@ -366,10 +360,7 @@ __global__ __launch_bounds__(256) void thresholds_kernel(DevTables t) {
     const uint32_t thr = remaining_threshold(e.x, t.W[(int64_t)mode * t.n_ops + v], ref);
     const int32_t U = thr == THR_NEVER ? 0x7FFFFFFF : (int32_t)thr - 1;
     t.ovf[(int64_t)mode * t.n_front + base + pos] = make_uint2((uint32_t)U, e.y);
-    if (slot < REC_SLOTS) {
-      uint32_t* rw = reinterpret_cast<uint32_t*>(t.rec + ((int64_t)mode * t.n_ops + v) * (REC_WORDS / 4));
-      rw[1 + slot] = (uint32_t)U;
-    }
+    if (slot < REC_SLOTS) *rec_word(t.rec, t.rec_tail, (int64_t)mode * t.n_ops + v, rec_u_word(slot)) = (uint32_t)U;
   }
 }
 
@@ -462,19 +453,56 @@ __global__ __launch_bounds__(256) void select_indexed_kernel(DevTables t, Batch 
 // the record.
 // ---------------------------------------------------------------------------
 
+// Choice from a record: the first feasible slot in descending-T order (the
+// cheapest feasible frontier entry), -1 if none; *n_out = frontier length.
 __device__ __forceinline__ int record_choice(const uint4& a, const uint4& bq, const uint4& c, const uint4& d,
                                              int32_t r0, int* n_out) {
-  const uint32_t T[REC_SLOTS] = {a.y, a.z, a.w, bq.x, bq.y, bq.z, bq.w, c.x, c.y, c.z};
-  const uint32_t K2[REC_SLOTS / 2] = {c.w, d.x, d.y, d.z, d.w};
+  const uint32_t U[REC_SLOTS] = {a.y, a.z, bq.x, bq.y, bq.z, bq.w, c.x, c.y, c.z, c.w};
+  const uint32_t K2[REC_SLOTS / 2] = {a.w, d.x, d.y, d.z, d.w};
   const int n = (int)(a.x & 0xFFFFu);
   int sel = -1;
 #pragma unroll
   for (int slot = REC_SLOTS - 1; slot >= 0; --slot) {
     const int k = (int)((K2[slot >> 1] >> (16 * (slot & 1))) & 0xFFFFu);
-    if (slot < n && (int32_t)T[slot] < r0) sel = k;
+    if (slot < n && (int32_t)U[slot] < r0) sel = k;
   }
   *n_out = n;
   return sel;
+}
+
+// The rest of the decision once the record's slots are known: overflow
+// search when the frontier continues past the record, else the fallback.
+__device__ __forceinline__ int finish_choice(const DevTables& t, const uint2* ovf, int v, int sel, int n,
+                                             int32_t r0) {
+  if (sel < 0 && n > REC_SLOTS) {
+    // every slot needs more time: search the rest of the frontier (ascending)
+    const int lo0 = t.hdr[(int64_t)v * t.hs];
+    int lo = lo0, hi = lo0 + n - REC_SLOTS;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if ((int32_t)ovf[mid].x < r0) lo = mid + 1; else hi = mid;
+    }
+    if (lo > lo0) sel = (int)(ovf[lo - 1].y & 0xFFFFu);
+  }
+  return sel;
+}
+
+// Decision from the hot record words h; the tail is read only when neither
+// of the two cheapest entries is affordable and the frontier is longer.
+__device__ __forceinline__ int decide_from_record(const DevTables& t, const uint4* tail, const uint2* ovf, int v,
+                                                  const uint4& h, int32_t r0, uint8_t* flag) {
+  const int n = (int)(h.x & 0xFFFFu);
+  int sel = -1;
+  if (n > 1 && (int32_t)h.z < r0) sel = (int)(h.w >> 16);
+  if (n > 0 && (int32_t)h.y < r0) sel = (int)(h.w & 0xFFFFu);
+  if (sel < 0 && n > 2) {
+    const uint4* r = tail + (int64_t)v * 3;
+    int nn;
+    sel = record_choice(h, r[0], r[1], r[2], r0, &nn);
+    sel = finish_choice(t, ovf, v, sel, n, r0);
+  }
+  if (flag) *flag = sel >= 0 ? 1 : 0;
+  return sel >= 0 ? sel : (int)(h.x >> 16);
 }
 
 // DECIDE_IPT = invocations per thread (a schedule parameter chosen by the
@@ -482,7 +510,7 @@ __device__ __forceinline__ int record_choice(const uint4& a, const uint4& bq, co
 // size, so every load instruction stays coalesced, and issues all loads first.
 template <int DECIDE_IPT>
 __global__ __launch_bounds__(256) void decide_indexed_kernel(DevTables t, Batch b, const uint4* rec,
-                                                             const uint2* ovf) {
+                                                             const uint4* tail, const uint2* ovf) {
   const int64_t base = (int64_t)blockIdx.x * blockDim.x * DECIDE_IPT + threadIdx.x;
   int v[DECIDE_IPT], e[DECIDE_IPT], s[DECIDE_IPT];
 #pragma unroll
@@ -493,16 +521,12 @@ __global__ __launch_bounds__(256) void decide_indexed_kernel(DevTables t, Batch 
     e[u] = in ? b.elapsed[i] : 0;
     s[u] = in ? b.slo[i] : 0;
   }
-  uint4 ra[DECIDE_IPT], rb[DECIDE_IPT], rc[DECIDE_IPT], rd[DECIDE_IPT];
+  uint4 h[DECIDE_IPT];
   bool ok[DECIDE_IPT];
 #pragma unroll
   for (int u = 0; u < DECIDE_IPT; ++u) {
     ok[u] = !invalid_invocation(v[u], e[u], s[u], t.n_ops);
-    const uint4* r = rec + (int64_t)(ok[u] ? v[u] : 0) * (REC_WORDS / 4);
-    ra[u] = r[0];
-    rb[u] = r[1];
-    rc[u] = r[2];
-    rd[u] = r[3];
+    h[u] = rec[ok[u] ? v[u] : 0];
   }
 #pragma unroll
   for (int u = 0; u < DECIDE_IPT; ++u) {
@@ -515,20 +539,43 @@ __global__ __launch_bounds__(256) void decide_indexed_kernel(DevTables t, Batch 
       continue;
     }
     const int32_t r0 = s[u] - e[u];  // both non-negative: no overflow
-    int n;
-    int sel = record_choice(ra[u], rb[u], rc[u], rd[u], r0, &n);
-    if (sel < 0 && n > REC_SLOTS) {
-      // every slot needs more time: search the rest of the frontier (ascending)
-      const int lo0 = t.hdr[(int64_t)v[u] * t.hs];
-      int lo = lo0, hi = lo0 + n - REC_SLOTS;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if ((int32_t)ovf[mid].x < r0) lo = mid + 1; else hi = mid;
-      }
-      if (lo > lo0) sel = (int)(ovf[lo - 1].y & 0xFFFFu);
+    b.cfg[i] = decide_from_record(t, tail, ovf, v[u], h[u], r0, b.flag ? b.flag + i : nullptr);
+  }
+}
+
+// Persistent variant: every workgroup first stages the first 16 bytes of
+// every op's record (header, the two cheapest thresholds and their
+// configurations) in LDS; an invocation that can afford one of those two is
+// decided from LDS, any other reads its full record from global memory.
+__global__ __launch_bounds__(1024) void decide_lds_kernel(DevTables t, Batch b, const uint4* rec,
+                                                         const uint4* tail, const uint2* ovf) {
+  extern __shared__ uint4 sRec[];
+  for (int v = threadIdx.x; v < t.n_ops; v += blockDim.x) sRec[v] = rec[v];
+  __syncthreads();
+  constexpr int IPT = 4;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x * IPT;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x * IPT + threadIdx.x; base < b.n; base += stride) {
+    int v[IPT], e[IPT], s[IPT];
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      const int64_t i = base + (int64_t)u * blockDim.x;
+      const bool in = i < b.n;
+      v[u] = in ? b.op[i] : 0;
+      e[u] = in ? b.elapsed[i] : 0;
+      s[u] = in ? b.slo[i] : 0;
     }
-    b.cfg[i] = sel >= 0 ? sel : (int)(ra[u].x >> 16);
-    if (b.flag) b.flag[i] = sel >= 0 ? 1 : 0;
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      const int64_t i = base + (int64_t)u * blockDim.x;
+      if (i >= b.n) continue;
+      if (invalid_invocation(v[u], e[u], s[u], t.n_ops)) {
+        b.cfg[i] = -1;
+        if (b.flag) b.flag[i] = 0;
+        atomicOr(t.err, 1u);
+        continue;
+      }
+      b.cfg[i] = decide_from_record(t, tail, ovf, v[u], sRec[v[u]], s[u] - e[u], b.flag ? b.flag + i : nullptr);
+    }
   }
 }
 
@@ -859,9 +906,9 @@ inline unsigned blocks_for(int64_t n, int per_block) {
 }  // namespace
 
 hipError_t launch_records(const DevTables& t, int mode0, int n_modes, const int64_t* queue, uint4* rec,
-                          uint2* ovf, hipStream_t s) {
+                          uint4* rec_tail, uint2* ovf, hipStream_t s) {
   if (t.n_ops <= 0) return hipSuccess;
-  LLAMA_DISPATCH_NHW(records_kernel, dim3(t.n_ops), dim3(64), s, t, mode0, n_modes, queue, rec, ovf);
+  LLAMA_DISPATCH_NHW(records_kernel, dim3(t.n_ops), dim3(64), s, t, mode0, n_modes, queue, rec, rec_tail, ovf);
   return hipGetLastError();
 }
 
@@ -887,24 +934,41 @@ hipError_t launch_select_indexed(const DevTables& t, const Batch& b, hipStream_t
 
 hipError_t launch_decide_indexed(const DevTables& t, const Batch& b, hipStream_t s) {
   if (b.n == 0) return hipSuccess;
-  const uint4* rec = t.rec + (int64_t)b.mode * t.n_ops * (REC_WORDS / 4);
+  const uint4* rec = t.rec + (int64_t)b.mode * t.n_ops;
+  const uint4* tail = t.rec_tail + (int64_t)b.mode * t.n_ops * 3;
   const uint2* ovf = t.ovf + (int64_t)b.mode * t.n_front;
   if (b.queue) {
-    // records for this call's queueing times, in the context's own buffer
-    hipError_t e = launch_records(t, b.mode, 1, b.queue, t.rec_q, t.ovf_q, s);
+    // records for this call's queueing times, in the context's own buffers
+    hipError_t e = launch_records(t, b.mode, 1, b.queue, t.rec_q, t.rec_tail_q, t.ovf_q, s);
     if (e != hipSuccess) return e;
     rec = t.rec_q;
+    tail = t.rec_tail_q;
     ovf = t.ovf_q;
   }
-  switch (t.decide_ipt) {
-    case 2:
-      hipLaunchKernelGGL(decide_indexed_kernel<2>, dim3(blocks_for(b.n, 256 * 2)), dim3(256), 0, s, t, b, rec, ovf);
+  switch (t.decide_sched) {
+    case SCHED_LDS: {
+      if (t.n_ops > LDS_REC_MAX_OPS) return hipErrorInvalidValue;
+      const size_t lds = sizeof(uint4) * (size_t)t.n_ops;
+      hipError_t e = hipFuncSetAttribute((const void*)decide_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)(sizeof(uint4) * LDS_REC_MAX_OPS));
+      if (e != hipSuccess) return e;
+      const int64_t per_block = 1024 * 4;
+      int64_t blocks = (b.n + per_block - 1) / per_block;
+      if (blocks > t.n_cu) blocks = t.n_cu;
+      hipLaunchKernelGGL(decide_lds_kernel, dim3((unsigned)blocks), dim3(1024), lds, s, t, b, rec, tail, ovf);
       break;
-    case 4:
-      hipLaunchKernelGGL(decide_indexed_kernel<4>, dim3(blocks_for(b.n, 256 * 4)), dim3(256), 0, s, t, b, rec, ovf);
+    }
+    case SCHED_DIRECT2:
+      hipLaunchKernelGGL(decide_indexed_kernel<2>, dim3(blocks_for(b.n, 256 * 2)), dim3(256), 0, s, t, b, rec, tail,
+                         ovf);
+      break;
+    case SCHED_DIRECT4:
+      hipLaunchKernelGGL(decide_indexed_kernel<4>, dim3(blocks_for(b.n, 256 * 4)), dim3(256), 0, s, t, b, rec, tail,
+                         ovf);
       break;
     default:
-      hipLaunchKernelGGL(decide_indexed_kernel<1>, dim3(blocks_for(b.n, 256)), dim3(256), 0, s, t, b, rec, ovf);
+      hipLaunchKernelGGL(decide_indexed_kernel<1>, dim3(blocks_for(b.n, 256)), dim3(256), 0, s, t, b, rec, tail,
+                         ovf);
       break;
   }
   return hipGetLastError();

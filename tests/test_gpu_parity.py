@@ -333,3 +333,20 @@ def test_c3_full_size_sampled():
     ws = w.with_invocations(w.inv_op[idx], w.elapsed[idx], w.slo[idx])
     c_or, f_or = oracle.Problem(ws).decide(PAPER)
     assert np.array_equal(c[idx], c_or) and np.array_equal(f[idx], f_or)
+
+
+@pytest.mark.parametrize("maker", ["c2", "c3"])
+def test_autotuned_schedules_agree_with_oracle(maker):
+    # llama_autotune runs every schedule of the indexed decision (1, 2, 4
+    # invocations per thread, and the LDS-staged persistent variant when the
+    # ops fit) and fails if any two disagree; the chosen one is then checked
+    # against the oracle, so all of them are.
+    torch = _torch()
+    w = (wl.make_c2(seed=31, n_pipelines=40, n_inv=100_003) if maker == "c2"
+         else wl.make_c3(seed=32, n_pipelines=48, n_inv=50_001))
+    r = Run(w)
+    sched, us = r.L.autotune(r.op, r.el, r.slo)
+    say(f"{maker}: autotuned schedule {sched} ({us:.2f} us)")
+    c, f = r.decide(PAPER, B.SCAN_INDEXED)
+    c_or, f_or = r.P.decide(PAPER)
+    assert np.array_equal(c, c_or) and np.array_equal(f, f_or)
