@@ -243,10 +243,11 @@ int llama_select_rows(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
  * Autotuner: time every schedule of the indexed decision kernel (0, 1, 2:
  * 1, 2 or 4 invocations per thread; 3: persistent workgroups with every op's
  * first 16 record bytes staged in LDS, offered when there are at most 9,216
- * ops) on the caller's batch (device pointers; d_cfg_scratch
+ * ops; 4, 5, 6: as 0, 1, 2 with non-temporal loads of the invocations) on the
+ * caller's batch (device pointers; d_cfg_scratch
  * [n_inv] receives decisions), check that all of them give identical
  * decisions (LLAMA_E_DEVICE otherwise), and keep the fastest for this
- * context.  *chosen receives its number (0..3) and *best_us its time per launch
+ * context.  *chosen receives its number (0..6) and *best_us its time per launch
  * (either may be NULL).  Synchronous.
  */
 int llama_autotune(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,

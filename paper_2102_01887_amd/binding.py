@@ -19,7 +19,8 @@ SLACK_PAPER, SLACK_PROB = 0, 1
 SCAN_AUTO, SCAN_INDEXED, SCAN_FULL, SCAN_WAVE = 0, 1, 2, 3
 SCANS = (SCAN_INDEXED, SCAN_FULL, SCAN_WAVE)
 # decision schedules that llama_autotune chooses among (index = its *chosen)
-SCHEDULE_NAMES = ("direct-1", "direct-2", "direct-4", "lds-persistent")
+SCHEDULE_NAMES = ("direct-1", "direct-2", "direct-4", "lds-persistent", "direct-1-nt", "direct-2-nt",
+                  "direct-4-nt")
 DEVERR_INVALID_INVOCATION = 1
 
 EXPORTS = ["llama_create", "llama_destroy", "llama_last_error", "llama_set_dag",

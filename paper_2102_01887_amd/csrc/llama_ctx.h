@@ -51,10 +51,12 @@ struct llama_ctx {
   // DAG
   bool has_dag = false;
   int32_t n_pipelines = 0, n_ops = 0, max_depth = 0;
+  int32_t max_pipe_ops = 0, max_pipe_edges = 0;  // largest pipeline (ops, edges)
   int64_t n_edges = 0;
   std::vector<int32_t> pipe_off, succ_off, succ_ids, pipe_of;
   std::vector<uint32_t> succ_q;
-  DevBuf d_pipe_off, d_pipe_lvl, d_lvl_bnd, d_lvl_ops, d_succ_off, d_succ_ids, d_succ_q;
+  DevBuf d_pipe_off, d_pipe_desc, d_lvl_bnd, d_lvl_ops, d_succ_off, d_succ_ids, d_succ_q;
+  DevBuf d_lvl_edge, d_lvl_edge_q, d_lvl_ebnd;
 
   // profiles
   bool has_prof = false;
@@ -64,7 +66,7 @@ struct llama_ctx {
   std::vector<int64_t> cost;
   std::vector<uint32_t> key;  // caller order
   DevBuf d_ref, d_W, d_hdr, d_front_L, d_rec, d_rec_tail, d_ovf, d_rec_q, d_rec_tail_q, d_ovf_q, d_seg_off, d_tab;
-  DevBuf d_mst, d_mst_op, d_mst_first;
+  DevBuf d_mst, d_mst_first;
   DevBuf d_cfg_off, d_cfg_hw, d_cfg_lat, d_cfg_key;
   int64_t n_mst = 0;
   DevBuf d_err;
@@ -83,10 +85,17 @@ struct llama_ctx {
     t.n_front = n_front;
     t.decide_sched = decide_sched;
     t.n_cu = n_cu;
+    // relaxation stage: the largest pipeline, within 1024 ops / 3072 edges
+    t.relax_ops = max_pipe_ops < 1024 ? max_pipe_ops : 1024;
+    t.relax_edges = max_pipe_edges < 3072 ? max_pipe_edges : 3072;
+    t.relax_lvls = max_depth < 1024 ? max_depth : 1024;
     t.pipe_off = d_pipe_off.as<int32_t>();
-    t.pipe_lvl = d_pipe_lvl.as<int32_t>();
+    t.pipe_desc = d_pipe_desc.as<int4>();
     t.lvl_bnd = d_lvl_bnd.as<int32_t>();
     t.lvl_ops = d_lvl_ops.as<int32_t>();
+    t.lvl_edge = d_lvl_edge.as<uint32_t>();
+    t.lvl_edge_q = d_lvl_edge_q.as<uint32_t>();
+    t.lvl_ebnd = d_lvl_ebnd.as<int32_t>();
     t.succ_off = d_succ_off.as<int32_t>();
     t.succ_ids = d_succ_ids.as<int32_t>();
     t.succ_q = d_succ_q.as<uint32_t>();
@@ -96,7 +105,6 @@ struct llama_ctx {
     t.front_L = d_front_L.as<uint2>();
     t.n_mst = n_mst;
     t.mst = d_mst.as<uint2>();
-    t.mst_op = d_mst_op.as<int32_t>();
     t.mst_first = d_mst_first.as<int32_t>();
     t.rec = d_rec.as<uint4>();
     t.rec_tail = d_rec_tail.as<uint4>();
@@ -115,10 +123,10 @@ struct llama_ctx {
   }
 
   int64_t device_bytes() const {
-    const DevBuf* all[] = {&d_pipe_off, &d_pipe_lvl, &d_lvl_bnd, &d_lvl_ops, &d_succ_off,
+    const DevBuf* all[] = {&d_pipe_off, &d_pipe_desc, &d_lvl_edge, &d_lvl_edge_q, &d_lvl_ebnd, &d_lvl_bnd, &d_lvl_ops, &d_succ_off,
                            &d_succ_ids, &d_succ_q, &d_ref, &d_W, &d_hdr, &d_front_L,
                            &d_rec, &d_rec_tail, &d_ovf, &d_rec_q, &d_rec_tail_q, &d_ovf_q, &d_seg_off, &d_tab, &d_err,
-                           &d_cnt, &d_start, &d_cursor, &d_perm, &d_hist, &d_mst, &d_mst_op,
+                           &d_cnt, &d_start, &d_cursor, &d_perm, &d_hist, &d_mst,
                            &d_mst_first, &d_cfg_off, &d_cfg_hw, &d_cfg_lat, &d_cfg_key};
     int64_t s = 0;
     for (auto* b : all) s += (int64_t)b->bytes;

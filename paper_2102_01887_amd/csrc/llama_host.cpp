@@ -212,7 +212,7 @@ int llama_set_dag(llama_ctx* c, int32_t n_pipelines, const int32_t* pipe_off,
 
   // Ops of each pipeline grouped by height (outputs first).
   std::vector<int32_t> pipe_lvl(n_pipelines + 1, 0), lvl_bnd, lvl_ops(n_ops);
-  int32_t max_depth = 0;
+  int32_t max_depth = 0, max_ops = 0, max_edges = 0;
   for (int p = 0; p < n_pipelines; ++p) {
     const int a = pipe_off[p], b = pipe_off[p + 1];
     int hmax = -1;
@@ -225,13 +225,28 @@ int llama_set_dag(llama_ctx* c, int32_t n_pipelines, const int32_t* pipe_off,
     for (int v = a; v < b; ++v) lvl_ops[a + fill[height[v]]++] = v;
     pipe_lvl[p + 1] = pipe_lvl[p] + (hmax + 1);
     max_depth = std::max(max_depth, hmax + 1);
+    max_ops = std::max(max_ops, b - a);
+    max_edges = std::max(max_edges, succ_off[b] - succ_off[a]);
   }
   lvl_bnd.push_back(n_ops);
+  std::vector<int32_t> pipe_desc((size_t)8 * n_pipelines, 0);
+  for (int p = 0; p < n_pipelines; ++p) {
+    int32_t* d = &pipe_desc[(size_t)8 * p];
+    const int a = pipe_off[p], b = pipe_off[p + 1];
+    d[0] = a;
+    d[1] = b - a;
+    d[2] = succ_off[a];
+    d[3] = succ_off[b] - succ_off[a];
+    d[4] = pipe_lvl[p];
+    d[5] = pipe_lvl[p + 1] - pipe_lvl[p];
+  }
 
   c->n_pipelines = n_pipelines;
   c->n_ops = n_ops;
   c->n_edges = n_edges;
   c->max_depth = max_depth;
+  c->max_pipe_ops = max_ops;
+  c->max_pipe_edges = max_edges;
   c->pipe_off.assign(pipe_off, pipe_off + n_pipelines + 1);
   c->succ_off.assign(succ_off, succ_off + n_ops + 1);
   c->succ_ids.assign(succ_ids ? succ_ids : succ_off, succ_ids ? succ_ids + n_edges : succ_off);
@@ -239,8 +254,37 @@ int llama_set_dag(llama_ctx* c, int32_t n_pipelines, const int32_t* pipe_off,
   else c->succ_q.assign(n_edges, (uint32_t)LLAMA_Q_ONE);
   c->pipe_of.swap(pipe_of);
 
+  // Edges of each pipeline grouped by the height of their source (outputs
+  // first), endpoints as pipeline-local indices packed src | dst << 16 (read
+  // only for pipelines small enough to be relaxed in LDS), and the first edge
+  // of each level.
+  std::vector<uint32_t> lvl_edge(n_edges), lvl_edge_q(n_edges);
+  std::vector<int32_t> lvl_ebnd;
+  lvl_ebnd.reserve(lvl_bnd.size());
+  {
+    int64_t pos = 0;
+    for (int p = 0; p < n_pipelines; ++p) {
+      const int a = pipe_off[p];
+      for (int l = pipe_lvl[p]; l < pipe_lvl[p + 1]; ++l) {
+        lvl_ebnd.push_back((int32_t)pos);
+        for (int idx = lvl_bnd[l]; idx < lvl_bnd[l + 1]; ++idx) {
+          const int v = lvl_ops[idx];
+          for (int e = succ_off[v]; e < succ_off[v + 1]; ++e) {
+            lvl_edge[pos] = ((uint32_t)(v - a) & 0xFFFFu) | (((uint32_t)(succ_ids[e] - a) & 0xFFFFu) << 16);
+            lvl_edge_q[pos] = c->succ_q[e];
+            ++pos;
+          }
+        }
+      }
+    }
+    lvl_ebnd.push_back((int32_t)pos);
+  }
+
   if ((rc = upload_vec(c, c->d_pipe_off, c->pipe_off, "pipe_off")) ||
-      (rc = upload_vec(c, c->d_pipe_lvl, pipe_lvl, "pipe_lvl")) ||
+      (rc = upload_vec(c, c->d_lvl_edge, lvl_edge, "level edges")) ||
+      (rc = upload_vec(c, c->d_lvl_edge_q, lvl_edge_q, "level edge probabilities")) ||
+      (rc = upload_vec(c, c->d_lvl_ebnd, lvl_ebnd, "level edge bounds")) ||
+      (rc = upload_vec(c, c->d_pipe_desc, pipe_desc, "pipeline descriptors")) ||
       (rc = upload_vec(c, c->d_lvl_bnd, lvl_bnd, "lvl_bnd")) ||
       (rc = upload_vec(c, c->d_lvl_ops, lvl_ops, "lvl_ops")) ||
       (rc = upload_vec(c, c->d_succ_off, c->succ_off, "succ_off")) ||
@@ -448,13 +492,11 @@ int build_tables(llama_ctx* c) {
   for (int v = 0; v < n_ops; ++v) mst_first[v + 1] = mst_first[v] + (int32_t)merged[v].size();
   c->n_mst = mst_first[n_ops];
   std::vector<uint2> mst(c->n_mst);
-  std::vector<int32_t> mst_op(c->n_mst);
   std::vector<uint4> rec_hot((size_t)2 * n_ops), rec_tail((size_t)2 * n_ops * 3);
   for (int v = 0; v < n_ops; ++v) {
     const int n = (int)merged[v].size();
     for (int j = 0; j < n; ++j) {
       mst[mst_first[v] + j] = merged[v][j];
-      mst_op[mst_first[v] + j] = v;
     }
     uint32_t w[llama::REC_WORDS] = {0};
     w[0] = (uint32_t)n | ((uint32_t)c->fastest[v] << 16);
@@ -497,7 +539,6 @@ int build_tables(llama_ctx* c) {
       (rc = upload_vec(c, c->d_rec, rec_hot, "records")) ||
       (rc = upload_vec(c, c->d_rec_tail, rec_tail, "record tails")) ||
       (rc = upload_vec(c, c->d_mst, mst, "merged frontier")) ||
-      (rc = upload_vec(c, c->d_mst_op, mst_op, "merged frontier ops")) ||
       (rc = upload_vec(c, c->d_mst_first, mst_first, "merged frontier offsets")) ||
       (rc = upload(c, c->d_ovf, nullptr, sizeof(uint2) * 2 * (size_t)pos, "record overflow")) ||
       (rc = upload(c, c->d_rec_q, nullptr, sizeof(uint4) * (size_t)n_ops, "records (queue)")) ||
@@ -626,7 +667,8 @@ int llama_autotune(llama_ctx* c, int64_t n, const int32_t* op, const int32_t* el
   if ((rc = check_batch(c, n, op, "autotune"))) return rc;
   if (n < 1 || !elapsed || !slo || !cfg_scratch) return fail(c, LLAMA_E_ARG, "autotune: need a non-empty batch and scratch");
   hipStream_t s = (hipStream_t)stream;
-  std::vector<int> cands = {llama::SCHED_DIRECT1, llama::SCHED_DIRECT2, llama::SCHED_DIRECT4};
+  std::vector<int> cands = {llama::SCHED_DIRECT1, llama::SCHED_DIRECT2, llama::SCHED_DIRECT4,
+                            llama::SCHED_DIRECT1_NT, llama::SCHED_DIRECT2_NT, llama::SCHED_DIRECT4_NT};
   if (c->n_ops <= llama::LDS_REC_MAX_OPS) cands.push_back(llama::SCHED_LDS);
   float best = 0.0f;
   int best_ipt = llama::SCHED_DIRECT1;

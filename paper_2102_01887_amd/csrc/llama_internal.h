@@ -26,9 +26,9 @@ constexpr int MAX_HW = 8;
 // The first 16 bytes alone decide every invocation that can afford one of
 // the two cheapest entries, so records are stored as two arrays: the hot
 // words 0..3 (one uint4 per op) and the tail words 4..15 (three uint4 per op).
-// The whole frontier, ascending in T, is also in
-// the overflow array at [hdr offset of the op, + n); the decision reads it
-// only when no slot is feasible and n > REC_SLOTS.
+// The entries past the record (the n - REC_SLOTS smallest T), ascending in T,
+// are in the overflow array at [hdr offset of the op, + n - REC_SLOTS); the
+// decision reads them only when no slot is feasible.
 constexpr int REC_WORDS = 16;
 constexpr int REC_SLOTS = 10;
 __host__ __device__ inline constexpr int rec_u_word(int slot) { return slot < 2 ? 1 + slot : slot + 2; }
@@ -40,8 +40,13 @@ __host__ __device__ inline uint32_t* rec_word(uint4* hot, uint4* tail, int64_t r
                : reinterpret_cast<uint32_t*>(tail + r * 3) + (w - 4);
 }
 
-// Schedules of the indexed decision (chosen by llama_autotune).
-enum DecideSchedule { SCHED_DIRECT1 = 0, SCHED_DIRECT2 = 1, SCHED_DIRECT4 = 2, SCHED_LDS = 3 };
+// Schedules of the indexed decision (chosen by llama_autotune): 1, 2 or 4
+// invocations per thread, LDS-staged hot records, and the direct schedules
+// with non-temporal loads of the invocation stream.
+enum DecideSchedule {
+  SCHED_DIRECT1 = 0, SCHED_DIRECT2 = 1, SCHED_DIRECT4 = 2, SCHED_LDS = 3,
+  SCHED_DIRECT1_NT = 4, SCHED_DIRECT2_NT = 5, SCHED_DIRECT4_NT = 6
+};
 constexpr int LDS_REC_MAX_OPS = 9216;  // 16 bytes per op staged in LDS (144 KB)
 
 // Stride (int32 words) of the per-op header: frontier offsets for each
@@ -59,15 +64,21 @@ struct DevTables {
   int64_t n_front;         // frontier entries (all ops, all backends)
   int32_t decide_sched;    // DecideSchedule of the indexed decision
   int32_t n_cu;            // compute units of the device
+  // LDS capacities of the relaxation (ops, edges, levels of one pipeline);
+  // larger pipelines are relaxed in global memory
+  int32_t relax_ops, relax_edges, relax_lvls;
 
   // DAG
   const int32_t* pipe_off;   // [P+1] op range of each pipeline
-  const int32_t* pipe_lvl;   // [P+1] range of each pipeline's levels in lvl_bnd
+  const int4* pipe_desc;     // [2*P] {first op, ops, first edge, edges}, {first level in lvl_bnd, levels, 0, 0}
   const int32_t* lvl_bnd;    // [n_levels+1] start of each level in lvl_ops
   const int32_t* lvl_ops;    // [n_ops] ops ordered by pipeline, then height (outputs first)
   const int32_t* succ_off;   // [n_ops+1]
   const int32_t* succ_ids;   // [n_edges]
   const uint32_t* succ_q;    // [n_edges] Q16 branch probability
+  const uint32_t* lvl_edge;  // [n_edges] per pipeline, by source height: src | dst << 16 (pipeline-local)
+  const uint32_t* lvl_edge_q;  // [n_edges] Q16 branch probability of lvl_edge
+  const int32_t* lvl_ebnd;   // [n_levels+1] first lvl_edge of each level
 
   // profiles
   const int32_t* ref;        // [n_ops] reference-configuration latency
@@ -76,7 +87,6 @@ struct DevTables {
   const uint2* front_L;      // [n_front] {latency, key}: per (op, backend), latency ascending, key strictly descending
   int64_t n_mst;              // entries of the queue-free merged frontiers (all ops)
   const uint2* mst;          // [n_mst] {L, key}, per op ascending in L
-  const int32_t* mst_op;     // [n_mst] op of each entry
   const int32_t* mst_first;  // [n_ops+1] first entry of each op
   uint4* rec;                // [2*n_ops] record words 0..3, PAPER then PROB, queue = 0
   uint4* rec_tail;           // [2*n_ops*3] record words 4..15

@@ -55,61 +55,211 @@ __device__ __forceinline__ uint32_t remaining_threshold(uint32_t L, int64_t W, i
 
 // ---------------------------------------------------------------------------
 // Relaxation: one workgroup per pipeline, levels from the outputs upward.
-// A pipeline's ops, edges and level lists are staged in LDS when they fit;
-// otherwise the same recurrence runs on global memory.
+// When a pipeline fits the LDS stage (sized at launch for the largest one),
+// its reference latencies and its edges, grouped by the level of their
+// source, are staged in LDS and each level is one pass with a lane per edge
+// that folds the successor's W into the source's accumulator by LDS atomic
+// max (max is order-free, so the result is exact); otherwise the op-parallel
+// form of the same recurrence runs on global memory.  op_records_kernel then
+// writes the queue-free decision records, one thread per op.
 // ---------------------------------------------------------------------------
-constexpr int RELAX_MAX_OPS = 1024;
-constexpr int RELAX_MAX_EDGES = 3072;
-
 __device__ __forceinline__ int64_t branch_discount(uint32_t q, int64_t w) {
   return (int64_t)(((uint64_t)q * (uint64_t)w) >> 16);
 }
 
+// Bytes of dynamic LDS that relax_kernel needs for the given capacities.
+size_t relax_lds_bytes(const DevTables& t) {
+  return sizeof(uint64_t) * 2 * (size_t)t.relax_ops +
+         sizeof(int32_t) * ((size_t)t.relax_ops + 2 * (size_t)t.relax_edges + (size_t)t.relax_lvls + 1);
+}
+
+// Exact thresholds of one (op, slack mode).  The stored threshold of an
+// entry with latency L is U = T - 1, T = ceil(y), y = (L + 1) * W / ref, or
+// INT32_MAX when T > 2^31 - 1 (no remaining time reaches it).
+//   * T > 2^31 - 1 iff (L + 1) * W > ref * (2^31 - 1) iff L + 1 > cutoff =
+//     floor(ref * (2^31 - 1) / W), computed exactly once per op.
+//   * Otherwise y < 2^31 and x = fl(fl(L + 1) * fl(fl(W) / ref)) carries three
+//     roundings of relative size 2^-53, so |x - y| < 2^31 * 3 * 2^-53 < 2^-20.
+//     When x is at least 2^-19 away from every integer, y is not an integer
+//     and floor(y) = floor(x), so U = T - 1 = floor(x).
+//   * Near an integer, the exact path: the numerator (L + 1) * W + ref - 1 is
+//     below 2^62 and the quotient below 2^31, so an FP64 estimate is off by
+//     at most one and one exact remainder step corrects it.
+struct OpScale {
+  uint32_t cut32;   // min(cutoff, 2^32 - 1); L + 1 <= 2^31 always
+  int64_t W;
+  int64_t ref;
+  double scale;     // fl(fl(W) / ref)
+  double inv_ref;
+};
+
+__device__ __forceinline__ OpScale op_scale(int64_t W, int32_t ref) {
+  OpScale o;
+  const uint64_t lim = (uint64_t)ref * (uint64_t)INT32_MAX_64;
+  const uint64_t cutoff = ((unsigned __int128)(uint64_t)W << 32) <= (unsigned __int128)lim
+                              ? 0xFFFFFFFFull
+                              : (uint64_t)div_floor_pos((int64_t)lim, W);
+  o.cut32 = (uint32_t)(cutoff < 0xFFFFFFFFull ? cutoff : 0xFFFFFFFFull);
+  o.W = W;
+  o.ref = ref;
+  o.scale = (double)W / (double)ref;
+  o.inv_ref = 1.0 / (double)ref;
+  return o;
+}
+
+__device__ __forceinline__ uint32_t entry_threshold_exact(const OpScale& o, uint32_t l1) {
+  const int64_t num = (int64_t)((uint64_t)l1 * (uint64_t)o.W) + o.ref - 1;
+  int64_t q = (int64_t)(uint32_t)((double)num * o.inv_ref);  // estimate below 2^31 + 1
+  const int64_t r = num - q * o.ref;
+  q += r < 0 ? -1 : (r >= o.ref ? 1 : 0);
+  return (uint32_t)q - 1u;  // q = T >= 1
+}
+
+__device__ __forceinline__ uint32_t entry_threshold(const OpScale& o, uint32_t L) {
+  const uint32_t l1 = L + 1u;
+  if (l1 > o.cut32) return 0x7FFFFFFFu;
+  const double x = (double)l1 * o.scale;
+  const double fl = floor(x);
+  const double fr = x - fl;
+  if (fr >= 0x1p-19 && fr <= 1.0 - 0x1p-19) return (uint32_t)fl;
+  return entry_threshold_exact(o, l1);
+}
+
+// Queue-free records of op v, both slack modes.  The merged frontier of an
+// op (which entries survive and their order) depends only on latencies,
+// because every threshold of an op is the same increasing function of L;
+// ingest fixes it in mst, and only the thresholds change with W.  Record
+// words are assembled in registers and written as whole 16-byte chunks;
+// entries past the record go to the overflow array, ascending.
+__device__ __forceinline__ void write_op_records(const DevTables& t, int v) {
+  const int first = t.mst_first[v];
+  const int n = t.mst_first[v + 1] - first;
+  const int32_t* hdr = t.hdr + (int64_t)v * t.hs;
+  const int base = hdr[0];
+  const uint32_t fastest = (uint32_t)hdr[t.n_hw + 1];
+  const int32_t ref = t.ref[v];
+  const int64_t Wm[2] = {t.W[v], t.W[(int64_t)t.n_ops + v]};
+  if (n <= 0) return;  // every op has at least its fastest configuration
+  // all slot entries are loaded before any store (the stores could alias);
+  // the loads are unconditional (clamped index) so that they issue together
+  uint2 e[REC_SLOTS];
+#pragma unroll
+  for (int slot = 0; slot < REC_SLOTS; ++slot) {
+    const int j = n - 1 - slot;
+    e[slot] = t.mst[first + (j > 0 ? j : 0)];
+  }
+  const int n_ovf = n - REC_SLOTS;
+#pragma unroll
+  for (int mode = 0; mode < 2; ++mode) {
+    const OpScale o = op_scale(Wm[mode], ref);
+    uint32_t w[REC_WORDS];
+#pragma unroll
+    for (int k = 0; k < REC_WORDS; ++k) w[k] = 0;
+    w[0] = (uint32_t)n | (fastest << 16);
+#pragma unroll
+    for (int slot = 0; slot < REC_SLOTS; ++slot) {
+      const bool used = slot < n;
+      w[rec_u_word(slot)] = used ? entry_threshold(o, e[slot].x) : 0x7FFFFFFFu;
+      w[rec_k_word(slot)] |= (used ? e[slot].y & 0xFFFFu : 0u) << rec_k_shift(slot);
+    }
+    const int64_t r = (int64_t)mode * t.n_ops + v;
+    t.rec[r] = make_uint4(w[0], w[1], w[2], w[3]);
+    uint4* tl = t.rec_tail + r * 3;
+    tl[0] = make_uint4(w[4], w[5], w[6], w[7]);
+    tl[1] = make_uint4(w[8], w[9], w[10], w[11]);
+    tl[2] = make_uint4(w[12], w[13], w[14], w[15]);
+    // entries past the record, ascending, four loads in flight at a time
+    uint2* ovf = t.ovf + (int64_t)mode * t.n_front + base;
+    for (int pos = 0; pos < n_ovf; pos += 4) {
+      uint2 x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[u] = t.mst[first + (pos + u < n_ovf ? pos + u : n_ovf - 1)];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (pos + u >= n_ovf) break;
+        ovf[pos + u] = make_uint2(entry_threshold(o, x[u].x), x[u].y);
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(64) void relax_kernel(DevTables t) {
-  __shared__ int64_t sWP[RELAX_MAX_OPS], sWQ[RELAX_MAX_OPS];
-  __shared__ int32_t sRef[RELAX_MAX_OPS], sOff[RELAX_MAX_OPS + 1];
-  __shared__ int32_t sLvl[RELAX_MAX_OPS], sBnd[RELAX_MAX_OPS + 1];
-  __shared__ int32_t sSucc[RELAX_MAX_EDGES];
-  __shared__ uint32_t sQ[RELAX_MAX_EDGES];
+  extern __shared__ uint64_t sDyn[];
+  const int cap_ops = t.relax_ops, cap_edges = t.relax_edges, cap_lvls = t.relax_lvls;
+  // W[v] = ref[v] + acc[v]: acc is the largest successor term, built level by
+  // level with LDS atomic max over the edges of the level (one lane per edge)
+  uint64_t* sAccP = sDyn;
+  uint64_t* sAccQ = sAccP + cap_ops;
+  int32_t* sRef = reinterpret_cast<int32_t*>(sAccQ + cap_ops);  // cap_ops
+  uint32_t* sE = reinterpret_cast<uint32_t*>(sRef + cap_ops);    // cap_edges
+  uint32_t* sEq = sE + cap_edges;                                // cap_edges
+  int32_t* sEb = reinterpret_cast<int32_t*>(sEq + cap_edges);     // cap_lvls + 1
   const int p = blockIdx.x;
   const int tid = threadIdx.x, bs = blockDim.x;
   const int n_ops = t.n_ops;
-  const int a = t.pipe_off[p], n = t.pipe_off[p + 1] - a;
-  const int e0 = t.succ_off[a], ne = t.succ_off[a + n] - e0;
-  const int l0 = t.pipe_lvl[p], nl = t.pipe_lvl[p + 1] - l0;
+  const int4 d0 = t.pipe_desc[2 * p], d1 = t.pipe_desc[2 * p + 1];
+  const int a = d0.x, n = d0.y, e0 = d0.z, ne = d0.w;
+  const int l0 = d1.x, nl = d1.y;
   int64_t* WP = t.W;
   int64_t* WQ = t.W + n_ops;
-  if (n <= RELAX_MAX_OPS && ne <= RELAX_MAX_EDGES) {
-    for (int i = tid; i < n; i += bs) {
-      sRef[i] = t.ref[a + i];
-      sOff[i] = t.succ_off[a + i] - e0;
-      sLvl[i] = t.lvl_ops[a + i] - a;
-    }
-    for (int i = tid; i <= nl; i += bs) sBnd[i] = t.lvl_bnd[l0 + i] - a;
-    for (int i = tid; i < ne; i += bs) {
-      sSucc[i] = t.succ_ids[e0 + i] - a;
-      sQ[i] = t.succ_q[e0 + i];
-    }
-    if (tid == 0) sOff[n] = ne;
-    __syncthreads();
-    for (int l = 0; l < nl; ++l) {
-      for (int idx = sBnd[l] + tid; idx < sBnd[l + 1]; idx += bs) {
-        const int v = sLvl[idx];
-        int64_t mp = 0, mq = 0;
-        for (int e = sOff[v]; e < sOff[v + 1]; ++e) {
-          const int w = sSucc[e];
-          const int64_t wp = sWP[w], wq = branch_discount(sQ[e], sWQ[w]);
-          mp = wp > mp ? wp : mp;
-          mq = wq > mq ? wq : mq;
+  const bool staged = n <= cap_ops && ne <= cap_edges && nl <= cap_lvls;
+  if (staged) {
+    // staging: RELAX_BATCH loads per lane in flight (clamped indices, so the
+    // loads are unconditional and issue together)
+    constexpr int RELAX_BATCH = 8;
+    for (int i0 = 0; i0 < n; i0 += RELAX_BATCH * bs) {
+      int r[RELAX_BATCH];
+#pragma unroll
+      for (int u = 0; u < RELAX_BATCH; ++u) {
+        const int i = i0 + u * bs + tid;
+        r[u] = t.ref[a + (i < n ? i : n - 1)];
+      }
+#pragma unroll
+      for (int u = 0; u < RELAX_BATCH; ++u) {
+        const int i = i0 + u * bs + tid;
+        if (i < n) {
+          sRef[i] = r[u];
+          sAccP[i] = 0;
+          sAccQ[i] = 0;
         }
-        sWP[v] = sRef[v] + mp;
-        sWQ[v] = sRef[v] + mq;
+      }
+    }
+    for (int i0 = 0; i0 < ne; i0 += RELAX_BATCH * bs) {
+      uint32_t pk[RELAX_BATCH], q[RELAX_BATCH];
+#pragma unroll
+      for (int u = 0; u < RELAX_BATCH; ++u) {
+        const int i = i0 + u * bs + tid;
+        const int g = e0 + (i < ne ? i : ne - 1);
+        pk[u] = t.lvl_edge[g];
+        q[u] = t.lvl_edge_q[g];
+      }
+#pragma unroll
+      for (int u = 0; u < RELAX_BATCH; ++u) {
+        const int i = i0 + u * bs + tid;
+        if (i < ne) {
+          sE[i] = pk[u];
+          sEq[i] = q[u];
+        }
+      }
+    }
+    for (int i = tid; i <= nl; i += bs) sEb[i] = t.lvl_ebnd[l0 + i] - e0;
+    __syncthreads();
+    // level 0 (the outputs) has no outgoing edges
+    for (int l = 1; l < nl; ++l) {
+      for (int idx = sEb[l] + tid; idx < sEb[l + 1]; idx += bs) {
+        const uint32_t pk = sE[idx];
+        const int src = (int)(pk & 0xFFFFu), dst = (int)(pk >> 16);
+        const int64_t ref = sRef[dst];
+        const uint64_t wp = (uint64_t)(ref + (int64_t)sAccP[dst]);
+        const uint64_t wq = (uint64_t)branch_discount(sEq[idx], ref + (int64_t)sAccQ[dst]);
+        atomicMax((unsigned long long*)&sAccP[src], (unsigned long long)wp);
+        atomicMax((unsigned long long*)&sAccQ[src], (unsigned long long)wq);
       }
       __syncthreads();
     }
     for (int i = tid; i < n; i += bs) {
-      WP[a + i] = sWP[i];
-      WQ[a + i] = sWQ[i];
+      WP[a + i] = sRef[i] + (int64_t)sAccP[i];
+      WQ[a + i] = sRef[i] + (int64_t)sAccQ[i];
     }
     return;
   }
@@ -130,6 +280,12 @@ __global__ __launch_bounds__(64) void relax_kernel(DevTables t) {
     }
     __syncthreads();
   }
+}
+
+// One thread per op: its records (both slack modes) from the relaxed W.
+__global__ __launch_bounds__(256) void op_records_kernel(DevTables t) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < t.n_ops) write_op_records(t, v);
 }
 
 // ---------------------------------------------------------------------------
@@ -338,32 +494,6 @@ __global__ __launch_bounds__(64) void records_kernel(DevTables t, int mode0, int
                       ovf_all + (int64_t)m * t.n_front, sT, sK, sC, sSlotT, sSlotK, &sN);
 }
 
-// Queue-free records: the merged frontier of each op (which entries survive
-// and their order) depends only on latencies, because every threshold of an
-// op is the same increasing function of L.  Ingest fixes that structure and
-// the record's static words; after each relaxation one thread per merged
-// entry writes its threshold for both slack modes into the record slot and
-// the ascending overflow copy.
-__global__ __launch_bounds__(256) void thresholds_kernel(DevTables t) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= t.n_mst) return;
-  const int v = t.mst_op[j];
-  const int first = t.mst_first[v];
-  const int n = t.mst_first[v + 1] - first;
-  const int pos = (int)(j - first);
-  const int slot = n - 1 - pos;
-  const uint2 e = t.mst[j];  // {L, key}
-  const int32_t ref = t.ref[v];
-  const int base = t.hdr[(int64_t)v * t.hs];
-#pragma unroll
-  for (int mode = 0; mode < 2; ++mode) {
-    const uint32_t thr = remaining_threshold(e.x, t.W[(int64_t)mode * t.n_ops + v], ref);
-    const int32_t U = thr == THR_NEVER ? 0x7FFFFFFF : (int32_t)thr - 1;
-    t.ovf[(int64_t)mode * t.n_front + base + pos] = make_uint2((uint32_t)U, e.y);
-    if (slot < REC_SLOTS) *rec_word(t.rec, t.rec_tail, (int64_t)mode * t.n_ops + v, rec_u_word(slot)) = (uint32_t)U;
-  }
-}
-
 __device__ __forceinline__ bool invalid_invocation(int v, int e, int s, int n_ops) {
   return (unsigned)v >= (unsigned)n_ops || (e | s) < 0;
 }
@@ -490,7 +620,7 @@ __device__ __forceinline__ int finish_choice(const DevTables& t, const uint2* ov
 // Decision from the hot record words h; the tail is read only when neither
 // of the two cheapest entries is affordable and the frontier is longer.
 __device__ __forceinline__ int decide_from_record(const DevTables& t, const uint4* tail, const uint2* ovf, int v,
-                                                  const uint4& h, int32_t r0, uint8_t* flag) {
+                                                  const uint4& h, int32_t r0, uint8_t* feasible) {
   const int n = (int)(h.x & 0xFFFFu);
   int sel = -1;
   if (n > 1 && (int32_t)h.z < r0) sel = (int)(h.w >> 16);
@@ -501,26 +631,41 @@ __device__ __forceinline__ int decide_from_record(const DevTables& t, const uint
     sel = record_choice(h, r[0], r[1], r[2], r0, &nn);
     sel = finish_choice(t, ovf, v, sel, n, r0);
   }
-  if (flag) *flag = sel >= 0 ? 1 : 0;
+  *feasible = sel >= 0 ? 1 : 0;
   return sel >= 0 ? sel : (int)(h.x >> 16);
+}
+
+__device__ __forceinline__ void store_decision(const Batch& b, int64_t i, int cfg, uint8_t feasible) {
+  b.cfg[i] = cfg;
+  if (b.flag) b.flag[i] = feasible;
+}
+
+// The invocation stream is read once; with NT its loads carry the
+// non-temporal hint, so that they need not displace decision records in L2.
+template <bool NT>
+__device__ __forceinline__ void load_invocation(const Batch& b, int64_t i, int* v, int* e, int* s) {
+  const bool in = i < b.n;
+  if (NT) {
+    *v = in ? __builtin_nontemporal_load(b.op + i) : 0;
+    *e = in ? __builtin_nontemporal_load(b.elapsed + i) : 0;
+    *s = in ? __builtin_nontemporal_load(b.slo + i) : 0;
+  } else {
+    *v = in ? b.op[i] : 0;
+    *e = in ? b.elapsed[i] : 0;
+    *s = in ? b.slo[i] : 0;
+  }
 }
 
 // DECIDE_IPT = invocations per thread (a schedule parameter chosen by the
 // autotuner): each thread decides DECIDE_IPT invocations spaced by the block
 // size, so every load instruction stays coalesced, and issues all loads first.
-template <int DECIDE_IPT>
+template <int DECIDE_IPT, bool NT>
 __global__ __launch_bounds__(256) void decide_indexed_kernel(DevTables t, Batch b, const uint4* rec,
                                                              const uint4* tail, const uint2* ovf) {
   const int64_t base = (int64_t)blockIdx.x * blockDim.x * DECIDE_IPT + threadIdx.x;
   int v[DECIDE_IPT], e[DECIDE_IPT], s[DECIDE_IPT];
 #pragma unroll
-  for (int u = 0; u < DECIDE_IPT; ++u) {
-    const int64_t i = base + (int64_t)u * blockDim.x;
-    const bool in = i < b.n;
-    v[u] = in ? b.op[i] : 0;
-    e[u] = in ? b.elapsed[i] : 0;
-    s[u] = in ? b.slo[i] : 0;
-  }
+  for (int u = 0; u < DECIDE_IPT; ++u) load_invocation<NT>(b, base + (int64_t)u * blockDim.x, &v[u], &e[u], &s[u]);
   uint4 h[DECIDE_IPT];
   bool ok[DECIDE_IPT];
 #pragma unroll
@@ -533,13 +678,14 @@ __global__ __launch_bounds__(256) void decide_indexed_kernel(DevTables t, Batch 
     const int64_t i = base + (int64_t)u * blockDim.x;
     if (i >= b.n) continue;
     if (!ok[u]) {
-      b.cfg[i] = -1;
-      if (b.flag) b.flag[i] = 0;
+      store_decision(b, i, -1, 0);
       atomicOr(t.err, 1u);
       continue;
     }
     const int32_t r0 = s[u] - e[u];  // both non-negative: no overflow
-    b.cfg[i] = decide_from_record(t, tail, ovf, v[u], h[u], r0, b.flag ? b.flag + i : nullptr);
+    uint8_t f;
+    const int c = decide_from_record(t, tail, ovf, v[u], h[u], r0, &f);
+    store_decision(b, i, c, f);
   }
 }
 
@@ -557,24 +703,19 @@ __global__ __launch_bounds__(1024) void decide_lds_kernel(DevTables t, Batch b, 
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x * IPT + threadIdx.x; base < b.n; base += stride) {
     int v[IPT], e[IPT], s[IPT];
 #pragma unroll
-    for (int u = 0; u < IPT; ++u) {
-      const int64_t i = base + (int64_t)u * blockDim.x;
-      const bool in = i < b.n;
-      v[u] = in ? b.op[i] : 0;
-      e[u] = in ? b.elapsed[i] : 0;
-      s[u] = in ? b.slo[i] : 0;
-    }
+    for (int u = 0; u < IPT; ++u) load_invocation<false>(b, base + (int64_t)u * blockDim.x, &v[u], &e[u], &s[u]);
 #pragma unroll
     for (int u = 0; u < IPT; ++u) {
       const int64_t i = base + (int64_t)u * blockDim.x;
       if (i >= b.n) continue;
       if (invalid_invocation(v[u], e[u], s[u], t.n_ops)) {
-        b.cfg[i] = -1;
-        if (b.flag) b.flag[i] = 0;
+        store_decision(b, i, -1, 0);
         atomicOr(t.err, 1u);
         continue;
       }
-      b.cfg[i] = decide_from_record(t, tail, ovf, v[u], sRec[v[u]], s[u] - e[u], b.flag ? b.flag + i : nullptr);
+      uint8_t f;
+      const int c = decide_from_record(t, tail, ovf, v[u], sRec[v[u]], s[u] - e[u], &f);
+      store_decision(b, i, c, f);
     }
   }
 }
@@ -914,9 +1055,8 @@ hipError_t launch_records(const DevTables& t, int mode0, int n_modes, const int6
 
 hipError_t launch_relax(const DevTables& t, hipStream_t s) {
   if (t.n_pipelines <= 0) return hipSuccess;
-  hipLaunchKernelGGL(relax_kernel, dim3(t.n_pipelines), dim3(64), 0, s, t);
-  if (t.n_mst > 0)
-    hipLaunchKernelGGL(thresholds_kernel, dim3(blocks_for(t.n_mst, 256)), dim3(256), 0, s, t);
+  hipLaunchKernelGGL(relax_kernel, dim3(t.n_pipelines), dim3(64), relax_lds_bytes(t), s, t);
+  if (t.n_ops > 0) hipLaunchKernelGGL(op_records_kernel, dim3(blocks_for(t.n_ops, 256)), dim3(256), 0, s, t);
   return hipGetLastError();
 }
 
@@ -958,18 +1098,16 @@ hipError_t launch_decide_indexed(const DevTables& t, const Batch& b, hipStream_t
       hipLaunchKernelGGL(decide_lds_kernel, dim3((unsigned)blocks), dim3(1024), lds, s, t, b, rec, tail, ovf);
       break;
     }
-    case SCHED_DIRECT2:
-      hipLaunchKernelGGL(decide_indexed_kernel<2>, dim3(blocks_for(b.n, 256 * 2)), dim3(256), 0, s, t, b, rec, tail,
-                         ovf);
-      break;
-    case SCHED_DIRECT4:
-      hipLaunchKernelGGL(decide_indexed_kernel<4>, dim3(blocks_for(b.n, 256 * 4)), dim3(256), 0, s, t, b, rec, tail,
-                         ovf);
-      break;
-    default:
-      hipLaunchKernelGGL(decide_indexed_kernel<1>, dim3(blocks_for(b.n, 256)), dim3(256), 0, s, t, b, rec, tail,
-                         ovf);
-      break;
+#define LLAMA_DIRECT(IPT, NT) \
+  hipLaunchKernelGGL((decide_indexed_kernel<IPT, NT>), dim3(blocks_for(b.n, 256 * IPT)), dim3(256), 0, s, t, b, rec, \
+                     tail, ovf)
+    case SCHED_DIRECT2: LLAMA_DIRECT(2, false); break;
+    case SCHED_DIRECT4: LLAMA_DIRECT(4, false); break;
+    case SCHED_DIRECT1_NT: LLAMA_DIRECT(1, true); break;
+    case SCHED_DIRECT2_NT: LLAMA_DIRECT(2, true); break;
+    case SCHED_DIRECT4_NT: LLAMA_DIRECT(4, true); break;
+    default: LLAMA_DIRECT(1, false); break;
+#undef LLAMA_DIRECT
   }
   return hipGetLastError();
 }

@@ -338,8 +338,9 @@ def test_c3_full_size_sampled():
 @pytest.mark.parametrize("maker", ["c2", "c3"])
 def test_autotuned_schedules_agree_with_oracle(maker):
     # llama_autotune runs every schedule of the indexed decision (1, 2, 4
-    # invocations per thread, and the LDS-staged persistent variant when the
-    # ops fit) and fails if any two disagree; the chosen one is then checked
+    # invocations per thread with plain or non-temporal input loads, and the
+    # LDS-staged persistent variant when the ops fit) and fails if any two
+    # disagree; the chosen one is then checked
     # against the oracle, so all of them are.
     torch = _torch()
     w = (wl.make_c2(seed=31, n_pipelines=40, n_inv=100_003) if maker == "c2"
