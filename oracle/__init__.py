@@ -51,8 +51,15 @@ def load(path):
     L.oracle_decide.argtypes = [i64, p, p, p, i32, p, i32, p, p, p, p, p,
                                 p, p, p, p, p]
     L.oracle_select_lat.argtypes = [i64, p, p, i32, i32, p, p, p, p, i64, p, p, p]
+    L.oracle_queue_time.argtypes = [i64, p, p, i32, i32, p, p, p, p, p, p, p]
+    u32 = ctypes.c_uint32
+    L.oracle_select_alpha.argtypes = [i64, p, p, i32, i32, p, p, p, p, p, p, p, u32, u32, p, p]
+    L.oracle_decide_alpha.argtypes = [i64, p, p, p, i32, p, i32, p, p, p, p, p, p, p, p, p,
+                                      u32, u32, p, p, p]
+    L.oracle_fraction_below.argtypes = [p, p, p, p]
     for f in (L.oracle_reference_cfg, L.oracle_worst_path, L.oracle_targets,
-              L.oracle_select, L.oracle_decide, L.oracle_select_lat):
+              L.oracle_select, L.oracle_decide, L.oracle_select_lat, L.oracle_queue_time,
+              L.oracle_select_alpha, L.oracle_decide_alpha, L.oracle_fraction_below):
         f.restype = ctypes.c_int
     return L
 
@@ -201,6 +208,68 @@ def decide(inv_op, elapsed, slo, n_hw, Q, ref_lat, W, cfg_off, hw, batch, lat, c
     return cfg, flag
 
 
+def queue_time(q_op, q_cfg, n_hw, cfg_off, hw, res, lat, r_total):
+    """Eq. 2 per backend from the queued invocations' (op, configuration);
+    returns (Q int64 [n_hw], number of skipped out-of-range entries)."""
+    q_op, q_cfg = _arr(q_op, np.int32), _arr(q_cfg, np.int32)
+    cfg_off = _arr(cfg_off, np.int32)
+    hw, res, lat = (_arr(x, np.int32) for x in (hw, res, lat))
+    r_total = _arr(r_total, np.int64)
+    Q = np.empty(n_hw, np.int64)
+    skipped = ctypes.c_int64()
+    _check("oracle_queue_time",
+           lib().oracle_queue_time(len(q_op), _ptr(q_op), _ptr(q_cfg), n_hw, len(cfg_off) - 1,
+                                   _ptr(cfg_off), _ptr(hw), _ptr(res), _ptr(lat), _ptr(r_total),
+                                   _ptr(Q), ctypes.byref(skipped)))
+    return Q, skipped.value
+
+
+def fraction_below(n1, d1, n2, d2):
+    """n1/d1 < n2/d2 as the oracle decides it (operands below 2^128)."""
+    limbs = [np.array([x & (2**64 - 1), x >> 64], np.uint64) for x in (n1, d1, n2, d2)]
+    return bool(lib().oracle_fraction_below(*(_ptr(a) for a in limbs)))
+
+
+def select_alpha(inv_op, target, n_hw, cfg_off, hw, batch, res, lat, cost, r_total,
+                 alpha_num, alpha_den):
+    """Eq. 1 with the finite weight alpha = alpha_num / alpha_den."""
+    inv_op = _arr(inv_op, np.int32)
+    n = len(inv_op)
+    target = _arr(target, np.int32).reshape(n, n_hw)
+    cfg_off = _arr(cfg_off, np.int32)
+    hw, batch, res, lat = (_arr(x, np.int32) for x in (hw, batch, res, lat))
+    cost, r_total = _arr(cost, np.int64), _arr(r_total, np.int64)
+    cfg = np.empty(n, np.int32)
+    flag = np.empty(n, np.uint8)
+    _check("oracle_select_alpha",
+           lib().oracle_select_alpha(n, _ptr(inv_op), _ptr(target), n_hw, len(cfg_off) - 1,
+                                     _ptr(cfg_off), _ptr(hw), _ptr(batch), _ptr(res), _ptr(lat),
+                                     _ptr(cost), _ptr(r_total), alpha_num, alpha_den,
+                                     _ptr(cfg), _ptr(flag)))
+    return cfg, flag
+
+
+def decide_alpha(inv_op, elapsed, slo, n_hw, Q, ref_lat, W, cfg_off, hw, batch, res, lat, cost,
+                 r_total, alpha_num, alpha_den):
+    inv_op, elapsed, slo = (_arr(x, np.int32) for x in (inv_op, elapsed, slo))
+    n = len(inv_op)
+    Q = _arr(Q, np.int64)
+    ref = _arr(ref_lat, np.int64)
+    Wa = _arr(W, np.int64)
+    cfg_off = _arr(cfg_off, np.int32)
+    hw, batch, res, lat = (_arr(x, np.int32) for x in (hw, batch, res, lat))
+    cost, r_total = _arr(cost, np.int64), _arr(r_total, np.int64)
+    cfg = np.empty(n, np.int32)
+    flag = np.empty(n, np.uint8)
+    scratch = np.empty(n_hw, np.int32)
+    _check("oracle_decide_alpha",
+           lib().oracle_decide_alpha(n, _ptr(inv_op), _ptr(elapsed), _ptr(slo), n_hw, _ptr(Q),
+                                     len(ref), _ptr(ref), _ptr(Wa), _ptr(cfg_off), _ptr(hw),
+                                     _ptr(batch), _ptr(res), _ptr(lat), _ptr(cost), _ptr(r_total),
+                                     alpha_num, alpha_den, _ptr(cfg), _ptr(flag), _ptr(scratch)))
+    return cfg, flag
+
+
 class Problem:
     """Bundle of one workload's arrays with the oracle's derived quantities.
 
@@ -235,3 +304,13 @@ class Problem:
         w = self.w
         return select(w.inv_op[sl], target, w.n_hw, w.cfg_off, w.hw, w.batch,
                       w.lat, w.cost)
+
+    def queue_time(self, q_op, q_cfg):
+        w = self.w
+        return queue_time(q_op, q_cfg, w.n_hw, w.cfg_off, w.hw, w.res, w.lat, w.hw_res_total)
+
+    def decide_alpha(self, mode, alpha_num, alpha_den, Q=None, sl=slice(None)):
+        w = self.w
+        return decide_alpha(w.inv_op[sl], w.elapsed[sl], w.slo[sl], w.n_hw, Q, self.ref,
+                            self.W(mode), w.cfg_off, w.hw, w.batch, w.res, w.lat, w.cost,
+                            w.hw_res_total, alpha_num, alpha_den)

@@ -349,3 +349,186 @@ int oracle_select_lat(int64_t n_inv, const int32_t *inv_op, const int32_t *targe
     }
     return ORACLE_OK;
 }
+
+/*
+ * Eq. 2 (Sec. 4.3): the estimated queueing time of backend h over the
+ * invocations queued there (the speculative and the commit queue together),
+ *     Q[h] = sum over queued i with hw(x_i) = h of L(x_i) * R(x_i) / R_total(h),
+ * where x_i is the configuration chosen for queued invocation i.  Reading:
+ * the products L * R are summed exactly (128-bit), the sum is divided once by
+ * R_total(h) and floored; a quotient above 2^62 is reported as 2^62 (such a
+ * queueing time already leaves no remaining time).  Queued entries whose op
+ * or configuration index is out of range are left out; *n_skipped (if not
+ * NULL) receives their number.  n_hw is at most 64.
+ */
+int oracle_queue_time(int64_t n_q, const int32_t *q_op, const int32_t *q_cfg,
+                      int32_t n_hw, int32_t n_ops, const int32_t *cfg_off,
+                      const int32_t *hw, const int32_t *res, const int32_t *lat,
+                      const int64_t *r_total, int64_t *Q, int64_t *n_skipped)
+{
+    unsigned __int128 sum[64];
+    int64_t skipped = 0;
+    if (n_q < 0 || n_hw < 1 || n_hw > 64 || n_ops < 0 || !Q || !r_total)
+        return ORACLE_E_ARG;
+    if (n_q > 0 && (!q_op || !q_cfg))
+        return ORACLE_E_ARG;
+    for (int32_t h = 0; h < n_hw; ++h) {
+        if (r_total[h] < 1)
+            return ORACLE_E_RANGE;
+        sum[h] = 0;
+    }
+    for (int64_t i = 0; i < n_q; ++i) {
+        int32_t v = q_op[i];
+        if (v < 0 || v >= n_ops || q_cfg[i] < 0 || q_cfg[i] >= cfg_off[v + 1] - cfg_off[v]) {
+            ++skipped;
+            continue;
+        }
+        int32_t x = cfg_off[v] + q_cfg[i];
+        if (hw[x] < 0 || hw[x] >= n_hw)
+            return ORACLE_E_RANGE;
+        sum[hw[x]] += (unsigned __int128)(uint32_t)lat[x] * (unsigned __int128)(uint32_t)res[x];
+    }
+    for (int32_t h = 0; h < n_hw; ++h) {
+        unsigned __int128 q = sum[h] / (unsigned __int128)r_total[h];
+        Q[h] = q > ((unsigned __int128)1 << 62) ? ((int64_t)1 << 62) : (int64_t)q;
+    }
+    if (n_skipped)
+        *n_skipped = skipped;
+    return ORACLE_OK;
+}
+
+/* a * b as a 256-bit number, four 64-bit limbs, least significant first. */
+static void wide_product(unsigned __int128 a, unsigned __int128 b, uint64_t out[4])
+{
+    uint64_t al = (uint64_t)a, ah = (uint64_t)(a >> 64);
+    uint64_t bl = (uint64_t)b, bh = (uint64_t)(b >> 64);
+    unsigned __int128 ll = (unsigned __int128)al * bl;
+    unsigned __int128 lh = (unsigned __int128)al * bh;
+    unsigned __int128 hl = (unsigned __int128)ah * bl;
+    unsigned __int128 hh = (unsigned __int128)ah * bh;
+    unsigned __int128 mid = (ll >> 64) + (uint64_t)lh + (uint64_t)hl;
+    out[0] = (uint64_t)ll;
+    out[1] = (uint64_t)mid;
+    unsigned __int128 top = (mid >> 64) + (lh >> 64) + (hl >> 64) + (uint64_t)hh;
+    out[2] = (uint64_t)top;
+    out[3] = (uint64_t)(top >> 64) + (uint64_t)(hh >> 64);
+}
+
+/* n1/d1 < n2/d2 for non-negative numerators and positive denominators,
+ * decided on the exact 256-bit products n1*d2 and n2*d1. */
+static int fraction_below(unsigned __int128 n1, unsigned __int128 d1,
+                          unsigned __int128 n2, unsigned __int128 d2)
+{
+    uint64_t p[4], r[4];
+    wide_product(n1, d2, p);
+    wide_product(n2, d1, r);
+    for (int k = 3; k >= 0; --k)
+        if (p[k] != r[k])
+            return p[k] < r[k];
+    return 0;
+}
+
+/*
+ * Eq. 1 with a finite weight alpha = alpha_num / alpha_den (Sec. 4.2): for
+ * invocation i of op v every configuration x of v is scored
+ *     obj(x) = C/B                                    when L < slack_{hw(x)}
+ *     obj(x) = C/B + alpha * L * R / (B * R_total(hw(x)))   otherwise,
+ * written as the single fraction
+ *     (C * R_total * alpha_den + [L >= slack] * alpha_num * L * R)
+ *       / (B * R_total * alpha_den),
+ * and the configuration with the smallest obj is chosen, lowest caller index
+ * on ties; flag 1 when the chosen configuration meets its slack.  Bounds that
+ * keep every numerator and denominator below 2^128: cost <= 2^40, batch <=
+ * 2^16, R_total <= 2^40, alpha_num < 2^32, 1 <= alpha_den < 2^32.
+ */
+int oracle_select_alpha(int64_t n_inv, const int32_t *inv_op, const int32_t *target,
+                        int32_t n_hw, int32_t n_ops, const int32_t *cfg_off,
+                        const int32_t *hw, const int32_t *batch, const int32_t *res,
+                        const int32_t *lat, const int64_t *cost, const int64_t *r_total,
+                        uint32_t alpha_num, uint32_t alpha_den, int32_t *cfg, uint8_t *flag)
+{
+    if (n_inv < 0 || n_hw < 1 || n_ops < 0 || alpha_den < 1)
+        return ORACLE_E_ARG;
+    if (n_inv > 0 && (!inv_op || !target || !cfg))
+        return ORACLE_E_ARG;
+    if (!cfg_off || !hw || !batch || !res || !lat || !cost || !r_total)
+        return ORACLE_E_ARG;
+    for (int64_t i = 0; i < n_inv; ++i) {
+        int32_t v = inv_op[i];
+        if (v < 0 || v >= n_ops || cfg_off[v + 1] <= cfg_off[v]) {
+            cfg[i] = -1;
+            if (flag)
+                flag[i] = 0;
+            continue;
+        }
+        int32_t best = -1;
+        int best_meets = 0;
+        unsigned __int128 best_n = 0, best_d = 1;
+        for (int32_t x = cfg_off[v]; x < cfg_off[v + 1]; ++x) {
+            int32_t h = hw[x];
+            if (h < 0 || h >= n_hw || r_total[h] < 1)
+                return ORACLE_E_RANGE;
+            int meets = lat[x] < target[i * n_hw + h];
+            unsigned __int128 num = (unsigned __int128)(uint64_t)cost[x] * (uint64_t)r_total[h] * alpha_den;
+            if (!meets)
+                num += (unsigned __int128)alpha_num * (uint32_t)lat[x] * (uint32_t)res[x];
+            unsigned __int128 den = (unsigned __int128)(uint32_t)batch[x] * (uint64_t)r_total[h] * alpha_den;
+            if (best < 0 || fraction_below(num, den, best_n, best_d)) {
+                best = x;
+                best_meets = meets;
+                best_n = num;
+                best_d = den;
+            }
+        }
+        cfg[i] = best - cfg_off[v];
+        if (flag)
+            flag[i] = (uint8_t)best_meets;
+    }
+    return ORACLE_OK;
+}
+
+/* Alg. 1 slack for every backend, then oracle_select_alpha, per invocation.
+ * Invalid invocations (op out of range, negative elapsed or slo) get cfg -1,
+ * flag 0.  target_scratch holds n_hw int32 (the caller's). */
+int oracle_decide_alpha(int64_t n_inv, const int32_t *inv_op, const int32_t *elapsed,
+                        const int32_t *slo, int32_t n_hw, const int64_t *Q,
+                        int32_t n_ops, const int64_t *ref_lat, const int64_t *W,
+                        const int32_t *cfg_off, const int32_t *hw, const int32_t *batch,
+                        const int32_t *res, const int32_t *lat, const int64_t *cost,
+                        const int64_t *r_total, uint32_t alpha_num, uint32_t alpha_den,
+                        int32_t *cfg, uint8_t *flag, int32_t *target_scratch)
+{
+    if (n_inv < 0 || n_hw < 1 || !target_scratch)
+        return ORACLE_E_ARG;
+    for (int64_t i = 0; i < n_inv; ++i) {
+        int rc = oracle_targets(1, inv_op + i, elapsed + i, slo + i, n_hw, Q,
+                                n_ops, ref_lat, W, target_scratch);
+        if (rc)
+            return rc;
+        if (target_scratch[0] < 0) {
+            cfg[i] = -1;
+            if (flag)
+                flag[i] = 0;
+            continue;
+        }
+        rc = oracle_select_alpha(1, inv_op + i, target_scratch, n_hw, n_ops, cfg_off, hw,
+                                 batch, res, lat, cost, r_total, alpha_num, alpha_den,
+                                 cfg + i, flag ? flag + i : 0);
+        if (rc)
+            return rc;
+    }
+    return ORACLE_OK;
+}
+
+/* n1/d1 < n2/d2 for 128-bit operands given as two 64-bit limbs each (least
+ * significant first); exported so that the 256-bit comparison can be checked
+ * on its own over the full operand range. */
+int oracle_fraction_below(const uint64_t *n1, const uint64_t *d1, const uint64_t *n2,
+                          const uint64_t *d2)
+{
+    unsigned __int128 a = ((unsigned __int128)n1[1] << 64) | n1[0];
+    unsigned __int128 b = ((unsigned __int128)d1[1] << 64) | d1[0];
+    unsigned __int128 c = ((unsigned __int128)n2[1] << 64) | n2[0];
+    unsigned __int128 d = ((unsigned __int128)d2[1] << 64) | d2[0];
+    return fraction_below(a, b, c, d);
+}

@@ -81,6 +81,28 @@ class Workload:
         return w
 
 
+def with_resource_totals(w, per_hw=None, slots=16):
+    """Copy of w with a resource limit per backend (R_total of Eq. 1 and
+    Eq. 2): per_hw if given, else room for `slots` runs of the backend's
+    largest configuration."""
+    import copy
+    w2 = copy.copy(w)
+    if per_hw is None:
+        per_hw = [slots * int(w.res[w.hw == h].max()) if (w.hw == h).any() else 1
+                  for h in range(w.n_hw)]
+    w2.hw_res_total = np.ascontiguousarray(per_hw, np.int64)
+    return w2
+
+
+def queue_snapshot(w, rng, n_q):
+    """n_q queued invocations (op, chosen configuration), ops drawn like the
+    workload's invocations and configurations uniformly within the op."""
+    q_op = w.inv_op[rng.integers(0, w.n_inv, n_q)] if w.n_inv else np.zeros(0, np.int32)
+    n_cfg_op = (w.cfg_off[q_op + 1] - w.cfg_off[q_op]).astype(np.int64)
+    q_cfg = (rng.random(n_q) * n_cfg_op).astype(np.int64)
+    return np.ascontiguousarray(q_op, np.int32), np.ascontiguousarray(q_cfg, np.int32)
+
+
 def csr_from_edges(n_ops, src, dst, q=None):
     """CSR successor lists (sorted by destination within each source)."""
     src = np.asarray(src, np.int64)
