@@ -52,6 +52,10 @@ def parse():
     ap.add_argument("--steps-per-graph", type=int, default=20,
                     help="steps captured in one HIP graph (the timed loop replays it, then a "
                          "one-step graph for the remainder, so exactly --steps steps run)")
+    ap.add_argument("--no-next1", action="store_true",
+                    help="skip the queueing-time + finite-alpha section")
+    ap.add_argument("--queue-entries", type=int, default=1_000_000)
+    ap.add_argument("--next1-sample", type=int, default=50_000)
     ap.add_argument("--kernel-reps", type=int, default=50,
                     help="launches per graph when timing single kernels")
     return ap.parse_args()
@@ -98,6 +102,85 @@ def regret_stats(choice, truth_choice, truth_flag, truth_lat, target, hw, cost, 
     reg = per_item[xc[ok]] / per_item[xt[ok]] - 1.0
     return {"mean_regret": float(reg.mean()) if reg.size else 0.0,
             "miss_rate": float(np.mean(has & ~feas)), "scored": int(ok.sum())}
+
+
+def bench_next1(args, torch, B, wl, log, w, op, el, slo, mode):
+    """Eq. 2 queueing time over a queue snapshot, then Alg. 1 with that Q and
+    the finite-alpha Eq. 1 (alpha = 1), chained on the device; parity on a
+    sample against the oracle."""
+    import numpy as np
+    n = w.n_inv
+    rng = np.random.default_rng(17)
+    n_q = args.queue_entries
+    q_op, q_cfg = wl.queue_snapshot(w, rng, n_q)
+    # pools sized so that the backlog waits 0.2 s to 2 s depending on the backend
+    waits = np.resize(np.array([200_000, 500_000, 1_000_000, 2_000_000]), w.n_hw)
+    wr = wl.with_resource_totals(w, per_hw=wl.totals_for_queue(w, q_op, q_cfg, waits))
+    L = B.Llama(0).load(wr)
+    dq_op = torch.from_numpy(q_op).cuda()
+    dq_cfg = torch.from_numpy(q_cfg).cuda()
+    L.set_alpha(1, 1)
+    s = torch.cuda.Stream()
+    Q = torch.empty(w.n_hw, dtype=torch.int64, device="cuda")
+    cfg = torch.empty(n, dtype=torch.int32, device="cuda")
+    flag = torch.empty(n, dtype=torch.uint8, device="cuda")
+
+    def qt():
+        L.queue_time(dq_op, dq_cfg, out=Q, stream=s)
+
+    def da():
+        L.decide_alpha(op, el, slo, Q, mode, cfg, flag, stream=s)
+
+    def da0():
+        L.decide_alpha(op, el, slo, None, mode, cfg, flag, stream=s)
+
+    def chain():
+        qt()
+        da()
+
+    with torch.cuda.stream(s):
+        for _ in range(3):
+            chain()
+    torch.cuda.synchronize()
+    reps = args.kernel_reps
+    ms_q = time_graph(torch, s, graph_of(torch, s, qt, reps), 5) / reps
+    ms_a = time_graph(torch, s, graph_of(torch, s, da, reps), 5) / reps
+    ms_0 = time_graph(torch, s, graph_of(torch, s, da0, reps), 5) / reps
+    with torch.cuda.stream(s):
+        da0()
+    torch.cuda.synchronize()
+    c0, f0 = cfg.cpu().numpy(), flag.cpu().numpy()
+    ms_c = time_graph(torch, s, graph_of(torch, s, chain, reps), 5) / reps
+    # parity: Q exactly, decisions on a sample of invocations
+    import oracle
+    P = oracle.Problem(wr)
+    Q_or, _ = P.queue_time(q_op, q_cfg)
+    sample = slice(0, min(n, args.next1_sample))
+    c_or, f_or = P.decide_alpha(mode, 1, 1, Q=Q_or, sl=sample)
+    cg, fg = cfg.cpu().numpy()[sample], flag.cpu().numpy()[sample]
+    c0_or, f0_or = P.decide_alpha(mode, 1, 1, Q=None, sl=sample)
+    exact = bool(np.array_equal(Q.cpu().numpy(), Q_or) and np.array_equal(cg, c_or)
+                 and np.array_equal(fg, f_or) and np.array_equal(c0[sample], c0_or)
+                 and np.array_equal(f0[sample], f0_or))
+    q_bytes = n_q * (8 + 12)
+    a_bytes = n * 17 + wr.n_cfg * 12
+    log(f"bench: next1 queue_time {ms_q * 1e3:.2f} us, decide_alpha {ms_a * 1e3:.2f} us, exact {exact}")
+    return {"alpha": [1, 1], "hw_res_total": wr.hw_res_total.tolist(), "queue_entries": n_q,
+            "Q_us": Q_or.tolist(), "ms_per_chain": ms_c, "decisions_per_s": n / (ms_c * 1e-3),
+            "met_slack": float(flag.float().mean().item()),
+            "queue_time": {"kernel": "queue_accumulate_kernel", "ms": ms_q,
+                           "roofline": {"bound": "hbm", "achieved": q_bytes / (ms_q * 1e-3) / 1e9,
+                                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                        "frac": q_bytes / (ms_q * 1e-3) / 1e9 / HBM_PEAK_GBS}},
+            "decide_alpha": {"kernel": "decide_alpha_kernel", "ms": ms_a,
+                             "roofline": {"bound": "hbm", "achieved": a_bytes / (ms_a * 1e-3) / 1e9,
+                                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                          "frac": a_bytes / (ms_a * 1e-3) / 1e9 / HBM_PEAK_GBS}},
+            "decide_alpha_without_queue": {"kernel": "decide_alpha_merged_kernel", "ms": ms_0,
+                                           "decisions_per_s": n / (ms_0 * 1e-3)},
+            "bit_exact": exact,
+            "parity_sample": f"Q exactly; decisions of the first {sample.stop} invocations, "
+                             f"with and without the queueing times"}
 
 
 def bench_surrogate(args, torch, B, wl, log):
@@ -386,6 +469,9 @@ def main():
                          f"decide (Alg. 1 + Eq. 1 scan of every configuration), median of "
                          f"{len(times)} runs"}
 
+    next1 = None
+    if not args.no_next1:
+        next1 = bench_next1(args, torch, B, wl, log, w, op, el, slo, mode)
     surr = None
     args._surrogate_ctx = None
     if not args.no_surrogate:
@@ -433,6 +519,7 @@ def main():
         "wave_scan": {"kernel": "decide_wave_kernel", "ms": ms_wave,
                       "decisions_per_s": n / (ms_wave * 1e-3)},
         "frontier_entries": st["frontier_entries"],
+        "next1": next1,
         "surrogate": surr,
         "serving": serve,
     }

@@ -81,9 +81,12 @@ enum llama_scan_mode {
 #define LLAMA_MAX_COST ((int64_t)1 << 40)
 #define LLAMA_MAX_BATCH 65536
 #define LLAMA_Q_ONE 65536              /* branch probability 1.0 in Q16 */
+#define LLAMA_MAX_RES_TOTAL ((int64_t)1 << 40)  /* resource limit of a backend */
+#define LLAMA_ALPHA_MAX_CFG_PER_OP 32767        /* finite-alpha objective */
 
 /* Device error word bits (llama_stats.device_error). */
 #define LLAMA_DEVERR_INVALID_INVOCATION 1u
+#define LLAMA_DEVERR_INVALID_QUEUE_ENTRY 2u
 
 /* Create a context bound to HIP device `device` (its ordinal). */
 int llama_create(llama_ctx **out, int32_t device);
@@ -142,7 +145,8 @@ int llama_set_dag(llama_ctx *ctx, int32_t n_pipelines,
  *                  configuration with the smallest resource size, lowest
  *                  index on ties (LLAMA_E_STATE if an op has none)
  *   hw_res_total   [n_hw] resource limit per backend (R_total of Eq. 1 and
- *                  Eq. 2), >= 1; may be NULL (not used by the decision)
+ *                  Eq. 2), 1..LLAMA_MAX_RES_TOTAL; may be NULL when neither
+ *                  llama_queue_time nor the finite-alpha objective is used
  *
  * Also bounded: (ops in a pipeline) * (largest reference latency in it)
  * < 2^46, so every path latency and every intermediate product fits int64.
@@ -238,6 +242,55 @@ int llama_decide(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
 int llama_select_rows(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
                       const int32_t *d_target_us, const int32_t *d_lat_us,
                       int64_t lat_stride, int32_t *d_cfg, uint8_t *d_flag, void *stream);
+
+/*
+ * Eq. 2 (Sec. 4.3): estimated queueing time of every backend from the
+ * invocations queued there (the speculative and commit queues together),
+ *     Q[h] = floor( sum over queued i with hw(x_i) = h of L(x_i) * R(x_i)
+ *                   / R_total(h) ),
+ * x_i being the configuration already chosen for queued invocation i; the
+ * products are summed exactly (128-bit) and divided once; a quotient above
+ * 2^62 is reported as 2^62.  Device pointers:
+ *   d_q_op        [n_queued] global op id of each queued invocation
+ *   d_q_cfg       [n_queued] its configuration, local index within the op
+ *   d_queue_out   [n_hw] int64 output, usable directly as the d_queue_us of
+ *                 llama_targets / llama_decide / llama_decide_alpha
+ * Entries with an op or configuration out of range are left out and set
+ * LLAMA_DEVERR_INVALID_QUEUE_ENTRY in the device error word.  Needs
+ * hw_res_total (LLAMA_E_STATE otherwise).  Uses 128 KB of context-owned
+ * scratch for per-workgroup partial sums: calls on one context must not
+ * overlap.
+ */
+int llama_queue_time(llama_ctx *ctx, int64_t n_queued, const int32_t *d_q_op,
+                     const int32_t *d_q_cfg, int64_t *d_queue_out, void *stream);
+
+/*
+ * Eq. 1 with a finite weight alpha = alpha_num / alpha_den (Sec. 4.2): every
+ * configuration x of the invocation's op is scored
+ *     obj(x) = C/B                                    if L < slack_{hw(x)}
+ *            = C/B + alpha * L * R / (B * R_total(hw(x)))   otherwise
+ * and the smallest obj wins, lowest caller index on ties; flag 1 when the
+ * chosen configuration meets its slack.  llama_set_alpha builds the tables:
+ * for each op the exact dense ranks of its 2n possible objective values
+ * (compared by 256-bit cross-multiplication) and, per (op, backend), the
+ * configurations in latency order with prefix minima of the feasible keys
+ * and suffix minima of the infeasible keys.  Needs hw_res_total; alpha_num
+ * < 2^32, 1 <= alpha_den < 2^32; every op at most
+ * LLAMA_ALPHA_MAX_CFG_PER_OP configurations (LLAMA_E_RANGE otherwise).
+ * Synchronous.  llama_update_latencies rebuilds the tables; llama_set_profiles
+ * drops them.
+ */
+int llama_set_alpha(llama_ctx *ctx, uint32_t alpha_num, uint32_t alpha_den);
+
+/*
+ * Alg. 1 targets (as llama_targets, with d_queue_us or zeros) and the
+ * finite-alpha Eq. 1 choice, fused; device pointers as in llama_decide.
+ * Invalid invocations get -1 / flag 0 and set the device error word.
+ */
+int llama_decide_alpha(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
+                       const int32_t *d_elapsed_us, const int32_t *d_slo_us,
+                       const int64_t *d_queue_us, int32_t slack_mode, int32_t *d_cfg,
+                       uint8_t *d_flag, void *stream);
 
 /*
  * Autotuner: time every schedule of the indexed decision kernel (0, 1, 2:

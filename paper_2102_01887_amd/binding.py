@@ -22,6 +22,7 @@ SCANS = (SCAN_INDEXED, SCAN_FULL, SCAN_WAVE)
 SCHEDULE_NAMES = ("direct-1", "direct-2", "direct-4", "lds-persistent", "direct-1-nt", "direct-2-nt",
                   "direct-4-nt")
 DEVERR_INVALID_INVOCATION = 1
+DEVERR_INVALID_QUEUE_ENTRY = 2
 
 EXPORTS = ["llama_create", "llama_destroy", "llama_last_error", "llama_set_dag",
            "llama_set_profiles", "llama_relax", "llama_update_latencies", "llama_targets",
@@ -32,7 +33,8 @@ EXPORTS = ["llama_create", "llama_destroy", "llama_last_error", "llama_set_dag",
            "llama_surrogate_save", "llama_surrogate_load", "llama_decide_learned",
            "llama_surrogate_fit", "llama_select_rows", "llama_serve_bytes_per_request",
            "llama_serve_open", "llama_serve_submit", "llama_serve_poll", "llama_serve_stats_get",
-           "llama_serve_close", "llama_autotune"]
+           "llama_serve_close", "llama_autotune", "llama_queue_time", "llama_set_alpha",
+           "llama_decide_alpha"]
 
 
 class LlamaStats(ctypes.Structure):
@@ -83,6 +85,9 @@ def load_library(path=LIB_PATH):
         "llama_select_rows": [p, i64, p, p, p, i64, p, p, p],
         "llama_serve_bytes_per_request": [i32],
         "llama_autotune": [p, i64, p, p, p, p, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float), p],
+        "llama_queue_time": [p, i64, p, p, p, p],
+        "llama_set_alpha": [p, ctypes.c_uint32, ctypes.c_uint32],
+        "llama_decide_alpha": [p, i64, p, p, p, p, i32, p, p, p],
         "llama_serve_open": [p, ctypes.POINTER(ServeConfig), ctypes.POINTER(p)],
         "llama_serve_submit": [p, i32, p, p, p, p, p, p, ctypes.POINTER(i32)],
         "llama_serve_poll": [p, i32, p, p, p, p, ctypes.POINTER(i32), i32],
@@ -289,6 +294,36 @@ class Llama:
             self._ctx, n, _dp(op, "int32"), _dp(elapsed, "int32", n), _dp(slo, "int32", n),
             _dp(queue, "int64", self.n_hw), int(mode), int(scan), _dp(cfg, "int32", n),
             _dp(flag, "uint8", n), _stream(stream)))
+        return cfg, flag
+
+    # -- Eq. 2 queueing time and the finite-alpha objective ------------------------
+    def queue_time(self, q_op, q_cfg, out=None, stream=None):
+        """Eq. 2 per backend from queued (op, configuration) pairs (device
+        tensors); returns the int64 [n_hw] device tensor."""
+        import torch
+        n = q_op.numel()
+        if out is None:
+            out = torch.empty(self.n_hw, dtype=torch.int64, device=q_op.device)
+        self._check("llama_queue_time", self._L.llama_queue_time(
+            self._ctx, n, _dp(q_op, "int32"), _dp(q_cfg, "int32", n), _dp(out, "int64", self.n_hw),
+            _stream(stream)))
+        return out
+
+    def set_alpha(self, alpha_num, alpha_den=1):
+        self._check("llama_set_alpha", self._L.llama_set_alpha(self._ctx, int(alpha_num), int(alpha_den)))
+
+    def decide_alpha(self, op, elapsed, slo, queue=None, mode=SLACK_PAPER, cfg=None, flag=None,
+                     stream=None):
+        import torch
+        n = op.numel()
+        if cfg is None:
+            cfg = torch.empty(n, dtype=torch.int32, device=op.device)
+        if flag is None:
+            flag = torch.empty(n, dtype=torch.uint8, device=op.device)
+        self._check("llama_decide_alpha", self._L.llama_decide_alpha(
+            self._ctx, n, _dp(op, "int32"), _dp(elapsed, "int32", n), _dp(slo, "int32", n),
+            _dp(queue, "int64", self.n_hw), int(mode), _dp(cfg, "int32", n), _dp(flag, "uint8", n),
+            _stream(stream)))
         return cfg, flag
 
     # -- introspection ----------------------------------------------------------

@@ -67,7 +67,14 @@ struct llama_ctx {
   std::vector<uint32_t> key;  // caller order
   DevBuf d_ref, d_W, d_hdr, d_front_L, d_rec, d_rec_tail, d_ovf, d_rec_q, d_rec_tail_q, d_ovf_q, d_seg_off, d_tab;
   DevBuf d_mst, d_mst_first;
-  DevBuf d_cfg_off, d_cfg_hw, d_cfg_lat, d_cfg_key;
+  DevBuf d_cfg_off, d_cfg_hw, d_cfg_lat, d_cfg_key, d_cfg_q;
+  std::vector<int64_t> res_total;  // [n_hw] or empty
+  // finite-alpha objective (llama_set_alpha)
+  bool has_alpha = false;
+  uint32_t alpha_num = 0, alpha_den = 1;
+  int32_t alpha_steps = 0, alpha_msteps = 0;
+  DevBuf d_a_lat, d_a_pf, d_a_si, d_m_lat, d_m_pf, d_m_si;
+  DevBuf d_qacc;  // Eq. 2 partial sums, QUEUE_PARTS x MAX_HW x 2 x 64 bits
   int64_t n_mst = 0;
   DevBuf d_err;
   llama::Surrogate surr;
@@ -116,6 +123,15 @@ struct llama_ctx {
     t.cfg_hw = d_cfg_hw.as<int32_t>();
     t.cfg_lat = d_cfg_lat.as<int32_t>();
     t.cfg_key = d_cfg_key.as<uint32_t>();
+    t.cfg_q = d_cfg_q.as<uint4>();
+    t.a_lat = d_a_lat.as<int32_t>();
+    t.a_pf = d_a_pf.as<uint32_t>();
+    t.a_si = d_a_si.as<uint32_t>();
+    t.a_steps = alpha_steps;
+    t.m_lat = d_m_lat.as<int32_t>();
+    t.m_pf = d_m_pf.as<uint32_t>();
+    t.m_si = d_m_si.as<uint32_t>();
+    t.m_steps = alpha_msteps;
     t.seg_off = d_seg_off.as<int32_t>();
     t.tab = d_tab.as<uint2>();
     t.err = d_err.as<uint32_t>();
@@ -127,7 +143,7 @@ struct llama_ctx {
                            &d_succ_ids, &d_succ_q, &d_ref, &d_W, &d_hdr, &d_front_L,
                            &d_rec, &d_rec_tail, &d_ovf, &d_rec_q, &d_rec_tail_q, &d_ovf_q, &d_seg_off, &d_tab, &d_err,
                            &d_cnt, &d_start, &d_cursor, &d_perm, &d_hist, &d_mst,
-                           &d_mst_first, &d_cfg_off, &d_cfg_hw, &d_cfg_lat, &d_cfg_key};
+                           &d_mst_first, &d_cfg_off, &d_cfg_hw, &d_cfg_lat, &d_cfg_key, &d_cfg_q, &d_a_lat, &d_a_pf, &d_a_si, &d_m_lat, &d_m_pf, &d_m_si, &d_qacc};
     int64_t s = 0;
     for (auto* b : all) s += (int64_t)b->bytes;
     return s;
@@ -142,4 +158,6 @@ int hip_fail(llama_ctx* c, hipError_t e, const char* what);
 int upload(llama_ctx* c, DevBuf& buf, const void* src, size_t bytes, const char* what);
 int enter(llama_ctx* c);
 int sync_ctx(llama_ctx* c, const char* what);
+// finite-alpha tables (next_host.cpp); called by llama_set_alpha and after latency updates
+int build_alpha_tables(llama_ctx* c);
 }  // namespace llama

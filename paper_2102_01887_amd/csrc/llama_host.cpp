@@ -324,7 +324,8 @@ int llama_set_profiles(llama_ctx* c, int32_t n_ops, int32_t n_hw, const int32_t*
   }
   if (hw_res_total)
     for (int h = 0; h < n_hw; ++h)
-      if (hw_res_total[h] < 1) return fail(c, LLAMA_E_RANGE, "set_profiles: hw_res_total[%d] < 1", h);
+      if (hw_res_total[h] < 1 || hw_res_total[h] > LLAMA_MAX_RES_TOTAL)
+        return fail(c, LLAMA_E_RANGE, "set_profiles: hw_res_total[%d] not in [1, 2^40]", h);
 
   std::vector<int32_t> ref_k(n_ops);
   for (int v = 0; v < n_ops; ++v) {
@@ -352,7 +353,15 @@ int llama_set_profiles(llama_ctx* c, int32_t n_ops, int32_t n_hw, const int32_t*
   }
 
   c->has_prof = false;
+  c->has_alpha = false;
   c->perm_cap = 0;  // full-scan scratch is sized by the op count: regrow on demand
+  if (hw_res_total) c->res_total.assign(hw_res_total, hw_res_total + n_hw);
+  else c->res_total.clear();
+  // Eq. 2 partial sums (allocated here, never during a decision call, so the
+  // queueing-time launch can be captured in a graph)
+  if (!c->d_qacc.p &&
+      (rc = upload(c, c->d_qacc, nullptr, (size_t)16 * llama::MAX_HW * llama::QUEUE_PARTS, "queue partial sums")))
+    return rc;
   c->n_hw = n_hw;
   c->n_cfg = n_cfg;
   c->cfg_off.assign(cfg_off, cfg_off + n_ops + 1);
@@ -401,6 +410,11 @@ int llama_update_latencies(llama_ctx* c, const int32_t* lat) {
   c->lat.assign(lat, lat + c->n_cfg);
   if ((rc = build_tables(c))) return rc;
   c->has_prof = true;
+  if (c->has_alpha) {
+    c->has_alpha = false;
+    if ((rc = llama::build_alpha_tables(c))) return rc;
+    c->has_alpha = true;
+  }
   return LLAMA_OK;
 }
 
@@ -554,6 +568,18 @@ int build_tables(llama_ctx* c) {
       (rc = upload(c, c->d_cursor, nullptr, sizeof(int32_t) * (size_t)n_ops, "bucket cursors")) ||
       (rc = upload_vec(c, c->d_tab, tab, "tab")))
     return rc;
+  // Eq. 2 reads, per queued invocation, one 16-byte record {L, R, hw, 0} of
+  // its configuration (only with resource limits); the host copy lives until
+  // the synchronisation below, like every staged table here
+  std::vector<uint4> cq;
+  if (!c->res_total.empty()) {
+    cq.resize(c->n_cfg);
+    for (int64_t x = 0; x < c->n_cfg; ++x)
+      cq[x] = make_uint4((uint32_t)c->lat[x], (uint32_t)c->res[x], (uint32_t)c->hw[x], 0u);
+    if ((rc = upload_vec(c, c->d_cfg_q, cq, "queue records"))) return rc;
+  } else {
+    c->d_cfg_q.release();
+  }
   hipError_t e = llama::launch_relax(c->tables(), c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "relax launch");
   return sync_ctx(c, "set_profiles");

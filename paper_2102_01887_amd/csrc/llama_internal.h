@@ -10,6 +10,7 @@ namespace llama {
 constexpr uint32_t KEY_NONE = 0xFFFFFFFFu;   // "no feasible configuration"
 constexpr uint32_t THR_NEVER = 0xFFFFFFFFu;  // remaining-time threshold never met
 constexpr int MAX_HW = 8;
+constexpr uint32_t DEVERR_QUEUE_ENTRY = 2u;  // device error bit: queued entry out of range
 
 // Per-op decision record (64 bytes).  The op's frontier over all backends in
 // remaining-time space: entries {T, k} such that configuration k (local index)
@@ -98,6 +99,17 @@ struct DevTables {
   const int32_t* cfg_hw;     // [n_cfg] backend, caller order
   const int32_t* cfg_lat;    // [n_cfg] profiled latency, caller order
   const uint32_t* cfg_key;   // [n_cfg] rank << 16 | k, caller order
+  const uint4* cfg_q;        // [n_cfg] {L, R, hw, 0} caller order (with resource limits only)
+  // finite-alpha objective, per (op, backend) segment of seg_off, sorted by latency
+  const int32_t* a_lat;      // [n_cfg] latency
+  const uint32_t* a_pf;      // [n_cfg] min feasible key over the segment's entries up to here
+  const uint32_t* a_si;      // [n_cfg] min infeasible key over the segment's entries from here
+  int32_t a_steps;           // binary-search steps covering the longest segment
+  // the same per op over all backends (cfg_off segments), for Q = 0
+  const int32_t* m_lat;
+  const uint32_t* m_pf;
+  const uint32_t* m_si;
+  int32_t m_steps;
   const int32_t* seg_off;    // [n_ops*n_hw+1] backend segments of the full table
   const uint2* tab;          // [n_cfg] {latency, key}, grouped by (op, backend), caller order inside
   uint32_t* err;             // device error word
@@ -137,6 +149,16 @@ struct FullScratch {
 int64_t full_scan_hist_words(int64_t n_inv, int32_t n_ops);
 hipError_t launch_decide_full(const DevTables& t, const Batch& b, const FullScratch& w, hipStream_t s);
 hipError_t launch_decide_wave(const DevTables& t, const Batch& b, hipStream_t s);
+// Eq. 2: per-workgroup 128-bit partial sums of L*R per backend (at most
+// QUEUE_PARTS workgroups, scratch of QUEUE_PARTS x MAX_HW x 16 bytes), then
+// their total divided by R_total.
+constexpr int QUEUE_PARTS = 1024;
+struct ResTotals {
+  int64_t r[MAX_HW];
+};
+hipError_t launch_queue_time(const DevTables& t, int64_t n, const int32_t* q_op, const int32_t* q_cfg,
+                             unsigned long long* part, const ResTotals& rt, int64_t* out, hipStream_t s);
+hipError_t launch_decide_alpha(const DevTables& t, const Batch& b, hipStream_t s);
 hipError_t launch_select_rows(const DevTables& t, const Batch& b, const int32_t* lat, int64_t stride,
                               hipStream_t s);
 

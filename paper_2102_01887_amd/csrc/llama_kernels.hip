@@ -1031,6 +1031,259 @@ inline unsigned blocks_for(int64_t n, int per_block) {
   return (unsigned)((n + per_block - 1) / per_block);
 }
 
+// ---------------------------------------------------------------------------
+// Eq. 2: queueing time per backend.  Each thread sums L * R of its queued
+// entries per backend in 128 bits; a wavefront reduction (two 64-bit halves)
+// and an LDS step leave one partial per workgroup and backend in scratch;
+// queue_finalize_kernel adds the partials (again in 128 bits) and divides.
+// No atomics: the result does not depend on the order of the additions.
+// ---------------------------------------------------------------------------
+constexpr int QUEUE_BATCH = 4;
+
+__device__ __forceinline__ unsigned __int128 wave_sum_u128(unsigned __int128 x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long lo = __shfl_xor((unsigned long long)x, off, 64);
+    const unsigned long long hi = __shfl_xor((unsigned long long)(x >> 64), off, 64);
+    x += ((unsigned __int128)hi << 64) | lo;
+  }
+  return x;
+}
+
+template <int NHW>
+__global__ __launch_bounds__(256) void queue_accumulate_kernel(DevTables t, int64_t n, const int32_t* q_op,
+                                                               const int32_t* q_cfg, unsigned long long* part) {
+  __shared__ unsigned long long sPart[4][NHW][2];
+  unsigned __int128 sum[NHW];
+#pragma unroll
+  for (int h = 0; h < NHW; ++h) sum[h] = 0;
+  bool bad = false;
+  // QUEUE_BATCH entries per thread and pass, their loads issued together
+  // (out-of-range entries read entry 0 of op 0 and contribute nothing)
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x * QUEUE_BATCH;
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x * QUEUE_BATCH + threadIdx.x; i0 < n; i0 += stride) {
+    int v[QUEUE_BATCH], k[QUEUE_BATCH], x[QUEUE_BATCH];
+    bool ok[QUEUE_BATCH];
+#pragma unroll
+    for (int u = 0; u < QUEUE_BATCH; ++u) {
+      const int64_t i = i0 + (int64_t)u * blockDim.x;
+      v[u] = i < n ? q_op[i] : 0;
+      k[u] = i < n ? q_cfg[i] : 0;
+      ok[u] = i < n && (unsigned)v[u] < (unsigned)t.n_ops;
+      bad |= i < n && !ok[u];
+    }
+#pragma unroll
+    for (int u = 0; u < QUEUE_BATCH; ++u) {
+      const int a = t.cfg_off[ok[u] ? v[u] : 0];
+      const int e = t.cfg_off[(ok[u] ? v[u] : 0) + 1];
+      const bool in = ok[u] && (unsigned)k[u] < (unsigned)(e - a);
+      bad |= ok[u] && !in;
+      ok[u] = in;
+      x[u] = in ? a + k[u] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < QUEUE_BATCH; ++u) {
+      const uint4 q = t.cfg_q[x[u]];  // {L, R, hw, 0}
+      const uint64_t p = ok[u] ? (uint64_t)q.x * (uint64_t)q.y : 0ull;
+#pragma unroll
+      for (int h = 0; h < NHW; ++h) sum[h] += h == (int)q.z ? p : 0ull;
+    }
+  }
+  if (bad) atomicOr(t.err, DEVERR_QUEUE_ENTRY);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int h = 0; h < NHW; ++h) {
+    const unsigned __int128 w = wave_sum_u128(sum[h]);
+    if (lane == 0) {
+      sPart[wave][h][0] = (unsigned long long)w;
+      sPart[wave][h][1] = (unsigned long long)(w >> 64);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < NHW) {
+    const int h = threadIdx.x;
+    unsigned __int128 tot = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) tot += ((unsigned __int128)sPart[w][h][1] << 64) | sPart[w][h][0];
+    unsigned long long* dst = part + ((int64_t)blockIdx.x * MAX_HW + h) * 2;
+    dst[0] = (unsigned long long)tot;
+    dst[1] = (unsigned long long)(tot >> 64);
+  }
+}
+
+// Q[h] = min(floor(total[h] / R_total[h]), 2^62): 1024 threads add the
+// n_part partials of every backend (wavefront sums, then LDS), then thread h
+// divides (a 128-bit total by a divisor below 2^41, 16 bits at a time).
+__global__ __launch_bounds__(1024) void queue_finalize_kernel(const unsigned long long* part, int n_part, ResTotals rt,
+                                                              int n_hw, int64_t* out) {
+  __shared__ unsigned long long sRed[16][MAX_HW][2];
+  __shared__ unsigned long long sTot[MAX_HW][2];
+  const int tid = threadIdx.x, wave = tid >> 6;
+  unsigned __int128 x[MAX_HW];
+#pragma unroll
+  for (int h = 0; h < MAX_HW; ++h) x[h] = 0;
+  if (tid < n_part) {  // n_part <= QUEUE_PARTS = blockDim.x: one partial per thread
+    const uint4* p = reinterpret_cast<const uint4*>(part) + (int64_t)tid * MAX_HW;
+#pragma unroll
+    for (int h = 0; h < MAX_HW; ++h) {
+      if (h >= n_hw) break;
+      const uint4 v = p[h];  // {low 64 bits, high 64 bits} as four 32-bit words
+      x[h] = ((unsigned __int128)(((uint64_t)v.w << 32) | v.z) << 64) | (((uint64_t)v.y << 32) | v.x);
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < MAX_HW; ++h) {
+    if (h >= n_hw) break;
+    const unsigned __int128 w = wave_sum_u128(x[h]);
+    if ((tid & 63) == 0) {
+      sRed[wave][h][0] = (unsigned long long)w;
+      sRed[wave][h][1] = (unsigned long long)(w >> 64);
+    }
+  }
+  __syncthreads();
+  if (tid < n_hw) {
+    unsigned __int128 tot = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += ((unsigned __int128)sRed[w][tid][1] << 64) | sRed[w][tid][0];
+    sTot[tid][0] = (unsigned long long)tot;
+    sTot[tid][1] = (unsigned long long)(tot >> 64);
+  }
+  __syncthreads();
+  const int lane = tid;
+  if (lane >= n_hw) return;
+  const unsigned __int128 s = ((unsigned __int128)sTot[lane][1] << 64) | sTot[lane][0];
+  const unsigned __int128 d = (unsigned __int128)(uint64_t)rt.r[lane];
+  if (s >= d << 62) {  // d < 2^41, so d * 2^62 < 2^103 does not overflow
+    out[lane] = (int64_t)1 << 62;
+    return;
+  }
+  // s < d * 2^62, so the quotient has at most 62 bits: long division by
+  // 16-bit digits of s, the running remainder (< d < 2^41) times 2^16 plus a
+  // digit staying below 2^57
+  const uint64_t dd = (uint64_t)d;
+  uint64_t rem = 0, q = 0;
+  for (int dig = 7; dig >= 0; --dig) {
+    const uint64_t cur = (rem << 16) | (uint64_t)((s >> (16 * dig)) & 0xFFFFu);
+    const uint64_t qd = cur / dd;
+    rem = cur - qd * dd;
+    q = (q << 16) | qd;  // qd < 2^16; bits shifted out are zero as q < 2^62
+  }
+  out[lane] = (int64_t)q;
+}
+
+// ---------------------------------------------------------------------------
+// Finite-alpha Eq. 1: per backend, j = number of configurations faster than
+// the target (branch-free binary search over the latency-sorted segment, the
+// NHW searches advancing in lockstep so their loads overlap); the backend's
+// best key is min(prefix-min feasible key before j, suffix-min infeasible key
+// from j); the smallest key over backends wins.
+// ---------------------------------------------------------------------------
+template <int NHW>
+__global__ __launch_bounds__(256) void decide_alpha_kernel(DevTables t, Batch b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= b.n) return;
+  const int v = b.op[i], e = b.elapsed[i], s = b.slo[i];
+  if (invalid_invocation(v, e, s, t.n_ops)) {
+    b.cfg[i] = -1;
+    if (b.flag) b.flag[i] = 0;
+    atomicOr(t.err, 1u);
+    return;
+  }
+  const int64_t r0 = (int64_t)s - e;
+  const int64_t ref = t.ref[v];
+  const int64_t W = t.W[(int64_t)b.mode * t.n_ops + v];
+  const int32_t* so = t.seg_off + (int64_t)v * NHW;
+  int base[NHW], len[NHW], end[NHW];
+  int32_t target[NHW];
+#pragma unroll
+  for (int h = 0; h < NHW; ++h) {
+    base[h] = so[h];
+    end[h] = so[h + 1];
+    len[h] = end[h] - base[h];
+    const int64_t R = remaining_time(r0, b.queue ? b.queue[h] : 0);
+    target[h] = R == 0 ? 0 : (int32_t)div_floor_pos(ref * R, W);
+  }
+  for (int step = 0; step < t.a_steps; ++step) {
+#pragma unroll
+    for (int h = 0; h < NHW; ++h) {
+      if (len[h] > 0) {
+        const int half = len[h] >> 1;
+        if (t.a_lat[base[h] + half] < target[h]) {
+          base[h] += half + 1;
+          len[h] -= half + 1;
+        } else {
+          len[h] = half;
+        }
+      }
+    }
+  }
+  uint32_t best = KEY_NONE;
+  uint8_t meets = 0;
+#pragma unroll
+  for (int h = 0; h < NHW; ++h) {
+    const int j = base[h];  // first configuration of the segment with L >= target
+    const int lo = so[h];
+    if (j > lo) {
+      const uint32_t kf = t.a_pf[j - 1];
+      if (kf < best) {
+        best = kf;
+        meets = 1;
+      }
+    }
+    if (j < end[h]) {
+      const uint32_t ki = t.a_si[j];
+      if (ki < best) {
+        best = ki;
+        meets = 0;
+      }
+    }
+  }
+  b.cfg[i] = (int)(best & 0xFFFFu);
+  if (b.flag) b.flag[i] = meets;
+}
+
+// Without queueing times every backend's target is the same, so one search
+// over the op's configurations of all backends (latency order) suffices.
+__global__ __launch_bounds__(256) void decide_alpha_merged_kernel(DevTables t, Batch b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= b.n) return;
+  const int v = b.op[i], e = b.elapsed[i], s = b.slo[i];
+  if (invalid_invocation(v, e, s, t.n_ops)) {
+    b.cfg[i] = -1;
+    if (b.flag) b.flag[i] = 0;
+    atomicOr(t.err, 1u);
+    return;
+  }
+  const int64_t R = remaining_time((int64_t)s - e, 0);
+  const int32_t target =
+      R == 0 ? 0 : (int32_t)div_floor_pos((int64_t)t.ref[v] * R, t.W[(int64_t)b.mode * t.n_ops + v]);
+  const int lo = t.cfg_off[v], end = t.cfg_off[v + 1];
+  int base = lo, len = end - lo;
+  for (int step = 0; step < t.m_steps && len > 0; ++step) {
+    const int half = len >> 1;
+    if (t.m_lat[base + half] < target) {
+      base += half + 1;
+      len -= half + 1;
+    } else {
+      len = half;
+    }
+  }
+  uint32_t best = KEY_NONE;
+  uint8_t meets = 0;
+  if (base > lo) {
+    best = t.m_pf[base - 1];
+    meets = 1;
+  }
+  if (base < end) {
+    const uint32_t ki = t.m_si[base];
+    if (ki < best) {
+      best = ki;
+      meets = 0;
+    }
+  }
+  b.cfg[i] = (int)(best & 0xFFFFu);
+  if (b.flag) b.flag[i] = meets;
+}
+
 #define LLAMA_DISPATCH_NHW(KERNEL, GRID, BLOCK, STREAM, ...)                         \
   switch (t.n_hw) {                                                                  \
     case 1: hipLaunchKernelGGL(KERNEL<1>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
@@ -1069,6 +1322,27 @@ hipError_t launch_targets(const DevTables& t, const Batch& b, hipStream_t s) {
 hipError_t launch_select_indexed(const DevTables& t, const Batch& b, hipStream_t s) {
   if (b.n == 0) return hipSuccess;
   LLAMA_DISPATCH_NHW(select_indexed_kernel, dim3(blocks_for(b.n, 256)), dim3(256), s, t, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_queue_time(const DevTables& t, int64_t n, const int32_t* q_op, const int32_t* q_cfg,
+                             unsigned long long* part, const ResTotals& rt, int64_t* out, hipStream_t s) {
+  int64_t blocks = (n + 256 * QUEUE_BATCH - 1) / (256 * QUEUE_BATCH);
+  if (blocks > QUEUE_PARTS) blocks = QUEUE_PARTS;
+  if (blocks > 0)
+    LLAMA_DISPATCH_NHW(queue_accumulate_kernel, dim3((unsigned)blocks), dim3(256), s, t, n, q_op, q_cfg, part);
+  hipLaunchKernelGGL(queue_finalize_kernel, dim3(1), dim3(1024), 0, s, (const unsigned long long*)part, (int)blocks,
+                     rt, t.n_hw, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_decide_alpha(const DevTables& t, const Batch& b, hipStream_t s) {
+  if (b.n == 0) return hipSuccess;
+  if (b.queue) {
+    LLAMA_DISPATCH_NHW(decide_alpha_kernel, dim3(blocks_for(b.n, 256)), dim3(256), s, t, b);
+  } else {
+    hipLaunchKernelGGL(decide_alpha_merged_kernel, dim3(blocks_for(b.n, 256)), dim3(256), 0, s, t, b);
+  }
   return hipGetLastError();
 }
 

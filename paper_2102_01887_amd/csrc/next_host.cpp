@@ -1,0 +1,234 @@
+// Host side of the queueing-time estimate (Eq. 2) and the finite-alpha form
+// of the Eq. 1 objective: argument checks, the alpha tables built at set-up,
+// and the launches.  Implements llama_queue_time, llama_set_alpha and
+// llama_decide_alpha of include/llama.h.
+//
+// Finite-alpha tables.  For configuration x of op v the objective takes one
+// of two values, independent of the invocation:
+//     feasible   F(x) = C/B
+//     infeasible I(x) = (C * R_total * a_den + a_num * L * R) / (B * R_total * a_den)
+// (R_total of x's backend).  Every op's 2n values are ranked exactly (dense
+// ranks, compared by 256-bit cross-multiplication), so the decision compares
+// 32-bit keys rank << 16 | k.  Feasibility on backend h is a latency prefix
+// of that backend's configurations (L < target_h), so per (op, backend) the
+// configurations are stored in latency order with the prefix minimum of the
+// feasible keys and the suffix minimum of the infeasible keys: the best
+// choice on backend h is min(prefix_min_F[j - 1], suffix_min_I[j]) with j the
+// number of configurations faster than the target.  Without queueing times
+// every backend has the same target, and one list per op over all backends
+// (same minima) needs a single search.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "llama.h"
+#include "llama_ctx.h"
+#include "llama_internal.h"
+
+namespace {
+
+// A non-negative fraction with 128-bit numerator and denominator.
+struct Frac {
+  unsigned __int128 num, den;
+};
+
+// 128 x 128 -> 256-bit product as four 64-bit limbs, least significant first,
+// by schoolbook multiplication of 32-bit digits into 64-bit columns.
+void mul_256(unsigned __int128 a, unsigned __int128 b, uint64_t out[4]) {
+  uint32_t x[4], y[4];
+  for (int i = 0; i < 4; ++i) {
+    x[i] = (uint32_t)(a >> (32 * i));
+    y[i] = (uint32_t)(b >> (32 * i));
+  }
+  uint32_t digit[8];
+  uint64_t carry = 0;
+  for (int k = 0; k < 8; ++k) {
+    // sum of x[i]*y[k-i]: at most four products below 2^64 each, so split
+    // every product into 32-bit halves to keep the column sum exact
+    uint64_t lo = carry, hi = 0;
+    for (int i = 0; i < 4; ++i) {
+      const int j = k - i;
+      if (j < 0 || j > 3) continue;
+      const uint64_t p = (uint64_t)x[i] * y[j];
+      lo += (uint32_t)p;
+      hi += p >> 32;
+    }
+    digit[k] = (uint32_t)lo;
+    carry = (lo >> 32) + hi;
+  }
+  for (int i = 0; i < 4; ++i) out[i] = (uint64_t)digit[2 * i] | ((uint64_t)digit[2 * i + 1] << 32);
+}
+
+// a < b exactly.
+bool frac_less(const Frac& a, const Frac& b) {
+  uint64_t l[4], r[4];
+  mul_256(a.num, b.den, l);
+  mul_256(b.num, a.den, r);
+  for (int i = 3; i >= 0; --i)
+    if (l[i] != r[i]) return l[i] < r[i];
+  return false;
+}
+
+}  // namespace
+
+namespace llama {
+
+int build_alpha_tables(llama_ctx* c) {
+  const int n_ops = c->n_ops, n_hw = c->n_hw;
+  const int64_t n_cfg = c->n_cfg;
+  std::vector<int32_t> a_lat(n_cfg), m_lat(n_cfg);
+  std::vector<uint32_t> a_pf(n_cfg), a_si(n_cfg), m_pf(n_cfg), m_si(n_cfg);
+  int max_seg = 0, max_op = 0;
+  bool too_many = false;
+#pragma omp parallel for schedule(dynamic, 64) reduction(max : max_seg, max_op) reduction(|| : too_many)
+  for (int v = 0; v < n_ops; ++v) {
+    const int a = c->cfg_off[v], b = c->cfg_off[v + 1], n = b - a;
+    if (n > LLAMA_ALPHA_MAX_CFG_PER_OP) {
+      too_many = true;
+      continue;
+    }
+    // the op's 2n objective values: index 2j = F of config j, 2j+1 = I
+    std::vector<Frac> val(2 * (size_t)n);
+    for (int j = 0; j < n; ++j) {
+      const int x = a + j;
+      const unsigned __int128 rt = (unsigned __int128)(uint64_t)c->res_total[c->hw[x]];
+      val[2 * j] = Frac{(unsigned __int128)(uint64_t)c->cost[x], (unsigned __int128)(uint32_t)c->batch[x]};
+      val[2 * j + 1] = Frac{(unsigned __int128)(uint64_t)c->cost[x] * rt * c->alpha_den +
+                                (unsigned __int128)c->alpha_num * (uint32_t)c->lat[x] * (uint32_t)c->res[x],
+                            (unsigned __int128)(uint32_t)c->batch[x] * rt * c->alpha_den};
+    }
+    std::vector<int32_t> ord(2 * (size_t)n);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::sort(ord.begin(), ord.end(), [&](int32_t p, int32_t q) { return frac_less(val[p], val[q]); });
+    std::vector<uint32_t> rank(2 * (size_t)n);
+    uint32_t r = 0;
+    for (size_t i = 0; i < ord.size(); ++i) {
+      if (i > 0 && frac_less(val[ord[i - 1]], val[ord[i]])) ++r;
+      rank[ord[i]] = r;
+    }
+    // per backend: configurations in latency order (caller index among equal
+    // latencies), prefix minima of feasible keys, suffix minima of infeasible keys
+    std::vector<int32_t> cnt(n_hw + 1, 0);
+    for (int x = a; x < b; ++x) cnt[c->hw[x] + 1]++;
+    for (int h = 0; h < n_hw; ++h) cnt[h + 1] += cnt[h];
+    std::vector<int32_t> seg(n);
+    {
+      std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+      for (int x = a; x < b; ++x) seg[fill[c->hw[x]]++] = x - a;
+    }
+    for (int h = 0; h < n_hw; ++h) {
+      const int s0 = cnt[h], s1 = cnt[h + 1];
+      max_seg = std::max(max_seg, s1 - s0);
+      std::sort(seg.begin() + s0, seg.begin() + s1, [&](int32_t p, int32_t q) {
+        return c->lat[a + p] != c->lat[a + q] ? c->lat[a + p] < c->lat[a + q] : p < q;
+      });
+      uint32_t m = KEY_NONE;
+      for (int i = s0; i < s1; ++i) {
+        const int j = seg[i];
+        a_lat[a + i] = c->lat[a + j];
+        m = std::min(m, (rank[2 * j] << 16) | (uint32_t)j);
+        a_pf[a + i] = m;
+      }
+      m = KEY_NONE;
+      for (int i = s1 - 1; i >= s0; --i) {
+        const int j = seg[i];
+        m = std::min(m, (rank[2 * j + 1] << 16) | (uint32_t)j);
+        a_si[a + i] = m;
+      }
+    }
+    // the same over all backends together, for calls without queueing times
+    // (every backend then has the same target)
+    max_op = std::max(max_op, n);
+    std::vector<int32_t> all(n);
+    std::iota(all.begin(), all.end(), 0);
+    std::sort(all.begin(), all.end(), [&](int32_t p, int32_t q) {
+      return c->lat[a + p] != c->lat[a + q] ? c->lat[a + p] < c->lat[a + q] : p < q;
+    });
+    uint32_t m = KEY_NONE;
+    for (int i = 0; i < n; ++i) {
+      m_lat[a + i] = c->lat[a + all[i]];
+      m = std::min(m, (rank[2 * all[i]] << 16) | (uint32_t)all[i]);
+      m_pf[a + i] = m;
+    }
+    m = KEY_NONE;
+    for (int i = n - 1; i >= 0; --i) {
+      m = std::min(m, (rank[2 * all[i] + 1] << 16) | (uint32_t)all[i]);
+      m_si[a + i] = m;
+    }
+  }
+  if (too_many)
+    return fail(c, LLAMA_E_RANGE, "set_alpha: an op has more than %d configurations", LLAMA_ALPHA_MAX_CFG_PER_OP);
+  int steps = 0, msteps = 0;
+  while ((1 << steps) <= max_seg) ++steps;
+  while ((1 << msteps) <= max_op) ++msteps;
+  int rc;
+  if ((rc = upload(c, c->d_a_lat, a_lat.data(), a_lat.size() * 4, "alpha latencies")) ||
+      (rc = upload(c, c->d_a_pf, a_pf.data(), a_pf.size() * 4, "alpha prefix keys")) ||
+      (rc = upload(c, c->d_a_si, a_si.data(), a_si.size() * 4, "alpha suffix keys")) ||
+      (rc = upload(c, c->d_m_lat, m_lat.data(), m_lat.size() * 4, "alpha merged latencies")) ||
+      (rc = upload(c, c->d_m_pf, m_pf.data(), m_pf.size() * 4, "alpha merged prefix keys")) ||
+      (rc = upload(c, c->d_m_si, m_si.data(), m_si.size() * 4, "alpha merged suffix keys")))
+    return rc;
+  if ((rc = sync_ctx(c, "alpha tables"))) return rc;
+  c->alpha_steps = steps;
+  c->alpha_msteps = msteps;
+  return LLAMA_OK;
+}
+
+}  // namespace llama
+
+extern "C" {
+
+int llama_queue_time(llama_ctx* c, int64_t n, const int32_t* q_op, const int32_t* q_cfg, int64_t* out,
+                     void* stream) {
+  int rc = llama::enter(c);
+  if (rc) return rc;
+  if (!c->has_prof) return llama::fail(c, LLAMA_E_STATE, "queue_time: no profiles");
+  if ((int)c->res_total.size() != c->n_hw)
+    return llama::fail(c, LLAMA_E_STATE, "queue_time: the profiles carry no hw_res_total");
+  if (n < 0) return llama::fail(c, LLAMA_E_ARG, "queue_time: n_queued < 0");
+  if (!out || (n > 0 && (!q_op || !q_cfg))) return llama::fail(c, LLAMA_E_ARG, "queue_time: null pointer");
+  if (!c->d_qacc.p) return llama::fail(c, LLAMA_E_STATE, "queue_time: no accumulators");
+  llama::ResTotals rt{};
+  for (int h = 0; h < c->n_hw; ++h) rt.r[h] = c->res_total[h];
+  hipError_t e = llama::launch_queue_time(c->tables(), n, q_op, q_cfg, c->d_qacc.as<unsigned long long>(), rt,
+                                          out, (hipStream_t)stream);
+  if (e != hipSuccess) return llama::hip_fail(c, e, "queue_time launch");
+  return LLAMA_OK;
+}
+
+int llama_set_alpha(llama_ctx* c, uint32_t alpha_num, uint32_t alpha_den) {
+  int rc = llama::enter(c);
+  if (rc) return rc;
+  if (!c->has_prof) return llama::fail(c, LLAMA_E_STATE, "set_alpha: no profiles");
+  if ((int)c->res_total.size() != c->n_hw)
+    return llama::fail(c, LLAMA_E_STATE, "set_alpha: the profiles carry no hw_res_total");
+  if (alpha_den < 1) return llama::fail(c, LLAMA_E_ARG, "set_alpha: alpha_den must be >= 1");
+  c->has_alpha = false;
+  c->alpha_num = alpha_num;
+  c->alpha_den = alpha_den;
+  if ((rc = llama::build_alpha_tables(c))) return rc;
+  c->has_alpha = true;
+  return LLAMA_OK;
+}
+
+int llama_decide_alpha(llama_ctx* c, int64_t n, const int32_t* op, const int32_t* elapsed, const int32_t* slo,
+                       const int64_t* queue, int32_t mode, int32_t* cfg, uint8_t* flag, void* stream) {
+  int rc = llama::enter(c);
+  if (rc) return rc;
+  if (!c->has_prof) return llama::fail(c, LLAMA_E_STATE, "decide_alpha: no profiles");
+  if (!c->has_alpha) return llama::fail(c, LLAMA_E_STATE, "decide_alpha: call llama_set_alpha first");
+  if (n < 0) return llama::fail(c, LLAMA_E_ARG, "decide_alpha: n_inv < 0");
+  if (n > 0 && (!op || !elapsed || !slo || !cfg)) return llama::fail(c, LLAMA_E_ARG, "decide_alpha: null pointer");
+  if (mode != LLAMA_SLACK_PAPER && mode != LLAMA_SLACK_PROB)
+    return llama::fail(c, LLAMA_E_ARG, "decide_alpha: bad slack_mode %d", mode);
+  llama::Batch b{};
+  b.n = n; b.op = op; b.elapsed = elapsed; b.slo = slo; b.queue = queue; b.cfg = cfg; b.flag = flag; b.mode = mode;
+  hipError_t e = llama::launch_decide_alpha(c->tables(), b, (hipStream_t)stream);
+  if (e != hipSuccess) return llama::hip_fail(c, e, "decide_alpha launch");
+  return LLAMA_OK;
+}
+
+}  // extern "C"

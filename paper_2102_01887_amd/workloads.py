@@ -94,6 +94,20 @@ def with_resource_totals(w, per_hw=None, slots=16):
     return w2
 
 
+def totals_for_queue(w, q_op, q_cfg, target_us=500_000):
+    """Per-backend resource limits that make a queue snapshot's estimated
+    waiting time about target_us (one value, or one per backend) on each
+    backend (an input recipe: pools sized to their backlogs)."""
+    x = w.cfg_off[q_op].astype(np.int64) + q_cfg
+    tgt = np.broadcast_to(np.asarray(target_us, np.int64), (w.n_hw,))
+    tot = [1] * w.n_hw
+    for h in range(w.n_hw):
+        sel = w.hw[x] == h
+        load = int((w.lat[x[sel]].astype(np.int64) * w.res[x[sel]].astype(np.int64)).sum())
+        tot[h] = max(1, load // int(tgt[h]))
+    return tot
+
+
 def queue_snapshot(w, rng, n_q):
     """n_q queued invocations (op, chosen configuration), ops drawn like the
     workload's invocations and configurations uniformly within the op."""
