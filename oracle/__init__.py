@@ -57,9 +57,11 @@ def load(path):
     L.oracle_decide_alpha.argtypes = [i64, p, p, p, i32, p, i32, p, p, p, p, p, p, p, p, p,
                                       u32, u32, p, p, p]
     L.oracle_fraction_below.argtypes = [p, p, p, p]
+    L.oracle_feedback.argtypes = [i64, p, p, p, i32, p, p, ctypes.c_uint32, p]
     for f in (L.oracle_reference_cfg, L.oracle_worst_path, L.oracle_targets,
               L.oracle_select, L.oracle_decide, L.oracle_select_lat, L.oracle_queue_time,
-              L.oracle_select_alpha, L.oracle_decide_alpha, L.oracle_fraction_below):
+              L.oracle_select_alpha, L.oracle_decide_alpha, L.oracle_fraction_below,
+              L.oracle_feedback):
         f.restype = ctypes.c_int
     return L
 
@@ -222,6 +224,20 @@ def queue_time(q_op, q_cfg, n_hw, cfg_off, hw, res, lat, r_total):
                                    _ptr(cfg_off), _ptr(hw), _ptr(res), _ptr(lat), _ptr(r_total),
                                    _ptr(Q), ctypes.byref(skipped)))
     return Q, skipped.value
+
+
+def feedback(obs_op, obs_cfg, obs_lat, cfg_off, lat, beta_q16):
+    """Exponential smoothing of the profile latencies from observations;
+    returns (new latencies, number of skipped observations)."""
+    obs_op, obs_cfg, obs_lat = (_arr(x, np.int32) for x in (obs_op, obs_cfg, obs_lat))
+    cfg_off = _arr(cfg_off, np.int32)
+    out = np.array(lat, dtype=np.int32, copy=True)
+    skipped = ctypes.c_int64()
+    _check("oracle_feedback",
+           lib().oracle_feedback(len(obs_op), _ptr(obs_op), _ptr(obs_cfg), _ptr(obs_lat),
+                                 len(cfg_off) - 1, _ptr(cfg_off), _ptr(out), beta_q16,
+                                 ctypes.byref(skipped)))
+    return out, skipped.value
 
 
 def fraction_below(n1, d1, n2, d2):

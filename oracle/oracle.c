@@ -532,3 +532,68 @@ int oracle_fraction_below(const uint64_t *n1, const uint64_t *d1, const uint64_t
     unsigned __int128 d = ((unsigned __int128)d2[1] << 64) | d2[0];
     return fraction_below(a, b, c, d);
 }
+
+/*
+ * Feedback (Sec. 3.3, Manager): the profiled latency of each configuration is
+ * updated from observed latencies by exponential smoothing.  Readings: the
+ * smoothing factor is beta = beta_q16 / 65536 in [0, 1]; the m >= 1
+ * observations of a configuration in one batch, with sum S, make one
+ * smoothing step toward their mean,
+ *     L_new = L + floor(beta_q16 * (S - m * L) / (65536 * m)),
+ * the floor taken exactly (also for negative numerators) and the result
+ * clamped to [1, 2^31 - 1]; with m = 1 this is floor((1 - beta) L + beta obs).
+ * Observations whose op or configuration index is out of range, or whose
+ * latency is below 1, are left out; *n_skipped (if not NULL) counts them.
+ * lat is updated in place (caller order).
+ */
+int oracle_feedback(int64_t n_obs, const int32_t *obs_op, const int32_t *obs_cfg,
+                    const int32_t *obs_lat, int32_t n_ops, const int32_t *cfg_off,
+                    int32_t *lat, uint32_t beta_q16, int64_t *n_skipped)
+{
+    if (n_obs < 0 || n_ops < 0 || !cfg_off || !lat || beta_q16 > 65536u)
+        return ORACLE_E_ARG;
+    if (n_obs > 0 && (!obs_op || !obs_cfg || !obs_lat))
+        return ORACLE_E_ARG;
+    int64_t n_cfg = cfg_off[n_ops];
+    int64_t skipped = 0;
+    /* count and sum of each configuration's observations */
+    int64_t *m = calloc((size_t)(n_cfg > 0 ? n_cfg : 1), sizeof(int64_t));
+    __int128 *S = calloc((size_t)(n_cfg > 0 ? n_cfg : 1), sizeof(__int128));
+    if (!m || !S) {
+        free(m);
+        free(S);
+        return ORACLE_E_ARG;
+    }
+    for (int64_t i = 0; i < n_obs; ++i) {
+        int32_t v = obs_op[i];
+        if (v < 0 || v >= n_ops || obs_cfg[i] < 0 || obs_cfg[i] >= cfg_off[v + 1] - cfg_off[v] ||
+            obs_lat[i] < 1) {
+            ++skipped;
+            continue;
+        }
+        int64_t x = cfg_off[v] + obs_cfg[i];
+        m[x] += 1;
+        S[x] += obs_lat[i];
+    }
+    /* one smoothing step per observed configuration */
+    for (int64_t x = 0; x < n_cfg; ++x) {
+        if (m[x] == 0)
+            continue;
+        __int128 num = (__int128)beta_q16 * (S[x] - (__int128)m[x] * lat[x]);
+        __int128 den = (__int128)65536 * m[x];
+        __int128 q = num / den;
+        if (num % den != 0 && num < 0)
+            q -= 1; /* floor, not truncation */
+        __int128 nl = (__int128)lat[x] + q;
+        if (nl < 1)
+            nl = 1;
+        if (nl > 2147483647)
+            nl = 2147483647;
+        lat[x] = (int32_t)nl;
+    }
+    free(m);
+    free(S);
+    if (n_skipped)
+        *n_skipped = skipped;
+    return ORACLE_OK;
+}

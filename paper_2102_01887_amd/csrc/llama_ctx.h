@@ -96,6 +96,7 @@ struct llama_ctx {
     t.relax_ops = max_pipe_ops < 1024 ? max_pipe_ops : 1024;
     t.relax_edges = max_pipe_edges < 3072 ? max_pipe_edges : 3072;
     t.relax_lvls = max_depth < 1024 ? max_depth : 1024;
+    t.max_pipe_ops = max_pipe_ops;
     t.pipe_off = d_pipe_off.as<int32_t>();
     t.pipe_desc = d_pipe_desc.as<int4>();
     t.lvl_bnd = d_lvl_bnd.as<int32_t>();

@@ -68,6 +68,7 @@ struct DevTables {
   // LDS capacities of the relaxation (ops, edges, levels of one pipeline);
   // larger pipelines are relaxed in global memory
   int32_t relax_ops, relax_edges, relax_lvls;
+  int32_t max_pipe_ops;      // ops of the largest pipeline
 
   // DAG
   const int32_t* pipe_off;   // [P+1] op range of each pipeline

@@ -131,36 +131,49 @@ __device__ __forceinline__ uint32_t entry_threshold(const OpScale& o, uint32_t L
 // ingest fixes it in mst, and only the thresholds change with W.  Record
 // words are assembled in registers and written as whole 16-byte chunks;
 // entries past the record go to the overflow array, ascending.
-__device__ __forceinline__ void write_op_records(const DevTables& t, int v) {
-  const int first = t.mst_first[v];
-  const int n = t.mst_first[v + 1] - first;
-  const int32_t* hdr = t.hdr + (int64_t)v * t.hs;
-  const int base = hdr[0];
-  const uint32_t fastest = (uint32_t)hdr[t.n_hw + 1];
-  const int32_t ref = t.ref[v];
-  const int64_t Wm[2] = {t.W[v], t.W[(int64_t)t.n_ops + v]};
-  if (n <= 0) return;  // every op has at least its fastest configuration
-  // all slot entries are loaded before any store (the stores could alias);
-  // the loads are unconditional (clamped index) so that they issue together
+// What an op's records need besides W: its merged-frontier range, overflow
+// offset, fastest configuration and the REC_SLOTS entries of largest latency
+// (static between latency updates, so they can be loaded ahead of W).
+struct OpStatic {
+  int first, n, base;
+  uint32_t fastest;
   uint2 e[REC_SLOTS];
+};
+
+__device__ __forceinline__ OpStatic load_op_static(const DevTables& t, int v) {
+  OpStatic o;
+  o.first = t.mst_first[v];
+  o.n = t.mst_first[v + 1] - o.first;
+  const int32_t* hdr = t.hdr + (int64_t)v * t.hs;
+  o.base = hdr[0];
+  o.fastest = (uint32_t)hdr[t.n_hw + 1];
+  // unconditional loads (clamped index) so that they issue together; every
+  // op has at least one entry (its fastest configuration)
 #pragma unroll
   for (int slot = 0; slot < REC_SLOTS; ++slot) {
-    const int j = n - 1 - slot;
-    e[slot] = t.mst[first + (j > 0 ? j : 0)];
+    const int j = o.n - 1 - slot;
+    o.e[slot] = t.mst[o.first + (j > 0 ? j : 0)];
   }
+  return o;
+}
+
+__device__ __forceinline__ void write_op_records(const DevTables& t, int v, const OpStatic& st, int32_t ref,
+                                                 int64_t Wp, int64_t Wq) {
+  const int n = st.n;
+  if (n <= 0) return;
   const int n_ovf = n - REC_SLOTS;
 #pragma unroll
   for (int mode = 0; mode < 2; ++mode) {
-    const OpScale o = op_scale(Wm[mode], ref);
+    const OpScale o = op_scale(mode ? Wq : Wp, ref);
     uint32_t w[REC_WORDS];
 #pragma unroll
     for (int k = 0; k < REC_WORDS; ++k) w[k] = 0;
-    w[0] = (uint32_t)n | (fastest << 16);
+    w[0] = (uint32_t)n | (st.fastest << 16);
 #pragma unroll
     for (int slot = 0; slot < REC_SLOTS; ++slot) {
       const bool used = slot < n;
-      w[rec_u_word(slot)] = used ? entry_threshold(o, e[slot].x) : 0x7FFFFFFFu;
-      w[rec_k_word(slot)] |= (used ? e[slot].y & 0xFFFFu : 0u) << rec_k_shift(slot);
+      w[rec_u_word(slot)] = used ? entry_threshold(o, st.e[slot].x) : 0x7FFFFFFFu;
+      w[rec_k_word(slot)] |= (used ? st.e[slot].y & 0xFFFFu : 0u) << rec_k_shift(slot);
     }
     const int64_t r = (int64_t)mode * t.n_ops + v;
     t.rec[r] = make_uint4(w[0], w[1], w[2], w[3]);
@@ -169,11 +182,11 @@ __device__ __forceinline__ void write_op_records(const DevTables& t, int v) {
     tl[1] = make_uint4(w[8], w[9], w[10], w[11]);
     tl[2] = make_uint4(w[12], w[13], w[14], w[15]);
     // entries past the record, ascending, four loads in flight at a time
-    uint2* ovf = t.ovf + (int64_t)mode * t.n_front + base;
+    uint2* ovf = t.ovf + (int64_t)mode * t.n_front + st.base;
     for (int pos = 0; pos < n_ovf; pos += 4) {
       uint2 x[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) x[u] = t.mst[first + (pos + u < n_ovf ? pos + u : n_ovf - 1)];
+      for (int u = 0; u < 4; ++u) x[u] = t.mst[st.first + (pos + u < n_ovf ? pos + u : n_ovf - 1)];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         if (pos + u >= n_ovf) break;
@@ -183,6 +196,10 @@ __device__ __forceinline__ void write_op_records(const DevTables& t, int v) {
   }
 }
 
+// RECORDS: every pipeline has at most 64 ops; lane i also writes the records
+// of the pipeline's op i, its static part loaded before the relaxation so
+// that the loads overlap the level passes.
+template <bool RECORDS>
 __global__ __launch_bounds__(64) void relax_kernel(DevTables t) {
   extern __shared__ uint64_t sDyn[];
   const int cap_ops = t.relax_ops, cap_edges = t.relax_edges, cap_lvls = t.relax_lvls;
@@ -202,6 +219,8 @@ __global__ __launch_bounds__(64) void relax_kernel(DevTables t) {
   const int l0 = d1.x, nl = d1.y;
   int64_t* WP = t.W;
   int64_t* WQ = t.W + n_ops;
+  OpStatic st;
+  if (RECORDS && tid < n) st = load_op_static(t, a + tid);
   const bool staged = n <= cap_ops && ne <= cap_edges && nl <= cap_lvls;
   if (staged) {
     // staging: RELAX_BATCH loads per lane in flight (clamped indices, so the
@@ -258,8 +277,10 @@ __global__ __launch_bounds__(64) void relax_kernel(DevTables t) {
       __syncthreads();
     }
     for (int i = tid; i < n; i += bs) {
-      WP[a + i] = sRef[i] + (int64_t)sAccP[i];
-      WQ[a + i] = sRef[i] + (int64_t)sAccQ[i];
+      const int64_t wp = sRef[i] + (int64_t)sAccP[i], wq = sRef[i] + (int64_t)sAccQ[i];
+      WP[a + i] = wp;
+      WQ[a + i] = wq;
+      if (RECORDS) write_op_records(t, a + i, st, sRef[i], wp, wq);
     }
     return;
   }
@@ -280,12 +301,57 @@ __global__ __launch_bounds__(64) void relax_kernel(DevTables t) {
     }
     __syncthreads();
   }
+  if (RECORDS && tid < n) write_op_records(t, a + tid, st, t.ref[a + tid], WP[a + tid], WQ[a + tid]);
 }
 
 // One thread per op: its records (both slack modes) from the relaxed W.
+// The workgroup's ops own one contiguous range of merged-frontier entries;
+// when it fits RECORDS_STAGE entries it is read once, coalesced, into LDS and
+// each thread takes its op's slot entries from there instead of gathering
+// them (ten scattered 8-byte loads per thread otherwise).
+constexpr int RECORDS_STAGE = 4096;
+
 __global__ __launch_bounds__(256) void op_records_kernel(DevTables t) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < t.n_ops) write_op_records(t, v);
+  __shared__ uint2 sE[RECORDS_STAGE];
+  const int v0 = blockIdx.x * blockDim.x;
+  const int v1 = min(v0 + (int)blockDim.x, t.n_ops);
+  const int v = v0 + threadIdx.x;
+  const int f0 = t.mst_first[v0], f1 = t.mst_first[v1];
+  const bool staged = f1 - f0 <= RECORDS_STAGE;
+  if (staged) {
+    const int m = f1 - f0;
+    for (int i0 = 0; i0 < m; i0 += 4 * (int)blockDim.x) {
+      uint2 x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
+        x[u] = t.mst[f0 + (i < m ? i : m - 1)];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
+        if (i < m) sE[i] = x[u];
+      }
+    }
+  }
+  __syncthreads();
+  if (v >= t.n_ops) return;
+  OpStatic st;
+  if (staged) {
+    st.first = t.mst_first[v];
+    st.n = t.mst_first[v + 1] - st.first;
+    const int32_t* hdr = t.hdr + (int64_t)v * t.hs;
+    st.base = hdr[0];
+    st.fastest = (uint32_t)hdr[t.n_hw + 1];
+#pragma unroll
+    for (int slot = 0; slot < REC_SLOTS; ++slot) {
+      const int j = st.n - 1 - slot;
+      st.e[slot] = sE[st.first - f0 + (j > 0 ? j : 0)];
+    }
+  } else {
+    st = load_op_static(t, v);
+  }
+  write_op_records(t, v, st, t.ref[v], t.W[v], t.W[(int64_t)t.n_ops + v]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1308,7 +1374,12 @@ hipError_t launch_records(const DevTables& t, int mode0, int n_modes, const int6
 
 hipError_t launch_relax(const DevTables& t, hipStream_t s) {
   if (t.n_pipelines <= 0) return hipSuccess;
-  hipLaunchKernelGGL(relax_kernel, dim3(t.n_pipelines), dim3(64), relax_lds_bytes(t), s, t);
+  if (t.max_pipe_ops <= 64) {
+    // one op per lane: records in the same launch
+    hipLaunchKernelGGL(relax_kernel<true>, dim3(t.n_pipelines), dim3(64), relax_lds_bytes(t), s, t);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(relax_kernel<false>, dim3(t.n_pipelines), dim3(64), relax_lds_bytes(t), s, t);
   if (t.n_ops > 0) hipLaunchKernelGGL(op_records_kernel, dim3(blocks_for(t.n_ops, 256)), dim3(256), 0, s, t);
   return hipGetLastError();
 }
