@@ -87,6 +87,8 @@ enum llama_scan_mode {
 /* Device error word bits (llama_stats.device_error). */
 #define LLAMA_DEVERR_INVALID_INVOCATION 1u
 #define LLAMA_DEVERR_INVALID_QUEUE_ENTRY 2u
+#define LLAMA_DEVERR_INVALID_OBSERVATION 4u
+#define LLAMA_FEEDBACK_MAX_CFG_PER_OP 4096       /* device rebuild after feedback */
 
 /* Create a context bound to HIP device `device` (its ordinal). */
 int llama_create(llama_ctx **out, int32_t device);
@@ -176,6 +178,28 @@ int llama_relax(llama_ctx *ctx, void *stream);
  * frontier tables and runs llama_relax synchronously.
  */
 int llama_update_latencies(llama_ctx *ctx, const int32_t *cfg_lat_us);
+
+/*
+ * Feedback (Sec. 3.3, Manager): update the profiled latencies from observed
+ * ones by exponential smoothing, then rebuild every table derived from them
+ * on the device and rerun the relaxation, all on `stream`.  Device pointers:
+ *   d_obs_op    [n_obs] global op id of each completed invocation
+ *   d_obs_cfg   [n_obs] the configuration it ran with (local index)
+ *   d_obs_lat   [n_obs] its observed latency (us, >= 1)
+ * beta_q16 in [0, 65536] is the smoothing factor times 65536.  The m
+ * observations of one configuration in a call, with sum S, make one step
+ * toward their mean: L' = L + floor(beta * (S - m L) / (65536 m)), clamped to
+ * [1, 2^31 - 1].  Observations out of range are left out and set
+ * LLAMA_DEVERR_INVALID_OBSERVATION.  Needs at most
+ * LLAMA_FEEDBACK_MAX_CFG_PER_OP configurations per op and fewer than 2^15 ops
+ * per pipeline (LLAMA_E_RANGE otherwise).  The first call allocates 12 bytes
+ * per configuration of scratch and copies static arrays (make it before
+ * capturing a graph); calls on one context must not overlap.  Drops the
+ * finite-alpha tables (call llama_set_alpha again).
+ */
+int llama_feedback(llama_ctx *ctx, int64_t n_obs, const int32_t *d_obs_op,
+                   const int32_t *d_obs_cfg, const int32_t *d_obs_lat, uint32_t beta_q16,
+                   void *stream);
 
 /*
  * Alg. 1 for n_inv invocations (device pointers):
@@ -331,6 +355,8 @@ int llama_get_stats(llama_ctx *ctx, llama_stats *out, int32_t reset_error);
  *             where rank is the dense rank of C/B within the op
  *   what = 3: reference latency  (int32 [n_ops])
  *   what = 4: fastest config     (int32 [n_ops], local index)
+ *   what = 5: profiled latencies (int32 [n_cfg], caller order; after
+ *             llama_feedback, the smoothed values)
  * `bytes` is the capacity of `host_out`; LLAMA_E_ARG if it is too small.
  */
 int llama_debug_export(llama_ctx *ctx, int32_t what, void *host_out, int64_t bytes);

@@ -23,6 +23,7 @@ SCHEDULE_NAMES = ("direct-1", "direct-2", "direct-4", "lds-persistent", "direct-
                   "direct-4-nt")
 DEVERR_INVALID_INVOCATION = 1
 DEVERR_INVALID_QUEUE_ENTRY = 2
+DEVERR_INVALID_OBSERVATION = 4
 
 EXPORTS = ["llama_create", "llama_destroy", "llama_last_error", "llama_set_dag",
            "llama_set_profiles", "llama_relax", "llama_update_latencies", "llama_targets",
@@ -34,7 +35,7 @@ EXPORTS = ["llama_create", "llama_destroy", "llama_last_error", "llama_set_dag",
            "llama_surrogate_fit", "llama_select_rows", "llama_serve_bytes_per_request",
            "llama_serve_open", "llama_serve_submit", "llama_serve_poll", "llama_serve_stats_get",
            "llama_serve_close", "llama_autotune", "llama_queue_time", "llama_set_alpha",
-           "llama_decide_alpha"]
+           "llama_decide_alpha", "llama_feedback"]
 
 
 class LlamaStats(ctypes.Structure):
@@ -88,6 +89,7 @@ def load_library(path=LIB_PATH):
         "llama_queue_time": [p, i64, p, p, p, p],
         "llama_set_alpha": [p, ctypes.c_uint32, ctypes.c_uint32],
         "llama_decide_alpha": [p, i64, p, p, p, p, i32, p, p, p],
+        "llama_feedback": [p, i64, p, p, p, ctypes.c_uint32, p],
         "llama_serve_open": [p, ctypes.POINTER(ServeConfig), ctypes.POINTER(p)],
         "llama_serve_submit": [p, i32, p, p, p, p, p, p, ctypes.POINTER(i32)],
         "llama_serve_poll": [p, i32, p, p, p, p, ctypes.POINTER(i32), i32],
@@ -309,6 +311,14 @@ class Llama:
             _stream(stream)))
         return out
 
+    def feedback(self, obs_op, obs_cfg, obs_lat, beta_q16, stream=None):
+        """Exponential smoothing of the profile from observations (device
+        tensors), then the device rebuild of the tables and the relaxation."""
+        n = obs_op.numel()
+        self._check("llama_feedback", self._L.llama_feedback(
+            self._ctx, n, _dp(obs_op, "int32"), _dp(obs_cfg, "int32", n), _dp(obs_lat, "int32", n),
+            int(beta_q16), _stream(stream)))
+
     def set_alpha(self, alpha_num, alpha_den=1):
         self._check("llama_set_alpha", self._L.llama_set_alpha(self._ctx, int(alpha_num), int(alpha_den)))
 
@@ -337,7 +347,7 @@ class Llama:
         n_ops, n_cfg = self.n_ops, self.n_cfg
         spec = {"W_paper": (0, np.int64, n_ops), "W_prob": (1, np.int64, n_ops),
                 "key": (2, np.uint32, n_cfg), "ref": (3, np.int32, n_ops),
-                "fastest": (4, np.int32, n_ops)}
+                "fastest": (4, np.int32, n_ops), "lat": (5, np.int32, n_cfg)}
         code, dt, n = spec[what]
         out = np.empty(n, dt)
         self._check("llama_debug_export", self._L.llama_debug_export(

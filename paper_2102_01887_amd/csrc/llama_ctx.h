@@ -66,7 +66,7 @@ struct llama_ctx {
   std::vector<int64_t> cost;
   std::vector<uint32_t> key;  // caller order
   DevBuf d_ref, d_W, d_hdr, d_front_L, d_rec, d_rec_tail, d_ovf, d_rec_q, d_rec_tail_q, d_ovf_q, d_seg_off, d_tab;
-  DevBuf d_mst, d_mst_first;
+  DevBuf d_mst, d_mst_n;
   DevBuf d_cfg_off, d_cfg_hw, d_cfg_lat, d_cfg_key, d_cfg_q;
   std::vector<int64_t> res_total;  // [n_hw] or empty
   // finite-alpha objective (llama_set_alpha)
@@ -75,7 +75,11 @@ struct llama_ctx {
   int32_t alpha_steps = 0, alpha_msteps = 0;
   DevBuf d_a_lat, d_a_pf, d_a_si, d_m_lat, d_m_pf, d_m_si;
   DevBuf d_qacc;  // Eq. 2 partial sums, QUEUE_PARTS x MAX_HW x 2 x 64 bits
-  int64_t n_mst = 0;
+  // feedback (llama_feedback): static arrays of the device rebuild, zeroed
+  // accumulators, and whether the host copy of the latencies is behind
+  bool fb_ready = false, host_stale = false;
+  int32_t fb_pow2 = 1;
+  DevBuf d_fb_keyord, d_fb_tab_src, d_fb_ref_k, d_fb_count, d_fb_sum;
   DevBuf d_err;
   llama::Surrogate surr;
   DevBuf d_cnt, d_start, d_cursor, d_perm, d_hist;  // bucketed full scan
@@ -89,7 +93,7 @@ struct llama_ctx {
     t.n_hw = n_hw;
     t.n_pipelines = n_pipelines;
     t.hs = llama::header_stride(n_hw);
-    t.n_front = n_front;
+    t.n_front = n_cfg;  // stride of the capacity layout
     t.decide_sched = decide_sched;
     t.n_cu = n_cu;
     // relaxation stage: the largest pipeline, within 1024 ops / 3072 edges
@@ -111,9 +115,8 @@ struct llama_ctx {
     t.W = d_W.as<int64_t>();
     t.hdr = d_hdr.as<int32_t>();
     t.front_L = d_front_L.as<uint2>();
-    t.n_mst = n_mst;
     t.mst = d_mst.as<uint2>();
-    t.mst_first = d_mst_first.as<int32_t>();
+    t.mst_n = d_mst_n.as<int32_t>();
     t.rec = d_rec.as<uint4>();
     t.rec_tail = d_rec_tail.as<uint4>();
     t.rec_tail_q = d_rec_tail_q.as<uint4>();
@@ -144,7 +147,7 @@ struct llama_ctx {
                            &d_succ_ids, &d_succ_q, &d_ref, &d_W, &d_hdr, &d_front_L,
                            &d_rec, &d_rec_tail, &d_ovf, &d_rec_q, &d_rec_tail_q, &d_ovf_q, &d_seg_off, &d_tab, &d_err,
                            &d_cnt, &d_start, &d_cursor, &d_perm, &d_hist, &d_mst,
-                           &d_mst_first, &d_cfg_off, &d_cfg_hw, &d_cfg_lat, &d_cfg_key, &d_cfg_q, &d_a_lat, &d_a_pf, &d_a_si, &d_m_lat, &d_m_pf, &d_m_si, &d_qacc};
+                           &d_mst_n, &d_cfg_off, &d_cfg_hw, &d_cfg_lat, &d_cfg_key, &d_cfg_q, &d_a_lat, &d_a_pf, &d_a_si, &d_m_lat, &d_m_pf, &d_m_si, &d_qacc, &d_fb_keyord, &d_fb_tab_src, &d_fb_ref_k, &d_fb_count, &d_fb_sum};
     int64_t s = 0;
     for (auto* b : all) s += (int64_t)b->bytes;
     return s;
@@ -161,4 +164,7 @@ int enter(llama_ctx* c);
 int sync_ctx(llama_ctx* c, const char* what);
 // finite-alpha tables (next_host.cpp); called by llama_set_alpha and after latency updates
 int build_alpha_tables(llama_ctx* c);
+// feedback (feedback_host.cpp): refresh the host copies of the latencies
+// after device-side feedback
+int pull_profiles(llama_ctx* c);
 }  // namespace llama

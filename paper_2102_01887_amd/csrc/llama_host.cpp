@@ -354,6 +354,8 @@ int llama_set_profiles(llama_ctx* c, int32_t n_ops, int32_t n_hw, const int32_t*
 
   c->has_prof = false;
   c->has_alpha = false;
+  c->fb_ready = false;    // the feedback arrays follow the table's shape
+  c->host_stale = false;
   c->perm_cap = 0;  // full-scan scratch is sized by the op count: regrow on demand
   if (hw_res_total) c->res_total.assign(hw_res_total, hw_res_total + n_hw);
   else c->res_total.clear();
@@ -407,6 +409,7 @@ int llama_update_latencies(llama_ctx* c, const int32_t* lat) {
       return fail(c, LLAMA_E_RANGE, "update_latencies: pipeline %d: ops * max reference latency >= 2^46", p);
   }
   c->has_prof = false;
+  c->host_stale = false;
   c->lat.assign(lat, lat + c->n_cfg);
   if ((rc = build_tables(c))) return rc;
   c->has_prof = true;
@@ -502,15 +505,18 @@ int build_tables(llama_ctx* c) {
         merged[v].push_back(e);
       }
   }
-  std::vector<int32_t> mst_first(n_ops + 1, 0);
-  for (int v = 0; v < n_ops; ++v) mst_first[v + 1] = mst_first[v] + (int32_t)merged[v].size();
-  c->n_mst = mst_first[n_ops];
-  std::vector<uint2> mst(c->n_mst);
+  // Capacity layout: every per-op structure (merged frontier, per-backend
+  // frontiers, overflow) lives inside the op's own configuration range
+  // [cfg_off[v], cfg_off[v+1]), which bounds its size, so a rebuild on the
+  // device (after feedback) never moves another op's data.
+  std::vector<int32_t> mst_n(n_ops, 0);
+  for (int v = 0; v < n_ops; ++v) mst_n[v] = (int32_t)merged[v].size();
+  std::vector<uint2> mst(c->n_cfg);
   std::vector<uint4> rec_hot((size_t)2 * n_ops), rec_tail((size_t)2 * n_ops * 3);
   for (int v = 0; v < n_ops; ++v) {
     const int n = (int)merged[v].size();
     for (int j = 0; j < n; ++j) {
-      mst[mst_first[v] + j] = merged[v][j];
+      mst[c->cfg_off[v] + j] = merged[v][j];
     }
     uint32_t w[llama::REC_WORDS] = {0};
     w[0] = (uint32_t)n | ((uint32_t)c->fastest[v] << 16);
@@ -528,17 +534,19 @@ int build_tables(llama_ctx* c) {
 
   // Pass 2: frontier offsets and headers.
   std::vector<int32_t> hdr((size_t)n_ops * hs, 0);
-  int64_t pos = 0;
+  int64_t n_entries = 0;
   for (int v = 0; v < n_ops; ++v) {
+    int64_t pos = c->cfg_off[v];
     for (int h = 0; h < n_hw; ++h) {
       hdr[(size_t)v * hs + h] = (int32_t)pos;
       pos += front_cnt[(size_t)v * n_hw + h];
     }
     hdr[(size_t)v * hs + n_hw] = (int32_t)pos;
     hdr[(size_t)v * hs + n_hw + 1] = c->fastest[v];
+    n_entries += pos - c->cfg_off[v];
   }
-  if (pos > INT32_MAX) return fail(c, LLAMA_E_RANGE, "set_profiles: frontier too large");
-  c->n_front = pos;
+  c->n_front = n_entries;
+  const int64_t pos = c->n_cfg;  // capacity of the frontier and overflow arrays
   std::vector<uint2> front_L(pos);
 #pragma omp parallel for schedule(dynamic, 64)
   for (int v = 0; v < n_ops; ++v)
@@ -553,7 +561,7 @@ int build_tables(llama_ctx* c) {
       (rc = upload_vec(c, c->d_rec, rec_hot, "records")) ||
       (rc = upload_vec(c, c->d_rec_tail, rec_tail, "record tails")) ||
       (rc = upload_vec(c, c->d_mst, mst, "merged frontier")) ||
-      (rc = upload_vec(c, c->d_mst_first, mst_first, "merged frontier offsets")) ||
+      (rc = upload_vec(c, c->d_mst_n, mst_n, "merged frontier sizes")) ||
       (rc = upload(c, c->d_ovf, nullptr, sizeof(uint2) * 2 * (size_t)pos, "record overflow")) ||
       (rc = upload(c, c->d_rec_q, nullptr, sizeof(uint4) * (size_t)n_ops, "records (queue)")) ||
       (rc = upload(c, c->d_rec_tail_q, nullptr, sizeof(uint4) * 3 * (size_t)n_ops, "record tails (queue)")) ||
@@ -781,6 +789,7 @@ int llama_debug_export(llama_ctx* c, int32_t what, void* out, int64_t bytes) {
   if (rc) return rc;
   if (!out) return fail(c, LLAMA_E_ARG, "debug_export: null pointer");
   if (!c->has_prof) return fail(c, LLAMA_E_STATE, "debug_export: no profiles");
+  if ((rc = llama::pull_profiles(c))) return rc;
   const void* src = nullptr;
   int64_t need = 0;
   bool device = false;
@@ -790,6 +799,7 @@ int llama_debug_export(llama_ctx* c, int32_t what, void* out, int64_t bytes) {
     case 2: src = c->key.data(); need = 4ll * c->n_cfg; break;
     case 3: src = c->ref.data(); need = 4ll * c->n_ops; break;
     case 4: src = c->fastest.data(); need = 4ll * c->n_ops; break;
+    case 5: src = c->lat.data(); need = 4ll * c->n_cfg; break;
     default: return fail(c, LLAMA_E_ARG, "debug_export: unknown table %d", what);
   }
   if (bytes < need) return fail(c, LLAMA_E_ARG, "debug_export: need %lld bytes", (long long)need);

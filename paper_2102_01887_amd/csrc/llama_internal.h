@@ -62,7 +62,7 @@ struct DevTables {
   int32_t n_hw;
   int32_t n_pipelines;
   int32_t hs;              // header_stride(n_hw)
-  int64_t n_front;         // frontier entries (all ops, all backends)
+  int64_t n_front;         // capacity of the frontier and overflow arrays (n_cfg)
   int32_t decide_sched;    // DecideSchedule of the indexed decision
   int32_t n_cu;            // compute units of the device
   // LDS capacities of the relaxation (ops, edges, levels of one pipeline);
@@ -87,9 +87,8 @@ struct DevTables {
   int64_t* W;                // [2*n_ops] remaining worst-path latency: PAPER rows, then PROB rows
   const int32_t* hdr;        // [n_ops*hs] frontier offsets per backend + fastest (local index)
   const uint2* front_L;      // [n_front] {latency, key}: per (op, backend), latency ascending, key strictly descending
-  int64_t n_mst;              // entries of the queue-free merged frontiers (all ops)
-  const uint2* mst;          // [n_mst] {L, key}, per op ascending in L
-  const int32_t* mst_first;  // [n_ops+1] first entry of each op
+  const uint2* mst;          // [n_cfg] {L, key}, per op ascending in L from cfg_off[v]
+  const int32_t* mst_n;      // [n_ops] entries of each op's merged frontier
   uint4* rec;                // [2*n_ops] record words 0..3, PAPER then PROB, queue = 0
   uint4* rec_tail;           // [2*n_ops*3] record words 4..15
   uint2* ovf;                // [2*n_front] full frontiers {T, key} ascending, PAPER then PROB
@@ -160,6 +159,30 @@ struct ResTotals {
 hipError_t launch_queue_time(const DevTables& t, int64_t n, const int32_t* q_op, const int32_t* q_cfg,
                              unsigned long long* part, const ResTotals& rt, int64_t* out, hipStream_t s);
 hipError_t launch_decide_alpha(const DevTables& t, const Batch& b, hipStream_t s);
+
+// Feedback: smoothing of the profiled latencies from observations, then the
+// device rebuild of every latency-derived table (reference latencies,
+// fastest configurations, per-backend and merged frontiers, the full table).
+constexpr uint32_t DEVERR_OBSERVATION = 4u;  // device error bit: observation out of range
+constexpr int FEEDBACK_MAX_CFG = 4096;        // configurations per op the rebuild sorts in LDS
+struct FeedbackArgs {
+  int32_t* lat;              // [n_cfg] profiled latency, caller order (updated)
+  uint32_t* count;           // [n_cfg] observations per configuration (zero between calls)
+  unsigned long long* sum;   // [n_cfg] their sum (zero between calls)
+  const uint16_t* keyord;    // [n_cfg] position of the configuration's key among its op's keys
+  const int32_t* ref_k;      // [n_ops] reference configuration (local index)
+  const int32_t* tab_src;    // [n_cfg] caller row of each position of tab
+  int32_t* ref;              // [n_ops]
+  int32_t* hdr;              // [n_ops * hs]
+  uint2* front;              // [n_cfg] per-backend frontiers (capacity layout)
+  uint2* mst;                // [n_cfg] merged frontiers (capacity layout)
+  int32_t* mst_n;            // [n_ops]
+  uint2* tab;                // [n_cfg]
+  uint4* cfg_q;              // [n_cfg] or nullptr
+  int32_t max_pow2;          // smallest power of two >= the largest op's configuration count
+};
+hipError_t launch_feedback(const DevTables& t, const FeedbackArgs& f, int64_t n, const int32_t* obs_op,
+                           const int32_t* obs_cfg, const int32_t* obs_lat, uint32_t beta_q16, hipStream_t s);
 hipError_t launch_select_rows(const DevTables& t, const Batch& b, const int32_t* lat, int64_t stride,
                               hipStream_t s);
 

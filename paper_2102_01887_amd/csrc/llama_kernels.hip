@@ -142,8 +142,8 @@ struct OpStatic {
 
 __device__ __forceinline__ OpStatic load_op_static(const DevTables& t, int v) {
   OpStatic o;
-  o.first = t.mst_first[v];
-  o.n = t.mst_first[v + 1] - o.first;
+  o.first = t.cfg_off[v];
+  o.n = t.mst_n[v];
   const int32_t* hdr = t.hdr + (int64_t)v * t.hs;
   o.base = hdr[0];
   o.fastest = (uint32_t)hdr[t.n_hw + 1];
@@ -305,52 +305,10 @@ __global__ __launch_bounds__(64) void relax_kernel(DevTables t) {
 }
 
 // One thread per op: its records (both slack modes) from the relaxed W.
-// The workgroup's ops own one contiguous range of merged-frontier entries;
-// when it fits RECORDS_STAGE entries it is read once, coalesced, into LDS and
-// each thread takes its op's slot entries from there instead of gathering
-// them (ten scattered 8-byte loads per thread otherwise).
-constexpr int RECORDS_STAGE = 4096;
-
 __global__ __launch_bounds__(256) void op_records_kernel(DevTables t) {
-  __shared__ uint2 sE[RECORDS_STAGE];
-  const int v0 = blockIdx.x * blockDim.x;
-  const int v1 = min(v0 + (int)blockDim.x, t.n_ops);
-  const int v = v0 + threadIdx.x;
-  const int f0 = t.mst_first[v0], f1 = t.mst_first[v1];
-  const bool staged = f1 - f0 <= RECORDS_STAGE;
-  if (staged) {
-    const int m = f1 - f0;
-    for (int i0 = 0; i0 < m; i0 += 4 * (int)blockDim.x) {
-      uint2 x[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
-        x[u] = t.mst[f0 + (i < m ? i : m - 1)];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
-        if (i < m) sE[i] = x[u];
-      }
-    }
-  }
-  __syncthreads();
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= t.n_ops) return;
-  OpStatic st;
-  if (staged) {
-    st.first = t.mst_first[v];
-    st.n = t.mst_first[v + 1] - st.first;
-    const int32_t* hdr = t.hdr + (int64_t)v * t.hs;
-    st.base = hdr[0];
-    st.fastest = (uint32_t)hdr[t.n_hw + 1];
-#pragma unroll
-    for (int slot = 0; slot < REC_SLOTS; ++slot) {
-      const int j = st.n - 1 - slot;
-      st.e[slot] = sE[st.first - f0 + (j > 0 ? j : 0)];
-    }
-  } else {
-    st = load_op_static(t, v);
-  }
+  const OpStatic st = load_op_static(t, v);
   write_op_records(t, v, st, t.ref[v], t.W[v], t.W[(int64_t)t.n_ops + v]);
 }
 
@@ -1350,6 +1308,203 @@ __global__ __launch_bounds__(256) void decide_alpha_merged_kernel(DevTables t, B
   if (b.flag) b.flag[i] = meets;
 }
 
+// ---------------------------------------------------------------------------
+// Feedback (exponential smoothing of the profile, then the table rebuild).
+//   feedback_accumulate_kernel  count and sum of each configuration's
+//                               observations (atomics into zeroed scratch)
+//   feedback_apply_kernel       one smoothing step per observed configuration,
+//                               taken by the observation that finds the count
+//                               non-zero (and resets count and sum to zero)
+//   retable_kernel              per op (one wavefront): sort by (backend, L,
+//                               key) in LDS, per-backend frontiers by a
+//                               segmented prefix minimum; sort by (L, key),
+//                               merged frontier; header, fastest, reference
+//   retab_kernel                the full table's latencies and the queue records
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void feedback_accumulate_kernel(DevTables t, FeedbackArgs f, int64_t n,
+                                                                  const int32_t* op, const int32_t* cfg,
+                                                                  const int32_t* obs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int v = op[i], k = cfg[i], o = obs[i];
+  if ((unsigned)v >= (unsigned)t.n_ops || o < 1 || (unsigned)k >= (unsigned)(t.cfg_off[v + 1] - t.cfg_off[v])) {
+    atomicOr(t.err, DEVERR_OBSERVATION);
+    return;
+  }
+  const int x = t.cfg_off[v] + k;
+  atomicAdd(&f.count[x], 1u);
+  atomicAdd(&f.sum[x], (unsigned long long)o);
+}
+
+// L' = L + floor(beta * (S - m L) / (2^16 m)), clamped to [1, 2^31 - 1], in
+// 64-bit integers: with D = S - m L = m t1 + r (0 <= r < m) and
+// beta t1 = 2^16 a + b (0 <= b < 2^16), the step is
+// a + [b m + beta r >= 2^16 m] (the bracket's left side is below 2^17 m).
+__global__ __launch_bounds__(256) void feedback_apply_kernel(DevTables t, FeedbackArgs f, int64_t n, const int32_t* op,
+                                                             const int32_t* cfg, const int32_t* obs, uint32_t beta) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int v = op[i], k = cfg[i], o = obs[i];
+  if ((unsigned)v >= (unsigned)t.n_ops || o < 1 || (unsigned)k >= (unsigned)(t.cfg_off[v + 1] - t.cfg_off[v])) return;
+  const int x = t.cfg_off[v] + k;
+  const uint32_t m = atomicExch(&f.count[x], 0u);
+  if (m == 0) return;  // another observation of x applied the step
+  const int64_t S = (int64_t)atomicExch(&f.sum[x], 0ull);
+  const int64_t L = f.lat[x];
+  const int64_t mm = m;
+  const int64_t D = S - mm * L;
+  int64_t t1 = D / mm, r = D - t1 * mm;
+  if (r < 0) {
+    t1 -= 1;
+    r += mm;
+  }
+  const int64_t u = (int64_t)beta * t1;
+  int64_t a = u >> 16;  // floor division by 2^16 (arithmetic shift)
+  const int64_t b = u - (a << 16);
+  if (b * mm + (int64_t)beta * r >= (mm << 16)) a += 1;
+  int64_t nl = L + a;
+  nl = nl < 1 ? 1 : (nl > INT32_MAX_64 ? INT32_MAX_64 : nl);
+  f.lat[x] = (int32_t)nl;
+}
+
+__device__ __forceinline__ void lds_bitonic_sort(uint64_t* a, int P) {
+  const int lane = threadIdx.x;
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = lane; i < P; i += 64) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t x = a[i], y = a[ixj];
+          const bool up = (i & k) == 0;
+          if ((x > y) == up) {
+            a[i] = y;
+            a[ixj] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <int NHW>
+__global__ __launch_bounds__(64) void retable_kernel(DevTables t, FeedbackArgs f) {
+  extern __shared__ uint64_t sS[];
+  uint32_t* sKey = reinterpret_cast<uint32_t*>(sS + f.max_pow2);
+  const int v = blockIdx.x, lane = threadIdx.x;
+  const int a = t.cfg_off[v], n = t.cfg_off[v + 1] - a;
+  int P = 1;
+  while (P < n) P <<= 1;
+  const int rk = f.ref_k[v];
+  uint64_t fast = ~0ull;
+  for (int i = lane; i < P; i += 64) {
+    if (i < n) {
+      const int x = a + i;
+      const uint32_t L = (uint32_t)f.lat[x], ko = f.keyord[x];
+      sKey[ko] = t.cfg_key[x];
+      sS[i] = ((uint64_t)(uint32_t)t.cfg_hw[x] << 43) | ((uint64_t)L << 12) | ko;
+      const uint64_t c = ((uint64_t)L << 16) | (uint32_t)i;  // fastest: smallest L, lowest index
+      fast = c < fast ? c : fast;
+      if (i == rk) f.ref[v] = (int32_t)L;
+    } else {
+      sS[i] = ~0ull;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t o = __shfl_xor(fast, off, 64);
+    fast = o < fast ? o : fast;
+  }
+  __syncthreads();
+  lds_bitonic_sort(sS, P);
+  // per-backend frontiers: entries sorted by (backend, L, key); an entry
+  // survives if its key is below every earlier key of its backend
+  constexpr uint32_t INF = 0xFFFFFFFFu;
+  int cnt = 0;
+  int hcnt[NHW];
+#pragma unroll
+  for (int h = 0; h < NHW; ++h) hcnt[h] = 0;
+  uint32_t carry_hw = INF, carry_val = INF;
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  for (int c0 = 0; c0 < n; c0 += 64) {
+    const int i = c0 + lane;
+    const bool valid = i < n;
+    const uint64_t e = valid ? sS[i] : ~0ull;
+    const uint32_t hw = valid ? (uint32_t)(e >> 43) : INF - 1;
+    const uint32_t ko = (uint32_t)(e & 0xFFFu);
+    uint32_t incl = valid ? ko : INF;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t o = __shfl_up(incl, d, 64);
+      const uint32_t ohw = __shfl_up(hw, d, 64);
+      if (lane >= d && ohw == hw && o < incl) incl = o;
+    }
+    if (hw == carry_hw && carry_val < incl) incl = carry_val;
+    const uint32_t pincl = __shfl_up(incl, 1, 64), phw = __shfl_up(hw, 1, 64);
+    const uint32_t excl = (lane > 0 && phw == hw) ? pincl : (hw == carry_hw ? carry_val : INF);
+    const bool surv = valid && ko < excl;
+    const uint64_t mask = __ballot(surv);
+    if (surv) {
+      const int pos = __popcll(mask & below);
+      f.front[a + cnt + pos] = make_uint2((uint32_t)((e >> 12) & 0x7FFFFFFFu), sKey[ko]);
+    }
+    cnt += __popcll(mask);
+#pragma unroll
+    for (int h = 0; h < NHW; ++h) hcnt[h] += __popcll(__ballot(surv && hw == (uint32_t)h));
+    carry_hw = __shfl(hw, 63, 64);
+    carry_val = __shfl(incl, 63, 64);
+  }
+  if (lane == 0) {
+    int32_t* hd = f.hdr + (int64_t)v * t.hs;
+    int pos = a;
+#pragma unroll
+    for (int h = 0; h < NHW; ++h) {
+      hd[h] = pos;
+      pos += hcnt[h];
+    }
+    hd[NHW] = pos;
+    hd[NHW + 1] = (int32_t)(fast & 0xFFFFu);
+  }
+  // merged frontier over all backends: drop the backend, sort by (L, key)
+  __syncthreads();
+  for (int i = lane; i < n; i += 64) sS[i] &= (1ull << 43) - 1;
+  __syncthreads();
+  lds_bitonic_sort(sS, P);
+  int cnt_m = 0;
+  uint32_t carry = INF;
+  for (int c0 = 0; c0 < n; c0 += 64) {
+    const int i = c0 + lane;
+    const bool valid = i < n;
+    const uint64_t e = valid ? sS[i] : ~0ull;
+    const uint32_t ko = (uint32_t)(e & 0xFFFu);
+    uint32_t incl = valid ? ko : INF;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t o = __shfl_up(incl, d, 64);
+      if (lane >= d && o < incl) incl = o;
+    }
+    if (carry < incl) incl = carry;
+    const uint32_t pincl = __shfl_up(incl, 1, 64);
+    const uint32_t excl = lane > 0 ? pincl : carry;
+    const bool surv = valid && ko < excl;
+    const uint64_t mask = __ballot(surv);
+    if (surv) {
+      const int pos = __popcll(mask & below);
+      f.mst[a + cnt_m + pos] = make_uint2((uint32_t)((e >> 12) & 0x7FFFFFFFu), sKey[ko]);
+    }
+    cnt_m += __popcll(mask);
+    carry = __shfl(incl, 63, 64);
+  }
+  if (lane == 0) f.mst_n[v] = cnt_m;
+}
+
+__global__ __launch_bounds__(256) void retab_kernel(DevTables t, FeedbackArgs f) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= t.n_front) return;  // n_front = n_cfg
+  f.tab[i].x = (uint32_t)f.lat[f.tab_src[i]];
+  if (f.cfg_q) f.cfg_q[i].x = (uint32_t)f.lat[i];
+}
+
 #define LLAMA_DISPATCH_NHW(KERNEL, GRID, BLOCK, STREAM, ...)                         \
   switch (t.n_hw) {                                                                  \
     case 1: hipLaunchKernelGGL(KERNEL<1>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
@@ -1404,6 +1559,27 @@ hipError_t launch_queue_time(const DevTables& t, int64_t n, const int32_t* q_op,
     LLAMA_DISPATCH_NHW(queue_accumulate_kernel, dim3((unsigned)blocks), dim3(256), s, t, n, q_op, q_cfg, part);
   hipLaunchKernelGGL(queue_finalize_kernel, dim3(1), dim3(1024), 0, s, (const unsigned long long*)part, (int)blocks,
                      rt, t.n_hw, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_feedback(const DevTables& t, const FeedbackArgs& f, int64_t n, const int32_t* obs_op,
+                           const int32_t* obs_cfg, const int32_t* obs_lat, uint32_t beta_q16, hipStream_t s) {
+  if (n > 0) {
+    hipLaunchKernelGGL(feedback_accumulate_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, t, f, n, obs_op,
+                       obs_cfg, obs_lat);
+    hipLaunchKernelGGL(feedback_apply_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, t, f, n, obs_op, obs_cfg,
+                       obs_lat, beta_q16);
+  }
+  const size_t lds = (sizeof(uint64_t) + sizeof(uint32_t)) * (size_t)f.max_pow2;
+  switch (t.n_hw) {
+#define LLAMA_RETABLE(NH) \
+  case NH: hipLaunchKernelGGL(retable_kernel<NH>, dim3(t.n_ops), dim3(64), lds, s, t, f); break;
+    LLAMA_RETABLE(1) LLAMA_RETABLE(2) LLAMA_RETABLE(3) LLAMA_RETABLE(4)
+    LLAMA_RETABLE(5) LLAMA_RETABLE(6) LLAMA_RETABLE(7) LLAMA_RETABLE(8)
+#undef LLAMA_RETABLE
+    default: return hipErrorInvalidValue;
+  }
+  if (t.n_front > 0) hipLaunchKernelGGL(retab_kernel, dim3(blocks_for(t.n_front, 256)), dim3(256), 0, s, t, f);
   return hipGetLastError();
 }
 

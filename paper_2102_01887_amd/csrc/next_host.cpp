@@ -206,6 +206,7 @@ int llama_set_alpha(llama_ctx* c, uint32_t alpha_num, uint32_t alpha_den) {
   if ((int)c->res_total.size() != c->n_hw)
     return llama::fail(c, LLAMA_E_STATE, "set_alpha: the profiles carry no hw_res_total");
   if (alpha_den < 1) return llama::fail(c, LLAMA_E_ARG, "set_alpha: alpha_den must be >= 1");
+  if ((rc = llama::pull_profiles(c))) return rc;
   c->has_alpha = false;
   c->alpha_num = alpha_num;
   c->alpha_den = alpha_den;
