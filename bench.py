@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--no-next1", action="store_true",
                     help="skip the queueing-time + finite-alpha section")
     ap.add_argument("--queue-entries", type=int, default=1_000_000)
+    ap.add_argument("--no-next2", action="store_true", help="skip the feedback section")
+    ap.add_argument("--feedback-obs", type=int, default=100_000)
     ap.add_argument("--next1-sample", type=int, default=50_000)
     ap.add_argument("--kernel-reps", type=int, default=50,
                     help="launches per graph when timing single kernels")
@@ -181,6 +183,61 @@ def bench_next1(args, torch, B, wl, log, w, op, el, slo, mode):
             "bit_exact": exact,
             "parity_sample": f"Q exactly; decisions of the first {sample.stop} invocations, "
                              f"with and without the queueing times"}
+
+
+def bench_next2(args, torch, B, wl, log, w, op, el, slo, mode):
+    """Feedback: smoothing of the profile from a batch of observations and the
+    device rebuild of the tables, then the decision of the invocation batch;
+    parity of one call against the oracle (latencies exactly, decisions on a
+    sample)."""
+    import numpy as np
+    import oracle
+    n = w.n_inv
+    rng = np.random.default_rng(23)
+    n_obs = args.feedback_obs
+    ob = [torch.from_numpy(a).cuda() for a in wl.observations(w, rng, n_obs)]
+    beta = 13107  # 0.2
+    L = B.Llama(0).load(w)
+    s = torch.cuda.Stream()
+    cfg = torch.empty(n, dtype=torch.int32, device="cuda")
+    flag = torch.empty(n, dtype=torch.uint8, device="cuda")
+    with torch.cuda.stream(s):
+        L.feedback(*ob, beta, stream=s)
+        L.decide(op, el, slo, None, mode, B.SCAN_INDEXED, cfg, flag, stream=s)
+    torch.cuda.synchronize()
+    lat_or, _ = oracle.feedback(*(a.cpu().numpy() for a in ob), w.cfg_off, w.lat, beta)
+    w2 = w.with_invocations(w.inv_op, w.elapsed, w.slo)
+    w2.lat = lat_or
+    sample = slice(0, min(n, args.next1_sample))
+    c_or, f_or = oracle.Problem(w2).decide(mode, sl=sample)
+    exact = bool(np.array_equal(L.export("lat"), lat_or)
+                 and np.array_equal(cfg.cpu().numpy()[sample], c_or)
+                 and np.array_equal(flag.cpu().numpy()[sample], f_or))
+
+    def fb():
+        L.feedback(*ob, beta, stream=s)
+
+    def step():
+        fb()
+        L.decide(op, el, slo, None, mode, B.SCAN_INDEXED, cfg, flag, stream=s)
+
+    reps = max(1, args.kernel_reps // 5)
+    ms_fb = time_graph(torch, s, graph_of(torch, s, fb, reps), 3) / reps
+    ms_step = time_graph(torch, s, graph_of(torch, s, step, reps), 3) / reps
+    # bytes of the rebuild per configuration: L, key, backend, key order read
+    # (14 B), frontier, merged-frontier and full-table writes (8 + 8 + 4 B)
+    rb_bytes = w.n_cfg * 34
+    log(f"bench: next2 feedback {ms_fb * 1e3:.1f} us, step {ms_step * 1e3:.1f} us, exact {exact}")
+    return {"observations": n_obs, "beta_q16": beta,
+            "ms_feedback": ms_fb, "ms_per_step": ms_step,
+            "decisions_per_s": n / (ms_step * 1e-3), "observations_per_s": n_obs / (ms_fb * 1e-3),
+            "step": "feedback (smoothing + table rebuild + relaxation) + decide",
+            "rebuild_roofline": {"bound": "hbm", "achieved": rb_bytes / (ms_fb * 1e-3) / 1e9,
+                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": rb_bytes / (ms_fb * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                 "note": "whole feedback call, 34 B per configuration"},
+            "bit_exact": exact,
+            "parity_sample": f"latencies exactly; decisions of the first {sample.stop} invocations"}
 
 
 def bench_surrogate(args, torch, B, wl, log):
@@ -472,6 +529,9 @@ def main():
     next1 = None
     if not args.no_next1:
         next1 = bench_next1(args, torch, B, wl, log, w, op, el, slo, mode)
+    next2 = None
+    if not args.no_next2:
+        next2 = bench_next2(args, torch, B, wl, log, w, op, el, slo, mode)
     surr = None
     args._surrogate_ctx = None
     if not args.no_surrogate:
@@ -520,6 +580,7 @@ def main():
                       "decisions_per_s": n / (ms_wave * 1e-3)},
         "frontier_entries": st["frontier_entries"],
         "next1": next1,
+        "next2": next2,
         "surrogate": surr,
         "serving": serve,
     }

@@ -88,7 +88,6 @@ enum llama_scan_mode {
 #define LLAMA_DEVERR_INVALID_INVOCATION 1u
 #define LLAMA_DEVERR_INVALID_QUEUE_ENTRY 2u
 #define LLAMA_DEVERR_INVALID_OBSERVATION 4u
-#define LLAMA_FEEDBACK_MAX_CFG_PER_OP 4096       /* device rebuild after feedback */
 
 /* Create a context bound to HIP device `device` (its ordinal). */
 int llama_create(llama_ctx **out, int32_t device);
@@ -190,9 +189,9 @@ int llama_update_latencies(llama_ctx *ctx, const int32_t *cfg_lat_us);
  * observations of one configuration in a call, with sum S, make one step
  * toward their mean: L' = L + floor(beta * (S - m L) / (65536 m)), clamped to
  * [1, 2^31 - 1].  Observations out of range are left out and set
- * LLAMA_DEVERR_INVALID_OBSERVATION.  Needs at most
- * LLAMA_FEEDBACK_MAX_CFG_PER_OP configurations per op and fewer than 2^15 ops
- * per pipeline (LLAMA_E_RANGE otherwise).  The first call allocates 12 bytes
+ * LLAMA_DEVERR_INVALID_OBSERVATION.  Only the ops with an observation are
+ * rebuilt.  Needs fewer than 2^15 ops per pipeline (LLAMA_E_RANGE
+ * otherwise), so that any latencies keep path sums below 2^46.  The first call allocates 12 bytes
  * per configuration of scratch and copies static arrays (make it before
  * capturing a graph); calls on one context must not overlap.  Drops the
  * finite-alpha tables (call llama_set_alpha again).

@@ -3,7 +3,8 @@
 // static helper arrays of the device rebuild, and the launches.  Implements
 // llama_feedback of include/llama.h.
 //
-// After the smoothing, every latency-derived table is rebuilt on the device
+// After the smoothing, every latency-derived table of the ops that had an
+// observation is rebuilt on the device
 // (reference latencies, fastest configurations, per-backend and merged
 // frontiers, the full table's latencies) and the relaxation runs, so that the
 // next decision uses the new profile.  The host copy of the latencies is
@@ -25,36 +26,31 @@ int prepare_feedback(llama_ctx* c) {
   if (c->fb_ready) return LLAMA_OK;
   const int n_ops = c->n_ops, n_hw = c->n_hw;
   const int64_t n_cfg = c->n_cfg;
-  std::vector<uint16_t> keyord(n_cfg);
+  std::vector<int32_t> ksrc(n_cfg);
   std::vector<int32_t> tab_src(n_cfg);
-  int max_n = 1;
   for (int v = 0; v < n_ops; ++v) {
-    const int a = c->cfg_off[v], b = c->cfg_off[v + 1], n = b - a;
-    max_n = std::max(max_n, n);
-    std::vector<int32_t> idx(n);
-    std::iota(idx.begin(), idx.end(), 0);
-    std::sort(idx.begin(), idx.end(), [&](int32_t p, int32_t q) { return c->key[a + p] < c->key[a + q]; });
-    for (int i = 0; i < n; ++i) keyord[a + idx[i]] = (uint16_t)i;
+    const int a = c->cfg_off[v], b = c->cfg_off[v + 1];
+    std::iota(ksrc.begin() + a, ksrc.begin() + b, a);
+    std::sort(ksrc.begin() + a, ksrc.begin() + b, [&](int32_t p, int32_t q) { return c->key[p] < c->key[q]; });
     // the full table's order: grouped by backend, caller order inside
     std::vector<int32_t> cnt(n_hw + 1, 0);
     for (int x = a; x < b; ++x) cnt[c->hw[x] + 1]++;
     for (int h = 0; h < n_hw; ++h) cnt[h + 1] += cnt[h];
     for (int x = a; x < b; ++x) tab_src[a + cnt[c->hw[x]]++] = x;
   }
-  int p2 = 1;
-  while (p2 < max_n) p2 <<= 1;
   int rc;
-  if ((rc = upload(c, c->d_fb_keyord, keyord.data(), keyord.size() * 2, "feedback key order")) ||
+  if ((rc = upload(c, c->d_fb_ksrc, ksrc.data(), ksrc.size() * 4, "feedback key order")) ||
       (rc = upload(c, c->d_fb_tab_src, tab_src.data(), tab_src.size() * 4, "feedback table order")) ||
       (rc = upload(c, c->d_fb_ref_k, c->ref_k.data(), c->ref_k.size() * 4, "feedback reference configs")) ||
       (rc = upload(c, c->d_fb_count, nullptr, 4 * (size_t)n_cfg, "feedback counts")) ||
-      (rc = upload(c, c->d_fb_sum, nullptr, 8 * (size_t)n_cfg, "feedback sums")))
+      (rc = upload(c, c->d_fb_sum, nullptr, 8 * (size_t)n_cfg, "feedback sums")) ||
+      (rc = upload(c, c->d_fb_dirty, nullptr, 4 * (size_t)n_ops, "feedback op flags")))
     return rc;
   hipError_t e = hipMemsetAsync(c->d_fb_count.p, 0, 4 * (size_t)n_cfg, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->d_fb_sum.p, 0, 8 * (size_t)n_cfg, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->d_fb_dirty.p, 0, 4 * (size_t)n_ops, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "feedback scratch");
   if ((rc = sync_ctx(c, "feedback set-up"))) return rc;
-  c->fb_pow2 = p2;
   c->fb_ready = true;
   return LLAMA_OK;
 }
@@ -92,10 +88,6 @@ int llama_feedback(llama_ctx* c, int64_t n, const int32_t* obs_op, const int32_t
   if (n > 0 && (!obs_op || !obs_cfg || !obs_lat)) return llama::fail(c, LLAMA_E_ARG, "feedback: null pointer");
   if (beta_q16 > 65536u) return llama::fail(c, LLAMA_E_ARG, "feedback: beta_q16 above 65536");
   if (n > INT32_MAX) return llama::fail(c, LLAMA_E_RANGE, "feedback: more than 2^31-1 observations");
-  for (int v = 0; v < c->n_ops; ++v)
-    if (c->cfg_off[v + 1] - c->cfg_off[v] > llama::FEEDBACK_MAX_CFG)
-      return llama::fail(c, LLAMA_E_RANGE, "feedback: op %d has more than %d configurations", v,
-                         llama::FEEDBACK_MAX_CFG);
   if (c->max_pipe_ops >= (1 << 15))
     return llama::fail(c, LLAMA_E_RANGE, "feedback: a pipeline has 2^15 or more ops");
   if ((rc = llama::prepare_feedback(c))) return rc;
@@ -104,7 +96,8 @@ int llama_feedback(llama_ctx* c, int64_t n, const int32_t* obs_op, const int32_t
   f.lat = c->d_cfg_lat.as<int32_t>();
   f.count = c->d_fb_count.as<uint32_t>();
   f.sum = c->d_fb_sum.as<unsigned long long>();
-  f.keyord = c->d_fb_keyord.as<uint16_t>();
+  f.dirty = c->d_fb_dirty.as<uint32_t>();
+  f.ksrc = c->d_fb_ksrc.as<int32_t>();
   f.ref_k = c->d_fb_ref_k.as<int32_t>();
   f.tab_src = c->d_fb_tab_src.as<int32_t>();
   f.ref = c->d_ref.as<int32_t>();
@@ -114,7 +107,6 @@ int llama_feedback(llama_ctx* c, int64_t n, const int32_t* obs_op, const int32_t
   f.mst_n = c->d_mst_n.as<int32_t>();
   f.tab = c->d_tab.as<uint2>();
   f.cfg_q = c->d_cfg_q.p ? c->d_cfg_q.as<uint4>() : nullptr;
-  f.max_pow2 = c->fb_pow2;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = llama::launch_feedback(t, f, n, obs_op, obs_cfg, obs_lat, beta_q16, s);
   if (e == hipSuccess) e = llama::launch_relax(t, s);

@@ -78,8 +78,7 @@ struct llama_ctx {
   // feedback (llama_feedback): static arrays of the device rebuild, zeroed
   // accumulators, and whether the host copy of the latencies is behind
   bool fb_ready = false, host_stale = false;
-  int32_t fb_pow2 = 1;
-  DevBuf d_fb_keyord, d_fb_tab_src, d_fb_ref_k, d_fb_count, d_fb_sum;
+  DevBuf d_fb_ksrc, d_fb_tab_src, d_fb_ref_k, d_fb_count, d_fb_sum, d_fb_dirty;
   DevBuf d_err;
   llama::Surrogate surr;
   DevBuf d_cnt, d_start, d_cursor, d_perm, d_hist;  // bucketed full scan
@@ -147,7 +146,7 @@ struct llama_ctx {
                            &d_succ_ids, &d_succ_q, &d_ref, &d_W, &d_hdr, &d_front_L,
                            &d_rec, &d_rec_tail, &d_ovf, &d_rec_q, &d_rec_tail_q, &d_ovf_q, &d_seg_off, &d_tab, &d_err,
                            &d_cnt, &d_start, &d_cursor, &d_perm, &d_hist, &d_mst,
-                           &d_mst_n, &d_cfg_off, &d_cfg_hw, &d_cfg_lat, &d_cfg_key, &d_cfg_q, &d_a_lat, &d_a_pf, &d_a_si, &d_m_lat, &d_m_pf, &d_m_si, &d_qacc, &d_fb_keyord, &d_fb_tab_src, &d_fb_ref_k, &d_fb_count, &d_fb_sum};
+                           &d_mst_n, &d_cfg_off, &d_cfg_hw, &d_cfg_lat, &d_cfg_key, &d_cfg_q, &d_a_lat, &d_a_pf, &d_a_si, &d_m_lat, &d_m_pf, &d_m_si, &d_qacc, &d_fb_ksrc, &d_fb_tab_src, &d_fb_ref_k, &d_fb_count, &d_fb_sum, &d_fb_dirty};
     int64_t s = 0;
     for (auto* b : all) s += (int64_t)b->bytes;
     return s;

@@ -164,12 +164,12 @@ hipError_t launch_decide_alpha(const DevTables& t, const Batch& b, hipStream_t s
 // device rebuild of every latency-derived table (reference latencies,
 // fastest configurations, per-backend and merged frontiers, the full table).
 constexpr uint32_t DEVERR_OBSERVATION = 4u;  // device error bit: observation out of range
-constexpr int FEEDBACK_MAX_CFG = 4096;        // configurations per op the rebuild sorts in LDS
 struct FeedbackArgs {
   int32_t* lat;              // [n_cfg] profiled latency, caller order (updated)
   uint32_t* count;           // [n_cfg] observations per configuration (zero between calls)
   unsigned long long* sum;   // [n_cfg] their sum (zero between calls)
-  const uint16_t* keyord;    // [n_cfg] position of the configuration's key among its op's keys
+  uint32_t* dirty;           // [n_ops] an observation touched the op (zero between calls)
+  const int32_t* ksrc;       // [n_cfg] the op's configurations in ascending key order (caller rows)
   const int32_t* ref_k;      // [n_ops] reference configuration (local index)
   const int32_t* tab_src;    // [n_cfg] caller row of each position of tab
   int32_t* ref;              // [n_ops]
@@ -179,7 +179,6 @@ struct FeedbackArgs {
   int32_t* mst_n;            // [n_ops]
   uint2* tab;                // [n_cfg]
   uint4* cfg_q;              // [n_cfg] or nullptr
-  int32_t max_pow2;          // smallest power of two >= the largest op's configuration count
 };
 hipError_t launch_feedback(const DevTables& t, const FeedbackArgs& f, int64_t n, const int32_t* obs_op,
                            const int32_t* obs_cfg, const int32_t* obs_lat, uint32_t beta_q16, hipStream_t s);

@@ -1315,11 +1315,11 @@ __global__ __launch_bounds__(256) void decide_alpha_merged_kernel(DevTables t, B
 //   feedback_apply_kernel       one smoothing step per observed configuration,
 //                               taken by the observation that finds the count
 //                               non-zero (and resets count and sum to zero)
-//   retable_kernel              per op (one wavefront): sort by (backend, L,
-//                               key) in LDS, per-backend frontiers by a
-//                               segmented prefix minimum; sort by (L, key),
-//                               merged frontier; header, fastest, reference
-//   retab_kernel                the full table's latencies and the queue records
+//   retable_kernel              per op with an observation (one wavefront):
+//                               merged and per-backend frontiers by running
+//                               minima in the static key order (no sort);
+//                               header, fastest, reference, the full table's
+//                               latencies
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void feedback_accumulate_kernel(DevTables t, FeedbackArgs f, int64_t n,
                                                                   const int32_t* op, const int32_t* cfg,
@@ -1334,6 +1334,7 @@ __global__ __launch_bounds__(256) void feedback_accumulate_kernel(DevTables t, F
   const int x = t.cfg_off[v] + k;
   atomicAdd(&f.count[x], 1u);
   atomicAdd(&f.sum[x], (unsigned long long)o);
+  if (f.dirty[v] == 0u) f.dirty[v] = 1u;  // racing writers all store 1
 }
 
 // L' = L + floor(beta * (S - m L) / (2^16 m)), clamped to [1, 2^31 - 1], in
@@ -1367,142 +1368,115 @@ __global__ __launch_bounds__(256) void feedback_apply_kernel(DevTables t, Feedba
   f.lat[x] = (int32_t)nl;
 }
 
-__device__ __forceinline__ void lds_bitonic_sort(uint64_t* a, int P) {
-  const int lane = threadIdx.x;
-  for (int k = 2; k <= P; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = lane; i < P; i += 64) {
-        const int ixj = i ^ j;
-        if (ixj > i) {
-          const uint64_t x = a[i], y = a[ixj];
-          const bool up = (i & k) == 0;
-          if ((x > y) == up) {
-            a[i] = y;
-            a[ixj] = x;
-          }
-        }
-      }
-      __syncthreads();
-    }
+// Exclusive prefix minimum over the wavefront (lane order) of x, continued
+// from `carry` (the minimum of everything before lane 0); returns the
+// exclusive value of this lane and updates carry to the chunk's total.
+__device__ __forceinline__ uint32_t wave_excl_min(uint32_t x, uint32_t& carry) {
+  const int lane = threadIdx.x & 63;
+  uint32_t incl = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t o = __shfl_up(incl, d, 64);
+    if (lane >= d && o < incl) incl = o;
   }
+  if (carry < incl) incl = carry;
+  const uint32_t p = __shfl_up(incl, 1, 64);
+  const uint32_t excl = lane > 0 ? p : carry;
+  carry = __shfl(incl, 63, 64);
+  return excl;
 }
 
+// Frontiers without sorting.  Along an op's frontier (latency ascending,
+// every entry cheaper than all faster ones) a configuration survives iff it
+// is strictly faster than every cheaper configuration: L_x < min{L_y : key_y
+// < key_x} (ties in L go to the cheaper key, as in the sorted construction).
+// Keys do not change with latencies, so the op's configurations are visited
+// in the static key order and one running minimum of L per list decides;
+// survivors come out in key order, which is descending latency, and are
+// written from the back.  The backend lists use the same test restricted to
+// their backend.  Two passes: counts, then writes.
 template <int NHW>
 __global__ __launch_bounds__(64) void retable_kernel(DevTables t, FeedbackArgs f) {
-  extern __shared__ uint64_t sS[];
-  uint32_t* sKey = reinterpret_cast<uint32_t*>(sS + f.max_pow2);
   const int v = blockIdx.x, lane = threadIdx.x;
+  // only ops with an observed configuration changed; the flag is cleared
+  // here for the next call (every lane has read it before the barrier)
+  const bool changed = f.dirty[v] != 0u;
+  __syncthreads();
+  if (!changed) return;
+  if (lane == 0) f.dirty[v] = 0u;
   const int a = t.cfg_off[v], n = t.cfg_off[v + 1] - a;
-  int P = 1;
-  while (P < n) P <<= 1;
   const int rk = f.ref_k[v];
   uint64_t fast = ~0ull;
-  for (int i = lane; i < P; i += 64) {
-    if (i < n) {
-      const int x = a + i;
-      const uint32_t L = (uint32_t)f.lat[x], ko = f.keyord[x];
-      sKey[ko] = t.cfg_key[x];
-      sS[i] = ((uint64_t)(uint32_t)t.cfg_hw[x] << 43) | ((uint64_t)L << 12) | ko;
-      const uint64_t c = ((uint64_t)L << 16) | (uint32_t)i;  // fastest: smallest L, lowest index
-      fast = c < fast ? c : fast;
-      if (i == rk) f.ref[v] = (int32_t)L;
-    } else {
-      sS[i] = ~0ull;
-    }
+  for (int i = lane; i < n; i += 64) {
+    const int x = a + i;
+    const uint32_t L = (uint32_t)f.lat[x];
+    const uint64_t c = ((uint64_t)L << 16) | (uint32_t)i;  // fastest: smallest L, lowest index
+    fast = c < fast ? c : fast;
+    if (i == rk) f.ref[v] = (int32_t)L;
+    if (f.cfg_q) f.cfg_q[x].x = L;
+    f.tab[x].x = (uint32_t)f.lat[f.tab_src[x]];  // the full table's row at position x
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     const uint64_t o = __shfl_xor(fast, off, 64);
     fast = o < fast ? o : fast;
   }
-  __syncthreads();
-  lds_bitonic_sort(sS, P);
-  // per-backend frontiers: entries sorted by (backend, L, key); an entry
-  // survives if its key is below every earlier key of its backend
   constexpr uint32_t INF = 0xFFFFFFFFu;
-  int cnt = 0;
-  int hcnt[NHW];
-#pragma unroll
-  for (int h = 0; h < NHW; ++h) hcnt[h] = 0;
-  uint32_t carry_hw = INF, carry_val = INF;
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  for (int c0 = 0; c0 < n; c0 += 64) {
-    const int i = c0 + lane;
-    const bool valid = i < n;
-    const uint64_t e = valid ? sS[i] : ~0ull;
-    const uint32_t hw = valid ? (uint32_t)(e >> 43) : INF - 1;
-    const uint32_t ko = (uint32_t)(e & 0xFFFu);
-    uint32_t incl = valid ? ko : INF;
+  int tot_m = 0, tot_h[NHW];
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t o = __shfl_up(incl, d, 64);
-      const uint32_t ohw = __shfl_up(hw, d, 64);
-      if (lane >= d && ohw == hw && o < incl) incl = o;
-    }
-    if (hw == carry_hw && carry_val < incl) incl = carry_val;
-    const uint32_t pincl = __shfl_up(incl, 1, 64), phw = __shfl_up(hw, 1, 64);
-    const uint32_t excl = (lane > 0 && phw == hw) ? pincl : (hw == carry_hw ? carry_val : INF);
-    const bool surv = valid && ko < excl;
-    const uint64_t mask = __ballot(surv);
-    if (surv) {
-      const int pos = __popcll(mask & below);
-      f.front[a + cnt + pos] = make_uint2((uint32_t)((e >> 12) & 0x7FFFFFFFu), sKey[ko]);
-    }
-    cnt += __popcll(mask);
+  for (int h = 0; h < NHW; ++h) tot_h[h] = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    uint32_t carry_m = INF, carry_h[NHW];
 #pragma unroll
-    for (int h = 0; h < NHW; ++h) hcnt[h] += __popcll(__ballot(surv && hw == (uint32_t)h));
-    carry_hw = __shfl(hw, 63, 64);
-    carry_val = __shfl(incl, 63, 64);
-  }
-  if (lane == 0) {
-    int32_t* hd = f.hdr + (int64_t)v * t.hs;
+    for (int h = 0; h < NHW; ++h) carry_h[h] = INF;
+    int seen_m = 0, seen_h[NHW], start_h[NHW];
     int pos = a;
 #pragma unroll
     for (int h = 0; h < NHW; ++h) {
-      hd[h] = pos;
-      pos += hcnt[h];
+      seen_h[h] = 0;
+      start_h[h] = pos;
+      pos += tot_h[h];
     }
-    hd[NHW] = pos;
-    hd[NHW + 1] = (int32_t)(fast & 0xFFFFu);
-  }
-  // merged frontier over all backends: drop the backend, sort by (L, key)
-  __syncthreads();
-  for (int i = lane; i < n; i += 64) sS[i] &= (1ull << 43) - 1;
-  __syncthreads();
-  lds_bitonic_sort(sS, P);
-  int cnt_m = 0;
-  uint32_t carry = INF;
-  for (int c0 = 0; c0 < n; c0 += 64) {
-    const int i = c0 + lane;
-    const bool valid = i < n;
-    const uint64_t e = valid ? sS[i] : ~0ull;
-    const uint32_t ko = (uint32_t)(e & 0xFFFu);
-    uint32_t incl = valid ? ko : INF;
+    for (int c0 = 0; c0 < n; c0 += 64) {
+      const int p = c0 + lane;
+      const bool valid = p < n;
+      const int x = valid ? f.ksrc[a + p] : a;
+      const uint32_t L = valid ? (uint32_t)f.lat[x] : INF;
+      const int hw = valid ? t.cfg_hw[x] : NHW;
+      const uint32_t em = wave_excl_min(L, carry_m);
+      const bool sm = valid && L < em;
+      const uint64_t bm = __ballot(sm);
+      if (pass == 1 && sm) {
+        const int r = seen_m + __popcll(bm & below);
+        f.mst[a + tot_m - 1 - r] = make_uint2(L, t.cfg_key[x]);
+      }
+      seen_m += __popcll(bm);
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t o = __shfl_up(incl, d, 64);
-      if (lane >= d && o < incl) incl = o;
+      for (int h = 0; h < NHW; ++h) {
+        const uint32_t eh = wave_excl_min(hw == h ? L : INF, carry_h[h]);
+        const bool sh = valid && hw == h && L < eh;
+        const uint64_t bh = __ballot(sh);
+        if (pass == 1 && sh) {
+          const int r = seen_h[h] + __popcll(bh & below);
+          f.front[start_h[h] + tot_h[h] - 1 - r] = make_uint2(L, t.cfg_key[x]);
+        }
+        seen_h[h] += __popcll(bh);
+      }
     }
-    if (carry < incl) incl = carry;
-    const uint32_t pincl = __shfl_up(incl, 1, 64);
-    const uint32_t excl = lane > 0 ? pincl : carry;
-    const bool surv = valid && ko < excl;
-    const uint64_t mask = __ballot(surv);
-    if (surv) {
-      const int pos = __popcll(mask & below);
-      f.mst[a + cnt_m + pos] = make_uint2((uint32_t)((e >> 12) & 0x7FFFFFFFu), sKey[ko]);
+    if (pass == 0) {
+      tot_m = seen_m;
+#pragma unroll
+      for (int h = 0; h < NHW; ++h) tot_h[h] = seen_h[h];
+    } else if (lane == 0) {
+      int32_t* hd = f.hdr + (int64_t)v * t.hs;
+#pragma unroll
+      for (int h = 0; h < NHW; ++h) hd[h] = start_h[h];
+      hd[NHW] = pos;
+      hd[NHW + 1] = (int32_t)(fast & 0xFFFFu);
+      f.mst_n[v] = tot_m;
     }
-    cnt_m += __popcll(mask);
-    carry = __shfl(incl, 63, 64);
   }
-  if (lane == 0) f.mst_n[v] = cnt_m;
-}
-
-__global__ __launch_bounds__(256) void retab_kernel(DevTables t, FeedbackArgs f) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= t.n_front) return;  // n_front = n_cfg
-  f.tab[i].x = (uint32_t)f.lat[f.tab_src[i]];
-  if (f.cfg_q) f.cfg_q[i].x = (uint32_t)f.lat[i];
 }
 
 #define LLAMA_DISPATCH_NHW(KERNEL, GRID, BLOCK, STREAM, ...)                         \
@@ -1570,16 +1544,14 @@ hipError_t launch_feedback(const DevTables& t, const FeedbackArgs& f, int64_t n,
     hipLaunchKernelGGL(feedback_apply_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, t, f, n, obs_op, obs_cfg,
                        obs_lat, beta_q16);
   }
-  const size_t lds = (sizeof(uint64_t) + sizeof(uint32_t)) * (size_t)f.max_pow2;
   switch (t.n_hw) {
 #define LLAMA_RETABLE(NH) \
-  case NH: hipLaunchKernelGGL(retable_kernel<NH>, dim3(t.n_ops), dim3(64), lds, s, t, f); break;
+  case NH: hipLaunchKernelGGL(retable_kernel<NH>, dim3(t.n_ops), dim3(64), 0, s, t, f); break;
     LLAMA_RETABLE(1) LLAMA_RETABLE(2) LLAMA_RETABLE(3) LLAMA_RETABLE(4)
     LLAMA_RETABLE(5) LLAMA_RETABLE(6) LLAMA_RETABLE(7) LLAMA_RETABLE(8)
 #undef LLAMA_RETABLE
     default: return hipErrorInvalidValue;
   }
-  if (t.n_front > 0) hipLaunchKernelGGL(retab_kernel, dim3(blocks_for(t.n_front, 256)), dim3(256), 0, s, t, f);
   return hipGetLastError();
 }
 

@@ -117,6 +117,18 @@ def queue_snapshot(w, rng, n_q):
     return np.ascontiguousarray(q_op, np.int32), np.ascontiguousarray(q_cfg, np.int32)
 
 
+def observations(w, rng, n_obs, spread=(0.5, 2.0)):
+    """Completed invocations for the feedback step: op and configuration drawn
+    like a queue snapshot, observed latency = profile latency times a factor
+    log-uniform in `spread` (contention or content making runs slower or
+    faster than profiled)."""
+    op, cfg = queue_snapshot(w, rng, n_obs)
+    x = w.cfg_off[op].astype(np.int64) + cfg
+    fac = np.exp(rng.uniform(np.log(spread[0]), np.log(spread[1]), n_obs))
+    lat = np.clip(np.rint(w.lat[x] * fac), 1, 2**31 - 1).astype(np.int32)
+    return op, cfg, lat
+
+
 def csr_from_edges(n_ops, src, dst, q=None):
     """CSR successor lists (sorted by destination within each source)."""
     src = np.asarray(src, np.int64)

@@ -18,13 +18,7 @@ pytestmark = pytest.mark.gpu
 
 
 def observe(w, rng, n_obs, spread=(0.5, 2.0)):
-    """Completed invocations: op and configuration drawn like a queue
-    snapshot, latency = profile latency times a lognormal-ish factor."""
-    op, cfg = wl.queue_snapshot(w, rng, n_obs)
-    x = w.cfg_off[op].astype(np.int64) + cfg
-    fac = np.exp(rng.uniform(np.log(spread[0]), np.log(spread[1]), n_obs))
-    lat = np.clip(np.rint(w.lat[x] * fac), 1, 2**31 - 1).astype(np.int32)
-    return op, cfg, lat
+    return wl.observations(w, rng, n_obs, spread)
 
 
 def apply(r, op, cfg, lat, beta):
