@@ -58,10 +58,12 @@ def load(path):
                                       u32, u32, p, p, p]
     L.oracle_fraction_below.argtypes = [p, p, p, p]
     L.oracle_feedback.argtypes = [i64, p, p, p, i32, p, p, ctypes.c_uint32, p]
+    L.oracle_affinity_terms.argtypes = [i64, p, p, p, i32, p, i32, p, p, p, p, p, p, p, p, p,
+                                        ctypes.c_uint32, ctypes.c_uint32, p, p, p, p, p]
     for f in (L.oracle_reference_cfg, L.oracle_worst_path, L.oracle_targets,
               L.oracle_select, L.oracle_decide, L.oracle_select_lat, L.oracle_queue_time,
               L.oracle_select_alpha, L.oracle_decide_alpha, L.oracle_fraction_below,
-              L.oracle_feedback):
+              L.oracle_feedback, L.oracle_affinity_terms):
         f.restype = ctypes.c_int
     return L
 
@@ -240,6 +242,52 @@ def feedback(obs_op, obs_cfg, obs_lat, cfg_off, lat, beta_q16):
     return out, skipped.value
 
 
+def affinity_terms(inv_op, elapsed, slo, n_hw, Q, ref_lat, W, cfg_off, hw, batch, res, lat, cost,
+                   r_total, alpha_num, alpha_den):
+    """Eq. 3's two minima per (invocation, backend) as exact Python Fractions
+    (None for a side without configurations): (own [n][n_hw], other [n][n_hw])."""
+    from fractions import Fraction
+    inv_op, elapsed, slo = (_arr(x, np.int32) for x in (inv_op, elapsed, slo))
+    n = len(inv_op)
+    Q = _arr(Q, np.int64)
+    ref = _arr(ref_lat, np.int64)
+    Wa = _arr(W, np.int64)
+    cfg_off = _arr(cfg_off, np.int32)
+    hw, batch, res, lat = (_arr(x, np.int32) for x in (hw, batch, res, lat))
+    cost, r_total = _arr(cost, np.int64), _arr(r_total, np.int64)
+    bufs = [np.zeros(n * n_hw * 2, np.uint64) for _ in range(4)]
+    scratch = np.empty(n_hw, np.int32)
+    _check("oracle_affinity_terms",
+           lib().oracle_affinity_terms(n, _ptr(inv_op), _ptr(elapsed), _ptr(slo), n_hw, _ptr(Q),
+                                       len(ref), _ptr(ref), _ptr(Wa), _ptr(cfg_off), _ptr(hw),
+                                       _ptr(batch), _ptr(res), _ptr(lat), _ptr(cost), _ptr(r_total),
+                                       alpha_num, alpha_den, *(_ptr(b) for b in bufs), _ptr(scratch)))
+    big = [b.reshape(n, n_hw, 2) for b in bufs]
+
+    def frac(num, den, i, h):
+        d = int(den[i, h, 0]) | (int(den[i, h, 1]) << 64)
+        if d == 0:
+            return None
+        return Fraction(int(num[i, h, 0]) | (int(num[i, h, 1]) << 64), d)
+
+    own = [[frac(big[0], big[1], i, h) for h in range(n_hw)] for i in range(n)]
+    oth = [[frac(big[2], big[3], i, h) for h in range(n_hw)] for i in range(n)]
+    return own, oth
+
+
+def affinity_value(own, oth):
+    """Eq. 3 from its two minima, with the readings for empty sides and zero
+    objectives: no configuration on the backend -> 0; none elsewhere -> inf;
+    zero own minimum -> inf (1 when the other minimum is zero as well)."""
+    if own is None:
+        return 0.0
+    if oth is None:
+        return float("inf")
+    if own == 0:
+        return 1.0 if oth == 0 else float("inf")
+    return float(oth / own)
+
+
 def fraction_below(n1, d1, n2, d2):
     """n1/d1 < n2/d2 as the oracle decides it (operands below 2^128)."""
     limbs = [np.array([x & (2**64 - 1), x >> 64], np.uint64) for x in (n1, d1, n2, d2)]
@@ -324,6 +372,15 @@ class Problem:
     def queue_time(self, q_op, q_cfg):
         w = self.w
         return queue_time(q_op, q_cfg, w.n_hw, w.cfg_off, w.hw, w.res, w.lat, w.hw_res_total)
+
+    def affinity(self, mode, alpha_num, alpha_den, Q=None, sl=slice(None)):
+        """Eq. 3 per (invocation, backend) as floats (correctly rounded from
+        the exact ratio), with the readings of affinity_value."""
+        w = self.w
+        own, oth = affinity_terms(w.inv_op[sl], w.elapsed[sl], w.slo[sl], w.n_hw, Q, self.ref,
+                                  self.W(mode), w.cfg_off, w.hw, w.batch, w.res, w.lat, w.cost,
+                                  w.hw_res_total, alpha_num, alpha_den)
+        return np.array([[affinity_value(o, t) for o, t in zip(ro, rt)] for ro, rt in zip(own, oth)])
 
     def decide_alpha(self, mode, alpha_num, alpha_den, Q=None, sl=slice(None)):
         w = self.w

@@ -597,3 +597,82 @@ int oracle_feedback(int64_t n_obs, const int32_t *obs_op, const int32_t *obs_cfg
         *n_skipped = skipped;
     return ORACLE_OK;
 }
+
+/*
+ * Eq. 3 (Sec. 4.4, priority-based commit): the affinity of an invocation of
+ * op v to backend h is
+ *     min over x of v not on h of obj(x)  /  min over x of v on h of obj(x),
+ * obj being Eq. 1 with the finite weight alpha (oracle_select_alpha) and each
+ * configuration's slack that of its own backend.  This function returns the
+ * two minima as exact fractions, per (invocation, backend), for the caller to
+ * divide: own_* is the minimum over the backend's configurations, oth_* over
+ * the others; each value is num / den with 128-bit num and den given as two
+ * 64-bit limbs (least significant first) at [(i * n_hw + h) * 2].  A side
+ * without any configuration has den 0.  Invalid invocations (op out of range,
+ * negative elapsed or slo) get den 0 on both sides.
+ */
+int oracle_affinity_terms(int64_t n_inv, const int32_t *inv_op, const int32_t *elapsed,
+                          const int32_t *slo, int32_t n_hw, const int64_t *Q,
+                          int32_t n_ops, const int64_t *ref_lat, const int64_t *W,
+                          const int32_t *cfg_off, const int32_t *hw, const int32_t *batch,
+                          const int32_t *res, const int32_t *lat, const int64_t *cost,
+                          const int64_t *r_total, uint32_t alpha_num, uint32_t alpha_den,
+                          uint64_t *own_num, uint64_t *own_den, uint64_t *oth_num,
+                          uint64_t *oth_den, int32_t *target_scratch)
+{
+    if (n_inv < 0 || n_hw < 1 || !target_scratch || alpha_den < 1)
+        return ORACLE_E_ARG;
+    for (int64_t i = 0; i < n_inv; ++i) {
+        for (int32_t h = 0; h < n_hw; ++h) {
+            int64_t o = (i * n_hw + h) * 2;
+            own_num[o] = own_num[o + 1] = own_den[o] = own_den[o + 1] = 0;
+            oth_num[o] = oth_num[o + 1] = oth_den[o] = oth_den[o + 1] = 0;
+        }
+        int rc = oracle_targets(1, inv_op + i, elapsed + i, slo + i, n_hw, Q, n_ops, ref_lat, W,
+                                target_scratch);
+        if (rc)
+            return rc;
+        if (target_scratch[0] < 0)
+            continue;
+        int32_t v = inv_op[i];
+        for (int32_t h = 0; h < n_hw; ++h) {
+            int have_own = 0, have_oth = 0;
+            unsigned __int128 on = 0, od = 1, tn = 0, td = 1;
+            for (int32_t x = cfg_off[v]; x < cfg_off[v + 1]; ++x) {
+                int32_t g = hw[x];
+                if (g < 0 || g >= n_hw || r_total[g] < 1)
+                    return ORACLE_E_RANGE;
+                int meets = lat[x] < target_scratch[g];
+                unsigned __int128 num = (unsigned __int128)(uint64_t)cost[x] * (uint64_t)r_total[g] * alpha_den;
+                if (!meets)
+                    num += (unsigned __int128)alpha_num * (uint32_t)lat[x] * (uint32_t)res[x];
+                unsigned __int128 den = (unsigned __int128)(uint32_t)batch[x] * (uint64_t)r_total[g] * alpha_den;
+                if (g == h) {
+                    if (!have_own || fraction_below(num, den, on, od)) {
+                        on = num;
+                        od = den;
+                        have_own = 1;
+                    }
+                } else if (!have_oth || fraction_below(num, den, tn, td)) {
+                    tn = num;
+                    td = den;
+                    have_oth = 1;
+                }
+            }
+            int64_t o = (i * n_hw + h) * 2;
+            if (have_own) {
+                own_num[o] = (uint64_t)on;
+                own_num[o + 1] = (uint64_t)(on >> 64);
+                own_den[o] = (uint64_t)od;
+                own_den[o + 1] = (uint64_t)(od >> 64);
+            }
+            if (have_oth) {
+                oth_num[o] = (uint64_t)tn;
+                oth_num[o + 1] = (uint64_t)(tn >> 64);
+                oth_den[o] = (uint64_t)td;
+                oth_den[o + 1] = (uint64_t)(td >> 64);
+            }
+        }
+    }
+    return ORACLE_OK;
+}
