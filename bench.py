@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--queue-entries", type=int, default=1_000_000)
     ap.add_argument("--no-next2", action="store_true", help="skip the feedback section")
     ap.add_argument("--feedback-obs", type=int, default=100_000)
+    ap.add_argument("--no-next3", action="store_true", help="skip the affinity section")
+    ap.add_argument("--next3-sample", type=int, default=5_000)
     ap.add_argument("--next1-sample", type=int, default=50_000)
     ap.add_argument("--kernel-reps", type=int, default=50,
                     help="launches per graph when timing single kernels")
@@ -238,6 +240,49 @@ def bench_next2(args, torch, B, wl, log, w, op, el, slo, mode):
                                  "note": "whole feedback call, 34 B per configuration"},
             "bit_exact": exact,
             "parity_sample": f"latencies exactly; decisions of the first {sample.stop} invocations"}
+
+
+def bench_next3(args, torch, B, wl, log, w, op, el, slo, mode):
+    """Eq. 3 affinities of every invocation to every backend and the commit
+    order per backend (alpha = 1); parity on a sample against the oracle."""
+    import numpy as np
+    import oracle
+    n = w.n_inv
+    wr = wl.with_resource_totals(w)
+    L = B.Llama(0).load(wr)
+    L.set_alpha(1, 1)
+    s = torch.cuda.Stream()
+    aff = torch.empty((n, w.n_hw), dtype=torch.float64, device="cuda")
+    order = torch.empty((w.n_hw, n), dtype=torch.int32, device="cuda")
+    with torch.cuda.stream(s):
+        L.affinity(op, el, slo, None, mode, aff, order, stream=s)
+    torch.cuda.synchronize()
+
+    def only_aff():
+        L.affinity(op, el, slo, None, mode, aff, None, with_order=False, stream=s)
+
+    def with_order():
+        L.affinity(op, el, slo, None, mode, aff, order, stream=s)
+
+    reps = max(1, args.kernel_reps // 5)
+    ms_a = time_graph(torch, s, graph_of(torch, s, only_aff, reps), 3) / reps
+    ms_o = time_graph(torch, s, graph_of(torch, s, with_order, reps), 3) / reps
+    sample = slice(0, min(n, args.next3_sample))
+    want = oracle.Problem(wr).affinity(mode, 1, 1, sl=sample)
+    got = aff.cpu().numpy()[sample]
+    special = ~np.isfinite(want) | (want == 0) | (want == 1)
+    rel = np.abs(got[~special] - want[~special]) / np.abs(want[~special])
+    ok = bool(np.array_equal(got[special], want[special]) and (rel.size == 0 or rel.max() <= 1e-15))
+    o = order.cpu().numpy()
+    a = aff.cpu().numpy()
+    ordered = all(bool((a[o[h], h][:-1] >= a[o[h], h][1:]).all()) for h in range(w.n_hw))
+    log(f"bench: next3 affinity {ms_a * 1e3:.1f} us, with commit order {ms_o * 1e3:.1f} us, within 1e-15 {ok}")
+    return {"alpha": [1, 1], "ms_affinity": ms_a, "ms_affinity_and_order": ms_o,
+            "invocations_per_s": n / (ms_o * 1e-3), "kernel": "affinity_kernel",
+            "order": "per backend, stable radix sort of the complemented affinity bits",
+            "within_tolerance": ok, "max_rel_error": float(rel.max()) if rel.size else 0.0,
+            "order_non_increasing": ordered,
+            "parity_sample": f"affinities of the first {sample.stop} invocations, relative 1e-15"}
 
 
 def bench_surrogate(args, torch, B, wl, log):
@@ -532,6 +577,9 @@ def main():
     next2 = None
     if not args.no_next2:
         next2 = bench_next2(args, torch, B, wl, log, w, op, el, slo, mode)
+    next3 = None
+    if not args.no_next3:
+        next3 = bench_next3(args, torch, B, wl, log, w, op, el, slo, mode)
     surr = None
     args._surrogate_ctx = None
     if not args.no_surrogate:
@@ -581,6 +629,7 @@ def main():
         "frontier_entries": st["frontier_entries"],
         "next1": next1,
         "next2": next2,
+        "next3": next3,
         "surrogate": surr,
         "serving": serve,
     }

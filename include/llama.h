@@ -316,6 +316,32 @@ int llama_decide_alpha(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
                        uint8_t *d_flag, void *stream);
 
 /*
+ * Eq. 3 (Sec. 4.4, priority-based commit): the affinity of each invocation's
+ * op to each backend h,
+ *     affinity = min obj over the op's configurations not on h
+ *                / min obj over its configurations on h,
+ * obj being the finite-alpha Eq. 1 objective (llama_set_alpha first) with
+ * every configuration judged against its own backend's Alg. 1 slack
+ * (d_queue_us as in llama_decide).  Readings: no configuration on h -> 0;
+ * none elsewhere -> +infinity; a zero minimum on h -> +infinity, or 1 when
+ * the other minimum is zero as well.  Device pointers:
+ *   d_affinity  [n_inv * n_hw] double output, row-major (invocation, backend);
+ *               the objective values are rounded to double once per value,
+ *               so the ratio is within 1e-15 relative of the exact one
+ *   d_order     [n_hw * n_inv] int32 output or NULL: for each backend, the
+ *               invocation indices by decreasing affinity, ties by index
+ *               (the commit order)
+ * With d_order the context keeps scratch of n_inv * (8 n_hw + 12) bytes plus
+ * the sort's temporary storage; it grows on demand but not while `stream` is
+ * being captured (LLAMA_E_STATE: call once before capturing).  Invalid
+ * invocations get affinity 0 and set the device error word.
+ */
+int llama_affinity(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
+                   const int32_t *d_elapsed_us, const int32_t *d_slo_us,
+                   const int64_t *d_queue_us, int32_t slack_mode, double *d_affinity,
+                   int32_t *d_order, void *stream);
+
+/*
  * Autotuner: time every schedule of the indexed decision kernel (0, 1, 2:
  * 1, 2 or 4 invocations per thread; 3: persistent workgroups with every op's
  * first 16 record bytes staged in LDS, offered when there are at most 9,216

@@ -35,7 +35,7 @@ EXPORTS = ["llama_create", "llama_destroy", "llama_last_error", "llama_set_dag",
            "llama_surrogate_fit", "llama_select_rows", "llama_serve_bytes_per_request",
            "llama_serve_open", "llama_serve_submit", "llama_serve_poll", "llama_serve_stats_get",
            "llama_serve_close", "llama_autotune", "llama_queue_time", "llama_set_alpha",
-           "llama_decide_alpha", "llama_feedback"]
+           "llama_decide_alpha", "llama_feedback", "llama_affinity"]
 
 
 class LlamaStats(ctypes.Structure):
@@ -90,6 +90,7 @@ def load_library(path=LIB_PATH):
         "llama_set_alpha": [p, ctypes.c_uint32, ctypes.c_uint32],
         "llama_decide_alpha": [p, i64, p, p, p, p, i32, p, p, p],
         "llama_feedback": [p, i64, p, p, p, ctypes.c_uint32, p],
+        "llama_affinity": [p, i64, p, p, p, p, i32, p, p, p],
         "llama_serve_open": [p, ctypes.POINTER(ServeConfig), ctypes.POINTER(p)],
         "llama_serve_submit": [p, i32, p, p, p, p, p, p, ctypes.POINTER(i32)],
         "llama_serve_poll": [p, i32, p, p, p, p, ctypes.POINTER(i32), i32],
@@ -318,6 +319,22 @@ class Llama:
         self._check("llama_feedback", self._L.llama_feedback(
             self._ctx, n, _dp(obs_op, "int32"), _dp(obs_cfg, "int32", n), _dp(obs_lat, "int32", n),
             int(beta_q16), _stream(stream)))
+
+    def affinity(self, op, elapsed, slo, queue=None, mode=SLACK_PAPER, aff=None, order=None,
+                 with_order=True, stream=None):
+        """Eq. 3 affinities [n, n_hw] (float64) and, optionally, the commit
+        order [n_hw, n] (invocations by decreasing affinity per backend)."""
+        import torch
+        n = op.numel()
+        if aff is None:
+            aff = torch.empty((n, self.n_hw), dtype=torch.float64, device=op.device)
+        if order is None and with_order:
+            order = torch.empty((self.n_hw, n), dtype=torch.int32, device=op.device)
+        self._check("llama_affinity", self._L.llama_affinity(
+            self._ctx, n, _dp(op, "int32"), _dp(elapsed, "int32", n), _dp(slo, "int32", n),
+            _dp(queue, "int64", self.n_hw), int(mode), _dp(aff, "float64", n * self.n_hw),
+            _dp(order, "int32", n * self.n_hw), _stream(stream)))
+        return aff, order
 
     def set_alpha(self, alpha_num, alpha_den=1):
         self._check("llama_set_alpha", self._L.llama_set_alpha(self._ctx, int(alpha_num), int(alpha_den)))

@@ -110,6 +110,7 @@ struct DevTables {
   const uint32_t* m_pf;
   const uint32_t* m_si;
   int32_t m_steps;
+  const double* a_val;       // [2 n_cfg] objective value of each rank, per op from 2 cfg_off[v]
   const int32_t* seg_off;    // [n_ops*n_hw+1] backend segments of the full table
   const uint2* tab;          // [n_cfg] {latency, key}, grouped by (op, backend), caller order inside
   uint32_t* err;             // device error word
@@ -159,6 +160,15 @@ struct ResTotals {
 hipError_t launch_queue_time(const DevTables& t, int64_t n, const int32_t* q_op, const int32_t* q_cfg,
                              unsigned long long* part, const ResTotals& rt, int64_t* out, hipStream_t s);
 hipError_t launch_decide_alpha(const DevTables& t, const Batch& b, hipStream_t s);
+// Eq. 3: affinities [n x n_hw] and, if order != nullptr, per backend the
+// invocations by decreasing affinity (stable), using scratch of
+// n * (8 n_hw + 8 + 4) bytes plus the sort's temporary storage.
+hipError_t launch_affinity(const DevTables& t, const Batch& b, double* aff, int32_t* order, void* scratch,
+                           size_t scratch_bytes, hipStream_t s);
+// Stable LSD radix sort of (uint64 key, int32 value) pairs (sort_kernels.hip).
+hipError_t sort_pairs_bytes(int n, size_t* bytes);
+hipError_t sort_pairs(void* tmp, size_t tmp_bytes, const uint64_t* kin, uint64_t* kout, const int32_t* vin,
+                      int32_t* vout, int n, hipStream_t s);
 
 // Feedback: smoothing of the profiled latencies from observations, then the
 // device rebuild of every latency-derived table (reference latencies,

@@ -1479,6 +1479,96 @@ __global__ __launch_bounds__(64) void retable_kernel(DevTables t, FeedbackArgs f
   }
 }
 
+// ---------------------------------------------------------------------------
+// Eq. 3 affinity: per backend the best key among its configurations (the
+// finite-alpha search of decide_alpha_kernel) and among the others; the
+// ratio of their objective values (per-rank table).  Readings: no
+// configuration on the backend -> 0; none elsewhere -> infinity; a zero own
+// minimum -> infinity, or 1 when the other minimum is zero too.  With `keys`,
+// also the sort keys for the commit order (descending affinity).
+// ---------------------------------------------------------------------------
+template <int NHW>
+__global__ __launch_bounds__(256) void affinity_kernel(DevTables t, Batch b, double* aff, uint64_t* keys,
+                                                       int32_t* iota) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= b.n) return;
+  if (iota) iota[i] = (int32_t)i;
+  const int v = b.op[i], e = b.elapsed[i], s = b.slo[i];
+  double out[NHW];
+  if (invalid_invocation(v, e, s, t.n_ops)) {
+    atomicOr(t.err, 1u);
+#pragma unroll
+    for (int h = 0; h < NHW; ++h) out[h] = 0.0;
+  } else {
+    const int64_t r0 = (int64_t)s - e;
+    const int64_t ref = t.ref[v];
+    const int64_t W = t.W[(int64_t)b.mode * t.n_ops + v];
+    const int32_t* so = t.seg_off + (int64_t)v * NHW;
+    int base[NHW], len[NHW], lo[NHW], end[NHW];
+    int32_t target[NHW];
+#pragma unroll
+    for (int h = 0; h < NHW; ++h) {
+      lo[h] = base[h] = so[h];
+      end[h] = so[h + 1];
+      len[h] = end[h] - base[h];
+      const int64_t R = remaining_time(r0, b.queue ? b.queue[h] : 0);
+      target[h] = R == 0 ? 0 : (int32_t)div_floor_pos(ref * R, W);
+    }
+    for (int step = 0; step < t.a_steps; ++step) {
+#pragma unroll
+      for (int h = 0; h < NHW; ++h) {
+        if (len[h] > 0) {
+          const int half = len[h] >> 1;
+          if (t.a_lat[base[h] + half] < target[h]) {
+            base[h] += half + 1;
+            len[h] -= half + 1;
+          } else {
+            len[h] = half;
+          }
+        }
+      }
+    }
+    uint32_t best[NHW];
+#pragma unroll
+    for (int h = 0; h < NHW; ++h) {
+      const int j = base[h];
+      uint32_t k = KEY_NONE;
+      if (j > lo[h]) k = t.a_pf[j - 1];
+      if (j < end[h]) {
+        const uint32_t ki = t.a_si[j];
+        k = ki < k ? ki : k;
+      }
+      best[h] = k;
+    }
+    const double* val = t.a_val + 2 * (int64_t)t.cfg_off[v];
+#pragma unroll
+    for (int h = 0; h < NHW; ++h) {
+      uint32_t oth = KEY_NONE;
+#pragma unroll
+      for (int g = 0; g < NHW; ++g)
+        if (g != h && best[g] < oth) oth = best[g];
+      double a;
+      if (best[h] == KEY_NONE) {
+        a = 0.0;
+      } else if (oth == KEY_NONE) {
+        a = __builtin_huge_val();
+      } else {
+        const double vo = val[best[h] >> 16], vt = val[oth >> 16];
+        a = vo == 0.0 ? (vt == 0.0 ? 1.0 : __builtin_huge_val()) : vt / vo;
+      }
+      out[h] = a;
+    }
+  }
+  double* dst = aff + i * NHW;
+#pragma unroll
+  for (int h = 0; h < NHW; ++h) {
+    dst[h] = out[h];
+    // non-negative doubles order like their bit patterns; complemented, an
+    // ascending sort gives decreasing affinity
+    if (keys) keys[(int64_t)h * b.n + i] = ~(uint64_t)__double_as_longlong(out[h]);
+  }
+}
+
 #define LLAMA_DISPATCH_NHW(KERNEL, GRID, BLOCK, STREAM, ...)                         \
   switch (t.n_hw) {                                                                  \
     case 1: hipLaunchKernelGGL(KERNEL<1>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
@@ -1551,6 +1641,26 @@ hipError_t launch_feedback(const DevTables& t, const FeedbackArgs& f, int64_t n,
     LLAMA_RETABLE(5) LLAMA_RETABLE(6) LLAMA_RETABLE(7) LLAMA_RETABLE(8)
 #undef LLAMA_RETABLE
     default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_affinity(const DevTables& t, const Batch& b, double* aff, int32_t* order, void* scratch,
+                           size_t scratch_bytes, hipStream_t s) {
+  if (b.n == 0) return hipSuccess;
+  const int64_t n = b.n;
+  uint64_t* keys = order ? static_cast<uint64_t*>(scratch) : nullptr;  // [n_hw * n]
+  uint64_t* kout = keys ? keys + (int64_t)t.n_hw * n : nullptr;          // [n]
+  int32_t* iota = kout ? reinterpret_cast<int32_t*>(kout + n) : nullptr; // [n]
+  LLAMA_DISPATCH_NHW(affinity_kernel, dim3(blocks_for(n, 256)), dim3(256), s, t, b, aff, keys, iota);
+  if (!order) return hipGetLastError();
+  const size_t off = ((size_t)n * (8 * (size_t)t.n_hw + 8 + 4) + 255) & ~(size_t)255;
+  if (scratch_bytes < off) return hipErrorInvalidValue;
+  void* tmp = static_cast<char*>(scratch) + off;
+  const size_t tmp_bytes = scratch_bytes - off;
+  for (int h = 0; h < t.n_hw; ++h) {
+    hipError_t e = sort_pairs(tmp, tmp_bytes, keys + (int64_t)h * n, kout, iota, order + (int64_t)h * n, (int)n, s);
+    if (e != hipSuccess) return e;
   }
   return hipGetLastError();
 }

@@ -79,6 +79,7 @@ int build_alpha_tables(llama_ctx* c) {
   const int n_ops = c->n_ops, n_hw = c->n_hw;
   const int64_t n_cfg = c->n_cfg;
   std::vector<int32_t> a_lat(n_cfg), m_lat(n_cfg);
+  std::vector<double> a_val(2 * (size_t)n_cfg, 0.0);
   std::vector<uint32_t> a_pf(n_cfg), a_si(n_cfg), m_pf(n_cfg), m_si(n_cfg);
   int max_seg = 0, max_op = 0;
   bool too_many = false;
@@ -107,6 +108,8 @@ int build_alpha_tables(llama_ctx* c) {
     for (size_t i = 0; i < ord.size(); ++i) {
       if (i > 0 && frac_less(val[ord[i - 1]], val[ord[i]])) ++r;
       rank[ord[i]] = r;
+      // the objective value of each rank, for Eq. 3's ratios (three roundings)
+      a_val[2 * (size_t)a + r] = (double)val[ord[i]].num / (double)val[ord[i]].den;
     }
     // per backend: configurations in latency order (caller index among equal
     // latencies), prefix minima of feasible keys, suffix minima of infeasible keys
@@ -169,7 +172,8 @@ int build_alpha_tables(llama_ctx* c) {
       (rc = upload(c, c->d_a_si, a_si.data(), a_si.size() * 4, "alpha suffix keys")) ||
       (rc = upload(c, c->d_m_lat, m_lat.data(), m_lat.size() * 4, "alpha merged latencies")) ||
       (rc = upload(c, c->d_m_pf, m_pf.data(), m_pf.size() * 4, "alpha merged prefix keys")) ||
-      (rc = upload(c, c->d_m_si, m_si.data(), m_si.size() * 4, "alpha merged suffix keys")))
+      (rc = upload(c, c->d_m_si, m_si.data(), m_si.size() * 4, "alpha merged suffix keys")) ||
+      (rc = upload(c, c->d_a_val, a_val.data(), a_val.size() * 8, "alpha objective values")))
     return rc;
   if ((rc = sync_ctx(c, "alpha tables"))) return rc;
   c->alpha_steps = steps;
@@ -229,6 +233,41 @@ int llama_decide_alpha(llama_ctx* c, int64_t n, const int32_t* op, const int32_t
   b.n = n; b.op = op; b.elapsed = elapsed; b.slo = slo; b.queue = queue; b.cfg = cfg; b.flag = flag; b.mode = mode;
   hipError_t e = llama::launch_decide_alpha(c->tables(), b, (hipStream_t)stream);
   if (e != hipSuccess) return llama::hip_fail(c, e, "decide_alpha launch");
+  return LLAMA_OK;
+}
+
+int llama_affinity(llama_ctx* c, int64_t n, const int32_t* op, const int32_t* elapsed, const int32_t* slo,
+                   const int64_t* queue, int32_t mode, double* aff, int32_t* order, void* stream) {
+  int rc = llama::enter(c);
+  if (rc) return rc;
+  if (!c->has_prof) return llama::fail(c, LLAMA_E_STATE, "affinity: no profiles");
+  if (!c->has_alpha) return llama::fail(c, LLAMA_E_STATE, "affinity: call llama_set_alpha first");
+  if (n < 0 || n > INT32_MAX) return llama::fail(c, LLAMA_E_RANGE, "affinity: n_inv out of range");
+  if (n > 0 && (!op || !elapsed || !slo || !aff)) return llama::fail(c, LLAMA_E_ARG, "affinity: null pointer");
+  if (mode != LLAMA_SLACK_PAPER && mode != LLAMA_SLACK_PROB)
+    return llama::fail(c, LLAMA_E_ARG, "affinity: bad slack_mode %d", mode);
+  if (n == 0) return LLAMA_OK;
+  hipStream_t s = (hipStream_t)stream;
+  if (order) {
+    // sort scratch (grows; not while the stream is being captured)
+    size_t tmp = 0;
+    hipError_t e = llama::sort_pairs_bytes((int)n, &tmp);
+    if (e != hipSuccess) return llama::hip_fail(c, e, "affinity sort size");
+    const size_t need = (((size_t)n * (8 * (size_t)c->n_hw + 8 + 4) + 255) & ~(size_t)255) + tmp;
+    if (need > c->d_aff_scratch.bytes) {
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      if (s) hipStreamIsCapturing(s, &cs);
+      if (cs != hipStreamCaptureStatusNone)
+        return llama::fail(c, LLAMA_E_STATE, "affinity: scratch must grow; call once before capturing");
+      if (s && hipStreamSynchronize(s) != hipSuccess) return llama::fail(c, LLAMA_E_DEVICE, "affinity: sync");
+      if ((rc = llama::upload(c, c->d_aff_scratch, nullptr, need, "affinity scratch"))) return rc;
+      if ((rc = llama::sync_ctx(c, "affinity scratch"))) return rc;
+    }
+  }
+  llama::Batch b{};
+  b.n = n; b.op = op; b.elapsed = elapsed; b.slo = slo; b.queue = queue; b.mode = mode;
+  hipError_t e = llama::launch_affinity(c->tables(), b, aff, order, c->d_aff_scratch.p, c->d_aff_scratch.bytes, s);
+  if (e != hipSuccess) return llama::hip_fail(c, e, "affinity launch");
   return LLAMA_OK;
 }
 

@@ -1,0 +1,107 @@
+"""GPU parity of Eq. 3 (affinity) and the commit order, through the C ABI.
+
+Tolerance: each objective value is rounded to double once (three roundings of
+relative size 2^-53: numerator, denominator, quotient) and the ratio once
+more, so the GPU's ratio is within 7 * 2^-53 of the exact one and within
+8 * 2^-53 < 1e-15 of the oracle's correctly rounded value; the special values
+(0, 1, infinity) are exact.  The commit order is a permutation whose GPU
+affinities never increase, ties in index order, and whose exact affinities
+never increase by more than the tolerance.
+"""
+import numpy as np
+import pytest
+
+from paper_2102_01887_amd import binding as B
+from paper_2102_01887_amd import workloads as wl
+from test_gpu_parity import PAPER, PROB, Run, dev, say
+
+pytestmark = pytest.mark.gpu
+RTOL = 1e-15
+
+
+def close(got, want):
+    special = ~np.isfinite(want) | (want == 0) | (want == 1)
+    assert np.array_equal(got[special], want[special])
+    f = ~special
+    rel = np.abs(got[f] - want[f]) / np.abs(want[f])
+    assert rel.size == 0 or rel.max() <= RTOL, rel.max()
+
+
+def check_order(order, aff_gpu, aff_or):
+    n = aff_gpu.shape[0]
+    for h in range(order.shape[0]):
+        o = order[h]
+        assert np.array_equal(np.sort(o), np.arange(n))
+        a = aff_gpu[o, h]
+        assert (a[:-1] >= a[1:]).all()
+        ties = a[:-1] == a[1:]
+        assert (o[:-1][ties] < o[1:][ties]).all()
+        e = aff_or[o, h]
+        fin = np.isfinite(e[:-1]) & np.isfinite(e[1:])
+        assert (e[:-1][fin] >= e[1:][fin] * (1 - 2 * RTOL)).all()
+
+
+def run_case(r, a, Q=None, modes=(PAPER, PROB), n_check=None):
+    torch = r.torch
+    q = None if Q is None else dev(np.asarray(Q, np.int64), torch)
+    r.L.set_alpha(*a)
+    for mode in modes:
+        aff, order = r.L.affinity(r.op, r.el, r.slo, q, mode)
+        torch.cuda.synchronize()
+        aff, order = aff.cpu().numpy(), order.cpu().numpy()
+        sl = slice(None) if n_check is None else slice(0, n_check)
+        want = r.P.affinity(mode, *a, Q=Q, sl=sl)
+        close(aff[sl], want)
+        if n_check is None:
+            check_order(order, aff, want)
+        say(f"{r.w.name} alpha {a} mode {mode}: median affinity {np.median(aff):.3f}")
+
+
+def test_affinity_c1():
+    w = wl.with_resource_totals(wl.make_c1(queue=True))
+    r = Run(w)
+    for a in ((0, 1), (1, 1), (7, 3)):
+        run_case(r, a)
+        run_case(r, a, Q=w.Q, modes=(PAPER,))
+
+
+def test_affinity_c2_reduced():
+    w = wl.with_resource_totals(wl.make_c2(seed=61, n_pipelines=12, n_inv=4_000))
+    r = Run(w)
+    run_case(r, (1, 1))
+    run_case(r, (1, 2), Q=[50_000, 0, 400_000, 2_000_000], modes=(PAPER,))
+
+
+def test_affinity_fuzz_small_tables():
+    rng = np.random.default_rng(11)
+    for rep in range(8):
+        w = wl.with_resource_totals(wl.random_small(rng, n_inv=600, name=f"aff{rep}"),
+                                    slots=int(rng.integers(1, 5)))
+        r = Run(w)
+        run_case(r, (int(rng.integers(0, 6)), int(rng.integers(1, 4))))
+        run_case(r, (1, 1), Q=rng.integers(0, 15_000, w.n_hw), modes=(PAPER,))
+
+
+def test_affinity_without_order_and_invalid_invocations():
+    w = wl.with_resource_totals(wl.make_c1())
+    r = Run(w)
+    r.L.set_alpha(1, 1)
+    torch = r.torch
+    op = w.inv_op.copy()
+    op[::6] = w.n_ops
+    aff, order = r.L.affinity(dev(op, torch), r.el, r.slo, with_order=False)
+    torch.cuda.synchronize()
+    assert order is None
+    aff = aff.cpu().numpy()
+    assert (aff[::6] == 0).all()
+    assert r.L.stats(reset_error=True)["device_error"] & B.DEVERR_INVALID_INVOCATION
+    ok = np.ones(len(op), bool)
+    ok[::6] = False
+    want = r.P.affinity(PAPER, 1, 1)
+    close(aff[ok], want[ok])
+
+
+def test_affinity_needs_alpha():
+    r = Run(wl.with_resource_totals(wl.make_c1()))
+    with pytest.raises(B.LlamaError):
+        r.L.affinity(r.op, r.el, r.slo)
