@@ -58,12 +58,14 @@ def load(path):
                                       u32, u32, p, p, p]
     L.oracle_fraction_below.argtypes = [p, p, p, p]
     L.oracle_feedback.argtypes = [i64, p, p, p, i32, p, p, ctypes.c_uint32, p]
+    L.oracle_decide_batching.argtypes = [i64, p, p, p, i32, p, i32, p, p, p, p, p, p, p, p, p, p,
+                                         p, p, p]
     L.oracle_affinity_terms.argtypes = [i64, p, p, p, i32, p, i32, p, p, p, p, p, p, p, p, p,
                                         ctypes.c_uint32, ctypes.c_uint32, p, p, p, p, p]
     for f in (L.oracle_reference_cfg, L.oracle_worst_path, L.oracle_targets,
               L.oracle_select, L.oracle_decide, L.oracle_select_lat, L.oracle_queue_time,
               L.oracle_select_alpha, L.oracle_decide_alpha, L.oracle_fraction_below,
-              L.oracle_feedback, L.oracle_affinity_terms):
+              L.oracle_feedback, L.oracle_affinity_terms, L.oracle_decide_batching):
         f.restype = ctypes.c_int
     return L
 
@@ -242,6 +244,33 @@ def feedback(obs_op, obs_cfg, obs_lat, cfg_off, lat, beta_q16):
     return out, skipped.value
 
 
+CFG_WAIT = -2
+
+
+def decide_batching(inv_op, elapsed, slo, n_hw, Q, ref_lat, W, cfg_off, hw, batch, lat, cost,
+                    available, upstream, wait_us):
+    """Safe delayed batching: (cfg, flag), cfg = CFG_WAIT for a wait."""
+    inv_op, elapsed, slo = (_arr(x, np.int32) for x in (inv_op, elapsed, slo))
+    n = len(inv_op)
+    Q = _arr(Q, np.int64)
+    ref = _arr(ref_lat, np.int64)
+    Wa = _arr(W, np.int64)
+    cfg_off = _arr(cfg_off, np.int32)
+    hw, batch, lat = (_arr(x, np.int32) for x in (hw, batch, lat))
+    cost = _arr(cost, np.int64)
+    available, upstream, wait_us = (_arr(x, np.int32) for x in (available, upstream, wait_us))
+    cfg = np.empty(n, np.int32)
+    flag = np.empty(n, np.uint8)
+    scratch = np.empty(n_hw, np.int32)
+    _check("oracle_decide_batching",
+           lib().oracle_decide_batching(n, _ptr(inv_op), _ptr(elapsed), _ptr(slo), n_hw, _ptr(Q),
+                                        len(ref), _ptr(ref), _ptr(Wa), _ptr(cfg_off), _ptr(hw),
+                                        _ptr(batch), _ptr(lat), _ptr(cost), _ptr(available),
+                                        _ptr(upstream), _ptr(wait_us), _ptr(cfg), _ptr(flag),
+                                        _ptr(scratch)))
+    return cfg, flag
+
+
 def affinity_terms(inv_op, elapsed, slo, n_hw, Q, ref_lat, W, cfg_off, hw, batch, res, lat, cost,
                    r_total, alpha_num, alpha_den):
     """Eq. 3's two minima per (invocation, backend) as exact Python Fractions
@@ -372,6 +401,12 @@ class Problem:
     def queue_time(self, q_op, q_cfg):
         w = self.w
         return queue_time(q_op, q_cfg, w.n_hw, w.cfg_off, w.hw, w.res, w.lat, w.hw_res_total)
+
+    def decide_batching(self, mode, available, upstream, wait_us, Q=None, sl=slice(None)):
+        w = self.w
+        return decide_batching(w.inv_op[sl], w.elapsed[sl], w.slo[sl], w.n_hw, Q, self.ref,
+                               self.W(mode), w.cfg_off, w.hw, w.batch, w.lat, w.cost, available,
+                               upstream, wait_us)
 
     def affinity(self, mode, alpha_num, alpha_den, Q=None, sl=slice(None)):
         """Eq. 3 per (invocation, backend) as floats (correctly rounded from

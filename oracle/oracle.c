@@ -676,3 +676,86 @@ int oracle_affinity_terms(int64_t n_inv, const int32_t *inv_op, const int32_t *e
     }
     return ORACLE_OK;
 }
+
+/* Eq. 1 (fastest fallback) for one invocation over the configurations of op
+ * v whose batch is at most max_batch; -1 if there is none.  *meets receives
+ * whether the choice meets its slack. */
+static int32_t select_within(int32_t v, const int32_t *target, const int32_t *cfg_off,
+                             const int32_t *hw, const int32_t *batch, const int32_t *lat,
+                             const int64_t *cost, int64_t max_batch, int *meets)
+{
+    int32_t best = -1, fast = -1;
+    for (int32_t x = cfg_off[v]; x < cfg_off[v + 1]; ++x) {
+        if (batch[x] > max_batch)
+            continue;
+        if (fast < 0 || lat[x] < lat[fast])
+            fast = x;
+        if (lat[x] < target[hw[x]] && (best < 0 || per_item_less(cost, batch, x, best)))
+            best = x;
+    }
+    *meets = best >= 0;
+    return best >= 0 ? best : fast;
+}
+
+/*
+ * Safe delayed batching (Sec. 4.4).  Per invocation of op v, with
+ * available[v] invocations of v ready now, upstream[v] more expected from
+ * upstream work already running, and wait_us[v] the estimated time until
+ * they arrive (all caller inputs, per op):
+ *   1. x* = the Eq. 1 choice over every configuration (fastest fallback);
+ *   2. if B(x*) <= available[v]: commit x*;
+ *   3. else, if x* meets its slack, available[v] + upstream[v] >= B(x*) and
+ *      wait_us[v] + L(x*) < slack of x*'s backend: wait (cfg -2, flag 1);
+ *   4. else commit the Eq. 1 choice over the configurations with
+ *      B <= max(available[v], 1) (fastest fallback), or x* if there is none.
+ * flag is 1 when the committed configuration meets its slack.  Invalid
+ * invocations get cfg -1, flag 0.  target_scratch holds n_hw int32.
+ */
+int oracle_decide_batching(int64_t n_inv, const int32_t *inv_op, const int32_t *elapsed,
+                           const int32_t *slo, int32_t n_hw, const int64_t *Q,
+                           int32_t n_ops, const int64_t *ref_lat, const int64_t *W,
+                           const int32_t *cfg_off, const int32_t *hw, const int32_t *batch,
+                           const int32_t *lat, const int64_t *cost, const int32_t *available,
+                           const int32_t *upstream, const int32_t *wait_us, int32_t *cfg,
+                           uint8_t *flag, int32_t *target_scratch)
+{
+    if (n_inv < 0 || n_hw < 1 || !target_scratch || !available || !upstream || !wait_us)
+        return ORACLE_E_ARG;
+    for (int64_t i = 0; i < n_inv; ++i) {
+        int rc = oracle_targets(1, inv_op + i, elapsed + i, slo + i, n_hw, Q, n_ops, ref_lat, W,
+                                target_scratch);
+        if (rc)
+            return rc;
+        if (target_scratch[0] < 0) {
+            cfg[i] = -1;
+            flag[i] = 0;
+            continue;
+        }
+        int32_t v = inv_op[i];
+        int meets = 0;
+        int32_t xs = select_within(v, target_scratch, cfg_off, hw, batch, lat, cost, INT64_MAX, &meets);
+        int64_t avail = available[v];
+        if (batch[xs] <= avail) {
+            cfg[i] = xs - cfg_off[v];
+            flag[i] = (uint8_t)meets;
+            continue;
+        }
+        if (meets && avail + (int64_t)upstream[v] >= batch[xs] &&
+            (int64_t)wait_us[v] + lat[xs] < target_scratch[hw[xs]]) {
+            cfg[i] = -2;
+            flag[i] = 1;
+            continue;
+        }
+        int meets_r = 0;
+        int32_t xr = select_within(v, target_scratch, cfg_off, hw, batch, lat, cost, avail > 1 ? avail : 1,
+                                   &meets_r);
+        if (xr < 0) {
+            cfg[i] = xs - cfg_off[v];
+            flag[i] = (uint8_t)meets;
+        } else {
+            cfg[i] = xr - cfg_off[v];
+            flag[i] = (uint8_t)meets_r;
+        }
+    }
+    return ORACLE_OK;
+}
