@@ -59,6 +59,7 @@ def parse():
     ap.add_argument("--feedback-obs", type=int, default=100_000)
     ap.add_argument("--no-next3", action="store_true", help="skip the affinity section")
     ap.add_argument("--next3-sample", type=int, default=5_000)
+    ap.add_argument("--no-next4", action="store_true", help="skip the safe delayed batching section")
     ap.add_argument("--next1-sample", type=int, default=50_000)
     ap.add_argument("--kernel-reps", type=int, default=50,
                     help="launches per graph when timing single kernels")
@@ -283,6 +284,42 @@ def bench_next3(args, torch, B, wl, log, w, op, el, slo, mode):
             "within_tolerance": ok, "max_rel_error": float(rel.max()) if rel.size else 0.0,
             "order_non_increasing": ordered,
             "parity_sample": f"affinities of the first {sample.stop} invocations, relative 1e-15"}
+
+
+def bench_next4(args, torch, B, wl, log, L, w, op, el, slo, mode):
+    """Safe delayed batching over the invocation batch: per op, invocations
+    available U{1..64}, expected from upstream U{0..64}, estimated wait
+    U[0, 0.2 s]; parity on a sample against the oracle."""
+    import numpy as np
+    import oracle
+    n = w.n_inv
+    rng = np.random.default_rng(29)
+    per_op = [rng.integers(1, 65, w.n_ops), rng.integers(0, 65, w.n_ops), rng.integers(0, 200_001, w.n_ops)]
+    per_op = [torch.from_numpy(a.astype(np.int32)).cuda() for a in per_op]
+    s = torch.cuda.Stream()
+    cfg = torch.empty(n, dtype=torch.int32, device="cuda")
+    flag = torch.empty(n, dtype=torch.uint8, device="cuda")
+
+    def run():
+        L.decide_batching(op, el, slo, *per_op, None, mode, cfg, flag, stream=s)
+
+    with torch.cuda.stream(s):
+        run()
+    torch.cuda.synchronize()
+    reps = max(1, args.kernel_reps // 5)
+    ms = time_graph(torch, s, graph_of(torch, s, run, reps), 3) / reps
+    sample = slice(0, min(n, args.next1_sample))
+    c_or, f_or = oracle.Problem(w).decide_batching(mode, *(a.cpu().numpy() for a in per_op), sl=sample)
+    c, f = cfg.cpu().numpy(), flag.cpu().numpy()
+    exact = bool(np.array_equal(c[sample], c_or) and np.array_equal(f[sample], f_or))
+    log(f"bench: next4 safe delayed batching {ms * 1e3:.1f} us, exact {exact}")
+    pairs = int(np.diff(w.cfg_off)[w.inv_op].sum())
+    return {"ms": ms, "decisions_per_s": n / (ms * 1e-3), "kernel": "decide_batching_kernel",
+            "wait_fraction": float(np.mean(c == B.CFG_WAIT)),
+            "roofline": {"bound": "alu", "achieved": pairs * 6 / (ms * 1e-3) / 1e9, "peak": 39321.6,
+                         "unit": "Gop/s", "frac": pairs * 6 / (ms * 1e-3) / 1e9 / 39321.6,
+                         "note": "6 lane-ops per (invocation, configuration) pair"},
+            "bit_exact": exact, "parity_sample": f"decisions of the first {sample.stop} invocations"}
 
 
 def bench_surrogate(args, torch, B, wl, log):
@@ -580,6 +617,9 @@ def main():
     next3 = None
     if not args.no_next3:
         next3 = bench_next3(args, torch, B, wl, log, w, op, el, slo, mode)
+    next4 = None
+    if not args.no_next4:
+        next4 = bench_next4(args, torch, B, wl, log, L, w, op, el, slo, mode)
     surr = None
     args._surrogate_ctx = None
     if not args.no_surrogate:
@@ -630,6 +670,7 @@ def main():
         "next1": next1,
         "next2": next2,
         "next3": next3,
+        "next4": next4,
         "surrogate": surr,
         "serving": serve,
     }

@@ -316,6 +316,30 @@ int llama_decide_alpha(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
                        uint8_t *d_flag, void *stream);
 
 /*
+ * Safe delayed batching (Sec. 4.4).  Per op (device pointers [n_ops]):
+ *   d_available   invocations of the op ready now
+ *   d_upstream    invocations of the op expected from upstream work already
+ *                 running
+ *   d_wait_us     the estimated time until they arrive
+ * For each invocation (other arguments as in llama_decide):
+ *   1. x* = the Eq. 1 choice over every configuration (fastest fallback);
+ *   2. B(x*) <= available: commit x*;
+ *   3. else, if x* meets its slack, available + upstream >= B(x*) and
+ *      wait_us + L(x*) < the slack of x*'s backend: wait
+ *      (d_cfg = LLAMA_CFG_WAIT, d_flag = 1);
+ *   4. else commit the Eq. 1 choice among the configurations with
+ *      B <= max(available, 1), or x* if none has.
+ * d_flag is 1 when the committed configuration meets its slack.  Invalid
+ * invocations get -1 / 0 and set the device error word.
+ */
+#define LLAMA_CFG_WAIT (-2)
+int llama_decide_batching(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
+                          const int32_t *d_elapsed_us, const int32_t *d_slo_us,
+                          const int64_t *d_queue_us, int32_t slack_mode,
+                          const int32_t *d_available, const int32_t *d_upstream,
+                          const int32_t *d_wait_us, int32_t *d_cfg, uint8_t *d_flag, void *stream);
+
+/*
  * Eq. 3 (Sec. 4.4, priority-based commit): the affinity of each invocation's
  * op to each backend h,
  *     affinity = min obj over the op's configurations not on h

@@ -24,6 +24,7 @@ SCHEDULE_NAMES = ("direct-1", "direct-2", "direct-4", "lds-persistent", "direct-
 DEVERR_INVALID_INVOCATION = 1
 DEVERR_INVALID_QUEUE_ENTRY = 2
 DEVERR_INVALID_OBSERVATION = 4
+CFG_WAIT = -2
 
 EXPORTS = ["llama_create", "llama_destroy", "llama_last_error", "llama_set_dag",
            "llama_set_profiles", "llama_relax", "llama_update_latencies", "llama_targets",
@@ -35,7 +36,7 @@ EXPORTS = ["llama_create", "llama_destroy", "llama_last_error", "llama_set_dag",
            "llama_surrogate_fit", "llama_select_rows", "llama_serve_bytes_per_request",
            "llama_serve_open", "llama_serve_submit", "llama_serve_poll", "llama_serve_stats_get",
            "llama_serve_close", "llama_autotune", "llama_queue_time", "llama_set_alpha",
-           "llama_decide_alpha", "llama_feedback", "llama_affinity"]
+           "llama_decide_alpha", "llama_feedback", "llama_affinity", "llama_decide_batching"]
 
 
 class LlamaStats(ctypes.Structure):
@@ -91,6 +92,7 @@ def load_library(path=LIB_PATH):
         "llama_decide_alpha": [p, i64, p, p, p, p, i32, p, p, p],
         "llama_feedback": [p, i64, p, p, p, ctypes.c_uint32, p],
         "llama_affinity": [p, i64, p, p, p, p, i32, p, p, p],
+        "llama_decide_batching": [p, i64, p, p, p, p, i32, p, p, p, p, p, p],
         "llama_serve_open": [p, ctypes.POINTER(ServeConfig), ctypes.POINTER(p)],
         "llama_serve_submit": [p, i32, p, p, p, p, p, p, ctypes.POINTER(i32)],
         "llama_serve_poll": [p, i32, p, p, p, p, ctypes.POINTER(i32), i32],
@@ -319,6 +321,23 @@ class Llama:
         self._check("llama_feedback", self._L.llama_feedback(
             self._ctx, n, _dp(obs_op, "int32"), _dp(obs_cfg, "int32", n), _dp(obs_lat, "int32", n),
             int(beta_q16), _stream(stream)))
+
+    def decide_batching(self, op, elapsed, slo, available, upstream, wait_us, queue=None,
+                        mode=SLACK_PAPER, cfg=None, flag=None, stream=None):
+        """Safe delayed batching; per-op inputs are int32 device tensors [n_ops];
+        cfg == CFG_WAIT marks a wait."""
+        import torch
+        n = op.numel()
+        if cfg is None:
+            cfg = torch.empty(n, dtype=torch.int32, device=op.device)
+        if flag is None:
+            flag = torch.empty(n, dtype=torch.uint8, device=op.device)
+        self._check("llama_decide_batching", self._L.llama_decide_batching(
+            self._ctx, n, _dp(op, "int32"), _dp(elapsed, "int32", n), _dp(slo, "int32", n),
+            _dp(queue, "int64", self.n_hw), int(mode), _dp(available, "int32", self.n_ops),
+            _dp(upstream, "int32", self.n_ops), _dp(wait_us, "int32", self.n_ops),
+            _dp(cfg, "int32", n), _dp(flag, "uint8", n), _stream(stream)))
+        return cfg, flag
 
     def affinity(self, op, elapsed, slo, queue=None, mode=SLACK_PAPER, aff=None, order=None,
                  with_order=True, stream=None):

@@ -67,7 +67,7 @@ struct llama_ctx {
   std::vector<uint32_t> key;  // caller order
   DevBuf d_ref, d_W, d_hdr, d_front_L, d_rec, d_rec_tail, d_ovf, d_rec_q, d_rec_tail_q, d_ovf_q, d_seg_off, d_tab;
   DevBuf d_mst, d_mst_n;
-  DevBuf d_cfg_off, d_cfg_hw, d_cfg_lat, d_cfg_key, d_cfg_q;
+  DevBuf d_cfg_off, d_cfg_hw, d_cfg_lat, d_cfg_key, d_cfg_q, d_cfg_batch;
   std::vector<int64_t> res_total;  // [n_hw] or empty
   // finite-alpha objective (llama_set_alpha)
   bool has_alpha = false;
@@ -128,6 +128,7 @@ struct llama_ctx {
     t.cfg_lat = d_cfg_lat.as<int32_t>();
     t.cfg_key = d_cfg_key.as<uint32_t>();
     t.cfg_q = d_cfg_q.as<uint4>();
+    t.cfg_batch = d_cfg_batch.as<int32_t>();
     t.a_lat = d_a_lat.as<int32_t>();
     t.a_pf = d_a_pf.as<uint32_t>();
     t.a_si = d_a_si.as<uint32_t>();
@@ -148,7 +149,7 @@ struct llama_ctx {
                            &d_succ_ids, &d_succ_q, &d_ref, &d_W, &d_hdr, &d_front_L,
                            &d_rec, &d_rec_tail, &d_ovf, &d_rec_q, &d_rec_tail_q, &d_ovf_q, &d_seg_off, &d_tab, &d_err,
                            &d_cnt, &d_start, &d_cursor, &d_perm, &d_hist, &d_mst,
-                           &d_mst_n, &d_cfg_off, &d_cfg_hw, &d_cfg_lat, &d_cfg_key, &d_cfg_q, &d_a_lat, &d_a_pf, &d_a_si, &d_m_lat, &d_m_pf, &d_m_si, &d_a_val, &d_aff_scratch, &d_qacc, &d_fb_ksrc, &d_fb_tab_src, &d_fb_ref_k, &d_fb_count, &d_fb_sum, &d_fb_dirty};
+                           &d_mst_n, &d_cfg_off, &d_cfg_hw, &d_cfg_lat, &d_cfg_key, &d_cfg_q, &d_cfg_batch, &d_a_lat, &d_a_pf, &d_a_si, &d_m_lat, &d_m_pf, &d_m_si, &d_a_val, &d_aff_scratch, &d_qacc, &d_fb_ksrc, &d_fb_tab_src, &d_fb_ref_k, &d_fb_count, &d_fb_sum, &d_fb_dirty};
     int64_t s = 0;
     for (auto* b : all) s += (int64_t)b->bytes;
     return s;

@@ -570,6 +570,7 @@ int build_tables(llama_ctx* c) {
       (rc = upload_vec(c, c->d_cfg_off, c->cfg_off, "cfg_off")) ||
       (rc = upload_vec(c, c->d_cfg_hw, c->hw, "cfg_hw")) ||
       (rc = upload_vec(c, c->d_cfg_lat, c->lat, "cfg_lat")) ||
+      (rc = upload_vec(c, c->d_cfg_batch, c->batch, "cfg_batch")) ||
       (rc = upload_vec(c, c->d_cfg_key, c->key, "cfg_key")) ||
       (rc = upload(c, c->d_cnt, nullptr, sizeof(int32_t) * ((size_t)n_ops + 1), "bucket counts")) ||
       (rc = upload(c, c->d_start, nullptr, sizeof(int32_t) * ((size_t)n_ops + 1), "bucket starts")) ||

@@ -100,6 +100,7 @@ struct DevTables {
   const int32_t* cfg_lat;    // [n_cfg] profiled latency, caller order
   const uint32_t* cfg_key;   // [n_cfg] rank << 16 | k, caller order
   const uint4* cfg_q;        // [n_cfg] {L, R, hw, 0} caller order (with resource limits only)
+  const int32_t* cfg_batch;  // [n_cfg] batch size, caller order
   // finite-alpha objective, per (op, backend) segment of seg_off, sorted by latency
   const int32_t* a_lat;      // [n_cfg] latency
   const uint32_t* a_pf;      // [n_cfg] min feasible key over the segment's entries up to here
@@ -165,6 +166,15 @@ hipError_t launch_decide_alpha(const DevTables& t, const Batch& b, hipStream_t s
 // n * (8 n_hw + 8 + 4) bytes plus the sort's temporary storage.
 hipError_t launch_affinity(const DevTables& t, const Batch& b, double* aff, int32_t* order, void* scratch,
                            size_t scratch_bytes, hipStream_t s);
+// Safe delayed batching: per op, invocations available now, expected from
+// upstream, and the estimated wait for them; cfg CFG_WAIT means wait.
+constexpr int CFG_WAIT = -2;
+struct BatchingArgs {
+  const int32_t* available;
+  const int32_t* upstream;
+  const int32_t* wait_us;
+};
+hipError_t launch_decide_batching(const DevTables& t, const Batch& b, const BatchingArgs& a, hipStream_t s);
 // Stable LSD radix sort of (uint64 key, int32 value) pairs (sort_kernels.hip).
 hipError_t sort_pairs_bytes(int n, size_t* bytes);
 hipError_t sort_pairs(void* tmp, size_t tmp_bytes, const uint64_t* kin, uint64_t* kout, const int32_t* vin,

@@ -1569,6 +1569,91 @@ __global__ __launch_bounds__(256) void affinity_kernel(DevTables t, Batch b, dou
   }
 }
 
+// ---------------------------------------------------------------------------
+// Safe delayed batching: one wavefront per invocation, lanes over the op's
+// configurations (caller order, coalesced), four running minima: the
+// cheapest feasible key and the fastest (L << 16 | k) over all
+// configurations, and the same over those whose batch fits the available
+// invocations; lane 0 then takes the commit-or-wait decision.
+// ---------------------------------------------------------------------------
+template <int NHW>
+__global__ __launch_bounds__(256) void decide_batching_kernel(DevTables t, Batch b, BatchingArgs ba) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= b.n) return;  // uniform per wavefront
+  const int v = b.op[i], e = b.elapsed[i], s = b.slo[i];
+  if (invalid_invocation(v, e, s, t.n_ops)) {
+    if (lane == 0) {
+      b.cfg[i] = -1;
+      if (b.flag) b.flag[i] = 0;
+      atomicOr(t.err, 1u);
+    }
+    return;
+  }
+  const int64_t r0 = (int64_t)s - e;
+  const int64_t ref = t.ref[v];
+  const int64_t W = t.W[(int64_t)b.mode * t.n_ops + v];
+  int32_t target[NHW];
+#pragma unroll
+  for (int h = 0; h < NHW; ++h) {
+    const int64_t R = remaining_time(r0, b.queue ? b.queue[h] : 0);
+    target[h] = R == 0 ? 0 : (int32_t)div_floor_pos(ref * R, W);
+  }
+  const int a = t.cfg_off[v], end = t.cfg_off[v + 1];
+  const int32_t av = ba.available[v];
+  const int64_t limit = av > 1 ? av : 1;
+  uint32_t kF = KEY_NONE, kFr = KEY_NONE;
+  uint64_t fA = ~0ull, fR = ~0ull;
+  for (int x = a + lane; x < end; x += 64) {
+    const int32_t L = t.cfg_lat[x];
+    const uint32_t key = t.cfg_key[x];
+    const int hw = t.cfg_hw[x];
+    const int32_t B = t.cfg_batch[x];
+    int32_t tg = target[0];
+#pragma unroll
+    for (int h = 1; h < NHW; ++h) tg = hw == h ? target[h] : tg;
+    const bool feas = L < tg;
+    const uint64_t fk = ((uint64_t)(uint32_t)L << 16) | (uint32_t)(x - a);
+    if (feas && key < kF) kF = key;
+    if (fk < fA) fA = fk;
+    if (B <= limit) {
+      if (feas && key < kFr) kFr = key;
+      if (fk < fR) fR = fk;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint32_t o1 = __shfl_xor(kF, off, 64), o2 = __shfl_xor(kFr, off, 64);
+    const uint64_t o3 = __shfl_xor(fA, off, 64), o4 = __shfl_xor(fR, off, 64);
+    kF = o1 < kF ? o1 : kF;
+    kFr = o2 < kFr ? o2 : kFr;
+    fA = o3 < fA ? o3 : fA;
+    fR = o4 < fR ? o4 : fR;
+  }
+  if (lane != 0) return;
+  const bool meets = kF != KEY_NONE;
+  const int xs = (int)((meets ? (uint64_t)kF : fA) & 0xFFFFu);
+  const int32_t Bx = t.cfg_batch[a + xs];
+  int c = xs;
+  uint8_t f = meets ? 1 : 0;
+  if (Bx > av) {
+    const int hx = t.cfg_hw[a + xs];
+    int32_t tx = target[0];
+#pragma unroll
+    for (int h = 1; h < NHW; ++h) tx = hx == h ? target[h] : tx;
+    if (meets && (int64_t)av + ba.upstream[v] >= Bx && (int64_t)ba.wait_us[v] + t.cfg_lat[a + xs] < tx) {
+      c = CFG_WAIT;
+      f = 1;
+    } else if (fR != ~0ull) {
+      const bool mr = kFr != KEY_NONE;
+      c = (int)((mr ? (uint64_t)kFr : fR) & 0xFFFFu);
+      f = mr ? 1 : 0;
+    }
+  }
+  b.cfg[i] = c;
+  if (b.flag) b.flag[i] = f;
+}
+
 #define LLAMA_DISPATCH_NHW(KERNEL, GRID, BLOCK, STREAM, ...)                         \
   switch (t.n_hw) {                                                                  \
     case 1: hipLaunchKernelGGL(KERNEL<1>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
@@ -1642,6 +1727,12 @@ hipError_t launch_feedback(const DevTables& t, const FeedbackArgs& f, int64_t n,
 #undef LLAMA_RETABLE
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_decide_batching(const DevTables& t, const Batch& b, const BatchingArgs& a, hipStream_t s) {
+  if (b.n == 0) return hipSuccess;
+  LLAMA_DISPATCH_NHW(decide_batching_kernel, dim3(blocks_for(b.n, 4)), dim3(256), s, t, b, a);
   return hipGetLastError();
 }
 

@@ -236,6 +236,25 @@ int llama_decide_alpha(llama_ctx* c, int64_t n, const int32_t* op, const int32_t
   return LLAMA_OK;
 }
 
+int llama_decide_batching(llama_ctx* c, int64_t n, const int32_t* op, const int32_t* elapsed, const int32_t* slo,
+                          const int64_t* queue, int32_t mode, const int32_t* available, const int32_t* upstream,
+                          const int32_t* wait_us, int32_t* cfg, uint8_t* flag, void* stream) {
+  int rc = llama::enter(c);
+  if (rc) return rc;
+  if (!c->has_prof) return llama::fail(c, LLAMA_E_STATE, "decide_batching: no profiles");
+  if (n < 0) return llama::fail(c, LLAMA_E_ARG, "decide_batching: n_inv < 0");
+  if (n > 0 && (!op || !elapsed || !slo || !cfg || !available || !upstream || !wait_us))
+    return llama::fail(c, LLAMA_E_ARG, "decide_batching: null pointer");
+  if (mode != LLAMA_SLACK_PAPER && mode != LLAMA_SLACK_PROB)
+    return llama::fail(c, LLAMA_E_ARG, "decide_batching: bad slack_mode %d", mode);
+  llama::Batch b{};
+  b.n = n; b.op = op; b.elapsed = elapsed; b.slo = slo; b.queue = queue; b.cfg = cfg; b.flag = flag; b.mode = mode;
+  llama::BatchingArgs a{available, upstream, wait_us};
+  hipError_t e = llama::launch_decide_batching(c->tables(), b, a, (hipStream_t)stream);
+  if (e != hipSuccess) return llama::hip_fail(c, e, "decide_batching launch");
+  return LLAMA_OK;
+}
+
 int llama_affinity(llama_ctx* c, int64_t n, const int32_t* op, const int32_t* elapsed, const int32_t* slo,
                    const int64_t* queue, int32_t mode, double* aff, int32_t* order, void* stream) {
   int rc = llama::enter(c);
