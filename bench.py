@@ -66,6 +66,37 @@ def parse():
     return ap.parse_args()
 
 
+# kernel of each decision schedule (llama_autotune's numbering)
+SCHEDULE_KERNELS = ("void decide_indexed_kernel<1, false>", "void decide_indexed_kernel<2, false>",
+                    "void decide_indexed_kernel<4, false>", "decide_lds_kernel",
+                    "void decide_indexed_kernel<1, true>", "void decide_indexed_kernel<2, true>",
+                    "void decide_indexed_kernel<4, true>")
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a device copy), or None
+    when there is none or the kernel source has changed since it was taken."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", f"decide_plain_{workload}_hbm_traffic.md")
+    src = os.path.join(here, "paper_2102_01887_amd", "csrc", "llama_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    with open(src, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    recorded, table = None, {}
+    for line in open(path):
+        if line.startswith("kernel source sha256:"):
+            recorded = line.split(":", 1)[1].strip()
+        elif line.startswith("traffic_bytes_per_launch "):
+            name, value = line[len("traffic_bytes_per_launch "):].rsplit(":", 1)
+            table[name.strip()] = int(value)
+    if recorded != digest:
+        return None
+    return table.get(kernel)
+
+
 def graph_of(torch, stream, fn, reps):
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=stream):
@@ -652,8 +683,9 @@ def main():
                    "steps_per_graph": spg,
                    "decide_schedule": B.SCHEDULE_NAMES[tuned[0]]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": ("decide_lds_kernel" if tuned[0] == 3 else "decide_indexed_kernel"), "kernel_ms": ms_dec,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.workload, SCHEDULE_KERNELS[tuned[0]]),
+                     "kernel": SCHEDULE_KERNELS[tuned[0]], "kernel_ms": ms_dec,
                      "algo_bytes": algo_bytes},
         "cpu_baseline": cpu,
         "bit_exact": bit_exact,
