@@ -49,6 +49,9 @@ def parse():
                     help="for hardware-counter runs: a 256 MiB device copy (calibration) and a few "
                          "eager relax + decide launches on the benchmark workload, nothing timed")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--no-pipeline", dest="pipeline", action="store_false",
+                    help="run each step's relaxation and decisions back to back on one stream "
+                         "(default: the relaxation of step k+1 overlaps the decisions of step k)")
     ap.add_argument("--steps-per-graph", type=int, default=20,
                     help="steps captured in one HIP graph (the timed loop replays it, then a "
                          "one-step graph for the remainder, so exactly --steps steps run)")
@@ -571,7 +574,35 @@ def main():
     log("bench: capturing graphs")
     g_step = graph_of(torch, s, step, 1)
     spg = max(1, min(args.steps_per_graph, args.steps))
-    g_steps = graph_of(torch, s, step, spg)
+    s_dec = torch.cuda.Stream()
+
+    def pipelined_graph(n_steps):
+        """n_steps steps in one graph on two streams: the relaxation of step
+        k+1 (stream s) overlaps the decisions of step k (stream s_dec); the
+        relaxations alternate between the two record sets, so the one of
+        step k+2 waits for the decisions of step k."""
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            fork = torch.cuda.Event()
+            fork.record(s)
+            s_dec.wait_event(fork)
+            done = [None, None]
+            last = None
+            for k in range(n_steps):
+                if done[k % 2] is not None:
+                    s.wait_event(done[k % 2])
+                relax()
+                ready = torch.cuda.Event()
+                ready.record(s)
+                s_dec.wait_event(ready)
+                L.decide(op, el, slo, None, mode, B.SCAN_INDEXED, cfg, flag, stream=s_dec)
+                last = torch.cuda.Event()
+                last.record(s_dec)
+                done[k % 2] = last
+            s.wait_event(last)
+        return g
+
+    g_steps = pipelined_graph(spg) if args.pipeline else graph_of(torch, s, step, spg)
     g_dec = graph_of(torch, s, decide(B.SCAN_INDEXED), args.kernel_reps)
     L.reserve(n)
     g_full = graph_of(torch, s, decide(B.SCAN_FULL), max(1, args.kernel_reps // 10))
@@ -615,9 +646,11 @@ def main():
     pairs = int(np.diff(w.cfg_off)[w.inv_op].sum())
     full_gops = pairs * 3 / (ms_full * 1e-3) / 1e9
 
-    # parity of what was timed (the oracle also gives the CPU baseline)
+    # parity of what was timed (the oracle also gives the CPU baseline): the
+    # decisions left by one more replay of the timed multi-step graph
     torch.cuda.synchronize()
-    g_step.replay()
+    cfg.fill_(-7)
+    g_steps.replay()
     torch.cuda.synchronize()
     c_gpu, f_gpu = cfg.cpu().numpy(), flag.cpu().numpy()
     cpu = None
@@ -681,6 +714,8 @@ def main():
                    "n_inv": n, "n_hw": w.n_hw, "slack_mode": args.mode,
                    "scan": "indexed", "step": "relax + records + decide",
                    "steps_per_graph": spg,
+                   "pipelined": ("relaxation of step k+1 overlaps the decisions of step k "
+                                 "(two streams, double-buffered records)") if args.pipeline else False,
                    "decide_schedule": B.SCHEDULE_NAMES[tuned[0]]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

@@ -167,6 +167,12 @@ int llama_set_profiles(llama_ctx *ctx, int32_t n_ops, int32_t n_hw,
  * outputs upward) and the per-configuration remaining-time thresholds that
  * llama_decide uses.  llama_set_profiles already does this; call it again
  * after changing reference latencies (llama_update_latencies).
+ * The thresholds are double-buffered: each call writes the set the previous
+ * call did not, and decision calls issued after it read the new set.  So a
+ * relaxation may run on one stream while the decisions that follow the
+ * previous relaxation run on another; the caller orders each decision after
+ * its relaxation, and each relaxation after the decisions of the
+ * relaxation before the previous one (which used the same set).
  */
 int llama_relax(llama_ctx *ctx, void *stream);
 

@@ -109,7 +109,7 @@ int llama_feedback(llama_ctx* c, int64_t n, const int32_t* obs_op, const int32_t
   f.cfg_q = c->d_cfg_q.p ? c->d_cfg_q.as<uint4>() : nullptr;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = llama::launch_feedback(t, f, n, obs_op, obs_cfg, obs_lat, beta_q16, s);
-  if (e == hipSuccess) e = llama::launch_relax(t, s);
+  if (e == hipSuccess) e = llama::relax_next(c, s);
   if (e != hipSuccess) return llama::hip_fail(c, e, "feedback launch");
   c->host_stale = true;
   c->has_alpha = false;  // the finite-alpha tables follow the latencies: llama_set_alpha again

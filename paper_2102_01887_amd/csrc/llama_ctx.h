@@ -65,7 +65,12 @@ struct llama_ctx {
   std::vector<int32_t> cfg_off, hw, batch, res, lat, ref_k, ref, fastest;
   std::vector<int64_t> cost;
   std::vector<uint32_t> key;  // caller order
-  DevBuf d_ref, d_W, d_hdr, d_front_L, d_rec, d_rec_tail, d_ovf, d_rec_q, d_rec_tail_q, d_ovf_q, d_seg_off, d_tab;
+  DevBuf d_ref, d_W, d_hdr, d_front_L, d_rec_q, d_rec_tail_q, d_ovf_q, d_seg_off, d_tab;
+  // Decision records, double-buffered: each relaxation writes the set the
+  // previous one did not, and decisions read the set of the latest one, so a
+  // relaxation can overlap the decisions of the batch before it.
+  DevBuf d_rec[2], d_rec_tail[2], d_ovf[2];
+  int rec_cur = 0;  // set written by the latest relaxation
   DevBuf d_mst, d_mst_n;
   DevBuf d_cfg_off, d_cfg_hw, d_cfg_lat, d_cfg_key, d_cfg_q, d_cfg_batch;
   std::vector<int64_t> res_total;  // [n_hw] or empty
@@ -117,10 +122,10 @@ struct llama_ctx {
     t.front_L = d_front_L.as<uint2>();
     t.mst = d_mst.as<uint2>();
     t.mst_n = d_mst_n.as<int32_t>();
-    t.rec = d_rec.as<uint4>();
-    t.rec_tail = d_rec_tail.as<uint4>();
+    t.rec = d_rec[rec_cur].as<uint4>();
+    t.rec_tail = d_rec_tail[rec_cur].as<uint4>();
     t.rec_tail_q = d_rec_tail_q.as<uint4>();
-    t.ovf = d_ovf.as<uint2>();
+    t.ovf = d_ovf[rec_cur].as<uint2>();
     t.rec_q = d_rec_q.as<uint4>();
     t.ovf_q = d_ovf_q.as<uint2>();
     t.cfg_off = d_cfg_off.as<int32_t>();
@@ -144,10 +149,19 @@ struct llama_ctx {
     return t;
   }
 
+  // Tables with the record set `set` (the relaxation's output).
+  DevTables tables_for(int set) const {
+    DevTables t = tables();
+    t.rec = d_rec[set].as<uint4>();
+    t.rec_tail = d_rec_tail[set].as<uint4>();
+    t.ovf = d_ovf[set].as<uint2>();
+    return t;
+  }
+
   int64_t device_bytes() const {
     const DevBuf* all[] = {&d_pipe_off, &d_pipe_desc, &d_lvl_edge, &d_lvl_edge_q, &d_lvl_ebnd, &d_lvl_bnd, &d_lvl_ops, &d_succ_off,
                            &d_succ_ids, &d_succ_q, &d_ref, &d_W, &d_hdr, &d_front_L,
-                           &d_rec, &d_rec_tail, &d_ovf, &d_rec_q, &d_rec_tail_q, &d_ovf_q, &d_seg_off, &d_tab, &d_err,
+                           &d_rec[0], &d_rec_tail[0], &d_ovf[0], &d_rec[1], &d_rec_tail[1], &d_ovf[1], &d_rec_q, &d_rec_tail_q, &d_ovf_q, &d_seg_off, &d_tab, &d_err,
                            &d_cnt, &d_start, &d_cursor, &d_perm, &d_hist, &d_mst,
                            &d_mst_n, &d_cfg_off, &d_cfg_hw, &d_cfg_lat, &d_cfg_key, &d_cfg_q, &d_cfg_batch, &d_a_lat, &d_a_pf, &d_a_si, &d_m_lat, &d_m_pf, &d_m_si, &d_a_val, &d_aff_scratch, &d_qacc, &d_fb_ksrc, &d_fb_tab_src, &d_fb_ref_k, &d_fb_count, &d_fb_sum, &d_fb_dirty};
     int64_t s = 0;
@@ -169,4 +183,6 @@ int build_alpha_tables(llama_ctx* c);
 // feedback (feedback_host.cpp): refresh the host copies of the latencies
 // after device-side feedback
 int pull_profiles(llama_ctx* c);
+// Relaxation into the record set not written last (then decisions use it).
+hipError_t relax_next(llama_ctx* c, hipStream_t s);
 }  // namespace llama

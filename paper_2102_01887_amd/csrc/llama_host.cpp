@@ -89,6 +89,13 @@ int sync_ctx(llama_ctx* c, const char* what) {
   return LLAMA_OK;
 }
 
+hipError_t relax_next(llama_ctx* c, hipStream_t s) {
+  const int set = 1 - c->rec_cur;
+  hipError_t e = launch_relax(c->tables_for(set), s);
+  if (e == hipSuccess) c->rec_cur = set;
+  return e;
+}
+
 }  // namespace llama
 
 namespace {
@@ -425,7 +432,7 @@ int llama_relax(llama_ctx* c, void* stream) {
   int rc = enter(c);
   if (rc) return rc;
   if (!c->has_prof) return fail(c, LLAMA_E_STATE, "relax: no profiles");
-  hipError_t e = llama::launch_relax(c->tables(), (hipStream_t)stream);
+  hipError_t e = llama::relax_next(c, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(c, e, "relax launch");
   return LLAMA_OK;
 }
@@ -558,11 +565,14 @@ int build_tables(llama_ctx* c) {
       (rc = upload(c, c->d_W, nullptr, sizeof(int64_t) * 2 * (size_t)n_ops, "W")) ||
       (rc = upload_vec(c, c->d_hdr, hdr, "hdr")) ||
       (rc = upload_vec(c, c->d_front_L, front_L, "front_L")) ||
-      (rc = upload_vec(c, c->d_rec, rec_hot, "records")) ||
-      (rc = upload_vec(c, c->d_rec_tail, rec_tail, "record tails")) ||
+      (rc = upload_vec(c, c->d_rec[0], rec_hot, "records")) ||
+      (rc = upload_vec(c, c->d_rec_tail[0], rec_tail, "record tails")) ||
+      (rc = upload_vec(c, c->d_rec[1], rec_hot, "records")) ||
+      (rc = upload_vec(c, c->d_rec_tail[1], rec_tail, "record tails")) ||
       (rc = upload_vec(c, c->d_mst, mst, "merged frontier")) ||
       (rc = upload_vec(c, c->d_mst_n, mst_n, "merged frontier sizes")) ||
-      (rc = upload(c, c->d_ovf, nullptr, sizeof(uint2) * 2 * (size_t)pos, "record overflow")) ||
+      (rc = upload(c, c->d_ovf[0], nullptr, sizeof(uint2) * 2 * (size_t)pos, "record overflow")) ||
+      (rc = upload(c, c->d_ovf[1], nullptr, sizeof(uint2) * 2 * (size_t)pos, "record overflow")) ||
       (rc = upload(c, c->d_rec_q, nullptr, sizeof(uint4) * (size_t)n_ops, "records (queue)")) ||
       (rc = upload(c, c->d_rec_tail_q, nullptr, sizeof(uint4) * 3 * (size_t)n_ops, "record tails (queue)")) ||
       (rc = upload(c, c->d_ovf_q, nullptr, sizeof(uint2) * (size_t)pos, "record overflow (queue)")) ||
@@ -589,7 +599,7 @@ int build_tables(llama_ctx* c) {
   } else {
     c->d_cfg_q.release();
   }
-  hipError_t e = llama::launch_relax(c->tables(), c->stream);
+  hipError_t e = llama::relax_next(c, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "relax launch");
   return sync_ctx(c, "set_profiles");
 }
