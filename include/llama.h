@@ -386,6 +386,15 @@ int llama_autotune(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
                    const int32_t *d_elapsed_us, const int32_t *d_slo_us, int32_t *d_cfg_scratch,
                    int32_t *chosen, float *best_us, void *stream);
 
+/*
+ * Pin the schedule of the indexed decision kernel (0..6, numbered as for
+ * llama_autotune) instead of timing them, e.g. when the decision runs beside
+ * other kernels and the schedule that is fastest alone is not.  Schedule 3
+ * needs at most 9,216 ops (LLAMA_E_ARG otherwise, as for a number outside
+ * 0..6).  Every schedule gives the same decisions.
+ */
+int llama_set_schedule(llama_ctx *ctx, int32_t schedule);
+
 /* Pre-size the scratch that LLAMA_SCAN_FULL needs for batches of up to
  * max_inv invocations (device memory, 4 bytes per invocation).  Synchronous. */
 int llama_reserve(llama_ctx *ctx, int64_t max_inv);

@@ -35,7 +35,7 @@ EXPORTS = ["llama_create", "llama_destroy", "llama_last_error", "llama_set_dag",
            "llama_surrogate_save", "llama_surrogate_load", "llama_decide_learned",
            "llama_surrogate_fit", "llama_select_rows", "llama_serve_bytes_per_request",
            "llama_serve_open", "llama_serve_submit", "llama_serve_poll", "llama_serve_stats_get",
-           "llama_serve_close", "llama_autotune", "llama_queue_time", "llama_set_alpha",
+           "llama_serve_close", "llama_autotune", "llama_set_schedule", "llama_queue_time", "llama_set_alpha",
            "llama_decide_alpha", "llama_feedback", "llama_affinity", "llama_decide_batching"]
 
 
@@ -98,6 +98,7 @@ def load_library(path=LIB_PATH):
         "llama_serve_poll": [p, i32, p, p, p, p, ctypes.POINTER(i32), i32],
         "llama_serve_stats_get": [p, ctypes.POINTER(ServeStats)],
         "llama_serve_close": [p],
+        "llama_set_schedule": [p, i32],
         "llama_get_stats": [p, ctypes.POINTER(LlamaStats), i32],
         "llama_debug_export": [p, i32, p, i64],
         "llama_surrogate_param_count": [i64],
@@ -241,6 +242,10 @@ class Llama:
             self._ctx, n, _dp(op, "int32"), _dp(elapsed, "int32", n), _dp(slo, "int32", n),
             _dp(scratch, "int32", n), ctypes.byref(k), ctypes.byref(us), _stream(stream)))
         return k.value, us.value
+
+    def set_schedule(self, schedule):
+        """Pin the indexed decision's schedule (0..6, as numbered by autotune)."""
+        self._check("llama_set_schedule", self._L.llama_set_schedule(self._ctx, int(schedule)))
 
     def reserve(self, max_inv):
         self._check("llama_reserve", self._L.llama_reserve(self._ctx, int(max_inv)))

@@ -762,6 +762,17 @@ int llama_autotune(llama_ctx* c, int64_t n, const int32_t* op, const int32_t* el
   return LLAMA_OK;
 }
 
+int llama_set_schedule(llama_ctx* c, int32_t schedule) {
+  int rc = enter(c);
+  if (rc) return rc;
+  if (schedule < llama::SCHED_DIRECT1 || schedule > llama::SCHED_DIRECT4_NT)
+    return fail(c, LLAMA_E_ARG, "set_schedule: schedule %d outside 0..6", schedule);
+  if (schedule == llama::SCHED_LDS && c->n_ops > llama::LDS_REC_MAX_OPS)
+    return fail(c, LLAMA_E_ARG, "set_schedule: the LDS schedule needs at most %d ops", llama::LDS_REC_MAX_OPS);
+  c->decide_sched = schedule;
+  return LLAMA_OK;
+}
+
 int llama_reserve(llama_ctx* c, int64_t max_inv) {
   int rc = enter(c);
   if (rc) return rc;

@@ -132,12 +132,15 @@ __device__ __forceinline__ uint32_t entry_threshold(const OpScale& o, uint32_t L
 // words are assembled in registers and written as whole 16-byte chunks;
 // entries past the record go to the overflow array, ascending.
 // What an op's records need besides W: its merged-frontier range, overflow
-// offset, fastest configuration and the REC_SLOTS entries of largest latency
-// (static between latency updates, so they can be loaded ahead of W).
+// offset, fastest configuration, the REC_SLOTS entries of largest latency and
+// the first OVF_PREFETCH entries past them (static between latency updates,
+// so they can be loaded ahead of W).
+constexpr int OVF_PREFETCH = 16;
 struct OpStatic {
   int first, n, base;
   uint32_t fastest;
   uint2 e[REC_SLOTS];
+  uint2 x[OVF_PREFETCH];
 };
 
 __device__ __forceinline__ OpStatic load_op_static(const DevTables& t, int v) {
@@ -153,6 +156,13 @@ __device__ __forceinline__ OpStatic load_op_static(const DevTables& t, int v) {
   for (int slot = 0; slot < REC_SLOTS; ++slot) {
     const int j = o.n - 1 - slot;
     o.e[slot] = t.mst[o.first + (j > 0 ? j : 0)];
+  }
+  const int last = o.n - REC_SLOTS - 1;  // last overflow entry, < 0 if none
+#pragma unroll
+  for (int k = 0; k < OVF_PREFETCH; ++k) o.x[k] = make_uint2(0u, 0u);
+  if (last >= 0) {
+#pragma unroll
+    for (int k = 0; k < OVF_PREFETCH; ++k) o.x[k] = t.mst[o.first + (k < last ? k : last)];
   }
   return o;
 }
@@ -181,9 +191,13 @@ __device__ __forceinline__ void write_op_records(const DevTables& t, int v, cons
     tl[0] = make_uint4(w[4], w[5], w[6], w[7]);
     tl[1] = make_uint4(w[8], w[9], w[10], w[11]);
     tl[2] = make_uint4(w[12], w[13], w[14], w[15]);
-    // entries past the record, ascending, four loads in flight at a time
+    // entries past the record, ascending: the prefetched ones, then four
+    // loads in flight at a time
     uint2* ovf = t.ovf + (int64_t)mode * t.n_front + st.base;
-    for (int pos = 0; pos < n_ovf; pos += 4) {
+#pragma unroll
+    for (int k = 0; k < OVF_PREFETCH; ++k)
+      if (k < n_ovf) ovf[k] = make_uint2(entry_threshold(o, st.x[k].x), st.x[k].y);
+    for (int pos = OVF_PREFETCH; pos < n_ovf; pos += 4) {
       uint2 x[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) x[u] = t.mst[st.first + (pos + u < n_ovf ? pos + u : n_ovf - 1)];

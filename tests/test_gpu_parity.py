@@ -351,3 +351,34 @@ def test_autotuned_schedules_agree_with_oracle(maker):
     c, f = r.decide(PAPER, B.SCAN_INDEXED)
     c_or, f_or = r.P.decide(PAPER)
     assert np.array_equal(c, c_or) and np.array_equal(f, f_or)
+
+
+def test_pinned_schedules_agree_with_oracle():
+    # llama_set_schedule pins each schedule in turn; every one must give the
+    # oracle's decisions in both slack modes, flags included, on a batch with
+    # a ragged tail and invalid invocations
+    torch = _torch()
+    w = wl.make_c2(seed=33, n_pipelines=30, n_inv=70_001)
+    r = Run(w)
+    for mode in (PAPER, PROB):
+        c_or, f_or = r.P.decide(mode)
+        for sched in range(len(B.SCHEDULE_NAMES)):
+            r.L.set_schedule(sched)
+            c, f = r.decide(mode, B.SCAN_INDEXED)
+            assert np.array_equal(c, c_or) and np.array_equal(f, f_or), (mode, B.SCHEDULE_NAMES[sched])
+    c_or, f_or = r.P.decide(PAPER)
+    op = w.inv_op.copy()
+    op[5::97] = -1
+    for sched in range(len(B.SCHEDULE_NAMES)):
+        r.L.set_schedule(sched)
+        c, f = r.L.decide(dev(op, torch), r.el, r.slo, scan=B.SCAN_INDEXED)
+        torch.cuda.synchronize()
+        c, f = c.cpu().numpy(), f.cpu().numpy()
+        assert (c[5::97] == -1).all() and (f[5::97] == 0).all()
+        ok = np.ones(len(op), bool)
+        ok[5::97] = False
+        assert np.array_equal(c[ok], c_or[ok]) and np.array_equal(f[ok], f_or[ok])
+        assert r.L.stats(reset_error=True)["device_error"] & B.DEVERR_INVALID_INVOCATION
+    for bad in (-1, len(B.SCHEDULE_NAMES)):
+        with pytest.raises(B.LlamaError):
+            r.L.set_schedule(bad)
