@@ -67,12 +67,6 @@ __device__ __forceinline__ int64_t branch_discount(uint32_t q, int64_t w) {
   return (int64_t)(((uint64_t)q * (uint64_t)w) >> 16);
 }
 
-// Bytes of dynamic LDS that relax_kernel needs for the given capacities.
-size_t relax_lds_bytes(const DevTables& t) {
-  return sizeof(uint64_t) * 2 * (size_t)t.relax_ops +
-         sizeof(int32_t) * ((size_t)t.relax_ops + 2 * (size_t)t.relax_edges + (size_t)t.relax_lvls + 1);
-}
-
 // Exact thresholds of one (op, slack mode).  The stored threshold of an
 // entry with latency L is U = T - 1, T = ceil(y), y = (L + 1) * W / ref, or
 // INT32_MAX when T > 2^31 - 1 (no remaining time reaches it).
@@ -90,7 +84,6 @@ struct OpScale {
   int64_t W;
   int64_t ref;
   double scale;     // fl(fl(W) / ref)
-  double inv_ref;
 };
 
 __device__ __forceinline__ OpScale op_scale(int64_t W, int32_t ref) {
@@ -103,15 +96,14 @@ __device__ __forceinline__ OpScale op_scale(int64_t W, int32_t ref) {
   o.W = W;
   o.ref = ref;
   o.scale = (double)W / (double)ref;
-  o.inv_ref = 1.0 / (double)ref;
   return o;
 }
 
-__device__ __forceinline__ uint32_t entry_threshold_exact(const OpScale& o, uint32_t l1) {
-  const int64_t num = (int64_t)((uint64_t)l1 * (uint64_t)o.W) + o.ref - 1;
-  int64_t q = (int64_t)(uint32_t)((double)num * o.inv_ref);  // estimate below 2^31 + 1
-  const int64_t r = num - q * o.ref;
-  q += r < 0 ? -1 : (r >= o.ref ? 1 : 0);
+__device__ __forceinline__ uint32_t entry_threshold_exact(int64_t W, int64_t ref, uint32_t l1) {
+  const int64_t num = (int64_t)((uint64_t)l1 * (uint64_t)W) + ref - 1;
+  int64_t q = (int64_t)(uint32_t)((double)num / (double)ref);  // estimate below 2^31 + 1
+  const int64_t r = num - q * ref;
+  q += r < 0 ? -1 : (r >= ref ? 1 : 0);
   return (uint32_t)q - 1u;  // q = T >= 1
 }
 
@@ -122,7 +114,7 @@ __device__ __forceinline__ uint32_t entry_threshold(const OpScale& o, uint32_t L
   const double fl = floor(x);
   const double fr = x - fl;
   if (fr >= 0x1p-19 && fr <= 1.0 - 0x1p-19) return (uint32_t)fl;
-  return entry_threshold_exact(o, l1);
+  return entry_threshold_exact(o.W, o.ref, l1);
 }
 
 // Queue-free records of op v, both slack modes.  The merged frontier of an
@@ -167,54 +159,88 @@ __device__ __forceinline__ OpStatic load_op_static(const DevTables& t, int v) {
   return o;
 }
 
+// Records of op v for one slack mode (W of that mode).
 __device__ __forceinline__ void write_op_records(const DevTables& t, int v, const OpStatic& st, int32_t ref,
-                                                 int64_t Wp, int64_t Wq) {
+                                                 int64_t W, int mode) {
   const int n = st.n;
   if (n <= 0) return;
   const int n_ovf = n - REC_SLOTS;
+  const OpScale o = op_scale(W, ref);
+  uint32_t Ls[REC_SLOTS], Us[REC_SLOTS], Lx[OVF_PREFETCH], Ux[OVF_PREFETCH];
 #pragma unroll
-  for (int mode = 0; mode < 2; ++mode) {
-    const OpScale o = op_scale(mode ? Wq : Wp, ref);
-    uint32_t w[REC_WORDS];
+  for (int slot = 0; slot < REC_SLOTS; ++slot) Ls[slot] = st.e[slot].x;
 #pragma unroll
-    for (int k = 0; k < REC_WORDS; ++k) w[k] = 0;
-    w[0] = (uint32_t)n | (st.fastest << 16);
+  for (int k = 0; k < OVF_PREFETCH; ++k) Lx[k] = st.x[k].x;
 #pragma unroll
-    for (int slot = 0; slot < REC_SLOTS; ++slot) {
-      const bool used = slot < n;
-      w[rec_u_word(slot)] = used ? entry_threshold(o, st.e[slot].x) : 0x7FFFFFFFu;
-      w[rec_k_word(slot)] |= (used ? st.e[slot].y & 0xFFFFu : 0u) << rec_k_shift(slot);
-    }
-    const int64_t r = (int64_t)mode * t.n_ops + v;
-    t.rec[r] = make_uint4(w[0], w[1], w[2], w[3]);
-    uint4* tl = t.rec_tail + r * 3;
-    tl[0] = make_uint4(w[4], w[5], w[6], w[7]);
-    tl[1] = make_uint4(w[8], w[9], w[10], w[11]);
-    tl[2] = make_uint4(w[12], w[13], w[14], w[15]);
-    // entries past the record, ascending: the prefetched ones, then four
-    // loads in flight at a time
-    uint2* ovf = t.ovf + (int64_t)mode * t.n_front + st.base;
+  for (int k = 0; k < REC_SLOTS; ++k) Us[k] = entry_threshold(o, Ls[k]);
 #pragma unroll
-    for (int k = 0; k < OVF_PREFETCH; ++k)
-      if (k < n_ovf) ovf[k] = make_uint2(entry_threshold(o, st.x[k].x), st.x[k].y);
-    for (int pos = OVF_PREFETCH; pos < n_ovf; pos += 4) {
-      uint2 x[4];
+  for (int k = 0; k < OVF_PREFETCH; ++k) Ux[k] = k < n_ovf ? entry_threshold(o, Lx[k]) : 0u;
+  uint32_t w[REC_WORDS];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) x[u] = t.mst[st.first + (pos + u < n_ovf ? pos + u : n_ovf - 1)];
+  for (int k = 0; k < REC_WORDS; ++k) w[k] = 0;
+  w[0] = (uint32_t)n | (st.fastest << 16);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (pos + u >= n_ovf) break;
-        ovf[pos + u] = make_uint2(entry_threshold(o, x[u].x), x[u].y);
-      }
+  for (int slot = 0; slot < REC_SLOTS; ++slot) {
+    const bool used = slot < n;
+    w[rec_u_word(slot)] = used ? Us[slot] : 0x7FFFFFFFu;
+    w[rec_k_word(slot)] |= (used ? st.e[slot].y & 0xFFFFu : 0u) << rec_k_shift(slot);
+  }
+  const int64_t r = (int64_t)mode * t.n_ops + v;
+  t.rec[r] = make_uint4(w[0], w[1], w[2], w[3]);
+  uint4* tl = t.rec_tail + r * 3;
+  tl[0] = make_uint4(w[4], w[5], w[6], w[7]);
+  tl[1] = make_uint4(w[8], w[9], w[10], w[11]);
+  tl[2] = make_uint4(w[12], w[13], w[14], w[15]);
+  // entries past the record, ascending: the prefetched ones, then four
+  // loads in flight at a time
+  uint2* ovf = t.ovf + (int64_t)mode * t.n_front + st.base;
+#pragma unroll
+  for (int k = 0; k < OVF_PREFETCH; ++k)
+    if (k < n_ovf) ovf[k] = make_uint2(Ux[k], st.x[k].y);
+  for (int pos = OVF_PREFETCH; pos < n_ovf; pos += 4) {
+    uint2 x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = t.mst[st.first + (pos + u < n_ovf ? pos + u : n_ovf - 1)];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (pos + u >= n_ovf) break;
+      ovf[pos + u] = make_uint2(entry_threshold(o, x[u].x), x[u].y);
     }
   }
 }
 
-// RECORDS: every pipeline has at most 64 ops; lane i also writes the records
-// of the pipeline's op i, its static part loaded before the relaxation so
-// that the loads overlap the level passes.
+// Bytes of dynamic LDS that relax_kernel needs for the given capacities:
+// accumulators, reference latencies, edges and level bounds, and with
+// RECORDS each op's static record inputs (16-byte aligned).
+__host__ __device__ inline size_t relax_lds_core_bytes(int ops, int edges, int lvls) {
+  const size_t b = sizeof(uint64_t) * 2 * (size_t)ops + sizeof(int32_t) * ((size_t)ops + 2 * (size_t)edges + (size_t)lvls + 1);
+  return (b + 15) & ~(size_t)15;
+}
+size_t relax_lds_bytes(const DevTables& t, bool records) {
+  return relax_lds_core_bytes(t.relax_ops, t.relax_edges, t.relax_lvls) +
+         (records ? sizeof(OpStatic) * (size_t)t.relax_ops : 0);
+}
+
+// One edge of a level: fold the successor's W (reference latency rd plus its
+// accumulator) into the source's accumulator, for both slack modes.
+__device__ __forceinline__ void relax_edge(uint64_t* sAccP, uint64_t* sAccQ, uint32_t pk, uint32_t q, int32_t rd) {
+  const int src = (int)(pk & 0xFFFFu), dst = (int)(pk >> 16);
+  const uint64_t wp = (uint64_t)(rd + (int64_t)sAccP[dst]);
+  const uint64_t wq = (uint64_t)branch_discount(q, rd + (int64_t)sAccQ[dst]);
+  atomicMax((unsigned long long*)&sAccP[src], (unsigned long long)wp);
+  atomicMax((unsigned long long*)&sAccQ[src], (unsigned long long)wq);
+}
+
+// RECORDS: every pipeline has at most 64 ops and the workgroup has two
+// wavefronts; wavefront m writes the records of slack mode m (lane i: the
+// pipeline's op i).  A staged pipeline is staged and relaxed by wavefront 0
+// alone, one lane per edge, while wavefront 1 loads the records' static
+// inputs and hands them to wavefront 0 in LDS: the level bounds sit in
+// registers and the next level's edges (static) are read from LDS while the
+// current level's maxima are applied; LDS operations of one wavefront take
+// effect in order, so wavefront-scope fences separate staging and levels.
 template <bool RECORDS>
-__global__ __launch_bounds__(64) void relax_kernel(DevTables t) {
+__global__ __launch_bounds__(128) void relax_kernel(DevTables t) {
   extern __shared__ uint64_t sDyn[];
   const int cap_ops = t.relax_ops, cap_edges = t.relax_edges, cap_lvls = t.relax_lvls;
   // W[v] = ref[v] + acc[v]: acc is the largest successor term, built level by
@@ -227,6 +253,7 @@ __global__ __launch_bounds__(64) void relax_kernel(DevTables t) {
   int32_t* sEb = reinterpret_cast<int32_t*>(sEq + cap_edges);     // cap_lvls + 1
   const int p = blockIdx.x;
   const int tid = threadIdx.x, bs = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int n_ops = t.n_ops;
   const int4 d0 = t.pipe_desc[2 * p], d1 = t.pipe_desc[2 * p + 1];
   const int a = d0.x, n = d0.y, e0 = d0.z, ne = d0.w;
@@ -234,70 +261,117 @@ __global__ __launch_bounds__(64) void relax_kernel(DevTables t) {
   int64_t* WP = t.W;
   int64_t* WQ = t.W + n_ops;
   OpStatic st;
-  if (RECORDS && tid < n) st = load_op_static(t, a + tid);
   const bool staged = n <= cap_ops && ne <= cap_edges && nl <= cap_lvls;
   if (staged) {
-    // staging: RELAX_BATCH loads per lane in flight (clamped indices, so the
-    // loads are unconditional and issue together)
-    constexpr int RELAX_BATCH = 8;
-    for (int i0 = 0; i0 < n; i0 += RELAX_BATCH * bs) {
-      int r[RELAX_BATCH];
-#pragma unroll
-      for (int u = 0; u < RELAX_BATCH; ++u) {
-        const int i = i0 + u * bs + tid;
-        r[u] = t.ref[a + (i < n ? i : n - 1)];
+    OpStatic* sSt = reinterpret_cast<OpStatic*>(reinterpret_cast<char*>(sDyn) +
+                                                relax_lds_core_bytes(cap_ops, cap_edges, cap_lvls));
+    if (RECORDS && wave == 1) {
+      // wavefront 1 loads the static record inputs while wavefront 0 relaxes
+      if (lane < n) {
+        st = load_op_static(t, a + lane);
+        sSt[lane] = st;
       }
+    } else {
+      // wavefront 0 stages the pipeline: RELAX_BATCH loads per lane in
+      // flight (clamped indices, so the loads are unconditional and issue
+      // together)
+      constexpr int RELAX_BATCH = 8;
+      for (int i0 = 0; i0 < n; i0 += RELAX_BATCH * 64) {
+        int r[RELAX_BATCH];
 #pragma unroll
-      for (int u = 0; u < RELAX_BATCH; ++u) {
-        const int i = i0 + u * bs + tid;
-        if (i < n) {
-          sRef[i] = r[u];
-          sAccP[i] = 0;
-          sAccQ[i] = 0;
+        for (int u = 0; u < RELAX_BATCH; ++u) {
+          const int i = i0 + u * 64 + lane;
+          r[u] = t.ref[a + (i < n ? i : n - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < RELAX_BATCH; ++u) {
+          const int i = i0 + u * 64 + lane;
+          if (i < n) {
+            sRef[i] = r[u];
+            sAccP[i] = 0;
+            sAccQ[i] = 0;
+          }
+        }
+      }
+      for (int i0 = 0; i0 < ne; i0 += RELAX_BATCH * 64) {
+        uint32_t pk[RELAX_BATCH], q[RELAX_BATCH];
+#pragma unroll
+        for (int u = 0; u < RELAX_BATCH; ++u) {
+          const int i = i0 + u * 64 + lane;
+          const int g = e0 + (i < ne ? i : ne - 1);
+          pk[u] = t.lvl_edge[g];
+          q[u] = t.lvl_edge_q[g];
+        }
+#pragma unroll
+        for (int u = 0; u < RELAX_BATCH; ++u) {
+          const int i = i0 + u * 64 + lane;
+          if (i < ne) {
+            sE[i] = pk[u];
+            sEq[i] = q[u];
+          }
+        }
+      }
+      for (int i = lane; i <= nl; i += 64) sEb[i] = t.lvl_ebnd[l0 + i] - e0;
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      if (nl > 1) {
+        // lane l holds the first edge of level l and of level l + 1
+        const int eb0 = lane <= nl ? sEb[lane] : 0;
+        const int eb1 = lane + 1 <= nl ? sEb[lane + 1] : 0;
+        auto lvl_lo = [&](int l) { return l < 64 ? __builtin_amdgcn_readlane(eb0, l) : sEb[l]; };
+        auto lvl_hi = [&](int l) { return l < 64 ? __builtin_amdgcn_readlane(eb1, l) : sEb[l + 1]; };
+        // level 0 (the outputs) has no outgoing edges
+        int lo = lvl_lo(1), hi = lvl_hi(1);
+        bool act = lo + lane < hi;
+        uint32_t pk = 0, q = 0;
+        int32_t rd = 0;
+        if (act) {
+          pk = sE[lo + lane];
+          q = sEq[lo + lane];
+          rd = sRef[pk >> 16];
+        }
+        for (int l = 1; l < nl; ++l) {
+          const bool more = l + 1 < nl;
+          const int lo_n = more ? lvl_lo(l + 1) : 0, hi_n = more ? lvl_hi(l + 1) : 0;
+          const bool act_n = more && lo_n + lane < hi_n;
+          uint32_t pk_n = 0, q_n = 0;
+          int32_t rd_n = 0;
+          if (act_n) {
+            pk_n = sE[lo_n + lane];
+            q_n = sEq[lo_n + lane];
+            rd_n = sRef[pk_n >> 16];
+          }
+          if (act) relax_edge(sAccP, sAccQ, pk, q, rd);
+          for (int idx = lo + 64 + lane; idx < hi; idx += 64) {
+            const uint32_t pk2 = sE[idx];
+            relax_edge(sAccP, sAccQ, pk2, sEq[idx], sRef[pk2 >> 16]);
+          }
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+          pk = pk_n;
+          q = q_n;
+          rd = rd_n;
+          act = act_n;
+          lo = lo_n;
+          hi = hi_n;
         }
       }
     }
-    for (int i0 = 0; i0 < ne; i0 += RELAX_BATCH * bs) {
-      uint32_t pk[RELAX_BATCH], q[RELAX_BATCH];
-#pragma unroll
-      for (int u = 0; u < RELAX_BATCH; ++u) {
-        const int i = i0 + u * bs + tid;
-        const int g = e0 + (i < ne ? i : ne - 1);
-        pk[u] = t.lvl_edge[g];
-        q[u] = t.lvl_edge_q[g];
-      }
-#pragma unroll
-      for (int u = 0; u < RELAX_BATCH; ++u) {
-        const int i = i0 + u * bs + tid;
-        if (i < ne) {
-          sE[i] = pk[u];
-          sEq[i] = q[u];
-        }
-      }
-    }
-    for (int i = tid; i <= nl; i += bs) sEb[i] = t.lvl_ebnd[l0 + i] - e0;
     __syncthreads();
-    // level 0 (the outputs) has no outgoing edges
-    for (int l = 1; l < nl; ++l) {
-      for (int idx = sEb[l] + tid; idx < sEb[l + 1]; idx += bs) {
-        const uint32_t pk = sE[idx];
-        const int src = (int)(pk & 0xFFFFu), dst = (int)(pk >> 16);
-        const int64_t ref = sRef[dst];
-        const uint64_t wp = (uint64_t)(ref + (int64_t)sAccP[dst]);
-        const uint64_t wq = (uint64_t)branch_discount(sEq[idx], ref + (int64_t)sAccQ[dst]);
-        atomicMax((unsigned long long*)&sAccP[src], (unsigned long long)wp);
-        atomicMax((unsigned long long*)&sAccQ[src], (unsigned long long)wq);
+    if (RECORDS) {
+      if (lane < n) {
+        if (wave == 0) st = sSt[lane];
+        const int64_t W = sRef[lane] + (int64_t)(wave ? sAccQ[lane] : sAccP[lane]);
+        t.W[(int64_t)wave * n_ops + a + lane] = W;
+        write_op_records(t, a + lane, st, sRef[lane], W, wave);
       }
-      __syncthreads();
-    }
-    for (int i = tid; i < n; i += bs) {
-      const int64_t wp = sRef[i] + (int64_t)sAccP[i], wq = sRef[i] + (int64_t)sAccQ[i];
-      WP[a + i] = wp;
-      WQ[a + i] = wq;
-      if (RECORDS) write_op_records(t, a + i, st, sRef[i], wp, wq);
+    } else {
+      for (int i = tid; i < n; i += bs) {
+        WP[a + i] = sRef[i] + (int64_t)sAccP[i];
+        WQ[a + i] = sRef[i] + (int64_t)sAccQ[i];
+      }
     }
     return;
   }
+  if (RECORDS && lane < n) st = load_op_static(t, a + lane);
   for (int l = l0; l < l0 + nl; ++l) {
     const int end = t.lvl_bnd[l + 1];
     for (int idx = t.lvl_bnd[l] + tid; idx < end; idx += bs) {
@@ -315,7 +389,8 @@ __global__ __launch_bounds__(64) void relax_kernel(DevTables t) {
     }
     __syncthreads();
   }
-  if (RECORDS && tid < n) write_op_records(t, a + tid, st, t.ref[a + tid], WP[a + tid], WQ[a + tid]);
+  if (RECORDS && lane < n)
+    write_op_records(t, a + lane, st, t.ref[a + lane], t.W[(int64_t)wave * n_ops + a + lane], wave);
 }
 
 // One thread per op: its records (both slack modes) from the relaxed W.
@@ -323,7 +398,9 @@ __global__ __launch_bounds__(256) void op_records_kernel(DevTables t) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= t.n_ops) return;
   const OpStatic st = load_op_static(t, v);
-  write_op_records(t, v, st, t.ref[v], t.W[v], t.W[(int64_t)t.n_ops + v]);
+  const int32_t ref = t.ref[v];
+  write_op_records(t, v, st, ref, t.W[v], 0);
+  write_op_records(t, v, st, ref, t.W[(int64_t)t.n_ops + v], 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -1694,10 +1771,10 @@ hipError_t launch_relax(const DevTables& t, hipStream_t s) {
   if (t.n_pipelines <= 0) return hipSuccess;
   if (t.max_pipe_ops <= 64) {
     // one op per lane: records in the same launch
-    hipLaunchKernelGGL(relax_kernel<true>, dim3(t.n_pipelines), dim3(64), relax_lds_bytes(t), s, t);
+    hipLaunchKernelGGL(relax_kernel<true>, dim3(t.n_pipelines), dim3(128), relax_lds_bytes(t, true), s, t);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(relax_kernel<false>, dim3(t.n_pipelines), dim3(64), relax_lds_bytes(t), s, t);
+  hipLaunchKernelGGL(relax_kernel<false>, dim3(t.n_pipelines), dim3(64), relax_lds_bytes(t, false), s, t);
   if (t.n_ops > 0) hipLaunchKernelGGL(op_records_kernel, dim3(blocks_for(t.n_ops, 256)), dim3(256), 0, s, t);
   return hipGetLastError();
 }
