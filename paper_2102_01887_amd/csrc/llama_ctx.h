@@ -65,11 +65,11 @@ struct llama_ctx {
   std::vector<int32_t> cfg_off, hw, batch, res, lat, ref_k, ref, fastest;
   std::vector<int64_t> cost;
   std::vector<uint32_t> key;  // caller order
-  DevBuf d_ref, d_W, d_hdr, d_front_L, d_rec_q, d_rec_tail_q, d_ovf_q, d_seg_off, d_tab;
+  DevBuf d_ref, d_W, d_hdr, d_front_L, d_rec_q, d_rec_tail_q, d_rec_tail2_q, d_ovf_q, d_seg_off, d_tab;
   // Decision records, double-buffered: each relaxation writes the set the
   // previous one did not, and decisions read the set of the latest one, so a
   // relaxation can overlap the decisions of the batch before it.
-  DevBuf d_rec[2], d_rec_tail[2], d_ovf[2];
+  DevBuf d_rec[2], d_rec_tail[2], d_rec_tail2[2], d_ovf[2];
   int rec_cur = 0;  // set written by the latest relaxation
   DevBuf d_mst, d_mst_n;
   DevBuf d_cfg_off, d_cfg_hw, d_cfg_lat, d_cfg_key, d_cfg_q, d_cfg_batch;
@@ -124,7 +124,9 @@ struct llama_ctx {
     t.mst_n = d_mst_n.as<int32_t>();
     t.rec = d_rec[rec_cur].as<uint4>();
     t.rec_tail = d_rec_tail[rec_cur].as<uint4>();
+    t.rec_tail2 = d_rec_tail2[rec_cur].as<uint4>();
     t.rec_tail_q = d_rec_tail_q.as<uint4>();
+    t.rec_tail2_q = d_rec_tail2_q.as<uint4>();
     t.ovf = d_ovf[rec_cur].as<uint2>();
     t.rec_q = d_rec_q.as<uint4>();
     t.ovf_q = d_ovf_q.as<uint2>();
@@ -154,6 +156,7 @@ struct llama_ctx {
     DevTables t = tables();
     t.rec = d_rec[set].as<uint4>();
     t.rec_tail = d_rec_tail[set].as<uint4>();
+    t.rec_tail2 = d_rec_tail2[set].as<uint4>();
     t.ovf = d_ovf[set].as<uint2>();
     return t;
   }
@@ -161,7 +164,7 @@ struct llama_ctx {
   int64_t device_bytes() const {
     const DevBuf* all[] = {&d_pipe_off, &d_pipe_desc, &d_lvl_edge, &d_lvl_edge_q, &d_lvl_ebnd, &d_lvl_bnd, &d_lvl_ops, &d_succ_off,
                            &d_succ_ids, &d_succ_q, &d_ref, &d_W, &d_hdr, &d_front_L,
-                           &d_rec[0], &d_rec_tail[0], &d_ovf[0], &d_rec[1], &d_rec_tail[1], &d_ovf[1], &d_rec_q, &d_rec_tail_q, &d_ovf_q, &d_seg_off, &d_tab, &d_err,
+                           &d_rec[0], &d_rec_tail[0], &d_rec_tail2[0], &d_ovf[0], &d_rec[1], &d_rec_tail[1], &d_rec_tail2[1], &d_ovf[1], &d_rec_q, &d_rec_tail_q, &d_rec_tail2_q, &d_ovf_q, &d_seg_off, &d_tab, &d_err,
                            &d_cnt, &d_start, &d_cursor, &d_perm, &d_hist, &d_mst,
                            &d_mst_n, &d_cfg_off, &d_cfg_hw, &d_cfg_lat, &d_cfg_key, &d_cfg_q, &d_cfg_batch, &d_a_lat, &d_a_pf, &d_a_si, &d_m_lat, &d_m_pf, &d_m_si, &d_a_val, &d_aff_scratch, &d_qacc, &d_fb_ksrc, &d_fb_tab_src, &d_fb_ref_k, &d_fb_count, &d_fb_sum, &d_fb_dirty};
     int64_t s = 0;

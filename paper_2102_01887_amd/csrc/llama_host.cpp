@@ -519,7 +519,7 @@ int build_tables(llama_ctx* c) {
   std::vector<int32_t> mst_n(n_ops, 0);
   for (int v = 0; v < n_ops; ++v) mst_n[v] = (int32_t)merged[v].size();
   std::vector<uint2> mst(c->n_cfg);
-  std::vector<uint4> rec_hot((size_t)2 * n_ops), rec_tail((size_t)2 * n_ops * 3);
+  std::vector<uint4> rec_hot((size_t)2 * n_ops), rec_tail((size_t)2 * n_ops * 3), rec_tail2((size_t)2 * n_ops * 4);
   for (int v = 0; v < n_ops; ++v) {
     const int n = (int)merged[v].size();
     for (int j = 0; j < n; ++j) {
@@ -535,7 +535,7 @@ int build_tables(llama_ctx* c) {
     }
     for (int mode = 0; mode < 2; ++mode)
       for (int k = 0; k < llama::REC_WORDS; ++k)
-        *llama::rec_word(rec_hot.data(), rec_tail.data(), (int64_t)mode * n_ops + v, k) = w[k];
+        *llama::rec_word(rec_hot.data(), rec_tail.data(), rec_tail2.data(), (int64_t)mode * n_ops + v, k) = w[k];
   }
   merged.clear();
 
@@ -567,14 +567,17 @@ int build_tables(llama_ctx* c) {
       (rc = upload_vec(c, c->d_front_L, front_L, "front_L")) ||
       (rc = upload_vec(c, c->d_rec[0], rec_hot, "records")) ||
       (rc = upload_vec(c, c->d_rec_tail[0], rec_tail, "record tails")) ||
+      (rc = upload_vec(c, c->d_rec_tail2[0], rec_tail2, "record second tails")) ||
       (rc = upload_vec(c, c->d_rec[1], rec_hot, "records")) ||
       (rc = upload_vec(c, c->d_rec_tail[1], rec_tail, "record tails")) ||
+      (rc = upload_vec(c, c->d_rec_tail2[1], rec_tail2, "record second tails")) ||
       (rc = upload_vec(c, c->d_mst, mst, "merged frontier")) ||
       (rc = upload_vec(c, c->d_mst_n, mst_n, "merged frontier sizes")) ||
       (rc = upload(c, c->d_ovf[0], nullptr, sizeof(uint2) * 2 * (size_t)pos, "record overflow")) ||
       (rc = upload(c, c->d_ovf[1], nullptr, sizeof(uint2) * 2 * (size_t)pos, "record overflow")) ||
       (rc = upload(c, c->d_rec_q, nullptr, sizeof(uint4) * (size_t)n_ops, "records (queue)")) ||
       (rc = upload(c, c->d_rec_tail_q, nullptr, sizeof(uint4) * 3 * (size_t)n_ops, "record tails (queue)")) ||
+      (rc = upload(c, c->d_rec_tail2_q, nullptr, sizeof(uint4) * 4 * (size_t)n_ops, "record second tails (queue)")) ||
       (rc = upload(c, c->d_ovf_q, nullptr, sizeof(uint2) * (size_t)pos, "record overflow (queue)")) ||
       (rc = upload_vec(c, c->d_seg_off, seg_off, "seg_off")) ||
       (rc = upload_vec(c, c->d_cfg_off, c->cfg_off, "cfg_off")) ||

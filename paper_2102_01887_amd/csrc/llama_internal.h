@@ -12,7 +12,7 @@ constexpr uint32_t THR_NEVER = 0xFFFFFFFFu;  // remaining-time threshold never m
 constexpr int MAX_HW = 8;
 constexpr uint32_t DEVERR_QUEUE_ENTRY = 2u;  // device error bit: queued entry out of range
 
-// Per-op decision record (64 bytes).  The op's frontier over all backends in
+// Per-op decision record (128 bytes).  The op's frontier over all backends in
 // remaining-time space: entries {T, k} such that configuration k (local index)
 // is feasible for an invocation iff slo - elapsed >= T, with T strictly
 // increasing and the configuration's cost key strictly decreasing along the
@@ -24,21 +24,31 @@ constexpr uint32_t DEVERR_QUEUE_ENTRY = 2u;  // device error bit: queued entry o
 //   word 3        k of slots 0 and 1 (16-bit halves)
 //   words 4..11   U of slots 2..9
 //   words 12..15  k of slots (2j, 2j+1), j = 1..4
+//   words 16..25  U of slots 10..19
+//   words 26..30  k of slots (2j, 2j+1), j = 5..9; word 31 unused
 // The first 16 bytes alone decide every invocation that can afford one of
-// the two cheapest entries, so records are stored as two arrays: the hot
-// words 0..3 (one uint4 per op) and the tail words 4..15 (three uint4 per op).
-// The entries past the record (the n - REC_SLOTS smallest T), ascending in T,
-// are in the overflow array at [hdr offset of the op, + n - REC_SLOTS); the
-// decision reads them only when no slot is feasible.
-constexpr int REC_WORDS = 16;
-constexpr int REC_SLOTS = 10;
-__host__ __device__ inline constexpr int rec_u_word(int slot) { return slot < 2 ? 1 + slot : slot + 2; }
-__host__ __device__ inline constexpr int rec_k_word(int slot) { return slot < 2 ? 3 : 12 + (slot - 2) / 2; }
+// the two cheapest entries, so records are stored as three arrays: the hot
+// words 0..3 (one uint4 per op), the tail words 4..15 (three uint4 per op)
+// and the second tail, words 16..31 (four uint4 per op), written and read
+// only for ops with more than 10 entries.  The entries past the record (the
+// n - REC_SLOTS smallest T), ascending in T, are in the overflow array at
+// [hdr offset of the op, + n - REC_SLOTS); the decision reads them only when
+// no slot is feasible.
+constexpr int REC_WORDS = 32;
+constexpr int REC_SLOTS = 20;
+constexpr int REC_SLOTS_TAIL = 10;  // slots in the hot words and the first tail
+__host__ __device__ inline constexpr int rec_u_word(int slot) {
+  return slot < 2 ? 1 + slot : slot < REC_SLOTS_TAIL ? slot + 2 : slot + 6;
+}
+__host__ __device__ inline constexpr int rec_k_word(int slot) {
+  return slot < 2 ? 3 : slot < REC_SLOTS_TAIL ? 12 + (slot - 2) / 2 : 26 + (slot - REC_SLOTS_TAIL) / 2;
+}
 __host__ __device__ inline constexpr int rec_k_shift(int slot) { return 16 * (slot & 1); }
-// Address of word w of record r (r = mode * n_ops + op) in the two arrays.
-__host__ __device__ inline uint32_t* rec_word(uint4* hot, uint4* tail, int64_t r, int w) {
+// Address of word w of record r (r = mode * n_ops + op) in the three arrays.
+__host__ __device__ inline uint32_t* rec_word(uint4* hot, uint4* tail, uint4* tail2, int64_t r, int w) {
   return w < 4 ? reinterpret_cast<uint32_t*>(hot + r) + w
-               : reinterpret_cast<uint32_t*>(tail + r * 3) + (w - 4);
+         : w < 16 ? reinterpret_cast<uint32_t*>(tail + r * 3) + (w - 4)
+                  : reinterpret_cast<uint32_t*>(tail2 + r * 4) + (w - 16);
 }
 
 // Schedules of the indexed decision (chosen by llama_autotune): 1, 2 or 4
@@ -91,9 +101,11 @@ struct DevTables {
   const int32_t* mst_n;      // [n_ops] entries of each op's merged frontier
   uint4* rec;                // [2*n_ops] record words 0..3, PAPER then PROB, queue = 0
   uint4* rec_tail;           // [2*n_ops*3] record words 4..15
+  uint4* rec_tail2;          // [2*n_ops*4] record words 16..31
   uint2* ovf;                // [2*n_front] full frontiers {T, key} ascending, PAPER then PROB
   uint4* rec_q;              // [n_ops] records for a per-call queueing-time vector
   uint4* rec_tail_q;         // [n_ops*3]
+  uint4* rec_tail2_q;        // [n_ops*4]
   uint2* ovf_q;              // [n_front]
   const int32_t* cfg_off;    // [n_ops+1] caller-order configuration rows of each op
   const int32_t* cfg_hw;     // [n_cfg] backend, caller order
@@ -132,10 +144,11 @@ struct Batch {
 };
 
 hipError_t launch_relax(const DevTables& t, hipStream_t s);
-// Build records for modes [mode0, mode0 + n_modes) into rec/rec_tail/ovf
-// (consecutive per-mode blocks of n_ops, 3*n_ops uint4 and n_front uint2).
+// Build records for modes [mode0, mode0 + n_modes) into rec/rec_tail/
+// rec_tail2/ovf (consecutive per-mode blocks of n_ops, 3*n_ops, 4*n_ops uint4
+// and n_front uint2).
 hipError_t launch_records(const DevTables& t, int mode0, int n_modes, const int64_t* queue, uint4* rec,
-                          uint4* rec_tail, uint2* ovf, hipStream_t s);
+                          uint4* rec_tail, uint4* rec_tail2, uint2* ovf, hipStream_t s);
 hipError_t launch_targets(const DevTables& t, const Batch& b, hipStream_t s);
 hipError_t launch_select_indexed(const DevTables& t, const Batch& b, hipStream_t s);
 hipError_t launch_decide_indexed(const DevTables& t, const Batch& b, hipStream_t s);

@@ -127,7 +127,7 @@ __device__ __forceinline__ uint32_t entry_threshold(const OpScale& o, uint32_t L
 // offset, fastest configuration, the REC_SLOTS entries of largest latency and
 // the first OVF_PREFETCH entries past them (static between latency updates,
 // so they can be loaded ahead of W).
-constexpr int OVF_PREFETCH = 16;
+constexpr int OVF_PREFETCH = 8;
 struct OpStatic {
   int first, n, base;
   uint32_t fastest;
@@ -191,6 +191,13 @@ __device__ __forceinline__ void write_op_records(const DevTables& t, int v, cons
   tl[0] = make_uint4(w[4], w[5], w[6], w[7]);
   tl[1] = make_uint4(w[8], w[9], w[10], w[11]);
   tl[2] = make_uint4(w[12], w[13], w[14], w[15]);
+  if (n > REC_SLOTS_TAIL) {
+    uint4* t2 = t.rec_tail2 + r * 4;
+    t2[0] = make_uint4(w[16], w[17], w[18], w[19]);
+    t2[1] = make_uint4(w[20], w[21], w[22], w[23]);
+    t2[2] = make_uint4(w[24], w[25], w[26], w[27]);
+    t2[3] = make_uint4(w[28], w[29], w[30], w[31]);
+  }
   // entries past the record, ascending: the prefetched ones, then four
   // loads in flight at a time
   uint2* ovf = t.ovf + (int64_t)mode * t.n_front + st.base;
@@ -441,7 +448,8 @@ __device__ __forceinline__ int wave_inclusive_scan(int x) {
 
 template <int NHW>
 __device__ __forceinline__ void build_record(const DevTables& t, int v, int mode, const int64_t* queue,
-                                             uint4* rec_hot, uint4* rec_tail, int64_t rec_index, uint2* ovf, int64_t* sT, uint32_t* sK,
+                                             uint4* rec_hot, uint4* rec_tail, uint4* rec_tail2, int64_t rec_index, uint2* ovf,
+                                             int64_t* sT, uint32_t* sK,
                                              int32_t* sC, uint32_t* sSlotT, uint32_t* sSlotK,
                                              int32_t* sN) {
   const int lane = threadIdx.x;
@@ -588,7 +596,7 @@ __device__ __forceinline__ void build_record(const DevTables& t, int v, int mode
       if (lane == rec_u_word(slot)) word = slot < n ? sSlotT[slot] : 0x7FFFFFFFu;
       if (lane == rec_k_word(slot) && slot < n) word |= sSlotK[slot] << rec_k_shift(slot);
     }
-    *rec_word(rec_hot, rec_tail, rec_index, lane) = word;
+    *rec_word(rec_hot, rec_tail, rec_tail2, rec_index, lane) = word;
   }
   __syncthreads();  // the LDS stage is reused by the next record
 }
@@ -597,7 +605,7 @@ __device__ __forceinline__ void build_record(const DevTables& t, int v, int mode
 // modes in turn (the frontier entries stay hot in cache between modes).
 template <int NHW>
 __global__ __launch_bounds__(64) void records_kernel(DevTables t, int mode0, int n_modes, const int64_t* queue,
-                                                     uint4* rec_all, uint4* tail_all, uint2* ovf_all) {
+                                                     uint4* rec_all, uint4* tail_all, uint4* tail2_all, uint2* ovf_all) {
   __shared__ int64_t sT[REC_LDS];
   __shared__ uint32_t sK[REC_LDS];
   __shared__ int32_t sC[REC_LDS];
@@ -605,7 +613,7 @@ __global__ __launch_bounds__(64) void records_kernel(DevTables t, int mode0, int
   __shared__ int32_t sN;
   const int v = blockIdx.x;
   for (int m = 0; m < n_modes; ++m)
-    build_record<NHW>(t, v, mode0 + m, queue, rec_all, tail_all, (int64_t)m * t.n_ops + v,
+    build_record<NHW>(t, v, mode0 + m, queue, rec_all, tail_all, tail2_all, (int64_t)m * t.n_ops + v,
                       ovf_all + (int64_t)m * t.n_front, sT, sK, sC, sSlotT, sSlotK, &sN);
 }
 
@@ -702,16 +710,30 @@ __global__ __launch_bounds__(256) void select_indexed_kernel(DevTables t, Batch 
 // cheapest feasible frontier entry), -1 if none; *n_out = frontier length.
 __device__ __forceinline__ int record_choice(const uint4& a, const uint4& bq, const uint4& c, const uint4& d,
                                              int32_t r0, int* n_out) {
-  const uint32_t U[REC_SLOTS] = {a.y, a.z, bq.x, bq.y, bq.z, bq.w, c.x, c.y, c.z, c.w};
-  const uint32_t K2[REC_SLOTS / 2] = {a.w, d.x, d.y, d.z, d.w};
+  const uint32_t U[REC_SLOTS_TAIL] = {a.y, a.z, bq.x, bq.y, bq.z, bq.w, c.x, c.y, c.z, c.w};
+  const uint32_t K2[REC_SLOTS_TAIL / 2] = {a.w, d.x, d.y, d.z, d.w};
   const int n = (int)(a.x & 0xFFFFu);
   int sel = -1;
 #pragma unroll
-  for (int slot = REC_SLOTS - 1; slot >= 0; --slot) {
+  for (int slot = REC_SLOTS_TAIL - 1; slot >= 0; --slot) {
     const int k = (int)((K2[slot >> 1] >> (16 * (slot & 1))) & 0xFFFFu);
     if (slot < n && (int32_t)U[slot] < r0) sel = k;
   }
   *n_out = n;
+  return sel;
+}
+
+// The same over the second tail (slots 10..19; n = frontier length).
+__device__ __forceinline__ int record_choice2(const uint4& a, const uint4& bq, const uint4& c, const uint4& d, int n,
+                                              int32_t r0) {
+  const uint32_t U[REC_SLOTS - REC_SLOTS_TAIL] = {a.x, a.y, a.z, a.w, bq.x, bq.y, bq.z, bq.w, c.x, c.y};
+  const uint32_t K2[(REC_SLOTS - REC_SLOTS_TAIL) / 2] = {c.z, c.w, d.x, d.y, d.z};
+  int sel = -1;
+#pragma unroll
+  for (int s = REC_SLOTS - REC_SLOTS_TAIL - 1; s >= 0; --s) {
+    const int k = (int)((K2[s >> 1] >> (16 * (s & 1))) & 0xFFFFu);
+    if (REC_SLOTS_TAIL + s < n && (int32_t)U[s] < r0) sel = k;
+  }
   return sel;
 }
 
@@ -733,9 +755,11 @@ __device__ __forceinline__ int finish_choice(const DevTables& t, const uint2* ov
 }
 
 // Decision from the hot record words h; the tail is read only when neither
-// of the two cheapest entries is affordable and the frontier is longer.
-__device__ __forceinline__ int decide_from_record(const DevTables& t, const uint4* tail, const uint2* ovf, int v,
-                                                  const uint4& h, int32_t r0, uint8_t* feasible) {
+// of the two cheapest entries is affordable and the frontier is longer, the
+// second tail only when no slot of the first is.
+__device__ __forceinline__ int decide_from_record(const DevTables& t, const uint4* tail, const uint4* tail2,
+                                                  const uint2* ovf, int v, const uint4& h, int32_t r0,
+                                                  uint8_t* feasible) {
   const int n = (int)(h.x & 0xFFFFu);
   int sel = -1;
   if (n > 1 && (int32_t)h.z < r0) sel = (int)(h.w >> 16);
@@ -744,7 +768,11 @@ __device__ __forceinline__ int decide_from_record(const DevTables& t, const uint
     const uint4* r = tail + (int64_t)v * 3;
     int nn;
     sel = record_choice(h, r[0], r[1], r[2], r0, &nn);
-    sel = finish_choice(t, ovf, v, sel, n, r0);
+    if (sel < 0 && n > REC_SLOTS_TAIL) {
+      const uint4* r2 = tail2 + (int64_t)v * 4;
+      sel = record_choice2(r2[0], r2[1], r2[2], r2[3], n, r0);
+      sel = finish_choice(t, ovf, v, sel, n, r0);
+    }
   }
   *feasible = sel >= 0 ? 1 : 0;
   return sel >= 0 ? sel : (int)(h.x >> 16);
@@ -776,7 +804,8 @@ __device__ __forceinline__ void load_invocation(const Batch& b, int64_t i, int* 
 // size, so every load instruction stays coalesced, and issues all loads first.
 template <int DECIDE_IPT, bool NT>
 __global__ __launch_bounds__(256) void decide_indexed_kernel(DevTables t, Batch b, const uint4* rec,
-                                                             const uint4* tail, const uint2* ovf) {
+                                                             const uint4* tail, const uint4* tail2,
+                                                             const uint2* ovf) {
   const int64_t base = (int64_t)blockIdx.x * blockDim.x * DECIDE_IPT + threadIdx.x;
   int v[DECIDE_IPT], e[DECIDE_IPT], s[DECIDE_IPT];
 #pragma unroll
@@ -799,7 +828,7 @@ __global__ __launch_bounds__(256) void decide_indexed_kernel(DevTables t, Batch 
     }
     const int32_t r0 = s[u] - e[u];  // both non-negative: no overflow
     uint8_t f;
-    const int c = decide_from_record(t, tail, ovf, v[u], h[u], r0, &f);
+    const int c = decide_from_record(t, tail, tail2, ovf, v[u], h[u], r0, &f);
     store_decision(b, i, c, f);
   }
 }
@@ -809,7 +838,7 @@ __global__ __launch_bounds__(256) void decide_indexed_kernel(DevTables t, Batch 
 // configurations) in LDS; an invocation that can afford one of those two is
 // decided from LDS, any other reads its full record from global memory.
 __global__ __launch_bounds__(1024) void decide_lds_kernel(DevTables t, Batch b, const uint4* rec,
-                                                         const uint4* tail, const uint2* ovf) {
+                                                         const uint4* tail, const uint4* tail2, const uint2* ovf) {
   extern __shared__ uint4 sRec[];
   for (int v = threadIdx.x; v < t.n_ops; v += blockDim.x) sRec[v] = rec[v];
   __syncthreads();
@@ -829,7 +858,70 @@ __global__ __launch_bounds__(1024) void decide_lds_kernel(DevTables t, Batch b, 
         continue;
       }
       uint8_t f;
-      const int c = decide_from_record(t, tail, ovf, v[u], sRec[v[u]], s[u] - e[u], &f);
+      const int c = decide_from_record(t, tail, tail2, ovf, v[u], sRec[v[u]], s[u] - e[u], &f);
+      store_decision(b, i, c, f);
+    }
+  }
+}
+
+// The persistent variant for 16-byte aligned invocation arrays: each thread
+// decides four consecutive invocations, read with one 16-byte load per array
+// and written with one 16-byte store of configurations and one 4-byte store
+// of flags, which cuts the memory instructions of the invocation stream to a
+// quarter.  The last n mod 4 invocations are decided by block 0.
+__global__ __launch_bounds__(1024) void decide_lds4_kernel(DevTables t, Batch b, const uint4* rec,
+                                                          const uint4* tail, const uint4* tail2, const uint2* ovf) {
+  extern __shared__ uint4 sRec[];
+  const int64_t n4 = b.n >> 2;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int4* op4 = reinterpret_cast<const int4*>(b.op);
+  const int4* el4 = reinterpret_cast<const int4*>(b.elapsed);
+  const int4* slo4 = reinterpret_cast<const int4*>(b.slo);
+  int4 v4 = make_int4(0, 0, 0, 0), e4 = v4, s4 = v4;
+  if (q < n4) {  // the first invocations are loaded before the staging
+    v4 = op4[q];
+    e4 = el4[q];
+    s4 = slo4[q];
+  }
+  for (int k = threadIdx.x; k < t.n_ops; k += blockDim.x) sRec[k] = rec[k];
+  __syncthreads();
+  for (; q < n4; q += stride) {
+    const int v[4] = {v4.x, v4.y, v4.z, v4.w}, e[4] = {e4.x, e4.y, e4.z, e4.w};
+    const int sl[4] = {s4.x, s4.y, s4.z, s4.w};
+    int c[4];
+    uint32_t flags = 0;
+    bool bad = false;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (invalid_invocation(v[u], e[u], sl[u], t.n_ops)) {
+        c[u] = -1;
+        bad = true;
+        continue;
+      }
+      uint8_t f;
+      c[u] = decide_from_record(t, tail, tail2, ovf, v[u], sRec[v[u]], sl[u] - e[u], &f);
+      flags |= (uint32_t)f << (8 * u);
+    }
+    reinterpret_cast<int4*>(b.cfg)[q] = make_int4(c[0], c[1], c[2], c[3]);
+    if (b.flag) reinterpret_cast<uint32_t*>(b.flag)[q] = flags;
+    if (bad) atomicOr(t.err, 1u);
+    const int64_t nq = q + stride;
+    if (nq < n4) {
+      v4 = op4[nq];
+      e4 = el4[nq];
+      s4 = slo4[nq];
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x < (b.n & 3)) {
+    const int64_t i = (n4 << 2) + threadIdx.x;
+    const int v = b.op[i], e = b.elapsed[i], sl = b.slo[i];
+    if (invalid_invocation(v, e, sl, t.n_ops)) {
+      store_decision(b, i, -1, 0);
+      atomicOr(t.err, 1u);
+    } else {
+      uint8_t f;
+      const int c = decide_from_record(t, tail, tail2, ovf, v, sRec[v], sl - e, &f);
       store_decision(b, i, c, f);
     }
   }
@@ -1761,9 +1853,10 @@ __global__ __launch_bounds__(256) void decide_batching_kernel(DevTables t, Batch
 }  // namespace
 
 hipError_t launch_records(const DevTables& t, int mode0, int n_modes, const int64_t* queue, uint4* rec,
-                          uint4* rec_tail, uint2* ovf, hipStream_t s) {
+                          uint4* rec_tail, uint4* rec_tail2, uint2* ovf, hipStream_t s) {
   if (t.n_ops <= 0) return hipSuccess;
-  LLAMA_DISPATCH_NHW(records_kernel, dim3(t.n_ops), dim3(64), s, t, mode0, n_modes, queue, rec, rec_tail, ovf);
+  LLAMA_DISPATCH_NHW(records_kernel, dim3(t.n_ops), dim3(64), s, t, mode0, n_modes, queue, rec, rec_tail, rec_tail2,
+                     ovf);
   return hipGetLastError();
 }
 
@@ -1861,31 +1954,40 @@ hipError_t launch_decide_indexed(const DevTables& t, const Batch& b, hipStream_t
   if (b.n == 0) return hipSuccess;
   const uint4* rec = t.rec + (int64_t)b.mode * t.n_ops;
   const uint4* tail = t.rec_tail + (int64_t)b.mode * t.n_ops * 3;
+  const uint4* tail2 = t.rec_tail2 + (int64_t)b.mode * t.n_ops * 4;
   const uint2* ovf = t.ovf + (int64_t)b.mode * t.n_front;
   if (b.queue) {
     // records for this call's queueing times, in the context's own buffers
-    hipError_t e = launch_records(t, b.mode, 1, b.queue, t.rec_q, t.rec_tail_q, t.ovf_q, s);
+    hipError_t e = launch_records(t, b.mode, 1, b.queue, t.rec_q, t.rec_tail_q, t.rec_tail2_q, t.ovf_q, s);
     if (e != hipSuccess) return e;
     rec = t.rec_q;
     tail = t.rec_tail_q;
+    tail2 = t.rec_tail2_q;
     ovf = t.ovf_q;
   }
   switch (t.decide_sched) {
     case SCHED_LDS: {
       if (t.n_ops > LDS_REC_MAX_OPS) return hipErrorInvalidValue;
       const size_t lds = sizeof(uint4) * (size_t)t.n_ops;
-      hipError_t e = hipFuncSetAttribute((const void*)decide_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+      const bool vec = ((reinterpret_cast<uintptr_t>(b.op) | reinterpret_cast<uintptr_t>(b.elapsed) |
+                         reinterpret_cast<uintptr_t>(b.slo) | reinterpret_cast<uintptr_t>(b.cfg)) & 15u) == 0 &&
+                       (reinterpret_cast<uintptr_t>(b.flag) & 3u) == 0;
+      const void* fn = vec ? (const void*)decide_lds4_kernel : (const void*)decide_lds_kernel;
+      hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)(sizeof(uint4) * LDS_REC_MAX_OPS));
       if (e != hipSuccess) return e;
       const int64_t per_block = 1024 * 4;
       int64_t blocks = (b.n + per_block - 1) / per_block;
       if (blocks > t.n_cu) blocks = t.n_cu;
-      hipLaunchKernelGGL(decide_lds_kernel, dim3((unsigned)blocks), dim3(1024), lds, s, t, b, rec, tail, ovf);
+      if (vec)
+        hipLaunchKernelGGL(decide_lds4_kernel, dim3((unsigned)blocks), dim3(1024), lds, s, t, b, rec, tail, tail2, ovf);
+      else
+        hipLaunchKernelGGL(decide_lds_kernel, dim3((unsigned)blocks), dim3(1024), lds, s, t, b, rec, tail, tail2, ovf);
       break;
     }
 #define LLAMA_DIRECT(IPT, NT) \
   hipLaunchKernelGGL((decide_indexed_kernel<IPT, NT>), dim3(blocks_for(b.n, 256 * IPT)), dim3(256), 0, s, t, b, rec, \
-                     tail, ovf)
+                     tail, tail2, ovf)
     case SCHED_DIRECT2: LLAMA_DIRECT(2, false); break;
     case SCHED_DIRECT4: LLAMA_DIRECT(4, false); break;
     case SCHED_DIRECT1_NT: LLAMA_DIRECT(1, true); break;

@@ -275,7 +275,7 @@ int llama_affinity(llama_ctx* c, int64_t n, const int32_t* op, const int32_t* el
     const size_t need = (((size_t)n * (8 * (size_t)c->n_hw + 8 + 4) + 255) & ~(size_t)255) + tmp;
     if (need > c->d_aff_scratch.bytes) {
       hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-      if (s) hipStreamIsCapturing(s, &cs);
+      if (s && hipStreamIsCapturing(s, &cs) != hipSuccess) return llama::fail(c, LLAMA_E_DEVICE, "affinity: capture status");
       if (cs != hipStreamCaptureStatusNone)
         return llama::fail(c, LLAMA_E_STATE, "affinity: scratch must grow; call once before capturing");
       if (s && hipStreamSynchronize(s) != hipSuccess) return llama::fail(c, LLAMA_E_DEVICE, "affinity: sync");
