@@ -75,15 +75,19 @@ __device__ __forceinline__ int64_t branch_discount(uint32_t q, int64_t w) {
 //   * Otherwise y < 2^31 and x = fl(fl(L + 1) * fl(fl(W) / ref)) carries three
 //     roundings of relative size 2^-53, so |x - y| < 2^31 * 3 * 2^-53 < 2^-20.
 //     When x is at least 2^-19 away from every integer, y is not an integer
-//     and floor(y) = floor(x), so U = T - 1 = floor(x).
+//     and floor(y) = floor(x), so U = T - 1 = floor(x).  When W / ref is an
+//     integer k (every output op has W = ref), x = y = (L + 1) * k exactly
+//     and U = x - 1.
 //   * Near an integer, the exact path: the numerator (L + 1) * W + ref - 1 is
 //     below 2^62 and the quotient below 2^31, so an FP64 estimate is off by
 //     at most one and one exact remainder step corrects it.
 struct OpScale {
   uint32_t cut32;   // min(cutoff, 2^32 - 1); L + 1 <= 2^31 always
+  bool int_scale;   // W / ref is an integer k: then x = (L + 1) * k exactly
   int64_t W;
   int64_t ref;
   double scale;     // fl(fl(W) / ref)
+  double inv_ref;   // fl(1 / ref), for the exact path's quotient estimate
 };
 
 __device__ __forceinline__ OpScale op_scale(int64_t W, int32_t ref) {
@@ -96,25 +100,38 @@ __device__ __forceinline__ OpScale op_scale(int64_t W, int32_t ref) {
   o.W = W;
   o.ref = ref;
   o.scale = (double)W / (double)ref;
+  o.inv_ref = 1.0 / (double)ref;
+  // W < 2^53, so an integer W / ref = k is represented exactly by scale;
+  // a scale that only rounds to an integer fails k * ref == W
+  const double k = floor(o.scale);
+  o.int_scale = k == o.scale && (int64_t)k * (int64_t)ref == W;
   return o;
 }
 
-__device__ __forceinline__ uint32_t entry_threshold_exact(int64_t W, int64_t ref, uint32_t l1) {
-  const int64_t num = (int64_t)((uint64_t)l1 * (uint64_t)W) + ref - 1;
-  int64_t q = (int64_t)(uint32_t)((double)num / (double)ref);  // estimate below 2^31 + 1
-  const int64_t r = num - q * ref;
-  q += r < 0 ? -1 : (r >= ref ? 1 : 0);
+// The quotient estimate fl(fl(num) * fl(1 / ref)) carries three roundings of
+// relative size 2^-53, so for quotients below 2^31 + 1 it is off by less than
+// 2^-20 and its truncation by at most one; one remainder step corrects it.
+__device__ __forceinline__ uint32_t entry_threshold_exact(const OpScale& o, uint32_t l1) {
+  const int64_t num = (int64_t)((uint64_t)l1 * (uint64_t)o.W) + o.ref - 1;
+  int64_t q = (int64_t)(uint32_t)((double)num * o.inv_ref);  // estimate below 2^31 + 1
+  const int64_t r = num - q * o.ref;
+  q += r < 0 ? -1 : (r >= o.ref ? 1 : 0);
   return (uint32_t)q - 1u;  // q = T >= 1
 }
 
+// Below the cutoff y = (L + 1) * W / ref < 2^31.  With an integer scale, x = y
+// is an integer and T = y; otherwise x at least 2^-19 from every integer gives
+// T - 1 = floor(x), and the exact path decides the rest (rare: x falls within
+// 2^-19 of an integer).
 __device__ __forceinline__ uint32_t entry_threshold(const OpScale& o, uint32_t L) {
   const uint32_t l1 = L + 1u;
   if (l1 > o.cut32) return 0x7FFFFFFFu;
   const double x = (double)l1 * o.scale;
   const double fl = floor(x);
   const double fr = x - fl;
+  if (o.int_scale) return (uint32_t)fl - 1u;
   if (fr >= 0x1p-19 && fr <= 1.0 - 0x1p-19) return (uint32_t)fl;
-  return entry_threshold_exact(o.W, o.ref, l1);
+  return entry_threshold_exact(o, l1);
 }
 
 // Queue-free records of op v, both slack modes.  The merged frontier of an
