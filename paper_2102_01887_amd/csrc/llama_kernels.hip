@@ -134,6 +134,31 @@ __device__ __forceinline__ uint32_t entry_threshold(const OpScale& o, uint32_t L
   return entry_threshold_exact(o, l1);
 }
 
+// The thresholds of N entries (latencies L[k]) as entry_threshold computes
+// them, without a branch per entry: the fast path of every entry first, so
+// that the entries' FP64 chains overlap, then the exact path for the entries
+// that need it (x within 2^-19 of an integer; rare).
+template <int N>
+__device__ __forceinline__ void entry_thresholds(const OpScale& o, const uint32_t (&L)[N], uint32_t (&U)[N]) {
+  uint32_t slow = 0;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const uint32_t l1 = L[k] + 1u;
+    const bool never = l1 > o.cut32;
+    const double x = (double)l1 * o.scale;
+    const double fl = floor(fmin(x, 2147483648.0));  // below 2^31 + 1 unless never
+    const double fr = x - fl;
+    const bool easy = o.int_scale || (fr >= 0x1p-19 && fr <= 1.0 - 0x1p-19);
+    U[k] = never ? 0x7FFFFFFFu : (uint32_t)fl - (o.int_scale ? 1u : 0u);
+    slow |= (!never && !easy) ? 1u << k : 0u;
+  }
+  if (slow) {
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+      if (slow & (1u << k)) U[k] = entry_threshold_exact(o, L[k] + 1u);
+  }
+}
+
 // Queue-free records of op v, both slack modes.  The merged frontier of an
 // op (which entries survive and their order) depends only on latencies,
 // because every threshold of an op is the same increasing function of L;
@@ -188,10 +213,10 @@ __device__ __forceinline__ void write_op_records(const DevTables& t, int v, cons
   for (int slot = 0; slot < REC_SLOTS; ++slot) Ls[slot] = st.e[slot].x;
 #pragma unroll
   for (int k = 0; k < OVF_PREFETCH; ++k) Lx[k] = st.x[k].x;
+  entry_thresholds<REC_SLOTS>(o, Ls, Us);
 #pragma unroll
-  for (int k = 0; k < REC_SLOTS; ++k) Us[k] = entry_threshold(o, Ls[k]);
-#pragma unroll
-  for (int k = 0; k < OVF_PREFETCH; ++k) Ux[k] = k < n_ovf ? entry_threshold(o, Lx[k]) : 0u;
+  for (int k = 0; k < OVF_PREFETCH; ++k) Ux[k] = 0u;
+  if (n_ovf > 0) entry_thresholds<OVF_PREFETCH>(o, Lx, Ux);
   uint32_t w[REC_WORDS];
 #pragma unroll
   for (int k = 0; k < REC_WORDS; ++k) w[k] = 0;
