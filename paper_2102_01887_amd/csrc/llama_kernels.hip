@@ -271,13 +271,69 @@ size_t relax_lds_bytes(const DevTables& t, bool records) {
 }
 
 // One edge of a level: fold the successor's W (reference latency rd plus its
-// accumulator) into the source's accumulator, for both slack modes.
-__device__ __forceinline__ void relax_edge(uint64_t* sAccP, uint64_t* sAccQ, uint32_t pk, uint32_t q, int32_t rd) {
-  const int src = (int)(pk & 0xFFFFu), dst = (int)(pk >> 16);
-  const uint64_t wp = (uint64_t)(rd + (int64_t)sAccP[dst]);
-  const uint64_t wq = (uint64_t)branch_discount(q, rd + (int64_t)sAccQ[dst]);
+// accumulators aP, aQ) into the source's accumulators, for both slack modes.
+__device__ __forceinline__ void relax_edge(uint64_t* sAccP, uint64_t* sAccQ, uint32_t pk, uint32_t q, int32_t rd,
+                                           uint64_t aP, uint64_t aQ) {
+  const int src = (int)(pk & 0xFFFFu);
+  const uint64_t wp = (uint64_t)(rd + (int64_t)aP);
+  const uint64_t wq = (uint64_t)branch_discount(q, rd + (int64_t)aQ);
   atomicMax((unsigned long long*)&sAccP[src], (unsigned long long)wp);
   atomicMax((unsigned long long*)&sAccQ[src], (unsigned long long)wq);
+}
+
+// The level passes of a staged pipeline on one wavefront, lane = edge.  The
+// next level's edges (static) are read together with the current level's
+// successor values, so each level costs one round of LDS reads and one of
+// atomics; LDS operations of a wavefront take effect in order, so the reads
+// of a level see the maxima of the one before.  SMALL: at most 64 levels,
+// every level bound in registers (lane l holds the first edge of level l and
+// of level l + 1); otherwise bounds past level 63 come from LDS.
+template <bool SMALL>
+__device__ __forceinline__ void relax_levels(uint64_t* sAccP, uint64_t* sAccQ, const int32_t* sRef,
+                                             const uint32_t* sE, const uint32_t* sEq, const int32_t* sEb, int nl,
+                                             int lane) {
+  const int eb0 = lane <= nl ? sEb[lane] : 0;
+  const int eb1 = lane + 1 <= nl ? sEb[lane + 1] : 0;
+  auto lvl_lo = [&](int l) { return SMALL || l < 64 ? __builtin_amdgcn_readlane(eb0, l) : sEb[l]; };
+  auto lvl_hi = [&](int l) { return SMALL || l < 64 ? __builtin_amdgcn_readlane(eb1, l) : sEb[l + 1]; };
+  // level 0 (the outputs) has no outgoing edges
+  int lo = lvl_lo(1), hi = lvl_hi(1);
+  bool act = lo + lane < hi;
+  uint32_t pk = 0, q = 0;
+  if (act) {
+    pk = sE[lo + lane];
+    q = sEq[lo + lane];
+  }
+  for (int l = 1; l < nl; ++l) {
+    const bool more = l + 1 < nl;
+    const int lo_n = more ? lvl_lo(l + 1) : 0, hi_n = more ? lvl_hi(l + 1) : 0;
+    const bool act_n = more && lo_n + lane < hi_n;
+    int32_t rd = 0;
+    uint64_t aP = 0, aQ = 0;
+    if (act) {
+      const int dst = (int)(pk >> 16);
+      rd = sRef[dst];
+      aP = sAccP[dst];
+      aQ = sAccQ[dst];
+    }
+    uint32_t pk_n = 0, q_n = 0;
+    if (act_n) {
+      pk_n = sE[lo_n + lane];
+      q_n = sEq[lo_n + lane];
+    }
+    if (act) relax_edge(sAccP, sAccQ, pk, q, rd, aP, aQ);
+    for (int idx = lo + 64 + lane; idx < hi; idx += 64) {  // levels wider than 64 edges
+      const uint32_t pk2 = sE[idx];
+      const int dst = (int)(pk2 >> 16);
+      relax_edge(sAccP, sAccQ, pk2, sEq[idx], sRef[dst], sAccP[dst], sAccQ[dst]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    pk = pk_n;
+    q = q_n;
+    act = act_n;
+    lo = lo_n;
+    hi = hi_n;
+  }
 }
 
 // RECORDS: every pipeline has at most 64 ops and the workgroup has two
@@ -362,47 +418,10 @@ __global__ __launch_bounds__(128) void relax_kernel(DevTables t) {
       }
       for (int i = lane; i <= nl; i += 64) sEb[i] = t.lvl_ebnd[l0 + i] - e0;
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      if (nl > 1) {
-        // lane l holds the first edge of level l and of level l + 1
-        const int eb0 = lane <= nl ? sEb[lane] : 0;
-        const int eb1 = lane + 1 <= nl ? sEb[lane + 1] : 0;
-        auto lvl_lo = [&](int l) { return l < 64 ? __builtin_amdgcn_readlane(eb0, l) : sEb[l]; };
-        auto lvl_hi = [&](int l) { return l < 64 ? __builtin_amdgcn_readlane(eb1, l) : sEb[l + 1]; };
-        // level 0 (the outputs) has no outgoing edges
-        int lo = lvl_lo(1), hi = lvl_hi(1);
-        bool act = lo + lane < hi;
-        uint32_t pk = 0, q = 0;
-        int32_t rd = 0;
-        if (act) {
-          pk = sE[lo + lane];
-          q = sEq[lo + lane];
-          rd = sRef[pk >> 16];
-        }
-        for (int l = 1; l < nl; ++l) {
-          const bool more = l + 1 < nl;
-          const int lo_n = more ? lvl_lo(l + 1) : 0, hi_n = more ? lvl_hi(l + 1) : 0;
-          const bool act_n = more && lo_n + lane < hi_n;
-          uint32_t pk_n = 0, q_n = 0;
-          int32_t rd_n = 0;
-          if (act_n) {
-            pk_n = sE[lo_n + lane];
-            q_n = sEq[lo_n + lane];
-            rd_n = sRef[pk_n >> 16];
-          }
-          if (act) relax_edge(sAccP, sAccQ, pk, q, rd);
-          for (int idx = lo + 64 + lane; idx < hi; idx += 64) {
-            const uint32_t pk2 = sE[idx];
-            relax_edge(sAccP, sAccQ, pk2, sEq[idx], sRef[pk2 >> 16]);
-          }
-          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-          pk = pk_n;
-          q = q_n;
-          rd = rd_n;
-          act = act_n;
-          lo = lo_n;
-          hi = hi_n;
-        }
-      }
+      if (nl > 64)
+        relax_levels<false>(sAccP, sAccQ, sRef, sE, sEq, sEb, nl, lane);
+      else if (nl > 1)
+        relax_levels<true>(sAccP, sAccQ, sRef, sE, sEq, sEb, nl, lane);
     }
     __syncthreads();
     if (RECORDS) {
