@@ -70,8 +70,9 @@ def parse():
 
 
 # kernel of each decision schedule (llama_autotune's numbering)
+# (the LDS-staged schedule runs its 16-byte variant: the bench's arrays are aligned)
 SCHEDULE_KERNELS = ("void decide_indexed_kernel<1, false>", "void decide_indexed_kernel<2, false>",
-                    "void decide_indexed_kernel<4, false>", "decide_lds_kernel",
+                    "void decide_indexed_kernel<4, false>", "decide_lds4_kernel",
                     "void decide_indexed_kernel<1, true>", "void decide_indexed_kernel<2, true>",
                     "void decide_indexed_kernel<4, true>")
 
