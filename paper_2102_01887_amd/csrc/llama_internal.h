@@ -186,7 +186,21 @@ struct BatchingArgs {
   const int32_t* available;
   const int32_t* upstream;
   const int32_t* wait_us;
+  uint2* queue;      // scratch: BATCH_QUEUES sub-queues of {invocation, x* | meets << 16} left
+                     // for the batch-limited scan, each of batch_queue_capacity(n) entries
+  uint32_t* count;   // scratch: entries of sub-queue j at count[32 * j] (one 128-byte line each)
 };
+// The commit kernel's workgroup g appends to sub-queue g mod BATCH_QUEUES, so
+// that no single counter takes every workgroup's atomic.
+constexpr int BATCH_QUEUES = 64;
+constexpr int BATCH_BLOCK = 256;
+inline int64_t batch_queue_capacity(int64_t n) {
+  const int64_t groups = (n + BATCH_BLOCK - 1) / BATCH_BLOCK;
+  return ((groups + BATCH_QUEUES - 1) / BATCH_QUEUES) * BATCH_BLOCK;
+}
+inline size_t batch_scratch_bytes(int64_t n) {
+  return sizeof(uint32_t) * 32 * BATCH_QUEUES + sizeof(uint2) * (size_t)BATCH_QUEUES * (size_t)batch_queue_capacity(n);
+}
 hipError_t launch_decide_batching(const DevTables& t, const Batch& b, const BatchingArgs& a, hipStream_t s);
 // Stable LSD radix sort of (uint64 key, int32 value) pairs (sort_kernels.hip).
 hipError_t sort_pairs_bytes(int n, size_t* bytes);

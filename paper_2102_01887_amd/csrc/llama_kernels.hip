@@ -1814,88 +1814,136 @@ __global__ __launch_bounds__(256) void affinity_kernel(DevTables t, Batch b, dou
 }
 
 // ---------------------------------------------------------------------------
-// Safe delayed batching: one wavefront per invocation, lanes over the op's
-// configurations (caller order, coalesced), four running minima: the
-// cheapest feasible key and the fastest (L << 16 | k) over all
-// configurations, and the same over those whose batch fits the available
-// invocations; lane 0 then takes the commit-or-wait decision.
+// Safe delayed batching, two kernels.
+//   batching_commit_kernel  one thread per invocation: x*, the Eq. 1 choice
+//                           over every configuration, from the op's decision
+//                           record (with queueing times the records are
+//                           rebuilt for the call); commit x* when its batch
+//                           is available, wait when it meets its slack and
+//                           the batch arrives in time; any other invocation
+//                           joins its workgroup's sub-queue (one atomic per
+//                           wavefront, 64 sub-queues)
+//   batching_scan_kernel    one wavefront per sub-queue slot (those past their
+//                           sub-queue's length exit at once): lanes over the
+//                           op's configurations (caller order, coalesced),
+//                           the cheapest feasible key and the fastest
+//                           (L << 16 | k) among those whose batch fits
+//                           max(available, 1); x* if none fits
 // ---------------------------------------------------------------------------
 template <int NHW>
-__global__ __launch_bounds__(256) void decide_batching_kernel(DevTables t, Batch b, BatchingArgs ba) {
-  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (i >= b.n) return;  // uniform per wavefront
-  const int v = b.op[i], e = b.elapsed[i], s = b.slo[i];
-  if (invalid_invocation(v, e, s, t.n_ops)) {
-    if (lane == 0) {
+__device__ __forceinline__ int32_t backend_target(const DevTables& t, const Batch& b, int v, int64_t r0, int h) {
+  const int64_t R = remaining_time(r0, b.queue ? b.queue[h] : 0);
+  return R == 0 ? 0 : (int32_t)div_floor_pos((int64_t)t.ref[v] * R, t.W[(int64_t)b.mode * t.n_ops + v]);
+}
+
+template <int NHW>
+__global__ __launch_bounds__(BATCH_BLOCK) void batching_commit_kernel(DevTables t, Batch b, BatchingArgs ba,
+                                                                      const uint4* rec, const uint4* tail,
+                                                                      const uint4* tail2, const uint2* ovf,
+                                                                      int64_t cap) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool push = false;
+  int xs = 0;
+  uint8_t meets = 0;
+  if (i < b.n) {
+    const int v = b.op[i], e = b.elapsed[i], s = b.slo[i];
+    if (invalid_invocation(v, e, s, t.n_ops)) {
       b.cfg[i] = -1;
       if (b.flag) b.flag[i] = 0;
       atomicOr(t.err, 1u);
+    } else {
+      xs = decide_from_record(t, tail, tail2, ovf, v, rec[v], s - e, &meets);
+      const int a = t.cfg_off[v];
+      const int32_t av = ba.available[v];
+      const int32_t Bx = t.cfg_batch[a + xs];
+      int c = xs;
+      uint8_t f = meets;
+      if (Bx > av) {
+        bool wait = false;
+        if (meets && (int64_t)av + ba.upstream[v] >= Bx) {
+          const int32_t tx = backend_target<NHW>(t, b, v, (int64_t)s - e, t.cfg_hw[a + xs]);
+          wait = (int64_t)ba.wait_us[v] + t.cfg_lat[a + xs] < tx;
+        }
+        if (wait) {
+          c = CFG_WAIT;
+          f = 1;
+        } else {
+          push = true;
+        }
+      }
+      if (!push) {
+        b.cfg[i] = c;
+        if (b.flag) b.flag[i] = f;
+      }
     }
-    return;
   }
-  const int64_t r0 = (int64_t)s - e;
-  const int64_t ref = t.ref[v];
-  const int64_t W = t.W[(int64_t)b.mode * t.n_ops + v];
-  int32_t target[NHW];
-#pragma unroll
-  for (int h = 0; h < NHW; ++h) {
-    const int64_t R = remaining_time(r0, b.queue ? b.queue[h] : 0);
-    target[h] = R == 0 ? 0 : (int32_t)div_floor_pos(ref * R, W);
+  // wavefront-aggregated append to this workgroup's sub-queue
+  const uint64_t mask = __ballot(push);
+  if (mask == 0) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)mask) - 1;
+  const int sq = (int)(blockIdx.x % BATCH_QUEUES);
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(ba.count + 32 * sq, (uint32_t)__popcll(mask));
+  base = __shfl(base, leader, 64);
+  if (push) {
+    const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+    ba.queue[(int64_t)sq * cap + base + rank] = make_uint2((uint32_t)i, (uint32_t)xs | ((uint32_t)meets << 16));
   }
-  const int a = t.cfg_off[v], end = t.cfg_off[v + 1];
-  const int32_t av = ba.available[v];
-  const int64_t limit = av > 1 ? av : 1;
-  uint32_t kF = KEY_NONE, kFr = KEY_NONE;
-  uint64_t fA = ~0ull, fR = ~0ull;
-  for (int x = a + lane; x < end; x += 64) {
-    const int32_t L = t.cfg_lat[x];
-    const uint32_t key = t.cfg_key[x];
-    const int hw = t.cfg_hw[x];
-    const int32_t B = t.cfg_batch[x];
-    int32_t tg = target[0];
+}
+
+template <int NHW>
+__global__ __launch_bounds__(256) void batching_scan_kernel(DevTables t, Batch b, BatchingArgs ba, int64_t cap) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int sq = (int)(w / cap);
+  const int64_t q = w - (int64_t)sq * cap;
+  // the counts are final: the commit kernel ran before on this stream
+  if (sq < BATCH_QUEUES && q < (int64_t)ba.count[32 * sq]) {  // uniform per wavefront
+    const uint2 ent = ba.queue[w];
+    const int64_t i = ent.x;
+    const int v = b.op[i];
+    const int64_t r0 = (int64_t)b.slo[i] - b.elapsed[i];
+    int32_t target[NHW];
 #pragma unroll
-    for (int h = 1; h < NHW; ++h) tg = hw == h ? target[h] : tg;
-    const bool feas = L < tg;
-    const uint64_t fk = ((uint64_t)(uint32_t)L << 16) | (uint32_t)(x - a);
-    if (feas && key < kF) kF = key;
-    if (fk < fA) fA = fk;
-    if (B <= limit) {
-      if (feas && key < kFr) kFr = key;
+    for (int h = 0; h < NHW; ++h) target[h] = backend_target<NHW>(t, b, v, r0, h);
+    const int a = t.cfg_off[v], end = t.cfg_off[v + 1];
+    const int32_t av = ba.available[v];
+    const int64_t limit = av > 1 ? av : 1;
+    uint32_t kFr = KEY_NONE;
+    uint64_t fR = ~0ull;
+    for (int x = a + lane; x < end; x += 64) {
+      const int32_t B = t.cfg_batch[x];
+      if (B > limit) continue;
+      const int32_t L = t.cfg_lat[x];
+      const uint32_t key = t.cfg_key[x];
+      const int hw = t.cfg_hw[x];
+      int32_t tg = target[0];
+#pragma unroll
+      for (int h = 1; h < NHW; ++h) tg = hw == h ? target[h] : tg;
+      const uint64_t fk = ((uint64_t)(uint32_t)L << 16) | (uint32_t)(x - a);
+      if (L < tg && key < kFr) kFr = key;
       if (fk < fR) fR = fk;
     }
-  }
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const uint32_t o1 = __shfl_xor(kF, off, 64), o2 = __shfl_xor(kFr, off, 64);
-    const uint64_t o3 = __shfl_xor(fA, off, 64), o4 = __shfl_xor(fR, off, 64);
-    kF = o1 < kF ? o1 : kF;
-    kFr = o2 < kFr ? o2 : kFr;
-    fA = o3 < fA ? o3 : fA;
-    fR = o4 < fR ? o4 : fR;
-  }
-  if (lane != 0) return;
-  const bool meets = kF != KEY_NONE;
-  const int xs = (int)((meets ? (uint64_t)kF : fA) & 0xFFFFu);
-  const int32_t Bx = t.cfg_batch[a + xs];
-  int c = xs;
-  uint8_t f = meets ? 1 : 0;
-  if (Bx > av) {
-    const int hx = t.cfg_hw[a + xs];
-    int32_t tx = target[0];
-#pragma unroll
-    for (int h = 1; h < NHW; ++h) tx = hx == h ? target[h] : tx;
-    if (meets && (int64_t)av + ba.upstream[v] >= Bx && (int64_t)ba.wait_us[v] + t.cfg_lat[a + xs] < tx) {
-      c = CFG_WAIT;
-      f = 1;
-    } else if (fR != ~0ull) {
-      const bool mr = kFr != KEY_NONE;
-      c = (int)((mr ? (uint64_t)kFr : fR) & 0xFFFFu);
-      f = mr ? 1 : 0;
+    for (int off = 32; off > 0; off >>= 1) {
+      const uint32_t o2 = __shfl_xor(kFr, off, 64);
+      const uint64_t o4 = __shfl_xor(fR, off, 64);
+      kFr = o2 < kFr ? o2 : kFr;
+      fR = o4 < fR ? o4 : fR;
+    }
+    if (lane == 0) {
+      int c = (int)(ent.y & 0xFFFFu);
+      uint8_t f = (uint8_t)(ent.y >> 16);
+      if (fR != ~0ull) {  // otherwise no configuration fits: x* stands
+        const bool mr = kFr != KEY_NONE;
+        c = (int)((mr ? (uint64_t)kFr : fR) & 0xFFFFu);
+        f = mr ? 1 : 0;
+      }
+      b.cfg[i] = c;
+      if (b.flag) b.flag[i] = f;
     }
   }
-  b.cfg[i] = c;
-  if (b.flag) b.flag[i] = f;
 }
 
 #define LLAMA_DISPATCH_NHW(KERNEL, GRID, BLOCK, STREAM, ...)                         \
@@ -1977,7 +2025,27 @@ hipError_t launch_feedback(const DevTables& t, const FeedbackArgs& f, int64_t n,
 
 hipError_t launch_decide_batching(const DevTables& t, const Batch& b, const BatchingArgs& a, hipStream_t s) {
   if (b.n == 0) return hipSuccess;
-  LLAMA_DISPATCH_NHW(decide_batching_kernel, dim3(blocks_for(b.n, 4)), dim3(256), s, t, b, a);
+  const uint4* rec = t.rec + (int64_t)b.mode * t.n_ops;
+  const uint4* tail = t.rec_tail + (int64_t)b.mode * t.n_ops * 3;
+  const uint4* tail2 = t.rec_tail2 + (int64_t)b.mode * t.n_ops * 4;
+  const uint2* ovf = t.ovf + (int64_t)b.mode * t.n_front;
+  if (b.queue) {
+    // records for this call's queueing times, in the context's own buffers
+    hipError_t e = launch_records(t, b.mode, 1, b.queue, t.rec_q, t.rec_tail_q, t.rec_tail2_q, t.ovf_q, s);
+    if (e != hipSuccess) return e;
+    rec = t.rec_q;
+    tail = t.rec_tail_q;
+    tail2 = t.rec_tail2_q;
+    ovf = t.ovf_q;
+  }
+  const int64_t cap = batch_queue_capacity(b.n);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks_for(32 * BATCH_QUEUES, 256)), dim3(256), 0, s,
+                     reinterpret_cast<int32_t*>(a.count), (int64_t)32 * BATCH_QUEUES);
+  LLAMA_DISPATCH_NHW(batching_commit_kernel, dim3(blocks_for(b.n, BATCH_BLOCK)), dim3(BATCH_BLOCK), s, t, b, a, rec,
+                     tail, tail2, ovf, cap);
+  // one wavefront per sub-queue slot; those past their sub-queue's count exit at once
+  LLAMA_DISPATCH_NHW(batching_scan_kernel, dim3(blocks_for((int64_t)BATCH_QUEUES * cap, 4)), dim3(256), s, t, b, a,
+                     cap);
   return hipGetLastError();
 }
 

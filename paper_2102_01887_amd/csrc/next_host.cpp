@@ -247,10 +247,29 @@ int llama_decide_batching(llama_ctx* c, int64_t n, const int32_t* op, const int3
     return llama::fail(c, LLAMA_E_ARG, "decide_batching: null pointer");
   if (mode != LLAMA_SLACK_PAPER && mode != LLAMA_SLACK_PROB)
     return llama::fail(c, LLAMA_E_ARG, "decide_batching: bad slack_mode %d", mode);
+  if (n > INT32_MAX) return llama::fail(c, LLAMA_E_RANGE, "decide_batching: n_inv out of range");
+  if (n == 0) return LLAMA_OK;
+  hipStream_t s = (hipStream_t)stream;
+  // scratch: sub-queue counters and the sub-queues (grows; not while the
+  // stream is being captured)
+  const size_t need = llama::batch_scratch_bytes(n);
+  if (need > c->d_batch_scratch.bytes) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (s && hipStreamIsCapturing(s, &cs) != hipSuccess)
+      return llama::fail(c, LLAMA_E_DEVICE, "decide_batching: capture status");
+    if (cs != hipStreamCaptureStatusNone)
+      return llama::fail(c, LLAMA_E_STATE, "decide_batching: scratch must grow; call once before capturing");
+    if (s && hipStreamSynchronize(s) != hipSuccess) return llama::fail(c, LLAMA_E_DEVICE, "decide_batching: sync");
+    if ((rc = llama::upload(c, c->d_batch_scratch, nullptr, need, "batching scratch"))) return rc;
+    if ((rc = llama::sync_ctx(c, "batching scratch"))) return rc;
+  }
   llama::Batch b{};
   b.n = n; b.op = op; b.elapsed = elapsed; b.slo = slo; b.queue = queue; b.cfg = cfg; b.flag = flag; b.mode = mode;
-  llama::BatchingArgs a{available, upstream, wait_us};
-  hipError_t e = llama::launch_decide_batching(c->tables(), b, a, (hipStream_t)stream);
+  char* scratch = static_cast<char*>(c->d_batch_scratch.p);
+  llama::BatchingArgs a{available, upstream, wait_us,
+                        reinterpret_cast<uint2*>(scratch + sizeof(uint32_t) * 32 * llama::BATCH_QUEUES),
+                        reinterpret_cast<uint32_t*>(scratch)};
+  hipError_t e = llama::launch_decide_batching(c->tables(), b, a, s);
   if (e != hipSuccess) return llama::hip_fail(c, e, "decide_batching launch");
   return LLAMA_OK;
 }
