@@ -336,7 +336,12 @@ int llama_decide_alpha(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
  *   4. else commit the Eq. 1 choice among the configurations with
  *      B <= max(available, 1), or x* if none has.
  * d_flag is 1 when the committed configuration meets its slack.  Invalid
- * invocations get -1 / 0 and set the device error word.
+ * invocations get -1 / 0 and set the device error word.  The context keeps a
+ * scratch queue of about 8 bytes per invocation (those that need the
+ * batch-limited choice); it grows on demand but not while `stream` is being
+ * captured (LLAMA_E_STATE: call once before capturing).  Calls that overlap on
+ * one context share it and must be ordered.  n_inv above 2^31 - 1 is
+ * LLAMA_E_RANGE.
  */
 #define LLAMA_CFG_WAIT (-2)
 int llama_decide_batching(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
