@@ -81,3 +81,20 @@ def test_batching_plenty_available_is_plain_decide_and_invalid():
     torch.cuda.synchronize()
     assert (c.cpu().numpy()[::5] == -1).all()
     assert r.L.stats(reset_error=True)["device_error"] & B.DEVERR_INVALID_INVOCATION
+
+
+def test_batching_scratch_grows_on_one_context():
+    # the queue scratch is sized by the first call and grows with a larger
+    # batch; each call's decisions must match the oracle's
+    w = wl.make_c2(seed=74, n_pipelines=10, n_inv=30_001)
+    r = Run(w)
+    torch = r.torch
+    rng = np.random.default_rng(5)
+    avail, up, wait = per_op(rng, w, 40, 40, 1_000_000)
+    for n in (1000, 30_001, 257):
+        ws = w.with_invocations(w.inv_op[:n], w.elapsed[:n], w.slo[:n])
+        c, f = r.L.decide_batching(dev(ws.inv_op, torch), dev(ws.elapsed, torch), dev(ws.slo, torch),
+                                   dev(avail, torch), dev(up, torch), dev(wait, torch))
+        torch.cuda.synchronize()
+        c_or, f_or = oracle.Problem(ws).decide_batching(PAPER, avail, up, wait)
+        assert np.array_equal(c.cpu().numpy(), c_or) and np.array_equal(f.cpu().numpy(), f_or), n
