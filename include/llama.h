@@ -314,7 +314,12 @@ int llama_set_alpha(llama_ctx *ctx, uint32_t alpha_num, uint32_t alpha_den);
 /*
  * Alg. 1 targets (as llama_targets, with d_queue_us or zeros) and the
  * finite-alpha Eq. 1 choice, fused; device pointers as in llama_decide.
- * Invalid invocations get -1 / flag 0 and set the device error word.
+ * Invalid invocations get -1 / flag 0 and set the device error word.  With
+ * d_queue_us, when no op has more than 4,096 configurations, each call first
+ * merges every op's configurations by remaining-time threshold plus its
+ * backend's queueing time into context-owned tables (12 bytes per
+ * configuration), so calls with queueing times that overlap on one context
+ * must be ordered.
  */
 int llama_decide_alpha(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
                        const int32_t *d_elapsed_us, const int32_t *d_slo_us,

@@ -125,6 +125,18 @@ struct DevTables {
   int32_t m_steps;
   const double* a_val;       // [2 n_cfg] objective value of each rank, per op from 2 cfg_off[v]
   const int32_t* seg_off;    // [n_ops*n_hw+1] backend segments of the full table
+  // finite alpha, per configuration in the a_lat order: its feasible and
+  // infeasible keys (rank << 16 | local index)
+  const uint32_t* a_fk;
+  const uint32_t* a_ik;
+  // finite alpha with queueing times, rebuilt per call: each op's
+  // configurations merged over its backends by T + Q[backend] (T the
+  // remaining-time threshold, 2^31 = never), with prefix minima of feasible
+  // keys and suffix minima of infeasible keys in that order
+  uint32_t* aq_T;
+  uint32_t* aq_pf;
+  uint32_t* aq_si;
+  int32_t alpha_max_op;      // most configurations of one op (finite-alpha tables)
   const uint2* tab;          // [n_cfg] {latency, key}, grouped by (op, backend), caller order inside
   uint32_t* err;             // device error word
 };
@@ -202,6 +214,11 @@ inline size_t batch_scratch_bytes(int64_t n) {
   return sizeof(uint32_t) * 32 * BATCH_QUEUES + sizeof(uint2) * (size_t)BATCH_QUEUES * (size_t)batch_queue_capacity(n);
 }
 hipError_t launch_decide_batching(const DevTables& t, const Batch& b, const BatchingArgs& a, hipStream_t s);
+// Finite-alpha Eq. 1 with queueing times through the per-call merged order
+// (alpha_kernels.hip); for tables with at most ALPHA_MERGE_MAX configurations
+// per op.
+constexpr int ALPHA_MERGE_MAX = 4096;
+hipError_t launch_decide_alpha_queue(const DevTables& t, const Batch& b, hipStream_t s);
 // Stable LSD radix sort of (uint64 key, int32 value) pairs (sort_kernels.hip).
 hipError_t sort_pairs_bytes(int n, size_t* bytes);
 hipError_t sort_pairs(void* tmp, size_t tmp_bytes, const uint64_t* kin, uint64_t* kout, const int32_t* vin,

@@ -80,7 +80,7 @@ int build_alpha_tables(llama_ctx* c) {
   const int64_t n_cfg = c->n_cfg;
   std::vector<int32_t> a_lat(n_cfg), m_lat(n_cfg);
   std::vector<double> a_val(2 * (size_t)n_cfg, 0.0);
-  std::vector<uint32_t> a_pf(n_cfg), a_si(n_cfg), m_pf(n_cfg), m_si(n_cfg);
+  std::vector<uint32_t> a_pf(n_cfg), a_si(n_cfg), m_pf(n_cfg), m_si(n_cfg), a_fk(n_cfg), a_ik(n_cfg);
   int max_seg = 0, max_op = 0;
   bool too_many = false;
 #pragma omp parallel for schedule(dynamic, 64) reduction(max : max_seg, max_op) reduction(|| : too_many)
@@ -131,7 +131,9 @@ int build_alpha_tables(llama_ctx* c) {
       for (int i = s0; i < s1; ++i) {
         const int j = seg[i];
         a_lat[a + i] = c->lat[a + j];
-        m = std::min(m, (rank[2 * j] << 16) | (uint32_t)j);
+        a_fk[a + i] = (rank[2 * j] << 16) | (uint32_t)j;
+        a_ik[a + i] = (rank[2 * j + 1] << 16) | (uint32_t)j;
+        m = std::min(m, a_fk[a + i]);
         a_pf[a + i] = m;
       }
       m = KEY_NONE;
@@ -173,11 +175,21 @@ int build_alpha_tables(llama_ctx* c) {
       (rc = upload(c, c->d_m_lat, m_lat.data(), m_lat.size() * 4, "alpha merged latencies")) ||
       (rc = upload(c, c->d_m_pf, m_pf.data(), m_pf.size() * 4, "alpha merged prefix keys")) ||
       (rc = upload(c, c->d_m_si, m_si.data(), m_si.size() * 4, "alpha merged suffix keys")) ||
-      (rc = upload(c, c->d_a_val, a_val.data(), a_val.size() * 8, "alpha objective values")))
+      (rc = upload(c, c->d_a_val, a_val.data(), a_val.size() * 8, "alpha objective values")) ||
+      (rc = upload(c, c->d_a_fk, a_fk.data(), a_fk.size() * 4, "alpha feasible keys")) ||
+      (rc = upload(c, c->d_a_ik, a_ik.data(), a_ik.size() * 4, "alpha infeasible keys")))
     return rc;
+  if (max_op <= ALPHA_MERGE_MAX) {
+    // per-call merged order for calls with queueing times
+    if ((rc = upload(c, c->d_aq_T, nullptr, (size_t)n_cfg * 4, "alpha merged thresholds")) ||
+        (rc = upload(c, c->d_aq_pf, nullptr, (size_t)n_cfg * 4, "alpha merged prefix keys")) ||
+        (rc = upload(c, c->d_aq_si, nullptr, (size_t)n_cfg * 4, "alpha merged suffix keys")))
+      return rc;
+  }
   if ((rc = sync_ctx(c, "alpha tables"))) return rc;
   c->alpha_steps = steps;
   c->alpha_msteps = msteps;
+  c->alpha_max_op = max_op;
   return LLAMA_OK;
 }
 
@@ -231,7 +243,11 @@ int llama_decide_alpha(llama_ctx* c, int64_t n, const int32_t* op, const int32_t
     return llama::fail(c, LLAMA_E_ARG, "decide_alpha: bad slack_mode %d", mode);
   llama::Batch b{};
   b.n = n; b.op = op; b.elapsed = elapsed; b.slo = slo; b.queue = queue; b.cfg = cfg; b.flag = flag; b.mode = mode;
-  hipError_t e = llama::launch_decide_alpha(c->tables(), b, (hipStream_t)stream);
+  // with queueing times, one search per invocation in the op's per-call
+  // merged order when every op fits the merge; else one search per backend
+  hipError_t e = queue && c->alpha_max_op <= llama::ALPHA_MERGE_MAX && c->d_aq_T.p
+                     ? llama::launch_decide_alpha_queue(c->tables(), b, (hipStream_t)stream)
+                     : llama::launch_decide_alpha(c->tables(), b, (hipStream_t)stream);
   if (e != hipSuccess) return llama::hip_fail(c, e, "decide_alpha launch");
   return LLAMA_OK;
 }

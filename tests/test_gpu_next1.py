@@ -180,3 +180,28 @@ def test_queue_time_feeds_decide_alpha_on_device():
     c_or, f_or = r.P.decide_alpha(PAPER, 1, 4, Q=Q_or)
     assert np.array_equal(c.cpu().numpy(), c_or) and np.array_equal(f.cpu().numpy(), f_or)
     say(f"chained: Q = {Q_or.tolist()}, {f_or.mean():.3f} meet their slack")
+
+
+def test_alpha_queue_extremes_and_c3():
+    # the per-call merged order with queueing times at the clamp's edges:
+    # negative (always within reach), zero, just under and at 2^31 (never)
+    w = wl.with_resource_totals(wl.make_c2(seed=45, n_pipelines=12, n_inv=20_000))
+    r = Run(w)
+    for Q in ([-(1 << 40), 0, (1 << 31) - 5, 1 << 31], [7, -3, 123_456, 1 << 62]):
+        alpha_parity(r, Q=Q, modes=(PAPER, PROB), alphas=((1, 1),))
+    w3 = wl.with_resource_totals(wl.make_c3(seed=46, n_pipelines=20, n_inv=20_000))
+    alpha_parity(Run(w3), Q=[100_000, 0, 2_000_000, 40_000], modes=(PAPER,), alphas=((2, 1),))
+
+
+def test_alpha_queue_fallback_for_large_ops():
+    # an op with more configurations than the per-call merge takes (4,096):
+    # one search per backend instead; same decisions
+    from test_oracle_affinity import single_op
+    rng = np.random.default_rng(47)
+    n = 5000
+    w = single_op(rng.integers(0, 3, n), rng.integers(1, 9, n), rng.integers(1, 5, n),
+                  rng.integers(1, 400_000, n), rng.integers(1, 10_000, n), 3, [40, 30, 20],
+                  slo=rng.integers(1, 800_000, 3000), elapsed=rng.integers(0, 1000, 3000))
+    r = Run(w)
+    alpha_parity(r, Q=[50_000, 0, 300_000], modes=(PAPER,), alphas=((1, 1),))
+    alpha_parity(r, alphas=((1, 1),))
