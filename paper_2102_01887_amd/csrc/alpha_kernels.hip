@@ -22,6 +22,8 @@
 //                        wavefront scans
 //   alpha_queue_kernel   one thread per invocation: one binary search over
 //                        the op's merged thresholds, two key loads
+//   affinity_queue_kernel  Eq. 3 the same way (the merge also records, per
+//                        merged position, each backend's entries before it)
 #include <hip/hip_runtime.h>
 
 #include "llama_internal.h"
@@ -113,19 +115,29 @@ __global__ __launch_bounds__(64) void alpha_merge_kernel(DevTables t, int mode, 
   for (int j = lane; j < n; j += 64) {
     const int h = seg_of(j);
     const uint32_t Tj = sT[j];
-    int pos = j - off[h];
+    int before_g[NHW];  // entries of each backend before j in the merged order
 #pragma unroll
     for (int g = 0; g < NHW; ++g) {
-      if (g == h) continue;
+      if (g == h) {
+        before_g[g] = j - off[h];
+        continue;
+      }
       int lo = off[g], hi = off[g + 1];
       while (lo < hi) {
         const int mid = (lo + hi) >> 1;
         const bool before = sT[mid] < Tj || (sT[mid] == Tj && g < h);
         if (before) lo = mid + 1; else hi = mid;
       }
-      pos += lo - off[g];
+      before_g[g] = lo - off[g];
     }
+    int pos = 0;
+#pragma unroll
+    for (int g = 0; g < NHW; ++g) pos += before_g[g];
     t.aq_T[a + pos] = Tj;
+    if (t.aq_cnt) {
+#pragma unroll
+      for (int g = 0; g < NHW; ++g) t.aq_cnt[(int64_t)(a + pos) * NHW + g] = (uint16_t)before_g[g];
+    }
     sF[pos] = t.a_fk[a + j];
     sI[pos] = t.a_ik[a + j];
   }
@@ -190,10 +202,109 @@ __global__ __launch_bounds__(256) void alpha_queue_kernel(DevTables t, Batch b) 
   if (b.flag) b.flag[i] = meets;
 }
 
+// Eq. 3 affinity: one search in a merged order gives j, the number of the
+// op's feasible configurations (QUEUE: the per-call order, T + Q <= r0;
+// otherwise every backend has the same target and the static latency order
+// m_lat serves, L < target); the per-backend counts at j give, for each
+// backend, how many of its configurations are feasible, which is exactly
+// where the per-backend search in latency order ends, so the prefix and
+// suffix minima of that order (a_pf, a_si) give each backend's best key.  The rest is the per-backend kernel's: the ratio of the
+// objective values of the best key on the backend and the best elsewhere
+// (no configuration on the backend -> 0; none elsewhere -> infinity; a zero
+// own minimum -> infinity, or 1 when the other minimum is zero too), and with
+// `keys` the sort keys for the commit order.
+template <int NHW, bool QUEUE>
+__global__ __launch_bounds__(256) void affinity_queue_kernel(DevTables t, Batch b, double* aff, uint64_t* keys,
+                                                             int32_t* iota) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= b.n) return;
+  if (iota) iota[i] = (int32_t)i;
+  const int v = b.op[i], e = b.elapsed[i], s = b.slo[i];
+  double out[NHW];
+  if ((unsigned)v >= (unsigned)t.n_ops || (e | s) < 0) {
+    atomicOr(t.err, 1u);
+#pragma unroll
+    for (int h = 0; h < NHW; ++h) out[h] = 0.0;
+  } else {
+    const int lo0 = t.cfg_off[v], end = t.cfg_off[v + 1];
+    int lo = lo0, len = end - lo0;
+    if (QUEUE) {
+      const uint32_t r0 = (uint32_t)((int64_t)s - e + R0_MAX);  // r0 on the stored scale
+      for (int step = 0; step < t.m_steps && len > 0; ++step) {
+        const int half = len >> 1;
+        if (t.aq_T[lo + half] <= r0) {
+          lo += half + 1;
+          len -= half + 1;
+        } else {
+          len = half;
+        }
+      }
+    } else {
+      // target = floor(ref * R / W), R = clamp(r0, 0, 2^31 - 1), 0 when R = 0
+      const int64_t r0 = (int64_t)s - e;
+      const int64_t R = r0 < 0 ? 0 : r0;
+      const int32_t target =
+          R == 0 ? 0 : (int32_t)floor_div((int64_t)t.ref[v] * R, t.W[(int64_t)b.mode * t.n_ops + v]);
+      for (int step = 0; step < t.m_steps && len > 0; ++step) {
+        const int half = len >> 1;
+        if (t.m_lat[lo + half] < target) {
+          lo += half + 1;
+          len -= half + 1;
+        } else {
+          len = half;
+        }
+      }
+    }
+    const uint16_t* cnt = QUEUE ? t.aq_cnt : t.m_cnt;
+    const int32_t* so = t.seg_off + (int64_t)v * NHW;
+    uint32_t best[NHW];
+#pragma unroll
+    for (int h = 0; h < NHW; ++h) {
+      const int feas = lo < end ? (int)cnt[(int64_t)lo * NHW + h] : so[h + 1] - so[h];
+      const int j = so[h] + feas;
+      uint32_t k = KEY_NONE;
+      if (feas > 0) k = t.a_pf[j - 1];
+      if (j < so[h + 1]) {
+        const uint32_t ki = t.a_si[j];
+        k = ki < k ? ki : k;
+      }
+      best[h] = k;
+    }
+    const double* val = t.a_val + 2 * (int64_t)lo0;
+#pragma unroll
+    for (int h = 0; h < NHW; ++h) {
+      uint32_t oth = KEY_NONE;
+#pragma unroll
+      for (int g = 0; g < NHW; ++g)
+        if (g != h && best[g] < oth) oth = best[g];
+      double a;
+      if (best[h] == KEY_NONE) {
+        a = 0.0;
+      } else if (oth == KEY_NONE) {
+        a = __builtin_huge_val();
+      } else {
+        const double vo = val[best[h] >> 16], vt = val[oth >> 16];
+        a = vo == 0.0 ? (vt == 0.0 ? 1.0 : __builtin_huge_val()) : vt / vo;
+      }
+      out[h] = a;
+    }
+  }
+  double* dst = aff + i * NHW;
+#pragma unroll
+  for (int h = 0; h < NHW; ++h) {
+    dst[h] = out[h];
+    // non-negative doubles order like their bit patterns; complemented, an
+    // ascending sort gives decreasing affinity
+    if (keys) keys[(int64_t)h * b.n + i] = ~(uint64_t)__double_as_longlong(out[h]);
+  }
+}
+
 }  // namespace
 
-hipError_t launch_decide_alpha_queue(const DevTables& t, const Batch& b, hipStream_t s) {
-  if (b.n == 0) return hipSuccess;
+namespace {
+
+// The per-call merged order for this call's queueing times and slack mode.
+hipError_t launch_alpha_merge(const DevTables& t, const Batch& b, hipStream_t s) {
   if (!b.queue || t.alpha_max_op > ALPHA_MERGE_MAX || t.n_hw < 1 || t.n_hw > MAX_HW) return hipErrorInvalidValue;
   const size_t lds = sizeof(uint32_t) * 3 * (size_t)(t.alpha_max_op > 0 ? t.alpha_max_op : 1);
   if (t.n_ops > 0) {
@@ -206,6 +317,56 @@ hipError_t launch_decide_alpha_queue(const DevTables& t, const Batch& b, hipStre
       default: return hipErrorInvalidValue;
     }
   }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_affinity_queue(const DevTables& t, const Batch& b, double* aff, int32_t* order, void* scratch,
+                                 size_t scratch_bytes, hipStream_t s) {
+  if (b.n == 0) return hipSuccess;
+  hipError_t e = hipSuccess;
+  if (b.queue) {
+    if (!t.aq_cnt) return hipErrorInvalidValue;
+    e = launch_alpha_merge(t, b, s);
+    if (e != hipSuccess) return e;
+  } else if (!t.m_cnt) {
+    return hipErrorInvalidValue;
+  }
+  const int64_t n = b.n;
+  uint64_t* keys = order ? static_cast<uint64_t*>(scratch) : nullptr;  // [n_hw * n]
+  uint64_t* kout = keys ? keys + (int64_t)t.n_hw * n : nullptr;          // [n]
+  int32_t* iota = kout ? reinterpret_cast<int32_t*>(kout + n) : nullptr; // [n]
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  switch (t.n_hw) {
+#define LLAMA_AFF(K)                                                                                      \
+  case K:                                                                                                 \
+    if (b.queue)                                                                                          \
+      hipLaunchKernelGGL((affinity_queue_kernel<K, true>), dim3(blocks), dim3(256), 0, s, t, b, aff, keys, iota); \
+    else                                                                                                  \
+      hipLaunchKernelGGL((affinity_queue_kernel<K, false>), dim3(blocks), dim3(256), 0, s, t, b, aff, keys, iota); \
+    break;
+    LLAMA_AFF(1) LLAMA_AFF(2) LLAMA_AFF(3) LLAMA_AFF(4)
+    LLAMA_AFF(5) LLAMA_AFF(6) LLAMA_AFF(7) LLAMA_AFF(8)
+#undef LLAMA_AFF
+    default: return hipErrorInvalidValue;
+  }
+  if (!order) return hipGetLastError();
+  const size_t off = ((size_t)n * (8 * (size_t)t.n_hw + 8 + 4) + 255) & ~(size_t)255;
+  if (scratch_bytes < off) return hipErrorInvalidValue;
+  void* tmp = static_cast<char*>(scratch) + off;
+  const size_t tmp_bytes = scratch_bytes - off;
+  for (int h = 0; h < t.n_hw; ++h) {
+    e = sort_pairs(tmp, tmp_bytes, keys + (int64_t)h * n, kout, iota, order + (int64_t)h * n, (int)n, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_decide_alpha_queue(const DevTables& t, const Batch& b, hipStream_t s) {
+  if (b.n == 0) return hipSuccess;
+  hipError_t e = launch_alpha_merge(t, b, s);
+  if (e != hipSuccess) return e;
   const int64_t blocks = (b.n + 255) / 256;
   hipLaunchKernelGGL(alpha_queue_kernel, dim3((unsigned)blocks), dim3(256), 0, s, t, b);
   return hipGetLastError();

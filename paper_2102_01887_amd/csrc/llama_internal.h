@@ -136,6 +136,8 @@ struct DevTables {
   uint32_t* aq_T;
   uint32_t* aq_pf;
   uint32_t* aq_si;
+  uint16_t* aq_cnt;           // [n_cfg * n_hw] per merged position p and backend h: entries of h before p
+  const uint16_t* m_cnt;      // [n_cfg * n_hw] the same for the merged latency order (m_lat)
   int32_t alpha_max_op;      // most configurations of one op (finite-alpha tables)
   const uint2* tab;          // [n_cfg] {latency, key}, grouped by (op, backend), caller order inside
   uint32_t* err;             // device error word
@@ -219,6 +221,11 @@ hipError_t launch_decide_batching(const DevTables& t, const Batch& b, const Batc
 // per op.
 constexpr int ALPHA_MERGE_MAX = 4096;
 hipError_t launch_decide_alpha_queue(const DevTables& t, const Batch& b, hipStream_t s);
+// Eq. 3 affinity through a merged order (one search, then each backend's
+// position from the per-backend counts): with queueing times the per-call
+// order, without them the static latency order.
+hipError_t launch_affinity_queue(const DevTables& t, const Batch& b, double* aff, int32_t* order, void* scratch,
+                                 size_t scratch_bytes, hipStream_t s);
 // Stable LSD radix sort of (uint64 key, int32 value) pairs (sort_kernels.hip).
 hipError_t sort_pairs_bytes(int n, size_t* bytes);
 hipError_t sort_pairs(void* tmp, size_t tmp_bytes, const uint64_t* kin, uint64_t* kout, const int32_t* vin,

@@ -81,6 +81,7 @@ int build_alpha_tables(llama_ctx* c) {
   std::vector<int32_t> a_lat(n_cfg), m_lat(n_cfg);
   std::vector<double> a_val(2 * (size_t)n_cfg, 0.0);
   std::vector<uint32_t> a_pf(n_cfg), a_si(n_cfg), m_pf(n_cfg), m_si(n_cfg), a_fk(n_cfg), a_ik(n_cfg);
+  std::vector<uint16_t> m_cnt((size_t)n_cfg * n_hw);
   int max_seg = 0, max_op = 0;
   bool too_many = false;
 #pragma omp parallel for schedule(dynamic, 64) reduction(max : max_seg, max_op) reduction(|| : too_many)
@@ -152,7 +153,10 @@ int build_alpha_tables(llama_ctx* c) {
       return c->lat[a + p] != c->lat[a + q] ? c->lat[a + p] < c->lat[a + q] : p < q;
     });
     uint32_t m = KEY_NONE;
+    std::vector<uint16_t> seen(n_hw, 0);  // per backend, entries before position i
     for (int i = 0; i < n; ++i) {
+      for (int h = 0; h < n_hw; ++h) m_cnt[(size_t)(a + i) * n_hw + h] = seen[h];
+      ++seen[c->hw[a + all[i]]];
       m_lat[a + i] = c->lat[a + all[i]];
       m = std::min(m, (rank[2 * all[i]] << 16) | (uint32_t)all[i]);
       m_pf[a + i] = m;
@@ -177,13 +181,15 @@ int build_alpha_tables(llama_ctx* c) {
       (rc = upload(c, c->d_m_si, m_si.data(), m_si.size() * 4, "alpha merged suffix keys")) ||
       (rc = upload(c, c->d_a_val, a_val.data(), a_val.size() * 8, "alpha objective values")) ||
       (rc = upload(c, c->d_a_fk, a_fk.data(), a_fk.size() * 4, "alpha feasible keys")) ||
-      (rc = upload(c, c->d_a_ik, a_ik.data(), a_ik.size() * 4, "alpha infeasible keys")))
+      (rc = upload(c, c->d_a_ik, a_ik.data(), a_ik.size() * 4, "alpha infeasible keys")) ||
+      (rc = upload(c, c->d_m_cnt, m_cnt.data(), m_cnt.size() * 2, "alpha merged backend counts")))
     return rc;
   if (max_op <= ALPHA_MERGE_MAX) {
     // per-call merged order for calls with queueing times
     if ((rc = upload(c, c->d_aq_T, nullptr, (size_t)n_cfg * 4, "alpha merged thresholds")) ||
         (rc = upload(c, c->d_aq_pf, nullptr, (size_t)n_cfg * 4, "alpha merged prefix keys")) ||
-        (rc = upload(c, c->d_aq_si, nullptr, (size_t)n_cfg * 4, "alpha merged suffix keys")))
+        (rc = upload(c, c->d_aq_si, nullptr, (size_t)n_cfg * 4, "alpha merged suffix keys")) ||
+        (rc = upload(c, c->d_aq_cnt, nullptr, (size_t)n_cfg * n_hw * 2, "alpha merged backend counts")))
       return rc;
   }
   if ((rc = sync_ctx(c, "alpha tables"))) return rc;
@@ -320,7 +326,13 @@ int llama_affinity(llama_ctx* c, int64_t n, const int32_t* op, const int32_t* el
   }
   llama::Batch b{};
   b.n = n; b.op = op; b.elapsed = elapsed; b.slo = slo; b.queue = queue; b.mode = mode;
-  hipError_t e = llama::launch_affinity(c->tables(), b, aff, order, c->d_aff_scratch.p, c->d_aff_scratch.bytes, s);
+  // one search per invocation in a merged order (with queueing times the
+  // per-call one, when every op fits the merge); else one per backend
+  hipError_t e = (queue ? c->alpha_max_op <= llama::ALPHA_MERGE_MAX && c->d_aq_cnt.p : c->d_m_cnt.p != nullptr)
+                     ? llama::launch_affinity_queue(c->tables(), b, aff, order, c->d_aff_scratch.p,
+                                                    c->d_aff_scratch.bytes, s)
+                     : llama::launch_affinity(c->tables(), b, aff, order, c->d_aff_scratch.p,
+                                              c->d_aff_scratch.bytes, s);
   if (e != hipSuccess) return llama::hip_fail(c, e, "affinity launch");
   return LLAMA_OK;
 }
