@@ -382,3 +382,31 @@ def test_pinned_schedules_agree_with_oracle():
     for bad in (-1, len(B.SCHEDULE_NAMES)):
         with pytest.raises(B.LlamaError):
             r.L.set_schedule(bad)
+
+
+def test_lds_schedule_on_unaligned_arrays():
+    # the LDS-staged schedule reads four invocations per 16-byte load only
+    # when every array is aligned; views that start one element in take its
+    # one-invocation-per-load form, which must give the same decisions
+    torch = _torch()
+    w = wl.make_c2(seed=34, n_pipelines=25, n_inv=50_003)
+    r = Run(w)
+    r.L.set_schedule(B.SCHEDULE_NAMES.index("lds-persistent"))
+    n = w.n_inv
+
+    def shifted(a):
+        buf = torch.empty(len(a) + 1, dtype=torch.int32, device="cuda")
+        buf[1:] = dev(a, torch)
+        return buf[1:]
+
+    op, el, slo = shifted(w.inv_op), shifted(w.elapsed), shifted(w.slo)
+    cfg_buf = torch.full((n + 1,), -9, dtype=torch.int32, device="cuda")
+    flag_buf = torch.full((n + 3,), 7, dtype=torch.uint8, device="cuda")
+    cfg, flag = cfg_buf[1:], flag_buf[3:]
+    assert op.data_ptr() % 16 != 0 and cfg.data_ptr() % 16 != 0 and flag.data_ptr() % 4 != 0
+    for mode in (PAPER, PROB):
+        r.L.decide(op, el, slo, None, mode, B.SCAN_INDEXED, cfg, flag)
+        torch.cuda.synchronize()
+        c_or, f_or = r.P.decide(mode)
+        assert np.array_equal(cfg.cpu().numpy(), c_or) and np.array_equal(flag.cpu().numpy(), f_or), mode
+    assert cfg_buf[0].item() == -9 and (flag_buf[:3].cpu().numpy() == 7).all()
