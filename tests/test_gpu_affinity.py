@@ -105,3 +105,18 @@ def test_affinity_needs_alpha():
     r = Run(wl.with_resource_totals(wl.make_c1()))
     with pytest.raises(B.LlamaError):
         r.L.affinity(r.op, r.el, r.slo)
+
+
+def test_affinity_large_op_fallback_and_static_order():
+    # one op with more configurations than the per-call merge takes (4,096):
+    # with queueing times the per-backend searches, without them the static
+    # merged order; both must match the oracle
+    from test_oracle_affinity import single_op
+    rng = np.random.default_rng(12)
+    n = 5000
+    w = single_op(rng.integers(0, 3, n), rng.integers(1, 9, n), rng.integers(1, 5, n),
+                  rng.integers(1, 400_000, n), rng.integers(1, 10_000, n), 3, [40, 30, 20],
+                  slo=rng.integers(1, 800_000, 2000), elapsed=rng.integers(0, 1000, 2000))
+    r = Run(w)
+    run_case(r, (1, 1), Q=[50_000, 0, 300_000], modes=(PAPER,))
+    run_case(r, (2, 3))
