@@ -461,14 +461,13 @@ __global__ __launch_bounds__(128) void relax_kernel(DevTables t) {
     write_op_records(t, a + lane, st, t.ref[a + lane], t.W[(int64_t)wave * n_ops + a + lane], wave);
 }
 
-// One thread per op: its records (both slack modes) from the relaxed W.
+// One thread per (op, slack mode): its records from the relaxed W.
 __global__ __launch_bounds__(256) void op_records_kernel(DevTables t) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= t.n_ops) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * (int64_t)t.n_ops) return;
+  const int v = (int)(i >> 1), mode = (int)(i & 1);
   const OpStatic st = load_op_static(t, v);
-  const int32_t ref = t.ref[v];
-  write_op_records(t, v, st, ref, t.W[v], 0);
-  write_op_records(t, v, st, ref, t.W[(int64_t)t.n_ops + v], 1);
+  write_op_records(t, v, st, t.ref[v], t.W[(int64_t)mode * t.n_ops + v], mode);
 }
 
 // ---------------------------------------------------------------------------
@@ -1977,7 +1976,7 @@ hipError_t launch_relax(const DevTables& t, hipStream_t s) {
     return hipGetLastError();
   }
   hipLaunchKernelGGL(relax_kernel<false>, dim3(t.n_pipelines), dim3(64), relax_lds_bytes(t, false), s, t);
-  if (t.n_ops > 0) hipLaunchKernelGGL(op_records_kernel, dim3(blocks_for(t.n_ops, 256)), dim3(256), 0, s, t);
+  if (t.n_ops > 0) hipLaunchKernelGGL(op_records_kernel, dim3(blocks_for(2 * (int64_t)t.n_ops, 256)), dim3(256), 0, s, t);
   return hipGetLastError();
 }
 
