@@ -525,8 +525,9 @@ def bench_serving(args, torch, B, wl, log, surrogate_ctx=None):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the decision path "
-              "has no multi-GPU form in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the decision path "
+              "is measured on one GPU's share of the pipelines; it has no multi-GPU launcher",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
