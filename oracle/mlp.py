@@ -4,7 +4,7 @@ The paper profiles each configuration once and corrects profiles through a
 feedback loop, noting that other estimators can replace exponential smoothing
 (Sec. 3.3, Manager) and that input content changes operation latency (Sec. 2,
 Fig. 3: 17.2x on CPU and 4x on GPU between 0 and 60 faces).  The surrogate is
-the build's such estimator: a 2-hidden-layer MLP that predicts, per
+such an estimator: a 2-hidden-layer MLP that predicts, per
 (invocation, configuration) row, the mean and the 95th percentile of ln(latency
 in microseconds) from a per-row embedding and 16 content features.  Nothing in
 the paper fixes the network; its form, loss and optimiser are stated here.
