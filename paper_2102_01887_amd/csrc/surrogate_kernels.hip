@@ -35,9 +35,18 @@ constexpr float GELU_A = 0.044715f;
 constexpr float TAU = 0.95f;
 constexpr int HID = 256, IN = 32, EMB = 16;
 
+// x * sigmoid(2u) with the hardware reciprocal (about one ulp) instead of an
+// IEEE division: the result is rounded to BF16, and the fused inference
+// evaluates 512 of these per row, which made the division its largest VALU
+// cost.  Large negative x: the exponential overflows to infinity and the
+// reciprocal to 0, giving -0.
+// The exponent -2u log2(e) = x (k1 + k2 x^2) goes to exp2 directly, with
+// k1 = -2 log2(e) sqrt(2/pi) and k2 = k1 * 0.044715 folded at compile time.
+constexpr float GELU_K1 = -2.0f * 1.4426950408889634f * GELU_C;
+constexpr float GELU_K2 = GELU_K1 * GELU_A;
 __device__ __forceinline__ float gelu(float x) {
-  const float u = GELU_C * (x + GELU_A * x * x * x);
-  return x / (1.0f + __expf(-2.0f * u));
+  const float t = x * fmaf(GELU_K2, x * x, GELU_K1);
+  return x * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(t));
 }
 
 __device__ __forceinline__ float gelu_grad(float x) {
