@@ -337,20 +337,22 @@ __global__ __launch_bounds__(256) void decide_learned_kernel(DevTables t, Batch 
 #pragma unroll
       for (int mb = 0; mb < 16; ++mb) {
         const bf16x8 w1 = *reinterpret_cast<const bf16x8*>(sW1 + (16 * mb + r) * IN + 8 * g);
+        // the accumulator starts at the bias of this lane's four units
+        const floatx4 b1 = *reinterpret_cast<const floatx4*>(sB1 + 16 * mb + 4 * g);
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) {
-          const floatx4 z = mfma16x16x32(w1, xfrag[nb], floatx4{0.f, 0.f, 0.f, 0.f});
+          const floatx4 z = mfma16x16x32(w1, xfrag[nb], b1);
 #pragma unroll
-          for (int q = 0; q < 4; ++q)
-            hf[mb >> 1][nb][4 * (mb & 1) + q] = (bf16)gelu(z[q] + sB1[16 * mb + 4 * g + q]);
+          for (int q = 0; q < 4; ++q) hf[mb >> 1][nb][4 * (mb & 1) + q] = (bf16)gelu(z[q]);
         }
       }
       // ---- layers 2 and 3
       float p0[4] = {0.f, 0.f, 0.f, 0.f}, p1[4] = {0.f, 0.f, 0.f, 0.f};
       for (int mb2 = 0; mb2 < 16; ++mb2) {
         floatx4 acc[4];
+        const floatx4 b2 = *reinterpret_cast<const floatx4*>(sB2 + 16 * mb2 + 4 * g);
 #pragma unroll
-        for (int nb = 0; nb < 4; ++nb) acc[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int nb = 0; nb < 4; ++nb) acc[nb] = b2;
 #pragma unroll
         for (int kb = 0; kb < 8; ++kb) {
           const bf16x8 w2 = *reinterpret_cast<const bf16x8*>(sW2 + (16 * mb2 + r) * HID + 32 * kb + 8 * g);
@@ -362,7 +364,7 @@ __global__ __launch_bounds__(256) void decide_learned_kernel(DevTables t, Batch 
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int u = 16 * mb2 + 4 * g + q;
-            const float h2 = (float)(bf16)gelu(acc[nb][q] + sB2[u]);
+            const float h2 = (float)(bf16)gelu(acc[nb][q]);
             p0[nb] += sW3[u] * h2;
             p1[nb] += sW3[HID + u] * h2;
           }
