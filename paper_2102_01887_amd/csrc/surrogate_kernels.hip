@@ -174,7 +174,7 @@ __global__ __launch_bounds__(256) void gelu_bwd_round_kernel(int64_t n, const fl
 // out[n] += sum over m of x[m][n]: each 256-lane workgroup sums 64 columns
 // over a chunk of COLSUM_ROWS rows (4 lanes per column), reduces in LDS and
 // adds atomically (out must be zeroed first).
-constexpr int COLSUM_ROWS = 512;
+constexpr int COLSUM_ROWS = 64;
 __global__ __launch_bounds__(256) void colsum_kernel(int64_t M, int N, const bf16* x, float* out) {
   __shared__ float part[4][64];
   const int col = blockIdx.x * 64 + (threadIdx.x & 63);
