@@ -68,6 +68,43 @@ __device__ __forceinline__ floatx4 mfma16x16x32(const bf16x8& a, const bf16x8& b
 // split across workgroups that add their partial sums atomically (C must then
 // be zeroed first, and the bias is added by split 0 only).
 // ---------------------------------------------------------------------------
+// One thread's share of a 64 x 32 operand tile: 8 consecutive elements along
+// the operand's contiguous dimension (the row dimension when `along_row`, else
+// k), with one 16-byte load when the 8 lie inside the matrix and are aligned,
+// else 8 bounds-checked loads.
+struct TileVec {
+  bf16x8 v;
+};
+__device__ __forceinline__ TileVec load_tile_vec(const bf16* __restrict__ p, int64_t s_row, int64_t s_k, bool along_row,
+                                                 bool vec_ok, int row0, int rows, int k0, int kend, int tid) {
+  TileVec t;
+  const int rr = along_row ? (tid & 7) * 8 : tid >> 2;   // first row of the vector
+  const int kk = along_row ? tid >> 3 : (tid & 3) * 8;   // first k of the vector
+  const int gr = row0 + rr, gk = k0 + kk;
+  const bool inside = along_row ? (gr + 8 <= rows && gk < kend) : (gr < rows && gk + 8 <= kend);
+  if (vec_ok && inside) {
+    t.v = *reinterpret_cast<const bf16x8*>(p + (int64_t)gr * s_row + (int64_t)gk * s_k);
+  } else {
+    const bf16 zero = (bf16)0.0f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int r = along_row ? gr + j : gr, k = along_row ? gk : gk + j;
+      t.v[j] = (r < rows && k < kend) ? p[(int64_t)r * s_row + (int64_t)k * s_k] : zero;
+    }
+  }
+  return t;
+}
+
+__device__ __forceinline__ void store_tile_vec(bf16 (*sT)[40], const TileVec& t, bool along_row, int tid) {
+  if (along_row) {
+    const int rr = (tid & 7) * 8, kk = tid >> 3;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) sT[rr + j][kk] = t.v[j];
+  } else {
+    *reinterpret_cast<bf16x8*>(&sT[tid >> 2][(tid & 3) * 8]) = t.v;
+  }
+}
+
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, const bf16* __restrict__ a,
                                                         int64_t sam, int64_t sak, const bf16* __restrict__ b,
                                                         int64_t sbk, int64_t sbn, float* __restrict__ c,
@@ -81,26 +118,30 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, con
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int g = lane >> 4, r = lane & 15;
+  // each operand is staged along its contiguous dimension; 16-byte loads need
+  // a unit stride there, the other stride a multiple of 8 and an aligned base
   const bool a_along_m = sam == 1 && sak != 1;
   const bool b_along_n = sbn == 1 && sbk != 1;
+  const bool a_vec = (a_along_m ? (sak % 8 == 0) : (sak == 1 && sam % 8 == 0)) &&
+                     (reinterpret_cast<uintptr_t>(a) & 15) == 0;
+  const bool b_vec = (b_along_n ? (sbk % 8 == 0) : (sbk == 1 && sbn % 8 == 0)) &&
+                     (reinterpret_cast<uintptr_t>(b) & 15) == 0;
   floatx4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const bf16 zero = (bf16)0.0f;
+  // the next tile is loaded into registers while the current one is multiplied
+  TileVec ta = load_tile_vec(a, sam, sak, a_along_m, a_vec, m0, M, kb0, kb1, tid);
+  TileVec tb = load_tile_vec(b, sbn, sbk, b_along_n, b_vec, n0, N, kb0, kb1, tid);
   for (int k0 = kb0; k0 < kb1; k0 += 32) {
-    for (int e = tid; e < 64 * 32; e += 256) {
-      int mm, kk;
-      if (a_along_m) { mm = e & 63; kk = e >> 6; } else { mm = e >> 5; kk = e & 31; }
-      const int gm = m0 + mm, gk = k0 + kk;
-      sA[mm][kk] = (gm < M && gk < kb1) ? a[gm * sam + gk * sak] : zero;
-      int nn, kn;
-      if (b_along_n) { nn = e & 63; kn = e >> 6; } else { nn = e >> 5; kn = e & 31; }
-      const int gn = n0 + nn, gkn = k0 + kn;
-      sB[nn][kn] = (gn < N && gkn < kb1) ? b[gkn * sbk + gn * sbn] : zero;
-    }
+    store_tile_vec(sA, ta, a_along_m, tid);
+    store_tile_vec(sB, tb, b_along_n, tid);
     __syncthreads();
+    if (k0 + 32 < kb1) {
+      ta = load_tile_vec(a, sam, sak, a_along_m, a_vec, m0, M, k0 + 32, kb1, tid);
+      tb = load_tile_vec(b, sbn, sbk, b_along_n, b_vec, n0, N, k0 + 32, kb1, tid);
+    }
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb) {
       const bf16x8 af = *reinterpret_cast<const bf16x8*>(&sA[wm + mb * 16 + r][8 * g]);
