@@ -285,7 +285,7 @@ struct LearnedArgs {
 
 hipError_t launch_gemm_bf16(int M, int N, int K, const void* a, int64_t sam, int64_t sak, const void* b,
                             int64_t sbk, int64_t sbn, float* c, int64_t ldc, const float* bias, bool accumulate,
-                            hipStream_t s);
+                            hipStream_t s, bool c_zeroed = false);
 hipError_t launch_surrogate_forward(const SurrogateBufs& w, int64_t B, const int32_t* rows, const void* feat,
                                     hipStream_t s);
 hipError_t launch_surrogate_backward(const SurrogateBufs& w, int64_t B, const int32_t* rows, const float* y,

@@ -469,7 +469,7 @@ inline unsigned grid1(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs);
 // ---------------------------------------------------------------------------
 hipError_t launch_gemm_bf16(int M, int N, int K, const void* a, int64_t sam, int64_t sak, const void* bm,
                             int64_t sbk, int64_t sbn, float* c, int64_t ldc, const float* bias, bool accumulate,
-                            hipStream_t s) {
+                            hipStream_t s, bool c_zeroed) {
   if (M <= 0 || N <= 0) return hipSuccess;
   const unsigned gx = grid1(N, 64), gy = grid1(M, 64);
   // few output tiles and a long K (weight gradients over the batch): split K
@@ -480,15 +480,15 @@ hipError_t launch_gemm_bf16(int M, int N, int K, const void* a, int64_t sam, int
   }
   const int k_chunk = (int)(((K + (int)gz - 1) / (int)gz + 31) / 32 * 32);
   gz = (unsigned)((K + k_chunk - 1) / k_chunk);
-  if (gz > 1)  // the split-K partial sums are added atomically into a zeroed C
+  if (gz > 1 && !c_zeroed)  // the split-K partial sums are added atomically into a zeroed C
     hipLaunchKernelGGL(zero_2d_kernel, dim3(grid1((int64_t)M * N, 256)), dim3(256), 0, s, M, N, c, ldc);
   hipLaunchKernelGGL(gemm_bf16_kernel, dim3(gx, gy, gz), dim3(256), 0, s, M, N, K, (const bf16*)a, sam, sak,
                      (const bf16*)bm, sbk, sbn, c, ldc, bias, accumulate ? 1 : 0, gz > 1 ? k_chunk : K);
   return hipGetLastError();
 }
 
+// out must hold zeros: the row chunks add their sums atomically
 hipError_t launch_colsum(int64_t M, int N, const void* x, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(fill_f32_kernel, dim3(grid1(N, 256)), dim3(256), 0, s, (int64_t)N, out, 0.0f);
   hipLaunchKernelGGL(colsum_kernel, dim3(grid1(N, 64), (unsigned)((M + COLSUM_ROWS - 1) / COLSUM_ROWS)), dim3(256), 0,
                      s, M, N, (const bf16*)x, out);
   return hipGetLastError();
@@ -510,25 +510,27 @@ hipError_t launch_surrogate_backward(const SurrogateBufs& w, int64_t B, const in
                                      float* loss_sum, hipStream_t s) {
   hipError_t e;
   float* g = w.grad;
+  // the whole gradient is cleared once: the bias column sums, the split-K
+  // weight gradients and the embedding scatter all add into it atomically
+  hipLaunchKernelGGL(fill_f32_kernel, dim3(grid1(w.n_params, 256)), dim3(256), 0, s, w.n_params, g, 0.0f);
   hipLaunchKernelGGL(loss_grad_kernel, dim3(grid1(B, 256)), dim3(256), 0, s, B, w.out, y, (bf16*)w.dout,
                      loss_sum);
   // layer 3: dW3 = dout^T h2, db3 = colsum(dout), dh2 = dout W3
-  if ((e = launch_gemm_bf16(2, HID, (int)B, w.dout, 1, 2, w.h2, HID, 1, g + w.oW3, HID, nullptr, false, s))) return e;
+  if ((e = launch_gemm_bf16(2, HID, (int)B, w.dout, 1, 2, w.h2, HID, 1, g + w.oW3, HID, nullptr, false, s, true))) return e;
   if ((e = launch_colsum(B, 2, w.dout, g + w.ob3, s))) return e;
   if ((e = launch_gemm_bf16((int)B, HID, 2, w.dout, 2, 1, w.W3_16, HID, 1, w.dh2, HID, nullptr, false, s))) return e;
   hipLaunchKernelGGL(gelu_bwd_round_kernel, dim3(grid1(B * HID, 256)), dim3(256), 0, s, B * HID, w.dh2, w.z2,
                      (bf16*)w.dz2);
   // layer 2
-  if ((e = launch_gemm_bf16(HID, HID, (int)B, w.dz2, 1, HID, w.h1, HID, 1, g + w.oW2, HID, nullptr, false, s))) return e;
+  if ((e = launch_gemm_bf16(HID, HID, (int)B, w.dz2, 1, HID, w.h1, HID, 1, g + w.oW2, HID, nullptr, false, s, true))) return e;
   if ((e = launch_colsum(B, HID, w.dz2, g + w.ob2, s))) return e;
   if ((e = launch_gemm_bf16((int)B, HID, HID, w.dz2, HID, 1, w.W2_16, HID, 1, w.dh1, HID, nullptr, false, s))) return e;
   hipLaunchKernelGGL(gelu_bwd_round_kernel, dim3(grid1(B * HID, 256)), dim3(256), 0, s, B * HID, w.dh1, w.z1,
                      (bf16*)w.dz1);
   // layer 1 and the embedding
-  if ((e = launch_gemm_bf16(HID, IN, (int)B, w.dz1, 1, HID, w.X16, IN, 1, g + w.oW1, IN, nullptr, false, s))) return e;
+  if ((e = launch_gemm_bf16(HID, IN, (int)B, w.dz1, 1, HID, w.X16, IN, 1, g + w.oW1, IN, nullptr, false, s, true))) return e;
   if ((e = launch_colsum(B, HID, w.dz1, g + w.ob1, s))) return e;
   if ((e = launch_gemm_bf16((int)B, IN, HID, w.dz1, HID, 1, w.W1_16, IN, 1, w.dX, IN, nullptr, false, s))) return e;
-  hipLaunchKernelGGL(fill_f32_kernel, dim3(grid1(w.nE, 256)), dim3(256), 0, s, w.nE, g, 0.0f);
   hipLaunchKernelGGL(scatter_embed_kernel, dim3(grid1(B * EMB, 256)), dim3(256), 0, s, B, rows, w.dX, g);
   return hipGetLastError();
 }
