@@ -473,10 +473,13 @@ hipError_t launch_gemm_bf16(int M, int N, int K, const void* a, int64_t sam, int
   if (M <= 0 || N <= 0) return hipSuccess;
   const unsigned gx = grid1(N, 64), gy = grid1(M, 64);
   // few output tiles and a long K (weight gradients over the batch): split K
+  // into chunks of at least 64 until about 256 workgroups fill the CUs
   unsigned gz = 1;
-  if (gx * gy < 128 && K >= 1024 && !accumulate) {
-    gz = (unsigned)((K + 255) / 256);
-    if (gz > 64) gz = 64;
+  if (gx * gy < 128 && K >= 256 && !accumulate) {
+    const unsigned by_k = (unsigned)((K + 255) / 256), by_cu = (256 + gx * gy - 1) / (gx * gy);
+    gz = by_k > by_cu ? by_k : by_cu;
+    const unsigned most = (unsigned)(K / 64) < 64 ? (unsigned)(K / 64) : 64;
+    if (gz > most) gz = most;
   }
   const int k_chunk = (int)(((K + (int)gz - 1) / (int)gz + 31) / 32 * 32);
   gz = (unsigned)((K + k_chunk - 1) / k_chunk);
