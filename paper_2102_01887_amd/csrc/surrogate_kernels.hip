@@ -231,6 +231,33 @@ __global__ __launch_bounds__(256) void colsum_kernel(int64_t M, int N, const bf1
                                                   part[3][threadIdx.x]);
 }
 
+// The same sum with 16-byte loads (N a multiple of 8, x 16-byte aligned):
+// 8 lanes cover a row's 64 columns, 32 rows at a time.
+__global__ __launch_bounds__(256) void colsum8_kernel(int64_t M, int N, const bf16* x, float* out) {
+  __shared__ float part[32][65];
+  const int cv = threadIdx.x & 7, q = threadIdx.x >> 3;
+  const int c0 = blockIdx.x * 64 + cv * 8;
+  const int64_t r0 = (int64_t)blockIdx.y * COLSUM_ROWS;
+  const int64_t r1 = r0 + COLSUM_ROWS < M ? r0 + COLSUM_ROWS : M;
+  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (c0 < N)  // N is a multiple of 8, so all 8 columns exist
+    for (int64_t m = r0 + q; m < r1; m += 32) {
+      const bf16x8 v = *reinterpret_cast<const bf16x8*>(x + m * N + c0);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[j] += (float)v[j];
+    }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) part[q][cv * 8 + j] = acc[j];
+  __syncthreads();
+  const int col = blockIdx.x * 64 + (int)threadIdx.x;
+  if (threadIdx.x < 64 && col < N) {
+    float t = 0.0f;
+#pragma unroll 8
+    for (int i = 0; i < 32; ++i) t += part[i][threadIdx.x];
+    atomicAdd(&out[col], t);
+  }
+}
+
 __global__ __launch_bounds__(256) void scatter_embed_kernel(int64_t B, const int32_t* rows, const float* dX,
                                                             float* dE) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -492,8 +519,11 @@ hipError_t launch_gemm_bf16(int M, int N, int K, const void* a, int64_t sam, int
 
 // out must hold zeros: the row chunks add their sums atomically
 hipError_t launch_colsum(int64_t M, int N, const void* x, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(colsum_kernel, dim3(grid1(N, 64), (unsigned)((M + COLSUM_ROWS - 1) / COLSUM_ROWS)), dim3(256), 0,
-                     s, M, N, (const bf16*)x, out);
+  const dim3 grid(grid1(N, 64), (unsigned)((M + COLSUM_ROWS - 1) / COLSUM_ROWS));
+  if (N % 8 == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0)
+    hipLaunchKernelGGL(colsum8_kernel, grid, dim3(256), 0, s, M, N, (const bf16*)x, out);
+  else
+    hipLaunchKernelGGL(colsum_kernel, grid, dim3(256), 0, s, M, N, (const bf16*)x, out);
   return hipGetLastError();
 }
 
