@@ -8,8 +8,13 @@
  *       weighted by reference-configuration latencies (Alg. 1, Sec. 4.1), and
  *   (2) the cheapest configuration of the operation whose latency is strictly
  *       below the slack of its own backend, by cost per item C/B, or the
- *       fastest configuration when none qualifies (Eq. 1, Sec. 4.2, with the
- *       fallback weight alpha taken as unbounded).
+ *       fastest configuration when none qualifies (Eq. 1, Sec. 4.2).  The
+ *       fallback is a rule of this library, not a limit of Eq. 1: Eq. 1
+ *       ranks a configuration that misses its slack by C/B plus a weighted
+ *       penalty that never names a value for the weight alpha, and as alpha
+ *       grows that ranking orders such configurations by L*R/(B*R_total), not
+ *       by L.  When none meets its slack this library takes the smallest L,
+ *       lowest index on ties; the finite-alpha objective is llama_decide_alpha.
  *
  * Units: latencies and times are int32 microseconds, costs int64 nano-dollars
  * per configuration run.  All arithmetic is integer, so results are exact.

@@ -393,6 +393,20 @@ class Problem:
         return decide(w.inv_op[sl], w.elapsed[sl], w.slo[sl], w.n_hw, Q, self.ref,
                       self.W(mode), w.cfg_off, w.hw, w.batch, w.lat, w.cost)
 
+    def decide_parallel(self, mode, threads, Q=None):
+        """decide() over every invocation on `threads` host threads: the
+        invocations are cut into that many contiguous parts and each part is
+        one single-threaded oracle call (ctypes releases the GIL), so the
+        result is the same as decide()'s."""
+        from concurrent.futures import ThreadPoolExecutor
+        n = self.w.n_inv
+        self.W(mode)
+        cuts = [n * k // threads for k in range(threads + 1)]
+        parts = [slice(cuts[k], cuts[k + 1]) for k in range(threads)]
+        with ThreadPoolExecutor(threads) as ex:
+            res = list(ex.map(lambda sl: self.decide(mode, Q, sl), parts))
+        return np.concatenate([r[0] for r in res]), np.concatenate([r[1] for r in res])
+
     def select(self, target, sl=slice(None)):
         w = self.w
         return select(w.inv_op[sl], target, w.n_hw, w.cfg_off, w.hw, w.batch,

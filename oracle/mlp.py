@@ -155,6 +155,36 @@ def loss_and_grads(p, rows, feat, y, emulate=True, tau=TAU):
     return loss, g
 
 
+def grad_magnitudes(p, rows, feat, y, emulate=True, tau=TAU):
+    """Per gradient element, the sum of the absolute values of the terms the
+    backward adds up for it: the same chain as loss_and_grads with every
+    factor replaced by its absolute value.  Any rounding of the terms (FP32
+    accumulation, one-ulp BF16 flips of an operand) changes a gradient element
+    by a fraction of this sum, so it scales element-wise tolerances; it is at
+    least |g| everywhere (triangle inequality)."""
+    r = bf16 if emulate else (lambda a: np.asarray(a, np.float64))
+    c = forward(p, rows, feat, emulate)
+    y = np.asarray(y, np.float64)
+    B = len(y)
+    out = c["out"]
+    dmu = 2.0 * (out[:, 0] - y) / B
+    dq = (((y - out[:, 1]) < 0).astype(np.float64) - tau) / B
+    a_out = np.abs(r(np.stack([dmu, dq], axis=1)))
+    m = {}
+    m["W3"] = a_out.T @ np.abs(c["h2"])
+    m["b3"] = a_out.sum(0)
+    a_z2 = (a_out @ np.abs(c["W3"])) * np.abs(gelu_grad(c["z2"]))
+    m["W2"] = a_z2.T @ np.abs(c["h1"])
+    m["b2"] = a_z2.sum(0)
+    a_z1 = (a_z2 @ np.abs(c["W2"])) * np.abs(gelu_grad(c["z1"]))
+    m["W1"] = a_z1.T @ np.abs(c["X"])
+    m["b1"] = a_z1.sum(0)
+    a_X = a_z1 @ np.abs(c["W1"])
+    m["E"] = np.zeros_like(p["E"])
+    np.add.at(m["E"], np.asarray(rows), a_X[:, :EMB])
+    return m
+
+
 # ---------------------------------------------------------------------------
 # AdamW (decoupled weight decay; decay on E, W1, W2, W3, not on biases)
 # ---------------------------------------------------------------------------

@@ -267,11 +267,6 @@ __global__ __launch_bounds__(256) void scatter_embed_kernel(int64_t B, const int
   atomicAdd(&dE[(int64_t)rows[m] * EMB + j], dX[m * IN + j]);
 }
 
-__global__ __launch_bounds__(256) void zero_2d_kernel(int M, int N, float* c, int64_t ldc) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < (int64_t)M * N) c[(e / N) * ldc + e % N] = 0.0f;
-}
-
 __global__ __launch_bounds__(256) void fill_f32_kernel(int64_t n, float* p, float v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -499,10 +494,13 @@ hipError_t launch_gemm_bf16(int M, int N, int K, const void* a, int64_t sam, int
                             hipStream_t s, bool c_zeroed) {
   if (M <= 0 || N <= 0) return hipSuccess;
   const unsigned gx = grid1(N, 64), gy = grid1(M, 64);
-  // few output tiles and a long K (weight gradients over the batch): split K
-  // into chunks of at least 64 until about 256 workgroups fill the CUs
+  // weight gradients over the batch (the only calls that pass a zeroed C):
+  // few output tiles and a long K, so K is split into chunks of at least 64
+  // until about 256 workgroups fill the CUs and the partial sums are added
+  // atomically.  Every other product (the forward, the input gradients) keeps
+  // one workgroup per tile, so its output does not depend on timing.
   unsigned gz = 1;
-  if (gx * gy < 128 && K >= 256 && !accumulate) {
+  if (c_zeroed && gx * gy < 128 && K >= 256 && !accumulate) {
     const unsigned by_k = (unsigned)((K + 255) / 256), by_cu = (256 + gx * gy - 1) / (gx * gy);
     gz = by_k > by_cu ? by_k : by_cu;
     const unsigned most = (unsigned)(K / 64) < 64 ? (unsigned)(K / 64) : 64;
@@ -510,8 +508,6 @@ hipError_t launch_gemm_bf16(int M, int N, int K, const void* a, int64_t sam, int
   }
   const int k_chunk = (int)(((K + (int)gz - 1) / (int)gz + 31) / 32 * 32);
   gz = (unsigned)((K + k_chunk - 1) / k_chunk);
-  if (gz > 1 && !c_zeroed)  // the split-K partial sums are added atomically into a zeroed C
-    hipLaunchKernelGGL(zero_2d_kernel, dim3(grid1((int64_t)M * N, 256)), dim3(256), 0, s, M, N, c, ldc);
   hipLaunchKernelGGL(gemm_bf16_kernel, dim3(gx, gy, gz), dim3(256), 0, s, M, N, K, (const bf16*)a, sam, sak,
                      (const bf16*)bm, sbk, sbn, c, ldc, bias, accumulate ? 1 : 0, gz > 1 ? k_chunk : K);
   return hipGetLastError();

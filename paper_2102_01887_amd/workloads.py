@@ -546,17 +546,6 @@ def c4_invocations(world, rng, n, slo=500_000):
     return w.with_invocations(inv_op, elapsed, np.full(n, slo, np.int32), name="c4-inference"), c
 
 
-def c4_truth_p95(world, inv_op, content):
-    """The simulator's true p95 latency (us) of every configuration of each
-    invocation's op: [n_inv, 64], ceil(exp(mean + 1.6448536 sigma))."""
-    w = world.w
-    rows = inv_op[:, None].astype(np.int64) * 64 + np.arange(64)[None, :]
-    op = inv_op[:, None]
-    mu = (np.log(w.lat[rows].astype(np.float64)) + world.a[op, w.hw[rows]] * np.log1p(content.n_obj[:, None])
-          + world.b[op] * np.log(content.px[:, None] / PX_720P))
-    return np.minimum(np.ceil(np.exp(mu + 1.6448536269514722 * world.sigma)), INT32_MAX).astype(np.int32)
-
-
 # ---------------------------------------------------------------------------
 # Configuration 5: serving (Poisson arrivals over 1,024 uneven pipelines)
 # ---------------------------------------------------------------------------

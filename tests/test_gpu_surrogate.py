@@ -5,8 +5,9 @@ Tolerances (floating point):
     and rounds the same activations to BF16 as the oracle (FP64), so the two
     differ only by accumulation order plus rare one-ulp BF16 rounding flips
     (2^-8 relative on one of 256 hidden units); |delta| <= 1e-2 absolute;
-  * gradients: relative Frobenius error <= 2e-2 per tensor (the backward adds
-    BF16 rounding points on gradients, where flips are likewise rare);
+  * gradients: element by element, in units of each element's sum of
+    |terms| M: every element within 2^-8 M (one BF16 ulp of the terms) and
+    all but 1% within 2^-14 M (see GRAD_RTOL_* below);
   * AdamW: FP32 against FP64 on the same gradients, 1e-5 relative;
   * fused inference: ln of the predicted latency within 1e-2 of the oracle's on
     rows both accept, the accept/fallback decision equal on >= 99% of rows, and
@@ -69,24 +70,54 @@ def test_forward_matches_oracle():
     assert err.max() <= 1e-2 and err.mean() <= 1e-4
 
 
-def test_gradients_match_oracle():
+# element-wise gradient bound, in units of the element's magnitude sum M (the
+# sum of |terms| that the backward adds for it, mlp.grad_magnitudes):
+#   every element        |g_gpu - g_oracle| <= GRAD_RTOL_MAX * M + GRAD_ATOL * max(M)
+#   all but GRAD_FRAC    |g_gpu - g_oracle| <= GRAD_RTOL_TYPICAL * M
+# FP32 accumulation of K terms errs by about sqrt(K) 2^-24 M; a one-ulp BF16
+# flip of an operand (dz, h) changes one term by 2^-8 of itself, so no element
+# can move by more than 2^-8 M, and in sums of many terms by far less.  A
+# dropped 64-row chunk or a wrong K slice of a split product moves a whole
+# tile by about sqrt(64) terms, i.e. 2^-9..2^-7 of M at these batch sizes,
+# which the second bound rejects.
+GRAD_RTOL_MAX = 2.0 ** -8
+GRAD_ATOL = 1e-7
+GRAD_RTOL_TYPICAL = 2.0 ** -14
+GRAD_FRAC = 0.01
+
+
+@pytest.mark.parametrize("n", [100, 2048, 3001])
+def test_gradients_match_oracle(n):
+    """Gradients element by element against the FP64 oracle at batch sizes
+    that take the unsplit products (100), whole 64-row chunks (2048) and a
+    ragged tail (3001).  Targets within 5e-3 of the oracle's predicted p95 are
+    moved 1e-2 above it: the pinball loss has a kink at y = q, where its
+    gradient jumps by 1/B and any rounding decides the side."""
     torch, world, L = setup_world()
     L.surrogate_init(seed=12, mean_log_latency=10.5)
     P = mlp.unflatten(L.surrogate_get().astype(np.float64), world.w.n_cfg)
-    rng = np.random.default_rng(1)
-    n = 2048
+    rng = np.random.default_rng(1 + n)
     rows, c, y = wl.simulate_c4(world, rng, n)
+    feat = c.feat.astype(np.float64)
+    q = mlp.forward(P, rows, feat)["out"][:, 1]
+    near = np.abs(y.astype(np.float64) - q) < 5e-3
+    y = np.where(near, (q + 1e-2).astype(np.float32), y).astype(np.float32)
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
     L.surrogate_train_step(dev(torch, rows), feat_dev(torch, c.feat), dev(torch, y), lr=0.0,
                            update=False, loss_sum=loss)
     torch.cuda.synchronize()
     g_gpu = mlp.unflatten(L.surrogate_grads().astype(np.float64), world.w.n_cfg)
-    l_or, g_or = mlp.loss_and_grads(P, rows, c.feat.astype(np.float64), y.astype(np.float64))
-    assert abs(loss.item() / n - l_or) <= 1e-3 * max(1.0, abs(l_or))
+    l_or, g_or = mlp.loss_and_grads(P, rows, feat, y.astype(np.float64))
+    mag = mlp.grad_magnitudes(P, rows, feat, y.astype(np.float64))
+    assert abs(loss.item() / n - l_or) <= 1e-5 * max(1.0, abs(l_or))
     for k in mlp.NAMES:
-        rel = np.linalg.norm(g_gpu[k] - g_or[k]) / max(np.linalg.norm(g_or[k]), 1e-30)
-        say(f"grad {k}: relative error {rel:.2e}")
-        assert rel <= 2e-2, k
+        d = np.abs(g_gpu[k] - g_or[k])
+        M = mag[k]
+        ratio = d / np.maximum(M, 1e-300)
+        say(f"grad {k} (B={n}): max |d|/M {ratio.max():.2e}, 99th pct {np.quantile(ratio, 0.99):.2e}, "
+            f"above 2^-14: {np.mean(d > GRAD_RTOL_TYPICAL * M):.4f}")
+        assert np.all(d <= GRAD_RTOL_MAX * M + GRAD_ATOL * M.max()), k
+        assert np.mean(d > GRAD_RTOL_TYPICAL * M) <= GRAD_FRAC, k
 
 
 def test_adamw_step_matches_oracle():

@@ -147,3 +147,25 @@ def test_select_lat_matches_select_for_constant_rows():
     a = oracle.select_lat(w.inv_op, t, w.n_hw, w.cfg_off, w.hw, w.batch, lat_rows, w.cost)
     b = P.select(t)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_grad_magnitudes_bound_the_gradients():
+    """The magnitude sums are at least |g| for every element and equal |g|
+    where every term has one sign (a single row, one sample per embedding
+    row, all-positive weights and inputs in the last layer)."""
+    rng = np.random.default_rng(7)
+    n_rows = 6
+    p = small_params(rng, n_rows)
+    rows = rng.integers(0, n_rows, 40)
+    feat = rng.uniform(0, 1, (40, mlp.FEAT))
+    y = rng.uniform(1.0, 3.5, 40)
+    _, g = mlp.loss_and_grads(p, rows, feat, y)
+    mag = mlp.grad_magnitudes(p, rows, feat, y)
+    for k in mlp.NAMES:
+        assert mag[k].shape == g[k].shape
+        assert np.all(mag[k] >= np.abs(g[k]) * (1 - 1e-12)), k
+    # one sample: the last layer's terms are single products, so equality
+    _, g1 = mlp.loss_and_grads(p, rows[:1], feat[:1], y[:1])
+    m1 = mlp.grad_magnitudes(p, rows[:1], feat[:1], y[:1])
+    for k in ("W3", "b3"):
+        assert np.allclose(m1[k], np.abs(g1[k]), rtol=1e-12, atol=0), k

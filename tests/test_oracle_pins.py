@@ -311,3 +311,14 @@ def test_relabelling_ops_leaves_targets_unchanged():
                          perm[w.inv_op].astype(np.int32), w.elapsed, w.slo)
         for mode in (PAPER, PROB):
             assert np.array_equal(oracle.Problem(w).targets(mode), oracle.Problem(w2).targets(mode))
+
+
+def test_parallel_decide_equals_single_threaded():
+    """The host-threaded oracle leg (used to time the oracle on every host
+    core) returns exactly the single-threaded decisions."""
+    w = wl.make_c2(seed=5, n_pipelines=8, n_inv=20_001)
+    P = oracle.Problem(w)
+    for mode in (oracle.PAPER, oracle.PROB):
+        c1, f1 = P.decide(mode)
+        c4, f4 = P.decide_parallel(mode, 4)
+        assert np.array_equal(c1, c4) and np.array_equal(f1, f4)
