@@ -557,7 +557,7 @@ def main():
         dst = torch.empty_like(src)
         dst.copy_(src)
         for _ in range(5):
-            L.relax()
+            L.relax(modes=1)
             L.decide(op, el, slo)
         torch.cuda.synchronize()
         print(json.dumps({"pmc_pass": args.workload, "copy_bytes": src.numel() * 4,
@@ -576,7 +576,8 @@ def main():
     s = torch.cuda.Stream()
 
     def relax():
-        L.relax(stream=s)
+        # W for both slack modes; thresholds for the mode the step decides in
+        L.relax(stream=s, modes=1 << mode)
 
     def decide(scan):
         return lambda: L.decide(op, el, slo, None, mode, scan, cfg, flag, stream=s)

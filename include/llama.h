@@ -182,6 +182,19 @@ int llama_set_profiles(llama_ctx *ctx, int32_t n_ops, int32_t n_hw,
 int llama_relax(llama_ctx *ctx, void *stream);
 
 /*
+ * llama_relax for the slack modes in `modes` only (bit m = LLAMA_SLACK_*
+ * value m: 1 = PAPER, 2 = PROB, 3 = both, the same as llama_relax).  W is
+ * relaxed for both modes; the thresholds are rebuilt only for the modes
+ * asked for, so a caller that decides in one mode halves the relaxation's
+ * record writes.  Until the next relaxation, the record-reading calls
+ * (llama_decide in the INDEXED/AUTO mode without a queue vector,
+ * llama_decide_batching without one, llama_serve_open in the plain form)
+ * return LLAMA_E_STATE for a mode left out; the other calls read W directly
+ * and are unaffected.  LLAMA_E_ARG for a mask outside 1..3.
+ */
+int llama_relax_modes(llama_ctx *ctx, int32_t modes, void *stream);
+
+/*
  * Replace the profiled latency of every configuration (for example after
  * feedback, Sec. 3.3 Manager) without changing the table's shape; host
  * pointer [n_cfg], same bounds as in llama_set_profiles.  Rebuilds the

@@ -36,7 +36,8 @@ EXPORTS = ["llama_create", "llama_destroy", "llama_last_error", "llama_set_dag",
            "llama_surrogate_fit", "llama_select_rows", "llama_serve_bytes_per_request",
            "llama_serve_open", "llama_serve_submit", "llama_serve_poll", "llama_serve_stats_get",
            "llama_serve_close", "llama_autotune", "llama_set_schedule", "llama_queue_time", "llama_set_alpha",
-           "llama_decide_alpha", "llama_feedback", "llama_affinity", "llama_decide_batching"]
+           "llama_decide_alpha", "llama_feedback", "llama_affinity", "llama_decide_batching",
+           "llama_relax_modes"]
 
 
 class LlamaStats(ctypes.Structure):
@@ -79,6 +80,7 @@ def load_library(path=LIB_PATH):
         "llama_set_dag": [p, i32, p, p, p, p],
         "llama_set_profiles": [p, i32, i32, p, p, p, p, p, p, p, p],
         "llama_relax": [p, p],
+        "llama_relax_modes": [p, i32, p],
         "llama_update_latencies": [p, p],
         "llama_targets": [p, i64, p, p, p, p, i32, p, p],
         "llama_select": [p, i64, p, p, p, p, p],
@@ -250,8 +252,13 @@ class Llama:
     def reserve(self, max_inv):
         self._check("llama_reserve", self._L.llama_reserve(self._ctx, int(max_inv)))
 
-    def relax(self, stream=None):
-        self._check("llama_relax", self._L.llama_relax(self._ctx, _stream(stream)))
+    def relax(self, stream=None, modes=3):
+        """Relaxation; `modes` = bit mask of the slack modes whose records are
+        rebuilt (3 = both, llama_relax)."""
+        if modes == 3:
+            self._check("llama_relax", self._L.llama_relax(self._ctx, _stream(stream)))
+        else:
+            self._check("llama_relax_modes", self._L.llama_relax_modes(self._ctx, int(modes), _stream(stream)))
 
     # -- decisions (device tensors) --------------------------------------------
     def targets(self, op, elapsed, slo, queue=None, mode=SLACK_PAPER, out=None, stream=None):

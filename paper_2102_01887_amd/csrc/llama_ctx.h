@@ -71,6 +71,7 @@ struct llama_ctx {
   // relaxation can overlap the decisions of the batch before it.
   DevBuf d_rec[2], d_rec_tail[2], d_rec_tail2[2], d_ovf[2];
   int rec_cur = 0;  // set written by the latest relaxation
+  int rec_modes[2] = {3, 3};  // slack modes (bit m = mode m) whose records each set holds
   DevBuf d_mst, d_mst_n;
   DevBuf d_cfg_off, d_cfg_hw, d_cfg_lat, d_cfg_key, d_cfg_q, d_cfg_batch;
   std::vector<int64_t> res_total;  // [n_hw] or empty
@@ -198,5 +199,7 @@ int build_alpha_tables(llama_ctx* c);
 // after device-side feedback
 int pull_profiles(llama_ctx* c);
 // Relaxation into the record set not written last (then decisions use it).
-hipError_t relax_next(llama_ctx* c, hipStream_t s);
+hipError_t relax_next(llama_ctx* c, hipStream_t s, int modes = 3);
+// Whether the current record set holds the records of slack mode `mode`.
+inline bool records_current(const llama_ctx* c, int mode) { return (c->rec_modes[c->rec_cur] >> mode) & 1; }
 }  // namespace llama

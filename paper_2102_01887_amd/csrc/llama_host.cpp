@@ -89,10 +89,13 @@ int sync_ctx(llama_ctx* c, const char* what) {
   return LLAMA_OK;
 }
 
-hipError_t relax_next(llama_ctx* c, hipStream_t s) {
+hipError_t relax_next(llama_ctx* c, hipStream_t s, int modes) {
   const int set = 1 - c->rec_cur;
-  hipError_t e = launch_relax(c->tables_for(set), s);
-  if (e == hipSuccess) c->rec_cur = set;
+  hipError_t e = launch_relax(c->tables_for(set), modes, s);
+  if (e == hipSuccess) {
+    c->rec_cur = set;
+    c->rec_modes[set] = modes;
+  }
   return e;
 }
 
@@ -428,11 +431,14 @@ int llama_update_latencies(llama_ctx* c, const int32_t* lat) {
   return LLAMA_OK;
 }
 
-int llama_relax(llama_ctx* c, void* stream) {
+int llama_relax(llama_ctx* c, void* stream) { return llama_relax_modes(c, 3, stream); }
+
+int llama_relax_modes(llama_ctx* c, int32_t modes, void* stream) {
   int rc = enter(c);
   if (rc) return rc;
   if (!c->has_prof) return fail(c, LLAMA_E_STATE, "relax: no profiles");
-  hipError_t e = llama::relax_next(c, (hipStream_t)stream);
+  if (modes < 1 || modes > 3) return fail(c, LLAMA_E_ARG, "relax_modes: mode mask %d is not 1, 2 or 3", modes);
+  hipError_t e = llama::relax_next(c, (hipStream_t)stream, modes);
   if (e != hipSuccess) return hip_fail(c, e, "relax launch");
   return LLAMA_OK;
 }
@@ -519,17 +525,20 @@ int build_tables(llama_ctx* c) {
   std::vector<int32_t> mst_n(n_ops, 0);
   for (int v = 0; v < n_ops; ++v) mst_n[v] = (int32_t)merged[v].size();
   std::vector<uint2> mst(c->n_cfg);
-  std::vector<uint4> rec_hot((size_t)2 * n_ops), rec_tail((size_t)2 * n_ops * 3), rec_tail2((size_t)2 * n_ops * 4);
+  std::vector<uint4> rec_hot((size_t)2 * n_ops), rec_tail((size_t)2 * n_ops * llama::REC_TAIL_VECS),
+      rec_tail2((size_t)2 * n_ops * llama::REC_TAIL2_VECS);
   for (int v = 0; v < n_ops; ++v) {
     const int n = (int)merged[v].size();
     for (int j = 0; j < n; ++j) {
       mst[c->cfg_off[v] + j] = merged[v][j];
     }
     uint32_t w[llama::REC_WORDS] = {0};
-    w[0] = (uint32_t)n | ((uint32_t)c->fastest[v] << 16);
+    // thresholds (and the code of the smallest) are written by the GPU after relaxation
+    w[0] = (uint32_t)c->fastest[v] | (0xFFFFu << 16);
+    w[llama::REC_N_WORD] = (uint32_t)n;
     for (int slot = 0; slot < llama::REC_SLOTS; ++slot) {
       const int j = n - 1 - slot;
-      w[llama::rec_u_word(slot)] = 0x7FFFFFFFu;  // thresholds: written by the GPU after relaxation
+      w[llama::rec_u_word(slot)] = 0x7FFFFFFFu;
       const uint32_t k = j >= 0 ? (merged[v][j].y & 0xFFFFu) : 0u;
       w[llama::rec_k_word(slot)] |= k << llama::rec_k_shift(slot);
     }
@@ -576,8 +585,8 @@ int build_tables(llama_ctx* c) {
       (rc = upload(c, c->d_ovf[0], nullptr, sizeof(uint2) * 2 * (size_t)pos, "record overflow")) ||
       (rc = upload(c, c->d_ovf[1], nullptr, sizeof(uint2) * 2 * (size_t)pos, "record overflow")) ||
       (rc = upload(c, c->d_rec_q, nullptr, sizeof(uint4) * (size_t)n_ops, "records (queue)")) ||
-      (rc = upload(c, c->d_rec_tail_q, nullptr, sizeof(uint4) * 3 * (size_t)n_ops, "record tails (queue)")) ||
-      (rc = upload(c, c->d_rec_tail2_q, nullptr, sizeof(uint4) * 4 * (size_t)n_ops, "record second tails (queue)")) ||
+      (rc = upload(c, c->d_rec_tail_q, nullptr, sizeof(uint4) * llama::REC_TAIL_VECS * (size_t)n_ops, "record tails (queue)")) ||
+      (rc = upload(c, c->d_rec_tail2_q, nullptr, sizeof(uint4) * llama::REC_TAIL2_VECS * (size_t)n_ops, "record second tails (queue)")) ||
       (rc = upload(c, c->d_ovf_q, nullptr, sizeof(uint2) * (size_t)pos, "record overflow (queue)")) ||
       (rc = upload_vec(c, c->d_seg_off, seg_off, "seg_off")) ||
       (rc = upload_vec(c, c->d_cfg_off, c->cfg_off, "cfg_off")) ||
@@ -688,6 +697,8 @@ int llama_decide(llama_ctx* c, int64_t n, const int32_t* op, const int32_t* elap
   } else if (scan == LLAMA_SCAN_WAVE) {
     e = llama::launch_decide_wave(c->tables(), b, (hipStream_t)stream);
   } else {
+    if (!queue && !llama::records_current(c, mode))
+      return fail(c, LLAMA_E_STATE, "decide: the last relaxation left out the records of slack mode %d (llama_relax_modes)", mode);
     e = llama::launch_decide_indexed(c->tables(), b, (hipStream_t)stream);
   }
   if (e != hipSuccess) return hip_fail(c, e, "decide launch");
@@ -727,7 +738,8 @@ int llama_autotune(llama_ctx* c, int64_t n, const int32_t* op, const int32_t* el
   for (size_t ci = 0; ci < cands.size(); ++ci) {
     c->decide_sched = cands[ci];
     llama::Batch bt{};
-    bt.n = n; bt.op = op; bt.elapsed = elapsed; bt.slo = slo; bt.cfg = cfg_scratch; bt.mode = LLAMA_SLACK_PAPER;
+    bt.n = n; bt.op = op; bt.elapsed = elapsed; bt.slo = slo; bt.cfg = cfg_scratch;
+    bt.mode = llama::records_current(c, LLAMA_SLACK_PAPER) ? LLAMA_SLACK_PAPER : LLAMA_SLACK_PROB;
     hipError_t e = llama::launch_decide_indexed(c->tables(), bt, s);  // warm-up
     if (e == hipSuccess) e = hipEventRecord(a, s);
     for (int r = 0; r < 10 && e == hipSuccess; ++r) e = llama::launch_decide_indexed(c->tables(), bt, s);

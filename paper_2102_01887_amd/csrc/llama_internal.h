@@ -12,43 +12,66 @@ constexpr uint32_t THR_NEVER = 0xFFFFFFFFu;  // remaining-time threshold never m
 constexpr int MAX_HW = 8;
 constexpr uint32_t DEVERR_QUEUE_ENTRY = 2u;  // device error bit: queued entry out of range
 
-// Per-op decision record (128 bytes).  The op's frontier over all backends in
-// remaining-time space: entries {T, k} such that configuration k (local index)
-// is feasible for an invocation iff slo - elapsed >= T, with T strictly
-// increasing and the configuration's cost key strictly decreasing along the
-// frontier.  The record keeps the REC_SLOTS entries with the largest T (the
-// cheapest configurations, which most invocations can afford), in descending
-// T order, thresholds stored as U = T - 1 (feasible iff U < slo - elapsed):
-//   word 0        entry count n (low 16 bits) | fastest configuration << 16
-//   words 1, 2    U of slots 0 and 1 (slot 0 = largest T)
-//   word 3        k of slots 0 and 1 (16-bit halves)
-//   words 4..11   U of slots 2..9
-//   words 12..15  k of slots (2j, 2j+1), j = 1..4
-//   words 16..25  U of slots 10..19
-//   words 26..30  k of slots (2j, 2j+1), j = 5..9; word 31 unused
-// The first 16 bytes alone decide every invocation that can afford one of
-// the two cheapest entries, so records are stored as three arrays: the hot
-// words 0..3 (one uint4 per op), the tail words 4..15 (three uint4 per op)
-// and the second tail, words 16..31 (four uint4 per op), written and read
-// only for ops with more than 10 entries.  The entries past the record (the
-// n - REC_SLOTS smallest T), ascending in T, are in the overflow array at
-// [hdr offset of the op, + n - REC_SLOTS); the decision reads them only when
-// no slot is feasible.
-constexpr int REC_WORDS = 32;
-constexpr int REC_SLOTS = 20;
-constexpr int REC_SLOTS_TAIL = 10;  // slots in the hot words and the first tail
-__host__ __device__ inline constexpr int rec_u_word(int slot) {
-  return slot < 2 ? 1 + slot : slot < REC_SLOTS_TAIL ? slot + 2 : slot + 6;
-}
+// Per-op decision record (112 bytes in three arrays).  The op's frontier
+// over all backends in remaining-time space: entries {T, k} such that
+// configuration k (local index) is feasible for an invocation iff
+// slo - elapsed >= T, with T strictly increasing and the configuration's cost
+// key strictly decreasing along the frontier.  The record keeps the REC_SLOTS
+// entries with the largest T (the cheapest configurations, which most
+// invocations can afford), in descending T order, thresholds stored as
+// U = T - 1 (feasible iff U < slo - elapsed; U = 2^31 - 1 for an unused slot
+// never is):
+//   hot, 16 bytes (one uint4 per op):
+//     word 0        fastest configuration (low 16 bits) | rec_floor_code of
+//                   the smallest U of the whole frontier (high 16 bits)
+//     words 1, 2    U of slots 0 and 1 (slot 0 = largest T)
+//     word 3        k of slots 0 and 1 (16-bit halves)
+//   tail, 32 bytes (two uint4 per op, one 32-byte sector):
+//     word 4        entry count n (low 16 bits) | k of slot 2
+//     words 5, 6    k of slots (3, 4) and (5, 6)
+//     words 7..11   U of slots 2..6
+//   second tail, 64 bytes (four uint4 per op), written and read only for ops
+//   with more than REC_SLOTS_TAIL entries:
+//     words 12..21  U of slots 7..16
+//     words 22..26  k of slots (7, 8) ... (15, 16); word 27 unused
+// The hot words alone decide every invocation that can afford one of the two
+// cheapest entries, and every invocation that can afford none (slo - elapsed
+// at or below the rounded-down smallest U: the fastest configuration, flag
+// 0).  The entries past the record (the n - REC_SLOTS smallest T), ascending
+// in T, are in the overflow array at [hdr offset of the op, + n - REC_SLOTS);
+// the decision reads them only when no slot is feasible.
+constexpr int REC_WORDS = 28;
+constexpr int REC_SLOTS = 17;
+constexpr int REC_SLOTS_TAIL = 7;   // slots in the hot words and the first tail
+constexpr int REC_TAIL_VECS = 2;    // uint4 per record in the tail array
+constexpr int REC_TAIL2_VECS = 4;   // uint4 per record in the second-tail array
+constexpr int REC_N_WORD = 4;       // word holding the entry count (low half)
+__host__ __device__ inline constexpr int rec_u_word(int slot) { return slot < 2 ? 1 + slot : slot + 5; }
 __host__ __device__ inline constexpr int rec_k_word(int slot) {
-  return slot < 2 ? 3 : slot < REC_SLOTS_TAIL ? 12 + (slot - 2) / 2 : 26 + (slot - REC_SLOTS_TAIL) / 2;
+  return slot < 2 ? 3 : slot < REC_SLOTS_TAIL ? 4 + (slot - 1) / 2 : 22 + (slot - REC_SLOTS_TAIL) / 2;
 }
-__host__ __device__ inline constexpr int rec_k_shift(int slot) { return 16 * (slot & 1); }
+__host__ __device__ inline constexpr int rec_k_shift(int slot) {
+  return slot < 2 ? 16 * (slot & 1) : 16 * ((slot + 1) & 1);
+}
 // Address of word w of record r (r = mode * n_ops + op) in the three arrays.
 __host__ __device__ inline uint32_t* rec_word(uint4* hot, uint4* tail, uint4* tail2, int64_t r, int w) {
   return w < 4 ? reinterpret_cast<uint32_t*>(hot + r) + w
-         : w < 16 ? reinterpret_cast<uint32_t*>(tail + r * 3) + (w - 4)
-                  : reinterpret_cast<uint32_t*>(tail2 + r * 4) + (w - 16);
+         : w < 12 ? reinterpret_cast<uint32_t*>(tail + r * REC_TAIL_VECS) + (w - 4)
+                  : reinterpret_cast<uint32_t*>(tail2 + r * REC_TAIL2_VECS) + (w - 12);
+}
+// 16-bit code of a stored threshold, rounded down: for u >= 0, an 11-bit
+// mantissa m and a shift e with m << e <= u < (m + 1) << e; 0xFFFF (value
+// INT32_MIN) for u < 0.  rec_code_value(rec_floor_code(u)) <= u for every u,
+// so "slo - elapsed <= value" proves that no entry is feasible.
+__host__ __device__ inline uint32_t rec_floor_code(int32_t u) {
+  if (u < 0) return 0xFFFFu;
+  const uint32_t x = (uint32_t)u;
+  const int bits = 32 - __builtin_clz(x | 1u);
+  const int e = bits > 11 ? bits - 11 : 0;
+  return ((uint32_t)e << 11) | (x >> e);
+}
+__host__ __device__ inline int32_t rec_code_value(uint32_t c) {
+  return c == 0xFFFFu ? INT32_MIN : (int32_t)((c & 0x7FFu) << (c >> 11));
 }
 
 // Schedules of the indexed decision (chosen by llama_autotune): 1, 2 or 4
@@ -100,12 +123,12 @@ struct DevTables {
   const uint2* mst;          // [n_cfg] {L, key}, per op ascending in L from cfg_off[v]
   const int32_t* mst_n;      // [n_ops] entries of each op's merged frontier
   uint4* rec;                // [2*n_ops] record words 0..3, PAPER then PROB, queue = 0
-  uint4* rec_tail;           // [2*n_ops*3] record words 4..15
-  uint4* rec_tail2;          // [2*n_ops*4] record words 16..31
+  uint4* rec_tail;           // [2*n_ops*REC_TAIL_VECS] record words 4..11
+  uint4* rec_tail2;          // [2*n_ops*REC_TAIL2_VECS] record words 12..27
   uint2* ovf;                // [2*n_front] full frontiers {T, key} ascending, PAPER then PROB
   uint4* rec_q;              // [n_ops] records for a per-call queueing-time vector
-  uint4* rec_tail_q;         // [n_ops*3]
-  uint4* rec_tail2_q;        // [n_ops*4]
+  uint4* rec_tail_q;         // [n_ops*REC_TAIL_VECS]
+  uint4* rec_tail2_q;        // [n_ops*REC_TAIL2_VECS]
   uint2* ovf_q;              // [n_front]
   const int32_t* cfg_off;    // [n_ops+1] caller-order configuration rows of each op
   const int32_t* cfg_hw;     // [n_cfg] backend, caller order
@@ -157,7 +180,9 @@ struct Batch {
   int32_t mode;              // 0 = PAPER, 1 = PROB
 };
 
-hipError_t launch_relax(const DevTables& t, hipStream_t s);
+// modes: bit m set = rebuild the decision records of slack mode m (W is
+// always relaxed for both modes).
+hipError_t launch_relax(const DevTables& t, int modes, hipStream_t s);
 // Build records for modes [mode0, mode0 + n_modes) into rec/rec_tail/
 // rec_tail2/ovf (consecutive per-mode blocks of n_ops, 3*n_ops, 4*n_ops uint4
 // and n_front uint2).

@@ -220,7 +220,12 @@ __device__ __forceinline__ void write_op_records(const DevTables& t, int v, cons
   uint32_t w[REC_WORDS];
 #pragma unroll
   for (int k = 0; k < REC_WORDS; ++k) w[k] = 0;
-  w[0] = (uint32_t)n | (st.fastest << 16);
+  // smallest U of the frontier: its fastest entry, the last slot when the
+  // frontier ends inside the record (unused slots load entry 0), else the
+  // first overflow entry
+  const uint32_t u_last = n > REC_SLOTS ? Ux[0] : Us[REC_SLOTS - 1];
+  w[0] = st.fastest | (rec_floor_code((int32_t)u_last) << 16);
+  w[REC_N_WORD] = (uint32_t)n;
 #pragma unroll
   for (int slot = 0; slot < REC_SLOTS; ++slot) {
     const bool used = slot < n;
@@ -229,16 +234,15 @@ __device__ __forceinline__ void write_op_records(const DevTables& t, int v, cons
   }
   const int64_t r = (int64_t)mode * t.n_ops + v;
   t.rec[r] = make_uint4(w[0], w[1], w[2], w[3]);
-  uint4* tl = t.rec_tail + r * 3;
+  uint4* tl = t.rec_tail + r * REC_TAIL_VECS;
   tl[0] = make_uint4(w[4], w[5], w[6], w[7]);
   tl[1] = make_uint4(w[8], w[9], w[10], w[11]);
-  tl[2] = make_uint4(w[12], w[13], w[14], w[15]);
   if (n > REC_SLOTS_TAIL) {
-    uint4* t2 = t.rec_tail2 + r * 4;
-    t2[0] = make_uint4(w[16], w[17], w[18], w[19]);
-    t2[1] = make_uint4(w[20], w[21], w[22], w[23]);
-    t2[2] = make_uint4(w[24], w[25], w[26], w[27]);
-    t2[3] = make_uint4(w[28], w[29], w[30], w[31]);
+    uint4* t2 = t.rec_tail2 + r * REC_TAIL2_VECS;
+    t2[0] = make_uint4(w[12], w[13], w[14], w[15]);
+    t2[1] = make_uint4(w[16], w[17], w[18], w[19]);
+    t2[2] = make_uint4(w[20], w[21], w[22], w[23]);
+    t2[3] = make_uint4(w[24], w[25], w[26], w[27]);
   }
   // entries past the record, ascending: the prefetched ones, then four
   // loads in flight at a time
@@ -345,7 +349,7 @@ __device__ __forceinline__ void relax_levels(uint64_t* sAccP, uint64_t* sAccQ, c
 // current level's maxima are applied; LDS operations of one wavefront take
 // effect in order, so wavefront-scope fences separate staging and levels.
 template <bool RECORDS>
-__global__ __launch_bounds__(128) void relax_kernel(DevTables t) {
+__global__ __launch_bounds__(128) void relax_kernel(DevTables t, int modes) {
   extern __shared__ uint64_t sDyn[];
   const int cap_ops = t.relax_ops, cap_edges = t.relax_edges, cap_lvls = t.relax_lvls;
   // W[v] = ref[v] + acc[v]: acc is the largest successor term, built level by
@@ -429,7 +433,7 @@ __global__ __launch_bounds__(128) void relax_kernel(DevTables t) {
         if (wave == 0) st = sSt[lane];
         const int64_t W = sRef[lane] + (int64_t)(wave ? sAccQ[lane] : sAccP[lane]);
         t.W[(int64_t)wave * n_ops + a + lane] = W;
-        write_op_records(t, a + lane, st, sRef[lane], W, wave);
+        if ((modes >> wave) & 1) write_op_records(t, a + lane, st, sRef[lane], W, wave);
       }
     } else {
       for (int i = tid; i < n; i += bs) {
@@ -457,15 +461,18 @@ __global__ __launch_bounds__(128) void relax_kernel(DevTables t) {
     }
     __syncthreads();
   }
-  if (RECORDS && lane < n)
+  if (RECORDS && lane < n && ((modes >> wave) & 1))
     write_op_records(t, a + lane, st, t.ref[a + lane], t.W[(int64_t)wave * n_ops + a + lane], wave);
 }
 
-// One thread per (op, slack mode): its records from the relaxed W.
-__global__ __launch_bounds__(256) void op_records_kernel(DevTables t) {
+// One thread per (op, slack mode) for both modes (modes = 3), else one
+// thread per op for the one mode asked for: its records from the relaxed W.
+__global__ __launch_bounds__(256) void op_records_kernel(DevTables t, int modes) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= 2 * (int64_t)t.n_ops) return;
-  const int v = (int)(i >> 1), mode = (int)(i & 1);
+  const bool both = modes == 3;
+  if (i >= (both ? 2 : 1) * (int64_t)t.n_ops) return;
+  const int v = both ? (int)(i >> 1) : (int)i;
+  const int mode = both ? (int)(i & 1) : (modes >> 1);
   const OpStatic st = load_op_static(t, v);
   write_op_records(t, v, st, t.ref[v], t.W[(int64_t)mode * t.n_ops + v], mode);
 }
@@ -511,7 +518,7 @@ __device__ __forceinline__ void build_record(const DevTables& t, int v, int mode
                                              uint4* rec_hot, uint4* rec_tail, uint4* rec_tail2, int64_t rec_index, uint2* ovf,
                                              int64_t* sT, uint32_t* sK,
                                              int32_t* sC, uint32_t* sSlotT, uint32_t* sSlotK,
-                                             int32_t* sN) {
+                                             int32_t* sN, uint32_t* sLast) {
   const int lane = threadIdx.x;
   const int32_t* hdr = t.hdr + (int64_t)v * t.hs;
   int off[NHW + 1];
@@ -594,6 +601,7 @@ __device__ __forceinline__ void build_record(const DevTables& t, int v, int mode
       }
       const int32_t Tc = stored_threshold(Tj);
       ovf[base + pos] = make_uint2((uint32_t)Tc, Kj);
+      if (pos == 0) *sLast = (uint32_t)Tc;
       const int slot = n - 1 - pos;
       if (slot < REC_SLOTS) {
         sSlotT[slot] = (uint32_t)Tc;
@@ -644,13 +652,17 @@ __device__ __forceinline__ void build_record(const DevTables& t, int v, int mode
       sSlotT[s] = f.x;
       sSlotK[s] = f.y & 0xFFFFu;
     }
+    if (n > 0) *sLast = ovf[base].x;
     *sN = n;
   }
   __syncthreads();
   if (lane < REC_WORDS) {
     const int n = *sN;
     uint32_t word = 0;
-    if (lane == 0) word = (uint32_t)n | ((uint32_t)hdr[NHW + 1] << 16);
+    // with no entry at all, every invocation falls back: the largest code
+    const uint32_t u_last = n > 0 ? *sLast : 0x7FFFFFFFu;
+    if (lane == 0) word = (uint32_t)hdr[NHW + 1] | (rec_floor_code((int32_t)u_last) << 16);
+    if (lane == REC_N_WORD) word = (uint32_t)n;
 #pragma unroll
     for (int slot = 0; slot < REC_SLOTS; ++slot) {
       if (lane == rec_u_word(slot)) word = slot < n ? sSlotT[slot] : 0x7FFFFFFFu;
@@ -671,10 +683,11 @@ __global__ __launch_bounds__(64) void records_kernel(DevTables t, int mode0, int
   __shared__ int32_t sC[REC_LDS];
   __shared__ uint32_t sSlotT[REC_SLOTS], sSlotK[REC_SLOTS];
   __shared__ int32_t sN;
+  __shared__ uint32_t sLast;
   const int v = blockIdx.x;
   for (int m = 0; m < n_modes; ++m)
     build_record<NHW>(t, v, mode0 + m, queue, rec_all, tail_all, tail2_all, (int64_t)m * t.n_ops + v,
-                      ovf_all + (int64_t)m * t.n_front, sT, sK, sC, sSlotT, sSlotK, &sN);
+                      ovf_all + (int64_t)m * t.n_front, sT, sK, sC, sSlotT, sSlotK, &sN, &sLast);
 }
 
 __device__ __forceinline__ bool invalid_invocation(int v, int e, int s, int n_ops) {
@@ -766,24 +779,21 @@ __global__ __launch_bounds__(256) void select_indexed_kernel(DevTables t, Batch 
 // the record.
 // ---------------------------------------------------------------------------
 
-// Choice from a record: the first feasible slot in descending-T order (the
-// cheapest feasible frontier entry), -1 if none; *n_out = frontier length.
-__device__ __forceinline__ int record_choice(const uint4& a, const uint4& bq, const uint4& c, const uint4& d,
-                                             int32_t r0, int* n_out) {
-  const uint32_t U[REC_SLOTS_TAIL] = {a.y, a.z, bq.x, bq.y, bq.z, bq.w, c.x, c.y, c.z, c.w};
-  const uint32_t K2[REC_SLOTS_TAIL / 2] = {a.w, d.x, d.y, d.z, d.w};
-  const int n = (int)(a.x & 0xFFFFu);
+// Choice from the first tail (slots 2..6; unused slots never feasible): the
+// first feasible slot in descending-T order, -1 if none; *n_out = frontier
+// length.
+__device__ __forceinline__ int tail_choice(const uint4& a, const uint4& bq, int32_t r0, int* n_out) {
+  const uint32_t U[REC_SLOTS_TAIL - 2] = {a.w, bq.x, bq.y, bq.z, bq.w};
+  const uint32_t K[REC_SLOTS_TAIL - 2] = {a.x >> 16, a.y & 0xFFFFu, a.y >> 16, a.z & 0xFFFFu, a.z >> 16};
   int sel = -1;
 #pragma unroll
-  for (int slot = REC_SLOTS_TAIL - 1; slot >= 0; --slot) {
-    const int k = (int)((K2[slot >> 1] >> (16 * (slot & 1))) & 0xFFFFu);
-    if (slot < n && (int32_t)U[slot] < r0) sel = k;
-  }
-  *n_out = n;
+  for (int s = REC_SLOTS_TAIL - 3; s >= 0; --s)
+    if ((int32_t)U[s] < r0) sel = (int)K[s];
+  *n_out = (int)(a.x & 0xFFFFu);
   return sel;
 }
 
-// The same over the second tail (slots 10..19; n = frontier length).
+// The same over the second tail (slots 7..16; n = frontier length).
 __device__ __forceinline__ int record_choice2(const uint4& a, const uint4& bq, const uint4& c, const uint4& d, int n,
                                               int32_t r0) {
   const uint32_t U[REC_SLOTS - REC_SLOTS_TAIL] = {a.x, a.y, a.z, a.w, bq.x, bq.y, bq.z, bq.w, c.x, c.y};
@@ -814,28 +824,29 @@ __device__ __forceinline__ int finish_choice(const DevTables& t, const uint2* ov
   return sel;
 }
 
-// Decision from the hot record words h; the tail is read only when neither
-// of the two cheapest entries is affordable and the frontier is longer, the
-// second tail only when no slot of the first is.
+// Decision from the hot record words h.  The tail is read only when neither
+// of the two cheapest entries is affordable and slo - elapsed exceeds the
+// rounded-down smallest threshold (at or below it nothing is feasible: the
+// fastest configuration, flag 0); the second tail only when no slot of the
+// first is and the frontier is longer.
 __device__ __forceinline__ int decide_from_record(const DevTables& t, const uint4* tail, const uint4* tail2,
                                                   const uint2* ovf, int v, const uint4& h, int32_t r0,
                                                   uint8_t* feasible) {
-  const int n = (int)(h.x & 0xFFFFu);
   int sel = -1;
-  if (n > 1 && (int32_t)h.z < r0) sel = (int)(h.w >> 16);
-  if (n > 0 && (int32_t)h.y < r0) sel = (int)(h.w & 0xFFFFu);
-  if (sel < 0 && n > 2) {
-    const uint4* r = tail + (int64_t)v * 3;
-    int nn;
-    sel = record_choice(h, r[0], r[1], r[2], r0, &nn);
+  if ((int32_t)h.z < r0) sel = (int)(h.w >> 16);
+  if ((int32_t)h.y < r0) sel = (int)(h.w & 0xFFFFu);
+  if (sel < 0 && r0 > rec_code_value(h.x >> 16)) {
+    const uint4* r = tail + (int64_t)v * REC_TAIL_VECS;
+    int n;
+    sel = tail_choice(r[0], r[1], r0, &n);
     if (sel < 0 && n > REC_SLOTS_TAIL) {
-      const uint4* r2 = tail2 + (int64_t)v * 4;
+      const uint4* r2 = tail2 + (int64_t)v * REC_TAIL2_VECS;
       sel = record_choice2(r2[0], r2[1], r2[2], r2[3], n, r0);
       sel = finish_choice(t, ovf, v, sel, n, r0);
     }
   }
   *feasible = sel >= 0 ? 1 : 0;
-  return sel >= 0 ? sel : (int)(h.x >> 16);
+  return sel >= 0 ? sel : (int)(h.x & 0xFFFFu);
 }
 
 __device__ __forceinline__ void store_decision(const Batch& b, int64_t i, int cfg, uint8_t feasible) {
@@ -1968,15 +1979,17 @@ hipError_t launch_records(const DevTables& t, int mode0, int n_modes, const int6
   return hipGetLastError();
 }
 
-hipError_t launch_relax(const DevTables& t, hipStream_t s) {
+hipError_t launch_relax(const DevTables& t, int modes, hipStream_t s) {
+  if (modes < 1 || modes > 3) return hipErrorInvalidValue;
   if (t.n_pipelines <= 0) return hipSuccess;
   if (t.max_pipe_ops <= 64) {
     // one op per lane: records in the same launch
-    hipLaunchKernelGGL(relax_kernel<true>, dim3(t.n_pipelines), dim3(128), relax_lds_bytes(t, true), s, t);
+    hipLaunchKernelGGL(relax_kernel<true>, dim3(t.n_pipelines), dim3(128), relax_lds_bytes(t, true), s, t, modes);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(relax_kernel<false>, dim3(t.n_pipelines), dim3(64), relax_lds_bytes(t, false), s, t);
-  if (t.n_ops > 0) hipLaunchKernelGGL(op_records_kernel, dim3(blocks_for(2 * (int64_t)t.n_ops, 256)), dim3(256), 0, s, t);
+  hipLaunchKernelGGL(relax_kernel<false>, dim3(t.n_pipelines), dim3(64), relax_lds_bytes(t, false), s, t, modes);
+  const int64_t threads = (modes == 3 ? 2 : 1) * (int64_t)t.n_ops;
+  if (t.n_ops > 0) hipLaunchKernelGGL(op_records_kernel, dim3(blocks_for(threads, 256)), dim3(256), 0, s, t, modes);
   return hipGetLastError();
 }
 
@@ -2025,8 +2038,8 @@ hipError_t launch_feedback(const DevTables& t, const FeedbackArgs& f, int64_t n,
 hipError_t launch_decide_batching(const DevTables& t, const Batch& b, const BatchingArgs& a, hipStream_t s) {
   if (b.n == 0) return hipSuccess;
   const uint4* rec = t.rec + (int64_t)b.mode * t.n_ops;
-  const uint4* tail = t.rec_tail + (int64_t)b.mode * t.n_ops * 3;
-  const uint4* tail2 = t.rec_tail2 + (int64_t)b.mode * t.n_ops * 4;
+  const uint4* tail = t.rec_tail + (int64_t)b.mode * t.n_ops * REC_TAIL_VECS;
+  const uint4* tail2 = t.rec_tail2 + (int64_t)b.mode * t.n_ops * REC_TAIL2_VECS;
   const uint2* ovf = t.ovf + (int64_t)b.mode * t.n_front;
   if (b.queue) {
     // records for this call's queueing times, in the context's own buffers
@@ -2081,8 +2094,8 @@ hipError_t launch_decide_alpha(const DevTables& t, const Batch& b, hipStream_t s
 hipError_t launch_decide_indexed(const DevTables& t, const Batch& b, hipStream_t s) {
   if (b.n == 0) return hipSuccess;
   const uint4* rec = t.rec + (int64_t)b.mode * t.n_ops;
-  const uint4* tail = t.rec_tail + (int64_t)b.mode * t.n_ops * 3;
-  const uint4* tail2 = t.rec_tail2 + (int64_t)b.mode * t.n_ops * 4;
+  const uint4* tail = t.rec_tail + (int64_t)b.mode * t.n_ops * REC_TAIL_VECS;
+  const uint4* tail2 = t.rec_tail2 + (int64_t)b.mode * t.n_ops * REC_TAIL2_VECS;
   const uint2* ovf = t.ovf + (int64_t)b.mode * t.n_front;
   if (b.queue) {
     // records for this call's queueing times, in the context's own buffers

@@ -270,6 +270,8 @@ int llama_decide_batching(llama_ctx* c, int64_t n, const int32_t* op, const int3
   if (mode != LLAMA_SLACK_PAPER && mode != LLAMA_SLACK_PROB)
     return llama::fail(c, LLAMA_E_ARG, "decide_batching: bad slack_mode %d", mode);
   if (n > INT32_MAX) return llama::fail(c, LLAMA_E_RANGE, "decide_batching: n_inv out of range");
+  if (!queue && !llama::records_current(c, mode))
+    return llama::fail(c, LLAMA_E_STATE, "decide_batching: the last relaxation left out the records of slack mode %d", mode);
   if (n == 0) return LLAMA_OK;
   hipStream_t s = (hipStream_t)stream;
   // scratch: sub-queue counters and the sub-queues (grows; not while the

@@ -193,6 +193,8 @@ int llama_serve_open(llama_ctx* c, const llama_serve_config* cfg, llama_server**
     return fail(c, LLAMA_E_ARG, "serve_open: need n_slots >= 1, max_batch >= 1, 1 <= max_inflight <= 16");
   if (cfg->slack_mode != LLAMA_SLACK_PAPER && cfg->slack_mode != LLAMA_SLACK_PROB)
     return fail(c, LLAMA_E_ARG, "serve_open: bad slack_mode");
+  if (!cfg->learned && !llama::records_current(c, cfg->slack_mode))
+    return fail(c, LLAMA_E_STATE, "serve_open: the last relaxation left out the records of slack mode %d", cfg->slack_mode);
   if (cfg->learned && (!c->surr.ready || c->surr.n_rows != c->n_cfg))
     return fail(c, LLAMA_E_STATE, "serve_open: learned mode needs a surrogate");
   if (cfg->learned && !(cfg->spread_max >= 0.0f)) return fail(c, LLAMA_E_ARG, "serve_open: spread_max < 0");

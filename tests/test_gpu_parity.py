@@ -242,6 +242,38 @@ def test_update_latencies_recomputes_everything():
     assert_full_parity(r)
 
 
+@pytest.mark.parametrize("maker", ["c2", "c3"])
+def test_relax_one_slack_mode(maker):
+    # records rebuilt for one slack mode: that mode stays bit-exact, the
+    # record-reading path refuses the other, the paths that read W directly
+    # serve both; a full relaxation restores both
+    w = (wl.make_c2(seed=13, n_pipelines=24, n_inv=30_000) if maker == "c2"
+         else wl.make_c3(seed=14, n_pipelines=48, n_inv=30_000))
+    r = Run(w)
+    rng = np.random.default_rng(2)
+    lat2 = np.maximum(1, (w.lat * rng.uniform(0.6, 1.4, w.n_cfg))).astype(np.int32)
+    r.L.update_latencies(lat2)
+    w2 = wl.Workload(**{**w.__dict__, "lat": lat2})
+    r.w, r.P = w2, oracle.Problem(w2)
+    for keep, drop in ((PAPER, PROB), (PROB, PAPER), (PAPER, PROB)):
+        r.L.relax(modes=1 << keep)
+        c, f = r.decide(keep, B.SCAN_INDEXED)
+        c_or, f_or = r.P.decide(keep)
+        assert np.array_equal(c, c_or) and np.array_equal(f, f_or)
+        with pytest.raises(B.LlamaError, match="slack mode"):
+            r.decide(drop, B.SCAN_INDEXED)
+        c, f = r.decide(drop, B.SCAN_WAVE)
+        c_or, f_or = r.P.decide(drop)
+        assert np.array_equal(c, c_or) and np.array_equal(f, f_or)
+        c, f = r.decide(drop, B.SCAN_INDEXED, Q=[10, 0, 300, 7])   # per-call records
+        c_or, f_or = r.P.decide(drop, Q=[10, 0, 300, 7])
+        assert np.array_equal(c, c_or) and np.array_equal(f, f_or)
+    with pytest.raises(B.LlamaError):
+        r.L.relax(modes=4)
+    r.L.relax()
+    assert_full_parity(r, scans=(B.SCAN_INDEXED,))
+
+
 def test_repeatable_and_order_independent():
     torch = _torch()
     w = wl.make_c2(seed=9, n_pipelines=10, n_inv=30_000)
