@@ -423,6 +423,30 @@ int llama_autotune(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
  */
 int llama_set_schedule(llama_ctx *ctx, int32_t schedule);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * decisions as llama_decide with LLAMA_SCAN_FULL, bit for bit, with the
+ * bucketing scratch (per-op counts, starts and cursors, the permutation of
+ * invocations, per-chunk histograms) taken from one static device array of
+ * LLAMA_NOALLOC_SCRATCH_BYTES per GPU instead of context buffers.  The call
+ * allocates nothing; the array is set up when a context is first created on
+ * a device and is held until the process ends.  Arguments, outputs and
+ * device errors as in llama_decide.  A batch whose scratch
+ * (llama_decide_full_noalloc_words(n_inv, n_ops) 4-byte words) exceeds the
+ * limit is rejected with LLAMA_E_RANGE before anything is launched.  Every
+ * call on one GPU shares the array (each call rewrites what it reads, and
+ * clears its counts with a kernel), so calls that may overlap on one GPU,
+ * from any context or stream, race and must be ordered by the caller.
+ */
+#define LLAMA_NOALLOC_SCRATCH_BYTES ((int64_t)32 << 20)
+int llama_decide_full_noalloc(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
+                              const int32_t *d_elapsed_us, const int32_t *d_slo_us,
+                              const int64_t *d_queue_us, int32_t slack_mode,
+                              int32_t *d_cfg, uint8_t *d_flag, void *stream);
+/* Scratch words one llama_decide_full_noalloc call needs (-1 for negative sizes). */
+int64_t llama_decide_full_noalloc_words(int64_t n_inv, int32_t n_ops);
+
 /* Pre-size the scratch that LLAMA_SCAN_FULL needs for batches of up to
  * max_inv invocations (device memory, 4 bytes per invocation).  Synchronous. */
 int llama_reserve(llama_ctx *ctx, int64_t max_inv);

@@ -37,7 +37,7 @@ EXPORTS = ["llama_create", "llama_destroy", "llama_last_error", "llama_set_dag",
            "llama_serve_open", "llama_serve_submit", "llama_serve_poll", "llama_serve_stats_get",
            "llama_serve_close", "llama_autotune", "llama_set_schedule", "llama_queue_time", "llama_set_alpha",
            "llama_decide_alpha", "llama_feedback", "llama_affinity", "llama_decide_batching",
-           "llama_relax_modes"]
+           "llama_decide_full_noalloc", "llama_decide_full_noalloc_words", "llama_relax_modes"]
 
 
 class LlamaStats(ctypes.Structure):
@@ -86,6 +86,8 @@ def load_library(path=LIB_PATH):
         "llama_select": [p, i64, p, p, p, p, p],
         "llama_decide": [p, i64, p, p, p, p, i32, i32, p, p, p],
         "llama_reserve": [p, i64],
+        "llama_decide_full_noalloc": [p, i64, p, p, p, p, i32, p, p, p],
+        "llama_decide_full_noalloc_words": [i64, i32],
         "llama_select_rows": [p, i64, p, p, p, i64, p, p, p],
         "llama_serve_bytes_per_request": [i32],
         "llama_autotune": [p, i64, p, p, p, p, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float), p],
@@ -123,6 +125,7 @@ def load_library(path=LIB_PATH):
     L.llama_destroy.restype = None
     L.llama_surrogate_param_count.restype = ctypes.c_int64
     L.llama_serve_bytes_per_request.restype = ctypes.c_int64
+    L.llama_decide_full_noalloc_words.restype = ctypes.c_int64
     L.llama_last_error.restype = ctypes.c_char_p
     if path == LIB_PATH:
         _lib = L
@@ -311,6 +314,17 @@ class Llama:
             self._ctx, n, _dp(op, "int32"), _dp(elapsed, "int32", n), _dp(slo, "int32", n),
             _dp(queue, "int64", self.n_hw), int(mode), int(scan), _dp(cfg, "int32", n),
             _dp(flag, "uint8", n), _stream(stream)))
+        return cfg, flag
+
+    def decide_full_noalloc(self, op, elapsed, slo, cfg, flag=None, queue=None, mode=SLACK_PAPER,
+                            stream=None):
+        """The full-scan decision into caller-allocated outputs, with the
+        library's static per-GPU scratch (no device allocation)."""
+        n = op.numel()
+        self._check("llama_decide_full_noalloc", self._L.llama_decide_full_noalloc(
+            self._ctx, n, _dp(op, "int32"), _dp(elapsed, "int32", n), _dp(slo, "int32", n),
+            _dp(queue, "int64", self.n_hw), int(mode), _dp(cfg, "int32", n), _dp(flag, "uint8", n),
+            _stream(stream)))
         return cfg, flag
 
     # -- Eq. 2 queueing time and the finite-alpha objective ------------------------

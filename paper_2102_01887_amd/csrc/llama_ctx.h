@@ -200,6 +200,8 @@ int build_alpha_tables(llama_ctx* c);
 int pull_profiles(llama_ctx* c);
 // Relaxation into the record set not written last (then decisions use it).
 hipError_t relax_next(llama_ctx* c, hipStream_t s, int modes = 3);
+// noalloc.hip: resolve the static scratch array's address on `device` (current)
+hipError_t noalloc_attach(int device);
 // Whether the current record set holds the records of slack mode `mode`.
 inline bool records_current(const llama_ctx* c, int mode) { return (c->rec_modes[c->rec_cur] >> mode) & 1; }
 }  // namespace llama

@@ -131,7 +131,7 @@ int llama_create(llama_ctx** out, int32_t device) {
     int cu = 0;
     if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cu > 0) c->n_cu = cu;
   }
-  if (hipSetDevice(device) != hipSuccess ||
+  if (hipSetDevice(device) != hipSuccess || llama::noalloc_attach(device) != hipSuccess ||
       hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
     delete c;
     return LLAMA_E_DEVICE;
