@@ -74,10 +74,14 @@ def parse():
 
 # kernel of each decision schedule (llama_autotune's numbering)
 # (the LDS-staged schedule runs its 16-byte variant: the bench's arrays are aligned)
-SCHEDULE_KERNELS = ("void decide_indexed_kernel<1, false>", "void decide_indexed_kernel<2, false>",
-                    "void decide_indexed_kernel<4, false>", "decide_lds4_kernel",
-                    "void decide_indexed_kernel<1, true>", "void decide_indexed_kernel<2, true>",
-                    "void decide_indexed_kernel<4, true>")
+def schedule_kernel(sched):
+    """Kernel name of a decision schedule (llama_autotune's numbering; the
+    LDS-staged schedule runs its 16-byte variant: the bench's arrays are
+    aligned)."""
+    if sched == 3:
+        return "decide_lds4_kernel"
+    ipt, nt = ((1, "false"), (2, "false"), (4, "false"), None, (1, "true"), (2, "true"), (4, "true"))[sched]
+    return f"void decide_indexed_kernel<{ipt}, {nt}>"
 
 
 def measured_traffic(workload, kernel):
@@ -457,74 +461,96 @@ def bench_surrogate(args, torch, B, wl, log):
 
 def drive_poisson(srv, op, el, slo, rate, duration, seed, feat=None):
     """Offer a Poisson stream of the given rate for `duration` seconds (numpy
-    request arrays); returns per-request latency (ns) and the sustained rate."""
+    request arrays).  Returns per-request latency (ns) from submission to the
+    device time of the decision, the same from the scheduled arrival (which
+    adds this Python load generator's lag), the sustained rate and the
+    requests the ring did not admit at their first offer."""
     import numpy as np
     from paper_2102_01887_amd import workloads as wl
     off = wl.poisson_arrivals(np.random.default_rng(seed), rate, duration)
     n = min(len(off), len(op))
     t0 = time.monotonic_ns() + 2_000_000
     arr = t0 + off[:n]
+    sub = np.zeros(n, np.int64)
     i = done = 0
-    lats = []
+    refused = 0
+    lats, tick = [], []
     while done < n:
         now = time.monotonic_ns()
         j = int(np.searchsorted(arr, now, side="right"))
         if j > i:
-            k, _ = srv.submit(op[i:j], el[i:j], slo[i:j], None if feat is None else feat[i:j],
-                              arrival_ns=arr[i:j])
+            k, tk = srv.submit(op[i:j], el[i:j], slo[i:j], None if feat is None else feat[i:j])
+            sub[i:i + k] = now
+            refused += (j - i) - k
             i += k
         t, _, _, lat = srv.poll(wait_ms=0)
         done += len(t)
         lats.append(lat)
+        tick.append(t)
     elapsed = (time.monotonic_ns() - t0) * 1e-9
-    return np.concatenate(lats), n / elapsed
+    lat, tick = np.concatenate(lats), np.concatenate(tick)
+    from_arrival = lat + (sub[tick] - arr[tick])
+    return lat, from_arrival, n / elapsed, refused
+
+
+def serve_runs(srv_factory, op, el, slo, rates, seconds, log, label, feat=None):
+    import numpy as np
+    out = []
+    srv = srv_factory()
+    drive_poisson(srv, op, el, slo, rates[0], 0.2, 1, feat=feat)  # warm-up, not reported
+    srv.close()
+    for rate in rates:
+        srv = srv_factory()
+        lat, lat_arr, sustained, refused = drive_poisson(srv, op, el, slo, rate, seconds, rate, feat=feat)
+        st = srv.stats()
+        srv.close()
+        p50, p99 = (np.percentile(lat, [50, 99]) / 1e3).tolist()
+        a50, a99 = (np.percentile(lat_arr, [50, 99]) / 1e3).tolist()
+        log(f"bench: serve {label} {rate}/s -> p50 {p50:.1f} us p99 {p99:.1f} us "
+            f"(from scheduled arrival {a50:.1f} / {a99:.1f}), {sustained:.0f}/s, "
+            f"{st['batches']} claims, {st['kernel_launches']} launches, "
+            f"clock {st['clock_anchors']} anchors, rate {st['clock_rate_ppb'] / 1e3:+.1f} ppm")
+        out.append({"offered_per_s": rate, "decisions": int(len(lat)), "sustained_per_s": sustained,
+                    "p50_us": p50, "p99_us": p99, "p50_from_arrival_us": a50, "p99_from_arrival_us": a99,
+                    "claims": st["batches"], "mean_claim": len(lat) / max(1, st["batches"]),
+                    "largest_claim": st["max_batch_seen"], "kernel_launches": st["kernel_launches"],
+                    "capacity": st["capacity"], "peak_bytes_in_use": st["peak_bytes_in_use"],
+                    "refused_at_first_offer": refused, "clock_rtt_us": st["clock_rtt_ns"] / 1e3,
+                    "clock_anchors": st["clock_anchors"], "clock_rate_ppm": st["clock_rate_ppb"] / 1e3})
+    return out
 
 
 def bench_serving(args, torch, B, wl, log, surrogate_ctx=None):
     """Serving loop on C5 (1,024 uneven pipelines): Poisson arrivals at
     50k-500k/s, 65,536 slots, 256 MB admission budget; p50/p99 latency from
-    arrival to decision and the sustained rate."""
+    submission to the device time of the decision, and the sustained rate.
+    A last run gives the ring a 64 KiB budget (2,048 plain slots), so memory,
+    not slots, limits admission."""
     import numpy as np
     log("bench: generating workload c5 (1,024 pipelines)")
     w = wl.make_c5(n_inv=600_000)
     L = B.Llama(0).load(w)
     out = {"workload": "c5: 1,024 layered pipelines of 3-200 ops, 16-2048 configs/op, "
                        "Poisson arrivals, 65,536 slots, 256 MB admission budget",
-           "n_ops": w.n_ops, "n_cfg": w.n_cfg, "plain": []}
-    srv = B.Server(L, n_slots=65536, mem_budget_bytes=256 << 20, max_batch=65536, max_inflight=4)
-    drive_poisson(srv, w.inv_op, w.elapsed, w.slo, 50_000, 0.2, 1)  # warm-up, not reported
-    srv.close()
-    for rate in (50_000, 100_000, 200_000, 500_000):
-        srv = B.Server(L, n_slots=65536, mem_budget_bytes=256 << 20, max_batch=65536, max_inflight=4)
-        lat, sustained = drive_poisson(srv, w.inv_op, w.elapsed, w.slo, rate, args.serve_seconds, rate)
-        st = srv.stats()
-        srv.close()
-        p50, p99 = (np.percentile(lat, [50, 99]) / 1e3).tolist()
-        log(f"bench: serve {rate}/s -> p50 {p50:.1f} us p99 {p99:.1f} us, {sustained:.0f}/s")
-        out["plain"].append({"offered_per_s": rate, "decisions": int(len(lat)),
-                             "sustained_per_s": sustained, "p50_us": p50, "p99_us": p99,
-                             "batches": st["batches"], "mean_batch": len(lat) / max(1, st["batches"])})
+           "n_ops": w.n_ops, "n_cfg": w.n_cfg,
+           "path": "persistent decision kernel (HIP graph, relaunched when it has exited) fed from a "
+                   "device-mapped ring; device-clock decision times",
+           "bytes_per_request": {"plain": int(L._L.llama_serve_bytes_per_request(0)),
+                                 "learned": int(L._L.llama_serve_bytes_per_request(1))}}
+    plain = lambda budget=256 << 20: B.Server(L, n_slots=65536, mem_budget_bytes=budget, max_batch=64,
+                                             max_inflight=4)
+    out["plain"] = serve_runs(plain, w.inv_op, w.elapsed, w.slo, (50_000, 100_000, 200_000, 500_000),
+                              args.serve_seconds, log, "plain")
+    out["plain_memory_bound"] = serve_runs(lambda: plain(64 << 10), w.inv_op, w.elapsed, w.slo, (500_000,),
+                                           args.serve_seconds, log, "plain, 64 KiB budget")
     if surrogate_ctx is not None:
         Ls, world = surrogate_ctx
         wq, content = wl.c4_invocations(world, np.random.default_rng(9), 400_000)
         bits = (np.ascontiguousarray(content.feat, np.float32).view(np.uint32) >> 16).astype(np.uint16)
-        out["learned"] = []
-        srv = B.Server(Ls, n_slots=65536, mem_budget_bytes=256 << 20, max_batch=65536, max_inflight=4,
-                       learned=True)
-        drive_poisson(srv, wq.inv_op, wq.elapsed, wq.slo, 50_000, 0.2, 1, feat=bits)  # warm-up
-        srv.close()
-        for rate in (50_000, 200_000):
-            srv = B.Server(Ls, n_slots=65536, mem_budget_bytes=256 << 20, max_batch=65536,
-                           max_inflight=4, learned=True)
-            lat, sustained = drive_poisson(srv, wq.inv_op, wq.elapsed, wq.slo, rate, args.serve_seconds,
-                                           rate, feat=bits)
-            st = srv.stats()
-            srv.close()
-            p50, p99 = (np.percentile(lat, [50, 99]) / 1e3).tolist()
-            log(f"bench: serve learned {rate}/s -> p50 {p50:.1f} us p99 {p99:.1f} us")
-            out["learned"].append({"offered_per_s": rate, "decisions": int(len(lat)),
-                                   "sustained_per_s": sustained, "p50_us": p50, "p99_us": p99,
-                                   "batches": st["batches"]})
+        learned = lambda: B.Server(Ls, n_slots=65536, mem_budget_bytes=256 << 20, max_batch=1,
+                                   max_inflight=16, learned=True)
+        out["learned"] = serve_runs(learned, wq.inv_op, wq.elapsed, wq.slo, (50_000, 200_000),
+                                    args.serve_seconds, log, "learned", feat=bits)
     return out
 
 
@@ -628,6 +654,8 @@ def main():
     g_steps = pipelined_graph(spg) if args.pipeline else graph_of(torch, s, step, spg)
     g_dec = graph_of(torch, s, decide(B.SCAN_INDEXED), args.kernel_reps)
     L.reserve(n)
+    full_cross, full_tuned_us = L.autotune_full(op, el, slo, mode, stream=s)
+    log(f"bench: full-scan schedule crossover {full_cross[0]}/{full_cross[1]} ({full_tuned_us:.1f} us)")
     g_full = graph_of(torch, s, decide(B.SCAN_FULL), max(1, args.kernel_reps // 10))
     g_wave = graph_of(torch, s, decide(B.SCAN_WAVE), 2)
     g_relax = graph_of(torch, s, relax, args.kernel_reps)
@@ -759,14 +787,16 @@ def main():
                    "decide_schedule": B.SCHEDULE_NAMES[tuned[0]]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.workload, SCHEDULE_KERNELS[tuned[0]]),
-                     "kernel": SCHEDULE_KERNELS[tuned[0]], "kernel_ms": ms_dec,
+                     "traffic": measured_traffic(args.workload, schedule_kernel(tuned[0])),
+                     "kernel": schedule_kernel(tuned[0]), "kernel_ms": ms_dec,
                      "algo_bytes": algo_bytes},
         "cpu_baseline": cpu,
         "bit_exact": bit_exact,
         "ms_per_step_device": ms_step_dev,
         "relax_ms": ms_relax,
-        "full_scan": {"kernels": "bucket by op + scan_bucketed_kernel", "ms": ms_full,
+        "full_scan": {"kernels": "bucket by op + scan_classes_kernel (one wavefront per op: lanes = "
+                                 "invocations or lanes = configurations, by the autotuned crossover)",
+                      "crossover": list(full_cross), "ms": ms_full,
                       "decisions_per_s": n / (ms_full * 1e-3), "pairs": pairs,
                       "roofline": {"bound": "alu", "achieved": full_gops,
                                    "peak": VALU_PEAK_GOPS, "unit": "Gop/s",

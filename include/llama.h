@@ -73,7 +73,8 @@ enum llama_scan_mode {
      * remaining-time thresholds (one 64-byte record per op). */
     LLAMA_SCAN_INDEXED = 1,
     /* Every configuration of the op: invocations are bucketed by op on the
-     * GPU and each wavefront scans one op's table for its invocations.  Uses
+     * GPU and one wavefront per op scans its table for its invocations, in
+     * the layout the schedule table picks (llama_autotune_full).  Uses
      * context scratch of 4 bytes per invocation (see llama_reserve). */
     LLAMA_SCAN_FULL = 2,
     /* Every configuration, one wavefront per invocation, lanes over the
@@ -333,11 +334,13 @@ int llama_set_alpha(llama_ctx *ctx, uint32_t alpha_num, uint32_t alpha_den);
  * Alg. 1 targets (as llama_targets, with d_queue_us or zeros) and the
  * finite-alpha Eq. 1 choice, fused; device pointers as in llama_decide.
  * Invalid invocations get -1 / flag 0 and set the device error word.  With
- * d_queue_us, when no op has more than 4,096 configurations, each call first
- * merges every op's configurations by remaining-time threshold plus its
- * backend's queueing time into context-owned tables (12 bytes per
- * configuration), so calls with queueing times that overlap on one context
- * must be ordered.
+ * d_queue_us, when no op has more than 4,096 configurations and the batch
+ * has at least one invocation per eight configurations (8 n_inv >= n_cfg),
+ * each call first merges every op's configurations by remaining-time
+ * threshold plus its backend's queueing time into context-owned tables (12
+ * bytes per configuration), so calls with queueing times that overlap on one
+ * context must be ordered; otherwise each invocation searches each backend's
+ * list (no per-call tables).  Both give the same decisions.
  */
 int llama_decide_alpha(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
                        const int32_t *d_elapsed_us, const int32_t *d_slo_us,
@@ -422,6 +425,28 @@ int llama_autotune(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
  * 0..6).  Every schedule gives the same decisions.
  */
 int llama_set_schedule(llama_ctx *ctx, int32_t schedule);
+
+/*
+ * Schedule table of the full scan (LLAMA_SCAN_FULL), per the per-operation
+ * configuration space of Sec. 4.2: each op's bucket of k invocations is
+ * evaluated against its c configurations either with lanes = invocations
+ * (the table as wave-uniform operands) or with lanes = configurations
+ * (groups of 16, 32 or 64 lanes and a group minimum), whichever has the
+ * smaller instruction count under the crossover: lanes = invocations when
+ * its count x cross_den <= the other's x cross_num (num 0: always
+ * configurations; num 2^20: almost always invocations).
+ * llama_autotune_full times seven crossovers on the caller's batch (device
+ * pointers, d_cfg_scratch [n_inv]; scratch reserved as by llama_reserve),
+ * checks that they decide alike and keeps the fastest, returning it (either
+ * output may be NULL) and its time per call; synchronous.  The chosen pair
+ * is the table a caller may store and restore with llama_set_full_schedule
+ * (LLAMA_E_ARG outside 0 <= num <= 2^20, den >= 1).  Default 1/1.
+ */
+int llama_autotune_full(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
+                        const int32_t *d_elapsed_us, const int32_t *d_slo_us, int32_t slack_mode,
+                        int32_t *d_cfg_scratch, int32_t *cross_num, int32_t *cross_den,
+                        float *best_us, void *stream);
+int llama_set_full_schedule(llama_ctx *ctx, int32_t cross_num, int32_t cross_den);
 
 /*
  * For callers that cannot allocate device memory (code under HIP graph
@@ -523,6 +548,37 @@ int llama_surrogate_grads(llama_ctx *ctx, float *grads, int64_t n);
  * (needed before capturing training or forward calls into a graph). */
 int llama_surrogate_reserve(llama_ctx *ctx, int64_t max_batch);
 
+/*
+ * The pipeline simulator that generates the surrogate's training executions
+ * on the GPU (content-dependent latency, Sec. 2 and Fig. 3).  An execution
+ * gets a profile row x uniform over the n_cfg rows, content, and the
+ * observed ln latency
+ *     ln L[x] + a[op(x) * n_hw + hw(x)] ln(1 + n_obj) + b[op(x)] ln(px / (1280 * 720))
+ *     + sigma N(0, 1)
+ * with L the row's current profiled latency.  Content: people and cars
+ * Poisson with rate exp(ln 2 + N(0, 1)) (people at most 60, cars at most
+ * 60 - people), faces Binomial(people, 0.6), resolution 854x480, 1280x720
+ * or 1920x1080 uniformly, motion, blur, brightness U(0, 1), branch hit rate
+ * Beta(3, 7), frame phase U(0, 2 pi); the 16 BF16 features are people / 60,
+ * cars / 60, faces / 60, ln(1 + n_obj) / ln 61, width / 1920, height / 1080,
+ * pixels / (1920 * 1080), motion, blur, brightness, hit rate, sin and cos of
+ * the phase, and three zeros.  Random numbers: Philox4x32-10 under key
+ * (seed mod 2^32, seed / 2^32) at counters (sample, k, 0, 0), k = 0..5, the
+ * 24 words used as: 0 row (floor(w n_cfg / 2^32)); 1-4 two Box-Muller pairs
+ * (people and cars rates; noise); 5, 6 Poisson inversions; 7 binomial
+ * inversion; 8 resolution (floor(3 w / 2^32)); 9-11 motion, blur,
+ * brightness; 12-21 the Beta as G3 / (G3 + G7) from sums of unit
+ * exponentials; 22 phase; with u = (w + 1/2) / 2^32; arithmetic in FP64.
+ * Sample i depends only on (seed, i), so batches may be drawn in any split.
+ * llama_set_simulator copies a [n_ops * n_hw], b [n_ops] (host, finite) and
+ * sigma >= 0; llama_simulate writes samples first .. first + n - 1
+ * (first + n <= 2^32) to device pointers d_rows [n], d_feat [n][16] BF16,
+ * d_y [n] FP32 on `stream`.
+ */
+int llama_set_simulator(llama_ctx *ctx, const double *a_coef, const double *b_coef, double sigma);
+int llama_simulate(llama_ctx *ctx, int64_t n, uint64_t seed, int64_t first, int32_t *d_rows,
+                   uint16_t *d_feat, float *d_y, void *stream);
+
 /* Training-path forward for n rows (device pointers): d_rows [n] profile row
  * ids, d_feat [n][16] BF16, d_out [n][2] FP32 (mu, q). */
 int llama_surrogate_forward(llama_ctx *ctx, int64_t n, const int32_t *d_rows,
@@ -575,35 +631,55 @@ int llama_decide_learned(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
  * spawning invocations and the Configurator deciding them, Sec. 3.3 and
  * Sec. 4; admission bounded like the paper's commit queues, Sec. 4.3).
  *
- * Requests sit in a ring of slots in pinned host memory that the decision
- * kernels read and write in place.  A request is admitted when a slot is free
- * and bytes_per_request x (admitted, not yet collected) stays within the
- * memory budget; llama_serve_submit admits the longest prefix that fits.  A
- * worker thread launches every admitted request not yet on the GPU as one
- * batch (at most max_batch, contiguous in the ring) on one of max_inflight
- * streams while earlier batches run, and retires batches in order.  Decisions
- * are collected in admission order (llama_serve_poll), which frees slots.
- * While a server is open, the context's tables and surrogate must not be
- * changed.  A server is driven by one caller thread.
+ * Requests sit in a ring in pinned host memory mapped into the device: a
+ * slot holds a request (16 bytes), its result (8) and the device time it
+ * was decided (8), plus 32 bytes of BF16 features in the learned form
+ * (llama_serve_bytes_per_request).  The ring is allocated with
+ * min(n_slots, mem_budget_bytes / bytes per request) slots, and a request
+ * holds its slot from admission until its decision is collected, so the
+ * smaller of the two limits how many requests are admitted at once;
+ * llama_serve_submit admits the longest prefix that fits and publishes it to
+ * the device at once.  A persistent decision kernel of max_inflight
+ * workgroups (captured as a HIP graph and relaunched by submit and poll
+ * whenever it has exited with requests outstanding) claims published
+ * requests as they appear, up to max_batch (at most 64) per wavefront in the
+ * plain form and one per wavefront in the learned form, and writes each
+ * decision with the device time it was made; a wavefront exits after 20 ms
+ * without work and after 250 ms in any case.  Decisions are collected in
+ * admission order (llama_serve_poll), which frees slots.  While a server is
+ * open, the context's tables and surrogate must not be changed.  A server is
+ * driven by one caller thread.
  * ---------------------------------------------------------------------- */
 typedef struct llama_server llama_server;
 
 typedef struct llama_serve_config {
     int32_t n_slots;           /* ring capacity, >= 1 */
     int64_t mem_budget_bytes;  /* admission budget, >= one request */
-    int32_t max_batch;         /* largest batch per launch, >= 1 */
-    int32_t max_inflight;      /* batches on the GPU at once, 1..16 */
+    int32_t max_batch;         /* requests one wavefront claims at once (plain form; capped at 64), >= 1 */
+    int32_t max_inflight;      /* workgroups of the persistent decision kernel, 1..256 */
     int32_t learned;           /* 0: profile latencies, 1: surrogate (features required) */
     int32_t slack_mode;        /* LLAMA_SLACK_PAPER or LLAMA_SLACK_PROB */
     float spread_max;          /* learned mode: see llama_decide_learned */
 } llama_serve_config;
 
 typedef struct llama_serve_stats {
-    int64_t submitted, admitted, rejected, decided, collected, batches;
-    int64_t bytes_in_use, peak_bytes_in_use, max_batch_seen, in_flight_batches;
+    int64_t submitted, admitted, rejected, decided, collected;
+    int64_t batches;            /* claims made by the kernel's wavefronts */
+    int64_t bytes_in_use, peak_bytes_in_use;
+    int64_t max_batch_seen;     /* largest claim */
+    int64_t in_flight_batches;  /* 1 while the persistent kernel runs */
+    int64_t capacity;           /* ring slots: min(n_slots, budget / bytes per request) */
+    int64_t kernel_launches;    /* graph launches of the persistent kernel */
+    int64_t clock_rtt_ns;       /* host round trip of the clock handshake at open (anchor error <= half) */
+    int64_t clock_anchors;      /* re-anchorings by handshakes with the running kernel */
+    int64_t clock_rate_ppb;     /* fitted device clock period vs its nominal one, parts per 10^9 */
+    int64_t clock_probes;       /* handshakes tried with the running kernel */
+    int64_t clock_probe_timeouts;     /* of which unanswered within 50 us */
+    int64_t clock_probe_rtt_min_ns;   /* shortest answered round trip */
+    int64_t clock_probe_rtt_last_ns;  /* latest answered round trip */
 } llama_serve_stats;
 
-/* Bytes charged per admitted request (64, or 96 with features). */
+/* Ring bytes a request holds while admitted (32, or 64 with features). */
 int64_t llama_serve_bytes_per_request(int32_t learned);
 
 int llama_serve_open(llama_ctx *ctx, const llama_serve_config *cfg, llama_server **out);
@@ -617,14 +693,19 @@ int llama_serve_submit(llama_server *srv, int32_t n, const int32_t *op, const in
                        int64_t *tickets, int32_t *n_admitted);
 
 /* Collect up to max decided requests in admission order (waiting up to
- * wait_ms for the first): tickets, choices, flags and arrival-to-decision
- * latency in ns (any output may be NULL).  *n_out receives the count. */
+ * wait_ms for the first): tickets, choices, flags and the latency from
+ * arrival to the device time of the decision in ns (device clock mapped to
+ * CLOCK_MONOTONIC by a handshake at open, re-anchored by handshakes with the
+ * running kernel every 10 ms of polling, each waiting at most 50 us, with
+ * the rate refitted over the baseline since open; any output may be NULL).
+ * *n_out receives the count. */
 int llama_serve_poll(llama_server *srv, int32_t max, int64_t *tickets, int32_t *cfg, uint8_t *flag,
                      int64_t *latency_ns, int32_t *n_out, int32_t wait_ms);
 
 int llama_serve_stats_get(llama_server *srv, llama_serve_stats *out);
 
-/* Finish every admitted request, stop the worker and free the server. */
+/* Decide every admitted request (waiting at most 10 s), stop the kernel and
+ * free the server. */
 int llama_serve_close(llama_server *srv);
 
 #ifdef __cplusplus

@@ -37,7 +37,9 @@ EXPORTS = ["llama_create", "llama_destroy", "llama_last_error", "llama_set_dag",
            "llama_serve_open", "llama_serve_submit", "llama_serve_poll", "llama_serve_stats_get",
            "llama_serve_close", "llama_autotune", "llama_set_schedule", "llama_queue_time", "llama_set_alpha",
            "llama_decide_alpha", "llama_feedback", "llama_affinity", "llama_decide_batching",
-           "llama_decide_full_noalloc", "llama_decide_full_noalloc_words", "llama_relax_modes"]
+           "llama_decide_full_noalloc", "llama_decide_full_noalloc_words", "llama_relax_modes",
+           "llama_autotune_full", "llama_set_full_schedule",
+           "llama_set_simulator", "llama_simulate"]
 
 
 class LlamaStats(ctypes.Structure):
@@ -58,7 +60,9 @@ class ServeConfig(ctypes.Structure):
 class ServeStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in (
         "submitted", "admitted", "rejected", "decided", "collected", "batches", "bytes_in_use",
-        "peak_bytes_in_use", "max_batch_seen", "in_flight_batches")]
+        "peak_bytes_in_use", "max_batch_seen", "in_flight_batches", "capacity", "kernel_launches",
+        "clock_rtt_ns", "clock_anchors", "clock_rate_ppb", "clock_probes", "clock_probe_timeouts",
+        "clock_probe_rtt_min_ns", "clock_probe_rtt_last_ns")]
 
 
 _lib = None
@@ -81,6 +85,11 @@ def load_library(path=LIB_PATH):
         "llama_set_profiles": [p, i32, i32, p, p, p, p, p, p, p, p],
         "llama_relax": [p, p],
         "llama_relax_modes": [p, i32, p],
+        "llama_autotune_full": [p, i64, p, p, p, i32, p, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                ctypes.POINTER(ctypes.c_float), p],
+        "llama_set_full_schedule": [p, i32, i32],
+        "llama_set_simulator": [p, p, p, ctypes.c_double],
+        "llama_simulate": [p, i64, ctypes.c_uint64, i64, p, p, p, p],
         "llama_update_latencies": [p, p],
         "llama_targets": [p, i64, p, p, p, p, i32, p, p],
         "llama_select": [p, i64, p, p, p, p, p],
@@ -251,6 +260,23 @@ class Llama:
     def set_schedule(self, schedule):
         """Pin the indexed decision's schedule (0..6, as numbered by autotune)."""
         self._check("llama_set_schedule", self._L.llama_set_schedule(self._ctx, int(schedule)))
+
+    def autotune_full(self, op, elapsed, slo, mode=SLACK_PAPER, stream=None):
+        """Pick the full scan's schedule crossover on this batch; returns
+        ((num, den), us per call)."""
+        import torch
+        n = op.numel()
+        scratch = torch.empty(n, dtype=torch.int32, device=op.device)
+        num, den, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+        self._check("llama_autotune_full", self._L.llama_autotune_full(
+            self._ctx, n, _dp(op, "int32"), _dp(elapsed, "int32", n), _dp(slo, "int32", n), int(mode),
+            _dp(scratch, "int32", n), ctypes.byref(num), ctypes.byref(den), ctypes.byref(us),
+            _stream(stream)))
+        return (num.value, den.value), us.value
+
+    def set_full_schedule(self, num, den):
+        """Pin the full scan's schedule crossover (the table autotune_full returns)."""
+        self._check("llama_set_full_schedule", self._L.llama_set_full_schedule(self._ctx, int(num), int(den)))
 
     def reserve(self, max_inv):
         self._check("llama_reserve", self._L.llama_reserve(self._ctx, int(max_inv)))
@@ -473,6 +499,24 @@ class Llama:
     def surrogate_load(self, path):
         self._check("llama_surrogate_load", self._L.llama_surrogate_load(self._ctx, str(path).encode()))
 
+    def set_simulator(self, a_coef, b_coef, sigma):
+        """The simulator's content coefficients (numpy [n_ops, n_hw] and [n_ops]) and noise."""
+        a = np.ascontiguousarray(a_coef, np.float64)
+        b = np.ascontiguousarray(b_coef, np.float64)
+        self._check("llama_set_simulator", self._L.llama_set_simulator(self._ctx, _hp(a), _hp(b), float(sigma)))
+
+    def simulate(self, n, seed, first=0, stream=None):
+        """n simulated executions on the GPU: (rows int32, features BF16 bits
+        as int16 [n, 16], y float32) device tensors."""
+        import torch
+        rows = torch.empty(n, dtype=torch.int32, device="cuda")
+        feat = torch.empty((n, 16), dtype=torch.int16, device="cuda")
+        y = torch.empty(n, dtype=torch.float32, device="cuda")
+        self._check("llama_simulate", self._L.llama_simulate(
+            self._ctx, int(n), int(seed) & ((1 << 64) - 1), int(first), _dp(rows, "int32", n),
+            _dp16(feat, 16 * n), _dp(y, "float32", n), _stream(stream)))
+        return rows, feat, y
+
     def decide_learned(self, op, elapsed, slo, feat, queue=None, mode=SLACK_PAPER, spread_max=1.3862944,
                        cfg=None, flag=None, lat_out=None, lat_stride=0, stream=None):
         import torch
@@ -503,6 +547,14 @@ class Server:
         self._srv = ctypes.c_void_p()
         llama._check("llama_serve_open", self._L.llama_serve_open(llama._ctx, ctypes.byref(cfg),
                                                                   ctypes.byref(self._srv)))
+        # poll's output buffers and their pointers, reused across calls
+        self._out = (np.empty(self.POLL_MAX, np.int64), np.empty(self.POLL_MAX, np.int32),
+                     np.empty(self.POLL_MAX, np.uint8), np.empty(self.POLL_MAX, np.int64))
+        self._out_p = tuple(_hp(a) for a in self._out)
+        self._k = ctypes.c_int32()
+        self._k_ref = ctypes.byref(self._k)
+
+    POLL_MAX = 1 << 16
 
     def submit(self, op, elapsed, slo, feat=None, arrival_ns=None):
         """Offer requests (numpy); returns the admitted count and their tickets."""
@@ -519,17 +571,14 @@ class Server:
         return k.value, tickets[:k.value]
 
     def poll(self, max_n=1 << 16, wait_ms=0):
-        tickets = np.empty(max_n, np.int64)
-        cfg = np.empty(max_n, np.int32)
-        flag = np.empty(max_n, np.uint8)
-        lat = np.empty(max_n, np.int64)
-        k = ctypes.c_int32()
-        rc = self._L.llama_serve_poll(self._srv, max_n, _hp(tickets), _hp(cfg), _hp(flag), _hp(lat),
-                                      ctypes.byref(k), int(wait_ms))
+        """Collect up to max_n decisions (at most POLL_MAX a call): tickets,
+        choices, flags, latencies in ns (numpy arrays of their own)."""
+        max_n = min(int(max_n), self.POLL_MAX)
+        rc = self._L.llama_serve_poll(self._srv, max_n, *self._out_p, self._k_ref, int(wait_ms))
         if rc != OK:
             raise LlamaError("llama_serve_poll", rc, "serving loop failed")
-        n = k.value
-        return tickets[:n], cfg[:n], flag[:n], lat[:n]
+        n = self._k.value
+        return tuple(a[:n].copy() for a in self._out)
 
     def stats(self):
         st = ServeStats()

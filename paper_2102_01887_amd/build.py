@@ -24,7 +24,7 @@ HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I" + INCLUDE, "-I" + CSRC]
 
-KERNELS = ["llama_kernels.hip", "surrogate_kernels.hip", "sort_kernels.hip", "alpha_kernels.hip", "noalloc.hip"]
+KERNELS = ["llama_kernels.hip", "surrogate_kernels.hip", "sort_kernels.hip", "alpha_kernels.hip", "noalloc.hip", "sim_kernels.hip"]
 HOST = ["llama_host.cpp", "surrogate_host.cpp", "serve_host.cpp", "next_host.cpp", "feedback_host.cpp"]
 
 

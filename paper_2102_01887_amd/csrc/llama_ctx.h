@@ -85,6 +85,9 @@ struct llama_ctx {
   DevBuf d_aff_scratch;  // Eq. 3 sort keys, indices and sort temporary storage
   DevBuf d_batch_scratch;  // safe delayed batching: count, then the queue of invocations left to scan
   DevBuf d_qacc;  // Eq. 2 partial sums, QUEUE_PARTS x MAX_HW x 2 x 64 bits
+  DevBuf d_sim_a, d_sim_b, d_sim_row_op;  // simulator: content coefficients per (op, backend) and op, op of each row
+  double sim_sigma = 0.0;
+  bool has_sim = false;
   // feedback (llama_feedback): static arrays of the device rebuild, zeroed
   // accumulators, and whether the host copy of the latencies is behind
   bool fb_ready = false, host_stale = false;
@@ -94,6 +97,7 @@ struct llama_ctx {
   DevBuf d_cnt, d_start, d_cursor, d_perm, d_hist;  // bucketed full scan
   int64_t perm_cap = 0;
   int32_t decide_sched = 0;  // schedule chosen by llama_autotune (llama::DecideSchedule)
+  int32_t full_cross_num = 1, full_cross_den = 1;  // full-scan schedule crossover (llama_autotune_full)
   int32_t n_cu = 256;        // compute units of the device
 
   DevTables tables() const {
@@ -104,6 +108,8 @@ struct llama_ctx {
     t.hs = llama::header_stride(n_hw);
     t.n_front = n_cfg;  // stride of the capacity layout
     t.decide_sched = decide_sched;
+    t.full_cross_num = full_cross_num;
+    t.full_cross_den = full_cross_den;
     t.n_cu = n_cu;
     // relaxation stage: the largest pipeline, within 1024 ops / 3072 edges
     t.relax_ops = max_pipe_ops < 1024 ? max_pipe_ops : 1024;
@@ -178,7 +184,7 @@ struct llama_ctx {
                            &d_succ_ids, &d_succ_q, &d_ref, &d_W, &d_hdr, &d_front_L,
                            &d_rec[0], &d_rec_tail[0], &d_rec_tail2[0], &d_ovf[0], &d_rec[1], &d_rec_tail[1], &d_rec_tail2[1], &d_ovf[1], &d_rec_q, &d_rec_tail_q, &d_rec_tail2_q, &d_ovf_q, &d_seg_off, &d_tab, &d_err,
                            &d_cnt, &d_start, &d_cursor, &d_perm, &d_hist, &d_mst,
-                           &d_mst_n, &d_cfg_off, &d_cfg_hw, &d_cfg_lat, &d_cfg_key, &d_cfg_q, &d_cfg_batch, &d_a_lat, &d_a_pf, &d_a_si, &d_m_lat, &d_m_pf, &d_m_si, &d_a_val, &d_a_fk, &d_a_ik, &d_aq_T, &d_aq_pf, &d_aq_si, &d_aq_cnt, &d_m_cnt, &d_aff_scratch, &d_batch_scratch, &d_qacc, &d_fb_ksrc, &d_fb_tab_src, &d_fb_ref_k, &d_fb_count, &d_fb_sum, &d_fb_dirty};
+                           &d_mst_n, &d_cfg_off, &d_cfg_hw, &d_cfg_lat, &d_cfg_key, &d_cfg_q, &d_cfg_batch, &d_a_lat, &d_a_pf, &d_a_si, &d_m_lat, &d_m_pf, &d_m_si, &d_a_val, &d_a_fk, &d_a_ik, &d_aq_T, &d_aq_pf, &d_aq_si, &d_aq_cnt, &d_m_cnt, &d_aff_scratch, &d_batch_scratch, &d_qacc, &d_fb_ksrc, &d_fb_tab_src, &d_fb_ref_k, &d_fb_count, &d_fb_sum, &d_fb_dirty, &d_sim_a, &d_sim_b, &d_sim_row_op};
     int64_t s = 0;
     for (auto* b : all) s += (int64_t)b->bytes;
     return s;
@@ -204,4 +210,6 @@ hipError_t relax_next(llama_ctx* c, hipStream_t s, int modes = 3);
 hipError_t noalloc_attach(int device);
 // Whether the current record set holds the records of slack mode `mode`.
 inline bool records_current(const llama_ctx* c, int mode) { return (c->rec_modes[c->rec_cur] >> mode) & 1; }
+// noalloc.hip: resolve the static scratch array's address on `device` (current)
+hipError_t noalloc_attach(int device);
 }  // namespace llama

@@ -788,6 +788,86 @@ int llama_set_schedule(llama_ctx* c, int32_t schedule) {
   return LLAMA_OK;
 }
 
+int llama_autotune_full(llama_ctx* c, int64_t n, const int32_t* op, const int32_t* elapsed, const int32_t* slo,
+                        int32_t slack_mode, int32_t* cfg_scratch, int32_t* cross_num, int32_t* cross_den,
+                        float* best_us, void* stream) {
+  int rc = enter(c);
+  if (rc) return rc;
+  if ((rc = check_batch(c, n, op, "autotune_full"))) return rc;
+  if (n < 1 || !elapsed || !slo || !cfg_scratch)
+    return fail(c, LLAMA_E_ARG, "autotune_full: need a non-empty batch and scratch");
+  if (slack_mode != LLAMA_SLACK_PAPER && slack_mode != LLAMA_SLACK_PROB)
+    return fail(c, LLAMA_E_ARG, "autotune_full: bad slack_mode %d", slack_mode);
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = reserve_perm(c, n, s))) return rc;
+  // crossovers, from "lanes = configurations unless far cheaper" to "lanes =
+  // invocations unless far cheaper", and the two pure layouts
+  const int32_t cands[][2] = {{1, 4}, {1, 2}, {1, 1}, {2, 1}, {4, 1}, {0, 1}, {1 << 20, 1}};
+  const int n_c = (int)(sizeof(cands) / sizeof(cands[0]));
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return fail(c, LLAMA_E_DEVICE, "autotune_full events");
+  const int32_t saved_num = c->full_cross_num, saved_den = c->full_cross_den;
+  std::vector<int32_t> ref_out, out;
+  float best = 0.0f;
+  int best_i = 2;
+  hipError_t e = hipSuccess;
+  for (int ci = 0; ci < n_c && e == hipSuccess; ++ci) {
+    c->full_cross_num = cands[ci][0];
+    c->full_cross_den = cands[ci][1];
+    llama::Batch bt{};
+    bt.n = n; bt.op = op; bt.elapsed = elapsed; bt.slo = slo; bt.cfg = cfg_scratch; bt.mode = slack_mode;
+    llama::FullScratch w{c->d_cnt.as<int32_t>(), c->d_start.as<int32_t>(), c->d_cursor.as<int32_t>(),
+                         c->d_perm.as<int32_t>(), c->d_hist.as<int32_t>()};
+    e = llama::launch_decide_full(c->tables(), bt, w, s);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(a, s);
+    for (int r = 0; r < 5 && e == hipSuccess; ++r) e = llama::launch_decide_full(c->tables(), bt, w, s);
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    out.resize(n);
+    if (e == hipSuccess) e = hipMemcpy(out.data(), cfg_scratch, sizeof(int32_t) * n, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) break;
+    if (ci == 0) {
+      ref_out = out;
+    } else if (out != ref_out) {
+      c->full_cross_num = saved_num;
+      c->full_cross_den = saved_den;
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+      return fail(c, LLAMA_E_DEVICE, "autotune_full: crossover %d/%d changed the decisions", cands[ci][0], cands[ci][1]);
+    }
+    const float us = ms * 200.0f;  // ms / 5 launches, in us
+    if (ci == 0 || us < best) {
+      best = us;
+      best_i = ci;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (e != hipSuccess) {
+    c->full_cross_num = saved_num;
+    c->full_cross_den = saved_den;
+    return hip_fail(c, e, "autotune_full");
+  }
+  c->full_cross_num = cands[best_i][0];
+  c->full_cross_den = cands[best_i][1];
+  if (cross_num) *cross_num = c->full_cross_num;
+  if (cross_den) *cross_den = c->full_cross_den;
+  if (best_us) *best_us = best;
+  return LLAMA_OK;
+}
+
+int llama_set_full_schedule(llama_ctx* c, int32_t cross_num, int32_t cross_den) {
+  int rc = enter(c);
+  if (rc) return rc;
+  if (cross_num < 0 || cross_den < 1 || cross_num > (1 << 20))
+    return fail(c, LLAMA_E_ARG, "set_full_schedule: need 0 <= num <= 2^20 and den >= 1");
+  c->full_cross_num = cross_num;
+  c->full_cross_den = cross_den;
+  return LLAMA_OK;
+}
+
 int llama_reserve(llama_ctx* c, int64_t max_inv) {
   int rc = enter(c);
   if (rc) return rc;

@@ -97,6 +97,8 @@ struct DevTables {
   int32_t hs;              // header_stride(n_hw)
   int64_t n_front;         // capacity of the frontier and overflow arrays (n_cfg)
   int32_t decide_sched;    // DecideSchedule of the indexed decision
+  int32_t full_cross_num;  // full scan: lanes = invocations when its cost x den <= the other's x num
+  int32_t full_cross_den;
   int32_t n_cu;            // compute units of the device
   // LDS capacities of the relaxation (ops, edges, levels of one pipeline);
   // larger pipelines are relaxed in global memory
@@ -123,8 +125,8 @@ struct DevTables {
   const uint2* mst;          // [n_cfg] {L, key}, per op ascending in L from cfg_off[v]
   const int32_t* mst_n;      // [n_ops] entries of each op's merged frontier
   uint4* rec;                // [2*n_ops] record words 0..3, PAPER then PROB, queue = 0
-  uint4* rec_tail;           // [2*n_ops*REC_TAIL_VECS] record words 4..11
-  uint4* rec_tail2;          // [2*n_ops*REC_TAIL2_VECS] record words 12..27
+  uint4* rec_tail;           // [2*n_ops*REC_TAIL_VECS] record tails
+  uint4* rec_tail2;          // [2*n_ops*REC_TAIL2_VECS] record second tails
   uint2* ovf;                // [2*n_front] full frontiers {T, key} ascending, PAPER then PROB
   uint4* rec_q;              // [n_ops] records for a per-call queueing-time vector
   uint4* rec_tail_q;         // [n_ops*REC_TAIL_VECS]
@@ -318,5 +320,60 @@ hipError_t launch_surrogate_backward(const SurrogateBufs& w, int64_t B, const in
 hipError_t launch_adamw(const SurrogateBufs& w, float lr, float wd, int64_t step, hipStream_t s);
 hipError_t launch_shadows(const SurrogateBufs& w, hipStream_t s);
 hipError_t launch_decide_learned(const DevTables& t, const Batch& b, const LearnedArgs& a, hipStream_t s);
+
+// Pipeline simulator (sim_kernels.hip): samples first .. first + n - 1.
+struct SimArgs {
+  int64_t n, first;
+  uint64_t seed;
+  int64_t n_rows;
+  int32_t n_hw;
+  const int32_t* row_op;   // [n_rows] op of each profile row
+  const int32_t* cfg_hw;   // [n_rows]
+  const int32_t* cfg_lat;  // [n_rows] profiled latency (us)
+  const double* a_coef;    // [n_ops * n_hw] ln latency per ln(1 + objects)
+  const double* b_coef;    // [n_ops] ln latency per ln(pixels / 720p pixels)
+  double sigma;            // noise of ln latency
+  int32_t* rows;           // [n] out
+  void* feat;              // [n][16] BF16 out
+  float* y;                // [n] out: observed ln latency
+};
+hipError_t launch_simulate(const SimArgs& a, hipStream_t s);
+
+// Serving ring shared by the host and the persistent decision kernels: the
+// request, feature, result and timestamp arrays and the control words are in
+// pinned host memory mapped into the device's address space; the claim
+// counters are in device memory.  Request seq sits in slot seq % cap.
+struct ServeRing {
+  const int4* req;              // [cap] {op, elapsed_us, slo_us, 0}
+  const void* feat;             // [cap][16] BF16 content features (learned form) or nullptr
+  unsigned long long* res;      // [cap] (seq + 1 mod 2^32) << 32 | (cfg + 1) | flag << 31
+  unsigned long long* ts;       // [cap] device clock when the decision was written
+  const long long* head;        // requests published by the host: seq < *head
+  const int* stop;              // nonzero: the kernels finish their claims and exit
+  const int* probe;             // clock probe number written by the host
+  int* ack;                     // last probe answered, after *stamp
+  unsigned long long* stamp;    // device clock when that probe was seen
+  int* exited;                  // set by the last wavefront to exit
+  unsigned long long* ctr;      // device memory: [0] next seq to claim, [1] claims, [2] largest claim,
+                                // [3] wavefronts alive, [4] device clock of the latest claim
+  int64_t cap;
+  int32_t mode;                 // slack mode
+  int32_t chunk;                // requests a wavefront claims at once (plain form, 1..64)
+  uint64_t idle_ticks;          // device-clock ticks without work before a wavefront exits
+  uint64_t life_ticks;          // device-clock ticks before a wavefront exits in any case
+};
+// Persistent plain decisions (records of r.mode, no queueing times) by
+// `workgroups` workgroups of four wavefronts.
+hipError_t launch_serve_plain(const DevTables& t, const ServeRing& r, int workgroups, hipStream_t s);
+// Persistent learned decisions: one wavefront per invocation.
+// prepare_serve_learned raises the kernel's LDS limit (once, before capture).
+hipError_t prepare_serve_learned(const DevTables& t);
+hipError_t launch_serve_learned(const DevTables& t, const ServeRing& r, const LearnedArgs& a, int workgroups,
+                                hipStream_t s);
+// Clock handshake for host/device time calibration: for round k < rounds the
+// kernel waits (at most timeout_ticks) until *flag == k + 1, then writes its
+// clock to stamp[k] and sets *ack = k + 1.
+hipError_t launch_clock_probe(const int* flag, int* ack, unsigned long long* stamp, int rounds,
+                              uint64_t timeout_ticks, hipStream_t s);
 
 }  // namespace llama

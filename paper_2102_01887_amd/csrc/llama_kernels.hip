@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include "llama_internal.h"
+#include "serve_device.h"
 
 namespace llama {
 namespace {
@@ -849,10 +850,19 @@ __device__ __forceinline__ int decide_from_record(const DevTables& t, const uint
   return sel >= 0 ? sel : (int)(h.x & 0xFFFFu);
 }
 
+// With NT the decision is stored with the non-temporal hint as well, so that
+// the output stream need not displace decision records in L2 either.
+template <bool NT = false>
 __device__ __forceinline__ void store_decision(const Batch& b, int64_t i, int cfg, uint8_t feasible) {
-  b.cfg[i] = cfg;
-  if (b.flag) b.flag[i] = feasible;
+  if (NT) {
+    __builtin_nontemporal_store(cfg, b.cfg + i);
+    if (b.flag) __builtin_nontemporal_store(feasible, b.flag + i);
+  } else {
+    b.cfg[i] = cfg;
+    if (b.flag) b.flag[i] = feasible;
+  }
 }
+
 
 // The invocation stream is read once; with NT its loads carry the
 // non-temporal hint, so that they need not displace decision records in L2.
@@ -893,14 +903,14 @@ __global__ __launch_bounds__(256) void decide_indexed_kernel(DevTables t, Batch 
     const int64_t i = base + (int64_t)u * blockDim.x;
     if (i >= b.n) continue;
     if (!ok[u]) {
-      store_decision(b, i, -1, 0);
+      store_decision<NT>(b, i, -1, 0);
       atomicOr(t.err, 1u);
       continue;
     }
     const int32_t r0 = s[u] - e[u];  // both non-negative: no overflow
     uint8_t f;
     const int c = decide_from_record(t, tail, tail2, ovf, v[u], h[u], r0, &f);
-    store_decision(b, i, c, f);
+    store_decision<NT>(b, i, c, f);
   }
 }
 
@@ -1002,10 +1012,11 @@ __global__ __launch_bounds__(1024) void decide_lds4_kernel(DevTables t, Batch b,
 // Full scan, the plain Eq. 1 evaluation of every configuration.
 //   bucket_count / bucket_offsets / bucket_scatter: counting sort of the
 //     valid invocations by op (invalid ones are answered at once);
-//   scan_bucketed_kernel: one wavefront per op, lanes = that op's
-//     invocations; the op's table is walked with wave-uniform (scalar)
-//     loads, so each (invocation, configuration) pair costs one compare, one
-//     select and one min.
+//   scan_classes_kernel: one wavefront per op, which takes lanes = the op's
+//     invocations (the table walked with wave-uniform scalar loads: one
+//     compare, one select and one min per pair) or lanes = configurations
+//     (wavefront min), whichever costs fewer instructions for the op's
+//     bucket size and table size.
 // decide_wave_kernel keeps the same evaluation with lanes = configurations
 // and a DPP min reduction across the wave; it needs no scratch.
 // ---------------------------------------------------------------------------
@@ -1129,74 +1140,10 @@ __global__ __launch_bounds__(1024) void bucket_offsets_kernel(const int32_t* cnt
   if (tid == 1023) start[n] = run;
 }
 
-// One 256-lane workgroup per op, lanes = the op's invocations.  The op's
-// table is the same for every lane, so it is read through the scalar cache
-// (constant address space: s_load into SGPRs) and each (invocation,
-// configuration) pair costs one compare, one select and one min, with the
-// configuration's latency and key as scalar operands.
+// Configurations read as scalar operands: the table through the constant
+// address space (s_load into SGPRs), two configurations per 16 bytes.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(4))) u32x4 const_u32x4;
-
-template <int NHW>
-__global__ __launch_bounds__(256) void scan_bucketed_kernel(DevTables t, Batch b, const int32_t* start,
-                                                            const int32_t* perm) {
-  const int v = blockIdx.x;
-  const int tid = threadIdx.x;
-  const int p0 = start[v], p1 = start[v + 1];
-  if (p0 == p1) return;
-  const int64_t ref = t.ref[v];
-  const int64_t W = t.W[(int64_t)b.mode * t.n_ops + v];
-  int seg[NHW + 1];
-#pragma unroll
-  for (int h = 0; h <= NHW; ++h) seg[h] = t.seg_off[(int64_t)v * NHW + h];
-  const int fastest = t.hdr[(int64_t)v * t.hs + NHW + 1];
-  const_u32x4* tab2 = (const_u32x4*)(const void*)t.tab;  // two configurations per 16 bytes
-  for (int pb = p0; pb < p1; pb += 256) {
-    const int p = pb + tid;
-    const bool live = p < p1;
-    const int64_t i = live ? perm[p] : 0;
-    const int64_t r0 = live ? (int64_t)b.slo[i] - b.elapsed[i] : 0;
-    uint32_t best = KEY_NONE;
-#pragma unroll
-    for (int h = 0; h < NHW; ++h) {
-      const int64_t R = remaining_time(r0, b.queue ? b.queue[h] : 0);
-      const int32_t tg = R == 0 ? 0 : (int32_t)div_floor_pos(ref * R, W);
-      int x = seg[h];
-      const int x1 = seg[h + 1];
-      if (x < x1 && (x & 1)) {  // align to a pair
-        const uint2 c = t.tab[x];
-        const uint32_t m = (int32_t)c.x < tg ? c.y : KEY_NONE;
-        best = m < best ? m : best;
-        ++x;
-      }
-      for (; x + 8 <= x1; x += 8) {
-        const u32x4 q0 = tab2[x >> 1], q1 = tab2[(x >> 1) + 1], q2 = tab2[(x >> 1) + 2], q3 = tab2[(x >> 1) + 3];
-        uint32_t m0 = (int32_t)q0.x < tg ? q0.y : KEY_NONE;
-        uint32_t m1 = (int32_t)q0.z < tg ? q0.w : KEY_NONE;
-        uint32_t m2 = (int32_t)q1.x < tg ? q1.y : KEY_NONE;
-        uint32_t m3 = (int32_t)q1.z < tg ? q1.w : KEY_NONE;
-        uint32_t m4 = (int32_t)q2.x < tg ? q2.y : KEY_NONE;
-        uint32_t m5 = (int32_t)q2.z < tg ? q2.w : KEY_NONE;
-        uint32_t m6 = (int32_t)q3.x < tg ? q3.y : KEY_NONE;
-        uint32_t m7 = (int32_t)q3.z < tg ? q3.w : KEY_NONE;
-        m0 = m0 < m1 ? m0 : m1;
-        m2 = m2 < m3 ? m2 : m3;
-        m4 = m4 < m5 ? m4 : m5;
-        m6 = m6 < m7 ? m6 : m7;
-        m0 = m0 < m2 ? m0 : m2;
-        m4 = m4 < m6 ? m4 : m6;
-        m0 = m0 < m4 ? m0 : m4;
-        best = m0 < best ? m0 : best;
-      }
-      for (; x < x1; ++x) {
-        const uint2 c = t.tab[x];
-        const uint32_t m = (int32_t)c.x < tg ? c.y : KEY_NONE;
-        best = m < best ? m : best;
-      }
-    }
-    if (live) write_choice(b, i, best, fastest);
-  }
-}
 
 // DPP controls (GFX9 encoding).
 constexpr int DPP_QUAD_XOR1 = 0xB1;      // quad_perm [1,0,3,2]
@@ -1253,6 +1200,113 @@ __global__ __launch_bounds__(256) void decide_wave_kernel(DevTables t, Batch b) 
     const uint64_t any = __builtin_amdgcn_ballot_w64(best != KEY_NONE);
     if (any) best = wave_min_u32(best);
     if (lane == 0) write_choice(b, i, best, t.hdr[(int64_t)v * t.hs + NHW + 1]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Full scan with schedule classes: one wavefront per op, which evaluates its
+// op's bucket of k invocations against the op's c configurations in the
+// cheaper of two layouts (wavefront instructions, from counting loop trips):
+//   lanes = invocations: ceil(k / 64) passes over the table, each
+//     configuration a scalar operand (compare, select, min):  ~3 c per pass;
+//   lanes = configurations: groups of S = 16, 32 or 64 lanes (the smallest
+//     that covers c, so 64 / S invocations share a pass), each lane walking
+//     every S-th configuration, then a min over the group:
+//     ~ceil(k / (64 / S)) (5 ceil(c / S) + 14).
+// The first is taken when its count times the crossover's den is at most the
+// second's times its num; the crossover is the schedule table entry the
+// autotuner picks on the caller's batch (llama_autotune_full).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t group_min_u32(uint32_t v, int S) {
+  v = umin32(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, DPP_QUAD_XOR1, 0xF, 0xF, false));
+  v = umin32(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, DPP_QUAD_XOR2, 0xF, 0xF, false));
+  v = umin32(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, DPP_ROW_HALF_MIRROR, 0xF, 0xF, false));
+  v = umin32(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, DPP_ROW_MIRROR, 0xF, 0xF, false));
+  // every lane of a 16-lane row holds the row minimum
+  if (S >= 32) v = umin32(v, (uint32_t)__shfl_xor((int)v, 16, 64));
+  if (S >= 64) v = umin32(v, (uint32_t)__shfl_xor((int)v, 32, 64));
+  return v;
+}
+
+template <int NHW>
+__global__ __launch_bounds__(256) void scan_classes_kernel(DevTables t, Batch b, const int32_t* start,
+                                                           const int32_t* perm, int32_t cross_num,
+                                                           int32_t cross_den) {
+  const int lane = threadIdx.x & 63;
+  // the op is the same for the whole wavefront: keep it (and what is loaded
+  // from it) in scalar registers
+  const int v = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+  if (v >= t.n_ops) return;
+  const int p0 = start[v], p1 = start[v + 1];
+  const int k = p1 - p0;
+  if (k == 0) return;
+  int seg[NHW + 1];
+#pragma unroll
+  for (int h = 0; h <= NHW; ++h) seg[h] = t.seg_off[(int64_t)v * NHW + h];
+  const int c = seg[NHW] - seg[0];
+  const int64_t ref = t.ref[v];
+  const int64_t W = t.W[(int64_t)b.mode * t.n_ops + v];
+  const int fastest = t.hdr[(int64_t)v * t.hs + NHW + 1];
+  const int S = c <= 16 ? 16 : c <= 32 ? 32 : 64;
+  const int per = 64 / S;
+  const int64_t cost_inv = (int64_t)((k + 63) / 64) * c * 3;
+  const int64_t cost_cfg = (int64_t)((k + per - 1) / per) * (5 * ((c + S - 1) / S) + 14);
+  if (cost_inv * cross_den <= cost_cfg * cross_num) {
+    // lanes = invocations; the table as scalar operands, two configurations per 16 bytes
+    const_u32x4* tab2 = (const_u32x4*)(const void*)t.tab;
+    for (int pb = p0; pb < p1; pb += 64) {
+      const int p = pb + lane;
+      const bool live = p < p1;
+      const int64_t i = live ? perm[p] : 0;
+      const int64_t r0 = live ? (int64_t)b.slo[i] - b.elapsed[i] : 0;
+      uint32_t best = KEY_NONE;
+#pragma unroll
+      for (int h = 0; h < NHW; ++h) {
+        const int64_t R = remaining_time(r0, b.queue ? b.queue[h] : 0);
+        const int32_t tg = R == 0 ? 0 : (int32_t)div_floor_pos(ref * R, W);
+        int x = seg[h];
+        const int x1 = seg[h + 1];
+        if (x < x1 && (x & 1)) {  // align to a pair
+          const uint2 q = t.tab[x];
+          best = umin32(best, (int32_t)q.x < tg ? q.y : KEY_NONE);
+          ++x;
+        }
+        for (; x + 8 <= x1; x += 8) {
+          const u32x4 q0 = tab2[x >> 1], q1 = tab2[(x >> 1) + 1], q2 = tab2[(x >> 1) + 2], q3 = tab2[(x >> 1) + 3];
+          uint32_t m0 = umin32((int32_t)q0.x < tg ? q0.y : KEY_NONE, (int32_t)q0.z < tg ? q0.w : KEY_NONE);
+          uint32_t m1 = umin32((int32_t)q1.x < tg ? q1.y : KEY_NONE, (int32_t)q1.z < tg ? q1.w : KEY_NONE);
+          uint32_t m2 = umin32((int32_t)q2.x < tg ? q2.y : KEY_NONE, (int32_t)q2.z < tg ? q2.w : KEY_NONE);
+          uint32_t m3 = umin32((int32_t)q3.x < tg ? q3.y : KEY_NONE, (int32_t)q3.z < tg ? q3.w : KEY_NONE);
+          best = umin32(best, umin32(umin32(m0, m1), umin32(m2, m3)));
+        }
+        for (; x < x1; ++x) {
+          const uint2 q = t.tab[x];
+          best = umin32(best, (int32_t)q.x < tg ? q.y : KEY_NONE);
+        }
+      }
+      if (live) write_choice(b, i, best, fastest);
+    }
+    return;
+  }
+  // lanes = configurations, 64 / S invocations per pass
+  const int g = lane / S, l = lane % S;
+  for (int pb = p0; pb < p1; pb += per) {
+    const int p = pb + g;
+    const bool live = p < p1;
+    const int64_t i = live ? perm[p] : 0;
+    const int64_t r0 = live ? (int64_t)b.slo[i] - b.elapsed[i] : 0;
+    uint32_t best = KEY_NONE;
+#pragma unroll
+    for (int h = 0; h < NHW; ++h) {
+      const int64_t R = remaining_time(r0, b.queue ? b.queue[h] : 0);
+      const int32_t tg = R == 0 ? 0 : (int32_t)div_floor_pos(ref * R, W);
+      for (int x = seg[h] + l; x < seg[h + 1]; x += S) {
+        const uint2 q = t.tab[x];
+        best = umin32(best, (int32_t)q.x < tg ? q.y : KEY_NONE);
+      }
+    }
+    best = group_min_u32(best, S);
+    if (live && l == 0) write_choice(b, i, best, fastest);
   }
 }
 
@@ -1969,6 +2023,68 @@ __global__ __launch_bounds__(256) void batching_scan_kernel(DevTables t, Batch b
     default: return hipErrorInvalidValue;                                            \
   }
 
+// ---------------------------------------------------------------------------
+// Serving: persistent plain decisions.  Each wavefront claims up to r.chunk
+// published requests (lanes = requests), decides them from the records and
+// writes result and device time into the ring; it exits when the host sets
+// stop, after idle_ticks without a claim, or once it has run life_ticks (it
+// never exits holding a claim).  The host relaunches the kernel whenever it
+// has exited with requests outstanding.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void serve_plain_kernel(DevTables t, ServeRing r) {
+  const int lane = threadIdx.x & 63;
+  const uint4* rec = t.rec + (int64_t)r.mode * t.n_ops;
+  const uint4* tail = t.rec_tail + (int64_t)r.mode * t.n_ops * REC_TAIL_VECS;
+  const uint4* tail2 = t.rec_tail2 + (int64_t)r.mode * t.n_ops * REC_TAIL2_VECS;
+  const uint2* ovf = t.ovf + (int64_t)r.mode * t.n_front;
+  int answered = 0;
+  int* clock = blockIdx.x == 0 && threadIdx.x < 64 ? &answered : nullptr;
+  serve_enter(r, lane);
+  const unsigned long long start = (unsigned long long)wall_clock64();
+  unsigned long long last = start;
+  for (;;) {
+    const unsigned long long now = (unsigned long long)wall_clock64();
+    if (now - start > r.life_ticks) break;
+    const ServeClaim c = serve_claim(r, lane, r.chunk, clock);
+    if (c.stop) break;
+    if (c.count == 0) {
+      if (serve_idle(r, now, last)) break;
+      __builtin_amdgcn_s_sleep(8);
+      continue;
+    }
+    last = now;
+    if (lane < c.count) {
+      const long long seq = c.first + lane;
+      const long long slot = seq % r.cap;
+      const int4 q = r.req[slot];
+      int cfg = -1;
+      uint8_t f = 0;
+      if (invalid_invocation(q.x, q.y, q.z, t.n_ops))
+        atomicOr(t.err, 1u);
+      else
+        cfg = decide_from_record(t, tail, tail2, ovf, q.x, rec[q.x], q.z - q.y, &f);
+      serve_write(r, seq, slot, cfg, f);
+    }
+  }
+  serve_leave(r, lane);
+}
+
+// Host/device clock handshake (one thread): see launch_clock_probe.
+__global__ void clock_probe_kernel(const int* flag, int* ack, unsigned long long* stamp, int rounds,
+                                   unsigned long long timeout_ticks) {
+  if (threadIdx.x != 0) return;
+  const unsigned long long start = (unsigned long long)wall_clock64();
+  for (int k = 0; k < rounds; ++k) {
+    while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) != k + 1) {
+      if ((unsigned long long)wall_clock64() - start > timeout_ticks) return;
+      __builtin_amdgcn_s_sleep(1);
+    }
+    stamp[k] = (unsigned long long)wall_clock64();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    __hip_atomic_store(ack, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_records(const DevTables& t, int mode0, int n_modes, const int64_t* queue, uint4* rec,
@@ -2140,6 +2256,19 @@ hipError_t launch_decide_indexed(const DevTables& t, const Batch& b, hipStream_t
   return hipGetLastError();
 }
 
+hipError_t launch_serve_plain(const DevTables& t, const ServeRing& r, int workgroups, hipStream_t s) {
+  if (workgroups < 1 || r.cap < 1 || r.chunk < 1 || r.chunk > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(serve_plain_kernel, dim3(workgroups), dim3(256), 0, s, t, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_clock_probe(const int* flag, int* ack, unsigned long long* stamp, int rounds,
+                              uint64_t timeout_ticks, hipStream_t s) {
+  hipLaunchKernelGGL(clock_probe_kernel, dim3(1), dim3(64), 0, s, flag, ack, stamp, rounds,
+                     (unsigned long long)timeout_ticks);
+  return hipGetLastError();
+}
+
 int64_t full_scan_hist_words(int64_t n_inv, int32_t n_ops) {
   if (n_ops > BUCKET_LDS_OPS) return 0;
   return ((n_inv + BUCKET_CHUNK - 1) / BUCKET_CHUNK) * (int64_t)n_ops;
@@ -2164,7 +2293,8 @@ hipError_t launch_decide_full(const DevTables& t, const Batch& b, const FullScra
     hipLaunchKernelGGL(bucket_offsets_kernel, dim3(1), dim3(1024), 0, s, w.cnt, t.n_ops, w.start, w.cursor);
     hipLaunchKernelGGL(bucket_scatter_kernel, dim3(g), dim3(256), 0, s, t, b, w.cursor, w.perm);
   }
-  LLAMA_DISPATCH_NHW(scan_bucketed_kernel, dim3(t.n_ops), dim3(256), s, t, b, w.start, w.perm);
+  LLAMA_DISPATCH_NHW(scan_classes_kernel, dim3((unsigned)((t.n_ops + 3) / 4)), dim3(256), s, t, b, w.start, w.perm,
+                     t.full_cross_num, t.full_cross_den);
   return hipGetLastError();
 }
 

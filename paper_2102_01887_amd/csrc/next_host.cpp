@@ -237,6 +237,20 @@ int llama_set_alpha(llama_ctx* c, uint32_t alpha_num, uint32_t alpha_den) {
   return LLAMA_OK;
 }
 
+namespace {
+
+// With queueing times the per-call merge rebuilds every op's merged order
+// (work in proportion to the configurations: NHW - 1 binary searches per
+// configuration), while one search per backend costs work in proportion to
+// the invocations (NHW searches each); the merge pays only when each
+// configuration serves enough invocations.  Measured on the MI355X: the
+// merge wins at 1 M invocations over 1.86 M configurations (256 pipelines of
+// 10-40 ops) and loses by about 4x at 4 M over 81 M (4,096 pipelines of
+// 3-200 ops), so it is used when 8 n_inv >= n_cfg.
+bool merge_pays(const llama_ctx* c, int64_t n) { return 8 * n >= c->n_cfg; }
+
+}  // namespace
+
 int llama_decide_alpha(llama_ctx* c, int64_t n, const int32_t* op, const int32_t* elapsed, const int32_t* slo,
                        const int64_t* queue, int32_t mode, int32_t* cfg, uint8_t* flag, void* stream) {
   int rc = llama::enter(c);
@@ -250,8 +264,9 @@ int llama_decide_alpha(llama_ctx* c, int64_t n, const int32_t* op, const int32_t
   llama::Batch b{};
   b.n = n; b.op = op; b.elapsed = elapsed; b.slo = slo; b.queue = queue; b.cfg = cfg; b.flag = flag; b.mode = mode;
   // with queueing times, one search per invocation in the op's per-call
-  // merged order when every op fits the merge; else one search per backend
-  hipError_t e = queue && c->alpha_max_op <= llama::ALPHA_MERGE_MAX && c->d_aq_T.p
+  // merged order when every op fits the merge and the merge pays; else one
+  // search per backend
+  hipError_t e = queue && c->alpha_max_op <= llama::ALPHA_MERGE_MAX && c->d_aq_T.p && merge_pays(c, n)
                      ? llama::launch_decide_alpha_queue(c->tables(), b, (hipStream_t)stream)
                      : llama::launch_decide_alpha(c->tables(), b, (hipStream_t)stream);
   if (e != hipSuccess) return llama::hip_fail(c, e, "decide_alpha launch");
@@ -329,8 +344,10 @@ int llama_affinity(llama_ctx* c, int64_t n, const int32_t* op, const int32_t* el
   llama::Batch b{};
   b.n = n; b.op = op; b.elapsed = elapsed; b.slo = slo; b.queue = queue; b.mode = mode;
   // one search per invocation in a merged order (with queueing times the
-  // per-call one, when every op fits the merge); else one per backend
-  hipError_t e = (queue ? c->alpha_max_op <= llama::ALPHA_MERGE_MAX && c->d_aq_cnt.p : c->d_m_cnt.p != nullptr)
+  // per-call one, when every op fits the merge and the merge pays); else one
+  // per backend
+  hipError_t e = (queue ? c->alpha_max_op <= llama::ALPHA_MERGE_MAX && c->d_aq_cnt.p && merge_pays(c, n)
+                        : c->d_m_cnt.p != nullptr)
                      ? llama::launch_affinity_queue(c->tables(), b, aff, order, c->d_aff_scratch.p,
                                                     c->d_aff_scratch.bytes, s)
                      : llama::launch_affinity(c->tables(), b, aff, order, c->d_aff_scratch.p,

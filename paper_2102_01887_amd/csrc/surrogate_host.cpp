@@ -335,6 +335,60 @@ int llama_surrogate_load(llama_ctx* c, const char* path) {
   return install(c, buf.data(), buf.data() + n, buf.data() + 2 * n, hdr[2]);
 }
 
+int llama_set_simulator(llama_ctx* c, const double* a_coef, const double* b_coef, double sigma) {
+  int rc = enter(c);
+  if (rc) return rc;
+  if (!c->has_prof) return fail(c, LLAMA_E_STATE, "set_simulator: call llama_set_profiles first");
+  if (!a_coef || !b_coef) return fail(c, LLAMA_E_ARG, "set_simulator: null pointer");
+  if (!(sigma >= 0.0) || !std::isfinite(sigma)) return fail(c, LLAMA_E_ARG, "set_simulator: sigma must be finite and >= 0");
+  const int64_t na = (int64_t)c->n_ops * c->n_hw;
+  for (int64_t i = 0; i < na; ++i)
+    if (!std::isfinite(a_coef[i])) return fail(c, LLAMA_E_RANGE, "set_simulator: a_coef[%lld] not finite", (long long)i);
+  for (int v = 0; v < c->n_ops; ++v)
+    if (!std::isfinite(b_coef[v])) return fail(c, LLAMA_E_RANGE, "set_simulator: b_coef[%d] not finite", v);
+  std::vector<int32_t> row_op(c->n_cfg);
+  for (int v = 0; v < c->n_ops; ++v)
+    for (int64_t x = c->cfg_off[v]; x < c->cfg_off[v + 1]; ++x) row_op[x] = v;
+  c->has_sim = false;
+  if ((rc = upload(c, c->d_sim_a, a_coef, sizeof(double) * (size_t)na, "simulator coefficients")) ||
+      (rc = upload(c, c->d_sim_b, b_coef, sizeof(double) * (size_t)c->n_ops, "simulator coefficients")) ||
+      (rc = upload(c, c->d_sim_row_op, row_op.data(), sizeof(int32_t) * row_op.size(), "simulator row ops")) ||
+      (rc = sync_ctx(c, "set_simulator")))
+    return rc;
+  c->sim_sigma = sigma;
+  c->has_sim = true;
+  return LLAMA_OK;
+}
+
+int llama_simulate(llama_ctx* c, int64_t n, uint64_t seed, int64_t first, int32_t* d_rows, uint16_t* d_feat,
+                   float* d_y, void* stream) {
+  int rc = enter(c);
+  if (rc) return rc;
+  if (!c->has_sim) return fail(c, LLAMA_E_STATE, "simulate: call llama_set_simulator first");
+  if (n < 0 || first < 0 || first > ((int64_t)1 << 32) - n)
+    return fail(c, LLAMA_E_ARG, "simulate: need n >= 0, first >= 0 and first + n <= 2^32");
+  if (n == 0) return LLAMA_OK;
+  if (!d_rows || !d_feat || !d_y) return fail(c, LLAMA_E_ARG, "simulate: null pointer");
+  llama::SimArgs a{};
+  a.n = n;
+  a.first = first;
+  a.seed = seed;
+  a.n_rows = c->n_cfg;
+  a.n_hw = c->n_hw;
+  a.row_op = c->d_sim_row_op.as<int32_t>();
+  a.cfg_hw = c->d_cfg_hw.as<int32_t>();
+  a.cfg_lat = c->d_cfg_lat.as<int32_t>();
+  a.a_coef = c->d_sim_a.as<double>();
+  a.b_coef = c->d_sim_b.as<double>();
+  a.sigma = c->sim_sigma;
+  a.rows = d_rows;
+  a.feat = d_feat;
+  a.y = d_y;
+  hipError_t e = llama::launch_simulate(a, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(c, e, "simulate launch");
+  return LLAMA_OK;
+}
+
 int llama_decide_learned(llama_ctx* c, int64_t n, const int32_t* op, const int32_t* elapsed, const int32_t* slo,
                          const int64_t* queue, int32_t mode, const uint16_t* d_feat, float spread_max, int32_t* cfg,
                          uint8_t* flag, int32_t* d_lat_out, int64_t lat_stride, void* stream) {

@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include "llama_internal.h"
+#include "serve_device.h"
 
 namespace llama {
 namespace {
@@ -328,35 +329,173 @@ __device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b) {
   return q;
 }
 
+// Weights of the fused inference staged in LDS by a whole workgroup.
+struct LearnedStage {
+  const bf16* sW2;   // [256][256] K-permuted
+  const bf16* sW1;   // [256][32]
+  const float* sB1;  // [256]
+  const float* sB2;  // [256]
+  const float* sW3;  // [2][256], BF16 values
+  float b3_0, b3_1;
+};
+
+// Every thread of the workgroup copies its share; the caller synchronizes.
+__device__ __forceinline__ LearnedStage learned_stage(const LearnedArgs& s, unsigned char* lds) {
+  bf16* sW2 = reinterpret_cast<bf16*>(lds);
+  bf16* sW1 = sW2 + HID * HID;
+  float* sB1 = reinterpret_cast<float*>(sW1 + HID * IN);
+  float* sB2 = sB1 + HID;
+  float* sW3 = sB2 + HID;
+  const int tid = threadIdx.x;
+  const bf16* W3_16 = reinterpret_cast<const bf16*>(s.W3_16);
+  const uint4* src = reinterpret_cast<const uint4*>(s.W2p16);  // 16 bytes = 8 BF16
+  uint4* dst = reinterpret_cast<uint4*>(sW2);
+  for (int i = tid; i < HID * HID / 8; i += blockDim.x) dst[i] = src[i];
+  const uint4* src1 = reinterpret_cast<const uint4*>(s.W1_16);
+  uint4* dst1 = reinterpret_cast<uint4*>(sW1);
+  for (int i = tid; i < HID * IN / 8; i += blockDim.x) dst1[i] = src1[i];
+  for (int i = tid; i < HID; i += blockDim.x) {
+    sB1[i] = s.b1[i];
+    sB2[i] = s.b2[i];
+    sW3[i] = (float)W3_16[i];
+    sW3[HID + i] = (float)W3_16[HID + i];
+  }
+  return LearnedStage{sW2, sW1, sB1, sB2, sW3, s.b3[0], s.b3[1]};
+}
+
+// One valid invocation (op v, elapsed e, SLO sl, features feat_i) decided by
+// a whole wavefront: targets, every configuration's predicted p95 latency
+// (profile fallback), Eq. 1 over them; the choice and flag come back in every
+// lane.  lat_row, when given, receives each configuration's latency.
+template <int NHW>
+__device__ __forceinline__ void learned_decide_one(const DevTables& t, int mode, const int64_t* queue,
+                                                   const LearnedArgs& s, const LearnedStage& st, int v, int e,
+                                                   int sl, const bf16* feat_i, int32_t* lat_row, int32_t* cfg_out,
+                                                   uint8_t* flag_out) {
+  const bf16* sW2 = st.sW2;
+  const bf16* sW1 = st.sW1;
+  const float* sB1 = st.sB1;
+  const float* sB2 = st.sB2;
+  const float* sW3 = st.sW3;
+  const float b3_0 = st.b3_0, b3_1 = st.b3_1;
+  const bf16* E16 = reinterpret_cast<const bf16*>(s.E16);
+  const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+  const int64_t r0 = (int64_t)sl - e;
+  const int64_t ref = t.ref[v];
+  const int64_t W = t.W[(int64_t)mode * t.n_ops + v];
+  int32_t tgt[NHW];
+#pragma unroll
+  for (int h = 0; h < NHW; ++h) {
+    const int64_t R = remaining(r0, queue ? queue[h] : 0);
+    tgt[h] = R == 0 ? 0 : (int32_t)floor_div(ref * R, W);
+  }
+  const int a0 = t.cfg_off[v], n_c = t.cfg_off[v + 1] - a0;
+  // feature half of the layer-1 input fragment (lane groups 2 and 3)
+  bf16x8 ffrag;
+  if (g >= 2) ffrag = *reinterpret_cast<const bf16x8*>(feat_i + 8 * (g - 2));
+  uint32_t best = KEY_NONE;
+  uint64_t fast = ~0ull;
+  for (int c0 = 0; c0 < n_c; c0 += 64) {
+    // ---- layer 1: z1^T[unit][row] = W1 . x^T, 16 unit blocks x 4 row blocks
+    bf16x8 xfrag[4];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+      const int k = c0 + nb * 16 + r;
+      const int row = a0 + (k < n_c ? k : 0);
+      xfrag[nb] = g < 2 ? *reinterpret_cast<const bf16x8*>(E16 + (int64_t)row * EMB + 8 * g) : ffrag;
+    }
+    // hf[kb][nb] is the layer-2 input fragment of row 16nb + r for K block
+    // kb: units 32kb + 4g + q (slots 0..3) and 32kb + 16 + 4g + q (slots
+    // 4..7), exactly the layer-1 outputs of unit blocks 2kb and 2kb + 1.
+    bf16x8 hf[8][4];
+#pragma unroll
+    for (int mb = 0; mb < 16; ++mb) {
+      const bf16x8 w1 = *reinterpret_cast<const bf16x8*>(sW1 + (16 * mb + r) * IN + 8 * g);
+      // the accumulator starts at the bias of this lane's four units
+      const floatx4 b1 = *reinterpret_cast<const floatx4*>(sB1 + 16 * mb + 4 * g);
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        const floatx4 z = mfma16x16x32(w1, xfrag[nb], b1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) hf[mb >> 1][nb][4 * (mb & 1) + q] = (bf16)gelu(z[q]);
+      }
+    }
+    // ---- layers 2 and 3
+    float p0[4] = {0.f, 0.f, 0.f, 0.f}, p1[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int mb2 = 0; mb2 < 16; ++mb2) {
+      floatx4 acc[4];
+      const floatx4 b2 = *reinterpret_cast<const floatx4*>(sB2 + 16 * mb2 + 4 * g);
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) acc[nb] = b2;
+#pragma unroll
+      for (int kb = 0; kb < 8; ++kb) {
+        const bf16x8 w2 = *reinterpret_cast<const bf16x8*>(sW2 + (16 * mb2 + r) * HID + 32 * kb + 8 * g);
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma16x16x32(w2, hf[kb][nb], acc[nb]);
+      }
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int u = 16 * mb2 + 4 * g + q;
+          const float h2 = (float)(bf16)gelu(acc[nb][q]);
+          p0[nb] += sW3[u] * h2;
+          p1[nb] += sW3[HID + u] * h2;
+        }
+    }
+    // sum the four lane groups' partial dot products (same row r)
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+      p0[nb] += __shfl_xor(p0[nb], 16, 64);
+      p1[nb] += __shfl_xor(p1[nb], 16, 64);
+      p0[nb] += __shfl_xor(p0[nb], 32, 64);
+      p1[nb] += __shfl_xor(p1[nb], 32, 64);
+    }
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+      const int k = c0 + nb * 16 + r;
+      if (k >= n_c) continue;
+      const int x = a0 + k;
+      const float mu = p0[nb] + b3_0, q95 = p1[nb] + b3_1;
+      const float spread = q95 - mu;
+      int32_t L;
+      // predicted p95 when the spread is finite and in [0, spread_max], else the profile
+      if (spread >= 0.0f && spread <= s.spread_max && mu == mu && q95 == q95) {
+        const float ex = ceilf(expf(q95));
+        L = ex >= 2147483647.0f ? 0x7FFFFFFF : (int32_t)ex;
+      } else {
+        L = t.cfg_lat[x];
+      }
+      if (lat_row && g == 0) lat_row[k] = L;
+      const int h = t.cfg_hw[x];
+      int32_t tg = tgt[0];
+#pragma unroll
+      for (int hh = 1; hh < NHW; ++hh) tg = h == hh ? tgt[hh] : tg;
+      const uint32_t key = t.cfg_key[x];
+      if (L < tg) best = key < best ? key : best;
+      const uint64_t fk = ((uint64_t)(uint32_t)L << 16) | (uint64_t)k;
+      fast = fk < fast ? fk : fast;
+    }
+  }
+  // minimum over the wavefront (every lane group holds the same rows)
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t ob = __shfl_xor(best, d, 64);
+    best = ob < best ? ob : best;
+    const uint64_t of = __shfl_xor(fast, d, 64);
+    fast = of < fast ? of : fast;
+  }
+  *flag_out = best != KEY_NONE ? 1 : 0;
+  *cfg_out = best != KEY_NONE ? (int32_t)(best & 0xFFFFu) : (int32_t)(fast & 0xFFFFu);
+}
+
 template <int NHW>
 __global__ __launch_bounds__(256) void decide_learned_kernel(DevTables t, Batch b, LearnedArgs s) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-  bf16* sW2 = reinterpret_cast<bf16*>(lds);               // [256][256] K-permuted
-  bf16* sW1 = sW2 + HID * HID;                             // [256][32]
-  float* sB1 = reinterpret_cast<float*>(sW1 + HID * IN);   // [256]
-  float* sB2 = sB1 + HID;                                  // [256]
-  float* sW3 = sB2 + HID;                                  // [2][256], BF16 values
-  const int tid = threadIdx.x;
-  const bf16* W3_16 = reinterpret_cast<const bf16*>(s.W3_16);
-  const bf16* E16 = reinterpret_cast<const bf16*>(s.E16);
-  const bf16* feat = reinterpret_cast<const bf16*>(s.feat);
-  {
-    const uint4* src = reinterpret_cast<const uint4*>(s.W2p16);  // 16 bytes = 8 BF16
-    uint4* dst = reinterpret_cast<uint4*>(sW2);
-    for (int i = tid; i < HID * HID / 8; i += blockDim.x) dst[i] = src[i];
-    const uint4* src1 = reinterpret_cast<const uint4*>(s.W1_16);
-    uint4* dst1 = reinterpret_cast<uint4*>(sW1);
-    for (int i = tid; i < HID * IN / 8; i += blockDim.x) dst1[i] = src1[i];
-    for (int i = tid; i < HID; i += blockDim.x) {
-      sB1[i] = s.b1[i];
-      sB2[i] = s.b2[i];
-      sW3[i] = (float)W3_16[i];
-      sW3[HID + i] = (float)W3_16[HID + i];
-    }
-  }
+  const LearnedStage st = learned_stage(s, lds);
   __syncthreads();
-  const float b3_0 = s.b3[0], b3_1 = s.b3[1];
-  const int lane = tid & 63, g = lane >> 4, r = lane & 15;
+  const bf16* feat = reinterpret_cast<const bf16*>(s.feat);
+  const int tid = threadIdx.x, lane = tid & 63;
   const int64_t wave0 = (int64_t)blockIdx.x * LEARNED_WAVES + (tid >> 6);
   const int64_t n_waves = (int64_t)gridDim.x * LEARNED_WAVES;
   for (int64_t i = wave0; i < b.n; i += n_waves) {
@@ -369,117 +508,55 @@ __global__ __launch_bounds__(256) void decide_learned_kernel(DevTables t, Batch 
       }
       continue;
     }
-    const int64_t r0 = (int64_t)sl - e;
-    const int64_t ref = t.ref[v];
-    const int64_t W = t.W[(int64_t)b.mode * t.n_ops + v];
-    int32_t tgt[NHW];
-#pragma unroll
-    for (int h = 0; h < NHW; ++h) {
-      const int64_t R = remaining(r0, b.queue ? b.queue[h] : 0);
-      tgt[h] = R == 0 ? 0 : (int32_t)floor_div(ref * R, W);
-    }
-    const int a0 = t.cfg_off[v], n_c = t.cfg_off[v + 1] - a0;
-    // feature half of the layer-1 input fragment (lane groups 2 and 3)
-    bf16x8 ffrag;
-    if (g >= 2) ffrag = *reinterpret_cast<const bf16x8*>(feat + i * EMB + 8 * (g - 2));
-    uint32_t best = KEY_NONE;
-    uint64_t fast = ~0ull;
-    for (int c0 = 0; c0 < n_c; c0 += 64) {
-      // ---- layer 1: z1^T[unit][row] = W1 . x^T, 16 unit blocks x 4 row blocks
-      bf16x8 xfrag[4];
-#pragma unroll
-      for (int nb = 0; nb < 4; ++nb) {
-        const int k = c0 + nb * 16 + r;
-        const int row = a0 + (k < n_c ? k : 0);
-        xfrag[nb] = g < 2 ? *reinterpret_cast<const bf16x8*>(E16 + (int64_t)row * EMB + 8 * g) : ffrag;
-      }
-      // hf[kb][nb] is the layer-2 input fragment of row 16nb + r for K block
-      // kb: units 32kb + 4g + q (slots 0..3) and 32kb + 16 + 4g + q (slots
-      // 4..7), exactly the layer-1 outputs of unit blocks 2kb and 2kb + 1.
-      bf16x8 hf[8][4];
-#pragma unroll
-      for (int mb = 0; mb < 16; ++mb) {
-        const bf16x8 w1 = *reinterpret_cast<const bf16x8*>(sW1 + (16 * mb + r) * IN + 8 * g);
-        // the accumulator starts at the bias of this lane's four units
-        const floatx4 b1 = *reinterpret_cast<const floatx4*>(sB1 + 16 * mb + 4 * g);
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-          const floatx4 z = mfma16x16x32(w1, xfrag[nb], b1);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) hf[mb >> 1][nb][4 * (mb & 1) + q] = (bf16)gelu(z[q]);
-        }
-      }
-      // ---- layers 2 and 3
-      float p0[4] = {0.f, 0.f, 0.f, 0.f}, p1[4] = {0.f, 0.f, 0.f, 0.f};
-      for (int mb2 = 0; mb2 < 16; ++mb2) {
-        floatx4 acc[4];
-        const floatx4 b2 = *reinterpret_cast<const floatx4*>(sB2 + 16 * mb2 + 4 * g);
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) acc[nb] = b2;
-#pragma unroll
-        for (int kb = 0; kb < 8; ++kb) {
-          const bf16x8 w2 = *reinterpret_cast<const bf16x8*>(sW2 + (16 * mb2 + r) * HID + 32 * kb + 8 * g);
-#pragma unroll
-          for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma16x16x32(w2, hf[kb][nb], acc[nb]);
-        }
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int u = 16 * mb2 + 4 * g + q;
-            const float h2 = (float)(bf16)gelu(acc[nb][q]);
-            p0[nb] += sW3[u] * h2;
-            p1[nb] += sW3[HID + u] * h2;
-          }
-      }
-      // sum the four lane groups' partial dot products (same row r)
-#pragma unroll
-      for (int nb = 0; nb < 4; ++nb) {
-        p0[nb] += __shfl_xor(p0[nb], 16, 64);
-        p1[nb] += __shfl_xor(p1[nb], 16, 64);
-        p0[nb] += __shfl_xor(p0[nb], 32, 64);
-        p1[nb] += __shfl_xor(p1[nb], 32, 64);
-      }
-#pragma unroll
-      for (int nb = 0; nb < 4; ++nb) {
-        const int k = c0 + nb * 16 + r;
-        if (k >= n_c) continue;
-        const int x = a0 + k;
-        const float mu = p0[nb] + b3_0, q95 = p1[nb] + b3_1;
-        const float spread = q95 - mu;
-        int32_t L;
-        // predicted p95 when the spread is finite and in [0, spread_max], else the profile
-        if (spread >= 0.0f && spread <= s.spread_max && mu == mu && q95 == q95) {
-          const float ex = ceilf(expf(q95));
-          L = ex >= 2147483647.0f ? 0x7FFFFFFF : (int32_t)ex;
-        } else {
-          L = t.cfg_lat[x];
-        }
-        if (s.lat_out && g == 0) s.lat_out[i * s.lat_stride + k] = L;
-        const int h = t.cfg_hw[x];
-        int32_t tg = tgt[0];
-#pragma unroll
-        for (int hh = 1; hh < NHW; ++hh) tg = h == hh ? tgt[hh] : tg;
-        const uint32_t key = t.cfg_key[x];
-        if (L < tg) best = key < best ? key : best;
-        const uint64_t fk = ((uint64_t)(uint32_t)L << 16) | (uint64_t)k;
-        fast = fk < fast ? fk : fast;
-      }
-    }
-    // minimum over the wavefront (every lane group holds the same rows)
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t ob = __shfl_xor(best, d, 64);
-      best = ob < best ? ob : best;
-      const uint64_t of = __shfl_xor(fast, d, 64);
-      fast = of < fast ? of : fast;
-    }
+    int32_t cfg;
+    uint8_t f;
+    learned_decide_one<NHW>(t, b.mode, b.queue, s, st, v, e, sl, feat + i * EMB,
+                            s.lat_out ? s.lat_out + i * s.lat_stride : nullptr, &cfg, &f);
     if (lane == 0) {
-      const bool feasible = best != KEY_NONE;
-      b.cfg[i] = feasible ? (int32_t)(best & 0xFFFFu) : (int32_t)(fast & 0xFFFFu);
-      if (b.flag) b.flag[i] = feasible ? 1 : 0;
+      b.cfg[i] = cfg;
+      if (b.flag) b.flag[i] = f;
     }
   }
+}
+
+// Persistent learned decisions for the serving ring: the weights are staged
+// once per workgroup, then each wavefront claims one published request at a
+// time (exit rules as serve_plain_kernel).
+template <int NHW>
+__global__ __launch_bounds__(256) void serve_learned_kernel(DevTables t, ServeRing r, LearnedArgs s) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  const LearnedStage st = learned_stage(s, lds);
+  __syncthreads();
+  const bf16* feat = reinterpret_cast<const bf16*>(r.feat);
+  const int lane = threadIdx.x & 63;
+  int answered = 0;
+  int* clock = blockIdx.x == 0 && threadIdx.x < 64 ? &answered : nullptr;
+  serve_enter(r, lane);
+  const unsigned long long start = (unsigned long long)wall_clock64();
+  unsigned long long last = start;
+  for (;;) {
+    const unsigned long long now = (unsigned long long)wall_clock64();
+    if (now - start > r.life_ticks) break;
+    const ServeClaim c = serve_claim(r, lane, 1, clock);
+    if (c.stop) break;
+    if (c.count == 0) {
+      if (serve_idle(r, now, last)) break;
+      __builtin_amdgcn_s_sleep(8);
+      continue;
+    }
+    last = now;
+    const long long seq = c.first, slot = seq % r.cap;
+    const int4 q = r.req[slot];
+    int32_t cfg = -1;
+    uint8_t f = 0;
+    if ((unsigned)q.x >= (unsigned)t.n_ops || (q.y | q.z) < 0) {
+      if (lane == 0) atomicOr(t.err, 1u);
+    } else {
+      learned_decide_one<NHW>(t, r.mode, nullptr, s, st, q.x, q.y, q.z, feat + slot * EMB, nullptr, &cfg, &f);
+    }
+    if (lane == 0) serve_write(r, seq, slot, cfg, f);
+  }
+  serve_leave(r, lane);
 }
 
 inline unsigned grid1(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -606,6 +683,49 @@ hipError_t launch_decide_learned(const DevTables& t, const Batch& b, const Learn
       return hipErrorInvalidValue;
   }
 #undef LLAMA_LEARNED_CASE
+  return hipGetLastError();
+}
+
+hipError_t prepare_serve_learned(const DevTables& t) {
+  switch (t.n_hw) {
+#define LLAMA_SERVE_PREP_CASE(N)                                                                      \
+  case N:                                                                                             \
+    return hipFuncSetAttribute((const void*)serve_learned_kernel<N>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                               (int)LEARNED_LDS);
+    LLAMA_SERVE_PREP_CASE(1)
+    LLAMA_SERVE_PREP_CASE(2)
+    LLAMA_SERVE_PREP_CASE(3)
+    LLAMA_SERVE_PREP_CASE(4)
+    LLAMA_SERVE_PREP_CASE(5)
+    LLAMA_SERVE_PREP_CASE(6)
+    LLAMA_SERVE_PREP_CASE(7)
+    LLAMA_SERVE_PREP_CASE(8)
+#undef LLAMA_SERVE_PREP_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_serve_learned(const DevTables& t, const ServeRing& r, const LearnedArgs& a, int workgroups,
+                                hipStream_t s) {
+  if (workgroups < 1 || r.cap < 1 || !r.feat) return hipErrorInvalidValue;
+#define LLAMA_SERVE_LEARNED_CASE(N)                                                                   \
+  case N:                                                                                             \
+    hipLaunchKernelGGL(serve_learned_kernel<N>, dim3(workgroups), dim3(64 * LEARNED_WAVES), LEARNED_LDS, s, t, r, a); \
+    break;
+  switch (t.n_hw) {
+    LLAMA_SERVE_LEARNED_CASE(1)
+    LLAMA_SERVE_LEARNED_CASE(2)
+    LLAMA_SERVE_LEARNED_CASE(3)
+    LLAMA_SERVE_LEARNED_CASE(4)
+    LLAMA_SERVE_LEARNED_CASE(5)
+    LLAMA_SERVE_LEARNED_CASE(6)
+    LLAMA_SERVE_LEARNED_CASE(7)
+    LLAMA_SERVE_LEARNED_CASE(8)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef LLAMA_SERVE_LEARNED_CASE
   return hipGetLastError();
 }
 

@@ -242,6 +242,35 @@ def test_update_latencies_recomputes_everything():
     assert_full_parity(r)
 
 
+@pytest.mark.parametrize("maker", ["c1", "c2", "c3"])
+def test_full_scan_schedule_classes(maker):
+    # every crossover of the full scan's schedule table (pure lanes =
+    # configurations, pure lanes = invocations, mixed) and the autotuned one
+    # decide bit-exactly like the oracle, with and without queueing times;
+    # c1 has 8 configurations per op (16-lane groups), c2 64-512, c3 16-256
+    # with up to ~300 invocations per op
+    w = {"c1": lambda: wl.make_c1(queue=True),
+         "c2": lambda: wl.make_c2(seed=15, n_pipelines=24, n_inv=40_000),
+         "c3": lambda: wl.make_c3(seed=16, n_pipelines=96, n_inv=60_000, max_cfg=256)}[maker]()
+    r = Run(w)
+    Q = [700, 0, 25_000, 3][:w.n_hw]
+    for mode in (PAPER, PROB):
+        c_or, f_or = r.P.decide(mode)
+        cq_or, fq_or = r.P.decide(mode, Q=Q)
+        for num, den in ((0, 1), (1 << 20, 1), (1, 1), (1, 4), (4, 1)):
+            r.L.set_full_schedule(num, den)
+            c, f = r.decide(mode, B.SCAN_FULL)
+            assert np.array_equal(c, c_or) and np.array_equal(f, f_or), (num, den)
+            c, f = r.decide(mode, B.SCAN_FULL, Q)
+            assert np.array_equal(c, cq_or) and np.array_equal(f, fq_or), (num, den)
+        (num, den), us = r.L.autotune_full(r.op, r.el, r.slo, mode)
+        say(f"{maker} mode {mode}: full-scan crossover {num}/{den}, {us:.1f} us")
+        c, f = r.decide(mode, B.SCAN_FULL)
+        assert np.array_equal(c, c_or) and np.array_equal(f, f_or)
+    with pytest.raises(B.LlamaError):
+        r.L.set_full_schedule(1, 0)
+
+
 @pytest.mark.parametrize("maker", ["c2", "c3"])
 def test_relax_one_slack_mode(maker):
     # records rebuilt for one slack mode: that mode stays bit-exact, the

@@ -2,7 +2,9 @@
 
 Each decision depends only on its own invocation, so a request's result must
 be the same decided alone as in any mix; this is checked bit-exactly in both
-the plain and the learned modes.
+the plain and the learned modes, and every served decision is checked
+against the CPU oracle: Alg. 1 + Eq. 1 in the plain form, Eq. 1 over the
+GPU's own predicted latencies in the learned form.
 """
 import math
 import sys
@@ -11,6 +13,7 @@ import time
 import numpy as np
 import pytest
 
+import oracle
 from paper_2102_01887_amd import binding as B
 from paper_2102_01887_amd import workloads as wl
 
@@ -61,6 +64,8 @@ def test_plain_mix_equals_alone():
     say(f"plain serving stats: {st}")
     assert np.array_equal(t, np.arange(w.n_inv))          # each request exactly once, in order
     assert st["batches"] > 1 and st["max_batch_seen"] <= 1024
+    c_or, f_or = oracle.Problem(w).decide(0)
+    assert np.array_equal(c, c_or) and np.array_equal(f, f_or)
     c_all, f_all = L.decide(dev(torch, w.inv_op), dev(torch, w.elapsed), dev(torch, w.slo))
     torch.cuda.synchronize()
     assert np.array_equal(c, c_all.cpu().numpy()) and np.array_equal(f, f_all.cpu().numpy())
@@ -83,10 +88,16 @@ def test_learned_mix_equals_alone():
     srv.close()
     assert np.array_equal(t, np.arange(w.n_inv))
     feat_t = dev(torch, feat_bits.view(np.int16))
+    lat = torch.empty(w.n_inv * 64, dtype=torch.int32, device="cuda")
     c_all, f_all = L.decide_learned(dev(torch, w.inv_op), dev(torch, w.elapsed), dev(torch, w.slo),
-                                    feat_t)
+                                    feat_t, lat_out=lat, lat_stride=64)
     torch.cuda.synchronize()
     assert np.array_equal(c, c_all.cpu().numpy()) and np.array_equal(f, f_all.cpu().numpy())
+    # the oracle's Eq. 1 over the GPU's predicted latencies and the oracle's own targets
+    tgt = oracle.Problem(w).targets(0)
+    c_or, f_or = oracle.select_lat(w.inv_op, tgt, w.n_hw, w.cfg_off, w.hw, w.batch,
+                                   lat.cpu().numpy().reshape(w.n_inv, 64), w.cost)
+    assert np.array_equal(c, c_or) and np.array_equal(f, f_or)
     for i in np.random.default_rng(3).choice(w.n_inv, 20, replace=False):
         ca, fa = L.decide_learned(dev(torch, w.inv_op[i:i + 1]), dev(torch, w.elapsed[i:i + 1]),
                                   dev(torch, w.slo[i:i + 1]), feat_t[i:i + 1])
@@ -115,6 +126,8 @@ def test_memory_admission():
         done += len(t)
     st = srv.stats()
     srv.close()
+    # the ring holds what the budget buys: 100 slots of the 4,096 asked for
+    assert st["capacity"] == 100 and bpr == 32
     assert st["peak_bytes_in_use"] <= 100 * bpr and st["rejected"] == 900 + 5 + 100
 
 
@@ -154,3 +167,66 @@ def test_poisson_stream_latency():
     p50, p99 = np.percentile(lat, [50, 99]) / 1e3
     say(f"poisson 100k/s: {len(lat)} decisions, p50 {p50:.1f} us, p99 {p99:.1f} us, sustained {rate:.0f}/s, {st}")
     assert len(lat) > 30_000 and (lat > 0).all() and p99 < 1e6
+
+
+def test_relaunch_after_idle_exit():
+    # the persistent kernel exits after 20 ms without work; requests published
+    # later must start it again, and decisions keep matching the oracle
+    _torch()
+    w = wl.make_c2(seed=23, n_pipelines=16, n_inv=3000)
+    L = B.Llama(0).load(w)
+    srv = B.Server(L, n_slots=1024, max_batch=64, max_inflight=2)
+    got_c, got_f = [], []
+    for part in range(3):
+        sl = slice(1000 * part, 1000 * (part + 1))
+        k, _ = srv.submit(w.inv_op[sl], w.elapsed[sl], w.slo[sl])
+        assert k == 1000
+        n = 0
+        while n < 1000:
+            t, c, f, lat = srv.poll(wait_ms=100)
+            assert (lat > 0).all() and (lat < 1_000_000_000).all()
+            n += len(t)
+            got_c.append(c)
+            got_f.append(f)
+        time.sleep(0.06)
+    st = srv.stats()
+    srv.close()
+    say(f"relaunch: {st}")
+    assert st["kernel_launches"] >= 3 and st["decided"] == 3000 and st["in_flight_batches"] == 0
+    assert 0 <= st["clock_rtt_ns"] < 1_000_000
+    c_or, f_or = oracle.Problem(w).decide(0)
+    assert np.array_equal(np.concatenate(got_c), c_or) and np.array_equal(np.concatenate(got_f), f_or)
+
+
+def test_latency_clock_does_not_drift():
+    # isolated requests for 0.6 s: the device-stamped latency must not grow
+    # with the time since open (the device clock is re-anchored to the host's
+    # while the kernel runs), and every latency is positive
+    _torch()
+    w = wl.make_c2(seed=24, n_pipelines=16, n_inv=2000)
+    L = B.Llama(0).load(w)
+    srv = B.Server(L, n_slots=1024, max_batch=64, max_inflight=2)
+    lat, when = [], []
+    t_start = time.monotonic_ns()
+    i = 0
+    while time.monotonic_ns() - t_start < 6e8:
+        t0 = time.monotonic_ns()
+        k, _ = srv.submit(w.inv_op[i:i + 1], w.elapsed[i:i + 1], w.slo[i:i + 1])
+        assert k == 1
+        n = 0
+        while n == 0:
+            t, c, f, l = srv.poll(wait_ms=100)
+            n = len(t)
+            lat.extend(l.tolist())
+        when.append((t0 - t_start) * 1e-9)
+        i = (i + 1) % 2000
+        while time.monotonic_ns() - t0 < 1_000_000:
+            pass
+    st = srv.stats()
+    srv.close()
+    lat, when = np.asarray(lat) / 1e3, np.asarray(when)
+    early, late = np.median(lat[when < 0.15]), np.median(lat[when > 0.45])
+    say(f"isolated requests: {len(lat)}, p50 first 0.15 s {early:.1f} us, last 0.15 s {late:.1f} us; {st}")
+    assert (lat > 0).all()
+    assert abs(late - early) < 15.0
+    assert st["clock_anchors"] >= 10 and abs(st["clock_rate_ppb"]) < 2_000_000
