@@ -84,21 +84,38 @@ def schedule_kernel(sched):
     return f"void decide_indexed_kernel<{ipt}, {nt}>"
 
 
+DECISION_PATH_END = b"// DECISION-PATH-END"
+
+
+def decision_path_digest():
+    """sha256 of the decision path's device source: llama_kernels.hip up to
+    its DECISION-PATH-END marker (records, relaxation, decision kernels and
+    their launchers) and the shared declarations in llama_internal.h."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2102_01887_amd", "csrc")
+    with open(os.path.join(csrc, "llama_kernels.hip"), "rb") as f:
+        text = f.read()
+    cut = text.find(DECISION_PATH_END)
+    if cut < 0:
+        raise RuntimeError("llama_kernels.hip has no DECISION-PATH-END marker")
+    h = hashlib.sha256(text[:cut])
+    with open(os.path.join(csrc, "llama_internal.h"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()
+
+
 def measured_traffic(workload, kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a device copy), or None
-    when there is none or the kernel source has changed since it was taken."""
-    import hashlib
-    here = os.path.dirname(os.path.abspath(__file__))
-    path = os.path.join(here, "profiles", f"decide_plain_{workload}_hbm_traffic.md")
-    src = os.path.join(here, "paper_2102_01887_amd", "csrc", "llama_kernels.hip")
+    when there is none or the decision path's source has changed since it
+    was taken."""
+    path = os.path.join(ROOT, "profiles", f"decide_plain_{workload}_hbm_traffic.md")
     if not os.path.exists(path):
         return None
-    with open(src, "rb") as f:
-        digest = hashlib.sha256(f.read()).hexdigest()
+    digest = decision_path_digest()
     recorded, table = None, {}
     for line in open(path):
-        if line.startswith("kernel source sha256:"):
+        if line.startswith("decision path sha256:"):
             recorded = line.split(":", 1)[1].strip()
         elif line.startswith("traffic_bytes_per_launch "):
             name, value = line[len("traffic_bytes_per_launch "):].rsplit(":", 1)
@@ -138,6 +155,25 @@ def time_graph(torch, stream, g, replays):
         b.record(stream)
     b.synchronize()
     return a.elapsed_time(b) / replays
+
+
+def device_copy_gbs(torch, stream, mib=512, reps=10):
+    """Bytes read + written per second by a device-to-device copy of `mib`
+    MiB (the runtime's copy kernel), HIP events on the copy stream: the
+    bandwidth a plain streaming kernel reaches, a second denominator."""
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    with torch.cuda.stream(stream):
+        dst.copy_(src)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            dst.copy_(src)
+        b.record(stream)
+    b.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    return 2 * (mib << 20) / (ms * 1e-3) / 1e9
 
 
 # BF16 dense MFMA peak (MI355X) in TFLOP/s; FLOPs per surrogate row (forward)
@@ -686,6 +722,7 @@ def main():
     ms_full = time_graph(torch, s, g_full, 3) / max(1, args.kernel_reps // 10)
     ms_wave = time_graph(torch, s, g_wave, 2) / 2
     ms_relax = time_graph(torch, s, g_relax, 5) / args.kernel_reps
+    copy_gbs = device_copy_gbs(torch, s)
 
     # algorithmic bytes of one decide launch (indexed form):
     # 12 B invocation input + 4 B choice + 1 B flag per invocation, plus each
@@ -789,7 +826,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.workload, schedule_kernel(tuned[0])),
                      "kernel": schedule_kernel(tuned[0]), "kernel_ms": ms_dec,
-                     "algo_bytes": algo_bytes},
+                     "algo_bytes": algo_bytes, "copy_gbs": copy_gbs,
+                     "frac_of_copy": achieved / copy_gbs},
         "cpu_baseline": cpu,
         "bit_exact": bit_exact,
         "ms_per_step_device": ms_step_dev,

@@ -1008,6 +1008,102 @@ __global__ __launch_bounds__(1024) void decide_lds4_kernel(DevTables t, Batch b,
   }
 }
 
+#define LLAMA_DISPATCH_NHW(KERNEL, GRID, BLOCK, STREAM, ...)                         \
+  switch (t.n_hw) {                                                                  \
+    case 1: hipLaunchKernelGGL(KERNEL<1>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
+    case 2: hipLaunchKernelGGL(KERNEL<2>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
+    case 3: hipLaunchKernelGGL(KERNEL<3>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
+    case 4: hipLaunchKernelGGL(KERNEL<4>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
+    case 5: hipLaunchKernelGGL(KERNEL<5>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
+    case 6: hipLaunchKernelGGL(KERNEL<6>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
+    case 7: hipLaunchKernelGGL(KERNEL<7>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
+    case 8: hipLaunchKernelGGL(KERNEL<8>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
+    default: return hipErrorInvalidValue;                                            \
+  }
+
+inline unsigned blocks_for(int64_t n, int per_block) {
+  return (unsigned)((n + per_block - 1) / per_block);
+}
+
+}  // namespace
+
+hipError_t launch_records(const DevTables& t, int mode0, int n_modes, const int64_t* queue, uint4* rec,
+                          uint4* rec_tail, uint4* rec_tail2, uint2* ovf, hipStream_t s) {
+  if (t.n_ops <= 0) return hipSuccess;
+  LLAMA_DISPATCH_NHW(records_kernel, dim3(t.n_ops), dim3(64), s, t, mode0, n_modes, queue, rec, rec_tail, rec_tail2,
+                     ovf);
+  return hipGetLastError();
+}
+
+hipError_t launch_relax(const DevTables& t, int modes, hipStream_t s) {
+  if (modes < 1 || modes > 3) return hipErrorInvalidValue;
+  if (t.n_pipelines <= 0) return hipSuccess;
+  if (t.max_pipe_ops <= 64) {
+    // one op per lane: records in the same launch
+    hipLaunchKernelGGL(relax_kernel<true>, dim3(t.n_pipelines), dim3(128), relax_lds_bytes(t, true), s, t, modes);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(relax_kernel<false>, dim3(t.n_pipelines), dim3(64), relax_lds_bytes(t, false), s, t, modes);
+  const int64_t threads = (modes == 3 ? 2 : 1) * (int64_t)t.n_ops;
+  if (t.n_ops > 0) hipLaunchKernelGGL(op_records_kernel, dim3(blocks_for(threads, 256)), dim3(256), 0, s, t, modes);
+  return hipGetLastError();
+}
+
+hipError_t launch_decide_indexed(const DevTables& t, const Batch& b, hipStream_t s) {
+  if (b.n == 0) return hipSuccess;
+  const uint4* rec = t.rec + (int64_t)b.mode * t.n_ops;
+  const uint4* tail = t.rec_tail + (int64_t)b.mode * t.n_ops * REC_TAIL_VECS;
+  const uint4* tail2 = t.rec_tail2 + (int64_t)b.mode * t.n_ops * REC_TAIL2_VECS;
+  const uint2* ovf = t.ovf + (int64_t)b.mode * t.n_front;
+  if (b.queue) {
+    // records for this call's queueing times, in the context's own buffers
+    hipError_t e = launch_records(t, b.mode, 1, b.queue, t.rec_q, t.rec_tail_q, t.rec_tail2_q, t.ovf_q, s);
+    if (e != hipSuccess) return e;
+    rec = t.rec_q;
+    tail = t.rec_tail_q;
+    tail2 = t.rec_tail2_q;
+    ovf = t.ovf_q;
+  }
+  switch (t.decide_sched) {
+    case SCHED_LDS: {
+      if (t.n_ops > LDS_REC_MAX_OPS) return hipErrorInvalidValue;
+      const size_t lds = sizeof(uint4) * (size_t)t.n_ops;
+      const bool vec = ((reinterpret_cast<uintptr_t>(b.op) | reinterpret_cast<uintptr_t>(b.elapsed) |
+                         reinterpret_cast<uintptr_t>(b.slo) | reinterpret_cast<uintptr_t>(b.cfg)) & 15u) == 0 &&
+                       (reinterpret_cast<uintptr_t>(b.flag) & 3u) == 0;
+      const void* fn = vec ? (const void*)decide_lds4_kernel : (const void*)decide_lds_kernel;
+      hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)(sizeof(uint4) * LDS_REC_MAX_OPS));
+      if (e != hipSuccess) return e;
+      const int64_t per_block = 1024 * 4;
+      int64_t blocks = (b.n + per_block - 1) / per_block;
+      if (blocks > t.n_cu) blocks = t.n_cu;
+      if (vec)
+        hipLaunchKernelGGL(decide_lds4_kernel, dim3((unsigned)blocks), dim3(1024), lds, s, t, b, rec, tail, tail2, ovf);
+      else
+        hipLaunchKernelGGL(decide_lds_kernel, dim3((unsigned)blocks), dim3(1024), lds, s, t, b, rec, tail, tail2, ovf);
+      break;
+    }
+#define LLAMA_DIRECT(IPT, NT) \
+  hipLaunchKernelGGL((decide_indexed_kernel<IPT, NT>), dim3(blocks_for(b.n, 256 * IPT)), dim3(256), 0, s, t, b, rec, \
+                     tail, tail2, ovf)
+    case SCHED_DIRECT2: LLAMA_DIRECT(2, false); break;
+    case SCHED_DIRECT4: LLAMA_DIRECT(4, false); break;
+    case SCHED_DIRECT1_NT: LLAMA_DIRECT(1, true); break;
+    case SCHED_DIRECT2_NT: LLAMA_DIRECT(2, true); break;
+    case SCHED_DIRECT4_NT: LLAMA_DIRECT(4, true); break;
+    default: LLAMA_DIRECT(1, false); break;
+#undef LLAMA_DIRECT
+  }
+  return hipGetLastError();
+}
+
+// The decision path (records, relaxation, indexed decisions) ends here; the
+// counter summaries of the decision kernels fingerprint the text above.
+// DECISION-PATH-END
+
+namespace {
+
 // ---------------------------------------------------------------------------
 // Full scan, the plain Eq. 1 evaluation of every configuration.
 //   bucket_count / bucket_offsets / bucket_scatter: counting sort of the
@@ -1357,10 +1453,6 @@ __global__ __launch_bounds__(256) void select_rows_kernel(DevTables t, Batch b, 
       if (b.flag) b.flag[i] = best != KEY_NONE ? 1 : 0;
     }
   }
-}
-
-inline unsigned blocks_for(int64_t n, int per_block) {
-  return (unsigned)((n + per_block - 1) / per_block);
 }
 
 // ---------------------------------------------------------------------------
@@ -2010,25 +2102,13 @@ __global__ __launch_bounds__(256) void batching_scan_kernel(DevTables t, Batch b
   }
 }
 
-#define LLAMA_DISPATCH_NHW(KERNEL, GRID, BLOCK, STREAM, ...)                         \
-  switch (t.n_hw) {                                                                  \
-    case 1: hipLaunchKernelGGL(KERNEL<1>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
-    case 2: hipLaunchKernelGGL(KERNEL<2>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
-    case 3: hipLaunchKernelGGL(KERNEL<3>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
-    case 4: hipLaunchKernelGGL(KERNEL<4>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
-    case 5: hipLaunchKernelGGL(KERNEL<5>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
-    case 6: hipLaunchKernelGGL(KERNEL<6>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
-    case 7: hipLaunchKernelGGL(KERNEL<7>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
-    case 8: hipLaunchKernelGGL(KERNEL<8>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
-    default: return hipErrorInvalidValue;                                            \
-  }
 
 // ---------------------------------------------------------------------------
 // Serving: persistent plain decisions.  Each wavefront claims up to r.chunk
 // published requests (lanes = requests), decides them from the records and
 // writes result and device time into the ring; it exits when the host sets
-// stop, after idle_ticks without a claim, or once it has run life_ticks (it
-// never exits holding a claim).  The host relaunches the kernel whenever it
+// stop, once no wavefront has claimed anything for idle_ticks, or once it has
+// run life_ticks (it never exits holding a claim).  The host relaunches the kernel whenever it
 // has exited with requests outstanding.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void serve_plain_kernel(DevTables t, ServeRing r) {
@@ -2086,28 +2166,6 @@ __global__ void clock_probe_kernel(const int* flag, int* ack, unsigned long long
 }
 
 }  // namespace
-
-hipError_t launch_records(const DevTables& t, int mode0, int n_modes, const int64_t* queue, uint4* rec,
-                          uint4* rec_tail, uint4* rec_tail2, uint2* ovf, hipStream_t s) {
-  if (t.n_ops <= 0) return hipSuccess;
-  LLAMA_DISPATCH_NHW(records_kernel, dim3(t.n_ops), dim3(64), s, t, mode0, n_modes, queue, rec, rec_tail, rec_tail2,
-                     ovf);
-  return hipGetLastError();
-}
-
-hipError_t launch_relax(const DevTables& t, int modes, hipStream_t s) {
-  if (modes < 1 || modes > 3) return hipErrorInvalidValue;
-  if (t.n_pipelines <= 0) return hipSuccess;
-  if (t.max_pipe_ops <= 64) {
-    // one op per lane: records in the same launch
-    hipLaunchKernelGGL(relax_kernel<true>, dim3(t.n_pipelines), dim3(128), relax_lds_bytes(t, true), s, t, modes);
-    return hipGetLastError();
-  }
-  hipLaunchKernelGGL(relax_kernel<false>, dim3(t.n_pipelines), dim3(64), relax_lds_bytes(t, false), s, t, modes);
-  const int64_t threads = (modes == 3 ? 2 : 1) * (int64_t)t.n_ops;
-  if (t.n_ops > 0) hipLaunchKernelGGL(op_records_kernel, dim3(blocks_for(threads, 256)), dim3(256), 0, s, t, modes);
-  return hipGetLastError();
-}
 
 hipError_t launch_targets(const DevTables& t, const Batch& b, hipStream_t s) {
   if (b.n == 0) return hipSuccess;
@@ -2203,55 +2261,6 @@ hipError_t launch_decide_alpha(const DevTables& t, const Batch& b, hipStream_t s
     LLAMA_DISPATCH_NHW(decide_alpha_kernel, dim3(blocks_for(b.n, 256)), dim3(256), s, t, b);
   } else {
     hipLaunchKernelGGL(decide_alpha_merged_kernel, dim3(blocks_for(b.n, 256)), dim3(256), 0, s, t, b);
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_decide_indexed(const DevTables& t, const Batch& b, hipStream_t s) {
-  if (b.n == 0) return hipSuccess;
-  const uint4* rec = t.rec + (int64_t)b.mode * t.n_ops;
-  const uint4* tail = t.rec_tail + (int64_t)b.mode * t.n_ops * REC_TAIL_VECS;
-  const uint4* tail2 = t.rec_tail2 + (int64_t)b.mode * t.n_ops * REC_TAIL2_VECS;
-  const uint2* ovf = t.ovf + (int64_t)b.mode * t.n_front;
-  if (b.queue) {
-    // records for this call's queueing times, in the context's own buffers
-    hipError_t e = launch_records(t, b.mode, 1, b.queue, t.rec_q, t.rec_tail_q, t.rec_tail2_q, t.ovf_q, s);
-    if (e != hipSuccess) return e;
-    rec = t.rec_q;
-    tail = t.rec_tail_q;
-    tail2 = t.rec_tail2_q;
-    ovf = t.ovf_q;
-  }
-  switch (t.decide_sched) {
-    case SCHED_LDS: {
-      if (t.n_ops > LDS_REC_MAX_OPS) return hipErrorInvalidValue;
-      const size_t lds = sizeof(uint4) * (size_t)t.n_ops;
-      const bool vec = ((reinterpret_cast<uintptr_t>(b.op) | reinterpret_cast<uintptr_t>(b.elapsed) |
-                         reinterpret_cast<uintptr_t>(b.slo) | reinterpret_cast<uintptr_t>(b.cfg)) & 15u) == 0 &&
-                       (reinterpret_cast<uintptr_t>(b.flag) & 3u) == 0;
-      const void* fn = vec ? (const void*)decide_lds4_kernel : (const void*)decide_lds_kernel;
-      hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)(sizeof(uint4) * LDS_REC_MAX_OPS));
-      if (e != hipSuccess) return e;
-      const int64_t per_block = 1024 * 4;
-      int64_t blocks = (b.n + per_block - 1) / per_block;
-      if (blocks > t.n_cu) blocks = t.n_cu;
-      if (vec)
-        hipLaunchKernelGGL(decide_lds4_kernel, dim3((unsigned)blocks), dim3(1024), lds, s, t, b, rec, tail, tail2, ovf);
-      else
-        hipLaunchKernelGGL(decide_lds_kernel, dim3((unsigned)blocks), dim3(1024), lds, s, t, b, rec, tail, tail2, ovf);
-      break;
-    }
-#define LLAMA_DIRECT(IPT, NT) \
-  hipLaunchKernelGGL((decide_indexed_kernel<IPT, NT>), dim3(blocks_for(b.n, 256 * IPT)), dim3(256), 0, s, t, b, rec, \
-                     tail, tail2, ovf)
-    case SCHED_DIRECT2: LLAMA_DIRECT(2, false); break;
-    case SCHED_DIRECT4: LLAMA_DIRECT(4, false); break;
-    case SCHED_DIRECT1_NT: LLAMA_DIRECT(1, true); break;
-    case SCHED_DIRECT2_NT: LLAMA_DIRECT(2, true); break;
-    case SCHED_DIRECT4_NT: LLAMA_DIRECT(4, true); break;
-    default: LLAMA_DIRECT(1, false); break;
-#undef LLAMA_DIRECT
   }
   return hipGetLastError();
 }
