@@ -588,7 +588,14 @@ int llama_surrogate_forward(llama_ctx *ctx, int64_t n, const int32_t *d_rows,
  * observed ln latency): forward, backward into the gradient buffer and, when
  * `update` is non-zero, one AdamW step (betas 0.9, 0.999, eps 1e-8; decoupled
  * weight decay on E, W1, W2, W3) with learning rate lr.  d_loss_sum, when not
- * NULL, has the batch's summed loss added to it. */
+ * NULL, has the batch's summed loss added to it.  Two launches per 16,384
+ * rows: a fused forward + backward kernel (one workgroup per 64 rows, partial
+ * gradients per chunk) and a kernel that sums the chunks in order, applies
+ * AdamW and writes the BF16 shadows.  The partial-gradient workspace
+ * (299 KB per 64 rows, at most 76.5 MB) is allocated on the first batch of a
+ * new size, so reserve it (one uncaptured step of the largest batch) before
+ * capturing steps into a graph.  Row ids outside [0, n_cfg) train as zero
+ * embedding rows. */
 int llama_surrogate_train_step(llama_ctx *ctx, int64_t batch, const int32_t *d_rows,
                                const uint16_t *d_feat, const float *d_y, float lr,
                                float weight_decay, int32_t update, float *d_loss_sum,

@@ -33,8 +33,12 @@ struct Surrogate {
   int64_t n_rows = 0, n_params = 0, step = 0;
   DevBuf master, adam_m, adam_v, grad;              // fp32 [n_params], layout E, W1, b1, W2, b2, W3, b3
   DevBuf E16, W1_16, W2_16, W2p16, W3_16;           // bf16 shadows
-  int64_t ws_batch = 0;                             // training workspace capacity (rows)
-  DevBuf X16, z1, h1, z2, h2, out, dout, dh2, dz2, dh1, dz1, dX;
+  DevBuf W1T16, W2T16;                              // transposed bf16 shadows (backward products)
+  DevBuf dE;                                        // fp32 [nE] embedding-gradient accumulator, zero between steps
+  int64_t ws_batch = 0;                             // forward workspace capacity (rows)
+  DevBuf X16, z1, h1, z2, h2, out;
+  int64_t part_chunks = 0;                          // training partial-gradient capacity (chunks)
+  DevBuf part;                                      // fp32 [part_chunks][n_params - nE]
 };
 
 }  // namespace llama

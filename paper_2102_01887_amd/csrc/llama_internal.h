@@ -296,9 +296,12 @@ struct SurrogateBufs {
   float *master, *adam_m, *adam_v, *grad;
   const float *b1, *b2, *b3;
   void *E16, *W1_16, *W2_16, *W2p16, *W3_16;
-  // training workspace, B rows
-  void *X16, *h1, *h2, *dout, *dz2, *dz1;
-  float *z1, *z2, *out, *dh2, *dh1, *dX;
+  void *W1T16, *W2T16;       // transposed shadows: W1T[k][o], W2T[k][o]
+  float* dE;                 // [nE] embedding-gradient accumulator, zero between steps
+  float* part;               // [TRAIN_MAX_CHUNKS][n_params - nE] per-chunk partial gradients
+  // forward workspace, B rows
+  void *X16, *h1, *h2;
+  float *z1, *z2, *out;
 };
 
 struct LearnedArgs {
@@ -312,12 +315,32 @@ struct LearnedArgs {
 
 hipError_t launch_gemm_bf16(int M, int N, int K, const void* a, int64_t sam, int64_t sak, const void* b,
                             int64_t sbk, int64_t sbn, float* c, int64_t ldc, const float* bias, bool accumulate,
-                            hipStream_t s, bool c_zeroed = false);
+                            hipStream_t s);
 hipError_t launch_surrogate_forward(const SurrogateBufs& w, int64_t B, const int32_t* rows, const void* feat,
                                     hipStream_t s);
-hipError_t launch_surrogate_backward(const SurrogateBufs& w, int64_t B, const int32_t* rows, const float* y,
-                                     float* loss_sum, hipStream_t s);
-hipError_t launch_adamw(const SurrogateBufs& w, float lr, float wd, int64_t step, hipStream_t s);
+
+// Fused training step.  launch_train_chunks: one workgroup per TRAIN_ROWS
+// rows runs the forward and backward passes of its rows with every
+// activation in LDS and registers, writes its partial gradients of W1, b1,
+// W2, b2, W3, b3 to part[chunk] (all of them) and adds its embedding
+// gradients to dE atomically; at most TRAIN_MAX_CHUNKS chunks a launch.
+// launch_train_reduce: a thread per parameter sums the chunks' partials in
+// chunk order (dE for the embedding, which it then clears), adds them to grad
+// (or overwrites it when `first`), and with `update` applies AdamW and writes
+// the BF16 shadows of the new value.
+constexpr int TRAIN_ROWS = 64;
+constexpr int TRAIN_MAX_CHUNKS = 256;
+struct TrainArgs {
+  int64_t n;                 // rows of this launch
+  const int32_t* rows;       // [n] profile rows
+  const void* feat;          // [n][16] BF16 features
+  const float* y;            // [n] observed ln latency
+  float inv_B;               // 1 / rows of the whole step
+  float* loss_sum;           // optional: += the rows' loss
+};
+hipError_t launch_train_chunks(const SurrogateBufs& w, const TrainArgs& a, hipStream_t s);
+hipError_t launch_train_reduce(const SurrogateBufs& w, int n_chunks, bool first, bool update, float lr, float wd,
+                               int64_t step, hipStream_t s);
 hipError_t launch_shadows(const SurrogateBufs& w, hipStream_t s);
 hipError_t launch_decide_learned(const DevTables& t, const Batch& b, const LearnedArgs& a, hipStream_t s);
 

@@ -63,18 +63,16 @@ llama::SurrogateBufs bufs(const llama_ctx* c) {
   w.W2_16 = s.W2_16.p;
   w.W2p16 = s.W2p16.p;
   w.W3_16 = s.W3_16.p;
+  w.W1T16 = s.W1T16.p;
+  w.W2T16 = s.W2T16.p;
+  w.dE = s.dE.as<float>();
+  w.part = s.part.as<float>();
   w.X16 = s.X16.p;
   w.h1 = s.h1.p;
   w.h2 = s.h2.p;
-  w.dout = s.dout.p;
-  w.dz2 = s.dz2.p;
-  w.dz1 = s.dz1.p;
   w.z1 = s.z1.as<float>();
   w.z2 = s.z2.as<float>();
   w.out = s.out.as<float>();
-  w.dh2 = s.dh2.as<float>();
-  w.dh1 = s.dh1.as<float>();
-  w.dX = s.dX.as<float>();
   return w;
 }
 
@@ -102,8 +100,12 @@ int install(llama_ctx* c, const float* params, const float* m, const float* v, i
       (rc = upload(c, s.W1_16, nullptr, 2 * (size_t)HID * IN, "W1 (bf16)")) ||
       (rc = upload(c, s.W2_16, nullptr, 2 * (size_t)HID * HID, "W2 (bf16)")) ||
       (rc = upload(c, s.W2p16, nullptr, 2 * (size_t)HID * HID, "W2 permuted (bf16)")) ||
-      (rc = upload(c, s.W3_16, nullptr, 2 * (size_t)2 * HID, "W3 (bf16)")))
+      (rc = upload(c, s.W3_16, nullptr, 2 * (size_t)2 * HID, "W3 (bf16)")) ||
+      (rc = upload(c, s.W1T16, nullptr, 2 * (size_t)HID * IN, "W1 transposed (bf16)")) ||
+      (rc = upload(c, s.W2T16, nullptr, 2 * (size_t)HID * HID, "W2 transposed (bf16)")) ||
+      (rc = upload(c, s.dE, nullptr, sizeof(float) * (size_t)(lay.nE ? lay.nE : 1), "embedding gradient")))
     return rc;
+  if (hipMemsetAsync(s.dE.p, 0, s.dE.bytes, c->stream) != hipSuccess) return fail(c, LLAMA_E_DEVICE, "memset");
   if (!m && hipMemsetAsync(s.adam_m.p, 0, pb, c->stream) != hipSuccess) return fail(c, LLAMA_E_DEVICE, "memset");
   if (!v && hipMemsetAsync(s.adam_v.p, 0, pb, c->stream) != hipSuccess) return fail(c, LLAMA_E_DEVICE, "memset");
   hipError_t e = llama::launch_shadows(bufs(c), c->stream);
@@ -112,6 +114,54 @@ int install(llama_ctx* c, const float* params, const float* m, const float* v, i
   s.step = step;
   s.ready = true;
   return LLAMA_OK;
+}
+
+// Partial-gradient buffer for training batches of B rows (at most
+// TRAIN_MAX_CHUNKS chunks per pass; larger batches run several passes).
+int reserve_part(llama_ctx* c, int64_t B, hipStream_t stream) {
+  llama::Surrogate& s = c->surr;
+  const int64_t chunks = std::min<int64_t>((B + llama::TRAIN_ROWS - 1) / llama::TRAIN_ROWS, llama::TRAIN_MAX_CHUNKS);
+  if (chunks <= s.part_chunks) return LLAMA_OK;
+  if (stream) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &st) == hipSuccess && st != hipStreamCaptureStatusNone)
+      return fail(c, LLAMA_E_STATE, "surrogate: training workspace for %lld rows must be reserved before graph capture", (long long)B);
+  }
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(c, e, "surrogate reserve sync");
+  s.part_chunks = 0;
+  const int64_t P = s.n_params - Layout(s.n_rows).nE;
+  int rc = upload(c, s.part, nullptr, sizeof(float) * (size_t)chunks * (size_t)P, "partial gradients");
+  if (rc) return rc;
+  s.part_chunks = chunks;
+  return LLAMA_OK;
+}
+
+// One training step on B rows: fused forward + backward per 64-row chunk,
+// then the chunk sums, AdamW and the shadows (update), in passes of at most
+// TRAIN_MAX_CHUNKS chunks.
+hipError_t train_step(llama_ctx* c, int64_t B, const int32_t* rows, const uint16_t* feat, const float* y, float lr,
+                      float wd, bool update, float* loss_sum, hipStream_t s) {
+  const llama::SurrogateBufs w = bufs(c);
+  const int64_t per = (int64_t)llama::TRAIN_ROWS * llama::TRAIN_MAX_CHUNKS;
+  hipError_t e = hipSuccess;
+  for (int64_t off = 0; off < B && e == hipSuccess; off += per) {
+    const int64_t n = std::min(per, B - off);
+    const bool last = off + per >= B;
+    llama::TrainArgs a;
+    a.n = n;
+    a.rows = rows + off;
+    a.feat = feat + off * llama::SURR_FEAT;
+    a.y = y + off;
+    a.inv_B = 1.0f / (float)B;
+    a.loss_sum = loss_sum;
+    e = llama::launch_train_chunks(w, a, s);
+    if (e != hipSuccess) break;
+    if (update && last) c->surr.step += 1;
+    e = llama::launch_train_reduce(w, (int)((n + llama::TRAIN_ROWS - 1) / llama::TRAIN_ROWS), off == 0,
+                                   update && last, lr, wd, c->surr.step, s);
+  }
+  return e;
 }
 
 int reserve_ws(llama_ctx* c, int64_t B, hipStream_t stream) {
@@ -129,10 +179,7 @@ int reserve_ws(llama_ctx* c, int64_t B, hipStream_t stream) {
   int rc;
   if ((rc = upload(c, s.X16, nullptr, 2 * b * IN, "X")) || (rc = upload(c, s.z1, nullptr, 4 * b * HID, "z1")) ||
       (rc = upload(c, s.h1, nullptr, 2 * b * HID, "h1")) || (rc = upload(c, s.z2, nullptr, 4 * b * HID, "z2")) ||
-      (rc = upload(c, s.h2, nullptr, 2 * b * HID, "h2")) || (rc = upload(c, s.out, nullptr, 4 * b * 2, "out")) ||
-      (rc = upload(c, s.dout, nullptr, 2 * b * 2, "dout")) || (rc = upload(c, s.dh2, nullptr, 4 * b * HID, "dh2")) ||
-      (rc = upload(c, s.dz2, nullptr, 2 * b * HID, "dz2")) || (rc = upload(c, s.dh1, nullptr, 4 * b * HID, "dh1")) ||
-      (rc = upload(c, s.dz1, nullptr, 2 * b * HID, "dz1")) || (rc = upload(c, s.dX, nullptr, 4 * b * IN, "dX")))
+      (rc = upload(c, s.h2, nullptr, 2 * b * HID, "h2")) || (rc = upload(c, s.out, nullptr, 4 * b * 2, "out")))
     return rc;
   s.ws_batch = B;
   return LLAMA_OK;
@@ -243,16 +290,9 @@ int llama_surrogate_train_step(llama_ctx* c, int64_t batch, const int32_t* d_row
   if (batch < 1 || batch > INT32_MAX) return fail(c, LLAMA_E_ARG, "surrogate_train_step: batch must be >= 1");
   if (!d_rows || !d_feat || !d_y) return fail(c, LLAMA_E_ARG, "surrogate_train_step: null pointer");
   if (!(lr >= 0.0f) || !(weight_decay >= 0.0f)) return fail(c, LLAMA_E_ARG, "surrogate_train_step: bad lr or weight decay");
-  if ((rc = reserve_ws(c, batch, (hipStream_t)stream))) return rc;
-  const llama::SurrogateBufs w = bufs(c);
-  hipStream_t s = (hipStream_t)stream;
-  hipError_t e = llama::launch_surrogate_forward(w, batch, d_rows, d_feat, s);
-  if (e == hipSuccess) e = llama::launch_surrogate_backward(w, batch, d_rows, d_y, d_loss_sum, s);
-  if (e == hipSuccess && update) {
-    c->surr.step += 1;
-    e = llama::launch_adamw(w, lr, weight_decay, c->surr.step, s);
-    if (e == hipSuccess) e = llama::launch_shadows(w, s);
-  }
+  if ((rc = reserve_part(c, batch, (hipStream_t)stream))) return rc;
+  hipError_t e = train_step(c, batch, d_rows, d_feat, d_y, lr, weight_decay, update != 0, d_loss_sum,
+                            (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(c, e, "surrogate_train_step launch");
   return LLAMA_OK;
 }
@@ -267,22 +307,16 @@ int llama_surrogate_fit(llama_ctx* c, int64_t n, const int32_t* d_rows, const ui
     return fail(c, LLAMA_E_ARG, "surrogate_fit: need epochs >= 1 and n >= batch >= 1");
   if (!d_rows || !d_feat || !d_y) return fail(c, LLAMA_E_ARG, "surrogate_fit: null pointer");
   if (!(lr_max >= 0.0f) || !(weight_decay >= 0.0f)) return fail(c, LLAMA_E_ARG, "surrogate_fit: bad lr or weight decay");
-  if ((rc = reserve_ws(c, batch, (hipStream_t)stream))) return rc;
+  if ((rc = reserve_part(c, batch, (hipStream_t)stream))) return rc;
   const int64_t per_epoch = n / batch, steps = per_epoch * epochs;
-  const llama::SurrogateBufs w = bufs(c);
   hipStream_t s = (hipStream_t)stream;
   for (int64_t k = 0; k < steps; ++k) {
     const int64_t off = (k % per_epoch) * batch;
     const float lr = (float)(0.5 * lr_max * (1.0 + std::cos(3.141592653589793 * (double)k / (double)steps)));
     // the loss of the last tenth of the final epoch
     float* loss = (d_loss_sum && k >= steps - (per_epoch + 9) / 10) ? d_loss_sum : nullptr;
-    hipError_t e = llama::launch_surrogate_forward(w, batch, d_rows + off, d_feat + off * llama::SURR_FEAT, s);
-    if (e == hipSuccess) e = llama::launch_surrogate_backward(w, batch, d_rows + off, d_y + off, loss, s);
-    if (e == hipSuccess) {
-      c->surr.step += 1;
-      e = llama::launch_adamw(w, lr, weight_decay, c->surr.step, s);
-    }
-    if (e == hipSuccess) e = llama::launch_shadows(w, s);
+    const hipError_t e = train_step(c, batch, d_rows + off, d_feat + off * llama::SURR_FEAT, d_y + off, lr,
+                                    weight_decay, true, loss, s);
     if (e != hipSuccess) return hip_fail(c, e, "surrogate_fit launch");
   }
   return LLAMA_OK;

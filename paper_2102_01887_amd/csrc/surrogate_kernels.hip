@@ -8,10 +8,12 @@
 // x * sigmoid(2u), u = sqrt(2/pi) (x + 0.044715 x^3), which is the same
 // function.
 //
-// Training: gemm_bf16_kernel (v_mfma_f32_16x16x32_bf16, FP32 accumulation,
-// LDS tiles) for every product of the forward and backward passes, plus
-// elementwise kernels (GELU, loss gradient, GELU', column sums, embedding
-// scatter) and AdamW on FP32 master weights with BF16 shadows.
+// Training: train_chunk_kernel runs the forward and backward passes of 64
+// rows per workgroup with v_mfma_f32_16x16x32_bf16 (FP32 accumulation) and
+// every activation in LDS and registers, writing per-chunk partial
+// gradients; train_reduce_kernel sums them, applies AdamW to the FP32 master
+// weights and writes the BF16 shadows.  gemm_bf16_kernel (LDS tiles) serves
+// the stand-alone training-path forward.
 //
 // Inference: decide_learned_kernel, persistent, one wavefront per invocation
 // and 64 configuration rows per pass.  W1 and a K-permuted copy of W2 sit in
@@ -50,10 +52,18 @@ __device__ __forceinline__ float gelu(float x) {
   return x * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(t));
 }
 
-__device__ __forceinline__ float gelu_grad(float x) {
-  const float u = GELU_C * (x + GELU_A * x * x * x);
-  const float t = 2.0f / (1.0f + __expf(-2.0f * u)) - 1.0f;  // tanh(u)
-  return 0.5f * (1.0f + t) + 0.5f * x * (1.0f - t * t) * GELU_C * (1.0f + 3.0f * GELU_A * x * x);
+// GELU and its derivative from one sigmoid: with s = sigmoid(2u) (the
+// forward's exp2 and reciprocal), GELU(x) = x s and GELU'(x) = s + 2 sqrt(2/pi)
+// x s (1 - s) (1 + 3 * 0.044715 x^2), the derivative of the tanh form written
+// with tanh(u) = 2s - 1.  h is bit-identical to gelu(x).
+constexpr float GELU_D1 = 2.0f * GELU_C, GELU_D2 = 3.0f * GELU_A;
+__device__ __forceinline__ void gelu_and_grad(float x, float* h, float* gp) {
+  const float x2 = x * x;
+  const float t = x * fmaf(GELU_K2, x2, GELU_K1);
+  const float sg = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(t));
+  *h = x * sg;
+  const float q = fmaf(-sg, sg, sg);  // s (1 - s)
+  *gp = fmaf(GELU_D1 * x * q, fmaf(GELU_D2, x2, 1.0f), sg);
 }
 
 __device__ __forceinline__ floatx4 mfma16x16x32(const bf16x8& a, const bf16x8& b, const floatx4& c) {
@@ -65,9 +75,8 @@ __device__ __forceinline__ floatx4 mfma16x16x32(const bf16x8& a, const bf16x8& b
 // element strides, FP32 output.  64x64 tile per 256-lane workgroup, each
 // wavefront a 32x32 quarter (2x2 MFMA blocks), K in steps of 32 through LDS.
 // Tiles are loaded along whichever index has unit stride, so both plain and
-// transposed operands read coalesced.  With gridDim.z > 1 the K range is
-// split across workgroups that add their partial sums atomically (C must then
-// be zeroed first, and the bias is added by split 0 only).
+// transposed operands read coalesced.  Used by the training-path forward
+// (llama_surrogate_forward); training steps run the fused kernels below.
 // ---------------------------------------------------------------------------
 // One thread's share of a 64 x 32 operand tile: 8 consecutive elements along
 // the operand's contiguous dimension (the row dimension when `along_row`, else
@@ -110,12 +119,11 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, con
                                                         int64_t sam, int64_t sak, const bf16* __restrict__ b,
                                                         int64_t sbk, int64_t sbn, float* __restrict__ c,
                                                         int64_t ldc, const float* __restrict__ bias,
-                                                        int accumulate, int k_chunk) {
+                                                        int accumulate) {
   __shared__ __attribute__((aligned(16))) bf16 sA[64][40];  // [m][k], 8 pad columns
   __shared__ __attribute__((aligned(16))) bf16 sB[64][40];  // [n][k]
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-  const int kb0 = blockIdx.z * k_chunk;
-  const int kb1 = kb0 + k_chunk < K ? kb0 + k_chunk : K;
+  const int kb0 = 0, kb1 = K;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int g = lane >> 4, r = lane & 15;
@@ -154,7 +162,6 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, con
     }
     __syncthreads();
   }
-  const bool split = gridDim.z > 1;
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
@@ -164,13 +171,9 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, con
         const int row = m0 + wm + mb * 16 + 4 * g + i;
         const int col = n0 + wn + nb * 16 + r;
         if (row < M && col < N) {
-          float x = acc[mb][nb][i] + ((bias && blockIdx.z == 0) ? bias[col] : 0.0f);
-          if (split) {
-            atomicAdd(&c[row * ldc + col], x);
-          } else {
-            if (accumulate) x += c[row * ldc + col];
-            c[row * ldc + col] = x;
-          }
+          float x = acc[mb][nb][i] + (bias ? bias[col] : 0.0f);
+          if (accumulate) x += c[row * ldc + col];
+          c[row * ldc + col] = x;
         }
       }
 }
@@ -190,124 +193,564 @@ __global__ __launch_bounds__(256) void gelu_round_kernel(int64_t n, const float*
   if (i < n) h[i] = (bf16)gelu(z[i]);
 }
 
-// Per row: d loss / d mu = 2 (mu - y) / B; d loss / d q = ([y < q] - tau) / B
-// (pinball loss on u = y - q); rounded to BF16.  Adds the batch's loss sum.
-__global__ __launch_bounds__(256) void loss_grad_kernel(int64_t B, const float* out, const float* y,
-                                                        bf16* dout, float* loss_sum) {
-  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= B) return;
-  const float mu = out[2 * m], q = out[2 * m + 1], t = y[m];
-  const float inv = 1.0f / (float)B;
-  const bool below = t < q;
-  dout[2 * m] = (bf16)(2.0f * (mu - t) * inv);
-  dout[2 * m + 1] = (bf16)(((below ? 1.0f : 0.0f) - TAU) * inv);
-  if (loss_sum) {
-    const float u = t - q;
-    atomicAdd(loss_sum, (mu - t) * (mu - t) + u * (TAU - (below ? 1.0f : 0.0f)));
+// BF16 shadows of one master parameter: E, W1 (and W1T[k][o]), W2 (and
+// W2T[k][o] and the K-permuted W2p used by the fused inference kernel:
+// W2p[o][32 kb + 8 g + j] = W2[o][32 kb + (j < 4 ? 4g + j : 12 + 4g + j)]),
+// W3; the biases have none.
+struct Shadows {
+  bf16 *E16, *W1_16, *W1T16, *W2_16, *W2T16, *W2p16, *W3_16;
+  int64_t nE;
+};
+
+__device__ __forceinline__ int w2p_column(int c) {
+  const int kb = c >> 5, ci = c & 31;
+  const int g = ci < 16 ? ci >> 2 : (ci - 16) >> 2;
+  const int j = ci < 16 ? ci & 3 : 4 + ((ci - 16) & 3);
+  return 32 * kb + 8 * g + j;
+}
+
+__device__ __forceinline__ void write_shadow(const Shadows& sh, int64_t i, float x) {
+  const bf16 h = (bf16)x;
+  if (i < sh.nE) {
+    sh.E16[i] = h;
+    return;
+  }
+  int64_t j = i - sh.nE;
+  if (j < HID * IN) {
+    sh.W1_16[j] = h;
+    sh.W1T16[(j % IN) * HID + j / IN] = h;
+    return;
+  }
+  j -= HID * IN + HID;
+  if (j < 0) return;  // b1
+  if (j < HID * HID) {
+    const int o = (int)(j / HID), c = (int)(j % HID);
+    sh.W2_16[j] = h;
+    sh.W2T16[(int64_t)c * HID + o] = h;
+    sh.W2p16[(int64_t)o * HID + w2p_column(c)] = h;
+    return;
+  }
+  j -= HID * HID + HID;
+  if (j >= 0 && j < 2 * HID) sh.W3_16[j] = h;  // else b2 or b3
+}
+
+__global__ __launch_bounds__(256) void shadows_kernel(const float* master, int64_t n, Shadows sh) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) write_shadow(sh, i, master[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Fused training step (launch_train_chunks / launch_train_reduce).
+//
+// A workgroup of eight wavefronts (two per SIMD) takes TRAIN_ROWS rows and
+// runs, with
+// the same rounding points as the product-by-product form (BF16 operands,
+// FP32 accumulation, activations and their gradients rounded to BF16):
+//   X = [E[row], f]               LDS, row-major and transposed
+//   z1 = X W1^T + b1              MFMA, K = 32; wavefront w: columns 32w..32w+31
+//   h1 = GELU(z1)                 LDS, row-major and transposed; GELU'(z1) kept in
+//                                 registers (one sigmoid gives both)
+//   z2 = h1 W2^T + b2             MFMA, K = 256, all of the wavefront's W2 fragments
+//                                 loaded from L2 before the first product
+//   h2 = GELU(z2)                 LDS; GELU'(z2) kept in registers
+//   (mu, q) = h2 W3^T + b3        VALU, TR_LPR lanes per row, W3 staged in LDS
+//   dout = loss gradient          LDS; rows past the batch get 0
+//   dW3 = dout^T h2, db3          VALU, a lane per column
+//   dz2 = (dout W3) GELU'(z2)     in registers, then LDS (both layouts); db2
+//   dz1 = (dz2 W2) GELU'(z1)      MFMA with the transposed W2 shadow, then LDS; db1
+//   dW1 = dz1^T X                 MFMA over the rows
+//   dE[row] += (dz1 W1)[:, :16]   MFMA with the transposed W1 shadow, atomics
+//   dW2 = dz2^T h1                MFMA over the rows, four passes of 64 columns,
+//                                 last, so that its stores delay no load
+// Partial gradients go to part[chunk] in the parameter order after E; the
+// reduce kernel sums them in chunk order, so the sum does not depend on
+// timing (only dE, whose atomics may add in any order).
+// ---------------------------------------------------------------------------
+constexpr int TR_LDX = IN + 8;          // bf16 stride of X rows
+constexpr int TR_LDT = TRAIN_ROWS + 8;  // bf16 stride of transposed rows
+constexpr int TR_LDA = HID + 8;         // bf16 stride of activation rows
+constexpr size_t TR_OFF_XT = sizeof(bf16) * TRAIN_ROWS * TR_LDX;
+constexpr size_t TR_OFF_A = TR_OFF_XT + sizeof(bf16) * IN * TR_LDT;
+constexpr size_t TR_OFF_AT = TR_OFF_A + sizeof(bf16) * TRAIN_ROWS * TR_LDA;
+constexpr size_t TR_OFF_B = TR_OFF_AT + sizeof(bf16) * HID * TR_LDT;
+constexpr size_t TR_OFF_BT = TR_OFF_B + sizeof(bf16) * TRAIN_ROWS * TR_LDA;
+constexpr size_t TR_OFF_D = TR_OFF_BT + sizeof(bf16) * HID * TR_LDT;
+constexpr size_t TR_OFF_ROW = TR_OFF_D + sizeof(float) * TRAIN_ROWS * 2;
+constexpr size_t TR_OFF_RED = TR_OFF_ROW + sizeof(int32_t) * TRAIN_ROWS;
+constexpr size_t TR_OFF_W3 = TR_OFF_RED + sizeof(float) * 8;
+constexpr size_t TRAIN_LDS = TR_OFF_W3 + sizeof(bf16) * 2 * HID;
+
+struct TrainKArgs {
+  TrainArgs a;
+  const bf16 *E16, *W1_16, *W1T16, *W2_16, *W2T16, *W3_16;
+  const float *b1, *b2, *b3;
+  float* part;
+  int64_t P;  // partial-gradient floats per chunk
+  float* dE;
+  int64_t n_rows;  // embedding rows: a row id outside [0, n_rows) trains as a zero row
+};
+
+// partial-gradient offsets (parameter order after E)
+constexpr int64_t PG_W1 = 0, PG_B1 = HID * IN, PG_W2 = PG_B1 + HID, PG_B2 = PG_W2 + HID * HID,
+                  PG_W3 = PG_B2 + HID, PG_B3 = PG_W3 + 2 * HID;
+
+__device__ __forceinline__ bf16x8 lds_frag(const bf16* base, int stride, int row, int col) {
+  return *reinterpret_cast<const bf16x8*>(base + row * stride + col);
+}
+
+__device__ __forceinline__ bf16x8 global_frag(const bf16* base, int64_t stride, int row, int col) {
+  return *reinterpret_cast<const bf16x8*>(base + (int64_t)row * stride + col);
+}
+
+// Store a 16 x 16 FP32 tile fragment (rows 4g..4g+3 of column r, offset by
+// row0/col0) rounded to BF16: row-major into A (stride lda) and, when AT is
+// given, transposed into AT (stride ldt), 4 consecutive rows in one 8-byte store.
+__device__ __forceinline__ void store_frag_bf16(bf16* A, int lda, bf16* AT, int ldt, int row0, int col0, int g, int r,
+                                                const float (&v)[4]) {
+  bf16 h[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    h[i] = (bf16)v[i];
+    A[(row0 + 4 * g + i) * lda + col0 + r] = h[i];
+  }
+  if (AT) {
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+    bf16x4 q = {h[0], h[1], h[2], h[3]};
+    *reinterpret_cast<bf16x4*>(AT + (col0 + r) * ldt + row0 + 4 * g) = q;
   }
 }
 
-__global__ __launch_bounds__(256) void gelu_bwd_round_kernel(int64_t n, const float* dh, const float* z,
-                                                             bf16* dz) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dz[i] = (bf16)(dh[i] * gelu_grad(z[i]));
-}
-
-// out[n] += sum over m of x[m][n]: each 256-lane workgroup sums 64 columns
-// over a chunk of COLSUM_ROWS rows (4 lanes per column), reduces in LDS and
-// adds atomically (out must be zeroed first).
-constexpr int COLSUM_ROWS = 64;
-__global__ __launch_bounds__(256) void colsum_kernel(int64_t M, int N, const bf16* x, float* out) {
-  __shared__ float part[4][64];
-  const int col = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int q = threadIdx.x >> 6;
-  const int64_t r0 = (int64_t)blockIdx.y * COLSUM_ROWS;
-  const int64_t r1 = r0 + COLSUM_ROWS < M ? r0 + COLSUM_ROWS : M;
-  float s = 0.0f;
-  if (col < N)
-    for (int64_t m = r0 + q; m < r1; m += 4) s += (float)x[m * N + col];
-  part[q][threadIdx.x & 63] = s;
-  __syncthreads();
-  if (q == 0 && col < N) atomicAdd(&out[col], part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] +
-                                                  part[3][threadIdx.x]);
-}
-
-// The same sum with 16-byte loads (N a multiple of 8, x 16-byte aligned):
-// 8 lanes cover a row's 64 columns, 32 rows at a time.
-__global__ __launch_bounds__(256) void colsum8_kernel(int64_t M, int N, const bf16* x, float* out) {
-  __shared__ float part[32][65];
-  const int cv = threadIdx.x & 7, q = threadIdx.x >> 3;
-  const int c0 = blockIdx.x * 64 + cv * 8;
-  const int64_t r0 = (int64_t)blockIdx.y * COLSUM_ROWS;
-  const int64_t r1 = r0 + COLSUM_ROWS < M ? r0 + COLSUM_ROWS : M;
-  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  if (c0 < N)  // N is a multiple of 8, so all 8 columns exist
-    for (int64_t m = r0 + q; m < r1; m += 32) {
-      const bf16x8 v = *reinterpret_cast<const bf16x8*>(x + m * N + c0);
+// Column sums over the rows of a wavefront's MB x NB tiles (values already
+// rounded to BF16), reduced across the four row groups; lanes 0..15 return
+// the sums of columns 16 nb + lane.
+template <int MB, int NB>
+__device__ __forceinline__ void column_sums(const float (&v)[MB][NB][4], float (&out)[NB]) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) acc[j] += (float)v[j];
+  for (int nb = 0; nb < NB; ++nb) {
+    float t = 0.0f;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) t += v[mb][nb][i];
+    t += __shfl_xor(t, 16, 64);
+    t += __shfl_xor(t, 32, 64);
+    out[nb] = t;
+  }
+}
+
+// Workgroup barrier for LDS data only: waits for this wavefront's LDS
+// accesses, not its global loads and stores, so weight fragments loaded
+// before a barrier stay in flight across it and partial-gradient stores
+// drain behind later work.  (The kernel reads no global memory that other
+// wavefronts of the workgroup write.)
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+constexpr int TR_WAVES = 8;                 // wavefronts per workgroup, two per SIMD
+constexpr int TR_THREADS = 64 * TR_WAVES;
+constexpr int TR_COLS = HID / TR_WAVES;     // hidden units per wavefront
+constexpr int TR_NB = TR_COLS / 16;         // 16-column tiles per wavefront
+constexpr int TR_KS = HID / 32;             // K steps of a 256-long contraction
+constexpr int TR_MB = TRAIN_ROWS / 16;      // 16-row tiles of a chunk
+constexpr int TR_LPR = TR_THREADS / TRAIN_ROWS;  // lanes per row in the output layer
+static_assert(TRAIN_ROWS % 32 == 0 && TRAIN_ROWS * 4 <= 256 && TR_LPR <= 64, "chunk shape");
+
+__global__ __launch_bounds__(TR_THREADS) void train_chunk_kernel(TrainKArgs k) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  bf16* sX = reinterpret_cast<bf16*>(lds);
+  bf16* sXT = reinterpret_cast<bf16*>(lds + TR_OFF_XT);
+  bf16* sA = reinterpret_cast<bf16*>(lds + TR_OFF_A);
+  bf16* sAT = reinterpret_cast<bf16*>(lds + TR_OFF_AT);
+  bf16* sB = reinterpret_cast<bf16*>(lds + TR_OFF_B);
+  bf16* sBT = reinterpret_cast<bf16*>(lds + TR_OFF_BT);
+  float* sD = reinterpret_cast<float*>(lds + TR_OFF_D);
+  int32_t* sRow = reinterpret_cast<int32_t*>(lds + TR_OFF_ROW);
+  float* sRed = reinterpret_cast<float*>(lds + TR_OFF_RED);
+  bf16* sW3 = reinterpret_cast<bf16*>(lds + TR_OFF_W3);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int g = lane >> 4, r = lane & 15;
+  const int c0 = TR_COLS * w;  // this wavefront's hidden units
+  const int64_t base = (int64_t)blockIdx.x * TRAIN_ROWS;
+  const int nrow = k.a.n - base < TRAIN_ROWS ? (int)(k.a.n - base) : TRAIN_ROWS;
+  float* part = k.part + (int64_t)blockIdx.x * k.P;
+  // Loads in the order their values are needed: a wavefront's loads complete
+  // in order, so a value loaded after a prefetch would make its first use
+  // wait for the prefetch.  Small operands and the gathered X first, then
+  // the W1 and W2 fragments, then the LDS stores of X.
+  float b1v[TR_NB], b2v[TR_NB];
+#pragma unroll
+  for (int nb = 0; nb < TR_NB; ++nb) {
+    b1v[nb] = k.b1[c0 + 16 * nb + r];
+    b2v[nb] = k.b2[c0 + 16 * nb + r];
+  }
+  const float b3a = k.b3[0], b3b = k.b3[1];
+  const float yv = tid < nrow ? k.a.y[base + tid] : 0.0f;
+  // X = [E[row], f]: threads 0 .. 4 TRAIN_ROWS - 1 take 8 columns of row t / 4;
+  // threads 256.. stage W3
+  const int xrow = tid >> 2, xq = tid & 3;
+  bf16x8 xv;
+  int xid = -1;
+  bf16 w3v[2];
+  if (tid < 4 * TRAIN_ROWS) {
+    xid = xrow < nrow ? k.a.rows[base + xrow] : -1;
+    if (xid >= k.n_rows) xid = -1;
+    if (xid >= 0) {
+      if (xq < 2) {
+        xv = *reinterpret_cast<const bf16x8*>(k.E16 + (int64_t)xid * EMB + 8 * xq);
+      } else {
+        const uint16_t* f = reinterpret_cast<const uint16_t*>(k.a.feat) + (base + xrow) * EMB + 8 * (xq - 2);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) xv[j] = __builtin_bit_cast(bf16, f[j]);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) xv[j] = (bf16)0.0f;
+    }
+  } else if (tid >= 256) {
+    w3v[0] = k.W3_16[2 * (tid - 256)];
+    w3v[1] = k.W3_16[2 * (tid - 256) + 1];
+  }
+  bf16x8 bw1[TR_NB];        // W1 fragments of z1
+  bf16x8 bw[TR_KS][TR_NB];  // W2 fragments of z2, then W2T of dh1
+#pragma unroll
+  for (int nb = 0; nb < TR_NB; ++nb) bw1[nb] = global_frag(k.W1_16, IN, c0 + 16 * nb + r, 8 * g);
+#pragma unroll
+  for (int ks = 0; ks < TR_KS; ++ks)
+#pragma unroll
+    for (int nb = 0; nb < TR_NB; ++nb) bw[ks][nb] = global_frag(k.W2_16, HID, c0 + 16 * nb + r, 32 * ks + 8 * g);
+  float* sY = sD;  // targets of the chunk's rows, until dout replaces them
+  if (tid < TRAIN_ROWS) sY[tid] = yv;
+  if (tid < 4 * TRAIN_ROWS) {
+    if (xq == 0) sRow[xrow] = xid;
+    *reinterpret_cast<bf16x8*>(sX + xrow * TR_LDX + 8 * xq) = xv;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) sXT[(8 * xq + j) * TR_LDT + xrow] = xv[j];
+  } else if (tid >= 256) {
+    sW3[2 * (tid - 256)] = w3v[0];
+    sW3[2 * (tid - 256) + 1] = w3v[1];
+  }
+  lds_barrier();
+
+  // ---- z1, h1; GELU'(z1) kept in registers ----
+  float gp1[TR_MB][TR_NB][4];
+  {
+    floatx4 c[TR_MB][TR_NB];
+#pragma unroll
+    for (int mb = 0; mb < TR_MB; ++mb) {
+      const bf16x8 ax = lds_frag(sX, TR_LDX, 16 * mb + r, 8 * g);
+#pragma unroll
+      for (int nb = 0; nb < TR_NB; ++nb) c[mb][nb] = mfma16x16x32(ax, bw1[nb], floatx4{0.f, 0.f, 0.f, 0.f});
     }
 #pragma unroll
-  for (int j = 0; j < 8; ++j) part[q][cv * 8 + j] = acc[j];
-  __syncthreads();
-  const int col = blockIdx.x * 64 + (int)threadIdx.x;
-  if (threadIdx.x < 64 && col < N) {
-    float t = 0.0f;
+    for (int nb = 0; nb < TR_NB; ++nb) {
+      const float bias = b1v[nb];
+#pragma unroll
+      for (int mb = 0; mb < TR_MB; ++mb) {
+        float h[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) gelu_and_grad(c[mb][nb][i] + bias, &h[i], &gp1[mb][nb][i]);
+        store_frag_bf16(sA, TR_LDA, sAT, TR_LDT, 16 * mb, c0 + 16 * nb, g, r, h);
+      }
+    }
+  }
+  lds_barrier();
+
+  // ---- z2, h2; GELU'(z2) kept in registers ----
+  float gp2[TR_MB][TR_NB][4];
+  {
+    floatx4 acc[TR_MB][TR_NB];
+#pragma unroll
+    for (int mb = 0; mb < TR_MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < TR_NB; ++nb) acc[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < TR_KS; ++ks) {
+      bf16x8 ah[TR_MB];
+#pragma unroll
+      for (int mb = 0; mb < TR_MB; ++mb) ah[mb] = lds_frag(sA, TR_LDA, 16 * mb + r, 32 * ks + 8 * g);
+#pragma unroll
+      for (int mb = 0; mb < TR_MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < TR_NB; ++nb) acc[mb][nb] = mfma16x16x32(ah[mb], bw[ks][nb], acc[mb][nb]);
+    }
+    // the transposed W2 fragments of dh1 load while the output layer runs
+#pragma unroll
+    for (int ks = 0; ks < TR_KS; ++ks)
+#pragma unroll
+      for (int nb = 0; nb < TR_NB; ++nb) bw[ks][nb] = global_frag(k.W2T16, HID, c0 + 16 * nb + r, 32 * ks + 8 * g);
+#pragma unroll
+    for (int nb = 0; nb < TR_NB; ++nb) {
+      const float bias = b2v[nb];
+#pragma unroll
+      for (int mb = 0; mb < TR_MB; ++mb) {
+        float h[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) gelu_and_grad(acc[mb][nb][i] + bias, &h[i], &gp2[mb][nb][i]);
+        store_frag_bf16(sB, TR_LDA, nullptr, 0, 16 * mb, c0 + 16 * nb, g, r, h);
+      }
+    }
+  }
+  lds_barrier();
+
+  // ---- (mu, q), loss, dout: TR_LPR lanes per row ----
+  {
+    constexpr int KPL = HID / TR_LPR;
+    const int row = tid / TR_LPR, q = tid % TR_LPR;
+    float s0 = 0.0f, s1 = 0.0f;
+    const bf16* h2 = sB + row * TR_LDA + KPL * q;
+    const bf16* w0 = sW3 + KPL * q;
+    const bf16* w1 = sW3 + HID + KPL * q;
 #pragma unroll 8
-    for (int i = 0; i < 32; ++i) t += part[i][threadIdx.x];
-    atomicAdd(&out[col], t);
+    for (int j = 0; j < KPL; ++j) {
+      const float h = (float)h2[j];
+      s0 = fmaf(h, (float)w0[j], s0);
+      s1 = fmaf(h, (float)w1[j], s1);
+    }
+#pragma unroll
+    for (int o = 1; o < TR_LPR; o <<= 1) {
+      s0 += __shfl_xor(s0, o, 64);
+      s1 += __shfl_xor(s1, o, 64);
+    }
+    float loss = 0.0f;
+    const float t = sY[row];
+    lds_barrier();  // every target is read before dout overwrites them
+    if (q == 0) {
+      float d0 = 0.0f, d1 = 0.0f;
+      if (row < nrow) {
+        const float mu = s0 + b3a, qv = s1 + b3b;
+        const bool below = t < qv;
+        d0 = (float)(bf16)(2.0f * (mu - t) * k.a.inv_B);
+        d1 = (float)(bf16)(((below ? 1.0f : 0.0f) - TAU) * k.a.inv_B);
+        const float u = t - qv;
+        loss = (mu - t) * (mu - t) + u * (TAU - (below ? 1.0f : 0.0f));
+      }
+      sD[2 * row] = d0;
+      sD[2 * row + 1] = d1;
+    }
+    if (k.a.loss_sum) {
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) loss += __shfl_xor(loss, o, 64);
+      if (lane == 0) sRed[w] = loss;
+    }
+  }
+  lds_barrier();
+  if (k.a.loss_sum && tid == 0) {
+    float t = 0.0f;
+    for (int i = 0; i < TR_WAVES; ++i) t += sRed[i];
+    atomicAdd(k.a.loss_sum, t);
+  }
+
+  // ---- dW3, db3 (a lane per column of h2) ----
+  if (tid < HID) {
+    float a0 = 0.0f, a1 = 0.0f;
+#pragma unroll 8
+    for (int row = 0; row < TRAIN_ROWS; ++row) {
+      const float h = (float)sB[row * TR_LDA + tid];
+      a0 = fmaf(sD[2 * row], h, a0);
+      a1 = fmaf(sD[2 * row + 1], h, a1);
+    }
+    part[PG_W3 + tid] = a0;
+    part[PG_W3 + HID + tid] = a1;
+    if (tid < 2) {
+      float t = 0.0f;
+      for (int row = 0; row < TRAIN_ROWS; ++row) t += sD[2 * row + tid];
+      part[PG_B3 + tid] = t;
+    }
+  }
+  lds_barrier();  // h2 is read above; dz2 overwrites it below
+
+  // ---- dz2 = (dout W3) GELU'(z2), db2 ----
+  {
+    float w3a[TR_NB], w3b[TR_NB];
+#pragma unroll
+    for (int nb = 0; nb < TR_NB; ++nb) {
+      w3a[nb] = (float)sW3[c0 + 16 * nb + r];
+      w3b[nb] = (float)sW3[HID + c0 + 16 * nb + r];
+    }
+#pragma unroll
+    for (int mb = 0; mb < TR_MB; ++mb) {
+      float d0[4], d1[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        d0[i] = sD[2 * (16 * mb + 4 * g + i)];
+        d1[i] = sD[2 * (16 * mb + 4 * g + i) + 1];
+      }
+#pragma unroll
+      for (int nb = 0; nb < TR_NB; ++nb) {
+        float v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float dh = fmaf(d1[i], w3b[nb], d0[i] * w3a[nb]);
+          v[i] = (float)(bf16)(dh * gp2[mb][nb][i]);
+          gp2[mb][nb][i] = v[i];  // GELU'(z2) is dead from here: keep dz2
+        }
+        store_frag_bf16(sB, TR_LDA, sBT, TR_LDT, 16 * mb, c0 + 16 * nb, g, r, v);
+      }
+    }
+    float cs[TR_NB];
+    column_sums<TR_MB, TR_NB>(gp2, cs);
+    if (g == 0)
+#pragma unroll
+      for (int nb = 0; nb < TR_NB; ++nb) part[PG_B2 + c0 + 16 * nb + r] = cs[nb];
+  }
+  lds_barrier();
+
+  // ---- dz1 = (dz2 W2) GELU'(z1), db1; dz1 goes to the row-major buffer of h1 ----
+  {
+    floatx4 acc[TR_MB][TR_NB];
+#pragma unroll
+    for (int mb = 0; mb < TR_MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < TR_NB; ++nb) acc[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < TR_KS; ++ks) {
+      bf16x8 ad[TR_MB];
+#pragma unroll
+      for (int mb = 0; mb < TR_MB; ++mb) ad[mb] = lds_frag(sB, TR_LDA, 16 * mb + r, 32 * ks + 8 * g);
+#pragma unroll
+      for (int mb = 0; mb < TR_MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < TR_NB; ++nb) acc[mb][nb] = mfma16x16x32(ad[mb], bw[ks][nb], acc[mb][nb]);
+    }
+#pragma unroll
+    for (int mb = 0; mb < TR_MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < TR_NB; ++nb) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) gp1[mb][nb][i] = (float)(bf16)(acc[mb][nb][i] * gp1[mb][nb][i]);
+        store_frag_bf16(sA, TR_LDA, nullptr, 0, 16 * mb, c0 + 16 * nb, g, r, gp1[mb][nb]);
+      }
+    float cs[TR_NB];
+    column_sums<TR_MB, TR_NB>(gp1, cs);
+    if (g == 0)
+#pragma unroll
+      for (int nb = 0; nb < TR_NB; ++nb) part[PG_B1 + c0 + 16 * nb + r] = cs[nb];
+  }
+  bf16x8 bt[TR_KS];  // W1T fragments of the embedding gradient
+  if (w < TRAIN_ROWS / 16)
+#pragma unroll
+    for (int ks = 0; ks < TR_KS; ++ks) bt[ks] = global_frag(k.W1T16, HID, r, 32 * ks + 8 * g);
+  lds_barrier();
+
+  // ---- dW1 = dz1^T X: wavefront w takes outputs c0..c0+31 (dz1 read down its
+  // columns: 8 two-byte LDS reads per fragment) ----
+  {
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < TRAIN_ROWS / 32; ++ks) {
+      bf16x8 a[2], b[2];
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[mb][j] = sA[(32 * ks + 8 * g + j) * TR_LDA + c0 + 16 * mb + r];
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) b[nb] = lds_frag(sXT, TR_LDT, 16 * nb + r, 32 * ks + 8 * g);
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = mfma16x16x32(a[mb], b[nb], acc[mb][nb]);
+    }
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          part[PG_W1 + (c0 + 16 * mb + 4 * g + i) * IN + 16 * nb + r] = acc[mb][nb][i];
+  }
+
+  // ---- embedding gradient: wavefronts 0..3 take rows 16w..16w+15 of dz1 W1[:, :16] ----
+  if (w < TRAIN_ROWS / 16) {
+    floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < TR_KS; ++ks) acc = mfma16x16x32(lds_frag(sA, TR_LDA, 16 * w + r, 32 * ks + 8 * g), bt[ks], acc);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = 16 * w + 4 * g + i;
+      if (row < nrow && sRow[row] >= 0) atomicAdd(k.dE + (int64_t)sRow[row] * EMB + r, acc[i]);
+    }
+  }
+
+  // ---- dW2 = dz2^T h1, last: its 256 KB of partial stores then hold up no
+  // later load.  Wavefront w takes outputs c0..c0+31, four passes of 64 inputs ----
+#pragma unroll 1
+  for (int pass = 0; pass < 4; ++pass) {
+    floatx4 acc[2][4];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < TRAIN_ROWS / 32; ++ks) {
+      bf16x8 a[2], b[4];
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) a[mb] = lds_frag(sBT, TR_LDT, c0 + 16 * mb + r, 32 * ks + 8 * g);
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) b[nb] = lds_frag(sAT, TR_LDT, 64 * pass + 16 * nb + r, 32 * ks + 8 * g);
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = mfma16x16x32(a[mb], b[nb], acc[mb][nb]);
+    }
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          part[PG_W2 + (int64_t)(c0 + 16 * mb + 4 * g + i) * HID + 64 * pass + 16 * nb + r] = acc[mb][nb][i];
   }
 }
 
-__global__ __launch_bounds__(256) void scatter_embed_kernel(int64_t B, const int32_t* rows, const float* dX,
-                                                            float* dE) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= B * EMB) return;
-  const int64_t m = e / EMB;
-  const int j = (int)(e % EMB);
-  atomicAdd(&dE[(int64_t)rows[m] * EMB + j], dX[m * IN + j]);
-}
-
-__global__ __launch_bounds__(256) void fill_f32_kernel(int64_t n, float* p, float v) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
-// AdamW on the flat master vector; decoupled decay only on [0, decay_end0)
-// (E and W1) and the W2, W3 ranges.
-__global__ __launch_bounds__(256) void adamw_kernel(int64_t n, float* p, const float* g, float* m, float* v,
-                                                    float lr, float wd, float c1, float c2, float beta1,
-                                                    float beta2, float eps, int64_t d0, int64_t d1a,
-                                                    int64_t d1b, int64_t d2a, int64_t d2b) {
+// Sum of the chunks' partials (chunk order) or the embedding accumulator;
+// then AdamW as adamw_kernel and the new value's shadows.
+__global__ __launch_bounds__(256) void train_reduce_kernel(int64_t n, int64_t nE, const float* part, int n_chunks,
+                                                           float* dE, float* grad, int first, int update, float* p,
+                                                           float* m, float* v, float lr, float wd, float c1,
+                                                           float c2, int64_t d0, int64_t d1a, int64_t d1b,
+                                                           int64_t d2a, int64_t d2b, Shadows sh) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  float w = p[i];
+  float gi;
+  if (i < nE) {
+    gi = dE[i];
+    dE[i] = 0.0f;
+  } else {
+    // 32 loads in flight, added in chunk order
+    const int64_t P = n - nE;
+    const float* q = part + (i - nE);
+    gi = 0.0f;
+    int c = 0;
+    for (; c + 32 <= n_chunks; c += 32) {
+      float t[32];
+#pragma unroll
+      for (int j = 0; j < 32; ++j) t[j] = q[(int64_t)(c + j) * P];
+#pragma unroll
+      for (int j = 0; j < 32; ++j) gi += t[j];
+    }
+    for (; c < n_chunks; ++c) gi += q[(int64_t)c * P];
+  }
+  if (!first) gi += grad[i];
+  grad[i] = gi;
+  if (!update) return;
+  const float beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f;
+  float wv = p[i];
   const bool decay = i < d0 || (i >= d1a && i < d1b) || (i >= d2a && i < d2b);
-  if (decay) w *= 1.0f - lr * wd;
-  const float gi = g[i];
+  if (decay) wv *= 1.0f - lr * wd;
   const float mi = beta1 * m[i] + (1.0f - beta1) * gi;
   const float vi = beta2 * v[i] + (1.0f - beta2) * gi * gi;
   m[i] = mi;
   v[i] = vi;
-  p[i] = w - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-}
-
-// BF16 shadows of E, W1, W2, W3 and the K-permuted W2 used by the fused
-// inference kernel: W2p[o][32 kb + 8 g + j] = W2[o][32 kb + (j < 4 ? 4g + j : 12 + 4g + j)].
-__global__ __launch_bounds__(256) void shadows_kernel(const float* master, int64_t nE, bf16* E16, bf16* W1_16,
-                                                      bf16* W2_16, bf16* W2p16, bf16* W3_16) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t oW1 = nE, oW2 = oW1 + HID * IN + HID, oW3 = oW2 + HID * HID + HID;
-  if (i < nE) E16[i] = (bf16)master[i];
-  if (i < HID * IN) W1_16[i] = (bf16)master[oW1 + i];
-  if (i < HID * HID) {
-    W2_16[i] = (bf16)master[oW2 + i];
-    const int o = (int)(i / HID), col = (int)(i % HID);
-    const int kb = col >> 5, g = (col >> 3) & 3, j = col & 7;
-    const int src = 32 * kb + (j < 4 ? 4 * g + j : 12 + 4 * g + j);
-    W2p16[i] = (bf16)master[oW2 + (int64_t)o * HID + src];
-  }
-  if (i < 2 * HID) W3_16[i] = (bf16)master[oW3 + i];
+  wv = wv - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  p[i] = wv;
+  write_shadow(sh, i, wv);
 }
 
 // ---------------------------------------------------------------------------
@@ -568,35 +1011,10 @@ inline unsigned grid1(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs);
 // ---------------------------------------------------------------------------
 hipError_t launch_gemm_bf16(int M, int N, int K, const void* a, int64_t sam, int64_t sak, const void* bm,
                             int64_t sbk, int64_t sbn, float* c, int64_t ldc, const float* bias, bool accumulate,
-                            hipStream_t s, bool c_zeroed) {
+                            hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  const unsigned gx = grid1(N, 64), gy = grid1(M, 64);
-  // weight gradients over the batch (the only calls that pass a zeroed C):
-  // few output tiles and a long K, so K is split into chunks of at least 64
-  // until about 256 workgroups fill the CUs and the partial sums are added
-  // atomically.  Every other product (the forward, the input gradients) keeps
-  // one workgroup per tile, so its output does not depend on timing.
-  unsigned gz = 1;
-  if (c_zeroed && gx * gy < 128 && K >= 256 && !accumulate) {
-    const unsigned by_k = (unsigned)((K + 255) / 256), by_cu = (256 + gx * gy - 1) / (gx * gy);
-    gz = by_k > by_cu ? by_k : by_cu;
-    const unsigned most = (unsigned)(K / 64) < 64 ? (unsigned)(K / 64) : 64;
-    if (gz > most) gz = most;
-  }
-  const int k_chunk = (int)(((K + (int)gz - 1) / (int)gz + 31) / 32 * 32);
-  gz = (unsigned)((K + k_chunk - 1) / k_chunk);
-  hipLaunchKernelGGL(gemm_bf16_kernel, dim3(gx, gy, gz), dim3(256), 0, s, M, N, K, (const bf16*)a, sam, sak,
-                     (const bf16*)bm, sbk, sbn, c, ldc, bias, accumulate ? 1 : 0, gz > 1 ? k_chunk : K);
-  return hipGetLastError();
-}
-
-// out must hold zeros: the row chunks add their sums atomically
-hipError_t launch_colsum(int64_t M, int N, const void* x, float* out, hipStream_t s) {
-  const dim3 grid(grid1(N, 64), (unsigned)((M + COLSUM_ROWS - 1) / COLSUM_ROWS));
-  if (N % 8 == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0)
-    hipLaunchKernelGGL(colsum8_kernel, grid, dim3(256), 0, s, M, N, (const bf16*)x, out);
-  else
-    hipLaunchKernelGGL(colsum_kernel, grid, dim3(256), 0, s, M, N, (const bf16*)x, out);
+  hipLaunchKernelGGL(gemm_bf16_kernel, dim3(grid1(N, 64), grid1(M, 64)), dim3(256), 0, s, M, N, K, (const bf16*)a,
+                     sam, sak, (const bf16*)bm, sbk, sbn, c, ldc, bias, accumulate ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -612,47 +1030,61 @@ hipError_t launch_surrogate_forward(const SurrogateBufs& w, int64_t B, const int
   return launch_gemm_bf16((int)B, 2, HID, w.h2, HID, 1, w.W3_16, 1, HID, w.out, 2, w.b3, false, s);
 }
 
-hipError_t launch_surrogate_backward(const SurrogateBufs& w, int64_t B, const int32_t* rows, const float* y,
-                                     float* loss_sum, hipStream_t s) {
-  hipError_t e;
-  float* g = w.grad;
-  // the whole gradient is cleared once: the bias column sums, the split-K
-  // weight gradients and the embedding scatter all add into it atomically
-  hipLaunchKernelGGL(fill_f32_kernel, dim3(grid1(w.n_params, 256)), dim3(256), 0, s, w.n_params, g, 0.0f);
-  hipLaunchKernelGGL(loss_grad_kernel, dim3(grid1(B, 256)), dim3(256), 0, s, B, w.out, y, (bf16*)w.dout,
-                     loss_sum);
-  // layer 3: dW3 = dout^T h2, db3 = colsum(dout), dh2 = dout W3
-  if ((e = launch_gemm_bf16(2, HID, (int)B, w.dout, 1, 2, w.h2, HID, 1, g + w.oW3, HID, nullptr, false, s, true))) return e;
-  if ((e = launch_colsum(B, 2, w.dout, g + w.ob3, s))) return e;
-  if ((e = launch_gemm_bf16((int)B, HID, 2, w.dout, 2, 1, w.W3_16, HID, 1, w.dh2, HID, nullptr, false, s))) return e;
-  hipLaunchKernelGGL(gelu_bwd_round_kernel, dim3(grid1(B * HID, 256)), dim3(256), 0, s, B * HID, w.dh2, w.z2,
-                     (bf16*)w.dz2);
-  // layer 2
-  if ((e = launch_gemm_bf16(HID, HID, (int)B, w.dz2, 1, HID, w.h1, HID, 1, g + w.oW2, HID, nullptr, false, s, true))) return e;
-  if ((e = launch_colsum(B, HID, w.dz2, g + w.ob2, s))) return e;
-  if ((e = launch_gemm_bf16((int)B, HID, HID, w.dz2, HID, 1, w.W2_16, HID, 1, w.dh1, HID, nullptr, false, s))) return e;
-  hipLaunchKernelGGL(gelu_bwd_round_kernel, dim3(grid1(B * HID, 256)), dim3(256), 0, s, B * HID, w.dh1, w.z1,
-                     (bf16*)w.dz1);
-  // layer 1 and the embedding
-  if ((e = launch_gemm_bf16(HID, IN, (int)B, w.dz1, 1, HID, w.X16, IN, 1, g + w.oW1, IN, nullptr, false, s, true))) return e;
-  if ((e = launch_colsum(B, HID, w.dz1, g + w.ob1, s))) return e;
-  if ((e = launch_gemm_bf16((int)B, IN, HID, w.dz1, HID, 1, w.W1_16, IN, 1, w.dX, IN, nullptr, false, s))) return e;
-  hipLaunchKernelGGL(scatter_embed_kernel, dim3(grid1(B * EMB, 256)), dim3(256), 0, s, B, rows, w.dX, g);
-  return hipGetLastError();
+namespace {
+Shadows shadows_of(const SurrogateBufs& w) {
+  Shadows sh;
+  sh.E16 = (bf16*)w.E16;
+  sh.W1_16 = (bf16*)w.W1_16;
+  sh.W1T16 = (bf16*)w.W1T16;
+  sh.W2_16 = (bf16*)w.W2_16;
+  sh.W2T16 = (bf16*)w.W2T16;
+  sh.W2p16 = (bf16*)w.W2p16;
+  sh.W3_16 = (bf16*)w.W3_16;
+  sh.nE = w.nE;
+  return sh;
 }
-
-hipError_t launch_adamw(const SurrogateBufs& w, float lr, float wd, int64_t step, hipStream_t s) {
-  const float beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f;
-  const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
-  hipLaunchKernelGGL(adamw_kernel, dim3(grid1(w.n_params, 256)), dim3(256), 0, s, w.n_params, w.master, w.grad,
-                     w.adam_m, w.adam_v, lr, wd, c1, c2, beta1, beta2, eps, w.ob1, w.oW2, w.ob2, w.oW3, w.ob3);
-  return hipGetLastError();
-}
+}  // namespace
 
 hipError_t launch_shadows(const SurrogateBufs& w, hipStream_t s) {
-  const int64_t n = w.nE > HID * HID ? w.nE : HID * HID;
-  hipLaunchKernelGGL(shadows_kernel, dim3(grid1(n, 256)), dim3(256), 0, s, w.master, w.nE, (bf16*)w.E16,
-                     (bf16*)w.W1_16, (bf16*)w.W2_16, (bf16*)w.W2p16, (bf16*)w.W3_16);
+  hipLaunchKernelGGL(shadows_kernel, dim3(grid1(w.n_params, 256)), dim3(256), 0, s, w.master, w.n_params,
+                     shadows_of(w));
+  return hipGetLastError();
+}
+
+hipError_t launch_train_chunks(const SurrogateBufs& w, const TrainArgs& a, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  const int64_t chunks = (a.n + TRAIN_ROWS - 1) / TRAIN_ROWS;
+  if (chunks > TRAIN_MAX_CHUNKS) return hipErrorInvalidValue;
+  TrainKArgs k;
+  k.a = a;
+  k.E16 = (const bf16*)w.E16;
+  k.W1_16 = (const bf16*)w.W1_16;
+  k.W1T16 = (const bf16*)w.W1T16;
+  k.W2_16 = (const bf16*)w.W2_16;
+  k.W2T16 = (const bf16*)w.W2T16;
+  k.W3_16 = (const bf16*)w.W3_16;
+  k.b1 = w.b1;
+  k.b2 = w.b2;
+  k.b3 = w.b3;
+  k.part = w.part;
+  k.P = w.n_params - w.nE;
+  k.dE = w.dE;
+  k.n_rows = w.nE / EMB;
+  hipError_t e = hipFuncSetAttribute((const void*)train_chunk_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)TRAIN_LDS);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(train_chunk_kernel, dim3((unsigned)chunks), dim3(TR_THREADS), TRAIN_LDS, s, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_train_reduce(const SurrogateBufs& w, int n_chunks, bool first, bool update, float lr, float wd,
+                               int64_t step, hipStream_t s) {
+  const float beta1 = 0.9f, beta2 = 0.999f;
+  const float c1 = update ? 1.0f - powf(beta1, (float)step) : 1.0f;
+  const float c2 = update ? 1.0f - powf(beta2, (float)step) : 1.0f;
+  hipLaunchKernelGGL(train_reduce_kernel, dim3(grid1(w.n_params, 256)), dim3(256), 0, s, w.n_params, w.nE, w.part,
+                     n_chunks, w.dE, w.grad, first ? 1 : 0, update ? 1 : 0, w.master, w.adam_m, w.adam_v, lr, wd, c1,
+                     c2, w.ob1, w.oW2, w.ob2, w.oW3, w.ob3, shadows_of(w));
   return hipGetLastError();
 }
 
