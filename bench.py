@@ -90,7 +90,7 @@ DECISION_PATH_END = b"// DECISION-PATH-END"
 def decision_path_digest():
     """sha256 of the decision path's device source: llama_kernels.hip up to
     its DECISION-PATH-END marker (records, relaxation, decision kernels and
-    their launchers) and the shared declarations in llama_internal.h."""
+    their launchers)."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2102_01887_amd", "csrc")
     with open(os.path.join(csrc, "llama_kernels.hip"), "rb") as f:
@@ -98,10 +98,7 @@ def decision_path_digest():
     cut = text.find(DECISION_PATH_END)
     if cut < 0:
         raise RuntimeError("llama_kernels.hip has no DECISION-PATH-END marker")
-    h = hashlib.sha256(text[:cut])
-    with open(os.path.join(csrc, "llama_internal.h"), "rb") as f:
-        h.update(f.read())
-    return h.hexdigest()
+    return hashlib.sha256(text[:cut]).hexdigest()
 
 
 def measured_traffic(workload, kernel):

@@ -1213,27 +1213,70 @@ __global__ __launch_bounds__(256) void bucket_scatter_kernel(DevTables t, Batch 
 }
 
 // Exclusive prefix sum of cnt[0..n) into start[0..n] and cursor[0..n), one
-// workgroup of 1024 lanes, each owning a contiguous chunk.
+// workgroup of 1024 lanes walking the array in tiles of 16 K counts: each
+// lane reads 16 consecutive counts with 16-byte loads, the tile is scanned
+// across lanes (wavefront scans, then the 16 wavefront totals), and a carry
+// links the tiles.
+constexpr int OFFS_PER_LANE = 16;
 __global__ __launch_bounds__(1024) void bucket_offsets_kernel(const int32_t* cnt, int32_t n,
                                                               int32_t* start, int32_t* cursor) {
   __shared__ int32_t wsum[16];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int c = (n + 1023) / 1024;
-  const int a0 = tid * c < n ? tid * c : n;
-  const int a1 = a0 + c < n ? a0 + c : n;
-  int sum = 0;
-  for (int j = a0; j < a1; ++j) sum += cnt[j];
-  const int incl = wave_inclusive_scan(sum);
-  if (lane == 63) wsum[wv] = incl;
-  __syncthreads();
-  int run = incl - sum;
-  for (int w = 0; w < wv; ++w) run += wsum[w];
-  for (int j = a0; j < a1; ++j) {
-    start[j] = run;
-    if (cursor) cursor[j] = run;
-    run += cnt[j];
+  int carry = 0;
+  for (int64_t base = 0; base < n; base += 1024 * OFFS_PER_LANE) {
+    const int64_t a = base + (int64_t)tid * OFFS_PER_LANE;
+    int x[OFFS_PER_LANE];
+    const bool whole = a + OFFS_PER_LANE <= n;
+    if (whole) {
+#pragma unroll
+      for (int q = 0; q < OFFS_PER_LANE / 4; ++q) {
+        const int4 v = *reinterpret_cast<const int4*>(cnt + a + 4 * q);
+        x[4 * q] = v.x;
+        x[4 * q + 1] = v.y;
+        x[4 * q + 2] = v.z;
+        x[4 * q + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < OFFS_PER_LANE; ++q) x[q] = a + q < n ? cnt[a + q] : 0;
+    }
+    int sum = 0;
+#pragma unroll
+    for (int q = 0; q < OFFS_PER_LANE; ++q) sum += x[q];
+    const int incl = wave_inclusive_scan(sum);
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    int run = carry + incl - sum, tile = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+      run += w < wv ? wsum[w] : 0;
+      tile += wsum[w];
+    }
+    int y[OFFS_PER_LANE];
+#pragma unroll
+    for (int q = 0; q < OFFS_PER_LANE; ++q) {
+      y[q] = run;
+      run += x[q];
+    }
+    if (whole) {
+#pragma unroll
+      for (int q = 0; q < OFFS_PER_LANE / 4; ++q) {
+        const int4 v = make_int4(y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]);
+        *reinterpret_cast<int4*>(start + a + 4 * q) = v;
+        if (cursor) *reinterpret_cast<int4*>(cursor + a + 4 * q) = v;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < OFFS_PER_LANE; ++q)
+        if (a + q < n) {
+          start[a + q] = y[q];
+          if (cursor) cursor[a + q] = y[q];
+        }
+    }
+    carry += tile;
+    __syncthreads();  // wsum is rewritten by the next tile
   }
-  if (tid == 1023) start[n] = run;
+  if (tid == 0) start[n] = carry;
 }
 
 // Configurations read as scalar operands: the table through the constant
