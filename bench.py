@@ -237,9 +237,15 @@ def bench_next1(args, torch, B, wl, log, w, op, el, slo, mode):
                  and np.array_equal(fg, f_or) and np.array_equal(c0[sample], c0_or)
                  and np.array_equal(f0[sample], f0_or))
     q_bytes = n_q * (8 + 12)
-    # per invocation 17 B; per configuration the per-call merge reads its
-    # latency and two keys and writes the merged threshold and two minima
-    a_bytes = n * 17 + wr.n_cfg * 24
+    # the library merges each op's backends per call only when the call's
+    # invocations pay for it (8 n_inv >= n_cfg): then per configuration the
+    # merge reads its latency and two keys and writes the merged threshold
+    # and two minima; otherwise each invocation counts per backend (two-level
+    # count) and reads the backend's two key minima.  Per invocation 17 B.
+    merged = 8 * n >= wr.n_cfg
+    a_bytes = n * 17 + (wr.n_cfg * 24 if merged else n * wr.n_hw * 8)
+    a_kernel = ("alpha_merge_kernel + alpha_queue_kernel" if merged else
+                "decide_alpha_kernel (per backend: block samples, then one block)")
     log(f"bench: next1 queue_time {ms_q * 1e3:.2f} us, decide_alpha {ms_a * 1e3:.2f} us, exact {exact}")
     return {"alpha": [1, 1], "hw_res_total": wr.hw_res_total.tolist(), "queue_entries": n_q,
             "Q_us": Q_or.tolist(), "ms_per_chain": ms_c, "decisions_per_s": n / (ms_c * 1e-3),
@@ -248,7 +254,7 @@ def bench_next1(args, torch, B, wl, log, w, op, el, slo, mode):
                            "roofline": {"bound": "hbm", "achieved": q_bytes / (ms_q * 1e-3) / 1e9,
                                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                         "frac": q_bytes / (ms_q * 1e-3) / 1e9 / HBM_PEAK_GBS}},
-            "decide_alpha": {"kernel": "alpha_merge_kernel + alpha_queue_kernel", "ms": ms_a,
+            "decide_alpha": {"kernel": a_kernel, "ms": ms_a,
                              "roofline": {"bound": "hbm", "achieved": a_bytes / (ms_a * 1e-3) / 1e9,
                                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                           "frac": a_bytes / (ms_a * 1e-3) / 1e9 / HBM_PEAK_GBS}},

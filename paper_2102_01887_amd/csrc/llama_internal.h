@@ -40,6 +40,7 @@ constexpr uint32_t DEVERR_QUEUE_ENTRY = 2u;  // device error bit: queued entry o
 // 0).  The entries past the record (the n - REC_SLOTS smallest T), ascending
 // in T, are in the overflow array at [hdr offset of the op, + n - REC_SLOTS);
 // the decision reads them only when no slot is feasible.
+constexpr int ALPHA_BLOCK = 16;  // latencies per sampled block of the finite-alpha runs
 constexpr int REC_WORDS = 28;
 constexpr int REC_SLOTS = 17;
 constexpr int REC_SLOTS_TAIL = 7;   // slots in the hot words and the first tail
@@ -148,6 +149,11 @@ struct DevTables {
   const uint32_t* m_pf;
   const uint32_t* m_si;
   int32_t m_steps;
+  // samples of the (op, backend) runs of a_lat for two-level counts: the last
+  // latency of every block of ALPHA_BLOCK entries, padded with INT32_MAX to a
+  // multiple of four samples; an op's runs start at a_soff[v], one after the other
+  const int32_t* a_smp;
+  const int32_t* a_soff;     // [n_ops + 1]
   const double* a_val;       // [2 n_cfg] objective value of each rank, per op from 2 cfg_off[v]
   const int32_t* seg_off;    // [n_ops*n_hw+1] backend segments of the full table
   // finite alpha, per configuration in the a_lat order: its feasible and

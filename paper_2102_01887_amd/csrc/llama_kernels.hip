@@ -1639,11 +1639,38 @@ __global__ __launch_bounds__(1024) void queue_finalize_kernel(const unsigned lon
 
 // ---------------------------------------------------------------------------
 // Finite-alpha Eq. 1: per backend, j = number of configurations faster than
-// the target (branch-free binary search over the latency-sorted segment, the
-// NHW searches advancing in lockstep so their loads overlap); the backend's
+// the target (a two-level count over the latency-sorted run); the backend's
 // best key is min(prefix-min feasible key before j, suffix-min infeasible key
 // from j); the smallest key over backends wins.
 // ---------------------------------------------------------------------------
+// Entries of the ascending run lat[0 .. len) below target.  smp holds the
+// last entry of each block of ALPHA_BLOCK (16-byte aligned, padded with
+// INT32_MAX): the samples below target count the blocks entirely below it,
+// and the next block is counted entry by entry.  Two dependent rounds of a
+// line or two each, where a binary search takes one dependent random load per
+// halving.
+__device__ __forceinline__ int count_below(const int32_t* lat, int len, const int32_t* smp, int32_t target) {
+  const int nb = (len + ALPHA_BLOCK - 1) / ALPHA_BLOCK;
+  int m = 0;
+  for (int q0 = 0; q0 < nb; q0 += 32) {  // up to eight 16-byte sample loads in flight
+    int4 sv[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      sv[k] = q0 + 4 * k < nb ? *reinterpret_cast<const int4*>(smp + q0 + 4 * k)
+                              : make_int4(INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      m += (sv[k].x < target) + (sv[k].y < target) + (sv[k].z < target) + (sv[k].w < target);
+  }
+  if (m >= nb) return len;
+  const int b0 = m * ALPHA_BLOCK;
+  const int bl = len - b0 < ALPHA_BLOCK ? len - b0 : ALPHA_BLOCK;
+  int c = 0;
+#pragma unroll
+  for (int i = 0; i < ALPHA_BLOCK; ++i) c += (i < bl && lat[b0 + i] < target) ? 1 : 0;
+  return b0 + c;
+}
+
 template <int NHW>
 __global__ __launch_bounds__(256) void decide_alpha_kernel(DevTables t, Batch b) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1659,29 +1686,16 @@ __global__ __launch_bounds__(256) void decide_alpha_kernel(DevTables t, Batch b)
   const int64_t ref = t.ref[v];
   const int64_t W = t.W[(int64_t)b.mode * t.n_ops + v];
   const int32_t* so = t.seg_off + (int64_t)v * NHW;
-  int base[NHW], len[NHW], end[NHW];
-  int32_t target[NHW];
+  int base[NHW], end[NHW];
+  const int32_t* smp = t.a_smp + t.a_soff[v];
 #pragma unroll
   for (int h = 0; h < NHW; ++h) {
-    base[h] = so[h];
-    end[h] = so[h + 1];
-    len[h] = end[h] - base[h];
+    const int lo = so[h], len = so[h + 1] - lo;
     const int64_t R = remaining_time(r0, b.queue ? b.queue[h] : 0);
-    target[h] = R == 0 ? 0 : (int32_t)div_floor_pos(ref * R, W);
-  }
-  for (int step = 0; step < t.a_steps; ++step) {
-#pragma unroll
-    for (int h = 0; h < NHW; ++h) {
-      if (len[h] > 0) {
-        const int half = len[h] >> 1;
-        if (t.a_lat[base[h] + half] < target[h]) {
-          base[h] += half + 1;
-          len[h] -= half + 1;
-        } else {
-          len[h] = half;
-        }
-      }
-    }
+    const int32_t target = R == 0 ? 0 : (int32_t)div_floor_pos(ref * R, W);
+    base[h] = lo + count_below(t.a_lat + lo, len, smp, target);
+    end[h] = lo + len;
+    smp += ((len + ALPHA_BLOCK - 1) / ALPHA_BLOCK + 3) & ~3;
   }
   uint32_t best = KEY_NONE;
   uint8_t meets = 0;
@@ -1724,6 +1738,9 @@ __global__ __launch_bounds__(256) void decide_alpha_merged_kernel(DevTables t, B
   const int32_t target =
       R == 0 ? 0 : (int32_t)div_floor_pos((int64_t)t.ref[v] * R, t.W[(int64_t)b.mode * t.n_ops + v]);
   const int lo = t.cfg_off[v], end = t.cfg_off[v + 1];
+  // one search per invocation: a binary search (an op's run is long and its
+  // upper levels are shared by the op's invocations in L2) measured faster
+  // here than the two-level count
   int base = lo, len = end - lo;
   for (int step = 0; step < t.m_steps && len > 0; ++step) {
     const int half = len >> 1;

@@ -169,6 +169,40 @@ int build_alpha_tables(llama_ctx* c) {
   }
   if (too_many)
     return fail(c, LLAMA_E_RANGE, "set_alpha: an op has more than %d configurations", LLAMA_ALPHA_MAX_CFG_PER_OP);
+  // block samples of every (op, backend) run of a_lat
+  auto padded_blocks = [](int len) { return ((len + ALPHA_BLOCK - 1) / ALPHA_BLOCK + 3) & ~3; };
+  auto backend_counts = [&](int v, std::vector<int32_t>& cnt) {  // run h = [a + cnt[h], a + cnt[h + 1])
+    std::fill(cnt.begin(), cnt.end(), 0);
+    for (int x = c->cfg_off[v]; x < c->cfg_off[v + 1]; ++x) cnt[c->hw[x] + 1]++;
+    for (int h = 0; h < n_hw; ++h) cnt[h + 1] += cnt[h];
+  };
+  std::vector<int32_t> a_soff(n_ops + 1, 0);
+  {
+    std::vector<int32_t> cnt(n_hw + 1);
+    for (int v = 0; v < n_ops; ++v) {
+      backend_counts(v, cnt);
+      int na = 0;
+      for (int h = 0; h < n_hw; ++h) na += padded_blocks(cnt[h + 1] - cnt[h]);
+      a_soff[v + 1] = a_soff[v] + na;
+    }
+  }
+  std::vector<int32_t> a_smp(std::max(a_soff[n_ops], 4), INT32_MAX);
+#pragma omp parallel
+  {
+    std::vector<int32_t> cnt(n_hw + 1);
+#pragma omp for schedule(dynamic, 256)
+    for (int v = 0; v < n_ops; ++v) {
+      const int a = c->cfg_off[v];
+      backend_counts(v, cnt);
+      int o = a_soff[v];
+      for (int h = 0; h < n_hw; ++h) {
+        const int s0 = a + cnt[h], len = cnt[h + 1] - cnt[h];
+        for (int b = 0; b * ALPHA_BLOCK < len; ++b)
+          a_smp[o + b] = a_lat[s0 + std::min(len - 1, b * ALPHA_BLOCK + ALPHA_BLOCK - 1)];
+        o += padded_blocks(len);
+      }
+    }
+  }
   int steps = 0, msteps = 0;
   while ((1 << steps) <= max_seg) ++steps;
   while ((1 << msteps) <= max_op) ++msteps;
@@ -182,7 +216,9 @@ int build_alpha_tables(llama_ctx* c) {
       (rc = upload(c, c->d_a_val, a_val.data(), a_val.size() * 8, "alpha objective values")) ||
       (rc = upload(c, c->d_a_fk, a_fk.data(), a_fk.size() * 4, "alpha feasible keys")) ||
       (rc = upload(c, c->d_a_ik, a_ik.data(), a_ik.size() * 4, "alpha infeasible keys")) ||
-      (rc = upload(c, c->d_m_cnt, m_cnt.data(), m_cnt.size() * 2, "alpha merged backend counts")))
+      (rc = upload(c, c->d_m_cnt, m_cnt.data(), m_cnt.size() * 2, "alpha merged backend counts")) ||
+      (rc = upload(c, c->d_a_smp, a_smp.data(), a_smp.size() * 4, "alpha latency samples")) ||
+      (rc = upload(c, c->d_a_soff, a_soff.data(), a_soff.size() * 4, "alpha sample offsets")))
     return rc;
   if (max_op <= ALPHA_MERGE_MAX) {
     // per-call merged order for calls with queueing times
