@@ -381,19 +381,22 @@ def test_c3_reduced():
 
 
 def test_c3_full_size_sampled():
-    # 4,096 pipelines, ~80M configurations, 4M invocations, decided in one call;
-    # the oracle checks a 200,000-invocation sample of the same call
+    # 4,096 pipelines, ~80M configurations, 4M invocations, decided in one call
+    # per slack mode; the oracle checks a 200,000-invocation sample of each call
     torch = _torch()
     w = wl.make_c3()
     say(f"c3: {w.n_ops} ops, {w.n_cfg} configurations, {w.n_inv} invocations")
     L = B.Llama(0).load(w)
-    c, f = L.decide(dev(w.inv_op, torch), dev(w.elapsed, torch), dev(w.slo, torch))
-    torch.cuda.synchronize()
-    c, f = c.cpu().numpy(), f.cpu().numpy()
+    op, el, slo = dev(w.inv_op, torch), dev(w.elapsed, torch), dev(w.slo, torch)
     idx = np.sort(np.random.default_rng(0).choice(w.n_inv, 200_000, replace=False))
     ws = w.with_invocations(w.inv_op[idx], w.elapsed[idx], w.slo[idx])
-    c_or, f_or = oracle.Problem(ws).decide(PAPER)
-    assert np.array_equal(c[idx], c_or) and np.array_equal(f[idx], f_or)
+    P = oracle.Problem(ws)
+    for mode in (PAPER, PROB):
+        c, f = L.decide(op, el, slo, mode=mode)
+        torch.cuda.synchronize()
+        c, f = c.cpu().numpy(), f.cpu().numpy()
+        c_or, f_or = P.decide(mode)
+        assert np.array_equal(c[idx], c_or) and np.array_equal(f[idx], f_or), mode
 
 
 @pytest.mark.parametrize("maker", ["c2", "c3"])
