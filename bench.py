@@ -412,20 +412,29 @@ def bench_next4(args, torch, B, wl, log, L, w, op, el, slo, mode):
 
 
 def bench_surrogate(args, torch, B, wl, log):
-    """Train the surrogate with the full recipe on the GPU, time the fused
-    inference kernel on 1M invocations x 64 configurations, and score its
-    decisions against the simulator's truth (and the plain profile's)."""
+    """Draw the training executions with the GPU simulator, train the
+    surrogate with the full recipe on the GPU, time the fused inference kernel
+    on 1M invocations x 64 configurations, and score its decisions against
+    the simulator's truth (and the plain profile's)."""
     import numpy as np
     world = wl.make_c4_world(3)
     L = B.Llama(0).load(world.w)
     L.surrogate_init(seed=15, mean_log_latency=10.5)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     bf = lambda f: torch.from_numpy(np.ascontiguousarray(f, np.float32)).to(torch.bfloat16).cuda()
-    log(f"bench: simulating {args.train_samples} training executions")
-    rows, c, y = wl.simulate_c4(world, np.random.default_rng(7), args.train_samples)
-    d_rows, d_feat, d_y = dev(rows), bf(c.feat), dev(y)
-    del rows, c, y
     s = torch.cuda.Stream()
+    # training executions drawn on the device (llama_simulate), timed
+    log(f"bench: simulating {args.train_samples} training executions on the GPU")
+    L.set_simulator(world.a, world.b, world.sigma)
+    L.simulate(4096, 1, stream=s)  # warm-up
+    sa, sb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        sa.record(s)
+        d_rows, d_feat, d_y = L.simulate(args.train_samples, 7, stream=s)
+        sb.record(s)
+    sb.synchronize()
+    sim_ms = sa.elapsed_time(sb)
     epochs, batch = 3, 4096
     steps = epochs * (args.train_samples // batch)
     L.surrogate_reserve(batch)
@@ -484,6 +493,9 @@ def bench_surrogate(args, torch, B, wl, log):
     return {
         "workload": "c4: C1's 6-op DAG, 64 configs/op; train 10M simulator samples x 3 epochs "
                     "(batch 4096, AdamW, cosine lr 5e-3); infer 1M invocations x 64 configs",
+        "simulator": {"kernel": "simulate_kernel (Philox4x32-10, FP64 transforms)",
+                      "samples": args.train_samples, "ms": sim_ms,
+                      "samples_per_s": args.train_samples / (sim_ms * 1e-3)},
         "train_ms": train_ms, "train_steps": steps,
         "train_samples_per_s": epochs * args.train_samples / (train_ms * 1e-3),
         "final_loss": final_loss,
