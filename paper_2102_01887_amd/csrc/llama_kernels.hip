@@ -2128,18 +2128,29 @@ __global__ __launch_bounds__(256) void batching_scan_kernel(DevTables t, Batch b
     const int64_t limit = av > 1 ? av : 1;
     uint32_t kFr = KEY_NONE;
     uint64_t fR = ~0ull;
-    for (int x = a + lane; x < end; x += 64) {
-      const int32_t B = t.cfg_batch[x];
-      if (B > limit) continue;
-      const int32_t L = t.cfg_lat[x];
-      const uint32_t key = t.cfg_key[x];
-      const int hw = t.cfg_hw[x];
-      int32_t tg = target[0];
+    // eight configurations per lane at a time, their loads issued together
+    for (int x0 = a + lane; x0 < end; x0 += 8 * 64) {
+      int32_t Bv[8], Lv[8], Hv[8];
+      uint32_t Kv[8];
 #pragma unroll
-      for (int h = 1; h < NHW; ++h) tg = hw == h ? target[h] : tg;
-      const uint64_t fk = ((uint64_t)(uint32_t)L << 16) | (uint32_t)(x - a);
-      if (L < tg && key < kFr) kFr = key;
-      if (fk < fR) fR = fk;
+      for (int u = 0; u < 8; ++u) {
+        const int x = x0 + 64 * u;
+        const bool in = x < end;
+        Bv[u] = in ? t.cfg_batch[x] : INT32_MAX;
+        Lv[u] = in ? t.cfg_lat[x] : 0;
+        Kv[u] = in ? t.cfg_key[x] : KEY_NONE;
+        Hv[u] = in ? t.cfg_hw[x] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (Bv[u] > limit) continue;
+        int32_t tg = target[0];
+#pragma unroll
+        for (int h = 1; h < NHW; ++h) tg = Hv[u] == h ? target[h] : tg;
+        const uint64_t fk = ((uint64_t)(uint32_t)Lv[u] << 16) | (uint32_t)(x0 + 64 * u - a);
+        if (Lv[u] < tg && Kv[u] < kFr) kFr = Kv[u];
+        if (fk < fR) fR = fk;
+      }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
