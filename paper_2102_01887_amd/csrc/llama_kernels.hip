@@ -1330,9 +1330,14 @@ __global__ __launch_bounds__(256) void decide_wave_kernel(DevTables t, Batch b) 
     for (int h = 0; h < NHW; ++h) {
       const int64_t R = remaining_time(r0, b.queue ? b.queue[h] : 0);
       const int32_t target = R == 0 ? 0 : (int32_t)div_floor_pos(ref * R, W);
-      for (int x = seg[h] + lane; x < seg[h + 1]; x += 64) {
-        const uint2 c = t.tab[x];
-        if ((int32_t)c.x < target) best = umin32(best, c.y);
+      // eight configurations per lane at a time, their loads issued together
+      for (int x0 = seg[h] + lane; x0 < seg[h + 1]; x0 += 8 * 64) {
+        uint2 c[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) c[u] = x0 + 64 * u < seg[h + 1] ? t.tab[x0 + 64 * u] : make_uint2(0x7FFFFFFFu, KEY_NONE);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if ((int32_t)c[u].x < target) best = umin32(best, c[u].y);
       }
     }
     // any lane feasible?  otherwise skip the reduction and fall back
@@ -1439,9 +1444,12 @@ __global__ __launch_bounds__(256) void scan_classes_kernel(DevTables t, Batch b,
     for (int h = 0; h < NHW; ++h) {
       const int64_t R = remaining_time(r0, b.queue ? b.queue[h] : 0);
       const int32_t tg = R == 0 ? 0 : (int32_t)div_floor_pos(ref * R, W);
-      for (int x = seg[h] + l; x < seg[h + 1]; x += S) {
-        const uint2 q = t.tab[x];
-        best = umin32(best, (int32_t)q.x < tg ? q.y : KEY_NONE);
+      for (int x0 = seg[h] + l; x0 < seg[h + 1]; x0 += 4 * S) {  // four loads in flight per lane
+        uint2 q[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) q[u] = x0 + S * u < seg[h + 1] ? t.tab[x0 + S * u] : make_uint2(0x7FFFFFFFu, KEY_NONE);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) best = umin32(best, (int32_t)q[u].x < tg ? q[u].y : KEY_NONE);
       }
     }
     best = group_min_u32(best, S);
