@@ -806,15 +806,17 @@ __device__ __forceinline__ LearnedStage learned_stage(const LearnedArgs& s, unsi
   return LearnedStage{sW2, sW1, sB1, sB2, sW3, s.b3[0], s.b3[1]};
 }
 
-// One valid invocation (op v, elapsed e, SLO sl, features feat_i) decided by
-// a whole wavefront: targets, every configuration's predicted p95 latency
-// (profile fallback), Eq. 1 over them; the choice and flag come back in every
-// lane.  lat_row, when given, receives each configuration's latency.
-template <int NHW>
-__device__ __forceinline__ void learned_decide_one(const DevTables& t, int mode, const int64_t* queue,
-                                                   const LearnedArgs& s, const LearnedStage& st, int v, int e,
-                                                   int sl, const bf16* feat_i, int32_t* lat_row, int32_t* cfg_out,
-                                                   uint8_t* flag_out) {
+// One valid invocation (op v, elapsed e, SLO sl, features feat_i) evaluated
+// by a wavefront over row blocks nb0 .. nb0 + NB - 1 (16 rows each) of every
+// 64-row chunk of its op's configurations: targets, each row's predicted p95
+// latency (profile fallback), and the wavefront's minima of Eq. 1's keys:
+// *best the cheapest feasible key, *fast the fastest (L << 16 | k), in every
+// lane.  lat_row, when given, receives each row's latency.
+template <int NHW, int NB>
+__device__ __forceinline__ void learned_scan_rows(const DevTables& t, int mode, const int64_t* queue,
+                                                  const LearnedArgs& s, const LearnedStage& st, int v, int e,
+                                                  int sl, const bf16* feat_i, int32_t* lat_row, int nb0,
+                                                  uint32_t* best_out, uint64_t* fast_out) {
   const bf16* sW2 = st.sW2;
   const bf16* sW1 = st.sW1;
   const float* sB1 = st.sB1;
@@ -840,44 +842,46 @@ __device__ __forceinline__ void learned_decide_one(const DevTables& t, int mode,
   uint64_t fast = ~0ull;
   for (int c0 = 0; c0 < n_c; c0 += 64) {
     // ---- layer 1: z1^T[unit][row] = W1 . x^T, 16 unit blocks x 4 row blocks
-    bf16x8 xfrag[4];
+    bf16x8 xfrag[NB];
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
-      const int k = c0 + nb * 16 + r;
+    for (int nb = 0; nb < NB; ++nb) {
+      const int k = c0 + (nb0 + nb) * 16 + r;
       const int row = a0 + (k < n_c ? k : 0);
       xfrag[nb] = g < 2 ? *reinterpret_cast<const bf16x8*>(E16 + (int64_t)row * EMB + 8 * g) : ffrag;
     }
     // hf[kb][nb] is the layer-2 input fragment of row 16nb + r for K block
     // kb: units 32kb + 4g + q (slots 0..3) and 32kb + 16 + 4g + q (slots
     // 4..7), exactly the layer-1 outputs of unit blocks 2kb and 2kb + 1.
-    bf16x8 hf[8][4];
+    bf16x8 hf[8][NB];
 #pragma unroll
     for (int mb = 0; mb < 16; ++mb) {
       const bf16x8 w1 = *reinterpret_cast<const bf16x8*>(sW1 + (16 * mb + r) * IN + 8 * g);
       // the accumulator starts at the bias of this lane's four units
       const floatx4 b1 = *reinterpret_cast<const floatx4*>(sB1 + 16 * mb + 4 * g);
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb) {
+      for (int nb = 0; nb < NB; ++nb) {
         const floatx4 z = mfma16x16x32(w1, xfrag[nb], b1);
 #pragma unroll
         for (int q = 0; q < 4; ++q) hf[mb >> 1][nb][4 * (mb & 1) + q] = (bf16)gelu(z[q]);
       }
     }
     // ---- layers 2 and 3
-    float p0[4] = {0.f, 0.f, 0.f, 0.f}, p1[4] = {0.f, 0.f, 0.f, 0.f};
+    float p0[NB], p1[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) p0[nb] = p1[nb] = 0.0f;
     for (int mb2 = 0; mb2 < 16; ++mb2) {
-      floatx4 acc[4];
+      floatx4 acc[NB];
       const floatx4 b2 = *reinterpret_cast<const floatx4*>(sB2 + 16 * mb2 + 4 * g);
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb) acc[nb] = b2;
+      for (int nb = 0; nb < NB; ++nb) acc[nb] = b2;
 #pragma unroll
       for (int kb = 0; kb < 8; ++kb) {
         const bf16x8 w2 = *reinterpret_cast<const bf16x8*>(sW2 + (16 * mb2 + r) * HID + 32 * kb + 8 * g);
 #pragma unroll
-        for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma16x16x32(w2, hf[kb][nb], acc[nb]);
+        for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma16x16x32(w2, hf[kb][nb], acc[nb]);
       }
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb)
+      for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int u = 16 * mb2 + 4 * g + q;
@@ -888,15 +892,15 @@ __device__ __forceinline__ void learned_decide_one(const DevTables& t, int mode,
     }
     // sum the four lane groups' partial dot products (same row r)
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
+    for (int nb = 0; nb < NB; ++nb) {
       p0[nb] += __shfl_xor(p0[nb], 16, 64);
       p1[nb] += __shfl_xor(p1[nb], 16, 64);
       p0[nb] += __shfl_xor(p0[nb], 32, 64);
       p1[nb] += __shfl_xor(p1[nb], 32, 64);
     }
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
-      const int k = c0 + nb * 16 + r;
+    for (int nb = 0; nb < NB; ++nb) {
+      const int k = c0 + (nb0 + nb) * 16 + r;
       if (k >= n_c) continue;
       const int x = a0 + k;
       const float mu = p0[nb] + b3_0, q95 = p1[nb] + b3_1;
@@ -928,8 +932,28 @@ __device__ __forceinline__ void learned_decide_one(const DevTables& t, int mode,
     const uint64_t of = __shfl_xor(fast, d, 64);
     fast = of < fast ? of : fast;
   }
+  *best_out = best;
+  *fast_out = fast;
+}
+
+// The choice and flag from the minima: the cheapest feasible configuration,
+// else the fastest.
+__device__ __forceinline__ void learned_choice(uint32_t best, uint64_t fast, int32_t* cfg_out, uint8_t* flag_out) {
   *flag_out = best != KEY_NONE ? 1 : 0;
   *cfg_out = best != KEY_NONE ? (int32_t)(best & 0xFFFFu) : (int32_t)(fast & 0xFFFFu);
+}
+
+// One valid invocation decided by a whole wavefront (all four row blocks);
+// the choice and flag come back in every lane.
+template <int NHW>
+__device__ __forceinline__ void learned_decide_one(const DevTables& t, int mode, const int64_t* queue,
+                                                   const LearnedArgs& s, const LearnedStage& st, int v, int e,
+                                                   int sl, const bf16* feat_i, int32_t* lat_row, int32_t* cfg_out,
+                                                   uint8_t* flag_out) {
+  uint32_t best;
+  uint64_t fast;
+  learned_scan_rows<NHW, 4>(t, mode, queue, s, st, v, e, sl, feat_i, lat_row, 0, &best, &fast);
+  learned_choice(best, fast, cfg_out, flag_out);
 }
 
 template <int NHW>
@@ -963,41 +987,83 @@ __global__ __launch_bounds__(256) void decide_learned_kernel(DevTables t, Batch 
 }
 
 // Persistent learned decisions for the serving ring: the weights are staged
-// once per workgroup, then each wavefront claims one published request at a
-// time (exit rules as serve_plain_kernel).
+// once per workgroup, then the workgroup takes one published request at a
+// time (wavefront 0 claims it), its four wavefronts each evaluate one
+// 16-row block of the op's configurations, and the minima meet in LDS, so a
+// request's latency is a quarter of one wavefront's work (exit rules as
+// serve_plain_kernel, decided by wavefront 0).
 template <int NHW>
 __global__ __launch_bounds__(256) void serve_learned_kernel(DevTables t, ServeRing r, LearnedArgs s) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   const LearnedStage st = learned_stage(s, lds);
+  __shared__ long long sClaim[2];  // first claimed sequence, claimed count (-1: exit)
+  __shared__ uint32_t sBest[LEARNED_WAVES];
+  __shared__ unsigned long long sFast[LEARNED_WAVES];
   __syncthreads();
   const bf16* feat = reinterpret_cast<const bf16*>(r.feat);
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   int answered = 0;
-  int* clock = blockIdx.x == 0 && threadIdx.x < 64 ? &answered : nullptr;
-  serve_enter(r, lane);
+  int* clock = blockIdx.x == 0 ? &answered : nullptr;
+  serve_enter(r, lane);  // every wavefront counts itself in; wavefront 0 claims for the workgroup
   const unsigned long long start = (unsigned long long)wall_clock64();
   unsigned long long last = start;
   for (;;) {
-    const unsigned long long now = (unsigned long long)wall_clock64();
-    if (now - start > r.life_ticks) break;
-    const ServeClaim c = serve_claim(r, lane, 1, clock);
-    if (c.stop) break;
-    if (c.count == 0) {
-      if (serve_idle(r, now, last)) break;
-      __builtin_amdgcn_s_sleep(8);
-      continue;
+    // wavefront 0 claims one request for the workgroup and tells the others
+    if (w == 0) {
+      const unsigned long long now = (unsigned long long)wall_clock64();
+      long long first = 0, count = -1;
+      if (now - start <= r.life_ticks) {
+        for (;;) {
+          const unsigned long long t_now = (unsigned long long)wall_clock64();
+          const ServeClaim c = serve_claim(r, lane, 1, clock);
+          if (c.stop) break;
+          if (c.count > 0) {
+            first = c.first;
+            count = c.count;
+            last = t_now;
+            break;
+          }
+          if (serve_idle(r, t_now, last) || t_now - start > r.life_ticks) break;
+          __builtin_amdgcn_s_sleep(8);
+        }
+      }
+      if (lane == 0) {
+        sClaim[0] = first;
+        sClaim[1] = count;
+      }
     }
-    last = now;
-    const long long seq = c.first, slot = seq % r.cap;
+    __syncthreads();
+    const long long seq = sClaim[0], count = sClaim[1];
+    if (count < 0) break;
+    const long long slot = seq % r.cap;
     const int4 q = r.req[slot];
-    int32_t cfg = -1;
-    uint8_t f = 0;
-    if ((unsigned)q.x >= (unsigned)t.n_ops || (q.y | q.z) < 0) {
-      if (lane == 0) atomicOr(t.err, 1u);
-    } else {
-      learned_decide_one<NHW>(t, r.mode, nullptr, s, st, q.x, q.y, q.z, feat + slot * EMB, nullptr, &cfg, &f);
+    const bool valid = (unsigned)q.x < (unsigned)t.n_ops && (q.y | q.z) >= 0;
+    // each wavefront takes one 16-row block of the op's 64-row chunks
+    uint32_t best = KEY_NONE;
+    uint64_t fast = ~0ull;
+    if (valid)
+      learned_scan_rows<NHW, 1>(t, r.mode, nullptr, s, st, q.x, q.y, q.z, feat + slot * EMB, nullptr, w, &best,
+                                &fast);
+    if (lane == 0) {
+      sBest[w] = best;
+      sFast[w] = fast;
     }
-    if (lane == 0) serve_write(r, seq, slot, cfg, f);
+    __syncthreads();
+    if (w == 0) {
+      int32_t cfg = -1;
+      uint8_t f = 0;
+      if (!valid) {
+        if (lane == 0) atomicOr(t.err, 1u);
+      } else {
+#pragma unroll
+        for (int u = 1; u < LEARNED_WAVES; ++u) {
+          best = sBest[u] < best ? sBest[u] : best;
+          fast = sFast[u] < fast ? sFast[u] : fast;
+        }
+        learned_choice(best, fast, &cfg, &f);
+      }
+      if (lane == 0) serve_write(r, seq, slot, cfg, f);
+    }
   }
   serve_leave(r, lane);
 }
