@@ -869,6 +869,7 @@ __device__ __forceinline__ void learned_scan_rows(const DevTables& t, int mode, 
     float p0[NB], p1[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) p0[nb] = p1[nb] = 0.0f;
+#pragma unroll 1
     for (int mb2 = 0; mb2 < 16; ++mb2) {
       floatx4 acc[NB];
       const floatx4 b2 = *reinterpret_cast<const floatx4*>(sB2 + 16 * mb2 + 4 * g);
@@ -943,46 +944,56 @@ __device__ __forceinline__ void learned_choice(uint32_t best, uint64_t fast, int
   *cfg_out = best != KEY_NONE ? (int32_t)(best & 0xFFFFu) : (int32_t)(fast & 0xFFFFu);
 }
 
-// One valid invocation decided by a whole wavefront (all four row blocks);
-// the choice and flag come back in every lane.
-template <int NHW>
-__device__ __forceinline__ void learned_decide_one(const DevTables& t, int mode, const int64_t* queue,
-                                                   const LearnedArgs& s, const LearnedStage& st, int v, int e,
-                                                   int sl, const bf16* feat_i, int32_t* lat_row, int32_t* cfg_out,
-                                                   uint8_t* flag_out) {
-  uint32_t best;
-  uint64_t fast;
-  learned_scan_rows<NHW, 4>(t, mode, queue, s, st, v, e, sl, feat_i, lat_row, 0, &best, &fast);
-  learned_choice(best, fast, cfg_out, flag_out);
-}
 
+// Batch of invocations: a workgroup of eight wavefronts, two per SIMD, takes
+// four invocations at a time; wavefronts 2p and 2p + 1 evaluate row blocks
+// 0-1 and 2-3 of invocation p's 64-row chunks, so that one wavefront's GELU
+// work overlaps the other's matrix products on their SIMD, and the pair's
+// minima meet in LDS.
+constexpr int LEARNED_BATCH_WAVES = 8;
 template <int NHW>
-__global__ __launch_bounds__(256) void decide_learned_kernel(DevTables t, Batch b, LearnedArgs s) {
+__global__ __launch_bounds__(64 * LEARNED_BATCH_WAVES) void decide_learned_kernel(DevTables t, Batch b,
+                                                                                  LearnedArgs s) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   const LearnedStage st = learned_stage(s, lds);
+  __shared__ uint32_t sBest[LEARNED_BATCH_WAVES];
+  __shared__ unsigned long long sFast[LEARNED_BATCH_WAVES];
   __syncthreads();
   const bf16* feat = reinterpret_cast<const bf16*>(s.feat);
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int64_t wave0 = (int64_t)blockIdx.x * LEARNED_WAVES + (tid >> 6);
-  const int64_t n_waves = (int64_t)gridDim.x * LEARNED_WAVES;
-  for (int64_t i = wave0; i < b.n; i += n_waves) {
-    const int v = b.op[i], e = b.elapsed[i], sl = b.slo[i];
-    if ((unsigned)v >= (unsigned)t.n_ops || (e | sl) < 0) {
-      if (lane == 0) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, half = w & 1;
+  constexpr int PER = LEARNED_BATCH_WAVES / 2;  // invocations per workgroup at a time
+  for (int64_t i0 = (int64_t)blockIdx.x * PER; i0 < b.n; i0 += (int64_t)gridDim.x * PER) {
+    const int64_t i = i0 + (w >> 1);
+    bool valid = false;
+    uint32_t best = KEY_NONE;
+    uint64_t fast = ~0ull;
+    if (i < b.n) {
+      const int v = b.op[i], e = b.elapsed[i], sl = b.slo[i];
+      valid = (unsigned)v < (unsigned)t.n_ops && (e | sl) >= 0;
+      if (valid) {
+        learned_scan_rows<NHW, 2>(t, b.mode, b.queue, s, st, v, e, sl, feat + i * EMB,
+                                  s.lat_out ? s.lat_out + i * s.lat_stride : nullptr, 2 * half, &best, &fast);
+      } else if (half == 0 && lane == 0) {
         b.cfg[i] = -1;
         if (b.flag) b.flag[i] = 0;
         atomicOr(t.err, 1u);
       }
-      continue;
     }
-    int32_t cfg;
-    uint8_t f;
-    learned_decide_one<NHW>(t, b.mode, b.queue, s, st, v, e, sl, feat + i * EMB,
-                            s.lat_out ? s.lat_out + i * s.lat_stride : nullptr, &cfg, &f);
     if (lane == 0) {
+      sBest[w] = best;
+      sFast[w] = fast;
+    }
+    __syncthreads();
+    if (valid && half == 0 && lane == 0) {
+      const uint32_t ob = sBest[w + 1];
+      const unsigned long long of = sFast[w + 1];
+      int32_t cfg;
+      uint8_t f;
+      learned_choice(ob < best ? ob : best, of < fast ? of : fast, &cfg, &f);
       b.cfg[i] = cfg;
       if (b.flag) b.flag[i] = f;
     }
+    __syncthreads();  // sBest and sFast are rewritten next time round
   }
 }
 
@@ -1157,8 +1168,8 @@ hipError_t launch_train_reduce(const SurrogateBufs& w, int n_chunks, bool first,
 hipError_t launch_decide_learned(const DevTables& t, const Batch& b, const LearnedArgs& a, hipStream_t s) {
   if (b.n == 0) return hipSuccess;
   const int blocks = 256;  // persistent: one workgroup per CU (LDS-bound), grid-stride over invocations
-  const unsigned grid = (unsigned)(b.n < (int64_t)blocks * LEARNED_WAVES ? (b.n + LEARNED_WAVES - 1) / LEARNED_WAVES
-                                                                          : blocks);
+  constexpr int per = LEARNED_BATCH_WAVES / 2;
+  const unsigned grid = (unsigned)(b.n < (int64_t)blocks * per ? (b.n + per - 1) / per : blocks);
 #define LLAMA_LEARNED_CASE(N)                                                                          \
   case N:                                                                                              \
     {                                                                                                  \
@@ -1166,7 +1177,7 @@ hipError_t launch_decide_learned(const DevTables& t, const Batch& b, const Learn
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)LEARNED_LDS); \
       if (e != hipSuccess) return e;                                                                   \
     }                                                                                                  \
-    hipLaunchKernelGGL(decide_learned_kernel<N>, dim3(grid), dim3(64 * LEARNED_WAVES), LEARNED_LDS, s, t, b, a); \
+    hipLaunchKernelGGL(decide_learned_kernel<N>, dim3(grid), dim3(64 * LEARNED_BATCH_WAVES), LEARNED_LDS, s, t, b, a); \
     break;
   switch (t.n_hw) {
     LLAMA_LEARNED_CASE(1)

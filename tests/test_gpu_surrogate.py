@@ -9,9 +9,12 @@ Tolerances (floating point):
     |terms| M: every element within 2^-8 M (one BF16 ulp of the terms) and
     all but 1% within 2^-14 M (see GRAD_RTOL_* below);
   * AdamW: FP32 against FP64 on the same gradients, 1e-5 relative;
-  * fused inference: ln of the predicted latency within 1e-2 of the oracle's on
-    rows both accept, the accept/fallback decision equal on >= 99% of rows, and
-    the configuration choice given the GPU's own integer latencies bit-exact.
+  * fused inference: ln of the predicted latency within 3e-2 of the oracle's on
+    rows both accept, and within 1e-4 on average: a one-ulp BF16 flip of a
+    layer-2 activation u moves the output by |W3[u]| 2^-8 |h2[u]|, which with
+    trained weights reaches about 1e-2, and a few flips can meet in one row of
+    a million; the accept/fallback decision equal on >= 99% of rows, and the
+    configuration choice given the GPU's own integer latencies bit-exact.
 """
 import math
 import sys
@@ -170,7 +173,7 @@ def check_inference(world, L, w, c, tgt, cfg, flag, lat):
     dl = np.abs(np.log(lat[keep].astype(np.float64)) - np.log(L_or[keep].astype(np.float64)))
     say(f"inference: {keep.sum()} predicted rows, max |d ln L| {dl.max() if dl.size else 0:.2e}, "
         f"{edge.sum()} rows at the spread limits")
-    assert dl.size == 0 or dl.max() <= 1e-2
+    assert dl.size == 0 or (dl.max() <= 3e-2 and dl.mean() <= 1e-4)
     assert np.array_equal(lat[~edge & ~ok_or], prof[~edge & ~ok_or])
     # decision given the GPU's own latencies: bit-exact
     c_or, f_or = oracle.select_lat(w.inv_op, tgt, w.n_hw, w.cfg_off, w.hw, w.batch, lat, w.cost)
