@@ -650,9 +650,10 @@ int llama_decide_learned(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
  * workgroups (captured as a HIP graph and relaunched by submit and poll
  * whenever it has exited with requests outstanding) claims published
  * requests as they appear, up to max_batch (at most 64) per wavefront in the
- * plain form and one per wavefront in the learned form, and writes each
- * decision with the device time it was made; a wavefront exits after 20 ms
- * without work and after 250 ms in any case.  Decisions are collected in
+ * plain form and one per workgroup in the learned form (its four wavefronts
+ * split the op's configuration rows), and writes each decision with the
+ * device time it was made; the kernel exits once no wavefront has claimed
+ * work for 20 ms, and after 250 ms in any case.  Decisions are collected in
  * admission order (llama_serve_poll), which frees slots.  While a server is
  * open, the context's tables and surrogate must not be changed.  A server is
  * driven by one caller thread.
