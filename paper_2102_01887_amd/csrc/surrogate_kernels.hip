@@ -757,7 +757,7 @@ __global__ __launch_bounds__(256) void train_reduce_kernel(int64_t n, int64_t nE
 // Fused inference + Eq. 1 scan (see file comment).
 // ---------------------------------------------------------------------------
 constexpr int LEARNED_WAVES = 4;  // wavefronts per workgroup (one per SIMD: 512 registers each)
-constexpr size_t LEARNED_LDS = sizeof(bf16) * (HID * HID + HID * IN) + sizeof(float) * (HID * 2 + 2 * HID);
+constexpr size_t LEARNED_LDS = sizeof(bf16) * (HID * HID + HID * IN + 3 * HID) + sizeof(float) * (HID * 2);
 
 __device__ __forceinline__ int64_t remaining(int64_t r0, int64_t queue) {
   int64_t r = r0 - queue;
@@ -778,7 +778,7 @@ struct LearnedStage {
   const bf16* sW1;   // [256][32]
   const float* sB1;  // [256]
   const float* sB2;  // [256]
-  const float* sW3;  // [2][256], BF16 values
+  const bf16* sW3;   // [3][256] K-permuted: W3's two rows, then zeros
   float b3_0, b3_1;
 };
 
@@ -788,7 +788,7 @@ __device__ __forceinline__ LearnedStage learned_stage(const LearnedArgs& s, unsi
   bf16* sW1 = sW2 + HID * HID;
   float* sB1 = reinterpret_cast<float*>(sW1 + HID * IN);
   float* sB2 = sB1 + HID;
-  float* sW3 = sB2 + HID;
+  bf16* sW3 = reinterpret_cast<bf16*>(sB2 + HID);
   const int tid = threadIdx.x;
   const bf16* W3_16 = reinterpret_cast<const bf16*>(s.W3_16);
   const uint4* src = reinterpret_cast<const uint4*>(s.W2p16);  // 16 bytes = 8 BF16
@@ -800,8 +800,9 @@ __device__ __forceinline__ LearnedStage learned_stage(const LearnedArgs& s, unsi
   for (int i = tid; i < HID; i += blockDim.x) {
     sB1[i] = s.b1[i];
     sB2[i] = s.b2[i];
-    sW3[i] = (float)W3_16[i];
-    sW3[HID + i] = (float)W3_16[HID + i];
+    sW3[w2p_column(i)] = W3_16[i];
+    sW3[HID + w2p_column(i)] = W3_16[HID + i];
+    sW3[2 * HID + i] = (bf16)0.0f;
   }
   return LearnedStage{sW2, sW1, sB1, sB2, sW3, s.b3[0], s.b3[1]};
 }
@@ -821,10 +822,12 @@ __device__ __forceinline__ void learned_scan_rows(const DevTables& t, int mode, 
   const bf16* sW1 = st.sW1;
   const float* sB1 = st.sB1;
   const float* sB2 = st.sB2;
-  const float* sW3 = st.sW3;
   const float b3_0 = st.b3_0, b3_1 = st.b3_1;
   const bf16* E16 = reinterpret_cast<const bf16*>(s.E16);
   const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+  // layer 3 as a product whose 16 A rows repeat (W3 row 0, W3 row 1, 0, 0):
+  // every lane group then holds mu and q of its row in accumulator slots 0, 1
+  const bf16* w3row = st.sW3 + (int64_t)((lane & 3) < 2 ? (lane & 3) : 2) * HID;
   const int64_t r0 = (int64_t)sl - e;
   const int64_t ref = t.ref[v];
   const int64_t W = t.W[(int64_t)mode * t.n_ops + v];
@@ -865,46 +868,42 @@ __device__ __forceinline__ void learned_scan_rows(const DevTables& t, int mode, 
         for (int q = 0; q < 4; ++q) hf[mb >> 1][nb][4 * (mb & 1) + q] = (bf16)gelu(z[q]);
       }
     }
-    // ---- layers 2 and 3
-    float p0[NB], p1[NB];
+    // ---- layers 2 and 3: unit blocks 2kb and 2kb + 1 of layer 2 make the
+    // layer-3 input fragment of K block kb (the layer-1 -> 2 arrangement)
+    floatx4 o3[NB];
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) p0[nb] = p1[nb] = 0.0f;
+    for (int nb = 0; nb < NB; ++nb) o3[nb] = floatx4{b3_0, b3_1, 0.0f, 0.0f};
 #pragma unroll 1
-    for (int mb2 = 0; mb2 < 16; ++mb2) {
-      floatx4 acc[NB];
-      const floatx4 b2 = *reinterpret_cast<const floatx4*>(sB2 + 16 * mb2 + 4 * g);
+    for (int kb3 = 0; kb3 < 8; ++kb3) {
+      bf16x8 h2f[NB];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[nb] = b2;
+      for (int hb = 0; hb < 2; ++hb) {
+        const int mb2 = 2 * kb3 + hb;
+        floatx4 acc[NB];
+        const floatx4 b2 = *reinterpret_cast<const floatx4*>(sB2 + 16 * mb2 + 4 * g);
 #pragma unroll
-      for (int kb = 0; kb < 8; ++kb) {
-        const bf16x8 w2 = *reinterpret_cast<const bf16x8*>(sW2 + (16 * mb2 + r) * HID + 32 * kb + 8 * g);
+        for (int nb = 0; nb < NB; ++nb) acc[nb] = b2;
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma16x16x32(w2, hf[kb][nb], acc[nb]);
-      }
+        for (int kb = 0; kb < 8; ++kb) {
+          const bf16x8 w2 = *reinterpret_cast<const bf16x8*>(sW2 + (16 * mb2 + r) * HID + 32 * kb + 8 * g);
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int u = 16 * mb2 + 4 * g + q;
-          const float h2 = (float)(bf16)gelu(acc[nb][q]);
-          p0[nb] += sW3[u] * h2;
-          p1[nb] += sW3[HID + u] * h2;
+          for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma16x16x32(w2, hf[kb][nb], acc[nb]);
         }
-    }
-    // sum the four lane groups' partial dot products (same row r)
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      p0[nb] += __shfl_xor(p0[nb], 16, 64);
-      p1[nb] += __shfl_xor(p1[nb], 16, 64);
-      p0[nb] += __shfl_xor(p0[nb], 32, 64);
-      p1[nb] += __shfl_xor(p1[nb], 32, 64);
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) h2f[nb][4 * hb + q] = (bf16)gelu(acc[nb][q]);
+      }
+      const bf16x8 w3 = *reinterpret_cast<const bf16x8*>(w3row + 32 * kb3 + 8 * g);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) o3[nb] = mfma16x16x32(w3, h2f[nb], o3[nb]);
     }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const int k = c0 + (nb0 + nb) * 16 + r;
       if (k >= n_c) continue;
       const int x = a0 + k;
-      const float mu = p0[nb] + b3_0, q95 = p1[nb] + b3_1;
+      const float mu = o3[nb][0], q95 = o3[nb][1];
       const float spread = q95 - mu;
       int32_t L;
       // predicted p95 when the spread is finite and in [0, spread_max], else the profile
