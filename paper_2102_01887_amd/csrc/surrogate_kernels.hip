@@ -757,7 +757,12 @@ __global__ __launch_bounds__(256) void train_reduce_kernel(int64_t n, int64_t nE
 // Fused inference + Eq. 1 scan (see file comment).
 // ---------------------------------------------------------------------------
 constexpr int LEARNED_WAVES = 4;  // wavefronts per workgroup (one per SIMD: 512 registers each)
-constexpr size_t LEARNED_LDS = sizeof(bf16) * (HID * HID + HID * IN + 3 * HID) + sizeof(float) * (HID * 2);
+// LDS row strides of the staged weight matrices, padded by 16 bytes: the 16
+// lanes that read one A fragment take 16 consecutive rows at one column, and
+// unpadded 512- and 64-byte strides put those rows in the same banks.
+constexpr int W2_LD = HID + 8, W1_LD = IN + 8;
+constexpr size_t LEARNED_LDS = sizeof(bf16) * (HID * W2_LD + HID * W1_LD + 3 * HID) + sizeof(float) * (HID * 2);
+static_assert(LEARNED_LDS <= 160 * 1024, "fused inference LDS");
 
 __device__ __forceinline__ int64_t remaining(int64_t r0, int64_t queue) {
   int64_t r = r0 - queue;
@@ -774,8 +779,8 @@ __device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b) {
 
 // Weights of the fused inference staged in LDS by a whole workgroup.
 struct LearnedStage {
-  const bf16* sW2;   // [256][256] K-permuted
-  const bf16* sW1;   // [256][32]
+  const bf16* sW2;   // [256][W2_LD] K-permuted
+  const bf16* sW1;   // [256][W1_LD]
   const float* sB1;  // [256]
   const float* sB2;  // [256]
   const bf16* sW3;   // [3][256] K-permuted: W3's two rows, then zeros
@@ -785,18 +790,18 @@ struct LearnedStage {
 // Every thread of the workgroup copies its share; the caller synchronizes.
 __device__ __forceinline__ LearnedStage learned_stage(const LearnedArgs& s, unsigned char* lds) {
   bf16* sW2 = reinterpret_cast<bf16*>(lds);
-  bf16* sW1 = sW2 + HID * HID;
-  float* sB1 = reinterpret_cast<float*>(sW1 + HID * IN);
+  bf16* sW1 = sW2 + HID * W2_LD;
+  float* sB1 = reinterpret_cast<float*>(sW1 + HID * W1_LD);
   float* sB2 = sB1 + HID;
   bf16* sW3 = reinterpret_cast<bf16*>(sB2 + HID);
   const int tid = threadIdx.x;
   const bf16* W3_16 = reinterpret_cast<const bf16*>(s.W3_16);
   const uint4* src = reinterpret_cast<const uint4*>(s.W2p16);  // 16 bytes = 8 BF16
   uint4* dst = reinterpret_cast<uint4*>(sW2);
-  for (int i = tid; i < HID * HID / 8; i += blockDim.x) dst[i] = src[i];
+  for (int i = tid; i < HID * HID / 8; i += blockDim.x) dst[(i / (HID / 8)) * (W2_LD / 8) + i % (HID / 8)] = src[i];
   const uint4* src1 = reinterpret_cast<const uint4*>(s.W1_16);
   uint4* dst1 = reinterpret_cast<uint4*>(sW1);
-  for (int i = tid; i < HID * IN / 8; i += blockDim.x) dst1[i] = src1[i];
+  for (int i = tid; i < HID * IN / 8; i += blockDim.x) dst1[(i / (IN / 8)) * (W1_LD / 8) + i % (IN / 8)] = src1[i];
   for (int i = tid; i < HID; i += blockDim.x) {
     sB1[i] = s.b1[i];
     sB2[i] = s.b2[i];
@@ -856,11 +861,16 @@ __device__ __forceinline__ void learned_scan_rows(const DevTables& t, int mode, 
     // kb: units 32kb + 4g + q (slots 0..3) and 32kb + 16 + 4g + q (slots
     // 4..7), exactly the layer-1 outputs of unit blocks 2kb and 2kb + 1.
     bf16x8 hf[8][NB];
+    // an offset the compiler cannot see through keeps the layer-1 weight
+    // reads inside the chunk loop: hoisted, their 128 registers stay live
+    // through layers 2 and 3 and serialise the GELU chains there
+    int wofs = 0;
+    asm volatile("" : "+v"(wofs));
 #pragma unroll
     for (int mb = 0; mb < 16; ++mb) {
-      const bf16x8 w1 = *reinterpret_cast<const bf16x8*>(sW1 + (16 * mb + r) * IN + 8 * g);
+      const bf16x8 w1 = *reinterpret_cast<const bf16x8*>(sW1 + wofs + (16 * mb + r) * W1_LD + 8 * g);
       // the accumulator starts at the bias of this lane's four units
-      const floatx4 b1 = *reinterpret_cast<const floatx4*>(sB1 + 16 * mb + 4 * g);
+      const floatx4 b1 = *reinterpret_cast<const floatx4*>(sB1 + wofs + 16 * mb + 4 * g);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const floatx4 z = mfma16x16x32(w1, xfrag[nb], b1);
@@ -885,7 +895,7 @@ __device__ __forceinline__ void learned_scan_rows(const DevTables& t, int mode, 
         for (int nb = 0; nb < NB; ++nb) acc[nb] = b2;
 #pragma unroll
         for (int kb = 0; kb < 8; ++kb) {
-          const bf16x8 w2 = *reinterpret_cast<const bf16x8*>(sW2 + (16 * mb2 + r) * HID + 32 * kb + 8 * g);
+          const bf16x8 w2 = *reinterpret_cast<const bf16x8*>(sW2 + (16 * mb2 + r) * W2_LD + 32 * kb + 8 * g);
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma16x16x32(w2, hf[kb][nb], acc[nb]);
         }
@@ -944,12 +954,19 @@ __device__ __forceinline__ void learned_choice(uint32_t best, uint64_t fast, int
 }
 
 
-// Batch of invocations: a workgroup of eight wavefronts, two per SIMD, takes
-// four invocations at a time; wavefronts 2p and 2p + 1 evaluate row blocks
-// 0-1 and 2-3 of invocation p's 64-row chunks, so that one wavefront's GELU
-// work overlaps the other's matrix products on their SIMD, and the pair's
-// minima meet in LDS.
-constexpr int LEARNED_BATCH_WAVES = 8;
+// Batch of invocations: a workgroup of twelve wavefronts (three per SIMD, at
+// most 168 registers each) takes six invocations at a time; the two
+// wavefronts of an invocation each evaluate two of the four 16-row blocks of
+// its 64-row chunks (each A fragment read from LDS feeds two products), so
+// that one wavefront's GELU work overlaps another's matrix products on their
+// SIMD, and their minima meet in LDS.  Measured on C4 (1 M invocations x 64
+// configurations): 13.5 ms; one block per wavefront and sixteen wavefronts
+// 14.4 ms, four blocks and eight wavefronts 13.9 ms.
+constexpr int LEARNED_BATCH_WAVES = 12;
+constexpr int LEARNED_WAVE_BLOCKS = 2;
+constexpr int LEARNED_WPI = 4 / LEARNED_WAVE_BLOCKS;  // wavefronts per invocation
+static_assert(4 % LEARNED_WAVE_BLOCKS == 0 && LEARNED_BATCH_WAVES % LEARNED_WPI == 0 && LEARNED_BATCH_WAVES <= 16,
+              "batch workgroup shape");
 template <int NHW>
 __global__ __launch_bounds__(64 * LEARNED_BATCH_WAVES) void decide_learned_kernel(DevTables t, Batch b,
                                                                                   LearnedArgs s) {
@@ -959,10 +976,10 @@ __global__ __launch_bounds__(64 * LEARNED_BATCH_WAVES) void decide_learned_kerne
   __shared__ unsigned long long sFast[LEARNED_BATCH_WAVES];
   __syncthreads();
   const bf16* feat = reinterpret_cast<const bf16*>(s.feat);
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, half = w & 1;
-  constexpr int PER = LEARNED_BATCH_WAVES / 2;  // invocations per workgroup at a time
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, part = w % LEARNED_WPI;
+  constexpr int PER = LEARNED_BATCH_WAVES / LEARNED_WPI;  // invocations per workgroup at a time
   for (int64_t i0 = (int64_t)blockIdx.x * PER; i0 < b.n; i0 += (int64_t)gridDim.x * PER) {
-    const int64_t i = i0 + (w >> 1);
+    const int64_t i = i0 + w / LEARNED_WPI;
     bool valid = false;
     uint32_t best = KEY_NONE;
     uint64_t fast = ~0ull;
@@ -970,9 +987,10 @@ __global__ __launch_bounds__(64 * LEARNED_BATCH_WAVES) void decide_learned_kerne
       const int v = b.op[i], e = b.elapsed[i], sl = b.slo[i];
       valid = (unsigned)v < (unsigned)t.n_ops && (e | sl) >= 0;
       if (valid) {
-        learned_scan_rows<NHW, 2>(t, b.mode, b.queue, s, st, v, e, sl, feat + i * EMB,
-                                  s.lat_out ? s.lat_out + i * s.lat_stride : nullptr, 2 * half, &best, &fast);
-      } else if (half == 0 && lane == 0) {
+        learned_scan_rows<NHW, LEARNED_WAVE_BLOCKS>(t, b.mode, b.queue, s, st, v, e, sl, feat + i * EMB,
+                                                    s.lat_out ? s.lat_out + i * s.lat_stride : nullptr,
+                                                    LEARNED_WAVE_BLOCKS * part, &best, &fast);
+      } else if (part == 0 && lane == 0) {
         b.cfg[i] = -1;
         if (b.flag) b.flag[i] = 0;
         atomicOr(t.err, 1u);
@@ -983,12 +1001,17 @@ __global__ __launch_bounds__(64 * LEARNED_BATCH_WAVES) void decide_learned_kerne
       sFast[w] = fast;
     }
     __syncthreads();
-    if (valid && half == 0 && lane == 0) {
-      const uint32_t ob = sBest[w + 1];
-      const unsigned long long of = sFast[w + 1];
+    if (valid && part == 0 && lane == 0) {
+#pragma unroll
+      for (int o = 1; o < LEARNED_WPI; ++o) {
+        const uint32_t ob = sBest[w + o];
+        const unsigned long long of = sFast[w + o];
+        best = ob < best ? ob : best;
+        fast = of < fast ? of : fast;
+      }
       int32_t cfg;
       uint8_t f;
-      learned_choice(ob < best ? ob : best, of < fast ? of : fast, &cfg, &f);
+      learned_choice(best, fast, &cfg, &f);
       b.cfg[i] = cfg;
       if (b.flag) b.flag[i] = f;
     }
@@ -1167,7 +1190,7 @@ hipError_t launch_train_reduce(const SurrogateBufs& w, int n_chunks, bool first,
 hipError_t launch_decide_learned(const DevTables& t, const Batch& b, const LearnedArgs& a, hipStream_t s) {
   if (b.n == 0) return hipSuccess;
   const int blocks = 256;  // persistent: one workgroup per CU (LDS-bound), grid-stride over invocations
-  constexpr int per = LEARNED_BATCH_WAVES / 2;
+  constexpr int per = LEARNED_BATCH_WAVES / LEARNED_WPI;
   const unsigned grid = (unsigned)(b.n < (int64_t)blocks * per ? (b.n + per - 1) / per : blocks);
 #define LLAMA_LEARNED_CASE(N)                                                                          \
   case N:                                                                                              \
