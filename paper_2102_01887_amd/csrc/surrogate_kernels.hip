@@ -15,11 +15,13 @@
 // weights and writes the BF16 shadows.  gemm_bf16_kernel (LDS tiles) serves
 // the stand-alone training-path forward.
 //
-// Inference: decide_learned_kernel, persistent, one wavefront per invocation
-// and 64 configuration rows per pass.  W1 and a K-permuted copy of W2 sit in
-// LDS (144 KB); hidden activations never leave registers: the layer-1 output
-// fragment of each lane is, up to a fixed permutation of the contraction
-// index, exactly its layer-2 input fragment.  Each row's p95 latency feeds
+// Inference: decide_learned_kernel, persistent, two wavefronts per
+// invocation, each taking 32 of every 64 configuration rows.  W1 and
+// K-permuted copies of W2 and W3 sit in LDS (about 156 KB, rows padded
+// against bank conflicts); hidden activations never leave registers: the
+// output fragment of each lane in layers 1 and 2 is, up to a fixed
+// permutation of the contraction index, exactly its input fragment of the
+// next layer.  Each row's p95 latency feeds
 // the Eq. 1 scan of the plain path, reduced across the wavefront.
 #include <hip/hip_runtime.h>
 
