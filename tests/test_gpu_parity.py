@@ -242,16 +242,20 @@ def test_update_latencies_recomputes_everything():
     assert_full_parity(r)
 
 
-@pytest.mark.parametrize("maker", ["c1", "c2", "c3"])
+@pytest.mark.parametrize("maker", ["c1", "c2", "c3", "c3w"])
 def test_full_scan_schedule_classes(maker):
     # every crossover of the full scan's schedule table (pure lanes =
     # configurations, pure lanes = invocations, mixed) and the autotuned one
     # decide bit-exactly like the oracle, with and without queueing times;
     # c1 has 8 configurations per op (16-lane groups), c2 64-512, c3 16-256
-    # with up to ~300 invocations per op
+    # with up to ~300 invocations per op, c3w up to 2,048 (backend runs of up
+    # to 512 configurations: every register slot count of the register-
+    # resident layout; longer runs, which take the walking layout, are in
+    # test_max_configs_per_op)
     w = {"c1": lambda: wl.make_c1(queue=True),
          "c2": lambda: wl.make_c2(seed=15, n_pipelines=24, n_inv=40_000),
-         "c3": lambda: wl.make_c3(seed=16, n_pipelines=96, n_inv=60_000, max_cfg=256)}[maker]()
+         "c3": lambda: wl.make_c3(seed=16, n_pipelines=96, n_inv=60_000, max_cfg=256),
+         "c3w": lambda: wl.make_c3(seed=17, n_pipelines=48, n_inv=30_000, max_cfg=2048)}[maker]()
     r = Run(w)
     Q = [700, 0, 25_000, 3][:w.n_hw]
     for mode in (PAPER, PROB):
