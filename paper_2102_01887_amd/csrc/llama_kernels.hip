@@ -1134,22 +1134,24 @@ __device__ __forceinline__ bool bucket_key(const DevTables& t, const Batch& b, i
   return true;
 }
 
-// Few ops: each workgroup counts its chunk of BUCKET_CHUNK invocations in an
-// LDS histogram and writes it as one row of hist[chunk][op].
-__global__ __launch_bounds__(1024) void bucket_hist_kernel(DevTables t, Batch b, int32_t* hist) {
+// Each workgroup counts its chunk of BUCKET_CHUNK invocations in an LDS
+// histogram over the keys op >> shift and writes it as one row of
+// hist[chunk][key]: the ops themselves with shift = 0 (few ops), groups of
+// 2^shift consecutive ops otherwise (the first level of a two-level sort).
+__global__ __launch_bounds__(1024) void bucket_hist_kernel(DevTables t, Batch b, int32_t* hist, int shift) {
   extern __shared__ int32_t sh[];
-  const int n_ops = t.n_ops;
-  for (int j = threadIdx.x; j < n_ops; j += blockDim.x) sh[j] = 0;
+  const int n_keys = ((t.n_ops - 1) >> shift) + 1;
+  for (int j = threadIdx.x; j < n_keys; j += blockDim.x) sh[j] = 0;
   __syncthreads();
   const int64_t a = (int64_t)blockIdx.x * BUCKET_CHUNK;
   const int64_t e = a + BUCKET_CHUNK < b.n ? a + BUCKET_CHUNK : b.n;
   for (int64_t i = a + threadIdx.x; i < e; i += blockDim.x) {
     int v;
-    if (bucket_key(t, b, i, &v)) atomicAdd(&sh[v], 1);
+    if (bucket_key(t, b, i, &v)) atomicAdd(&sh[v >> shift], 1);
   }
   __syncthreads();
-  int32_t* row = hist + (int64_t)blockIdx.x * n_ops;
-  for (int j = threadIdx.x; j < n_ops; j += blockDim.x) row[j] = sh[j];
+  int32_t* row = hist + (int64_t)blockIdx.x * n_keys;
+  for (int j = threadIdx.x; j < n_keys; j += blockDim.x) row[j] = sh[j];
 }
 
 // Per op: exclusive prefix over chunks (in place) and the op's total.
@@ -1177,21 +1179,70 @@ __global__ __launch_bounds__(256) void bucket_columns_kernel(int32_t* hist, int 
   total[v] = run;
 }
 
-// Each chunk places its invocations at start[op] + (earlier chunks' count) +
-// (rank inside the chunk, from an LDS counter).
+// Each chunk places its invocations at start[key] + (earlier chunks' count)
+// + (rank inside the chunk, from an LDS counter).  With shift = 0 the entry
+// is the invocation's index; otherwise it carries the op's low shift bits
+// above a 24-bit index, for the second level.
 __global__ __launch_bounds__(1024) void bucket_place_kernel(DevTables t, Batch b, const int32_t* hist,
-                                                           const int32_t* start, int32_t* perm) {
+                                                           const int32_t* start, int32_t* perm, int shift) {
   extern __shared__ int32_t sh[];
   const int n_ops = t.n_ops;
-  for (int j = threadIdx.x; j < n_ops; j += blockDim.x) sh[j] = 0;
+  const int n_keys = ((n_ops - 1) >> shift) + 1;
+  for (int j = threadIdx.x; j < n_keys; j += blockDim.x) sh[j] = 0;
   __syncthreads();
-  const int32_t* row = hist + (int64_t)blockIdx.x * n_ops;
+  const int32_t* row = hist + (int64_t)blockIdx.x * n_keys;
   const int64_t a = (int64_t)blockIdx.x * BUCKET_CHUNK;
   const int64_t e = a + BUCKET_CHUNK < b.n ? a + BUCKET_CHUNK : b.n;
+  const uint32_t low = (1u << shift) - 1u;
   for (int64_t i = a + threadIdx.x; i < e; i += blockDim.x) {
     const int v = b.op[i];
     if (invalid_invocation(v, b.elapsed[i], b.slo[i], n_ops)) continue;
-    perm[start[v] + row[v] + atomicAdd(&sh[v], 1)] = (int32_t)i;
+    const int k = v >> shift;
+    const uint32_t entry = shift ? (((uint32_t)v & low) << 24) | (uint32_t)i : (uint32_t)i;
+    perm[start[k] + row[k] + atomicAdd(&sh[k], 1)] = (int32_t)entry;
+  }
+}
+
+// Second level: one workgroup per group of FINE_OPS consecutive ops sorts the
+// group's packed entries (its run [cstart[g], cstart[g + 1]) of packed) by
+// the op's low bits, with LDS counters, into perm, and writes the start of
+// each of its ops (start[n_ops] = the end of the last group).  Entries of one
+// op come out in any order.
+constexpr int FINE_BITS = 8;
+constexpr int FINE_OPS = 1 << FINE_BITS;
+__global__ __launch_bounds__(FINE_OPS) void bucket_fine_kernel(const int32_t* cstart, const int32_t* packed,
+                                                               int n_ops, int32_t* start, int32_t* perm) {
+  __shared__ int32_t cnt[FINE_OPS];
+  __shared__ int32_t wsum[FINE_OPS / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int g = blockIdx.x;
+  const int a = cstart[g], e = cstart[g + 1];
+  cnt[tid] = 0;
+  __syncthreads();
+  for (int j = a + tid; j < e; j += FINE_OPS) atomicAdd(&cnt[(uint32_t)packed[j] >> 24], 1);
+  __syncthreads();
+  // exclusive prefix of the FINE_OPS counts: wavefront scans, then the
+  // wavefront totals
+  const int x = cnt[tid];
+  int incl = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += y;
+  }
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  int off = a;
+  for (int w = 0; w < wv; ++w) off += wsum[w];
+  const int pos = off + incl - x;
+  cnt[tid] = pos;  // every thread read its own count above
+  const int v = g * FINE_OPS + tid;
+  if (v < n_ops) start[v] = pos;
+  if (g == (int)gridDim.x - 1 && tid == 0) start[n_ops] = e;
+  __syncthreads();
+  for (int j = a + tid; j < e; j += FINE_OPS) {
+    const uint32_t q = (uint32_t)packed[j];
+    perm[atomicAdd(&cnt[q >> 24], 1)] = (int32_t)(q & 0xFFFFFFu);
   }
 }
 
@@ -2451,22 +2502,51 @@ hipError_t launch_clock_probe(const int* flag, int* ack, unsigned long long* sta
   return hipGetLastError();
 }
 
+// Bucketing by op: few ops, one LDS-histogram counting sort; many ops, a
+// two-level one (groups of FINE_OPS ops, then the ops of each group) while the
+// groups fit one LDS histogram and an index fits 24 bits; else global
+// atomics.
+namespace {
+bool two_level(int64_t n_inv, int32_t n_ops) {
+  return n_ops > BUCKET_LDS_OPS && ((n_ops - 1) >> FINE_BITS) + 1 <= BUCKET_LDS_OPS && n_inv <= (1 << 24);
+}
+int64_t round_words(int64_t w) { return (w + 63) & ~(int64_t)63; }
+}  // namespace
+
 int64_t full_scan_hist_words(int64_t n_inv, int32_t n_ops) {
-  if (n_ops > BUCKET_LDS_OPS) return 0;
-  return ((n_inv + BUCKET_CHUNK - 1) / BUCKET_CHUNK) * (int64_t)n_ops;
+  const int64_t n_chunks = (n_inv + BUCKET_CHUNK - 1) / BUCKET_CHUNK;
+  if (n_ops <= BUCKET_LDS_OPS) return n_chunks * (int64_t)n_ops;
+  // group histograms, then the packed entries of the first level
+  if (two_level(n_inv, n_ops)) return round_words(n_chunks * (int64_t)(((n_ops - 1) >> FINE_BITS) + 1)) + n_inv;
+  return 0;
 }
 
 hipError_t launch_decide_full(const DevTables& t, const Batch& b, const FullScratch& w, hipStream_t s) {
   if (b.n == 0) return hipSuccess;
+  const int n_chunks = (int)((b.n + BUCKET_CHUNK - 1) / BUCKET_CHUNK);
   if (t.n_ops <= BUCKET_LDS_OPS) {
-    const int n_chunks = (int)((b.n + BUCKET_CHUNK - 1) / BUCKET_CHUNK);
     const size_t lds = sizeof(int32_t) * (size_t)t.n_ops;
-    hipLaunchKernelGGL(bucket_hist_kernel, dim3(n_chunks), dim3(1024), lds, s, t, b, w.hist);
+    hipLaunchKernelGGL(bucket_hist_kernel, dim3(n_chunks), dim3(1024), lds, s, t, b, w.hist, 0);
     hipLaunchKernelGGL(bucket_columns_kernel, dim3(blocks_for(t.n_ops, 256)), dim3(256), 0, s, w.hist,
                        n_chunks, t.n_ops, w.cnt);
     hipLaunchKernelGGL(bucket_offsets_kernel, dim3(1), dim3(1024), 0, s, w.cnt, t.n_ops, w.start,
                        (int32_t*)nullptr);
-    hipLaunchKernelGGL(bucket_place_kernel, dim3(n_chunks), dim3(1024), lds, s, t, b, w.hist, w.start, w.perm);
+    hipLaunchKernelGGL(bucket_place_kernel, dim3(n_chunks), dim3(1024), lds, s, t, b, w.hist, w.start, w.perm, 0);
+  } else if (two_level(b.n, t.n_ops)) {
+    // groups of FINE_OPS ops: counts in cnt, group starts in cursor (n_ops >
+    // groups + 1 words), packed entries after the group histograms
+    const int n_groups = ((t.n_ops - 1) >> FINE_BITS) + 1;
+    const size_t lds = sizeof(int32_t) * (size_t)n_groups;
+    int32_t* packed = w.hist + round_words((int64_t)n_chunks * n_groups);
+    hipLaunchKernelGGL(bucket_hist_kernel, dim3(n_chunks), dim3(1024), lds, s, t, b, w.hist, FINE_BITS);
+    hipLaunchKernelGGL(bucket_columns_kernel, dim3(blocks_for(n_groups, 256)), dim3(256), 0, s, w.hist,
+                       n_chunks, n_groups, w.cnt);
+    hipLaunchKernelGGL(bucket_offsets_kernel, dim3(1), dim3(1024), 0, s, w.cnt, n_groups, w.cursor,
+                       (int32_t*)nullptr);
+    hipLaunchKernelGGL(bucket_place_kernel, dim3(n_chunks), dim3(1024), lds, s, t, b, w.hist, w.cursor, packed,
+                       FINE_BITS);
+    hipLaunchKernelGGL(bucket_fine_kernel, dim3(n_groups), dim3(FINE_OPS), 0, s, w.cursor, packed, t.n_ops,
+                       w.start, w.perm);
   } else {
     const unsigned g = blocks_for(b.n, 256);
     hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks_for(t.n_ops + 1, 256)), dim3(256), 0, s, w.cnt,

@@ -242,7 +242,7 @@ def test_update_latencies_recomputes_everything():
     assert_full_parity(r)
 
 
-@pytest.mark.parametrize("maker", ["c1", "c2", "c3", "c3w"])
+@pytest.mark.parametrize("maker", ["c1", "c2", "c3", "c3w", "c3m"])
 def test_full_scan_schedule_classes(maker):
     # every crossover of the full scan's schedule table (pure lanes =
     # configurations, pure lanes = invocations, mixed) and the autotuned one
@@ -251,11 +251,13 @@ def test_full_scan_schedule_classes(maker):
     # with up to ~300 invocations per op, c3w up to 2,048 (backend runs of up
     # to 512 configurations: every register slot count of the register-
     # resident layout; longer runs, which take the walking layout, are in
-    # test_max_configs_per_op)
+    # test_max_configs_per_op); c3m has more ops than one LDS histogram holds,
+    # so its invocations are bucketed in two levels (groups of ops, then ops)
     w = {"c1": lambda: wl.make_c1(queue=True),
          "c2": lambda: wl.make_c2(seed=15, n_pipelines=24, n_inv=40_000),
          "c3": lambda: wl.make_c3(seed=16, n_pipelines=96, n_inv=60_000, max_cfg=256),
-         "c3w": lambda: wl.make_c3(seed=17, n_pipelines=48, n_inv=30_000, max_cfg=2048)}[maker]()
+         "c3w": lambda: wl.make_c3(seed=17, n_pipelines=48, n_inv=30_000, max_cfg=2048),
+         "c3m": lambda: wl.make_c3(seed=18, n_pipelines=320, n_inv=90_000, max_cfg=256)}[maker]()
     r = Run(w)
     Q = [700, 0, 25_000, 3][:w.n_hw]
     for mode in (PAPER, PROB):
@@ -396,11 +398,32 @@ def test_c3_full_size_sampled():
     ws = w.with_invocations(w.inv_op[idx], w.elapsed[idx], w.slo[idx])
     P = oracle.Problem(ws)
     for mode in (PAPER, PROB):
-        c, f = L.decide(op, el, slo, mode=mode)
-        torch.cuda.synchronize()
-        c, f = c.cpu().numpy(), f.cpu().numpy()
         c_or, f_or = P.decide(mode)
-        assert np.array_equal(c[idx], c_or) and np.array_equal(f[idx], f_or), mode
+        # the indexed decision, the full scan (two-level bucketing, both
+        # schedule layouts) and the wave scan
+        for scan in (B.SCAN_AUTO, B.SCAN_FULL, B.SCAN_WAVE):
+            c, f = L.decide(op, el, slo, mode=mode, scan=scan)
+            torch.cuda.synchronize()
+            c, f = c.cpu().numpy(), f.cpu().numpy()
+            assert np.array_equal(c[idx], c_or) and np.array_equal(f[idx], f_or), (mode, scan)
+
+
+def test_full_scan_beyond_packed_indices():
+    # more than 2^24 invocations over more ops than one LDS histogram holds:
+    # the full scan buckets with global atomics instead of the two-level
+    # sort (whose entries pack a 24-bit index); the oracle checks a sample
+    torch = _torch()
+    w = wl.make_c3(seed=19, n_pipelines=320, n_inv=(1 << 24) + 4096, max_cfg=64)
+    L = B.Llama(0).load(w)
+    op, el, slo = dev(w.inv_op, torch), dev(w.elapsed, torch), dev(w.slo, torch)
+    idx = np.sort(np.random.default_rng(1).choice(w.n_inv, 50_000, replace=False))
+    idx[-1] = w.n_inv - 1
+    ws = w.with_invocations(w.inv_op[idx], w.elapsed[idx], w.slo[idx])
+    c_or, f_or = oracle.Problem(ws).decide(PAPER)
+    c, f = L.decide(op, el, slo, mode=PAPER, scan=B.SCAN_FULL)
+    torch.cuda.synchronize()
+    c, f = c.cpu().numpy(), f.cpu().numpy()
+    assert np.array_equal(c[idx], c_or) and np.array_equal(f[idx], f_or)
 
 
 @pytest.mark.parametrize("maker", ["c2", "c3"])
