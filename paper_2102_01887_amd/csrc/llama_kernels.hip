@@ -1407,14 +1407,13 @@ __global__ __launch_bounds__(256) void decide_wave_kernel(DevTables t, Batch b) 
 //   lanes = configurations: groups of S = 16, 32 or 64 lanes (the smallest
 //     that covers c, so 64 / S invocations share a pass), each lane walking
 //     every S-th configuration, then a min over the group:
-//     ~ceil(k / (64 / S)) (5 ceil(c / S) + 14).  With S = 64 and every
-//     backend's run at most 64 CFG_REG_SLOTS long, the table is read once
-//     into registers (one round of loads instead of one per pass) and the
-//     invocations take their turns: each lane computes one invocation's
-//     targets, which the wavefront then reads lane by lane:
-//     ~ceil(k / 64) 24 NHW + k (NHW (1 + 3 rs) + 10), rs = the 64-entry
-//     register slots per backend that the longest run needs (1, 2, 3, 4, 6
-//     or 8).
+//     ~ceil(k / (64 / S)) (5 ceil(c / S) + 14).  With S = 64 the table is
+//     held in registers instead, in pieces of at most CFG_REG_SLOTS slots of
+//     64 per backend (one round of loads per piece instead of one per pass),
+//     and the invocations take their turns: each lane computes one
+//     invocation's targets, which the wavefront then reads lane by lane:
+//     ~ceil(k / 64) 24 NHW + k sum over pieces of (NHW (1 + 3 rs) + 10), rs
+//     = the slots of the piece.
 // The first is taken when its count times the crossover's den is at most the
 // second's times its num; the crossover is the schedule table entry the
 // autotuner picks on the caller's batch (llama_autotune_full).
@@ -1430,7 +1429,7 @@ __device__ __forceinline__ uint32_t group_min_u32(uint32_t v, int S) {
   return v;
 }
 
-constexpr int CFG_REG_SLOTS = 8;  // register slots of 64 configurations per backend run
+constexpr int CFG_REG_SLOTS = 4;  // register slots of 64 configurations per backend run and piece
 // Minimum over the 64 lanes, returned to every lane; the identity as the
 // DPP "old" value lets each step fuse into one v_min_u32 with a DPP source.
 __device__ __forceinline__ uint32_t wave_min_u32_fused(uint32_t v) {
@@ -1444,27 +1443,51 @@ __device__ __forceinline__ uint32_t wave_min_u32_fused(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
-// Lanes = configurations held in registers, for an op whose every backend
-// run is at most 64 RS long: slot u of backend h holds configuration
-// seg[h] + lane + 64 u (never feasible past the run).  The table is read in
-// one round of loads; each lane then computes one invocation's targets, and
-// the wavefront takes the invocations in turn, reading their targets lane by
-// lane.
+// Lanes = configurations held in registers, one piece of every backend's run
+// at a time: slot u of backend h holds configuration seg[h] + base + lane +
+// 64 u (never feasible past the run), RS <= CFG_REG_SLOTS slots per backend.
+// The piece is read in one round of loads; the wavefront then takes the
+// batch's cnt invocations in turn, reading each one's targets (tgv, one
+// invocation per lane) lane by lane, and folds the piece's minimum into the
+// invocation's lane of res.
 template <int NHW, int RS>
-__device__ __forceinline__ void scan_cfg_regs(const DevTables& t, const Batch& b, const int32_t* perm, int p0,
-                                              int p1, const int (&seg)[NHW + 1], int64_t ref, int64_t W,
-                                              int fastest) {
+__device__ __forceinline__ void scan_cfg_piece(const DevTables& t, const int (&seg)[NHW + 1], int base,
+                                               const int32_t (&tgv)[NHW], int cnt, uint32_t& res) {
   const int lane = threadIdx.x & 63;
   uint32_t cL[NHW][RS], cK[NHW][RS];
 #pragma unroll
   for (int h = 0; h < NHW; ++h)
 #pragma unroll
     for (int u = 0; u < RS; ++u) {
-      const int x = seg[h] + lane + 64 * u;
+      const int x = seg[h] + base + lane + 64 * u;
       const uint2 q = x < seg[h + 1] ? t.tab[x] : make_uint2(0x7FFFFFFFu, KEY_NONE);
       cL[h][u] = q.x;
       cK[h][u] = q.y;
     }
+  for (int j = 0; j < cnt; ++j) {
+    // every slot's candidate on its own, then a tree of minima (no chain
+    // through one accumulator)
+    uint32_t cand[NHW * RS];
+#pragma unroll
+    for (int h = 0; h < NHW; ++h) {
+      const int32_t tg = __builtin_amdgcn_readlane(tgv[h], j);
+#pragma unroll
+      for (int u = 0; u < RS; ++u) cand[h * RS + u] = (int32_t)cL[h][u] < tg ? cK[h][u] : KEY_NONE;
+    }
+#pragma unroll
+    for (int w = 1; w < NHW * RS; w *= 2)
+#pragma unroll
+      for (int q = 0; q + w < NHW * RS; q += 2 * w) cand[q] = umin32(cand[q], cand[q + w]);
+    const uint32_t best = wave_min_u32_fused(cand[0]);
+    res = lane == j && best < res ? best : res;
+  }
+}
+
+template <int NHW>
+__device__ __forceinline__ void scan_cfg_regs(const DevTables& t, const Batch& b, const int32_t* perm, int p0,
+                                              int p1, const int (&seg)[NHW + 1], int longest, int64_t ref,
+                                              int64_t W, int fastest) {
+  const int lane = threadIdx.x & 63;
   for (int pb = p0; pb < p1; pb += 64) {
     const int p = pb + lane;
     const bool live = p < p1;
@@ -1478,22 +1501,14 @@ __device__ __forceinline__ void scan_cfg_regs(const DevTables& t, const Batch& b
     }
     uint32_t res = KEY_NONE;
     const int cnt = p1 - pb < 64 ? p1 - pb : 64;
-    for (int j = 0; j < cnt; ++j) {
-      // every slot's candidate on its own, then a tree of minima (no chain
-      // through one accumulator)
-      uint32_t cand[NHW * RS];
-#pragma unroll
-      for (int h = 0; h < NHW; ++h) {
-        const int32_t tg = __builtin_amdgcn_readlane(tgv[h], j);
-#pragma unroll
-        for (int u = 0; u < RS; ++u) cand[h * RS + u] = (int32_t)cL[h][u] < tg ? cK[h][u] : KEY_NONE;
+    for (int base = 0; base < longest; base += 64 * CFG_REG_SLOTS) {
+      const int rest = longest - base;
+      switch (rest <= 64 ? 1 : rest <= 128 ? 2 : rest <= 192 ? 3 : 4) {
+        case 1: scan_cfg_piece<NHW, 1>(t, seg, base, tgv, cnt, res); break;
+        case 2: scan_cfg_piece<NHW, 2>(t, seg, base, tgv, cnt, res); break;
+        case 3: scan_cfg_piece<NHW, 3>(t, seg, base, tgv, cnt, res); break;
+        default: scan_cfg_piece<NHW, 4>(t, seg, base, tgv, cnt, res); break;
       }
-#pragma unroll
-      for (int w = 1; w < NHW * RS; w *= 2)
-#pragma unroll
-        for (int q = 0; q + w < NHW * RS; q += 2 * w) cand[q] = umin32(cand[q], cand[q + w]);
-      const uint32_t best = wave_min_u32_fused(cand[0]);
-      res = lane == j ? best : res;
     }
     if (live) write_choice(b, i, res, fastest);
   }
@@ -1523,11 +1538,11 @@ __global__ __launch_bounds__(256) void scan_classes_kernel(DevTables t, Batch b,
   int longest = 0;
 #pragma unroll
   for (int h = 0; h < NHW; ++h) longest = seg[h + 1] - seg[h] > longest ? seg[h + 1] - seg[h] : longest;
-  const bool in_regs = S == 64 && longest <= 64 * CFG_REG_SLOTS;
-  const int rs = longest <= 64 ? 1 : longest <= 128 ? 2 : longest <= 192 ? 3 : longest <= 256 ? 4
-               : longest <= 384 ? 6 : 8;
+  // register pieces: full ones of CFG_REG_SLOTS slots, then the rest
+  const int full = longest / (64 * CFG_REG_SLOTS), rest = longest % (64 * CFG_REG_SLOTS);
+  const int per_inv = full * (NHW * (1 + 3 * CFG_REG_SLOTS) + 10) + (rest ? NHW * (1 + 3 * ((rest + 63) >> 6)) + 10 : 0);
   const int64_t cost_inv = (int64_t)((k + 63) / 64) * c * 3;
-  const int64_t cost_cfg = in_regs ? (int64_t)((k + 63) / 64) * 24 * NHW + (int64_t)k * (NHW * (1 + 3 * rs) + 10)
+  const int64_t cost_cfg = S == 64 ? (int64_t)((k + 63) / 64) * 24 * NHW + (int64_t)k * per_inv
                                    : (int64_t)((k + per - 1) / per) * (5 * ((c + S - 1) / S) + 14);
   if (cost_inv * cross_den <= cost_cfg * cross_num) {
     // lanes = invocations; the table as scalar operands, two configurations per 16 bytes
@@ -1566,15 +1581,8 @@ __global__ __launch_bounds__(256) void scan_classes_kernel(DevTables t, Batch b,
     }
     return;
   }
-  if (in_regs) {
-    switch (rs) {
-      case 1: scan_cfg_regs<NHW, 1>(t, b, perm, p0, p1, seg, ref, W, fastest); break;
-      case 2: scan_cfg_regs<NHW, 2>(t, b, perm, p0, p1, seg, ref, W, fastest); break;
-      case 3: scan_cfg_regs<NHW, 3>(t, b, perm, p0, p1, seg, ref, W, fastest); break;
-      case 4: scan_cfg_regs<NHW, 4>(t, b, perm, p0, p1, seg, ref, W, fastest); break;
-      case 6: scan_cfg_regs<NHW, 6>(t, b, perm, p0, p1, seg, ref, W, fastest); break;
-      default: scan_cfg_regs<NHW, 8>(t, b, perm, p0, p1, seg, ref, W, fastest); break;
-    }
+  if (S == 64) {
+    scan_cfg_regs<NHW>(t, b, perm, p0, p1, seg, longest, ref, W, fastest);
     return;
   }
   // lanes = configurations, 64 / S invocations per pass

@@ -249,9 +249,9 @@ def test_full_scan_schedule_classes(maker):
     # decide bit-exactly like the oracle, with and without queueing times;
     # c1 has 8 configurations per op (16-lane groups), c2 64-512, c3 16-256
     # with up to ~300 invocations per op, c3w up to 2,048 (backend runs of up
-    # to 512 configurations: every register slot count of the register-
-    # resident layout; longer runs, which take the walking layout, are in
-    # test_max_configs_per_op); c3m has more ops than one LDS histogram holds,
+    # to 512 configurations: one or two register pieces of every slot count;
+    # test_max_configs_per_op has runs of ~16 K, 64 pieces); c3m has more ops
+    # than one LDS histogram holds,
     # so its invocations are bucketed in two levels (groups of ops, then ops)
     w = {"c1": lambda: wl.make_c1(queue=True),
          "c2": lambda: wl.make_c2(seed=15, n_pipelines=24, n_inv=40_000),
