@@ -208,7 +208,7 @@ __global__ __launch_bounds__(256) void alpha_queue_kernel(DevTables t, Batch b) 
 // m_lat serves, L < target); the per-backend counts at j give, for each
 // backend, how many of its configurations are feasible, which is exactly
 // where the per-backend search in latency order ends, so the prefix and
-// suffix minima of that order (a_pf, a_si) give each backend's best key.  The rest is the per-backend kernel's: the ratio of the
+// suffix minima of that order (a_ps) give each backend's best key.  The rest is the per-backend kernel's: the ratio of the
 // objective values of the best key on the backend and the best elsewhere
 // (no configuration on the backend -> 0; none elsewhere -> infinity; a zero
 // own minimum -> infinity, or 1 when the other minimum is zero too), and with
@@ -261,14 +261,8 @@ __global__ __launch_bounds__(256) void affinity_queue_kernel(DevTables t, Batch 
 #pragma unroll
     for (int h = 0; h < NHW; ++h) {
       const int feas = lo < end ? (int)cnt[(int64_t)lo * NHW + h] : so[h + 1] - so[h];
-      const int j = so[h] + feas;
-      uint32_t k = KEY_NONE;
-      if (feas > 0) k = t.a_pf[j - 1];
-      if (j < so[h + 1]) {
-        const uint32_t ki = t.a_si[j];
-        k = ki < k ? ki : k;
-      }
-      best[h] = k;
+      const uint2 ps = t.a_ps[(int64_t)so[h] + feas + (int64_t)v * NHW + h];
+      best[h] = ps.y < ps.x ? ps.y : ps.x;
     }
     const double* val = t.a_val + 2 * (int64_t)lo0;
 #pragma unroll

@@ -83,7 +83,7 @@ struct llama_ctx {
   bool has_alpha = false;
   uint32_t alpha_num = 0, alpha_den = 1;
   int32_t alpha_steps = 0, alpha_msteps = 0;
-  DevBuf d_a_lat, d_a_pf, d_a_si, d_m_lat, d_m_pf, d_m_si, d_a_val;
+  DevBuf d_a_lat, d_a_ps, d_m_lat, d_m_pf, d_m_si, d_a_val;
   DevBuf d_a_smp, d_a_soff;
   DevBuf d_a_fk, d_a_ik, d_aq_T, d_aq_pf, d_aq_si, d_aq_cnt, d_m_cnt;  // finite alpha: per-configuration keys; per-call merged order
   int32_t alpha_max_op = 0;
@@ -152,8 +152,7 @@ struct llama_ctx {
     t.cfg_q = d_cfg_q.as<uint4>();
     t.cfg_batch = d_cfg_batch.as<int32_t>();
     t.a_lat = d_a_lat.as<int32_t>();
-    t.a_pf = d_a_pf.as<uint32_t>();
-    t.a_si = d_a_si.as<uint32_t>();
+    t.a_ps = d_a_ps.as<uint2>();
     t.a_steps = alpha_steps;
     t.m_lat = d_m_lat.as<int32_t>();
     t.m_pf = d_m_pf.as<uint32_t>();
@@ -191,7 +190,7 @@ struct llama_ctx {
                            &d_succ_ids, &d_succ_q, &d_ref, &d_W, &d_hdr, &d_front_L,
                            &d_rec[0], &d_rec_tail[0], &d_rec_tail2[0], &d_ovf[0], &d_rec[1], &d_rec_tail[1], &d_rec_tail2[1], &d_ovf[1], &d_rec_q, &d_rec_tail_q, &d_rec_tail2_q, &d_ovf_q, &d_seg_off, &d_tab, &d_err,
                            &d_cnt, &d_start, &d_cursor, &d_perm, &d_hist, &d_mst,
-                           &d_mst_n, &d_cfg_off, &d_cfg_hw, &d_cfg_lat, &d_cfg_key, &d_cfg_q, &d_cfg_batch, &d_a_lat, &d_a_pf, &d_a_si, &d_m_lat, &d_m_pf, &d_m_si, &d_a_val, &d_a_smp, &d_a_soff, &d_a_fk, &d_a_ik, &d_aq_T, &d_aq_pf, &d_aq_si, &d_aq_cnt, &d_m_cnt, &d_aff_scratch, &d_batch_scratch, &d_qacc, &d_fb_ksrc, &d_fb_tab_src, &d_fb_ref_k, &d_fb_count, &d_fb_sum, &d_fb_dirty, &d_sim_a, &d_sim_b, &d_sim_row_op};
+                           &d_mst_n, &d_cfg_off, &d_cfg_hw, &d_cfg_lat, &d_cfg_key, &d_cfg_q, &d_cfg_batch, &d_a_lat, &d_a_ps, &d_m_lat, &d_m_pf, &d_m_si, &d_a_val, &d_a_smp, &d_a_soff, &d_a_fk, &d_a_ik, &d_aq_T, &d_aq_pf, &d_aq_si, &d_aq_cnt, &d_m_cnt, &d_aff_scratch, &d_batch_scratch, &d_qacc, &d_fb_ksrc, &d_fb_tab_src, &d_fb_ref_k, &d_fb_count, &d_fb_sum, &d_fb_dirty, &d_sim_a, &d_sim_b, &d_sim_row_op};
     int64_t s = 0;
     for (auto* b : all) s += (int64_t)b->bytes;
     return s;

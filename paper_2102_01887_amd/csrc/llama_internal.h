@@ -141,8 +141,10 @@ struct DevTables {
   const int32_t* cfg_batch;  // [n_cfg] batch size, caller order
   // finite-alpha objective, per (op, backend) segment of seg_off, sorted by latency
   const int32_t* a_lat;      // [n_cfg] latency
-  const uint32_t* a_pf;      // [n_cfg] min feasible key over the segment's entries up to here
-  const uint32_t* a_si;      // [n_cfg] min infeasible key over the segment's entries from here
+  // [n_cfg + n_ops*n_hw] per segment of len entries, len + 1 pairs {min
+  // feasible key over its first j entries, min infeasible key over entries j..}
+  // (KEY_NONE for none), the pair of global entry index x at x + segment index
+  const uint2* a_ps;
   int32_t a_steps;           // binary-search steps covering the longest segment
   // the same per op over all backends (cfg_off segments), for Q = 0
   const int32_t* m_lat;

@@ -1847,7 +1847,7 @@ __global__ __launch_bounds__(256) void decide_alpha_kernel(DevTables t, Batch b)
   const int64_t ref = t.ref[v];
   const int64_t W = t.W[(int64_t)b.mode * t.n_ops + v];
   const int32_t* so = t.seg_off + (int64_t)v * NHW;
-  int base[NHW], end[NHW];
+  int base[NHW];
   const int32_t* smp = t.a_smp + t.a_soff[v];
 #pragma unroll
   for (int h = 0; h < NHW; ++h) {
@@ -1855,28 +1855,23 @@ __global__ __launch_bounds__(256) void decide_alpha_kernel(DevTables t, Batch b)
     const int64_t R = remaining_time(r0, b.queue ? b.queue[h] : 0);
     const int32_t target = R == 0 ? 0 : (int32_t)div_floor_pos(ref * R, W);
     base[h] = lo + count_below(t.a_lat + lo, len, smp, target);
-    end[h] = lo + len;
     smp += ((len + ALPHA_BLOCK - 1) / ALPHA_BLOCK + 3) & ~3;
   }
   uint32_t best = KEY_NONE;
   uint8_t meets = 0;
+  uint2 ps[NHW];
+#pragma unroll
+  for (int h = 0; h < NHW; ++h) ps[h] = t.a_ps[(int64_t)base[h] + (int64_t)v * NHW + h];
 #pragma unroll
   for (int h = 0; h < NHW; ++h) {
-    const int j = base[h];  // first configuration of the segment with L >= target
-    const int lo = so[h];
-    if (j > lo) {
-      const uint32_t kf = t.a_pf[j - 1];
-      if (kf < best) {
-        best = kf;
-        meets = 1;
-      }
+    // keys of the segment's entries below and from the first with L >= target
+    if (ps[h].x < best) {
+      best = ps[h].x;
+      meets = 1;
     }
-    if (j < end[h]) {
-      const uint32_t ki = t.a_si[j];
-      if (ki < best) {
-        best = ki;
-        meets = 0;
-      }
+    if (ps[h].y < best) {
+      best = ps[h].y;
+      meets = 0;
     }
   }
   b.cfg[i] = (int)(best & 0xFFFFu);
@@ -2125,13 +2120,12 @@ __global__ __launch_bounds__(256) void affinity_kernel(DevTables t, Batch b, dou
     const int64_t ref = t.ref[v];
     const int64_t W = t.W[(int64_t)b.mode * t.n_ops + v];
     const int32_t* so = t.seg_off + (int64_t)v * NHW;
-    int base[NHW], len[NHW], lo[NHW], end[NHW];
+    int base[NHW], len[NHW];
     int32_t target[NHW];
 #pragma unroll
     for (int h = 0; h < NHW; ++h) {
-      lo[h] = base[h] = so[h];
-      end[h] = so[h + 1];
-      len[h] = end[h] - base[h];
+      base[h] = so[h];
+      len[h] = so[h + 1] - so[h];
       const int64_t R = remaining_time(r0, b.queue ? b.queue[h] : 0);
       target[h] = R == 0 ? 0 : (int32_t)div_floor_pos(ref * R, W);
     }
@@ -2152,14 +2146,8 @@ __global__ __launch_bounds__(256) void affinity_kernel(DevTables t, Batch b, dou
     uint32_t best[NHW];
 #pragma unroll
     for (int h = 0; h < NHW; ++h) {
-      const int j = base[h];
-      uint32_t k = KEY_NONE;
-      if (j > lo[h]) k = t.a_pf[j - 1];
-      if (j < end[h]) {
-        const uint32_t ki = t.a_si[j];
-        k = ki < k ? ki : k;
-      }
-      best[h] = k;
+      const uint2 ps = t.a_ps[(int64_t)base[h] + (int64_t)v * NHW + h];
+      best[h] = ps.y < ps.x ? ps.y : ps.x;
     }
     const double* val = t.a_val + 2 * (int64_t)t.cfg_off[v];
 #pragma unroll

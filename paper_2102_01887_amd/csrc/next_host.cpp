@@ -203,13 +203,31 @@ int build_alpha_tables(llama_ctx* c) {
       }
     }
   }
+  // per backend run of len entries, len + 1 pairs {min feasible key over its
+  // first j entries, min infeasible key over entries j..}: run h of op v
+  // starts at seg_off + v * n_hw + h, one extra pair per earlier run
+  std::vector<uint2> a_ps((size_t)n_cfg + (size_t)n_ops * n_hw);
+#pragma omp parallel
+  {
+    std::vector<int32_t> cnt(n_hw + 1);
+#pragma omp for schedule(dynamic, 256)
+    for (int v = 0; v < n_ops; ++v) {
+      const int a = c->cfg_off[v];
+      backend_counts(v, cnt);
+      for (int h = 0; h < n_hw; ++h) {
+        const int s0 = a + cnt[h], len = cnt[h + 1] - cnt[h];
+        uint2* ps = a_ps.data() + (size_t)s0 + (size_t)v * n_hw + h;
+        for (int j = 0; j <= len; ++j)
+          ps[j] = make_uint2(j > 0 ? a_pf[s0 + j - 1] : KEY_NONE, j < len ? a_si[s0 + j] : KEY_NONE);
+      }
+    }
+  }
   int steps = 0, msteps = 0;
   while ((1 << steps) <= max_seg) ++steps;
   while ((1 << msteps) <= max_op) ++msteps;
   int rc;
   if ((rc = upload(c, c->d_a_lat, a_lat.data(), a_lat.size() * 4, "alpha latencies")) ||
-      (rc = upload(c, c->d_a_pf, a_pf.data(), a_pf.size() * 4, "alpha prefix keys")) ||
-      (rc = upload(c, c->d_a_si, a_si.data(), a_si.size() * 4, "alpha suffix keys")) ||
+      (rc = upload(c, c->d_a_ps, a_ps.data(), a_ps.size() * sizeof(uint2), "alpha prefix and suffix keys")) ||
       (rc = upload(c, c->d_m_lat, m_lat.data(), m_lat.size() * 4, "alpha merged latencies")) ||
       (rc = upload(c, c->d_m_pf, m_pf.data(), m_pf.size() * 4, "alpha merged prefix keys")) ||
       (rc = upload(c, c->d_m_si, m_si.data(), m_si.size() * 4, "alpha merged suffix keys")) ||
