@@ -238,6 +238,13 @@ struct BatchingArgs {
   uint2* queue;      // scratch: BATCH_QUEUES sub-queues of {invocation, x* | meets << 16} left
                      // for the batch-limited scan, each of batch_queue_capacity(n) entries
   uint32_t* count;   // scratch: entries of sub-queue j at count[32 * j] (one 128-byte line each)
+  // scratch of the grouping by op (batch_group_words): per-op counts, starts
+  // and cursors, the slots by op, and the counting sort's histograms
+  int32_t* op_cnt;
+  int32_t* op_start;
+  int32_t* op_cursor;
+  int32_t* perm;
+  int32_t* hist;
 };
 // The commit kernel's workgroup g appends to sub-queue g mod BATCH_QUEUES, so
 // that no single counter takes every workgroup's atomic.
@@ -247,8 +254,16 @@ inline int64_t batch_queue_capacity(int64_t n) {
   const int64_t groups = (n + BATCH_BLOCK - 1) / BATCH_BLOCK;
   return ((groups + BATCH_QUEUES - 1) / BATCH_QUEUES) * BATCH_BLOCK;
 }
-inline size_t batch_scratch_bytes(int64_t n) {
-  return sizeof(uint32_t) * 32 * BATCH_QUEUES + sizeof(uint2) * (size_t)BATCH_QUEUES * (size_t)batch_queue_capacity(n);
+int64_t full_scan_hist_words(int64_t n_inv, int32_t n_ops);
+// Words of the grouping scratch, each part on a 64-word boundary.
+inline int64_t batch_words64(int64_t w) { return (w + 63) & ~(int64_t)63; }
+inline int64_t batch_group_words(int64_t n, int32_t n_ops) {
+  const int64_t slots = (int64_t)BATCH_QUEUES * batch_queue_capacity(n);
+  return 3 * batch_words64((int64_t)n_ops + 1) + batch_words64(slots) + batch_words64(full_scan_hist_words(slots, n_ops));
+}
+inline size_t batch_scratch_bytes(int64_t n, int32_t n_ops) {
+  return sizeof(uint32_t) * 32 * BATCH_QUEUES + sizeof(uint2) * (size_t)BATCH_QUEUES * (size_t)batch_queue_capacity(n) +
+         sizeof(int32_t) * (size_t)batch_group_words(n, n_ops);
 }
 hipError_t launch_decide_batching(const DevTables& t, const Batch& b, const BatchingArgs& a, hipStream_t s);
 // Finite-alpha Eq. 1 with queueing times through the per-call merged order

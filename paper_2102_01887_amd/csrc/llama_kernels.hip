@@ -1134,20 +1134,49 @@ __device__ __forceinline__ bool bucket_key(const DevTables& t, const Batch& b, i
   return true;
 }
 
-// Each workgroup counts its chunk of BUCKET_CHUNK invocations in an LDS
+// Sources of bucketing keys over positions 0 .. size() - 1.  count_key is
+// the first pass's (it may answer what it leaves out), place_key the second's.
+struct InvocationKeys {  // the batch's invocations by op; invalid ones answered at once
+  DevTables t;
+  Batch b;
+  __device__ int64_t size() const { return b.n; }
+  __device__ bool count_key(int64_t i, int* v) const { return bucket_key(t, b, i, v); }
+  __device__ bool place_key(int64_t i, int* v) const {
+    *v = b.op[i];
+    return !invalid_invocation(*v, b.elapsed[i], b.slo[i], t.n_ops);
+  }
+};
+struct QueueKeys {  // occupied slots of the batching sub-queues, by their invocation's op
+  const int32_t* op;
+  const uint2* queue;
+  const uint32_t* count;
+  int64_t cap;
+  __device__ int64_t size() const { return (int64_t)BATCH_QUEUES * cap; }
+  __device__ bool place_key(int64_t w, int* v) const {
+    const int sq = (int)(w / cap);
+    if (w - (int64_t)sq * cap >= (int64_t)count[32 * sq]) return false;
+    *v = op[queue[w].x];
+    return true;
+  }
+  __device__ bool count_key(int64_t w, int* v) const { return place_key(w, v); }
+};
+
+// Each workgroup counts its chunk of BUCKET_CHUNK positions in an LDS
 // histogram over the keys op >> shift and writes it as one row of
 // hist[chunk][key]: the ops themselves with shift = 0 (few ops), groups of
 // 2^shift consecutive ops otherwise (the first level of a two-level sort).
-__global__ __launch_bounds__(1024) void bucket_hist_kernel(DevTables t, Batch b, int32_t* hist, int shift) {
+template <class K>
+__global__ __launch_bounds__(1024) void bucket_hist_kernel(K keys, int n_ops, int32_t* hist, int shift) {
   extern __shared__ int32_t sh[];
-  const int n_keys = ((t.n_ops - 1) >> shift) + 1;
+  const int n_keys = ((n_ops - 1) >> shift) + 1;
   for (int j = threadIdx.x; j < n_keys; j += blockDim.x) sh[j] = 0;
   __syncthreads();
+  const int64_t n = keys.size();
   const int64_t a = (int64_t)blockIdx.x * BUCKET_CHUNK;
-  const int64_t e = a + BUCKET_CHUNK < b.n ? a + BUCKET_CHUNK : b.n;
+  const int64_t e = a + BUCKET_CHUNK < n ? a + BUCKET_CHUNK : n;
   for (int64_t i = a + threadIdx.x; i < e; i += blockDim.x) {
     int v;
-    if (bucket_key(t, b, i, &v)) atomicAdd(&sh[v >> shift], 1);
+    if (keys.count_key(i, &v)) atomicAdd(&sh[v >> shift], 1);
   }
   __syncthreads();
   int32_t* row = hist + (int64_t)blockIdx.x * n_keys;
@@ -1179,24 +1208,25 @@ __global__ __launch_bounds__(256) void bucket_columns_kernel(int32_t* hist, int 
   total[v] = run;
 }
 
-// Each chunk places its invocations at start[key] + (earlier chunks' count)
-// + (rank inside the chunk, from an LDS counter).  With shift = 0 the entry
-// is the invocation's index; otherwise it carries the op's low shift bits
-// above a 24-bit index, for the second level.
-__global__ __launch_bounds__(1024) void bucket_place_kernel(DevTables t, Batch b, const int32_t* hist,
+// Each chunk places its positions at start[key] + (earlier chunks' count) +
+// (rank inside the chunk, from an LDS counter).  With shift = 0 the entry is
+// the position; otherwise it carries the op's low shift bits above a 24-bit
+// position, for the second level.
+template <class K>
+__global__ __launch_bounds__(1024) void bucket_place_kernel(K keys, int n_ops, const int32_t* hist,
                                                            const int32_t* start, int32_t* perm, int shift) {
   extern __shared__ int32_t sh[];
-  const int n_ops = t.n_ops;
   const int n_keys = ((n_ops - 1) >> shift) + 1;
   for (int j = threadIdx.x; j < n_keys; j += blockDim.x) sh[j] = 0;
   __syncthreads();
   const int32_t* row = hist + (int64_t)blockIdx.x * n_keys;
+  const int64_t n = keys.size();
   const int64_t a = (int64_t)blockIdx.x * BUCKET_CHUNK;
-  const int64_t e = a + BUCKET_CHUNK < b.n ? a + BUCKET_CHUNK : b.n;
+  const int64_t e = a + BUCKET_CHUNK < n ? a + BUCKET_CHUNK : n;
   const uint32_t low = (1u << shift) - 1u;
   for (int64_t i = a + threadIdx.x; i < e; i += blockDim.x) {
-    const int v = b.op[i];
-    if (invalid_invocation(v, b.elapsed[i], b.slo[i], n_ops)) continue;
+    int v;
+    if (!keys.place_key(i, &v)) continue;
     const int k = v >> shift;
     const uint32_t entry = shift ? (((uint32_t)v & low) << 24) | (uint32_t)i : (uint32_t)i;
     perm[start[k] + row[k] + atomicAdd(&sh[k], 1)] = (int32_t)entry;
@@ -1210,6 +1240,13 @@ __global__ __launch_bounds__(1024) void bucket_place_kernel(DevTables t, Batch b
 // op come out in any order.
 constexpr int FINE_BITS = 8;
 constexpr int FINE_OPS = 1 << FINE_BITS;
+// Bucketing by op: few ops, one LDS-histogram counting sort; many ops, a
+// two-level one (groups of FINE_OPS ops, then the ops of each group) while the
+// groups fit one LDS histogram and a position fits 24 bits.
+inline bool two_level(int64_t n, int32_t n_ops) {
+  return n_ops > BUCKET_LDS_OPS && ((n_ops - 1) >> FINE_BITS) + 1 <= BUCKET_LDS_OPS && n <= (1 << 24);
+}
+inline int64_t round_words(int64_t w) { return (w + 63) & ~(int64_t)63; }
 __global__ __launch_bounds__(FINE_OPS) void bucket_fine_kernel(const int32_t* cstart, const int32_t* packed,
                                                                int n_ops, int32_t* start, int32_t* perm) {
   __shared__ int32_t cnt[FINE_OPS];
@@ -1450,9 +1487,12 @@ __device__ __forceinline__ uint32_t wave_min_u32_fused(uint32_t v) {
 // batch's cnt invocations in turn, reading each one's targets (tgv, one
 // invocation per lane) lane by lane, and folds the piece's minimum into the
 // invocation's lane of res.
-template <int NHW, int RS>
+// With MASK, configurations whose batch (batch_a[k], k = the key's low 16
+// bits) exceeds limit are never feasible either.
+template <int NHW, int RS, bool MASK = false>
 __device__ __forceinline__ void scan_cfg_piece(const DevTables& t, const int (&seg)[NHW + 1], int base,
-                                               const int32_t (&tgv)[NHW], int cnt, uint32_t& res) {
+                                               const int32_t (&tgv)[NHW], int cnt, uint32_t& res,
+                                               const int32_t* batch_a = nullptr, int32_t limit = 0) {
   const int lane = threadIdx.x & 63;
   uint32_t cL[NHW][RS], cK[NHW][RS];
 #pragma unroll
@@ -1460,7 +1500,8 @@ __device__ __forceinline__ void scan_cfg_piece(const DevTables& t, const int (&s
 #pragma unroll
     for (int u = 0; u < RS; ++u) {
       const int x = seg[h] + base + lane + 64 * u;
-      const uint2 q = x < seg[h + 1] ? t.tab[x] : make_uint2(0x7FFFFFFFu, KEY_NONE);
+      uint2 q = x < seg[h + 1] ? t.tab[x] : make_uint2(0x7FFFFFFFu, KEY_NONE);
+      if (MASK && q.y != KEY_NONE && batch_a[q.y & 0xFFFFu] > limit) q = make_uint2(0x7FFFFFFFu, KEY_NONE);
       cL[h][u] = q.x;
       cK[h][u] = q.y;
     }
@@ -2323,6 +2364,77 @@ __global__ __launch_bounds__(256) void batching_scan_kernel(DevTables t, Batch b
 }
 
 
+// The batch-limited scan grouped by op: one wavefront per op with queued
+// invocations (perm[start[v] .. start[v + 1]) are their sub-queue slots).
+// The op's configurations whose batch fits max(available, 1) are scanned
+// from registers in pieces as in the full scan, the others never feasible;
+// the fastest of them (L << 16 | k) is found once for the op.
+template <int NHW>
+__global__ __launch_bounds__(256) void batching_ops_kernel(DevTables t, Batch b, BatchingArgs ba,
+                                                           const int32_t* start, const int32_t* perm) {
+  const int lane = threadIdx.x & 63;
+  const int v = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+  if (v >= t.n_ops) return;
+  const int p0 = start[v], p1 = start[v + 1];
+  if (p0 == p1) return;
+  int seg[NHW + 1];
+#pragma unroll
+  for (int h = 0; h <= NHW; ++h) seg[h] = t.seg_off[(int64_t)v * NHW + h];
+  int longest = 0;
+#pragma unroll
+  for (int h = 0; h < NHW; ++h) longest = seg[h + 1] - seg[h] > longest ? seg[h + 1] - seg[h] : longest;
+  const int32_t* batch_a = t.cfg_batch + t.cfg_off[v];
+  const int32_t av = ba.available[v];
+  const int32_t limit = av > 1 ? av : 1;
+  uint64_t fR = ~0ull;
+  for (int x = seg[0] + lane; x < seg[NHW]; x += 64) {
+    const uint2 q = t.tab[x];
+    const uint32_t k = q.y & 0xFFFFu;
+    const uint64_t fk = ((uint64_t)q.x << 16) | k;
+    if (batch_a[k] <= limit && fk < fR) fR = fk;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t o = __shfl_xor(fR, off, 64);
+    fR = o < fR ? o : fR;
+  }
+  for (int pb = p0; pb < p1; pb += 64) {
+    const int p = pb + lane;
+    const bool live = p < p1;
+    const uint2 ent = live ? ba.queue[perm[p]] : make_uint2(0u, 0u);
+    const int64_t i = ent.x;
+    const int64_t r0 = live ? (int64_t)b.slo[i] - b.elapsed[i] : 0;
+    int32_t tgv[NHW];
+#pragma unroll
+    for (int h = 0; h < NHW; ++h) tgv[h] = backend_target<NHW>(t, b, v, r0, h);
+    uint32_t res = KEY_NONE;
+    const int cnt = p1 - pb < 64 ? p1 - pb : 64;
+    if (fR != ~0ull) {  // otherwise no configuration fits and every x* stands
+      for (int base = 0; base < longest; base += 64 * CFG_REG_SLOTS) {
+        const int rest = longest - base;
+        switch (rest <= 64 ? 1 : rest <= 128 ? 2 : rest <= 192 ? 3 : 4) {
+          case 1: scan_cfg_piece<NHW, 1, true>(t, seg, base, tgv, cnt, res, batch_a, limit); break;
+          case 2: scan_cfg_piece<NHW, 2, true>(t, seg, base, tgv, cnt, res, batch_a, limit); break;
+          case 3: scan_cfg_piece<NHW, 3, true>(t, seg, base, tgv, cnt, res, batch_a, limit); break;
+          default: scan_cfg_piece<NHW, 4, true>(t, seg, base, tgv, cnt, res, batch_a, limit); break;
+        }
+      }
+    }
+    if (live) {
+      int c = (int)(ent.y & 0xFFFFu);
+      uint8_t f = (uint8_t)(ent.y >> 16);
+      if (fR != ~0ull) {
+        const bool mr = res != KEY_NONE;
+        c = (int)((mr ? (uint64_t)res : fR) & 0xFFFFu);
+        f = mr ? 1 : 0;
+      }
+      b.cfg[i] = c;
+      if (b.flag) b.flag[i] = f;
+    }
+  }
+}
+
+
 // ---------------------------------------------------------------------------
 // Serving: persistent plain decisions.  Each wavefront claims up to r.chunk
 // published requests (lanes = requests), decides them from the records and
@@ -2449,9 +2561,42 @@ hipError_t launch_decide_batching(const DevTables& t, const Batch& b, const Batc
                      reinterpret_cast<int32_t*>(a.count), (int64_t)32 * BATCH_QUEUES);
   LLAMA_DISPATCH_NHW(batching_commit_kernel, dim3(blocks_for(b.n, BATCH_BLOCK)), dim3(BATCH_BLOCK), s, t, b, a, rec,
                      tail, tail2, ovf, cap);
+  const int64_t n_slots = (int64_t)BATCH_QUEUES * cap;
+  if (t.n_ops <= BUCKET_LDS_OPS || two_level(n_slots, t.n_ops)) {
+    // the queued invocations grouped by op (counting sort of the occupied
+    // slots), then one wavefront per op
+    const QueueKeys keys{b.op, a.queue, a.count, cap};
+    const int n_chunks = (int)((n_slots + BUCKET_CHUNK - 1) / BUCKET_CHUNK);
+    if (t.n_ops <= BUCKET_LDS_OPS) {
+      const size_t lds = sizeof(int32_t) * (size_t)t.n_ops;
+      hipLaunchKernelGGL(bucket_hist_kernel<QueueKeys>, dim3(n_chunks), dim3(1024), lds, s, keys, t.n_ops, a.hist, 0);
+      hipLaunchKernelGGL(bucket_columns_kernel, dim3(blocks_for(t.n_ops, 256)), dim3(256), 0, s, a.hist, n_chunks,
+                         t.n_ops, a.op_cnt);
+      hipLaunchKernelGGL(bucket_offsets_kernel, dim3(1), dim3(1024), 0, s, a.op_cnt, t.n_ops, a.op_start,
+                         (int32_t*)nullptr);
+      hipLaunchKernelGGL(bucket_place_kernel<QueueKeys>, dim3(n_chunks), dim3(1024), lds, s, keys, t.n_ops, a.hist,
+                         a.op_start, a.perm, 0);
+    } else {
+      const int n_groups = ((t.n_ops - 1) >> FINE_BITS) + 1;
+      const size_t lds = sizeof(int32_t) * (size_t)n_groups;
+      int32_t* packed = a.hist + round_words((int64_t)n_chunks * n_groups);
+      hipLaunchKernelGGL(bucket_hist_kernel<QueueKeys>, dim3(n_chunks), dim3(1024), lds, s, keys, t.n_ops, a.hist,
+                         FINE_BITS);
+      hipLaunchKernelGGL(bucket_columns_kernel, dim3(blocks_for(n_groups, 256)), dim3(256), 0, s, a.hist, n_chunks,
+                         n_groups, a.op_cnt);
+      hipLaunchKernelGGL(bucket_offsets_kernel, dim3(1), dim3(1024), 0, s, a.op_cnt, n_groups, a.op_cursor,
+                         (int32_t*)nullptr);
+      hipLaunchKernelGGL(bucket_place_kernel<QueueKeys>, dim3(n_chunks), dim3(1024), lds, s, keys, t.n_ops, a.hist,
+                         a.op_cursor, packed, FINE_BITS);
+      hipLaunchKernelGGL(bucket_fine_kernel, dim3(n_groups), dim3(FINE_OPS), 0, s, a.op_cursor, packed, t.n_ops,
+                         a.op_start, a.perm);
+    }
+    LLAMA_DISPATCH_NHW(batching_ops_kernel, dim3((unsigned)((t.n_ops + 3) / 4)), dim3(256), s, t, b, a, a.op_start,
+                       a.perm);
+    return hipGetLastError();
+  }
   // one wavefront per sub-queue slot; those past their sub-queue's count exit at once
-  LLAMA_DISPATCH_NHW(batching_scan_kernel, dim3(blocks_for((int64_t)BATCH_QUEUES * cap, 4)), dim3(256), s, t, b, a,
-                     cap);
+  LLAMA_DISPATCH_NHW(batching_scan_kernel, dim3(blocks_for(n_slots, 4)), dim3(256), s, t, b, a, cap);
   return hipGetLastError();
 }
 
@@ -2498,17 +2643,7 @@ hipError_t launch_clock_probe(const int* flag, int* ack, unsigned long long* sta
   return hipGetLastError();
 }
 
-// Bucketing by op: few ops, one LDS-histogram counting sort; many ops, a
-// two-level one (groups of FINE_OPS ops, then the ops of each group) while the
-// groups fit one LDS histogram and an index fits 24 bits; else global
-// atomics.
-namespace {
-bool two_level(int64_t n_inv, int32_t n_ops) {
-  return n_ops > BUCKET_LDS_OPS && ((n_ops - 1) >> FINE_BITS) + 1 <= BUCKET_LDS_OPS && n_inv <= (1 << 24);
-}
-int64_t round_words(int64_t w) { return (w + 63) & ~(int64_t)63; }
-}  // namespace
-
+// Few ops and two-level bucketing as two_level() tells; else global atomics.
 int64_t full_scan_hist_words(int64_t n_inv, int32_t n_ops) {
   const int64_t n_chunks = (n_inv + BUCKET_CHUNK - 1) / BUCKET_CHUNK;
   if (n_ops <= BUCKET_LDS_OPS) return n_chunks * (int64_t)n_ops;
@@ -2520,27 +2655,30 @@ int64_t full_scan_hist_words(int64_t n_inv, int32_t n_ops) {
 hipError_t launch_decide_full(const DevTables& t, const Batch& b, const FullScratch& w, hipStream_t s) {
   if (b.n == 0) return hipSuccess;
   const int n_chunks = (int)((b.n + BUCKET_CHUNK - 1) / BUCKET_CHUNK);
+  const InvocationKeys keys{t, b};
   if (t.n_ops <= BUCKET_LDS_OPS) {
     const size_t lds = sizeof(int32_t) * (size_t)t.n_ops;
-    hipLaunchKernelGGL(bucket_hist_kernel, dim3(n_chunks), dim3(1024), lds, s, t, b, w.hist, 0);
+    hipLaunchKernelGGL(bucket_hist_kernel<InvocationKeys>, dim3(n_chunks), dim3(1024), lds, s, keys, t.n_ops, w.hist, 0);
     hipLaunchKernelGGL(bucket_columns_kernel, dim3(blocks_for(t.n_ops, 256)), dim3(256), 0, s, w.hist,
                        n_chunks, t.n_ops, w.cnt);
     hipLaunchKernelGGL(bucket_offsets_kernel, dim3(1), dim3(1024), 0, s, w.cnt, t.n_ops, w.start,
                        (int32_t*)nullptr);
-    hipLaunchKernelGGL(bucket_place_kernel, dim3(n_chunks), dim3(1024), lds, s, t, b, w.hist, w.start, w.perm, 0);
+    hipLaunchKernelGGL(bucket_place_kernel<InvocationKeys>, dim3(n_chunks), dim3(1024), lds, s, keys, t.n_ops, w.hist,
+                       w.start, w.perm, 0);
   } else if (two_level(b.n, t.n_ops)) {
     // groups of FINE_OPS ops: counts in cnt, group starts in cursor (n_ops >
     // groups + 1 words), packed entries after the group histograms
     const int n_groups = ((t.n_ops - 1) >> FINE_BITS) + 1;
     const size_t lds = sizeof(int32_t) * (size_t)n_groups;
     int32_t* packed = w.hist + round_words((int64_t)n_chunks * n_groups);
-    hipLaunchKernelGGL(bucket_hist_kernel, dim3(n_chunks), dim3(1024), lds, s, t, b, w.hist, FINE_BITS);
+    hipLaunchKernelGGL(bucket_hist_kernel<InvocationKeys>, dim3(n_chunks), dim3(1024), lds, s, keys, t.n_ops, w.hist,
+                       FINE_BITS);
     hipLaunchKernelGGL(bucket_columns_kernel, dim3(blocks_for(n_groups, 256)), dim3(256), 0, s, w.hist,
                        n_chunks, n_groups, w.cnt);
     hipLaunchKernelGGL(bucket_offsets_kernel, dim3(1), dim3(1024), 0, s, w.cnt, n_groups, w.cursor,
                        (int32_t*)nullptr);
-    hipLaunchKernelGGL(bucket_place_kernel, dim3(n_chunks), dim3(1024), lds, s, t, b, w.hist, w.cursor, packed,
-                       FINE_BITS);
+    hipLaunchKernelGGL(bucket_place_kernel<InvocationKeys>, dim3(n_chunks), dim3(1024), lds, s, keys, t.n_ops, w.hist,
+                       w.cursor, packed, FINE_BITS);
     hipLaunchKernelGGL(bucket_fine_kernel, dim3(n_groups), dim3(FINE_OPS), 0, s, w.cursor, packed, t.n_ops,
                        w.start, w.perm);
   } else {

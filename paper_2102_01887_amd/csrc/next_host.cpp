@@ -345,7 +345,7 @@ int llama_decide_batching(llama_ctx* c, int64_t n, const int32_t* op, const int3
   hipStream_t s = (hipStream_t)stream;
   // scratch: sub-queue counters and the sub-queues (grows; not while the
   // stream is being captured)
-  const size_t need = llama::batch_scratch_bytes(n);
+  const size_t need = llama::batch_scratch_bytes(n, c->n_ops);
   if (need > c->d_batch_scratch.bytes) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (s && hipStreamIsCapturing(s, &cs) != hipSuccess)
@@ -359,9 +359,14 @@ int llama_decide_batching(llama_ctx* c, int64_t n, const int32_t* op, const int3
   llama::Batch b{};
   b.n = n; b.op = op; b.elapsed = elapsed; b.slo = slo; b.queue = queue; b.cfg = cfg; b.flag = flag; b.mode = mode;
   char* scratch = static_cast<char*>(c->d_batch_scratch.p);
+  const int64_t slots = (int64_t)llama::BATCH_QUEUES * llama::batch_queue_capacity(n);
+  int32_t* g = reinterpret_cast<int32_t*>(scratch + sizeof(uint32_t) * 32 * llama::BATCH_QUEUES +
+                                          sizeof(uint2) * (size_t)slots);
+  const int64_t ow = llama::batch_words64((int64_t)c->n_ops + 1);
   llama::BatchingArgs a{available, upstream, wait_us,
                         reinterpret_cast<uint2*>(scratch + sizeof(uint32_t) * 32 * llama::BATCH_QUEUES),
-                        reinterpret_cast<uint32_t*>(scratch)};
+                        reinterpret_cast<uint32_t*>(scratch),
+                        g, g + ow, g + 2 * ow, g + 3 * ow, g + 3 * ow + llama::batch_words64(slots)};
   hipError_t e = llama::launch_decide_batching(c->tables(), b, a, s);
   if (e != hipSuccess) return llama::hip_fail(c, e, "decide_batching launch");
   return LLAMA_OK;

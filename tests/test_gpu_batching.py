@@ -6,7 +6,7 @@ import pytest
 import oracle
 from paper_2102_01887_amd import binding as B
 from paper_2102_01887_amd import workloads as wl
-from test_gpu_parity import PAPER, PROB, Run, dev, say
+from test_gpu_parity import PAPER, PROB, Run, _torch, dev, say
 
 pytestmark = pytest.mark.gpu
 
@@ -54,6 +54,36 @@ def test_batching_c3_reduced():
     r = Run(w)
     rng = np.random.default_rng(3)
     case(r, *per_op(rng, w, 65, 65, 2_000_000), modes=(PAPER,))
+
+
+def test_batching_c3_many_ops():
+    # more ops than one LDS histogram holds: the queued invocations are
+    # grouped by op in two levels before the per-op scan
+    w = wl.make_c3(seed=75, n_pipelines=320, n_inv=30_000, max_cfg=512)
+    assert w.n_ops > 12288
+    r = Run(w)
+    rng = np.random.default_rng(5)
+    case(r, *per_op(rng, w, 65, 65, 2_000_000))
+    case(r, *per_op(rng, w, 8, 200, 500_000), Q=[10_000, 0, 100_000, 900_000], modes=(PAPER,))
+
+
+def test_batching_beyond_packed_slots():
+    # more sub-queue slots than a packed 24-bit position holds, over many ops:
+    # the batch-limited scan takes one wavefront per slot instead of grouping
+    # by op; the oracle checks a sample
+    torch = _torch()
+    w = wl.make_c3(seed=76, n_pipelines=320, n_inv=(1 << 24) + 4096, max_cfg=64)
+    L = B.Llama(0).load(w)
+    op, el, slo = dev(w.inv_op, torch), dev(w.elapsed, torch), dev(w.slo, torch)
+    rng = np.random.default_rng(6)
+    avail, up, wait = per_op(rng, w, 65, 65, 2_000_000)
+    idx = np.sort(np.random.default_rng(1).choice(w.n_inv, 50_000, replace=False))
+    idx[-1] = w.n_inv - 1
+    c_or, f_or = oracle.Problem(w).decide_batching(PAPER, avail, up, wait, sl=idx)
+    c, f = L.decide_batching(op, el, slo, dev(avail, torch), dev(up, torch), dev(wait, torch), None, PAPER)
+    torch.cuda.synchronize()
+    c, f = c.cpu().numpy(), f.cpu().numpy()
+    assert np.array_equal(c[idx], c_or) and np.array_equal(f[idx], f_or)
 
 
 def test_batching_fuzz_small_tables():
