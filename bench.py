@@ -400,13 +400,14 @@ def bench_next4(args, torch, B, wl, log, L, w, op, el, slo, mode):
     scanned = (w.batch[w.cfg_off[v_s] + xs_or] > avail[v_s]) & (c_or != B.CFG_WAIT)
     n_cfg_op = np.diff(w.cfg_off)
     pairs = int(round(n_cfg_op[v_s][scanned].sum() * n / len(v_s)))
-    ops = pairs * 5
+    ops = pairs * 3
     return {"ms": ms, "decisions_per_s": n / (ms * 1e-3),
-            "kernels": "batching_commit_kernel (records) + batching_scan_kernel (scans)",
+            "kernels": "batching_commit_kernel (records) + grouping by op (bucket_hist/place/fine over the "
+                       "sub-queue slots) + batching_ops_kernel (scans)",
             "wait_fraction": float(np.mean(c == B.CFG_WAIT)), "scan_fraction": float(scanned.mean()),
             "roofline": {"bound": "alu", "achieved": ops / (ms * 1e-3) / 1e9, "peak": 39321.6,
                          "unit": "Gop/s", "frac": ops / (ms * 1e-3) / 1e9 / 39321.6,
-                         "note": "5 lane-ops per scanned (invocation, configuration) pair; "
+                         "note": "3 lane-ops per scanned (invocation, configuration) pair (compare, select, min); "
                                  "scanned pairs estimated from the parity sample"},
             "bit_exact": exact, "parity_sample": f"decisions of the first {sample.stop} invocations"}
 
