@@ -240,12 +240,14 @@ def bench_next1(args, torch, B, wl, log, w, op, el, slo, mode):
     # the library merges each op's backends per call only when the call's
     # invocations pay for it (8 n_inv >= n_cfg): then per configuration the
     # merge reads its latency and two keys and writes the merged threshold
-    # and two minima; otherwise each invocation counts per backend (two-level
-    # count) and reads the backend's two key minima.  Per invocation 17 B.
+    # and two minima; otherwise the invocations are grouped by op, each op's
+    # latency runs are read once and each invocation reads one pair of key
+    # minima per backend.  Per invocation 17 B.
     merged = 8 * n >= wr.n_cfg
-    a_bytes = n * 17 + (wr.n_cfg * 24 if merged else n * wr.n_hw * 8)
+    a_bytes = n * 17 + (wr.n_cfg * 24 if merged else wr.n_cfg * 4 + n * wr.n_hw * 8)
     a_kernel = ("alpha_merge_kernel + alpha_queue_kernel" if merged else
-                "decide_alpha_kernel (per backend: block samples, then one block)")
+                "grouping by op (bucket_hist/place/fine) + decide_alpha_ops_kernel (per backend: the op's "
+                "latency runs in registers, counts by ballot)")
     log(f"bench: next1 queue_time {ms_q * 1e3:.2f} us, decide_alpha {ms_a * 1e3:.2f} us, exact {exact}")
     return {"alpha": [1, 1], "hw_res_total": wr.hw_res_total.tolist(), "queue_entries": n_q,
             "Q_us": Q_or.tolist(), "ms_per_chain": ms_c, "decisions_per_s": n / (ms_c * 1e-3),

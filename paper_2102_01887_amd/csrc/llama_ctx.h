@@ -207,6 +207,11 @@ int enter(llama_ctx* c);
 int sync_ctx(llama_ctx* c, const char* what);
 // finite-alpha tables (next_host.cpp); called by llama_set_alpha and after latency updates
 int build_alpha_tables(llama_ctx* c);
+}  // namespace llama
+// Grows the context's full-scan scratch (permutation and histograms) to n
+// invocations; refused while `stream` is being captured.
+int reserve_perm(llama_ctx* c, int64_t n, hipStream_t stream);
+namespace llama {
 // feedback (feedback_host.cpp): refresh the host copies of the latencies
 // after device-side feedback
 int pull_profiles(llama_ctx* c);

@@ -616,6 +616,16 @@ int build_tables(llama_ctx* c) {
   return sync_ctx(c, "set_profiles");
 }
 
+
+int check_batch(llama_ctx* c, int64_t n, const void* op, const char* fn) {
+  if (!c->has_prof) return fail(c, LLAMA_E_STATE, "%s: call llama_set_dag and llama_set_profiles first", fn);
+  if (n < 0) return fail(c, LLAMA_E_ARG, "%s: n_inv < 0", fn);
+  if (n > 0 && !op) return fail(c, LLAMA_E_ARG, "%s: null invocation pointer", fn);
+  return LLAMA_OK;
+}
+
+}  // namespace
+
 int reserve_perm(llama_ctx* c, int64_t n, hipStream_t stream) {
   if (n <= c->perm_cap) return LLAMA_OK;
   if (n > INT32_MAX) return fail(c, LLAMA_E_RANGE, "full scan: more than 2^31-1 invocations in one call");
@@ -637,15 +647,6 @@ int reserve_perm(llama_ctx* c, int64_t n, hipStream_t stream) {
   c->perm_cap = n;
   return LLAMA_OK;
 }
-
-int check_batch(llama_ctx* c, int64_t n, const void* op, const char* fn) {
-  if (!c->has_prof) return fail(c, LLAMA_E_STATE, "%s: call llama_set_dag and llama_set_profiles first", fn);
-  if (n < 0) return fail(c, LLAMA_E_ARG, "%s: n_inv < 0", fn);
-  if (n > 0 && !op) return fail(c, LLAMA_E_ARG, "%s: null invocation pointer", fn);
-  return LLAMA_OK;
-}
-
-}  // namespace
 
 extern "C" {
 

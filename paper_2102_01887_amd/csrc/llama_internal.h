@@ -222,7 +222,11 @@ struct ResTotals {
 };
 hipError_t launch_queue_time(const DevTables& t, int64_t n, const int32_t* q_op, const int32_t* q_cfg,
                              unsigned long long* part, const ResTotals& rt, int64_t* out, hipStream_t s);
-hipError_t launch_decide_alpha(const DevTables& t, const Batch& b, hipStream_t s);
+// With queueing times and scratch w (FullScratch of b.n invocations) the
+// invocations are first grouped by op when a counting sort applies
+// (decide_alpha_ops_kernel); otherwise, or with w null, one thread per
+// invocation.
+hipError_t launch_decide_alpha(const DevTables& t, const Batch& b, const FullScratch* w, hipStream_t s);
 // Eq. 3: affinities [n x n_hw] and, if order != nullptr, per backend the
 // invocations by decreasing affinity (stable), using scratch of
 // n * (8 n_hw + 8 + 4) bytes plus the sort's temporary storage.

@@ -1919,6 +1919,100 @@ __global__ __launch_bounds__(256) void decide_alpha_kernel(DevTables t, Batch b)
   if (b.flag) b.flag[i] = meets;
 }
 
+// Finite-alpha Eq. 1 with queueing times, grouped by op: one wavefront per op
+// with invocations (perm[start[v] .. start[v + 1])).  Each backend's latency
+// run is held in registers in pieces of up to CFG_REG_SLOTS slots of 64
+// (padded with INT32_MAX); each invocation's count of entries below its
+// target is the population count of the wavefront's compares, invocation by
+// invocation with the targets read lane by lane, and each lane then reads its
+// invocation's pair of key minima at that count.
+template <int R, int RS>
+__device__ __forceinline__ void alpha_count_piece(const int32_t* lat, const int (&lo)[R], const int (&hi)[R],
+                                                  int base, const int32_t (&tgv)[R], int cnt, int (&cntv)[R]) {
+  const int lane = threadIdx.x & 63;
+  int32_t L[R][RS];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int u = 0; u < RS; ++u) {
+      const int x = lo[r] + base + lane + 64 * u;
+      L[r][u] = x < hi[r] ? lat[x] : INT32_MAX;
+    }
+  for (int j = 0; j < cnt; ++j) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int32_t tg = __builtin_amdgcn_readlane(tgv[r], j);
+      int c = 0;
+#pragma unroll
+      for (int u = 0; u < RS; ++u) c += __popcll(__builtin_amdgcn_ballot_w64(L[r][u] < tg));
+      cntv[r] += lane == j ? c : 0;
+    }
+  }
+}
+
+template <int NHW>
+__global__ __launch_bounds__(256) void decide_alpha_ops_kernel(DevTables t, Batch b, const int32_t* start,
+                                                               const int32_t* perm) {
+  const int lane = threadIdx.x & 63;
+  const int v = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+  if (v >= t.n_ops) return;
+  const int p0 = start[v], p1 = start[v + 1];
+  if (p0 == p1) return;
+  int lo[NHW], hi[NHW];
+  int longest = 0;
+#pragma unroll
+  for (int h = 0; h < NHW; ++h) {
+    lo[h] = t.seg_off[(int64_t)v * NHW + h];
+    hi[h] = t.seg_off[(int64_t)v * NHW + h + 1];
+    longest = hi[h] - lo[h] > longest ? hi[h] - lo[h] : longest;
+  }
+  const int64_t ref = t.ref[v];
+  const int64_t W = t.W[(int64_t)b.mode * t.n_ops + v];
+  for (int pb = p0; pb < p1; pb += 64) {
+    const int p = pb + lane;
+    const bool live = p < p1;
+    const int64_t i = live ? perm[p] : 0;
+    const int64_t r0 = live ? (int64_t)b.slo[i] - b.elapsed[i] : 0;
+    int32_t tgv[NHW];
+    int cntv[NHW];
+#pragma unroll
+    for (int h = 0; h < NHW; ++h) {
+      const int64_t R = remaining_time(r0, b.queue[h]);
+      tgv[h] = R == 0 ? 0 : (int32_t)div_floor_pos(ref * R, W);
+      cntv[h] = 0;
+    }
+    const int cnt = p1 - pb < 64 ? p1 - pb : 64;
+    for (int base = 0; base < longest; base += 64 * CFG_REG_SLOTS) {
+      const int rest = longest - base;
+      switch (rest <= 64 ? 1 : rest <= 128 ? 2 : rest <= 192 ? 3 : 4) {
+        case 1: alpha_count_piece<NHW, 1>(t.a_lat, lo, hi, base, tgv, cnt, cntv); break;
+        case 2: alpha_count_piece<NHW, 2>(t.a_lat, lo, hi, base, tgv, cnt, cntv); break;
+        case 3: alpha_count_piece<NHW, 3>(t.a_lat, lo, hi, base, tgv, cnt, cntv); break;
+        default: alpha_count_piece<NHW, 4>(t.a_lat, lo, hi, base, tgv, cnt, cntv); break;
+      }
+    }
+    if (!live) continue;
+    uint2 ps[NHW];
+#pragma unroll
+    for (int h = 0; h < NHW; ++h) ps[h] = t.a_ps[(int64_t)lo[h] + cntv[h] + (int64_t)v * NHW + h];
+    uint32_t best = KEY_NONE;
+    uint8_t meets = 0;
+#pragma unroll
+    for (int h = 0; h < NHW; ++h) {
+      if (ps[h].x < best) {
+        best = ps[h].x;
+        meets = 1;
+      }
+      if (ps[h].y < best) {
+        best = ps[h].y;
+        meets = 0;
+      }
+    }
+    b.cfg[i] = (int)(best & 0xFFFFu);
+    if (b.flag) b.flag[i] = meets;
+  }
+}
+
 // Without queueing times every backend's target is the same, so one search
 // over the op's configurations of all backends (latency order) suffices.
 __global__ __launch_bounds__(256) void decide_alpha_merged_kernel(DevTables t, Batch b) {
@@ -2541,6 +2635,40 @@ hipError_t launch_feedback(const DevTables& t, const FeedbackArgs& f, int64_t n,
   return hipGetLastError();
 }
 
+// Counting sort of positions 0 .. n - 1 of `keys` by op into perm, with
+// start[v] .. start[v + 1] the positions of op v: one LDS-histogram pass for
+// few ops, two levels for many (two_level).  cnt and cursor are scratch of
+// n_ops + 1 words, hist of full_scan_hist_words(n, n_ops).  Returns false,
+// launching nothing, when neither applies.
+template <class K>
+bool launch_counting_sort(const K& keys, int64_t n, int n_ops, int32_t* cnt, int32_t* start, int32_t* cursor,
+                          int32_t* perm, int32_t* hist, hipStream_t s) {
+  const int n_chunks = (int)((n + BUCKET_CHUNK - 1) / BUCKET_CHUNK);
+  if (n_ops <= BUCKET_LDS_OPS) {
+    const size_t lds = sizeof(int32_t) * (size_t)n_ops;
+    hipLaunchKernelGGL(bucket_hist_kernel<K>, dim3(n_chunks), dim3(1024), lds, s, keys, n_ops, hist, 0);
+    hipLaunchKernelGGL(bucket_columns_kernel, dim3(blocks_for(n_ops, 256)), dim3(256), 0, s, hist, n_chunks, n_ops,
+                       cnt);
+    hipLaunchKernelGGL(bucket_offsets_kernel, dim3(1), dim3(1024), 0, s, cnt, n_ops, start, (int32_t*)nullptr);
+    hipLaunchKernelGGL(bucket_place_kernel<K>, dim3(n_chunks), dim3(1024), lds, s, keys, n_ops, hist, start, perm, 0);
+    return true;
+  }
+  if (!two_level(n, n_ops)) return false;
+  // groups of FINE_OPS ops: counts in cnt, group starts in cursor (n_ops >
+  // groups + 1 words), packed entries after the group histograms
+  const int n_groups = ((n_ops - 1) >> FINE_BITS) + 1;
+  const size_t lds = sizeof(int32_t) * (size_t)n_groups;
+  int32_t* packed = hist + round_words((int64_t)n_chunks * n_groups);
+  hipLaunchKernelGGL(bucket_hist_kernel<K>, dim3(n_chunks), dim3(1024), lds, s, keys, n_ops, hist, FINE_BITS);
+  hipLaunchKernelGGL(bucket_columns_kernel, dim3(blocks_for(n_groups, 256)), dim3(256), 0, s, hist, n_chunks,
+                     n_groups, cnt);
+  hipLaunchKernelGGL(bucket_offsets_kernel, dim3(1), dim3(1024), 0, s, cnt, n_groups, cursor, (int32_t*)nullptr);
+  hipLaunchKernelGGL(bucket_place_kernel<K>, dim3(n_chunks), dim3(1024), lds, s, keys, n_ops, hist, cursor, packed,
+                     FINE_BITS);
+  hipLaunchKernelGGL(bucket_fine_kernel, dim3(n_groups), dim3(FINE_OPS), 0, s, cursor, packed, n_ops, start, perm);
+  return true;
+}
+
 hipError_t launch_decide_batching(const DevTables& t, const Batch& b, const BatchingArgs& a, hipStream_t s) {
   if (b.n == 0) return hipSuccess;
   const uint4* rec = t.rec + (int64_t)b.mode * t.n_ops;
@@ -2562,35 +2690,10 @@ hipError_t launch_decide_batching(const DevTables& t, const Batch& b, const Batc
   LLAMA_DISPATCH_NHW(batching_commit_kernel, dim3(blocks_for(b.n, BATCH_BLOCK)), dim3(BATCH_BLOCK), s, t, b, a, rec,
                      tail, tail2, ovf, cap);
   const int64_t n_slots = (int64_t)BATCH_QUEUES * cap;
-  if (t.n_ops <= BUCKET_LDS_OPS || two_level(n_slots, t.n_ops)) {
-    // the queued invocations grouped by op (counting sort of the occupied
-    // slots), then one wavefront per op
-    const QueueKeys keys{b.op, a.queue, a.count, cap};
-    const int n_chunks = (int)((n_slots + BUCKET_CHUNK - 1) / BUCKET_CHUNK);
-    if (t.n_ops <= BUCKET_LDS_OPS) {
-      const size_t lds = sizeof(int32_t) * (size_t)t.n_ops;
-      hipLaunchKernelGGL(bucket_hist_kernel<QueueKeys>, dim3(n_chunks), dim3(1024), lds, s, keys, t.n_ops, a.hist, 0);
-      hipLaunchKernelGGL(bucket_columns_kernel, dim3(blocks_for(t.n_ops, 256)), dim3(256), 0, s, a.hist, n_chunks,
-                         t.n_ops, a.op_cnt);
-      hipLaunchKernelGGL(bucket_offsets_kernel, dim3(1), dim3(1024), 0, s, a.op_cnt, t.n_ops, a.op_start,
-                         (int32_t*)nullptr);
-      hipLaunchKernelGGL(bucket_place_kernel<QueueKeys>, dim3(n_chunks), dim3(1024), lds, s, keys, t.n_ops, a.hist,
-                         a.op_start, a.perm, 0);
-    } else {
-      const int n_groups = ((t.n_ops - 1) >> FINE_BITS) + 1;
-      const size_t lds = sizeof(int32_t) * (size_t)n_groups;
-      int32_t* packed = a.hist + round_words((int64_t)n_chunks * n_groups);
-      hipLaunchKernelGGL(bucket_hist_kernel<QueueKeys>, dim3(n_chunks), dim3(1024), lds, s, keys, t.n_ops, a.hist,
-                         FINE_BITS);
-      hipLaunchKernelGGL(bucket_columns_kernel, dim3(blocks_for(n_groups, 256)), dim3(256), 0, s, a.hist, n_chunks,
-                         n_groups, a.op_cnt);
-      hipLaunchKernelGGL(bucket_offsets_kernel, dim3(1), dim3(1024), 0, s, a.op_cnt, n_groups, a.op_cursor,
-                         (int32_t*)nullptr);
-      hipLaunchKernelGGL(bucket_place_kernel<QueueKeys>, dim3(n_chunks), dim3(1024), lds, s, keys, t.n_ops, a.hist,
-                         a.op_cursor, packed, FINE_BITS);
-      hipLaunchKernelGGL(bucket_fine_kernel, dim3(n_groups), dim3(FINE_OPS), 0, s, a.op_cursor, packed, t.n_ops,
-                         a.op_start, a.perm);
-    }
+  // the queued invocations grouped by op (counting sort of the occupied
+  // slots), then one wavefront per op
+  if (launch_counting_sort(QueueKeys{b.op, a.queue, a.count, cap}, n_slots, t.n_ops, a.op_cnt, a.op_start,
+                           a.op_cursor, a.perm, a.hist, s)) {
     LLAMA_DISPATCH_NHW(batching_ops_kernel, dim3((unsigned)((t.n_ops + 3) / 4)), dim3(256), s, t, b, a, a.op_start,
                        a.perm);
     return hipGetLastError();
@@ -2620,8 +2723,18 @@ hipError_t launch_affinity(const DevTables& t, const Batch& b, double* aff, int3
   return hipGetLastError();
 }
 
-hipError_t launch_decide_alpha(const DevTables& t, const Batch& b, hipStream_t s) {
+hipError_t launch_decide_alpha(const DevTables& t, const Batch& b, const FullScratch* w, hipStream_t s) {
   if (b.n == 0) return hipSuccess;
+  // grouped by op only with queueing times: without them one binary search
+  // per invocation over the op's merged run is as fast (0.60 against
+  // 0.62 ms with grouping on 4 M invocations over 81 M configurations), the
+  // run's upper levels being shared in L2 by the op's invocations
+  if (b.queue && w &&
+      launch_counting_sort(InvocationKeys{t, b}, b.n, t.n_ops, w->cnt, w->start, w->cursor, w->perm, w->hist, s)) {
+    LLAMA_DISPATCH_NHW(decide_alpha_ops_kernel, dim3((unsigned)((t.n_ops + 3) / 4)), dim3(256), s, t, b, w->start,
+                       w->perm);
+    return hipGetLastError();
+  }
   if (b.queue) {
     LLAMA_DISPATCH_NHW(decide_alpha_kernel, dim3(blocks_for(b.n, 256)), dim3(256), s, t, b);
   } else {
@@ -2654,34 +2767,7 @@ int64_t full_scan_hist_words(int64_t n_inv, int32_t n_ops) {
 
 hipError_t launch_decide_full(const DevTables& t, const Batch& b, const FullScratch& w, hipStream_t s) {
   if (b.n == 0) return hipSuccess;
-  const int n_chunks = (int)((b.n + BUCKET_CHUNK - 1) / BUCKET_CHUNK);
-  const InvocationKeys keys{t, b};
-  if (t.n_ops <= BUCKET_LDS_OPS) {
-    const size_t lds = sizeof(int32_t) * (size_t)t.n_ops;
-    hipLaunchKernelGGL(bucket_hist_kernel<InvocationKeys>, dim3(n_chunks), dim3(1024), lds, s, keys, t.n_ops, w.hist, 0);
-    hipLaunchKernelGGL(bucket_columns_kernel, dim3(blocks_for(t.n_ops, 256)), dim3(256), 0, s, w.hist,
-                       n_chunks, t.n_ops, w.cnt);
-    hipLaunchKernelGGL(bucket_offsets_kernel, dim3(1), dim3(1024), 0, s, w.cnt, t.n_ops, w.start,
-                       (int32_t*)nullptr);
-    hipLaunchKernelGGL(bucket_place_kernel<InvocationKeys>, dim3(n_chunks), dim3(1024), lds, s, keys, t.n_ops, w.hist,
-                       w.start, w.perm, 0);
-  } else if (two_level(b.n, t.n_ops)) {
-    // groups of FINE_OPS ops: counts in cnt, group starts in cursor (n_ops >
-    // groups + 1 words), packed entries after the group histograms
-    const int n_groups = ((t.n_ops - 1) >> FINE_BITS) + 1;
-    const size_t lds = sizeof(int32_t) * (size_t)n_groups;
-    int32_t* packed = w.hist + round_words((int64_t)n_chunks * n_groups);
-    hipLaunchKernelGGL(bucket_hist_kernel<InvocationKeys>, dim3(n_chunks), dim3(1024), lds, s, keys, t.n_ops, w.hist,
-                       FINE_BITS);
-    hipLaunchKernelGGL(bucket_columns_kernel, dim3(blocks_for(n_groups, 256)), dim3(256), 0, s, w.hist,
-                       n_chunks, n_groups, w.cnt);
-    hipLaunchKernelGGL(bucket_offsets_kernel, dim3(1), dim3(1024), 0, s, w.cnt, n_groups, w.cursor,
-                       (int32_t*)nullptr);
-    hipLaunchKernelGGL(bucket_place_kernel<InvocationKeys>, dim3(n_chunks), dim3(1024), lds, s, keys, t.n_ops, w.hist,
-                       w.cursor, packed, FINE_BITS);
-    hipLaunchKernelGGL(bucket_fine_kernel, dim3(n_groups), dim3(FINE_OPS), 0, s, w.cursor, packed, t.n_ops,
-                       w.start, w.perm);
-  } else {
+  if (!launch_counting_sort(InvocationKeys{t, b}, b.n, t.n_ops, w.cnt, w.start, w.cursor, w.perm, w.hist, s)) {
     const unsigned g = blocks_for(b.n, 256);
     hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks_for(t.n_ops + 1, 256)), dim3(256), 0, s, w.cnt,
                        (int64_t)t.n_ops + 1);

@@ -320,9 +320,22 @@ int llama_decide_alpha(llama_ctx* c, int64_t n, const int32_t* op, const int32_t
   // with queueing times, one search per invocation in the op's per-call
   // merged order when every op fits the merge and the merge pays; else one
   // search per backend
-  hipError_t e = queue && c->alpha_max_op <= llama::ALPHA_MERGE_MAX && c->d_aq_T.p && merge_pays(c, n)
-                     ? llama::launch_decide_alpha_queue(c->tables(), b, (hipStream_t)stream)
-                     : llama::launch_decide_alpha(c->tables(), b, (hipStream_t)stream);
+  hipError_t e;
+  if (queue && c->alpha_max_op <= llama::ALPHA_MERGE_MAX && c->d_aq_T.p && merge_pays(c, n)) {
+    e = llama::launch_decide_alpha_queue(c->tables(), b, (hipStream_t)stream);
+  } else {
+    // with queueing times, grouped by op in the full scan's scratch when it
+    // holds n invocations (grown here, except while the stream is being
+    // captured)
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    const bool capturing = stream && hipStreamIsCapturing((hipStream_t)stream, &cs) == hipSuccess &&
+                           cs != hipStreamCaptureStatusNone;
+    const bool grouped = queue && n > 0 &&
+                         (n <= c->perm_cap || (!capturing && reserve_perm(c, n, (hipStream_t)stream) == LLAMA_OK));
+    llama::FullScratch w{c->d_cnt.as<int32_t>(), c->d_start.as<int32_t>(), c->d_cursor.as<int32_t>(),
+                         c->d_perm.as<int32_t>(), c->d_hist.as<int32_t>()};
+    e = llama::launch_decide_alpha(c->tables(), b, grouped ? &w : nullptr, (hipStream_t)stream);
+  }
   if (e != hipSuccess) return llama::hip_fail(c, e, "decide_alpha launch");
   return LLAMA_OK;
 }

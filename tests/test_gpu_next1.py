@@ -7,7 +7,7 @@ import pytest
 import oracle
 from paper_2102_01887_amd import binding as B
 from paper_2102_01887_amd import workloads as wl
-from test_gpu_parity import PAPER, PROB, Run, dev, say
+from test_gpu_parity import PAPER, PROB, Run, _torch, dev, say
 
 pytestmark = pytest.mark.gpu
 
@@ -113,6 +113,47 @@ def test_alpha_c3_reduced():
     w = wl.with_resource_totals(wl.make_c3(seed=44, n_pipelines=30, n_inv=30_000))
     r = Run(w)
     alpha_parity(r, modes=(PAPER,), alphas=((1, 1), (3, 2)))
+
+
+def test_alpha_c3_many_ops_grouped():
+    # more ops than one LDS histogram holds and far more configurations than
+    # invocations: with queueing times the per-backend counts (no per-call
+    # merge) after grouping the invocations by op in two levels; without,
+    # one search per invocation in the op's merged run
+    w = wl.with_resource_totals(wl.make_c3(seed=47, n_pipelines=320, n_inv=20_000, max_cfg=2048))
+    assert w.n_ops > 12288 and 8 * w.n_inv < w.n_cfg
+    r = Run(w)
+    alpha_parity(r, modes=(PAPER,), alphas=((1, 1), (3, 2)))
+    alpha_parity(r, Q=[30_000, 0, 200_000, 5_000_000], alphas=((1, 1),))
+
+
+def test_alpha_captured_before_any_scratch():
+    # captured into a graph on a fresh context, before any call has grown the
+    # scratch that grouping by op needs: with queueing times one thread per
+    # invocation instead (no allocation under capture), and the merged search
+    # without; every replay checked
+    torch = _torch()
+    w = wl.with_resource_totals(wl.make_c3(seed=49, n_pipelines=40, n_inv=2000, max_cfg=512))
+    assert 8 * w.n_inv < w.n_cfg
+    r = Run(w)
+    r.L.set_alpha(1, 1)
+    n = w.n_inv
+    s = torch.cuda.Stream()
+    for Q in (None, [30_000, 0, 200_000, 5_000_000]):
+        q = None if Q is None else dev(np.asarray(Q, np.int64), torch)
+        cfg = torch.empty(n, dtype=torch.int32, device="cuda")
+        flag = torch.empty(n, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            r.L.decide_alpha(r.op, r.el, r.slo, q, PAPER, cfg=cfg, flag=flag, stream=s)
+        c_or, f_or = r.P.decide_alpha(PAPER, 1, 1, Q=Q)
+        for _ in range(2):
+            cfg.fill_(-7)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert np.array_equal(cfg.cpu().numpy(), c_or) and np.array_equal(flag.cpu().numpy(), f_or), Q
 
 
 def test_alpha_fuzz_small_tables():
