@@ -359,7 +359,7 @@ def bench_next3(args, torch, B, wl, log, w, op, el, slo, mode):
     log(f"bench: next3 affinity {ms_a * 1e3:.1f} us, with commit order {ms_o * 1e3:.1f} us, within 1e-15 {ok}")
     return {"alpha": [1, 1], "ms_affinity": ms_a, "ms_affinity_and_order": ms_o,
             "invocations_per_s": n / (ms_o * 1e-3),
-            "kernel": "affinity_queue_kernel (one search in the merged latency order)",
+            "kernel": "grouping by op (bucket_hist/place/fine) + affinity_ops_kernel (per backend: the op's latency runs in registers, counts by ballot)",
             "order": "per backend, stable radix sort of the complemented affinity bits",
             "within_tolerance": ok, "max_rel_error": float(rel.max()) if rel.size else 0.0,
             "order_non_increasing": ordered,

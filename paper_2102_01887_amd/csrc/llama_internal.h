@@ -229,9 +229,12 @@ hipError_t launch_queue_time(const DevTables& t, int64_t n, const int32_t* q_op,
 hipError_t launch_decide_alpha(const DevTables& t, const Batch& b, const FullScratch* w, hipStream_t s);
 // Eq. 3: affinities [n x n_hw] and, if order != nullptr, per backend the
 // invocations by decreasing affinity (stable), using scratch of
-// n * (8 n_hw + 8 + 4) bytes plus the sort's temporary storage.
+// n * (8 n_hw + 8 + 4) bytes plus the sort's temporary storage.  With w
+// (FullScratch of b.n invocations) the invocations are first grouped by op
+// when a counting sort applies (affinity_ops_kernel); otherwise one thread
+// per invocation with a search per backend.
 hipError_t launch_affinity(const DevTables& t, const Batch& b, double* aff, int32_t* order, void* scratch,
-                           size_t scratch_bytes, hipStream_t s);
+                           size_t scratch_bytes, const FullScratch* w, hipStream_t s);
 // Safe delayed batching: per op, invocations available now, expected from
 // upstream, and the estimated wait for them; cfg CFG_WAIT means wait.
 constexpr int CFG_WAIT = -2;

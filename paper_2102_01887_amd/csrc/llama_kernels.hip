@@ -1161,6 +1161,29 @@ struct QueueKeys {  // occupied slots of the batching sub-queues, by their invoc
   __device__ bool count_key(int64_t w, int* v) const { return place_key(w, v); }
 };
 
+struct AffinityKeys {  // the batch's invocations by op; invalid ones get zero affinities
+  DevTables t;
+  Batch b;
+  double* aff;
+  uint64_t* keys;
+  int32_t* iota;
+  __device__ int64_t size() const { return b.n; }
+  __device__ bool place_key(int64_t i, int* v) const {
+    *v = b.op[i];
+    return !invalid_invocation(*v, b.elapsed[i], b.slo[i], t.n_ops);
+  }
+  __device__ bool count_key(int64_t i, int* v) const {
+    if (iota) iota[i] = (int32_t)i;
+    if (place_key(i, v)) return true;
+    atomicOr(t.err, 1u);
+    for (int h = 0; h < t.n_hw; ++h) {
+      aff[i * t.n_hw + h] = 0.0;
+      if (keys) keys[(int64_t)h * b.n + i] = ~0ull;  // complemented bits of 0.0
+    }
+    return false;
+  }
+};
+
 // Each workgroup counts its chunk of BUCKET_CHUNK positions in an LDS
 // histogram over the keys op >> shift and writes it as one row of
 // hist[chunk][key]: the ops themselves with shift = 0 (few ops), groups of
@@ -1919,13 +1942,55 @@ __global__ __launch_bounds__(256) void decide_alpha_kernel(DevTables t, Batch b)
   if (b.flag) b.flag[i] = meets;
 }
 
-// Finite-alpha Eq. 1 with queueing times, grouped by op: one wavefront per op
-// with invocations (perm[start[v] .. start[v + 1])).  Each backend's latency
-// run is held in registers in pieces of up to CFG_REG_SLOTS slots of 64
-// (padded with INT32_MAX); each invocation's count of entries below its
-// target is the population count of the wavefront's compares, invocation by
-// invocation with the targets read lane by lane, and each lane then reads its
-// invocation's pair of key minima at that count.
+// Eq. 3 from each backend's best key: the ratio of the objective values of
+// the best key elsewhere and the best key on the backend (no configuration
+// on the backend -> 0; none elsewhere -> infinity; a zero own value ->
+// infinity, or 1 when the other is zero too).
+template <int NHW>
+__device__ __forceinline__ void affinities_from_best(const DevTables& t, int v, const uint32_t (&best)[NHW],
+                                                     double (&out)[NHW]) {
+  const double* val = t.a_val + 2 * (int64_t)t.cfg_off[v];
+#pragma unroll
+  for (int h = 0; h < NHW; ++h) {
+    uint32_t oth = KEY_NONE;
+#pragma unroll
+    for (int g = 0; g < NHW; ++g)
+      if (g != h && best[g] < oth) oth = best[g];
+    double a;
+    if (best[h] == KEY_NONE) {
+      a = 0.0;
+    } else if (oth == KEY_NONE) {
+      a = __builtin_huge_val();
+    } else {
+      const double vo = val[best[h] >> 16], vt = val[oth >> 16];
+      a = vo == 0.0 ? (vt == 0.0 ? 1.0 : __builtin_huge_val()) : vt / vo;
+    }
+    out[h] = a;
+  }
+}
+
+// An invocation's affinities, and with keys the commit order's sort keys:
+// non-negative doubles order like their bit patterns; complemented, an
+// ascending sort gives decreasing affinity.
+template <int NHW>
+__device__ __forceinline__ void store_affinities(const Batch& b, int64_t i, const double (&out)[NHW], double* aff,
+                                                 uint64_t* keys) {
+  double* dst = aff + i * NHW;
+#pragma unroll
+  for (int h = 0; h < NHW; ++h) {
+    dst[h] = out[h];
+    if (keys) keys[(int64_t)h * b.n + i] = ~(uint64_t)__double_as_longlong(out[h]);
+  }
+}
+
+// Finite-alpha Eq. 1 (with queueing times) and Eq. 3 (with or without),
+// grouped by op: one wavefront per op with invocations (perm[start[v] ..
+// start[v + 1])).  Each backend's latency run is held in registers in pieces
+// of up to CFG_REG_SLOTS slots of 64 (padded with INT32_MAX); each
+// invocation's count of entries below its target is the population count of
+// the wavefront's compares, invocation by invocation with the targets read
+// lane by lane, and each lane then reads its invocation's pair of key minima
+// at that count: the decision, or with AFF the affinities.
 template <int R, int RS>
 __device__ __forceinline__ void alpha_count_piece(const int32_t* lat, const int (&lo)[R], const int (&hi)[R],
                                                   int base, const int32_t (&tgv)[R], int cnt, int (&cntv)[R]) {
@@ -1950,9 +2015,9 @@ __device__ __forceinline__ void alpha_count_piece(const int32_t* lat, const int 
   }
 }
 
-template <int NHW>
-__global__ __launch_bounds__(256) void decide_alpha_ops_kernel(DevTables t, Batch b, const int32_t* start,
-                                                               const int32_t* perm) {
+template <int NHW, bool AFF>
+__device__ __forceinline__ void alpha_ops(const DevTables& t, const Batch& b, const int32_t* start,
+                                          const int32_t* perm, double* aff, uint64_t* keys) {
   const int lane = threadIdx.x & 63;
   const int v = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
   if (v >= t.n_ops) return;
@@ -1977,7 +2042,7 @@ __global__ __launch_bounds__(256) void decide_alpha_ops_kernel(DevTables t, Batc
     int cntv[NHW];
 #pragma unroll
     for (int h = 0; h < NHW; ++h) {
-      const int64_t R = remaining_time(r0, b.queue[h]);
+      const int64_t R = remaining_time(r0, b.queue ? b.queue[h] : 0);
       tgv[h] = R == 0 ? 0 : (int32_t)div_floor_pos(ref * R, W);
       cntv[h] = 0;
     }
@@ -1995,6 +2060,15 @@ __global__ __launch_bounds__(256) void decide_alpha_ops_kernel(DevTables t, Batc
     uint2 ps[NHW];
 #pragma unroll
     for (int h = 0; h < NHW; ++h) ps[h] = t.a_ps[(int64_t)lo[h] + cntv[h] + (int64_t)v * NHW + h];
+    if (AFF) {
+      uint32_t best[NHW];
+      double out[NHW];
+#pragma unroll
+      for (int h = 0; h < NHW; ++h) best[h] = ps[h].y < ps[h].x ? ps[h].y : ps[h].x;
+      affinities_from_best<NHW>(t, v, best, out);
+      store_affinities<NHW>(b, i, out, aff, keys);
+      continue;
+    }
     uint32_t best = KEY_NONE;
     uint8_t meets = 0;
 #pragma unroll
@@ -2011,6 +2085,18 @@ __global__ __launch_bounds__(256) void decide_alpha_ops_kernel(DevTables t, Batc
     b.cfg[i] = (int)(best & 0xFFFFu);
     if (b.flag) b.flag[i] = meets;
   }
+}
+
+template <int NHW>
+__global__ __launch_bounds__(256) void decide_alpha_ops_kernel(DevTables t, Batch b, const int32_t* start,
+                                                               const int32_t* perm) {
+  alpha_ops<NHW, false>(t, b, start, perm, nullptr, nullptr);
+}
+
+template <int NHW>
+__global__ __launch_bounds__(256) void affinity_ops_kernel(DevTables t, Batch b, const int32_t* start,
+                                                           const int32_t* perm, double* aff, uint64_t* keys) {
+  alpha_ops<NHW, true>(t, b, start, perm, aff, keys);
 }
 
 // Without queueing times every backend's target is the same, so one search
@@ -2284,33 +2370,9 @@ __global__ __launch_bounds__(256) void affinity_kernel(DevTables t, Batch b, dou
       const uint2 ps = t.a_ps[(int64_t)base[h] + (int64_t)v * NHW + h];
       best[h] = ps.y < ps.x ? ps.y : ps.x;
     }
-    const double* val = t.a_val + 2 * (int64_t)t.cfg_off[v];
-#pragma unroll
-    for (int h = 0; h < NHW; ++h) {
-      uint32_t oth = KEY_NONE;
-#pragma unroll
-      for (int g = 0; g < NHW; ++g)
-        if (g != h && best[g] < oth) oth = best[g];
-      double a;
-      if (best[h] == KEY_NONE) {
-        a = 0.0;
-      } else if (oth == KEY_NONE) {
-        a = __builtin_huge_val();
-      } else {
-        const double vo = val[best[h] >> 16], vt = val[oth >> 16];
-        a = vo == 0.0 ? (vt == 0.0 ? 1.0 : __builtin_huge_val()) : vt / vo;
-      }
-      out[h] = a;
-    }
+    affinities_from_best<NHW>(t, v, best, out);
   }
-  double* dst = aff + i * NHW;
-#pragma unroll
-  for (int h = 0; h < NHW; ++h) {
-    dst[h] = out[h];
-    // non-negative doubles order like their bit patterns; complemented, an
-    // ascending sort gives decreasing affinity
-    if (keys) keys[(int64_t)h * b.n + i] = ~(uint64_t)__double_as_longlong(out[h]);
-  }
+  store_affinities<NHW>(b, i, out, aff, keys);
 }
 
 // ---------------------------------------------------------------------------
@@ -2704,13 +2766,19 @@ hipError_t launch_decide_batching(const DevTables& t, const Batch& b, const Batc
 }
 
 hipError_t launch_affinity(const DevTables& t, const Batch& b, double* aff, int32_t* order, void* scratch,
-                           size_t scratch_bytes, hipStream_t s) {
+                           size_t scratch_bytes, const FullScratch* w, hipStream_t s) {
   if (b.n == 0) return hipSuccess;
   const int64_t n = b.n;
   uint64_t* keys = order ? static_cast<uint64_t*>(scratch) : nullptr;  // [n_hw * n]
   uint64_t* kout = keys ? keys + (int64_t)t.n_hw * n : nullptr;          // [n]
   int32_t* iota = kout ? reinterpret_cast<int32_t*>(kout + n) : nullptr; // [n]
-  LLAMA_DISPATCH_NHW(affinity_kernel, dim3(blocks_for(n, 256)), dim3(256), s, t, b, aff, keys, iota);
+  if (w && launch_counting_sort(AffinityKeys{t, b, aff, keys, iota}, n, t.n_ops, w->cnt, w->start, w->cursor, w->perm,
+                                w->hist, s)) {
+    LLAMA_DISPATCH_NHW(affinity_ops_kernel, dim3((unsigned)((t.n_ops + 3) / 4)), dim3(256), s, t, b, w->start,
+                       w->perm, aff, keys);
+  } else {
+    LLAMA_DISPATCH_NHW(affinity_kernel, dim3(blocks_for(n, 256)), dim3(256), s, t, b, aff, keys, iota);
+  }
   if (!order) return hipGetLastError();
   const size_t off = ((size_t)n * (8 * (size_t)t.n_hw + 8 + 4) + 255) & ~(size_t)255;
   if (scratch_bytes < off) return hipErrorInvalidValue;

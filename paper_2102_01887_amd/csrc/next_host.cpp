@@ -415,15 +415,27 @@ int llama_affinity(llama_ctx* c, int64_t n, const int32_t* op, const int32_t* el
   }
   llama::Batch b{};
   b.n = n; b.op = op; b.elapsed = elapsed; b.slo = slo; b.queue = queue; b.mode = mode;
-  // one search per invocation in a merged order (with queueing times the
-  // per-call one, when every op fits the merge and the merge pays); else one
-  // per backend
-  hipError_t e = (queue ? c->alpha_max_op <= llama::ALPHA_MERGE_MAX && c->d_aq_cnt.p && merge_pays(c, n)
-                        : c->d_m_cnt.p != nullptr)
-                     ? llama::launch_affinity_queue(c->tables(), b, aff, order, c->d_aff_scratch.p,
-                                                    c->d_aff_scratch.bytes, s)
-                     : llama::launch_affinity(c->tables(), b, aff, order, c->d_aff_scratch.p,
-                                              c->d_aff_scratch.bytes, s);
+  // with queueing times, one search per invocation in the per-call merged
+  // order when every op fits the merge and the merge pays; else the
+  // invocations grouped by op in the full scan's scratch when it holds n
+  // (grown here, except while the stream is being captured), counted per
+  // backend; else one thread per invocation (without queueing times, one
+  // search in the static merged order)
+  hipError_t e;
+  if (queue && c->alpha_max_op <= llama::ALPHA_MERGE_MAX && c->d_aq_cnt.p && merge_pays(c, n)) {
+    e = llama::launch_affinity_queue(c->tables(), b, aff, order, c->d_aff_scratch.p, c->d_aff_scratch.bytes, s);
+  } else {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    const bool capturing = s && hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+    const bool grouped = n <= c->perm_cap || (!capturing && reserve_perm(c, n, s) == LLAMA_OK);
+    llama::FullScratch w{c->d_cnt.as<int32_t>(), c->d_start.as<int32_t>(), c->d_cursor.as<int32_t>(),
+                         c->d_perm.as<int32_t>(), c->d_hist.as<int32_t>()};
+    if (!grouped && !queue && c->d_m_cnt.p)
+      e = llama::launch_affinity_queue(c->tables(), b, aff, order, c->d_aff_scratch.p, c->d_aff_scratch.bytes, s);
+    else
+      e = llama::launch_affinity(c->tables(), b, aff, order, c->d_aff_scratch.p, c->d_aff_scratch.bytes,
+                                 grouped ? &w : nullptr, s);
+  }
   if (e != hipSuccess) return llama::hip_fail(c, e, "affinity launch");
   return LLAMA_OK;
 }

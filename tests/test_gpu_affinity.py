@@ -13,7 +13,7 @@ import pytest
 
 from paper_2102_01887_amd import binding as B
 from paper_2102_01887_amd import workloads as wl
-from test_gpu_parity import PAPER, PROB, Run, dev, say
+from test_gpu_parity import PAPER, PROB, Run, _torch, dev, say
 
 pytestmark = pytest.mark.gpu
 RTOL = 1e-15
@@ -99,6 +99,63 @@ def test_affinity_without_order_and_invalid_invocations():
     ok[::6] = False
     want = r.P.affinity(PAPER, 1, 1)
     close(aff[ok], want[ok])
+
+
+def test_affinity_order_with_invalid_invocations():
+    # invalid invocations get zero affinities, and the commit order still
+    # holds every invocation once, affinities non-increasing, ties by index
+    w = wl.with_resource_totals(wl.make_c2(seed=62, n_pipelines=8, n_inv=3_000))
+    r = Run(w)
+    r.L.set_alpha(1, 1)
+    torch = r.torch
+    op = w.inv_op.copy()
+    op[::7] = -1
+    aff, order = r.L.affinity(dev(op, torch), r.el, r.slo)
+    torch.cuda.synchronize()
+    aff, order = aff.cpu().numpy(), order.cpu().numpy()
+    assert r.L.stats(reset_error=True)["device_error"] & B.DEVERR_INVALID_INVOCATION
+    want = r.P.affinity(PAPER, 1, 1)
+    want[::7] = 0.0
+    close(aff, want)
+    check_order(order, aff, want)
+
+
+def test_affinity_c3_many_ops_grouped():
+    # more ops than one LDS histogram holds, far more configurations than
+    # invocations: the invocations are grouped by op in two levels and
+    # counted per backend, with and without queueing times
+    w = wl.with_resource_totals(wl.make_c3(seed=63, n_pipelines=320, n_inv=20_000, max_cfg=2048))
+    assert w.n_ops > 12288 and 8 * w.n_inv < w.n_cfg
+    r = Run(w)
+    run_case(r, (1, 1), modes=(PAPER,))
+    run_case(r, (3, 2), Q=[50_000, 0, 400_000, 2_000_000], modes=(PAPER,))
+
+
+def test_affinity_captured_before_any_scratch():
+    # captured into a graph on a fresh context, before any call has grown the
+    # grouping scratch: the static merged order without queueing times, one
+    # thread per invocation with them (no allocation under capture); every
+    # replay checked
+    torch = _torch()
+    w = wl.with_resource_totals(wl.make_c3(seed=64, n_pipelines=40, n_inv=2000, max_cfg=512))
+    assert 8 * w.n_inv < w.n_cfg
+    r = Run(w)
+    r.L.set_alpha(1, 1)
+    s = torch.cuda.Stream()
+    for Q in (None, [50_000, 0, 400_000, 2_000_000]):
+        q = None if Q is None else dev(np.asarray(Q, np.int64), torch)
+        aff = torch.empty((w.n_inv, w.n_hw), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            r.L.affinity(r.op, r.el, r.slo, q, PAPER, aff=aff, with_order=False, stream=s)
+        want = r.P.affinity(PAPER, 1, 1, Q=Q)
+        for _ in range(2):
+            aff.fill_(-1.0)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            close(aff.cpu().numpy(), want)
 
 
 def test_affinity_needs_alpha():
