@@ -156,6 +156,41 @@ def test_alpha_captured_before_any_scratch():
             assert np.array_equal(cfg.cpu().numpy(), c_or) and np.array_equal(flag.cpu().numpy(), f_or), Q
 
 
+def test_grouping_with_few_invocations_over_many_ops():
+    # five invocations (one invalid) over more ops than one LDS histogram
+    # holds: the two-level counting sort with nearly every op empty, for the
+    # full scan, the finite-alpha decision with queueing times and the
+    # affinities
+    from test_gpu_affinity import close
+    torch = _torch()
+    base = wl.with_resource_totals(wl.make_c3(seed=50, n_pipelines=320, n_inv=1000, max_cfg=256))
+    assert base.n_ops > 12288
+    op = np.array([base.n_ops - 1, 0, base.n_ops // 2, base.n_ops + 3, 12288], np.int32)
+    slo = np.array([900_000, 50_000, 2_000_000, 10, 400_000], np.int32)
+    el = np.array([1000, 40_000, 0, 0, 399_000], np.int32)
+    w = base.with_invocations(op, el, slo)
+    L = B.Llama(0).load(w)
+    P = oracle.Problem(w)
+    ok = np.arange(5) != 3
+    d_op, d_el, d_slo = dev(op, torch), dev(el, torch), dev(slo, torch)
+    c, f = L.decide(d_op, d_el, d_slo, mode=PAPER, scan=B.SCAN_FULL)
+    c_or, f_or = P.decide(PAPER, sl=np.flatnonzero(ok))
+    c, f = c.cpu().numpy(), f.cpu().numpy()
+    assert c[3] == -1 and np.array_equal(c[ok], c_or) and np.array_equal(f[ok], f_or)
+    L.set_alpha(1, 1)
+    Q = [30_000, 0, 200_000, 5_000_000]
+    c, f = L.decide_alpha(d_op, d_el, d_slo, dev(np.asarray(Q, np.int64), torch), PAPER)
+    c_or, f_or = P.decide_alpha(PAPER, 1, 1, Q=Q, sl=np.flatnonzero(ok))
+    c, f = c.cpu().numpy(), f.cpu().numpy()
+    assert c[3] == -1 and np.array_equal(c[ok], c_or) and np.array_equal(f[ok], f_or)
+    aff, order = L.affinity(d_op, d_el, d_slo)
+    aff, order = aff.cpu().numpy(), order.cpu().numpy()
+    assert (aff[3] == 0).all()
+    close(aff[ok], P.affinity(PAPER, 1, 1, sl=np.flatnonzero(ok)))
+    assert all(sorted(order[h]) == list(range(5)) for h in range(w.n_hw))
+    L.stats(reset_error=True)
+
+
 def test_alpha_fuzz_small_tables():
     rng = np.random.default_rng(8)
     for rep in range(12):
