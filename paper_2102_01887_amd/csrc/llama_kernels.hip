@@ -2208,18 +2208,29 @@ __global__ __launch_bounds__(256) void feedback_apply_kernel(DevTables t, Feedba
 // Exclusive prefix minimum over the wavefront (lane order) of x, continued
 // from `carry` (the minimum of everything before lane 0); returns the
 // exclusive value of this lane and updates carry to the chunk's total.
+// min(x, x of the lane the DPP control names); lanes it names none (or that
+// the row or bank mask leaves out) take the identity 0xFFFFFFFF
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ uint32_t dpp_min(uint32_t x) {
+  return umin32(x, (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFFu, (int)x, CTRL, ROW_MASK, BANK_MASK, false));
+}
+constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114, DPP_ROW_SHR8 = 0x118;
+constexpr int DPP_WAVE_SHR1 = 0x138;
+
+// Exclusive running minimum over the wavefront's lanes, continuing from
+// carry (updated to the minimum through lane 63): the inclusive minimum by
+// doubling shifts within each 16-lane row, then the rows' last lanes carried
+// into the rows after them; shifted one lane, with carry in lane 0.
 __device__ __forceinline__ uint32_t wave_excl_min(uint32_t x, uint32_t& carry) {
-  const int lane = threadIdx.x & 63;
-  uint32_t incl = x;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t o = __shfl_up(incl, d, 64);
-    if (lane >= d && o < incl) incl = o;
-  }
-  if (carry < incl) incl = carry;
-  const uint32_t p = __shfl_up(incl, 1, 64);
-  const uint32_t excl = lane > 0 ? p : carry;
-  carry = __shfl(incl, 63, 64);
+  uint32_t incl = dpp_min<DPP_ROW_SHR1, 0xF, 0xF>(x);
+  incl = dpp_min<DPP_ROW_SHR2, 0xF, 0xF>(incl);
+  incl = dpp_min<DPP_ROW_SHR4, 0xF, 0xF>(incl);
+  incl = dpp_min<DPP_ROW_SHR8, 0xF, 0xF>(incl);
+  incl = dpp_min<DPP_ROW_BCAST15, 0xA, 0xF>(incl);
+  incl = dpp_min<DPP_ROW_BCAST31, 0xC, 0xF>(incl);
+  incl = umin32(incl, carry);
+  const uint32_t excl = (uint32_t)__builtin_amdgcn_update_dpp((int)carry, (int)incl, DPP_WAVE_SHR1, 0xF, 0xF, false);
+  carry = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
   return excl;
 }
 
