@@ -339,8 +339,14 @@ int llama_set_alpha(llama_ctx *ctx, uint32_t alpha_num, uint32_t alpha_den);
  * each call first merges every op's configurations by remaining-time
  * threshold plus its backend's queueing time into context-owned tables (12
  * bytes per configuration), so calls with queueing times that overlap on one
- * context must be ordered; otherwise each invocation searches each backend's
- * list (no per-call tables).  Both give the same decisions.
+ * context must be ordered; otherwise the invocations are grouped by op (a
+ * counting sort in the scratch that LLAMA_SCAN_FULL uses, grown on demand as
+ * by llama_reserve, so such calls that overlap on one context must be
+ * ordered too) and each op's backend lists are counted once per invocation;
+ * while `stream` is being captured and that scratch is too small, each
+ * invocation searches each backend's list instead.  Without d_queue_us, one
+ * search per invocation in the op's list merged over its backends.  Every
+ * path gives the same decisions.
  */
 int llama_decide_alpha(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
                        const int32_t *d_elapsed_us, const int32_t *d_slo_us,
@@ -364,10 +370,11 @@ int llama_decide_alpha(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
  * d_flag is 1 when the committed configuration meets its slack.  Invalid
  * invocations get -1 / 0 and set the device error word.  The context keeps a
  * scratch queue of about 8 bytes per invocation (those that need the
- * batch-limited choice); it grows on demand but not while `stream` is being
- * captured (LLAMA_E_STATE: call once before capturing).  Calls that overlap on
- * one context share it and must be ordered.  n_inv above 2^31 - 1 is
- * LLAMA_E_RANGE.
+ * batch-limited choice, grouped by op for that choice: about 8 bytes more per
+ * invocation and 12 per op); it grows on demand but not while `stream` is
+ * being captured (LLAMA_E_STATE: call once before capturing).  Calls that
+ * overlap on one context share it and must be ordered.  n_inv above
+ * 2^31 - 1 is LLAMA_E_RANGE.
  */
 #define LLAMA_CFG_WAIT (-2)
 int llama_decide_batching(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
@@ -395,7 +402,12 @@ int llama_decide_batching(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op
  * With d_order the context keeps scratch of n_inv * (8 n_hw + 12) bytes plus
  * the sort's temporary storage; it grows on demand but not while `stream` is
  * being captured (LLAMA_E_STATE: call once before capturing).  Invalid
- * invocations get affinity 0 and set the device error word.
+ * invocations get affinity 0 and set the device error word.  Unless the
+ * per-call merge of llama_decide_alpha applies, the invocations are grouped
+ * by op in the scratch that LLAMA_SCAN_FULL uses (grown on demand as by
+ * llama_reserve; calls that overlap on one context must be ordered); while
+ * `stream` is being captured and that scratch is too small, one search per
+ * invocation instead.  Every path gives the same affinities.
  */
 int llama_affinity(llama_ctx *ctx, int64_t n_inv, const int32_t *d_inv_op,
                    const int32_t *d_elapsed_us, const int32_t *d_slo_us,
@@ -472,8 +484,10 @@ int llama_decide_full_noalloc(llama_ctx *ctx, int64_t n_inv, const int32_t *d_in
 /* Scratch words one llama_decide_full_noalloc call needs (-1 for negative sizes). */
 int64_t llama_decide_full_noalloc_words(int64_t n_inv, int32_t n_ops);
 
-/* Pre-size the scratch that LLAMA_SCAN_FULL needs for batches of up to
- * max_inv invocations (device memory, 4 bytes per invocation).  Synchronous. */
+/* Pre-size the scratch that LLAMA_SCAN_FULL (and the grouping by op of
+ * llama_decide_alpha, llama_affinity) needs for batches of up to max_inv
+ * invocations (device memory, 4 bytes per invocation, 8 with more than
+ * 12,288 ops).  Synchronous. */
 int llama_reserve(llama_ctx *ctx, int64_t max_inv);
 
 /* Context-level counters (Tab. 3 analogue).  Synchronises the context. */
