@@ -30,8 +30,9 @@
  *   - `stream` is a hipStream_t (NULL = the default stream); decision calls
  *     only enqueue work and return; outputs are valid once the stream has
  *     synchronised; they may be captured into a hipGraph and allocate
- *     nothing, except the full-scan scratch growth described at
- *     llama_decide;
+ *     nothing, except the scratch growth (outside capture) described at
+ *     llama_decide, llama_decide_alpha, llama_affinity and
+ *     llama_decide_batching;
  *   - a context is not thread-safe: use one per thread or lock around it.
  */
 #ifndef LLAMA_H
@@ -74,8 +75,9 @@ enum llama_scan_mode {
     LLAMA_SCAN_INDEXED = 1,
     /* Every configuration of the op: invocations are bucketed by op on the
      * GPU and one wavefront per op scans its table for its invocations, in
-     * the layout the schedule table picks (llama_autotune_full).  Uses
-     * context scratch of 4 bytes per invocation (see llama_reserve). */
+     the layout the schedule table picks (llama_autotune_full).  Uses
+     * context scratch of 4 bytes per invocation, 8 with more than 12,288 ops
+     * (see llama_reserve). */
     LLAMA_SCAN_FULL = 2,
     /* Every configuration, one wavefront per invocation, lanes over the
      * configurations, wavefront min reduction; no scratch. */
