@@ -1585,7 +1585,7 @@ __global__ __launch_bounds__(256) void scan_classes_kernel(DevTables t, Batch b,
   const int lane = threadIdx.x & 63;
   // the op is the same for the whole wavefront: keep it (and what is loaded
   // from it) in scalar registers
-  const int v = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+  const int v = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
   if (v >= t.n_ops) return;
   const int p0 = start[v], p1 = start[v + 1];
   const int k = p1 - p0;
@@ -2019,7 +2019,7 @@ template <int NHW, bool AFF>
 __device__ __forceinline__ void alpha_ops(const DevTables& t, const Batch& b, const int32_t* start,
                                           const int32_t* perm, double* aff, uint64_t* keys) {
   const int lane = threadIdx.x & 63;
-  const int v = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+  const int v = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
   if (v >= t.n_ops) return;
   const int p0 = start[v], p1 = start[v + 1];
   if (p0 == p1) return;
@@ -2540,7 +2540,7 @@ template <int NHW>
 __global__ __launch_bounds__(256) void batching_ops_kernel(DevTables t, Batch b, BatchingArgs ba,
                                                            const int32_t* start, const int32_t* perm) {
   const int lane = threadIdx.x & 63;
-  const int v = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+  const int v = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
   if (v >= t.n_ops) return;
   const int p0 = start[v], p1 = start[v + 1];
   if (p0 == p1) return;
@@ -2767,7 +2767,7 @@ hipError_t launch_decide_batching(const DevTables& t, const Batch& b, const Batc
   // slots), then one wavefront per op
   if (launch_counting_sort(QueueKeys{b.op, a.queue, a.count, cap}, n_slots, t.n_ops, a.op_cnt, a.op_start,
                            a.op_cursor, a.perm, a.hist, s)) {
-    LLAMA_DISPATCH_NHW(batching_ops_kernel, dim3((unsigned)((t.n_ops + 3) / 4)), dim3(256), s, t, b, a, a.op_start,
+    LLAMA_DISPATCH_NHW(batching_ops_kernel, dim3((unsigned)t.n_ops), dim3(64), s, t, b, a, a.op_start,
                        a.perm);
     return hipGetLastError();
   }
@@ -2785,7 +2785,7 @@ hipError_t launch_affinity(const DevTables& t, const Batch& b, double* aff, int3
   int32_t* iota = kout ? reinterpret_cast<int32_t*>(kout + n) : nullptr; // [n]
   if (w && launch_counting_sort(AffinityKeys{t, b, aff, keys, iota}, n, t.n_ops, w->cnt, w->start, w->cursor, w->perm,
                                 w->hist, s)) {
-    LLAMA_DISPATCH_NHW(affinity_ops_kernel, dim3((unsigned)((t.n_ops + 3) / 4)), dim3(256), s, t, b, w->start,
+    LLAMA_DISPATCH_NHW(affinity_ops_kernel, dim3((unsigned)t.n_ops), dim3(64), s, t, b, w->start,
                        w->perm, aff, keys);
   } else {
     LLAMA_DISPATCH_NHW(affinity_kernel, dim3(blocks_for(n, 256)), dim3(256), s, t, b, aff, keys, iota);
@@ -2810,7 +2810,7 @@ hipError_t launch_decide_alpha(const DevTables& t, const Batch& b, const FullScr
   // run's upper levels being shared in L2 by the op's invocations
   if (b.queue && w &&
       launch_counting_sort(InvocationKeys{t, b}, b.n, t.n_ops, w->cnt, w->start, w->cursor, w->perm, w->hist, s)) {
-    LLAMA_DISPATCH_NHW(decide_alpha_ops_kernel, dim3((unsigned)((t.n_ops + 3) / 4)), dim3(256), s, t, b, w->start,
+    LLAMA_DISPATCH_NHW(decide_alpha_ops_kernel, dim3((unsigned)t.n_ops), dim3(64), s, t, b, w->start,
                        w->perm);
     return hipGetLastError();
   }
@@ -2854,7 +2854,7 @@ hipError_t launch_decide_full(const DevTables& t, const Batch& b, const FullScra
     hipLaunchKernelGGL(bucket_offsets_kernel, dim3(1), dim3(1024), 0, s, w.cnt, t.n_ops, w.start, w.cursor);
     hipLaunchKernelGGL(bucket_scatter_kernel, dim3(g), dim3(256), 0, s, t, b, w.cursor, w.perm);
   }
-  LLAMA_DISPATCH_NHW(scan_classes_kernel, dim3((unsigned)((t.n_ops + 3) / 4)), dim3(256), s, t, b, w.start, w.perm,
+  LLAMA_DISPATCH_NHW(scan_classes_kernel, dim3((unsigned)t.n_ops), dim3(64), s, t, b, w.start, w.perm,
                      t.full_cross_num, t.full_cross_den);
   return hipGetLastError();
 }
