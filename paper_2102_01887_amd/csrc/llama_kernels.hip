@@ -1134,16 +1134,23 @@ __device__ __forceinline__ bool bucket_key(const DevTables& t, const Batch& b, i
   return true;
 }
 
-// Sources of bucketing keys over positions 0 .. size() - 1.  count_key is
-// the first pass's (it may answer what it leaves out), place_key the second's.
+// Sources of bucketing keys over positions 0 .. size() - 1: key() only
+// loads (so that a thread's loads for several positions can be in flight
+// together); visit() takes the counting pass's side effects for a position
+// (answering what key() leaves out).
 struct InvocationKeys {  // the batch's invocations by op; invalid ones answered at once
   DevTables t;
   Batch b;
   __device__ int64_t size() const { return b.n; }
-  __device__ bool count_key(int64_t i, int* v) const { return bucket_key(t, b, i, v); }
-  __device__ bool place_key(int64_t i, int* v) const {
+  __device__ bool key(int64_t i, int* v) const {
     *v = b.op[i];
     return !invalid_invocation(*v, b.elapsed[i], b.slo[i], t.n_ops);
+  }
+  __device__ void visit(int64_t i, bool ok) const {
+    if (ok) return;
+    b.cfg[i] = -1;
+    if (b.flag) b.flag[i] = 0;
+    atomicOr(t.err, 1u);
   }
 };
 struct QueueKeys {  // occupied slots of the batching sub-queues, by their invocation's op
@@ -1152,15 +1159,14 @@ struct QueueKeys {  // occupied slots of the batching sub-queues, by their invoc
   const uint32_t* count;
   int64_t cap;
   __device__ int64_t size() const { return (int64_t)BATCH_QUEUES * cap; }
-  __device__ bool place_key(int64_t w, int* v) const {
+  __device__ bool key(int64_t w, int* v) const {
     const int sq = (int)(w / cap);
     if (w - (int64_t)sq * cap >= (int64_t)count[32 * sq]) return false;
     *v = op[queue[w].x];
     return true;
   }
-  __device__ bool count_key(int64_t w, int* v) const { return place_key(w, v); }
+  __device__ void visit(int64_t, bool) const {}
 };
-
 struct AffinityKeys {  // the batch's invocations by op; invalid ones get zero affinities
   DevTables t;
   Batch b;
@@ -1168,21 +1174,23 @@ struct AffinityKeys {  // the batch's invocations by op; invalid ones get zero a
   uint64_t* keys;
   int32_t* iota;
   __device__ int64_t size() const { return b.n; }
-  __device__ bool place_key(int64_t i, int* v) const {
+  __device__ bool key(int64_t i, int* v) const {
     *v = b.op[i];
     return !invalid_invocation(*v, b.elapsed[i], b.slo[i], t.n_ops);
   }
-  __device__ bool count_key(int64_t i, int* v) const {
+  __device__ void visit(int64_t i, bool ok) const {
     if (iota) iota[i] = (int32_t)i;
-    if (place_key(i, v)) return true;
+    if (ok) return;
     atomicOr(t.err, 1u);
     for (int h = 0; h < t.n_hw; ++h) {
       aff[i * t.n_hw + h] = 0.0;
       if (keys) keys[(int64_t)h * b.n + i] = ~0ull;  // complemented bits of 0.0
     }
-    return false;
   }
 };
+
+// Positions a thread of the counting sort's chunk kernels takes at once.
+constexpr int BUCKET_UNROLL = 8;
 
 // Each workgroup counts its chunk of BUCKET_CHUNK positions in an LDS
 // histogram over the keys op >> shift and writes it as one row of
@@ -1197,38 +1205,63 @@ __global__ __launch_bounds__(1024) void bucket_hist_kernel(K keys, int n_ops, in
   const int64_t n = keys.size();
   const int64_t a = (int64_t)blockIdx.x * BUCKET_CHUNK;
   const int64_t e = a + BUCKET_CHUNK < n ? a + BUCKET_CHUNK : n;
-  for (int64_t i = a + threadIdx.x; i < e; i += blockDim.x) {
-    int v;
-    if (keys.count_key(i, &v)) atomicAdd(&sh[v >> shift], 1);
+  const int64_t bs = blockDim.x;
+  for (int64_t i0 = a + threadIdx.x; i0 < e; i0 += BUCKET_UNROLL * bs) {
+    int v[BUCKET_UNROLL];
+    bool ok[BUCKET_UNROLL];
+#pragma unroll
+    for (int u = 0; u < BUCKET_UNROLL; ++u) ok[u] = i0 + u * bs < e && keys.key(i0 + u * bs, &v[u]);
+#pragma unroll
+    for (int u = 0; u < BUCKET_UNROLL; ++u) {
+      if (i0 + u * bs >= e) break;
+      keys.visit(i0 + u * bs, ok[u]);
+      if (ok[u]) atomicAdd(&sh[v[u] >> shift], 1);
+    }
   }
   __syncthreads();
   int32_t* row = hist + (int64_t)blockIdx.x * n_keys;
   for (int j = threadIdx.x; j < n_keys; j += blockDim.x) row[j] = sh[j];
 }
 
-// Per op: exclusive prefix over chunks (in place) and the op's total.
-__global__ __launch_bounds__(256) void bucket_columns_kernel(int32_t* hist, int n_chunks, int n_ops,
-                                                             int32_t* total) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+// Per key: exclusive prefix over chunks (in place) and the key's total.  A
+// workgroup takes COL_KEYS consecutive keys with COL_PARTS threads each; part
+// p of a key sums its run of chunks (loads in flight together), the parts'
+// sums meet in LDS, and each part then rewrites its run as the running prefix
+// from its offset.
+constexpr int COL_KEYS = 32, COL_PARTS = 8;
+__global__ __launch_bounds__(COL_KEYS * COL_PARTS) void bucket_columns_kernel(int32_t* hist, int n_chunks,
+                                                                              int n_ops, int32_t* total) {
+  __shared__ int32_t sPart[COL_PARTS][COL_KEYS];
+  const int kl = threadIdx.x % COL_KEYS, part = threadIdx.x / COL_KEYS;
+  const int v = blockIdx.x * COL_KEYS + kl;
+  const int per = (n_chunks + COL_PARTS - 1) / COL_PARTS;
+  const int c0 = part * per, c1 = c0 + per < n_chunks ? c0 + per : n_chunks;
+  int sum = 0;
+  if (v < n_ops) {
+    for (int c = c0; c < c1; c += 32) {  // up to 32 loads in flight
+      int x[32];
+#pragma unroll
+      for (int k = 0; k < 32; ++k) x[k] = c + k < c1 ? hist[(int64_t)(c + k) * n_ops + v] : 0;
+#pragma unroll
+      for (int k = 0; k < 32; ++k) sum += x[k];
+    }
+  }
+  sPart[part][kl] = sum;
+  __syncthreads();
   if (v >= n_ops) return;
   int run = 0;
-  int c = 0;
-  for (; c + 8 <= n_chunks; c += 8) {  // eight independent loads in flight
-    int x[8];
+  for (int q = 0; q < part; ++q) run += sPart[q][kl];
+  if (part == COL_PARTS - 1) total[v] = run + sum;
+  for (int c = c0; c < c1; c += 32) {
+    int x[32];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) x[k] = hist[(int64_t)(c + k) * n_ops + v];
+    for (int k = 0; k < 32; ++k) x[k] = c + k < c1 ? hist[(int64_t)(c + k) * n_ops + v] : 0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      hist[(int64_t)(c + k) * n_ops + v] = run;
+    for (int k = 0; k < 32; ++k) {
+      if (c + k < c1) hist[(int64_t)(c + k) * n_ops + v] = run;
       run += x[k];
     }
   }
-  for (; c < n_chunks; ++c) {
-    const int x = hist[(int64_t)c * n_ops + v];
-    hist[(int64_t)c * n_ops + v] = run;
-    run += x;
-  }
-  total[v] = run;
 }
 
 // Each chunk places its positions at start[key] + (earlier chunks' count) +
@@ -1247,12 +1280,20 @@ __global__ __launch_bounds__(1024) void bucket_place_kernel(K keys, int n_ops, c
   const int64_t a = (int64_t)blockIdx.x * BUCKET_CHUNK;
   const int64_t e = a + BUCKET_CHUNK < n ? a + BUCKET_CHUNK : n;
   const uint32_t low = (1u << shift) - 1u;
-  for (int64_t i = a + threadIdx.x; i < e; i += blockDim.x) {
-    int v;
-    if (!keys.place_key(i, &v)) continue;
-    const int k = v >> shift;
-    const uint32_t entry = shift ? (((uint32_t)v & low) << 24) | (uint32_t)i : (uint32_t)i;
-    perm[start[k] + row[k] + atomicAdd(&sh[k], 1)] = (int32_t)entry;
+  const int64_t bs = blockDim.x;
+  for (int64_t i0 = a + threadIdx.x; i0 < e; i0 += BUCKET_UNROLL * bs) {
+    int v[BUCKET_UNROLL];
+    bool ok[BUCKET_UNROLL];
+#pragma unroll
+    for (int u = 0; u < BUCKET_UNROLL; ++u) ok[u] = i0 + u * bs < e && keys.key(i0 + u * bs, &v[u]);
+#pragma unroll
+    for (int u = 0; u < BUCKET_UNROLL; ++u) {
+      if (!ok[u]) continue;
+      const int64_t i = i0 + u * bs;
+      const int k = v[u] >> shift;
+      const uint32_t entry = shift ? (((uint32_t)v[u] & low) << 24) | (uint32_t)i : (uint32_t)i;
+      perm[start[k] + row[k] + atomicAdd(&sh[k], 1)] = (int32_t)entry;
+    }
   }
 }
 
@@ -1270,8 +1311,8 @@ inline bool two_level(int64_t n, int32_t n_ops) {
   return n_ops > BUCKET_LDS_OPS && ((n_ops - 1) >> FINE_BITS) + 1 <= BUCKET_LDS_OPS && n <= (1 << 24);
 }
 inline int64_t round_words(int64_t w) { return (w + 63) & ~(int64_t)63; }
-__global__ __launch_bounds__(FINE_OPS) void bucket_fine_kernel(const int32_t* cstart, const int32_t* packed,
-                                                               int n_ops, int32_t* start, int32_t* perm) {
+__global__ __launch_bounds__(FINE_OPS) void bucket_fine_kernel(const int32_t* cstart, const int32_t* __restrict__ packed,
+                                                               int n_ops, int32_t* start, int32_t* __restrict__ perm) {
   __shared__ int32_t cnt[FINE_OPS];
   __shared__ int32_t wsum[FINE_OPS / 64];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1279,7 +1320,14 @@ __global__ __launch_bounds__(FINE_OPS) void bucket_fine_kernel(const int32_t* cs
   const int a = cstart[g], e = cstart[g + 1];
   cnt[tid] = 0;
   __syncthreads();
-  for (int j = a + tid; j < e; j += FINE_OPS) atomicAdd(&cnt[(uint32_t)packed[j] >> 24], 1);
+  for (int j0 = a + tid; j0 < e; j0 += BUCKET_UNROLL * FINE_OPS) {
+    uint32_t q[BUCKET_UNROLL];
+#pragma unroll
+    for (int u = 0; u < BUCKET_UNROLL; ++u) q[u] = j0 + u * FINE_OPS < e ? (uint32_t)packed[j0 + u * FINE_OPS] : 0u;
+#pragma unroll
+    for (int u = 0; u < BUCKET_UNROLL; ++u)
+      if (j0 + u * FINE_OPS < e) atomicAdd(&cnt[q[u] >> 24], 1);
+  }
   __syncthreads();
   // exclusive prefix of the FINE_OPS counts: wavefront scans, then the
   // wavefront totals
@@ -1300,9 +1348,13 @@ __global__ __launch_bounds__(FINE_OPS) void bucket_fine_kernel(const int32_t* cs
   if (v < n_ops) start[v] = pos;
   if (g == (int)gridDim.x - 1 && tid == 0) start[n_ops] = e;
   __syncthreads();
-  for (int j = a + tid; j < e; j += FINE_OPS) {
-    const uint32_t q = (uint32_t)packed[j];
-    perm[atomicAdd(&cnt[q >> 24], 1)] = (int32_t)(q & 0xFFFFFFu);
+  for (int j0 = a + tid; j0 < e; j0 += BUCKET_UNROLL * FINE_OPS) {
+    uint32_t q[BUCKET_UNROLL];
+#pragma unroll
+    for (int u = 0; u < BUCKET_UNROLL; ++u) q[u] = j0 + u * FINE_OPS < e ? (uint32_t)packed[j0 + u * FINE_OPS] : 0u;
+#pragma unroll
+    for (int u = 0; u < BUCKET_UNROLL; ++u)
+      if (j0 + u * FINE_OPS < e) perm[atomicAdd(&cnt[q[u] >> 24], 1)] = (int32_t)(q[u] & 0xFFFFFFu);
   }
 }
 
@@ -2720,8 +2772,8 @@ bool launch_counting_sort(const K& keys, int64_t n, int n_ops, int32_t* cnt, int
   if (n_ops <= BUCKET_LDS_OPS) {
     const size_t lds = sizeof(int32_t) * (size_t)n_ops;
     hipLaunchKernelGGL(bucket_hist_kernel<K>, dim3(n_chunks), dim3(1024), lds, s, keys, n_ops, hist, 0);
-    hipLaunchKernelGGL(bucket_columns_kernel, dim3(blocks_for(n_ops, 256)), dim3(256), 0, s, hist, n_chunks, n_ops,
-                       cnt);
+    hipLaunchKernelGGL(bucket_columns_kernel, dim3(blocks_for(n_ops, COL_KEYS)), dim3(COL_KEYS * COL_PARTS), 0, s,
+                       hist, n_chunks, n_ops, cnt);
     hipLaunchKernelGGL(bucket_offsets_kernel, dim3(1), dim3(1024), 0, s, cnt, n_ops, start, (int32_t*)nullptr);
     hipLaunchKernelGGL(bucket_place_kernel<K>, dim3(n_chunks), dim3(1024), lds, s, keys, n_ops, hist, start, perm, 0);
     return true;
@@ -2733,8 +2785,8 @@ bool launch_counting_sort(const K& keys, int64_t n, int n_ops, int32_t* cnt, int
   const size_t lds = sizeof(int32_t) * (size_t)n_groups;
   int32_t* packed = hist + round_words((int64_t)n_chunks * n_groups);
   hipLaunchKernelGGL(bucket_hist_kernel<K>, dim3(n_chunks), dim3(1024), lds, s, keys, n_ops, hist, FINE_BITS);
-  hipLaunchKernelGGL(bucket_columns_kernel, dim3(blocks_for(n_groups, 256)), dim3(256), 0, s, hist, n_chunks,
-                     n_groups, cnt);
+  hipLaunchKernelGGL(bucket_columns_kernel, dim3(blocks_for(n_groups, COL_KEYS)), dim3(COL_KEYS * COL_PARTS), 0, s,
+                     hist, n_chunks, n_groups, cnt);
   hipLaunchKernelGGL(bucket_offsets_kernel, dim3(1), dim3(1024), 0, s, cnt, n_groups, cursor, (int32_t*)nullptr);
   hipLaunchKernelGGL(bucket_place_kernel<K>, dim3(n_chunks), dim3(1024), lds, s, keys, n_ops, hist, cursor, packed,
                      FINE_BITS);
