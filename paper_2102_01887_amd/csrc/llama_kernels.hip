@@ -1271,11 +1271,13 @@ __global__ __launch_bounds__(COL_KEYS * COL_PARTS) void bucket_columns_kernel(in
 template <class K>
 __global__ __launch_bounds__(1024) void bucket_place_kernel(K keys, int n_ops, const int32_t* hist,
                                                            const int32_t* start, int32_t* perm, int shift) {
+  // the chunk's first position of each key (start + earlier chunks), then
+  // advanced by an LDS atomic per placed position
   extern __shared__ int32_t sh[];
   const int n_keys = ((n_ops - 1) >> shift) + 1;
-  for (int j = threadIdx.x; j < n_keys; j += blockDim.x) sh[j] = 0;
-  __syncthreads();
   const int32_t* row = hist + (int64_t)blockIdx.x * n_keys;
+  for (int j = threadIdx.x; j < n_keys; j += blockDim.x) sh[j] = start[j] + row[j];
+  __syncthreads();
   const int64_t n = keys.size();
   const int64_t a = (int64_t)blockIdx.x * BUCKET_CHUNK;
   const int64_t e = a + BUCKET_CHUNK < n ? a + BUCKET_CHUNK : n;
@@ -1292,7 +1294,7 @@ __global__ __launch_bounds__(1024) void bucket_place_kernel(K keys, int n_ops, c
       const int64_t i = i0 + u * bs;
       const int k = v[u] >> shift;
       const uint32_t entry = shift ? (((uint32_t)v[u] & low) << 24) | (uint32_t)i : (uint32_t)i;
-      perm[start[k] + row[k] + atomicAdd(&sh[k], 1)] = (int32_t)entry;
+      perm[atomicAdd(&sh[k], 1)] = (int32_t)entry;
     }
   }
 }
@@ -1311,50 +1313,59 @@ inline bool two_level(int64_t n, int32_t n_ops) {
   return n_ops > BUCKET_LDS_OPS && ((n_ops - 1) >> FINE_BITS) + 1 <= BUCKET_LDS_OPS && n <= (1 << 24);
 }
 inline int64_t round_words(int64_t w) { return (w + 63) & ~(int64_t)63; }
-__global__ __launch_bounds__(FINE_OPS) void bucket_fine_kernel(const int32_t* cstart, const int32_t* __restrict__ packed,
-                                                               int n_ops, int32_t* start, int32_t* __restrict__ perm) {
+constexpr int FINE_THREADS = 1024;  // threads of a group's workgroup (the first FINE_OPS scan the counts)
+__global__ __launch_bounds__(FINE_THREADS) void bucket_fine_kernel(const int32_t* cstart,
+                                                                  const int32_t* __restrict__ packed, int n_ops,
+                                                                  int32_t* start, int32_t* __restrict__ perm) {
   __shared__ int32_t cnt[FINE_OPS];
   __shared__ int32_t wsum[FINE_OPS / 64];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int g = blockIdx.x;
   const int a = cstart[g], e = cstart[g + 1];
-  cnt[tid] = 0;
+  if (tid < FINE_OPS) cnt[tid] = 0;
   __syncthreads();
-  for (int j0 = a + tid; j0 < e; j0 += BUCKET_UNROLL * FINE_OPS) {
+  for (int j0 = a + tid; j0 < e; j0 += BUCKET_UNROLL * FINE_THREADS) {
     uint32_t q[BUCKET_UNROLL];
 #pragma unroll
-    for (int u = 0; u < BUCKET_UNROLL; ++u) q[u] = j0 + u * FINE_OPS < e ? (uint32_t)packed[j0 + u * FINE_OPS] : 0u;
+    for (int u = 0; u < BUCKET_UNROLL; ++u)
+      q[u] = j0 + u * FINE_THREADS < e ? (uint32_t)packed[j0 + u * FINE_THREADS] : 0u;
 #pragma unroll
     for (int u = 0; u < BUCKET_UNROLL; ++u)
-      if (j0 + u * FINE_OPS < e) atomicAdd(&cnt[q[u] >> 24], 1);
+      if (j0 + u * FINE_THREADS < e) atomicAdd(&cnt[q[u] >> 24], 1);
   }
   __syncthreads();
   // exclusive prefix of the FINE_OPS counts: wavefront scans, then the
   // wavefront totals
-  const int x = cnt[tid];
-  int incl = x;
+  int x = 0, incl = 0;
+  if (tid < FINE_OPS) {
+    x = cnt[tid];
+    incl = x;
 #pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int y = __shfl_up(incl, d, 64);
-    if (lane >= d) incl += y;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += y;
+    }
+    if (lane == 63) wsum[wv] = incl;
   }
-  if (lane == 63) wsum[wv] = incl;
   __syncthreads();
-  int off = a;
-  for (int w = 0; w < wv; ++w) off += wsum[w];
-  const int pos = off + incl - x;
-  cnt[tid] = pos;  // every thread read its own count above
-  const int v = g * FINE_OPS + tid;
-  if (v < n_ops) start[v] = pos;
+  if (tid < FINE_OPS) {
+    int off = a;
+    for (int w = 0; w < wv; ++w) off += wsum[w];
+    const int pos = off + incl - x;
+    cnt[tid] = pos;  // every thread read its own count above
+    const int v = g * FINE_OPS + tid;
+    if (v < n_ops) start[v] = pos;
+  }
   if (g == (int)gridDim.x - 1 && tid == 0) start[n_ops] = e;
   __syncthreads();
-  for (int j0 = a + tid; j0 < e; j0 += BUCKET_UNROLL * FINE_OPS) {
+  for (int j0 = a + tid; j0 < e; j0 += BUCKET_UNROLL * FINE_THREADS) {
     uint32_t q[BUCKET_UNROLL];
 #pragma unroll
-    for (int u = 0; u < BUCKET_UNROLL; ++u) q[u] = j0 + u * FINE_OPS < e ? (uint32_t)packed[j0 + u * FINE_OPS] : 0u;
+    for (int u = 0; u < BUCKET_UNROLL; ++u)
+      q[u] = j0 + u * FINE_THREADS < e ? (uint32_t)packed[j0 + u * FINE_THREADS] : 0u;
 #pragma unroll
     for (int u = 0; u < BUCKET_UNROLL; ++u)
-      if (j0 + u * FINE_OPS < e) perm[atomicAdd(&cnt[q[u] >> 24], 1)] = (int32_t)(q[u] & 0xFFFFFFu);
+      if (j0 + u * FINE_THREADS < e) perm[atomicAdd(&cnt[q[u] >> 24], 1)] = (int32_t)(q[u] & 0xFFFFFFu);
   }
 }
 
@@ -2790,7 +2801,8 @@ bool launch_counting_sort(const K& keys, int64_t n, int n_ops, int32_t* cnt, int
   hipLaunchKernelGGL(bucket_offsets_kernel, dim3(1), dim3(1024), 0, s, cnt, n_groups, cursor, (int32_t*)nullptr);
   hipLaunchKernelGGL(bucket_place_kernel<K>, dim3(n_chunks), dim3(1024), lds, s, keys, n_ops, hist, cursor, packed,
                      FINE_BITS);
-  hipLaunchKernelGGL(bucket_fine_kernel, dim3(n_groups), dim3(FINE_OPS), 0, s, cursor, packed, n_ops, start, perm);
+  hipLaunchKernelGGL(bucket_fine_kernel, dim3(n_groups), dim3(FINE_THREADS), 0, s, cursor, packed, n_ops, start,
+                     perm);
   return true;
 }
 
