@@ -279,7 +279,7 @@ constexpr size_t TR_OFF_BT = TR_OFF_B + sizeof(bf16) * TRAIN_ROWS * TR_LDA;
 constexpr size_t TR_OFF_D = TR_OFF_BT + sizeof(bf16) * HID * TR_LDT;
 constexpr size_t TR_OFF_ROW = TR_OFF_D + sizeof(float) * TRAIN_ROWS * 2;
 constexpr size_t TR_OFF_RED = TR_OFF_ROW + sizeof(int32_t) * TRAIN_ROWS;
-constexpr size_t TR_OFF_W3 = TR_OFF_RED + sizeof(float) * 8;
+constexpr size_t TR_OFF_W3 = TR_OFF_RED + sizeof(float) * 16;  // one loss partial per wavefront (at most 16)
 constexpr size_t TRAIN_LDS = TR_OFF_W3 + sizeof(bf16) * 2 * HID;
 
 struct TrainKArgs {
@@ -359,6 +359,8 @@ constexpr int TR_KS = HID / 32;             // K steps of a 256-long contraction
 constexpr int TR_MB = TRAIN_ROWS / 16;      // 16-row tiles of a chunk
 constexpr int TR_LPR = TR_THREADS / TRAIN_ROWS;  // lanes per row in the output layer
 static_assert(TRAIN_ROWS % 32 == 0 && TRAIN_ROWS * 4 <= 256 && TR_LPR <= 64, "chunk shape");
+static_assert(TR_WAVES <= 16 && HID % (16 * TR_WAVES) == 0 && TR_THREADS >= 256 + HID,
+              "one loss partial per wavefront, whole column tiles, threads for the X and W3 staging");
 
 __global__ __launch_bounds__(TR_THREADS) void train_chunk_kernel(TrainKArgs k) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
@@ -391,7 +393,7 @@ __global__ __launch_bounds__(TR_THREADS) void train_chunk_kernel(TrainKArgs k) {
   const float b3a = k.b3[0], b3b = k.b3[1];
   const float yv = tid < nrow ? k.a.y[base + tid] : 0.0f;
   // X = [E[row], f]: threads 0 .. 4 TRAIN_ROWS - 1 take 8 columns of row t / 4;
-  // threads 256.. stage W3
+  // threads 256 .. 256 + HID - 1 stage W3
   const int xrow = tid >> 2, xq = tid & 3;
   bf16x8 xv;
   int xid = -1;
@@ -411,7 +413,7 @@ __global__ __launch_bounds__(TR_THREADS) void train_chunk_kernel(TrainKArgs k) {
 #pragma unroll
       for (int j = 0; j < 8; ++j) xv[j] = (bf16)0.0f;
     }
-  } else if (tid >= 256) {
+  } else if (tid >= 256 && tid < 256 + HID) {  // two W3 values per thread
     w3v[0] = k.W3_16[2 * (tid - 256)];
     w3v[1] = k.W3_16[2 * (tid - 256) + 1];
   }
@@ -430,7 +432,7 @@ __global__ __launch_bounds__(TR_THREADS) void train_chunk_kernel(TrainKArgs k) {
     *reinterpret_cast<bf16x8*>(sX + xrow * TR_LDX + 8 * xq) = xv;
 #pragma unroll
     for (int j = 0; j < 8; ++j) sXT[(8 * xq + j) * TR_LDT + xrow] = xv[j];
-  } else if (tid >= 256) {
+  } else if (tid >= 256 && tid < 256 + HID) {
     sW3[2 * (tid - 256)] = w3v[0];
     sW3[2 * (tid - 256) + 1] = w3v[1];
   }
@@ -637,30 +639,30 @@ __global__ __launch_bounds__(TR_THREADS) void train_chunk_kernel(TrainKArgs k) {
     for (int ks = 0; ks < TR_KS; ++ks) bt[ks] = global_frag(k.W1T16, HID, r, 32 * ks + 8 * g);
   lds_barrier();
 
-  // ---- dW1 = dz1^T X: wavefront w takes outputs c0..c0+31 (dz1 read down its
-  // columns: 8 two-byte LDS reads per fragment) ----
+  // ---- dW1 = dz1^T X: wavefront w takes outputs c0 .. c0 + TR_COLS - 1 (dz1
+  // read down its columns: 8 two-byte LDS reads per fragment) ----
   {
-    floatx4 acc[2][2];
+    floatx4 acc[TR_NB][2];
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+    for (int mb = 0; mb < TR_NB; ++mb)
 #pragma unroll
       for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < TRAIN_ROWS / 32; ++ks) {
-      bf16x8 a[2], b[2];
+      bf16x8 a[TR_NB], b[2];
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
+      for (int mb = 0; mb < TR_NB; ++mb)
 #pragma unroll
         for (int j = 0; j < 8; ++j) a[mb][j] = sA[(32 * ks + 8 * g + j) * TR_LDA + c0 + 16 * mb + r];
 #pragma unroll
       for (int nb = 0; nb < 2; ++nb) b[nb] = lds_frag(sXT, TR_LDT, 16 * nb + r, 32 * ks + 8 * g);
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
+      for (int mb = 0; mb < TR_NB; ++mb)
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = mfma16x16x32(a[mb], b[nb], acc[mb][nb]);
     }
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+    for (int mb = 0; mb < TR_NB; ++mb)
 #pragma unroll
       for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
@@ -681,28 +683,29 @@ __global__ __launch_bounds__(TR_THREADS) void train_chunk_kernel(TrainKArgs k) {
   }
 
   // ---- dW2 = dz2^T h1, last: its 256 KB of partial stores then hold up no
-  // later load.  Wavefront w takes outputs c0..c0+31, four passes of 64 inputs ----
+  // later load.  Wavefront w takes outputs c0 .. c0 + TR_COLS - 1, four
+  // passes of 64 inputs ----
 #pragma unroll 1
   for (int pass = 0; pass < 4; ++pass) {
-    floatx4 acc[2][4];
+    floatx4 acc[TR_NB][4];
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+    for (int mb = 0; mb < TR_NB; ++mb)
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < TRAIN_ROWS / 32; ++ks) {
-      bf16x8 a[2], b[4];
+      bf16x8 a[TR_NB], b[4];
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb) a[mb] = lds_frag(sBT, TR_LDT, c0 + 16 * mb + r, 32 * ks + 8 * g);
+      for (int mb = 0; mb < TR_NB; ++mb) a[mb] = lds_frag(sBT, TR_LDT, c0 + 16 * mb + r, 32 * ks + 8 * g);
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) b[nb] = lds_frag(sAT, TR_LDT, 64 * pass + 16 * nb + r, 32 * ks + 8 * g);
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
+      for (int mb = 0; mb < TR_NB; ++mb)
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = mfma16x16x32(a[mb], b[nb], acc[mb][nb]);
     }
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+    for (int mb = 0; mb < TR_NB; ++mb)
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb)
 #pragma unroll
