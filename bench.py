@@ -48,6 +48,10 @@ def parse():
                     help="skip the learned-surrogate section (training + fused inference)")
     ap.add_argument("--train-samples", type=int, default=10_000_000)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop section")
+    ap.add_argument("--counter-pass", choices=["full", "learned"], default=None,
+                    help="run only three launches of the full scan (C3 or C2, crossover 1/2) or of the "
+                         "fused inference (C4 world, random-initialised surrogate, 1M invocations), for "
+                         "rocprofv3 counter passes, and exit")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="for hardware-counter runs: a 256 MiB device copy (calibration) and a few "
                          "eager relax + decide launches on the benchmark workload, nothing timed")
@@ -624,6 +628,35 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     mode = B.SLACK_PAPER if args.mode == "paper" else B.SLACK_PROB
+
+    if args.counter_pass:
+        import numpy as np
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        if args.counter_pass == "full":
+            log(f"bench: full-scan counter pass on {args.workload}")
+            w = wl.make_c2() if args.workload == "c2" else wl.make_c3()
+            L = B.Llama(0).load(w)
+            op, el, slo = dev(w.inv_op), dev(w.elapsed), dev(w.slo)
+            L.relax(modes=1 << mode)
+            L.reserve(w.n_inv)
+            L.set_full_schedule(1, 2)
+            for _ in range(3):
+                L.decide(op, el, slo, None, mode, B.SCAN_FULL)
+            n = w.n_inv
+        else:
+            log("bench: fused-inference counter pass on the C4 world")
+            world = wl.make_c4_world(3)
+            L = B.Llama(0).load(world.w)
+            L.surrogate_init(seed=15, mean_log_latency=10.5)
+            n = 1_000_000
+            w4, c4 = wl.c4_invocations(world, np.random.default_rng(8), n)
+            feat = torch.from_numpy(np.ascontiguousarray(c4.feat, np.float32)).to(torch.bfloat16).cuda()
+            op, el, slo = dev(w4.inv_op), dev(w4.elapsed), dev(w4.slo)
+            for _ in range(3):
+                L.decide_learned(op, el, slo, feat)
+        torch.cuda.synchronize()
+        print(json.dumps({"counter_pass": args.counter_pass, "invocations": n}), flush=True)
+        return
 
     if args.pmc_pass:
         import numpy as np
