@@ -34,7 +34,7 @@ struct Surrogate {
   DevBuf master, adam_m, adam_v, grad;              // fp32 [n_params], layout E, W1, b1, W2, b2, W3, b3
   DevBuf E16, W1_16, W2_16, W2p16, W3_16;           // bf16 shadows
   DevBuf W1T16, W2T16;                              // transposed bf16 shadows (backward products)
-  DevBuf dE;                                        // fp32 [nE] embedding-gradient accumulator, zero between steps
+  DevBuf dE;                                        // int64 [nE] embedding-gradient accumulator (2^-40 units), zero between steps
   int64_t ws_batch = 0;                             // forward workspace capacity (rows)
   DevBuf X16, z1, h1, z2, h2, out;
   int64_t part_chunks = 0;                          // training partial-gradient capacity (chunks)

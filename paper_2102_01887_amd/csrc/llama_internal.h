@@ -327,7 +327,7 @@ struct SurrogateBufs {
   const float *b1, *b2, *b3;
   void *E16, *W1_16, *W2_16, *W2p16, *W3_16;
   void *W1T16, *W2T16;       // transposed shadows: W1T[k][o], W2T[k][o]
-  float* dE;                 // [nE] embedding-gradient accumulator, zero between steps
+  unsigned long long* dE;    // [nE] embedding-gradient accumulator (fixed point, 2^-40), zero between steps
   float* part;               // [TRAIN_MAX_CHUNKS][n_params - nE] per-chunk partial gradients
   // forward workspace, B rows
   void *X16, *h1, *h2;

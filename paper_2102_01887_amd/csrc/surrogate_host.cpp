@@ -65,7 +65,7 @@ llama::SurrogateBufs bufs(const llama_ctx* c) {
   w.W3_16 = s.W3_16.p;
   w.W1T16 = s.W1T16.p;
   w.W2T16 = s.W2T16.p;
-  w.dE = s.dE.as<float>();
+  w.dE = s.dE.as<unsigned long long>();
   w.part = s.part.as<float>();
   w.X16 = s.X16.p;
   w.h1 = s.h1.p;
@@ -103,7 +103,7 @@ int install(llama_ctx* c, const float* params, const float* m, const float* v, i
       (rc = upload(c, s.W3_16, nullptr, 2 * (size_t)2 * HID, "W3 (bf16)")) ||
       (rc = upload(c, s.W1T16, nullptr, 2 * (size_t)HID * IN, "W1 transposed (bf16)")) ||
       (rc = upload(c, s.W2T16, nullptr, 2 * (size_t)HID * HID, "W2 transposed (bf16)")) ||
-      (rc = upload(c, s.dE, nullptr, sizeof(float) * (size_t)(lay.nE ? lay.nE : 1), "embedding gradient")))
+      (rc = upload(c, s.dE, nullptr, sizeof(uint64_t) * (size_t)(lay.nE ? lay.nE : 1), "embedding gradient")))
     return rc;
   if (hipMemsetAsync(s.dE.p, 0, s.dE.bytes, c->stream) != hipSuccess) return fail(c, LLAMA_E_DEVICE, "memset");
   if (!m && hipMemsetAsync(s.adam_m.p, 0, pb, c->stream) != hipSuccess) return fail(c, LLAMA_E_DEVICE, "memset");

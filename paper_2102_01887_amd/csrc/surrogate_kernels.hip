@@ -261,13 +261,21 @@ __global__ __launch_bounds__(256) void shadows_kernel(const float* master, int64
 //   dz2 = (dout W3) GELU'(z2)     in registers, then LDS (both layouts); db2
 //   dz1 = (dz2 W2) GELU'(z1)      MFMA with the transposed W2 shadow, then LDS; db1
 //   dW1 = dz1^T X                 MFMA over the rows
-//   dE[row] += (dz1 W1)[:, :16]   MFMA with the transposed W1 shadow, atomics
+//   dE[row] += (dz1 W1)[:, :16]   MFMA with the transposed W1 shadow, 64-bit
+//                                 fixed-point integer atomics
 //   dW2 = dz2^T h1                MFMA over the rows, four passes of 64 columns,
 //                                 last, so that its stores delay no load
 // Partial gradients go to part[chunk] in the parameter order after E; the
 // reduce kernel sums them in chunk order, so the sum does not depend on
-// timing (only dE, whose atomics may add in any order).
+// timing.  dE is summed in fixed point (units of 2^-40, each term clamped
+// to |t| <= 2^8): integer addition is associative, so its atomics give the
+// same sum in any order and a training run is repeatable bit for bit.  At
+// most 256 chunks x 64 rows add into one element per launch, so the sum
+// stays below 2^(8 + 40 + 14) = 2^62.
 // ---------------------------------------------------------------------------
+constexpr float DE_SCALE = 1099511627776.0f;  // 2^40
+constexpr double DE_UNIT = 1.0 / 1099511627776.0;
+constexpr float DE_CLAMP = 256.0f;
 constexpr int TR_LDX = IN + 8;          // bf16 stride of X rows
 constexpr int TR_LDT = TRAIN_ROWS + 8;  // bf16 stride of transposed rows
 constexpr int TR_LDA = HID + 8;         // bf16 stride of activation rows
@@ -288,7 +296,7 @@ struct TrainKArgs {
   const float *b1, *b2, *b3;
   float* part;
   int64_t P;  // partial-gradient floats per chunk
-  float* dE;
+  unsigned long long* dE;  // fixed point, units of DE_UNIT
   int64_t n_rows;  // embedding rows: a row id outside [0, n_rows) trains as a zero row
 };
 
@@ -678,7 +686,10 @@ __global__ __launch_bounds__(TR_THREADS) void train_chunk_kernel(TrainKArgs k) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int row = 16 * w + 4 * g + i;
-      if (row < nrow && sRow[row] >= 0) atomicAdd(k.dE + (int64_t)sRow[row] * EMB + r, acc[i]);
+      if (row < nrow && sRow[row] >= 0) {
+        const float t = fminf(fmaxf(acc[i], -DE_CLAMP), DE_CLAMP) * DE_SCALE;
+        atomicAdd(k.dE + (int64_t)sRow[row] * EMB + r, (unsigned long long)__float2ll_rn(t));
+      }
     }
   }
 
@@ -717,7 +728,7 @@ __global__ __launch_bounds__(TR_THREADS) void train_chunk_kernel(TrainKArgs k) {
 // Sum of the chunks' partials (chunk order) or the embedding accumulator;
 // then AdamW as adamw_kernel and the new value's shadows.
 __global__ __launch_bounds__(256) void train_reduce_kernel(int64_t n, int64_t nE, const float* part, int n_chunks,
-                                                           float* dE, float* grad, int first, int update, float* p,
+                                                           unsigned long long* dE, float* grad, int first, int update, float* p,
                                                            float* m, float* v, float lr, float wd, float c1,
                                                            float c2, int64_t d0, int64_t d1a, int64_t d1b,
                                                            int64_t d2a, int64_t d2b, Shadows sh) {
@@ -725,8 +736,8 @@ __global__ __launch_bounds__(256) void train_reduce_kernel(int64_t n, int64_t nE
   if (i >= n) return;
   float gi;
   if (i < nE) {
-    gi = dE[i];
-    dE[i] = 0.0f;
+    gi = (float)((double)(long long)dE[i] * DE_UNIT);
+    dE[i] = 0ull;
   } else {
     // 32 loads in flight, added in chunk order
     const int64_t P = n - nE;

@@ -89,9 +89,8 @@ def test_simulator_split_and_errors():
 def test_training_on_gpu_simulated_executions():
     # the learned form trained on executions drawn on the device beats the
     # static profile on misses, as it does with host-drawn executions; the
-    # training set is the 10M-sample one of the host-drawn test, since with
-    # 4M samples the regret of one training run to the next (the embedding
-    # gradients are summed in no fixed order) ranged from 0.014 to 0.030
+    # training set is the 10M-sample one of the host-drawn test (with 4M
+    # samples the regret sat near the bound)
     from test_gpu_surrogate import check_inference, evaluate, inference_case, setup_world
     torch, world, L = setup_world()
     L.set_simulator(world.a, world.b, world.sigma)

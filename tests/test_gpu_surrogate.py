@@ -232,6 +232,21 @@ def test_trained_surrogate_beats_the_profile():
     assert r_s["miss_rate"] < r_p["miss_rate"]
 
 
+def test_training_repeats_bit_for_bit():
+    """Two trainings from the same initialisation on the same samples give
+    identical parameters: the partial gradients are summed in chunk order
+    and the embedding gradients in integer fixed point, so no sum depends on
+    the order in which workgroups finish."""
+    torch, world, L = setup_world()
+    got = []
+    for _ in range(2):
+        L.surrogate_init(seed=15, mean_log_latency=10.5)
+        train(torch, L, world, n_samples=300_000)
+        got.append(L.surrogate_get().copy())
+    assert np.array_equal(got[0], got[1])
+    L.close()
+
+
 def test_checkpoint_resume(tmp_path):
     torch, world, L = setup_world()
     rng = np.random.default_rng(9)
